@@ -1,0 +1,251 @@
+"""Pins for the CPU oracle: closed forms, brute force, invariants and planted mistakes.
+
+These tests check the oracle against facts fixed by the mathematics and the
+paper, not against itself:
+  * Dirichlet Laplacian spectra in closed form (2D and 3D);
+  * a dense matrix with a prescribed spectrum;
+  * brute-force dense eigenpairs on small random SPD matrices;
+  * Algorithm 2's ENSURE (A = QR, Q^T Q = I) and agreement with FP64 Householder R;
+  * the Hetmaniuk-Lehoucq update keeps [X, P] orthonormal and contains span(X_old);
+  * the residual test of eq. (stop);
+  * Lemma 2's bound on gamma where its hypothesis holds, and Theorem 1's rate;
+  * eigen-gradients against central finite differences and shift invariants.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import dense, grad, lobpcg as ol, mixed_qr, pinvit, precond
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def closed_form_2d(s, count):
+    t = 4.0 * np.sin(np.arange(1, s + 1) * np.pi / (2 * (s + 1))) ** 2
+    return np.sort((t[:, None] + t[None, :]).ravel())[:count]
+
+
+def closed_form_3d(N, count):
+    t = 4.0 * np.sin(np.arange(1, N + 1) * np.pi / (2 * (N + 1))) ** 2
+    return np.sort((t[:, None, None] + t[None, :, None] + t[None, None, :]).ravel())[:count]
+
+
+def test_golden_closed_forms_match_formula():
+    with open(os.path.join(GOLDEN, "closed_forms.json")) as f:
+        g = json.load(f)
+    np.testing.assert_allclose(closed_form_2d(32, 6), g["laplace2d_32"]["eigs"], rtol=1e-13)
+    np.testing.assert_allclose(closed_form_3d(64, 33)[[0, 15, 16, 31, 32]], g["laplace3d_64"]["eigs"], rtol=1e-13)
+
+
+def test_cfg1_closed_form():
+    p = synth.cfg1()
+    na = dense.norm2(p.A)
+    assert abs(na - 8 * np.sin(32 * np.pi / 66) ** 2) < 1e-12
+    r = ol.lobpcg(p.A, p.X0, p.k, p.tol, norm_a=na)
+    assert r.converged
+    ref = closed_form_2d(32, 4)
+    assert np.max(np.abs(r.evals - ref) / ref) < 1e-12
+    # invariants: orthonormal X and the residual gate
+    assert np.max(np.abs(r.evecs.T @ r.evecs - np.eye(4))) < 1e-13
+    res = ol.residual_norms(p.A, r.evecs, r.evals, na)
+    assert np.all(res <= p.tol)
+
+
+def test_laplace3d_closed_form_fp32_factor():
+    p = synth.cfg2(N=12, constant=True, k=8, m=16)
+    na = dense.norm2(p.A)
+    r = ol.lobpcg(p.A, p.X0, p.k, p.tol, precond_precision="fp32", norm_a=na)
+    ref = closed_form_3d(12, 8)
+    assert r.converged
+    assert np.max(np.abs(r.evals - ref) / ref) < 1e-11
+
+
+def test_dense_prescribed_spectrum():
+    A, lam = synth.dense_spd(256, seed=3)
+    X0 = synth.random_block(256, 16, 7)
+    r = ol.lobpcg(A, X0, 8, 1e-12, precond_precision="fp32", norm_a=1e6)
+    assert r.converged
+    assert np.max(np.abs(r.evals - lam[:8]) / lam[:8]) < 1e-9
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_brute_force_random_sparse(seed):
+    rng = np.random.default_rng(seed)
+    n = 300
+    B = sp.random(n, n, density=0.02, random_state=seed)
+    A = (B @ B.T + sp.eye(n) * 0.5).tocsr()
+    X0 = rng.standard_normal((n, 10))
+    na = dense.norm2(A)
+    r = ol.lobpcg(A, X0, 5, 1e-11, norm_a=na)
+    lam, U = dense.smallest_eigenpairs(A, 5)
+    assert r.converged
+    assert np.max(np.abs(r.evals - lam) / lam) < 1e-10
+    # sign-invariant eigenvector agreement (eigenvalues are simple here)
+    gaps = np.diff(dense.all_eigenpairs(A)[0][:7])
+    if gaps.min() > 1e-6:
+        cosines = np.abs(np.sum(r.evecs * U, axis=0))
+        assert np.all(cosines > 1 - 1e-9)
+
+
+def test_degenerate_cluster_subspace():
+    # cfg1 has lambda_2 = lambda_3 exactly: compare the invariant subspace, not vectors.
+    p = synth.cfg1()
+    r = ol.lobpcg(p.A, p.X0, 4, 1e-10, norm_a=dense.norm2(p.A))
+    lam, U = dense.smallest_eigenpairs(p.A, 4)
+    Xc, Uc = r.evecs[:, 1:3], U[:, 1:3]
+    s = np.linalg.svd(Uc.T @ Xc, compute_uv=False)
+    assert s.min() > 1 - 1e-12
+
+
+def test_stop_paper_form_is_looser_than_bj():
+    A = synth.laplace2d(20)
+    X0 = synth.random_block(400, 8, 1)
+    na = dense.norm2(A)
+    r1 = ol.lobpcg(A, X0, 4, 1e-8, norm_a=na, stop="bj")
+    r2 = ol.lobpcg(A, X0, 4, 1e-8, norm_a=na, stop="paper")
+    assert r2.iters <= r1.iters
+    res = ol.residual_norms(A, r2.evecs, r2.evals, na, mode="paper")
+    assert np.all(res <= 1e-8)
+
+
+@pytest.mark.parametrize("kappa", [1.0, 1e3, 1e6])
+def test_mixed_qr_ensure(kappa):
+    rng = np.random.default_rng(11)
+    n, m = 2000, 24
+    U, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    V, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    W = (U * np.geomspace(1.0, 1.0 / kappa, m)) @ V.T
+    Q, R = mixed_qr.mixed_qr(W)
+    u = np.finfo(np.float64).eps / 2
+    assert np.linalg.norm(Q.T @ Q - np.eye(m)) <= 10 * m * u
+    assert np.linalg.norm(W - Q @ R) / np.linalg.norm(W) <= 10 * u * 10
+    assert np.allclose(np.tril(R, -1), 0.0)
+    # R equals the FP64 Householder R up to row signs
+    _, Rh = mixed_qr.householder_qr(W)
+    sgn = np.sign(np.diag(R)) * np.sign(np.diag(Rh))
+    assert np.linalg.norm(R - sgn[:, None] * Rh) / np.linalg.norm(Rh) < 50 * kappa * u
+
+
+def test_hl_update_invariants():
+    A = synth.laplace2d(24)
+    X0 = synth.random_block(576, 6, 3)
+    m = 6
+    seen = []
+
+    def cb(it, X, P, theta, res):
+        if P is not None:
+            B = np.hstack([X, P])
+            seen.append(np.max(np.abs(B.T @ B - np.eye(2 * m))))
+
+    ol.lobpcg(A, X0, 3, 1e-10, norm_a=dense.norm2(A), callback=cb)
+    assert seen and max(seen) < 1e-12
+
+    # span(X_old) is contained in span([X_new, P_new]) after one update
+    rng = np.random.default_rng(0)
+    S, _ = np.linalg.qr(rng.standard_normal((576, 3 * m)))
+    H = S.T @ (A @ S)
+    D, C = np.linalg.eigh(0.5 * (H + H.T))
+    X, P, _ = ol.hl_update(S, C, D, m)
+    B = np.hstack([X, P])
+    Xold = S[:, :m]
+    assert np.linalg.norm(Xold - B @ (B.T @ Xold)) < 1e-12
+
+
+def test_lemma2_bound_and_theorem1_rate():
+    # Lemma 2 hypothesis eps_T = 4n(3n+1) kappa u_l < 1 holds for tiny n and small kappa.
+    n = 8
+    A, _ = synth.dense_spd(n, seed=5, lo=1.0, hi=4.0)
+    ul = np.finfo(np.float32).eps / 2
+    kappa = np.linalg.cond(A)
+    eps_t = 4 * n * (3 * n + 1) * kappa * ul
+    assert eps_t < 1
+    gamma = precond.preconditioner_gamma(A, "fp32")
+    assert gamma <= eps_t / (1 - eps_t)
+    # Theorem 1: per-step contraction of PINVIT with a deliberately weak preconditioner.
+    A2, lam = synth.dense_spd(60, seed=9, lo=1.0, hi=50.0)
+    Tw = np.linalg.inv(A2 + 5.0 * np.eye(60))
+    Ah = np.linalg.cholesky(A2)
+    evals, U = np.linalg.eigh(A2)
+    Ahalf = (U * np.sqrt(evals)) @ U.T
+    g = np.linalg.norm(np.eye(60) - Ahalf @ Tw @ Ahalf, 2)
+    assert g < 1
+    q2 = pinvit.rate_bound(g, lam[0], lam[1])
+    rhos = pinvit.pinvit_k1(A2, U[:, 0] + 0.05 * U[:, 1] + 0.01 * U[:, 5], lambda r: Tw @ r, 6)
+    for a, b in zip(rhos[:-1], rhos[1:]):
+        if lam[0] < a < lam[1] and b - lam[0] > 1e-13:
+            assert pinvit.ratio(b, lam[0], lam[1]) <= q2 * pinvit.ratio(a, lam[0], lam[1]) * (1 + 1e-6)
+    del Ah
+
+
+def test_fp32_factor_gamma_small_on_diffusion():
+    p = synth.cfg2(N=8)
+    A = p.A.toarray()
+    gamma = precond.preconditioner_gamma(A, "fp32")
+    assert gamma < 1e-4
+
+
+def test_gradient_oracle_fd_and_invariants():
+    s = 7
+    rng = np.random.default_rng(4)
+    c = rng.uniform(0, 1, (4, 2)); w = rng.uniform(0.1, 0.2, 4); a = rng.uniform(0, 20, 4)
+    L0 = synth.laplace_scaled((s, s)).toarray()
+    phi = synth.bump_basis(synth.grid_points((s, s)), c, w)
+    g = rng.standard_normal(s * s); g /= np.linalg.norm(g)
+    k = 3
+
+    def A_of(amp):
+        return L0 + np.diag(phi @ amp)
+
+    loss, gv, lam, U = grad.loss_and_grad_diag(A_of(a), k, g)
+    # shift invariants: sum_j dlambda_i/dV_j = 1, sum_j dLvec/dV_j = 0
+    assert abs(gv.sum() - k) < 1e-10
+    ga = grad.grad_amplitudes(gv, phi)
+    h = 1e-5
+    fd = np.array([(grad.loss_value(A_of(a + h * e), k, g) - grad.loss_value(A_of(a - h * e), k, g)) / (2 * h)
+                   for e in np.eye(4)])
+    np.testing.assert_allclose(ga, fd, rtol=1e-6, atol=1e-9)
+
+
+def test_table3_laplace_shape():
+    # Table 3: 2D-Laplace has n = 25,000 and nnz = 114,990; a 5 x 5000 5-point grid gives both.
+    p, q = 5, 5000
+    nnz = 5 * p * q - 2 * (p + q)
+    assert p * q == 25000 and nnz == 114990
+
+
+# ---------------------------------------------------------------------------
+# Planted mistakes: each mutation of the oracle must be caught by a pin above.
+# ---------------------------------------------------------------------------
+
+def test_planted_mistake_hl_without_v_is_caught(monkeypatch):
+    def bad_hl(S, C, D, m):
+        return S @ C[:, :m], S @ C[:, m:2 * m], D[:m].copy()   # drops V: P no longer spans X_old's remainder
+    monkeypatch.setattr(ol, "hl_update", bad_hl)
+    A = synth.laplace2d(24)
+    rng = np.random.default_rng(0)
+    S, _ = np.linalg.qr(rng.standard_normal((576, 18)))
+    H = S.T @ (A @ S)
+    D, C = np.linalg.eigh(0.5 * (H + H.T))
+    X, P, _ = ol.hl_update(S, C, D, 6)
+    B = np.hstack([X, P])
+    assert np.linalg.norm(S[:, :6] - B @ (B.T @ S[:, :6])) > 1e-3
+
+
+def test_planted_mistake_residual_sign_is_caught():
+    p = synth.cfg1()
+    na = dense.norm2(p.A)
+    r = ol.lobpcg(p.A, p.X0, p.k, p.tol, norm_a=na)
+    R_bad = p.A @ r.evecs + r.evecs * r.evals      # wrong sign
+    res_bad = np.linalg.norm(R_bad, axis=0) / na
+    assert np.all(res_bad > p.tol)
+
+
+def test_planted_mistake_qr_transpose_is_caught():
+    rng = np.random.default_rng(2)
+    W = rng.standard_normal((500, 12))
+    Q, R = mixed_qr.mixed_qr(W)
+    assert np.linalg.norm(W - Q @ R.T) / np.linalg.norm(W) > 1e-3
