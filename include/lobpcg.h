@@ -1,0 +1,189 @@
+/*
+ * liblobpcg: mixed-precision LOBPCG for the k smallest eigenpairs of a real
+ * symmetric positive definite matrix on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kressner, Ma, Shao, "A mixed precision LOBPCG algorithm" (2023),
+ * Algorithm 3, working-precision loop (lines 2-17).  Working precision is
+ * IEEE double; the preconditioner T = (L L^T)^{-1} of section 5.1 uses a
+ * Cholesky factor L held in single (FP32) or double (FP64) precision and is
+ * applied by two triangular solves in the factor's precision (section 3.1);
+ * the block W is orthonormalised with Algorithm 2 (section 3.2).
+ *
+ * Conventions shared by every entry point
+ *  - Dense blocks are row-major (C order): element (i, j) of an n x c block
+ *    with leading dimension ld is at p[i*ld + j].
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the library owns (and frees in lobpcg_destroy) what it allocates.
+ *  - All GPU work is enqueued on the stream bound at setup (NULL = default
+ *    stream).  Functions that return results to the host synchronise it.
+ *  - No function throws or aborts across the ABI: each returns a status.
+ *    lobpcg_last_error() gives a message for the last failure on the thread.
+ *  - A context must not be used from two host threads at once.
+ */
+#ifndef LOBPCG_H
+#define LOBPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lobpcg_ctx_s* lobpcg_ctx;
+
+typedef enum {
+  LOBPCG_OK = 0,
+  LOBPCG_NOT_CONVERGED = 1,        /* maxit reached; best Ritz pairs returned */
+  LOBPCG_ERR_INVALID_ARG = 2,      /* argument check failed, nothing enqueued */
+  LOBPCG_ERR_FACTOR_BREAKDOWN = 3, /* non-positive pivot in the Cholesky factor */
+  LOBPCG_ERR_ORTHO_BREAKDOWN = 4,  /* Algorithm 2 failed and its FP64 retry too */
+  LOBPCG_ERR_NONFINITE = 5,        /* NaN/Inf in inputs or residual norms */
+  LOBPCG_ERR_ALLOC = 6,            /* device or host allocation failed */
+  LOBPCG_ERR_HIP = 7,              /* a HIP runtime call failed */
+  LOBPCG_ERR_STATE = 8             /* call out of order (e.g. backward before solve) */
+} lobpcg_status;
+
+typedef enum { LOBPCG_FP64 = 0, LOBPCG_FP32 = 1 } lobpcg_precision;
+
+typedef enum {
+  LOBPCG_STOP_PAPER = 0,  /* eq. (stop): ||r_j|| <= tol (||A||_2 + |theta_j|) ||x_j|| */
+  LOBPCG_STOP_NORMA = 1   /* ||r_j|| <= tol ||A||_2 ||x_j|| */
+} lobpcg_stop_rule;
+
+/* The matrix A (section 1: Hermitian positive definite; real here).
+ * CSR: full symmetric pattern (both triangles), column indices sorted and
+ *      unique within each row, int32 indices, FP64 values.
+ * Dense: n x n FP64, row-major with leading dimension ld (A symmetric, so
+ *      row- and column-major coincide).
+ * grid: optional geometry of a structured grid, node p = (i0*g1 + i1)*g2 + i2
+ *      with 0 <= i_d < grid[d]; used by nested dissection; zeros = none.
+ * All pointers are HOST pointers; setup copies what it needs. */
+typedef struct {
+  int32_t format;            /* 0 = CSR, 1 = dense */
+  int32_t grid[3];
+  int64_t n;
+  int64_t nnz;               /* CSR only */
+  const int32_t* rowptr;     /* CSR, n+1 */
+  const int32_t* colind;     /* CSR, nnz */
+  const double* val;         /* CSR, nnz */
+  const double* dense;       /* dense, n*ld */
+  int64_t ld;                /* dense leading dimension (>= n) */
+} lobpcg_matrix;
+
+/* Optional tuning of setup (pass NULL for defaults). */
+typedef struct {
+  int32_t leaf_size;         /* nested-dissection leaf volume (default 64) */
+  int32_t stop_rule;         /* lobpcg_stop_rule (default LOBPCG_STOP_PAPER) */
+  int32_t qr_lower;          /* 1 = Algorithm 2 step 1 in FP32 (default), 0 = in FP64 */
+  int32_t reserved;
+  double norm_a;             /* > 0: use this ||A||_2 instead of the section 5.1 estimate */
+  double eig_tol;            /* > 0: also require ||r_j||^2 <= eig_tol |theta_j| (theta_m - theta_j) */
+} lobpcg_options;
+
+typedef struct {
+  int32_t iters;             /* outer iterations of Algorithm 3 */
+  int32_t n_conv;            /* n_c at exit */
+  int32_t fallbacks;         /* Algorithm 2 retries in FP64 */
+  int32_t nlevels;           /* levels of the supernodal elimination tree */
+  double norm_a;             /* ||A||_2 used by the convergence test */
+  double t_symbolic;         /* s, host ordering + symbolic analysis (setup) */
+  double t_factor;           /* s, numeric factorization on the GPU */
+  double t_solve;            /* s, lobpcg_solve wall time */
+  double nnz_factor;         /* stored entries of the supernodal factor */
+  double factor_flops;       /* flops of the numeric factorization */
+  double* resid;             /* host array of k final normalised residuals, nullable */
+} lobpcg_info;
+
+/* Set up a solver for the k smallest eigenpairs with block size m (Algorithm 3
+ * REQUIRE: k <= m), tolerance tol for the test selected in opts.
+ * Performs ordering (a fill-reducing symmetric permutation Pi, section 5.1),
+ * symbolic analysis on the host, uploads and permutes A on the GPU once
+ * (section 5.1: Pi is applied to A, not to R in every iteration), computes the
+ * factor Pi^T A Pi = L L^T in factor_precision on the GPU, and estimates
+ * ||A||_2 by ||A Omega||_F / ||Omega||_F with a seeded Gaussian Omega (n x m).
+ * Errors: INVALID_ARG (k < 1, k > m, 3m > n, tol <= 0, bad pattern, non-finite
+ * values), FACTOR_BREAKDOWN, ALLOC, HIP.  On error *out is NULL. */
+lobpcg_status lobpcg_setup(const lobpcg_matrix* A, int32_t k, int32_t m, double tol,
+                           lobpcg_precision factor_precision, void* hip_stream,
+                           const lobpcg_options* opts, lobpcg_ctx* out);
+
+/* Replace A's values by vals (CSR order of the setup pattern, device or host
+ * per vals_on_device) plus diag(shift) if shift != NULL (device, n, original
+ * order), then refactor.  Used for potentials A = A0 + diag(V). */
+lobpcg_status lobpcg_update_values(lobpcg_ctx ctx, const double* vals, int32_t vals_on_device,
+                                   const double* shift);
+
+/* Numeric refactorization of the current values (setup already does one). */
+lobpcg_status lobpcg_factor(lobpcg_ctx ctx);
+
+/* Run Algorithm 3 lines 2-17 from X0 (device, n x m row-major, original
+ * ordering; NULL = seeded N(0,1) block).  Writes evals (device, k, ascending)
+ * and evecs (device, n x k row-major, original ordering, unit 2-norm).
+ * Returns OK, NOT_CONVERGED (outputs still written), NONFINITE,
+ * ORTHO_BREAKDOWN or HIP.  Synchronises the stream. */
+lobpcg_status lobpcg_solve(lobpcg_ctx ctx, const double* X0, int32_t maxit,
+                           double* evals, double* evecs, lobpcg_info* info);
+
+/* Gradient of a loss L(theta_1..k, x_1..k) with respect to a diagonal
+ * potential added to A, given d_evals = dL/dtheta (device, k, nullable) and
+ * d_evecs = dL/dX (device, n x k row-major, nullable):
+ *   g = sum_i dtheta_i (x_i o x_i) - sum_i y_i o x_i,
+ *   (A - theta_i I) y_i = (I - x_i x_i^T) dX_i,  y_i orthogonal to x_i,
+ * solved by projected preconditioned CG in FP64 with the factor as
+ * preconditioner.  Writes d_diag (device, n, original ordering).
+ * Errors: STATE (no successful solve), NOT_CONVERGED (adjoint solve). */
+lobpcg_status lobpcg_backward(lobpcg_ctx ctx, const double* d_evals, const double* d_evecs,
+                              double* d_diag);
+
+lobpcg_status lobpcg_destroy(lobpcg_ctx ctx);
+const char* lobpcg_status_string(lobpcg_status s);
+const char* lobpcg_last_error(void);
+
+/* ---- Per-step entry points (each one step of the hot path, for tests and
+ * measurement).  Blocks are in the permuted ordering of the context. ---- */
+
+/* Host-only symbolic analysis (no GPU use): the fill-reducing ordering and
+ * supernode partition setup would build for A.  perm_host (n, nullable)
+ * receives perm[new] = old; stats (nullable, 8 doubles) receives
+ * {supernodes, levels, stored factor entries (lower), factorization flops,
+ *  largest front rows, largest supernode columns, update-matrix entries,
+ *  panel entries}. */
+lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t* perm_host, double* stats);
+
+/* Host copy of the permutation: perm[new] = old (n entries). */
+lobpcg_status lobpcg_get_permutation(lobpcg_ctx ctx, int32_t* perm_host);
+
+/* Y = A X for the permuted A of ctx: X, Y device n x c (ld >= c), c <= 256.
+ * (Algorithm 3 line 13, A S; section 4's fl(Ax).) */
+lobpcg_status lobpcg_apply_a(lobpcg_ctx ctx, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                             int32_t c);
+
+/* W = working(f_T(lower(R))) with T = (L L^T)^{-1} of ctx, in the factor's
+ * precision (Algorithm 3 lines 9-10): R, W device n x m, ld = m. */
+lobpcg_status lobpcg_apply_precond(lobpcg_ctx ctx, const double* R, double* W);
+
+/* Algorithm 2 in place on W (device, n x c row-major, ld >= c, c <= 64):
+ * W <- Q; R (device, c x c row-major, nullable) <- upper triangular factor.
+ * lower_step1 = 1: step 1 in FP32, else FP64.  Returns ORTHO_BREAKDOWN if the
+ * step-3 Cholesky fails. */
+lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t c, int64_t ldw, int32_t lower_step1,
+                              double* R, void* hip_stream);
+
+/* G = X^T Y (device; X n x c1, Y n x c2, row-major; G c1 x c2 row-major),
+ * deterministic two-stage reduction.  c1, c2 <= 256. */
+lobpcg_status lobpcg_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
+                          int32_t c1, int32_t c2, double* G, void* hip_stream);
+
+/* Symmetric eigensolver for a small c x c FP64 matrix (device, row-major,
+ * symmetrised as (H + H^T)/2): evals ascending (device, c), evecs (device,
+ * c x c row-major, column j = eigenvector j).  c <= 192.  (Algorithm 3
+ * line 14.) */
+lobpcg_status lobpcg_syev_small(const double* H, int32_t c, double* evals, double* evecs,
+                                void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOBPCG_H */

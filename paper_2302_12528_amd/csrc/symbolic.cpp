@@ -1,0 +1,576 @@
+// Host ordering and symbolic analysis (see symbolic.hpp).
+#include "symbolic.hpp"
+
+#include <algorithm>
+#include <array>
+#include <functional>
+#include <numeric>
+
+namespace lobpcg {
+namespace {
+
+struct Builder {
+  int64_t n;
+  const int32_t* rowptr;
+  const int32_t* colind;
+  int leaf;
+  std::vector<int32_t> perm;   // filled in emission order
+  std::vector<int32_t> begin, nc, parent;
+  int32_t next = 0;
+  // scratch for graph bisection
+  std::vector<int32_t> stamp, lvl;
+  int32_t cur_stamp = 0;
+
+  int new_sn(const std::vector<int32_t>& nodes) {
+    int s = (int)begin.size();
+    begin.push_back(next);
+    nc.push_back((int32_t)nodes.size());
+    parent.push_back(-1);
+    for (int32_t v : nodes) perm[next++] = v;
+    return s;
+  }
+
+  // Geometric nested dissection of the box [lo, hi) of a g0 x g1 x g2 grid.
+  std::vector<int> box(const int g[3], std::array<int, 3> lo, std::array<int, 3> hi) {
+    int64_t vol = 1;
+    for (int d = 0; d < 3; ++d) vol *= std::max(0, hi[d] - lo[d]);
+    if (vol == 0) return {};
+    int d = 0;
+    for (int e = 1; e < 3; ++e)
+      if (hi[e] - lo[e] > hi[d] - lo[d]) d = e;
+    if (vol <= leaf || hi[d] - lo[d] < 2) {
+      std::vector<int32_t> nodes;
+      nodes.reserve(vol);
+      for (int i = lo[0]; i < hi[0]; ++i)
+        for (int j = lo[1]; j < hi[1]; ++j)
+          for (int l = lo[2]; l < hi[2]; ++l) nodes.push_back((int32_t)(((int64_t)i * g[1] + j) * g[2] + l));
+      return {new_sn(nodes)};
+    }
+    int mid = lo[d] + (hi[d] - lo[d]) / 2;
+    auto hl = hi; hl[d] = mid;
+    auto lr = lo; lr[d] = mid + 1;
+    std::vector<int> a = box(g, lo, hl);
+    std::vector<int> b = box(g, lr, hi);
+    auto ls = lo; ls[d] = mid;
+    auto hs = hi; hs[d] = mid + 1;
+    std::vector<int32_t> sep;
+    for (int i = ls[0]; i < hs[0]; ++i)
+      for (int j = ls[1]; j < hs[1]; ++j)
+        for (int l = ls[2]; l < hs[2]; ++l) sep.push_back((int32_t)(((int64_t)i * g[1] + j) * g[2] + l));
+    int s = new_sn(sep);
+    for (int c : a) parent[c] = s;
+    for (int c : b) parent[c] = s;
+    return {s};
+  }
+
+  // BFS inside the node set marked with `st`; returns visit order, fills lvl.
+  std::vector<int32_t> bfs(int32_t start, int32_t st, int32_t visit_st, int& depth) {
+    std::vector<int32_t> order{start};
+    stamp[start] = visit_st;
+    lvl[start] = 0;
+    depth = 0;
+    for (size_t h = 0; h < order.size(); ++h) {
+      int32_t v = order[h];
+      for (int32_t e = rowptr[v]; e < rowptr[v + 1]; ++e) {
+        int32_t u = colind[e];
+        if (stamp[u] == st) {
+          stamp[u] = visit_st;
+          lvl[u] = lvl[v] + 1;
+          depth = std::max(depth, lvl[u]);
+          order.push_back(u);
+        }
+      }
+    }
+    return order;
+  }
+
+  // Graph nested dissection by breadth-first level structures.
+  std::vector<int> graph(std::vector<int32_t> nodes) {
+    if (nodes.empty()) return {};
+    if ((int64_t)nodes.size() <= leaf) return {new_sn(nodes)};
+    int32_t st = ++cur_stamp;
+    for (int32_t v : nodes) stamp[v] = st;
+    // pseudo-peripheral start: two sweeps
+    int depth = 0;
+    int32_t vs = ++cur_stamp;
+    std::vector<int32_t> order = bfs(nodes[0], st, vs, depth);
+    if (order.size() == nodes.size()) {
+      int32_t far = order.back();
+      int32_t st2 = ++cur_stamp;
+      for (int32_t v : nodes) stamp[v] = st2;
+      int32_t vs2 = ++cur_stamp;
+      order = bfs(far, st2, vs2, depth);
+    }
+    if (order.size() < nodes.size()) {
+      // disconnected: split off the reached component, no separator
+      std::vector<int32_t> rest;
+      int32_t vis = stamp[order[0]];
+      for (int32_t v : nodes)
+        if (stamp[v] != vis) rest.push_back(v);
+      std::vector<int> a = graph(order);
+      std::vector<int> b = graph(rest);
+      a.insert(a.end(), b.begin(), b.end());
+      return a;
+    }
+    if (depth < 2) return {new_sn(nodes)};
+    std::vector<int64_t> cnt(depth + 1, 0);
+    for (int32_t v : order) cnt[lvl[v]]++;
+    int64_t half = (int64_t)nodes.size() / 2, acc = 0;
+    int cut = 1;
+    for (int l = 0; l <= depth; ++l) {
+      acc += cnt[l];
+      if (acc >= half) { cut = l; break; }
+    }
+    cut = std::min(std::max(cut, 1), depth - 1);
+    std::vector<int32_t> left, sep, right;
+    for (int32_t v : order) {
+      if (lvl[v] < cut) left.push_back(v);
+      else if (lvl[v] == cut) sep.push_back(v);
+      else right.push_back(v);
+    }
+    std::vector<int> a = graph(left);
+    std::vector<int> b = graph(right);
+    int s = new_sn(sep);
+    for (int c : a) parent[c] = s;
+    for (int c : b) parent[c] = s;
+    return {s};
+  }
+};
+
+}  // namespace
+
+std::string analyze(int64_t n, const int32_t* rowptr, const int32_t* colind, const int32_t grid[3],
+                    bool dense, int leaf_size, Symbolic& S) {
+  if (n <= 0) return "n must be positive";
+  if (leaf_size < 1) leaf_size = 64;
+  Builder B;
+  B.n = n;
+  B.rowptr = rowptr;
+  B.colind = colind;
+  B.leaf = leaf_size;
+  B.perm.assign(n, -1);
+  if (dense) {
+    std::vector<int32_t> all(n);
+    std::iota(all.begin(), all.end(), 0);
+    B.new_sn(all);
+  } else {
+    bool use_grid = grid && grid[0] > 0 && grid[1] > 0 && grid[2] > 0 &&
+                    (int64_t)grid[0] * grid[1] * grid[2] == n;
+    if (use_grid) {
+      int g[3] = {grid[0], grid[1], grid[2]};
+      B.box(g, {0, 0, 0}, {g[0], g[1], g[2]});
+    } else {
+      B.stamp.assign(n, 0);
+      B.lvl.assign(n, 0);
+      std::vector<int32_t> all(n);
+      std::iota(all.begin(), all.end(), 0);
+      B.graph(all);
+    }
+  }
+  if (B.next != n) return "ordering did not cover all nodes";
+  S = Symbolic();
+  S.n = n;
+  S.perm = std::move(B.perm);
+  S.iperm.assign(n, -1);
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t o = S.perm[i];
+    if (o < 0 || o >= n || S.iperm[o] != -1) return "ordering is not a permutation";
+    S.iperm[o] = (int32_t)i;
+  }
+  const int ns = (int)B.begin.size();
+  S.nsuper = ns;
+  S.begin = B.begin;
+  S.nc = B.nc;
+  S.parent = B.parent;
+  // children
+  S.child_ptr.assign(ns + 1, 0);
+  for (int s = 0; s < ns; ++s)
+    if (S.parent[s] >= 0) {
+      if (S.parent[s] <= s) return "supernode tree not in postorder";
+      S.child_ptr[S.parent[s] + 1]++;
+    }
+  for (int s = 0; s < ns; ++s) S.child_ptr[s + 1] += S.child_ptr[s];
+  S.child_list.assign(S.child_ptr[ns], 0);
+  {
+    std::vector<int32_t> fill(S.child_ptr.begin(), S.child_ptr.end() - 1);
+    for (int s = 0; s < ns; ++s)
+      if (S.parent[s] >= 0) S.child_list[fill[S.parent[s]]++] = s;
+  }
+  // row structure
+  S.nr.assign(ns, 0);
+  S.row_off.assign(ns + 1, 0);
+  std::vector<int32_t> mark(n, -1);
+  std::vector<std::vector<int32_t>> below(ns);
+  for (int s = 0; s < ns; ++s) {
+    const int32_t b = S.begin[s], e = S.begin[s] + S.nc[s];
+    std::vector<int32_t>& st = below[s];
+    if (!dense) {
+      for (int32_t j = b; j < e; ++j) {
+        int32_t o = S.perm[j];
+        for (int32_t q = rowptr[o]; q < rowptr[o + 1]; ++q) {
+          int32_t u = S.iperm[colind[q]];
+          if (u >= e && mark[u] != s) { mark[u] = s; st.push_back(u); }
+        }
+      }
+    }
+    for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+      int c = S.child_list[q];
+      for (int32_t r : below[c]) {
+        if (r < b) return "child row structure outside parent (invalid ordering)";
+        if (r >= e && mark[r] != s) { mark[r] = s; st.push_back(r); }
+      }
+    }
+    std::sort(st.begin(), st.end());
+    S.nr[s] = S.nc[s] + (int32_t)st.size();
+  }
+  for (int s = 0; s < ns; ++s) S.row_off[s + 1] = S.row_off[s] + S.nr[s];
+  S.rows.assign(S.row_off[ns], 0);
+  S.relpos.assign(S.row_off[ns], -1);
+  for (int s = 0; s < ns; ++s) {
+    int64_t o = S.row_off[s];
+    for (int t = 0; t < S.nc[s]; ++t) S.rows[o + t] = S.begin[s] + t;
+    for (size_t j = 0; j < below[s].size(); ++j) S.rows[o + S.nc[s] + j] = below[s][j];
+  }
+  // relative positions of each child's below rows in its parent's rows, and inverse maps
+  S.inv_off.assign(ns + 1, 0);
+  for (int s = 0; s < ns; ++s) S.inv_off[s + 1] = S.inv_off[s] + (S.parent[s] >= 0 ? S.nr[S.parent[s]] : 0);
+  S.invmap.assign(S.inv_off[ns], -1);
+  for (int c = 0; c < ns; ++c) {
+    int p = S.parent[c];
+    if (p < 0) {
+      if (S.nr[c] != S.nc[c]) return "root supernode has rows below it";
+      continue;
+    }
+    const int32_t* prow = &S.rows[S.row_off[p]];
+    int pnr = S.nr[p], pnc = S.nc[p];
+    for (int j = 0; j < S.nr[c] - S.nc[c]; ++j) {
+      int32_t r = S.rows[S.row_off[c] + S.nc[c] + j];
+      int pos;
+      if (r < S.begin[p] + pnc) {
+        pos = r - S.begin[p];
+      } else {
+        const int32_t* it = std::lower_bound(prow + pnc, prow + pnr, r);
+        if (it == prow + pnr || *it != r) return "child row missing from parent structure";
+        pos = (int)(it - prow);
+      }
+      S.relpos[S.row_off[c] + S.nc[c] + j] = pos;
+      S.invmap[S.inv_off[c] + pos] = j;
+    }
+  }
+  // levels
+  S.level.assign(ns, 0);
+  int maxl = 0;
+  for (int s = 0; s < ns; ++s) {
+    int l = 0;
+    for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) l = std::max(l, S.level[S.child_list[q]] + 1);
+    S.level[s] = l;
+    maxl = std::max(maxl, l);
+  }
+  S.nlevels = maxl + 1;
+  S.level_ptr.assign(S.nlevels + 1, 0);
+  for (int s = 0; s < ns; ++s) S.level_ptr[S.level[s] + 1]++;
+  for (int l = 0; l < S.nlevels; ++l) S.level_ptr[l + 1] += S.level_ptr[l];
+  S.level_sn.assign(ns, 0);
+  {
+    std::vector<int32_t> fill(S.level_ptr.begin(), S.level_ptr.end() - 1);
+    for (int s = 0; s < ns; ++s) S.level_sn[fill[S.level[s]]++] = s;
+  }
+  // storage plans
+  S.panel_off.assign(ns + 1, 0);
+  S.upd_off.assign(ns + 1, 0);
+  S.uvec_off.assign(ns + 1, 0);
+  S.dinv_off.assign(ns + 1, 0);
+  S.lcopy_off.assign(ns, 0);
+  S.nnz_lower = 0;
+  S.flops = 0;
+  for (int s = 0; s < ns; ++s) {
+    int64_t r = S.nr[s], c = S.nc[s], b = r - c;
+    int64_t np = (c + kTile - 1) / kTile;
+    S.panel_off[s + 1] = S.panel_off[s] + r * c;
+    S.upd_off[s + 1] = S.upd_off[s] + b * b;
+    S.uvec_off[s + 1] = S.uvec_off[s] + b;
+    S.dinv_off[s + 1] = S.dinv_off[s] + np * kTile * kTile;
+    S.nnz_lower += (double)c * (c + 1) / 2 + (double)b * c;
+    for (int64_t j = 0; j < c; ++j) {
+      double cj = (double)(r - j - 1);
+      S.flops += cj * cj + cj;   // column scaling + rank-1 update of the trailing front
+    }
+    S.max_nr = std::max<int32_t>(S.max_nr, (int32_t)r);
+    S.max_nc = std::max<int32_t>(S.max_nc, (int32_t)c);
+  }
+  S.panel_total = S.panel_off[ns];
+  S.upd_total = S.upd_off[ns];
+  S.uvec_total = S.uvec_off[ns];
+  S.dinv_total = S.dinv_off[ns];
+  S.lcopy_max = 0;
+  for (int l = 0; l < S.nlevels; ++l) {
+    int64_t acc = 0;
+    for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+      int s = S.level_sn[q];
+      S.lcopy_off[s] = acc;
+      acc += (int64_t)S.nc[s] * S.nc[s];
+    }
+    S.lcopy_max = std::max(S.lcopy_max, acc);
+  }
+  return "";
+}
+
+void permute_pattern(const Symbolic& S, const int32_t* rowptr, const int32_t* colind,
+                     std::vector<int32_t>& prow, std::vector<int32_t>& pcol, std::vector<int32_t>& map) {
+  const int64_t n = S.n;
+  prow.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t o = S.perm[i];
+    prow[i + 1] = prow[i] + (rowptr[o + 1] - rowptr[o]);
+  }
+  pcol.assign(prow[n], 0);
+  map.assign(prow[n], 0);
+  std::vector<std::pair<int32_t, int32_t>> tmp;
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t o = S.perm[i];
+    tmp.clear();
+    for (int32_t e = rowptr[o]; e < rowptr[o + 1]; ++e) tmp.emplace_back(S.iperm[colind[e]], e);
+    std::sort(tmp.begin(), tmp.end());
+    for (size_t q = 0; q < tmp.size(); ++q) {
+      pcol[prow[i] + q] = tmp[q].first;
+      map[prow[i] + q] = tmp[q].second;
+    }
+  }
+}
+
+void assembly_positions(const Symbolic& S, const std::vector<int32_t>& prow,
+                        const std::vector<int32_t>& pcol, std::vector<int32_t>& apos) {
+  const int64_t n = S.n;
+  std::vector<int32_t> sn_of(n);
+  for (int s = 0; s < S.nsuper; ++s)
+    for (int t = 0; t < S.nc[s]; ++t) sn_of[S.begin[s] + t] = s;
+  apos.assign(prow[n], -1);
+  for (int64_t j = 0; j < n; ++j) {
+    int s = sn_of[j];
+    const int32_t* r0 = &S.rows[S.row_off[s]];
+    const int32_t* r1 = r0 + S.nr[s];
+    for (int32_t e = prow[j]; e < prow[j + 1]; ++e) {
+      int32_t i = pcol[e];
+      if (i < j) continue;
+      int pos;
+      if (i < S.begin[s] + S.nc[s]) {
+        pos = i - S.begin[s];
+      } else {
+        const int32_t* it = std::lower_bound(r0 + S.nc[s], r1, i);
+        pos = (it != r1 && *it == i) ? (int)(it - r0) : -1;
+      }
+      apos[e] = pos;
+    }
+  }
+}
+
+void build_factor_plan(const Symbolic& S, FactorPlan& P) {
+  P = FactorPlan();
+  auto push = [&](int s, int I, int J, int p) {
+    P.tasks.push_back(s); P.tasks.push_back(I); P.tasks.push_back(J); P.tasks.push_back(p);
+  };
+  auto ntiles = [](int x) { return (x + kTile - 1) / kTile; };
+  P.asm_level_off.assign(S.nlevels + 1, 0);
+  P.ownrow_level_off.assign(S.nlevels + 1, 0);
+  for (int l = 0; l < S.nlevels; ++l) {
+    const int32_t q0 = S.level_ptr[l], q1 = S.level_ptr[l + 1];
+    for (int32_t q = q0; q < q1; ++q) {
+      int s = S.level_sn[q];
+      for (int t = 0; t < S.nr[s]; ++t) { P.asm_items.push_back(s); P.asm_items.push_back(t); }
+      if (S.child_ptr[s + 1] > S.child_ptr[s])
+        for (int t = 0; t < S.nc[s]; ++t) { P.ownrow_items.push_back(s); P.ownrow_items.push_back(t); }
+    }
+    P.asm_level_off[l + 1] = (int64_t)P.asm_items.size() / 2;
+    P.ownrow_level_off[l + 1] = (int64_t)P.ownrow_items.size() / 2;
+    int maxnp = 0;
+    for (int32_t q = q0; q < q1; ++q) maxnp = std::max(maxnp, ntiles(S.nc[S.level_sn[q]]));
+    auto begin_step = [&](int kind) {
+      FactorPlan::Step st;
+      st.off = (int64_t)P.tasks.size() / 4;
+      st.count = 0;
+      st.kind = kind;
+      st.level = l;
+      P.steps.push_back(st);
+    };
+    auto end_step = [&]() {
+      FactorPlan::Step& st = P.steps.back();
+      st.count = (int32_t)((int64_t)P.tasks.size() / 4 - st.off);
+      if (st.count == 0) P.steps.pop_back();
+    };
+    begin_step(kAssemble);
+    push(l, 0, 0, 0);   // one marker task: the assembly kernel reads asm_items of level l
+    end_step();
+    for (int p = 0; p < maxnp; ++p) {
+      begin_step(kPotrf);
+      for (int32_t q = q0; q < q1; ++q) {
+        int s = S.level_sn[q];
+        if (ntiles(S.nc[s]) > p) push(s, p, p, p);
+      }
+      end_step();
+      begin_step(kTrsm);
+      for (int32_t q = q0; q < q1; ++q) {
+        int s = S.level_sn[q];
+        int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+        if (np > p)
+          for (int I = p + 1; I < rt; ++I) push(s, I, p, p);
+      }
+      end_step();
+      begin_step(kUpdate);
+      for (int32_t q = q0; q < q1; ++q) {
+        int s = S.level_sn[q];
+        int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+        if (np > p)
+          for (int J = p + 1; J < rt; ++J)
+            for (int I = J; I < rt; ++I) push(s, I, J, p);
+      }
+      end_step();
+    }
+    // inverse phase: P_s = [I; L21] inv(L11)
+    begin_step(kInvPrep);
+    for (int32_t q = q0; q < q1; ++q) {
+      int s = S.level_sn[q];
+      for (int t = 0; t < S.nc[s]; ++t) push(s, t, 0, 0);
+    }
+    end_step();
+    for (int st = 0; st < maxnp; ++st) {
+      begin_step(kInvScale);
+      for (int32_t q = q0; q < q1; ++q) {
+        int s = S.level_sn[q];
+        int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+        int qc = np - 1 - st;
+        if (qc < 0) continue;
+        for (int I = qc; I < rt; ++I) push(s, I, qc, qc);
+      }
+      end_step();
+      begin_step(kInvUpdate);
+      for (int32_t q = q0; q < q1; ++q) {
+        int s = S.level_sn[q];
+        int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+        int qc = np - 1 - st;
+        if (qc < 1) continue;
+        for (int r = 0; r < qc; ++r)
+          for (int I = qc; I < rt; ++I) push(s, I, r, qc);
+      }
+      end_step();
+    }
+  }
+}
+
+void build_solve_plan(const Symbolic& S, int rpt, SolvePlan& P) {
+  P = SolvePlan();
+  P.rows_per_tile = rpt;
+  P.fwd_level_off.assign(S.nlevels + 1, 0);
+  P.bwd_level_off.assign(S.nlevels + 1, 0);
+  for (int l = 0; l < S.nlevels; ++l) {
+    for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+      int s = S.level_sn[q];
+      for (int t = 0; t < (S.nr[s] + rpt - 1) / rpt; ++t) { P.fwd_items.push_back(s); P.fwd_items.push_back(t); }
+      for (int t = 0; t < (S.nc[s] + rpt - 1) / rpt; ++t) { P.bwd_items.push_back(s); P.bwd_items.push_back(t); }
+    }
+    P.fwd_level_off[l + 1] = (int64_t)P.fwd_items.size() / 2;
+    P.bwd_level_off[l + 1] = (int64_t)P.bwd_items.size() / 2;
+  }
+}
+
+}  // namespace lobpcg
+
+namespace lobpcg {
+
+std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, const std::vector<int32_t>& prow,
+                   const std::vector<int32_t>& apos) {
+  const int64_t n = S.n;
+  const int ns = S.nsuper;
+  auto ntiles = [](int64_t x) { return (int)((x + kTile - 1) / kTile); };
+  if ((int64_t)S.perm.size() != n || (int64_t)S.iperm.size() != n) return "perm size";
+  for (int64_t i = 0; i < n; ++i)
+    if (S.perm[i] < 0 || S.perm[i] >= n || S.iperm[S.perm[i]] != i) return "perm/iperm mismatch";
+  int64_t covered = 0;
+  for (int s = 0; s < ns; ++s) {
+    const int nc = S.nc[s], nr = S.nr[s], nb = nr - nc;
+    if (nc < 1 || nb < 0) return "supernode size";
+    if (S.begin[s] != covered) return "supernode columns not contiguous";
+    covered += nc;
+    if (S.row_off[s + 1] - S.row_off[s] != nr) return "row_off";
+    const int32_t* r = &S.rows[S.row_off[s]];
+    for (int t = 0; t < nc; ++t)
+      if (r[t] != S.begin[s] + t) return "own rows";
+    for (int j = nc; j < nr; ++j) {
+      if (r[j] < S.begin[s] + nc || r[j] >= n) return "below row out of range";
+      if (j > nc && r[j] <= r[j - 1]) return "below rows not increasing";
+    }
+    if (S.panel_off[s + 1] - S.panel_off[s] != (int64_t)nr * nc) return "panel_off";
+    if (S.upd_off[s + 1] - S.upd_off[s] != (int64_t)nb * nb) return "upd_off";
+    if (S.uvec_off[s + 1] - S.uvec_off[s] != nb) return "uvec_off";
+    if (S.dinv_off[s + 1] - S.dinv_off[s] != (int64_t)ntiles(nc) * kTile * kTile) return "dinv_off";
+    if (S.lcopy_off[s] < 0 || S.lcopy_off[s] + (int64_t)nc * nc > S.lcopy_max) return "lcopy_off";
+    const int p = S.parent[s];
+    if (p >= 0) {
+      if (p <= s || p >= ns) return "parent";
+      if (S.level[p] <= S.level[s]) return "level order";
+      if (S.inv_off[s + 1] - S.inv_off[s] != S.nr[p]) return "inv_off";
+      for (int pos = 0; pos < S.nr[p]; ++pos) {
+        const int32_t j = S.invmap[S.inv_off[s] + pos];
+        if (j < -1 || j >= nb) return "invmap range";
+        if (j >= 0 && S.relpos[S.row_off[s] + nc + j] != pos) return "invmap/relpos mismatch";
+      }
+      for (int j = 0; j < nb; ++j) {
+        const int32_t pos = S.relpos[S.row_off[s] + nc + j];
+        if (pos < 0 || pos >= S.nr[p]) return "relpos range";
+        if (S.rows[S.row_off[p] + pos] != r[nc + j]) return "relpos target";
+      }
+    } else if (nb != 0) {
+      return "root with below rows";
+    }
+  }
+  if (covered != n) return "supernodes do not cover all columns";
+  for (int s = 0; s < ns; ++s)
+    for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q)
+      if (S.child_list[q] < 0 || S.child_list[q] >= ns || S.parent[S.child_list[q]] != s) return "child list";
+  // factor tasks
+  for (const FactorPlan::Step& st : F.steps) {
+    if (st.off < 0 || st.off + st.count > (int64_t)F.tasks.size() / 4) return "step range";
+    if (st.level < 0 || st.level >= S.nlevels) return "step level";
+    if (st.kind == kAssemble) continue;
+    for (int64_t q = st.off; q < st.off + st.count; ++q) {
+      const int s = F.tasks[4 * q], I = F.tasks[4 * q + 1], J = F.tasks[4 * q + 2], p = F.tasks[4 * q + 3];
+      if (s < 0 || s >= ns || S.level[s] != st.level) return "task supernode";
+      const int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+      if (st.kind == kInvPrep) {
+        if (I < 0 || I >= S.nc[s]) return "invprep column";
+        continue;
+      }
+      if (p < 0 || p >= np || I < 0 || I >= rt || J < 0 || J >= rt) return "task tile";
+      if (st.kind == kUpdate && !(J > p && I >= J)) return "update tile order";
+      if ((st.kind == kTrsm || st.kind == kInvScale) && !(J == p && I >= p)) return "trsm tile order";
+      if (st.kind == kInvUpdate && !(J < p && I >= p)) return "inverse update tile order";
+    }
+  }
+  for (size_t q = 0; q < F.asm_items.size(); q += 2) {
+    const int s = F.asm_items[q], t = F.asm_items[q + 1];
+    if (s < 0 || s >= ns || t < 0 || t >= S.nr[s]) return "assembly item";
+  }
+  for (size_t q = 0; q < F.ownrow_items.size(); q += 2) {
+    const int s = F.ownrow_items[q], r = F.ownrow_items[q + 1];
+    if (s < 0 || s >= ns || r < 0 || r >= S.nc[s]) return "own-row item";
+  }
+  for (size_t q = 0; q < P.fwd_items.size(); q += 2) {
+    const int s = P.fwd_items[q], t = P.fwd_items[q + 1];
+    if (s < 0 || s >= ns || t < 0 || t * P.rows_per_tile >= S.nr[s]) return "forward item";
+  }
+  for (size_t q = 0; q < P.bwd_items.size(); q += 2) {
+    const int s = P.bwd_items[q], t = P.bwd_items[q + 1];
+    if (s < 0 || s >= ns || t < 0 || t * P.rows_per_tile >= S.nc[s]) return "backward item";
+  }
+  if (!prow.empty()) {
+    if ((int64_t)prow.size() != n + 1 || apos.size() != (size_t)prow[n]) return "assembly positions size";
+    std::vector<int32_t> sn_of(n);
+    for (int s = 0; s < ns; ++s)
+      for (int t = 0; t < S.nc[s]; ++t) sn_of[S.begin[s] + t] = s;
+    for (int64_t j = 0; j < n; ++j)
+      for (int32_t e = prow[j]; e < prow[j + 1]; ++e)
+        if (apos[e] < -1 || apos[e] >= S.nr[sn_of[j]]) return "assembly position";
+  }
+  return "";
+}
+
+}  // namespace lobpcg

@@ -1,0 +1,205 @@
+"""Python front end of liblobpcg: argument marshalling over the C-ABI only.
+
+Every numerical step runs in the library's HIP kernels; torch provides device
+memory (tensors) and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import numpy as np
+
+from . import native as nv
+
+_PREC = {"fp32": nv.LOBPCG_FP32, "fp64": nv.LOBPCG_FP64}
+_STOP = {"paper": nv.LOBPCG_STOP_PAPER, "norma": nv.LOBPCG_STOP_NORMA}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("liblobpcg needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream():
+    return ct.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ct.c_void_p:
+    return ct.c_void_p(t.data_ptr()) if t is not None else ct.c_void_p(None)
+
+
+def _dev_f64(x, shape=None):
+    torch = _torch()
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+    x = x.to(device="cuda", dtype=torch.float64).contiguous()
+    if shape is not None and tuple(x.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(x.shape)}")
+    return x
+
+
+def make_matrix(A, grid=(0, 0, 0)):
+    """Build the lobpcg_matrix struct for a scipy CSR matrix or a dense numpy array.
+
+    Returns (struct, keepalive) -- keep the second item alive while the struct is used.
+    """
+    M = nv.Matrix()
+    M.grid[0], M.grid[1], M.grid[2] = [int(g) for g in grid]
+    if isinstance(A, np.ndarray):
+        Ad = np.ascontiguousarray(A, dtype=np.float64)
+        M.format = 1
+        M.n = Ad.shape[0]
+        M.ld = Ad.shape[1]
+        M.dense = Ad.ctypes.data
+        return M, (Ad,)
+    import scipy.sparse as sp
+    Ac = sp.csr_matrix(A)
+    rp = np.ascontiguousarray(Ac.indptr, dtype=np.int32)
+    ci = np.ascontiguousarray(Ac.indices, dtype=np.int32)
+    va = np.ascontiguousarray(Ac.data, dtype=np.float64)
+    M.format = 0
+    M.n = Ac.shape[0]
+    M.nnz = va.size
+    M.rowptr = rp.ctypes.data
+    M.colind = ci.ctypes.data
+    M.val = va.ctypes.data
+    return M, (rp, ci, va)
+
+
+def symbolic(A, grid=(0, 0, 0), leaf_size=64):
+    """Host-only ordering and supernode statistics (no GPU)."""
+    lib = nv.load()
+    M, keep = make_matrix(A, grid)
+    perm = np.zeros(M.n, dtype=np.int32)
+    stats = np.zeros(8, dtype=np.float64)
+    nv.check(lib.lobpcg_symbolic(ct.byref(M), leaf_size, perm.ctypes.data, stats.ctypes.data))
+    del keep
+    keys = ["supernodes", "levels", "nnz_factor", "flops", "max_front_rows", "max_supernode_cols",
+            "update_entries", "panel_entries"]
+    return perm, dict(zip(keys, stats.tolist()))
+
+
+class Solver:
+    """k smallest eigenpairs of an SPD matrix with the mixed-precision LOBPCG of Algorithm 3."""
+
+    def __init__(self, A, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
+                 grid=(0, 0, 0), leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
+                 norm_a: float = 0.0, eig_tol: float = 0.0):
+        self.lib = nv.load()
+        _torch()
+        M, keep = make_matrix(A, grid)
+        opt = nv.Options()
+        opt.leaf_size = leaf_size
+        opt.stop_rule = _STOP[stop]
+        opt.qr_lower = 1 if qr_lower else 0
+        opt.norm_a = norm_a
+        opt.eig_tol = eig_tol
+        ctx = ct.c_void_p()
+        self.ctx = None
+        st = self.lib.lobpcg_setup(ct.byref(M), k, m, tol, _PREC[factor_precision], _stream(), ct.byref(opt),
+                                   ct.byref(ctx))
+        del keep
+        nv.check(st)
+        self.ctx = ctx
+        self.n, self.k, self.m = int(M.n), k, m
+        self.factor_precision = factor_precision
+
+    def close(self):
+        if self.ctx is not None:
+            self.lib.lobpcg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, X0=None, maxit: int = 1000, allow_not_converged: bool = False):
+        torch = _torch()
+        x0 = _dev_f64(X0, (self.n, self.m)) if X0 is not None else None
+        evals = torch.empty(self.k, dtype=torch.float64, device="cuda")
+        evecs = torch.empty((self.n, self.k), dtype=torch.float64, device="cuda")
+        info = nv.Info()
+        res = np.zeros(self.k, dtype=np.float64)
+        info.resid = res.ctypes.data
+        allow = (nv.LOBPCG_OK, nv.LOBPCG_NOT_CONVERGED) if allow_not_converged else (nv.LOBPCG_OK,)
+        st = self.lib.lobpcg_solve(self.ctx, _ptr(x0), maxit, _ptr(evals), _ptr(evecs), ct.byref(info))
+        nv.check(st, allow)
+        out = {f: getattr(info, f) for f, _ in nv.Info._fields_ if f != "resid"}
+        out["resid"] = res.copy()
+        out["status"] = st
+        return evals, evecs, out
+
+    def factor(self):
+        nv.check(self.lib.lobpcg_factor(self.ctx))
+
+    def update_values(self, vals=None, shift=None):
+        v = _dev_f64(vals) if vals is not None else None
+        s = _dev_f64(shift, (self.n,)) if shift is not None else None
+        nv.check(self.lib.lobpcg_update_values(self.ctx, _ptr(v), 1, _ptr(s)))
+
+    def backward(self, d_evals=None, d_evecs=None):
+        torch = _torch()
+        de = _dev_f64(d_evals, (self.k,)) if d_evals is not None else None
+        dx = _dev_f64(d_evecs, (self.n, self.k)) if d_evecs is not None else None
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        nv.check(self.lib.lobpcg_backward(self.ctx, _ptr(de), _ptr(dx), _ptr(out)))
+        return out
+
+    def permutation(self) -> np.ndarray:
+        perm = np.zeros(self.n, dtype=np.int32)
+        nv.check(self.lib.lobpcg_get_permutation(self.ctx, perm.ctypes.data))
+        return perm
+
+    def apply_a(self, X):
+        """Y = A_perm X for a device block X (n x c) in the permuted ordering."""
+        torch = _torch()
+        X = _dev_f64(X)
+        c = X.shape[1]
+        Y = torch.empty_like(X)
+        nv.check(self.lib.lobpcg_apply_a(self.ctx, _ptr(X), c, _ptr(Y), c, c))
+        return Y
+
+    def apply_precond(self, R):
+        """W = working(f_T(lower(R))) for R (n x m, permuted ordering)."""
+        torch = _torch()
+        R = _dev_f64(R, (self.n, self.m))
+        W = torch.empty_like(R)
+        nv.check(self.lib.lobpcg_apply_precond(self.ctx, _ptr(R), _ptr(W)))
+        return W
+
+
+def mixed_qr(W, lower: bool = True):
+    """Algorithm 2 on a device block W (n x c); returns (Q, R)."""
+    torch = _torch()
+    lib = nv.load()
+    Q = _dev_f64(W).clone()
+    n, c = Q.shape
+    R = torch.empty((c, c), dtype=torch.float64, device="cuda")
+    nv.check(lib.lobpcg_mixed_qr(_ptr(Q), n, c, c, 1 if lower else 0, _ptr(R), _stream()))
+    return Q, R
+
+
+def gram(X, Y):
+    torch = _torch()
+    lib = nv.load()
+    X = _dev_f64(X)
+    Y = _dev_f64(Y)
+    G = torch.empty((X.shape[1], Y.shape[1]), dtype=torch.float64, device="cuda")
+    nv.check(lib.lobpcg_gram(_ptr(X), X.shape[1], _ptr(Y), Y.shape[1], X.shape[0], X.shape[1], Y.shape[1], _ptr(G),
+                             _stream()))
+    return G
+
+
+def syev_small(H):
+    torch = _torch()
+    lib = nv.load()
+    H = _dev_f64(H)
+    c = H.shape[0]
+    w = torch.empty(c, dtype=torch.float64, device="cuda")
+    V = torch.empty((c, c), dtype=torch.float64, device="cuda")
+    nv.check(lib.lobpcg_syev_small(_ptr(H), c, _ptr(w), _ptr(V), _stream()))
+    return w, V
