@@ -73,7 +73,7 @@ struct lobpcg_ctx_s {
   double *gpart = nullptr, *H = nullptr, *Cev = nullptr, *evals = nullptr, *Gupd = nullptr, *Gc = nullptr;
   double *norms = nullptr, *rpart = nullptr, *syev_work = nullptr;
   void *tsqr_ws = nullptr, *Rl = nullptr;
-  double *Rinv = nullptr, *Gv = nullptr, *Tm = nullptr, *Vtmp = nullptr;
+  double *Gv = nullptr, *Tm = nullptr;
   double norm_a = 0;
   int cur = 0;
   bool solved = false;
@@ -232,18 +232,16 @@ void precond(lobpcg_ctx c, double* W, int64_t ldw) {
     precond_t<double>(c, W, ldw);
 }
 
-// Algorithm 2 on W (n x cc, ld) in place.  lower: step 1 in FP32.  Returns nonzero flag on breakdown
-// (read back synchronously).
+// Algorithm 2 on W (n x cc, ld) in place; flag set on a step-3 breakdown.
 template <typename T>
-void mixed_qr_t(hipStream_t st, double* W, int64_t ld, int64_t n, int cc, void* ws, void* Rl_, double* Rinv,
-                double* Vtmp, double* Gv, double* Tm, double* gpart, int* flag, double* Rout) {
+void mixed_qr_t(hipStream_t st, double* W, int64_t ld, int64_t n, int cc, void* ws, void* Rl_, double* Lt,
+                double* Gv, double* gpart, int* flag, double* Rout) {
   T* Rl = static_cast<T*>(Rl_);
-  launch_tsqr<T>(W, ld, n, cc, static_cast<T*>(ws), Rl, st);                        // step 1
-  launch_trinv_upper<T>(Rl, cc, Rinv, flag, st);
-  launch_block_update(W, ld, Rinv, cc, Vtmp, cc, n, cc, cc, 1.0, 0.0, st);           // step 2: V = W R^{-1}
-  launch_gram(Vtmp, cc, Vtmp, cc, n, cc, cc, Gv, gpart, st);                         // step 3: V^T V
-  launch_alg2_finish<T>(Gv, Rinv, Rl, cc, Tm, Rout, flag, st);                       //         = L L^T
-  launch_block_update(W, ld, Tm, cc, W, ld, n, cc, cc, 1.0, 0.0, st);                // step 4: Q = V L^{-T}
+  launch_tsqr<T>(W, ld, n, cc, static_cast<T*>(ws), Rl, st);      // step 1: lower(W) = Q_l R_l
+  launch_trsm_rows<T>(W, ld, n, cc, Rl, st);                       // step 2: V = W working(R_l)^{-1}
+  launch_gram(W, ld, W, ld, n, cc, cc, Gv, gpart, st);             // step 3: V^T V = L L^T
+  launch_chol_upper<T>(Gv, Rl, cc, Lt, Rout, flag, st);
+  launch_trsm_rows<double>(W, ld, n, cc, Lt, st);                  // step 4: Q = V L^{-T}
 }
 
 lobpcg_status ortho(lobpcg_ctx c, double* W, int64_t ld, int cc) {
@@ -252,11 +250,10 @@ lobpcg_status ortho(lobpcg_ctx c, double* W, int64_t ld, int cc) {
     const bool lower = (attempt == 0) && c->opt.qr_lower;
     HIP_TRY(hipMemsetAsync(c->d_flag + 1, 0, sizeof(int), c->st));
     if (lower)
-      mixed_qr_t<float>(c->st, W, ld, c->n, cc, c->tsqr_ws, c->Rl, c->Rinv, c->Vtmp, c->Gv, c->Tm, c->gpart,
-                        c->d_flag + 1, nullptr);
+      mixed_qr_t<float>(c->st, W, ld, c->n, cc, c->tsqr_ws, c->Rl, c->Tm, c->Gv, c->gpart, c->d_flag + 1, nullptr);
     else
-      mixed_qr_t<double>(c->st, W, ld, c->n, cc, c->tsqr_ws, c->Rl, c->Rinv, c->Vtmp, c->Gv, c->Tm, c->gpart,
-                         c->d_flag + 1, nullptr);
+      mixed_qr_t<double>(c->st, W, ld, c->n, cc, c->tsqr_ws, c->Rl, c->Tm, c->Gv, c->gpart, c->d_flag + 1,
+                         nullptr);
     ST_TRY(check_launch("mixed QR"));
     HIP_TRY(hipMemcpyAsync(&flag, c->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
@@ -435,10 +432,8 @@ lobpcg_status lobpcg_setup(const lobpcg_matrix* A, int32_t k, int32_t m, double 
   SETUP_TRY(C.alloc(C.syev_work, syev_scratch(m3)));
   SETUP_TRY(C.alloc_bytes(C.tsqr_ws, tsqr_scratch_elems(n, m) * 8));
   SETUP_TRY(C.alloc_bytes(C.Rl, (int64_t)m * m * 8));
-  SETUP_TRY(C.alloc(C.Rinv, (int64_t)m * m));
   SETUP_TRY(C.alloc(C.Gv, (int64_t)m * m));
   SETUP_TRY(C.alloc(C.Tm, (int64_t)m * m));
-  SETUP_TRY(C.alloc(C.Vtmp, n * m));
   if (check_launch("setup") != LOBPCG_OK) return cleanup(LOBPCG_ERR_HIP);
   // ---- numeric factorization ----
   {
@@ -699,21 +694,19 @@ lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t cc, int64_t ldw, int
   };
   void* ws = get(tsqr_scratch_elems(n, cc) * 8);
   void* Rl = get((int64_t)cc * cc * 8);
-  double* Rinv = (double*)get((int64_t)cc * cc * 8);
-  double* Vt = (double*)get(n * cc * 8);
   double* Gv = (double*)get((int64_t)cc * cc * 8);
   double* Tm = (double*)get((int64_t)cc * cc * 8);
   double* gp = (double*)get(gram_scratch(n, cc, cc) * 8);
   int* flag = (int*)get(16);
   lobpcg_status s = LOBPCG_OK;
-  if (!ws || !Rl || !Rinv || !Vt || !Gv || !Tm || !gp || !flag) {
+  if (!ws || !Rl || !Gv || !Tm || !gp || !flag) {
     s = fail(LOBPCG_ERR_ALLOC, "hipMalloc failed");
   } else {
     (void)hipMemsetAsync(flag, 0, 16, st);
     if (lower_step1)
-      mixed_qr_t<float>(st, W, ldw, n, cc, ws, Rl, Rinv, Vt, Gv, Tm, gp, flag, R);
+      mixed_qr_t<float>(st, W, ldw, n, cc, ws, Rl, Tm, Gv, gp, flag, R);
     else
-      mixed_qr_t<double>(st, W, ldw, n, cc, ws, Rl, Rinv, Vt, Gv, Tm, gp, flag, R);
+      mixed_qr_t<double>(st, W, ldw, n, cc, ws, Rl, Tm, Gv, gp, flag, R);
     int h = 0;
     s = check_launch("mixed_qr");
     if (s == LOBPCG_OK && hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)

@@ -53,13 +53,12 @@ void launch_syev(const double* H, int64_t ldh, int c, double* evals, double* C, 
 // Hetmaniuk-Lehoucq: from C (c x c) of the Rayleigh-Ritz, G (c x 2m, ld 2m) = [C(:,1:m), C(:,m+1:c) V],
 // V = Householder Q of C(1:m, m+1:c)^T.  If c == m, G = C(:, 1:m) (ld m).
 void launch_hl_build(const double* C, int c, int m, double* G, double* work, hipStream_t st);
-// Algorithm 2 middle steps.  Rl: c x c upper (T, ld c).  Out Rinv (c x c, FP64) = working(Rl)^{-1}.
+// Algorithm 2 steps 2 and 4: W <- W U^{-1} row by row (U c x c upper, row-major, type TU), in place.
+template <typename TU>
+void launch_trsm_rows(double* W, int64_t ld, int64_t n, int c, const TU* U, hipStream_t st);
+// Algorithm 2 step 3: G = V^T V = L L^T; Lt = L^T (c x c row-major); Rout = L^T working(Rl) if non-NULL.
 template <typename T>
-void launch_trinv_upper(const T* Rl, int c, double* Rinv, int* flag, hipStream_t st);
-// From Gram G = V^T V (c x c) and Rinv: L = chol(G); Tm = Rinv L^{-T}; Rout = L^T working(Rl) (optional).
-template <typename T>
-void launch_alg2_finish(const double* G, const double* Rinv, const T* Rl, int c, double* Tm, double* Rout,
-                        int* flag, hipStream_t st);
+void launch_chol_upper(const double* G, const T* Rl, int c, double* Lt, double* Rout, int* flag, hipStream_t st);
 
 // ---- TSQR (k_tsqr.hip): R factor only of an n x c block, Householder in precision T ----
 int64_t tsqr_scratch_elems(int64_t n, int c);   // elements of T

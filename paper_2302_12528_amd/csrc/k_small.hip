@@ -4,8 +4,8 @@
 //    rotations of a round are disjoint and applied together as J^T A J);
 //  * the Hetmaniuk-Lehoucq step (lines 15-16): V = orthonormal factor of
 //    C(1:m, m+1:c)^T and G = [C(:,1:m), C(:,m+1:c) V];
-//  * Algorithm 2's middle steps: inverse of the lower-precision R factor
-//    (step 2), Cholesky of V^T V (step 3) and the combined transform of step 4.
+//  * Algorithm 2's steps 2-4: row-wise triangular solves with the lower-precision
+//    R factor and with L^T, and the Cholesky factorization of V^T V.
 #include <cmath>
 
 #include "common.hpp"
@@ -241,38 +241,51 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   }
 }
 
-template <typename T>
-__global__ void trinv_upper_kernel(const T* __restrict__ Rl, int c, double* __restrict__ Rinv, int* flag) {
-  const int j = threadIdx.x;
-  if (j >= c) return;
-  // column j of inv(R): x_i = (delta_ij - sum_{k>i} r_ik x_k) / r_ii, i = j..0
-  for (int i = c - 1; i > j; --i) Rinv[i * c + j] = 0.0;
-  for (int i = j; i >= 0; --i) {
-    double s = (i == j) ? 1.0 : 0.0;
-    for (int k = i + 1; k <= j; ++k) s -= (double)Rl[i * c + k] * Rinv[k * c + j];
-    const double rii = (double)Rl[i * c + i];
-    if (!(rii != 0.0) || !isfinite(rii)) {
-      flag[0] = 1;
-      Rinv[i * c + j] = 0.0;
-    } else {
-      Rinv[i * c + j] = s / rii;
-    }
+// Algorithm 2 steps 2 and 4: solve Y U = X row by row (U upper triangular, c x c,
+// row-major), in place, by forward substitution over the columns.  One thread
+// owns one row; 64 rows per workgroup are staged through LDS.
+template <typename TU>
+__global__ void __launch_bounds__(64) trsm_rows_kernel(double* W, int64_t ld, int64_t n, int c,
+                                                       const TU* __restrict__ U) {
+  __shared__ double Us[64][65];
+  __shared__ double Ws[64][65];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  for (int e = t; e < c * c; e += 64) {
+    const int i = e / c, j = e % c;
+    Us[i][j] = (double)U[e];
+  }
+  for (int e = t; e < 64 * c; e += 64) {
+    const int i = e / c, j = e % c;
+    Ws[i][j] = (r0 + i < n) ? W[(r0 + i) * ld + j] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < c; ++j) {
+    double s = Ws[t][j];
+    for (int i = 0; i < j; ++i) s -= Ws[t][i] * Us[i][j];
+    Ws[t][j] = s / Us[j][j];
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * c; e += 64) {
+    const int i = e / c, j = e % c;
+    if (r0 + i < n) W[(r0 + i) * ld + j] = Ws[i][j];
   }
 }
 
+// Algorithm 2 step 3: V^T V = L L^T (FP64).  Writes Lt = L^T (upper, row-major) for
+// the step-4 solve, and Rout = L^T working(Rl) (the R factor) when requested.
+// Flags a non-positive or non-finite pivot (W numerically rank deficient).
 template <typename T>
-__global__ void __launch_bounds__(256) alg2_finish_kernel(const double* __restrict__ G, const double* __restrict__ Rinv,
-                                                          const T* __restrict__ Rl, int c, double* __restrict__ Tm,
-                                                          double* __restrict__ Rout, int* flag) {
+__global__ void __launch_bounds__(256) chol_upper_kernel(const double* __restrict__ G, const T* __restrict__ Rl,
+                                                         int c, double* __restrict__ Lt, double* __restrict__ Rout,
+                                                         int* flag) {
   __shared__ double L[64 * 64];
-  __shared__ double Li[64 * 64];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < c * c; e += nt) {
     const int i = e / c, j = e % c;
     L[e] = 0.5 * (G[i * c + j] + G[j * c + i]);
   }
   __syncthreads();
-  // right-looking Cholesky, lower triangle
   for (int j = 0; j < c; ++j) {
     if (tid == 0) {
       double d = L[j * c + j];
@@ -290,26 +303,11 @@ __global__ void __launch_bounds__(256) alg2_finish_kernel(const double* __restri
     }
     __syncthreads();
   }
-  // Li = L^{-1}, column per thread
-  if (tid < c) {
-    const int j = tid;
-    for (int i = 0; i < j; ++i) Li[i * c + j] = 0.0;
-    for (int i = j; i < c; ++i) {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int k = j; k < i; ++k) s -= L[i * c + k] * Li[k * c + j];
-      Li[i * c + j] = s / L[i * c + i];
-    }
-  }
-  __syncthreads();
-  // Tm = Rinv Li^T   (Tm[i][j] = sum_k Rinv[i][k] Li[j][k])
   for (int e = tid; e < c * c; e += nt) {
     const int i = e / c, j = e % c;
-    double s = 0.0;
-    for (int k = 0; k < c; ++k) s += Rinv[i * c + k] * Li[j * c + k];
-    Tm[e] = s;
+    Lt[e] = (j >= i) ? L[j * c + i] : 0.0;
   }
   if (Rout) {
-    // Rout = L^T working(Rl)   (Rout[i][j] = sum_k L[k][i] Rl[k][j])
     for (int e = tid; e < c * c; e += nt) {
       const int i = e / c, j = e % c;
       double s = 0.0;
@@ -339,21 +337,19 @@ void launch_hl_build(const double* C, int c, int m, double* G, double* work, hip
   hl_build_kernel<<<1, kHlThreads, 0, st>>>(C, c, m, G);
 }
 
-template <typename T>
-void launch_trinv_upper(const T* Rl, int c, double* Rinv, int* flag, hipStream_t st) {
-  trinv_upper_kernel<T><<<1, 64, 0, st>>>(Rl, c, Rinv, flag);
+template <typename TU>
+void launch_trsm_rows(double* W, int64_t ld, int64_t n, int c, const TU* U, hipStream_t st) {
+  if (n <= 0) return;
+  trsm_rows_kernel<TU><<<(unsigned)((n + 63) / 64), 64, 0, st>>>(W, ld, n, c, U);
 }
-template void launch_trinv_upper<float>(const float*, int, double*, int*, hipStream_t);
-template void launch_trinv_upper<double>(const double*, int, double*, int*, hipStream_t);
+template void launch_trsm_rows<float>(double*, int64_t, int64_t, int, const float*, hipStream_t);
+template void launch_trsm_rows<double>(double*, int64_t, int64_t, int, const double*, hipStream_t);
 
 template <typename T>
-void launch_alg2_finish(const double* G, const double* Rinv, const T* Rl, int c, double* Tm, double* Rout,
-                        int* flag, hipStream_t st) {
-  alg2_finish_kernel<T><<<1, 256, 0, st>>>(G, Rinv, Rl, c, Tm, Rout, flag);
+void launch_chol_upper(const double* G, const T* Rl, int c, double* Lt, double* Rout, int* flag, hipStream_t st) {
+  chol_upper_kernel<T><<<1, 256, 0, st>>>(G, Rl, c, Lt, Rout, flag);
 }
-template void launch_alg2_finish<float>(const double*, const double*, const float*, int, double*, double*, int*,
-                                        hipStream_t);
-template void launch_alg2_finish<double>(const double*, const double*, const double*, int, double*, double*, int*,
-                                         hipStream_t);
+template void launch_chol_upper<float>(const double*, const float*, int, double*, double*, int*, hipStream_t);
+template void launch_chol_upper<double>(const double*, const double*, int, double*, double*, int*, hipStream_t);
 
 }  // namespace lobpcg
