@@ -58,6 +58,7 @@ struct lobpcg_ctx_s {
   FactorPlan FP;
   SolvePlan SP;
   FactorDev FD{};
+  SolveDev SD{};
   std::vector<void*> allocs;
   // matrix
   int32_t *d_prow = nullptr, *d_pcol = nullptr, *d_vmap = nullptr, *d_perm = nullptr, *d_iperm = nullptr;
@@ -69,7 +70,7 @@ struct lobpcg_ctx_s {
   // iteration
   double* Sb[2] = {nullptr, nullptr};
   double* ASb[2] = {nullptr, nullptr};
-  void *rhs = nullptr, *ybuf = nullptr, *xbuf = nullptr, *uvec = nullptr;
+  void *rhs = nullptr, *ybuf = nullptr, *xbuf = nullptr, *uvec = nullptr, *fpart = nullptr, *bpart = nullptr;
   double *gpart = nullptr, *H = nullptr, *Cev = nullptr, *evals = nullptr, *Gupd = nullptr, *Gc = nullptr;
   double *norms = nullptr, *rpart = nullptr, *syev_work = nullptr;
   void *tsqr_ws = nullptr, *Rl = nullptr;
@@ -207,22 +208,9 @@ lobpcg_status factor(lobpcg_ctx c) {
 // W = working(f_T(lower(rhs))): rhs already holds lower(R) (T, n x mp); W (n x m, ldw)
 template <typename T>
 void precond_t(lobpcg_ctx c, double* W, int64_t ldw) {
-  const Symbolic& S = c->S;
-  T* panel = static_cast<T*>(c->panel);
-  T* rhs = static_cast<T*>(c->rhs);
-  T* y = static_cast<T*>(c->ybuf);
-  T* x = static_cast<T*>(c->xbuf);
-  T* uv = static_cast<T*>(c->uvec);
-  for (int l = 0; l < S.nlevels; ++l) {
-    const int64_t a0 = c->FP.ownrow_level_off[l], a1 = c->FP.ownrow_level_off[l + 1];
-    launch_fwd_assemble<T>(c->FD, a0, a1 - a0, rhs, uv, c->mp, c->st);
-    const int64_t f0 = c->SP.fwd_level_off[l], f1 = c->SP.fwd_level_off[l + 1];
-    launch_fwd_gemm<T>(c->FD, f0, f1 - f0, panel, rhs, y, uv, c->mp, c->st);
-  }
-  for (int l = S.nlevels - 1; l >= 0; --l) {
-    const int64_t b0 = c->SP.bwd_level_off[l], b1 = c->SP.bwd_level_off[l + 1];
-    launch_bwd_gemm<T>(c->FD, b0, b1 - b0, panel, y, x, W, ldw, c->m, c->st);
-  }
+  launch_precond<T>(c->FD, c->SD, c->S.nlevels, c->mp, static_cast<const T*>(c->panel), static_cast<T*>(c->rhs),
+                    static_cast<T*>(c->ybuf), static_cast<T*>(c->xbuf), static_cast<T*>(c->uvec),
+                    static_cast<T*>(c->fpart), static_cast<T*>(c->bpart), W, ldw, c->m, c->st);
 }
 
 void precond(lobpcg_ctx c, double* W, int64_t ldw) {
@@ -330,7 +318,7 @@ lobpcg_status lobpcg_setup(const lobpcg_matrix* A, int32_t k, int32_t m, double 
     return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
   }
   build_factor_plan(C.S, C.FP);
-  build_solve_plan(C.S, 64, C.SP);
+  build_solve_plan(C.S, 64, 256, C.SP);
   std::vector<int32_t> prow, pcol, vmap, apos;
   if (!C.dense) {
     permute_pattern(C.S, A->rowptr, A->colind, prow, pcol, vmap);
@@ -373,8 +361,22 @@ lobpcg_status lobpcg_setup(const lobpcg_matrix* A, int32_t k, int32_t m, double 
   SETUP_TRY(upload(c, D.asm_items, C.FP.asm_items));
   SETUP_TRY(upload(c, D.tasks, C.FP.tasks));
   SETUP_TRY(upload(c, D.ownrow_items, C.FP.ownrow_items));
-  SETUP_TRY(upload(c, D.fwd_items, C.SP.fwd_items));
-  SETUP_TRY(upload(c, D.bwd_items, C.SP.bwd_items));
+  {
+    int32_t *fi = nullptr, *ff = nullptr, *bi = nullptr, *bf = nullptr;
+    SETUP_TRY(upload(c, fi, C.SP.fwd_items));
+    SETUP_TRY(upload(c, ff, C.SP.fwd_fin));
+    SETUP_TRY(upload(c, bi, C.SP.bwd_items));
+    SETUP_TRY(upload(c, bf, C.SP.bwd_fin));
+    C.SD.fwd_items = fi;
+    C.SD.fwd_fin = ff;
+    C.SD.bwd_items = bi;
+    C.SD.bwd_fin = bf;
+    C.SD.fwd_level_off = C.SP.fwd_level_off.data();
+    C.SD.fwd_fin_level_off = C.SP.fwd_fin_level_off.data();
+    C.SD.bwd_level_off = C.SP.bwd_level_off.data();
+    C.SD.bwd_fin_level_off = C.SP.bwd_fin_level_off.data();
+    C.SD.ownrow_level_off = C.FP.ownrow_level_off.data();
+  }
   SETUP_TRY(upload(c, C.d_perm, S.perm));
   SETUP_TRY(upload(c, C.d_iperm, S.iperm));
   if (C.dense) {
@@ -418,6 +420,8 @@ lobpcg_status lobpcg_setup(const lobpcg_matrix* A, int32_t k, int32_t m, double 
   SETUP_TRY(C.alloc_bytes(C.ybuf, n * C.mp * tsz));
   SETUP_TRY(C.alloc_bytes(C.xbuf, n * C.mp * tsz));
   SETUP_TRY(C.alloc_bytes(C.uvec, std::max<int64_t>(1, S.uvec_total) * C.mp * tsz));
+  SETUP_TRY(C.alloc_bytes(C.fpart, std::max<int64_t>(1, C.SP.fwd_slots) * 64 * C.mp * tsz));
+  SETUP_TRY(C.alloc_bytes(C.bpart, std::max<int64_t>(1, C.SP.bwd_slots) * 64 * C.mp * tsz));
   if (hipMemset(C.rhs, 0, n * C.mp * tsz) != hipSuccess) return cleanup(fail(LOBPCG_ERR_HIP, "memset"));
   int64_t gp = std::max(gram_scratch(n, m3, m3), gram_scratch(n, m, m));
   gp = std::max(gp, gram_scratch(n, 2 * m, m));
@@ -630,7 +634,7 @@ lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t
     FactorPlan F;
     SolvePlan P;
     build_factor_plan(S, F);
-    build_solve_plan(S, 64, P);
+    build_solve_plan(S, 64, 256, P);
     std::vector<int32_t> prow, pcol, vmap, apos;
     if (!dense) {
       permute_pattern(S, A->rowptr, A->colind, prow, pcol, vmap);

@@ -72,7 +72,7 @@ struct FactorDev {
   int64_t* panel_off; int64_t* upd_off; int64_t* uvec_off; int64_t* dinv_off; int64_t* lcopy_off;
   int32_t* prow; int32_t* pcol; int32_t* apos; double* aval;   // permuted A (CSR)
   const double* dense; int64_t ld_dense; int is_dense;
-  int32_t* asm_items; int32_t* tasks; int32_t* ownrow_items; int32_t* fwd_items; int32_t* bwd_items;
+  int32_t* asm_items; int32_t* tasks; int32_t* ownrow_items;
 };
 template <typename T>
 void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_off, int count,
@@ -80,16 +80,17 @@ void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_of
                         hipStream_t st);
 
 // ---- supernodal triangular solves (k_trisolve.hip) ----
+struct SolveDev {
+  const int32_t* fwd_items; const int32_t* fwd_fin; const int32_t* bwd_items; const int32_t* bwd_fin;  // device
+  const int64_t* fwd_level_off; const int64_t* fwd_fin_level_off;                                       // host
+  const int64_t* bwd_level_off; const int64_t* bwd_fin_level_off; const int64_t* ownrow_level_off;      // host
+};
+// Both sweeps: rhs (T, n x M, permuted, overwritten by the forward assembly) -> y -> x, and W (FP64, n x mw,
+// ld ldw) = working(x).  fpart / bpart: partial tiles (slots x 64 x M).
 template <typename T>
-void launch_fwd_assemble(const FactorDev& D, int64_t item_off, int64_t count, T* rhs, const T* uvec, int m,
-                         hipStream_t st);
-template <typename T>
-void launch_fwd_gemm(const FactorDev& D, int64_t item_off, int64_t count, const T* panel, const T* rhs, T* y,
-                     T* uvec, int m, hipStream_t st);
-template <typename T>
-void launch_bwd_gemm(const FactorDev& D, int64_t item_off, int64_t count, const T* panel, const T* y, T* x,
-                     double* W, int64_t ldw, int m, hipStream_t st);
-// rhs (T, n x m) = lower(R) given R FP64 (n x m, ld)
+void launch_precond(const FactorDev& D, const SolveDev& Sd, int nlevels, int M, const T* panel, T* rhs, T* y, T* x,
+                    T* uvec, T* fpart, T* bpart, double* W, int64_t ldw, int mw, hipStream_t st);
+// rhs (T, n x M padded with zeros) = lower(R) given R FP64 (n x m, ld)
 template <typename T>
 void launch_cast_to(const double* src, int64_t lds, T* dst, int64_t n, int m, hipStream_t st);
 

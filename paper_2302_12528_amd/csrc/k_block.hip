@@ -143,18 +143,27 @@ __global__ void __launch_bounds__(kThreads) gram_partial_kernel(const double* __
   if (ib < c1 && jb < c2) P[ib * c2 + jb] = acc11;
 }
 
-__global__ void reduce_parts_kernel(const double* __restrict__ part, int nb, int len, double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= len) return;
+// out[e] = sum_b part[b][e] in a fixed order: four interleaved partial sums per output
+// (b = g, g + 4, ...), combined in order g = 0..3.
+__global__ void __launch_bounds__(256) reduce_parts_kernel(const double* __restrict__ part, int nb, int len,
+                                                           double* __restrict__ out) {
+  __shared__ double red[4][64];
+  const int g = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int e = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * len + e];
-  out[e] = s;
+  if (e < len) {
+#pragma unroll 4
+    for (int b = g; b < nb; b += 4) s += part[(int64_t)b * len + e];
+  }
+  red[g][lane] = s;
+  __syncthreads();
+  if (g == 0 && e < len) out[e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 int gram_chunks(int64_t n, int c1, int c2) {
   const int tiles = ceil_div(c1, 32) * ceil_div(c2, 32);
   int chunks = ceil_div(n, 256);
-  const int target = (2048 + tiles - 1) / tiles;
+  const int target = (1024 + tiles - 1) / tiles;
   if (chunks > target) chunks = target;
   if (chunks < 1) chunks = 1;
   return chunks;
@@ -336,7 +345,7 @@ void launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int
   dim3 g(chunks, ceil_div(c1, 32) * tj);
   gram_partial_kernel<<<g, kThreads, 0, st>>>(X, ldx, Y, ldy, n, c1, c2, rpc, tj, part);
   const int len = c1 * c2;
-  reduce_parts_kernel<<<ceil_div(len, kThreads), kThreads, 0, st>>>(part, chunks, len, G);
+  reduce_parts_kernel<<<ceil_div(len, 64), 256, 0, st>>>(part, chunks, len, G);
 }
 
 void launch_block_update(const double* X, int64_t ldx, const double* M, int64_t ldm, double* Y, int64_t ldy,
@@ -354,7 +363,7 @@ void launch_residual(const double* AX, int64_t ldax, const double* X, int64_t ld
   const int nb = resid_blocks(n);
   const int64_t rpb = (n + nb - 1) / nb;
   residual_kernel<T><<<nb, kThreads, 0, st>>>(AX, ldax, X, ldx, theta, n, m, rpb, R, ldr, part);
-  reduce_parts_kernel<<<ceil_div(2 * m, kThreads), kThreads, 0, st>>>(part, nb, 2 * m, norms);
+  reduce_parts_kernel<<<ceil_div(2 * m, 64), 256, 0, st>>>(part, nb, 2 * m, norms);
 }
 template void launch_residual<float>(const double*, int64_t, const double*, int64_t, const double*, int64_t, int,
                                      float*, int64_t, double*, double*, hipStream_t);
@@ -365,7 +374,7 @@ void launch_colnorms(const double* X, int64_t ldx, int64_t n, int c, double* nor
   const int nb = resid_blocks(n);
   const int64_t rpb = (n + nb - 1) / nb;
   colnorm_kernel<<<nb, kThreads, 0, st>>>(X, ldx, n, c, rpb, part);
-  reduce_parts_kernel<<<ceil_div(c, kThreads), kThreads, 0, st>>>(part, nb, c, norms);
+  reduce_parts_kernel<<<ceil_div(c, 64), 256, 0, st>>>(part, nb, c, norms);
 }
 
 void launch_gather_rows(const double* src, int64_t lds, const int32_t* idx, double* dst, int64_t ldd, int64_t nrows,
@@ -405,7 +414,7 @@ void launch_cast_f32_f64(const float* src, int64_t lds, double* dst, int64_t ldd
 }
 
 void launch_reduce_parts(const double* part, int nb, int len, double* out, hipStream_t st) {
-  reduce_parts_kernel<<<ceil_div(len, kThreads), kThreads, 0, st>>>(part, nb, len, out);
+  reduce_parts_kernel<<<ceil_div(len, 64), 256, 0, st>>>(part, nb, len, out);
 }
 
 }  // namespace lobpcg

@@ -161,14 +161,15 @@ constexpr int kHlMaxM = 64;
 
 __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __restrict__ C, int c, int m,
                                                               double* __restrict__ G) {
-  __shared__ double z[kHlMaxR * kHlMaxM];
-  __shared__ double qm[kHlMaxR * kHlMaxM];
+  __shared__ double z[kHlMaxR * (kHlMaxM + 1)];
+  __shared__ double qm[kHlMaxR * (kHlMaxM + 1)];
   __shared__ double tau[kHlMaxM];
   __shared__ double wv[kHlMaxM];
   __shared__ double red[kHlThreads / 64];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid % 64, wid = tid / 64, nw = nt / 64;
   const int r = c - m;
+  const int lz = m + 1;   // odd LDS row stride
   const int ldg = (r > 0) ? 2 * m : m;
   // copy C(:, 0:m)
   for (int e = tid; e < c * m; e += nt) {
@@ -178,16 +179,16 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   if (r <= 0) return;
   for (int e = tid; e < r * m; e += nt) {
     const int i = e / m, j = e % m;
-    z[i * m + j] = C[(int64_t)j * c + m + i];
-    qm[i * m + j] = (i == j) ? 1.0 : 0.0;
+    z[i * lz + j] = C[(int64_t)j * c + m + i];
+    qm[i * lz + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int kmax = (m < r) ? m : r;
   for (int j = 0; j < kmax; ++j) {
     double s = 0.0;
-    for (int i = j + 1 + tid; i < r; i += nt) s += z[i * m + j] * z[i * m + j];
+    for (int i = j + 1 + tid; i < r; i += nt) s += z[i * lz + j] * z[i * lz + j];
     s = block_sum(s, red);
-    const double alpha = z[j * m + j];
+    const double alpha = z[j * lz + j];
     const double xn = sqrt(alpha * alpha + s);
     double tj = 0.0, beta = alpha, scale = 0.0;
     if (s > 0.0) {
@@ -197,21 +198,21 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
     }
     __syncthreads();
     if (s > 0.0)
-      for (int i = j + 1 + tid; i < r; i += nt) z[i * m + j] *= scale;
-    if (tid == 0) { tau[j] = tj; z[j * m + j] = beta; }
+      for (int i = j + 1 + tid; i < r; i += nt) z[i * lz + j] *= scale;
+    if (tid == 0) { tau[j] = tj; z[j * lz + j] = beta; }
     __syncthreads();
     // apply H_j = I - tau v v^T (v_j = 1) to columns k > j
     for (int k = j + 1 + wid; k < m; k += nw) {
       double w = 0.0;
-      for (int i = j + lane; i < r; i += 64) w += (i == j ? 1.0 : z[i * m + j]) * z[i * m + k];
+      for (int i = j + lane; i < r; i += 64) w += (i == j ? 1.0 : z[i * lz + j]) * z[i * lz + k];
       w = wave_sum(w);
       if (lane == 0) wv[k] = w;
     }
     __syncthreads();
     for (int e = tid; e < (r - j) * (m - j - 1); e += nt) {
       const int i = j + e / (m - j - 1), k = j + 1 + e % (m - j - 1);
-      const double vi = (i == j) ? 1.0 : z[i * m + j];
-      z[i * m + k] -= tj * vi * wv[k];
+      const double vi = (i == j) ? 1.0 : z[i * lz + j];
+      z[i * lz + k] -= tj * vi * wv[k];
     }
     __syncthreads();
   }
@@ -220,15 +221,15 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
     const double tj = tau[j];
     for (int k = wid; k < m; k += nw) {
       double w = 0.0;
-      for (int i = j + lane; i < r; i += 64) w += (i == j ? 1.0 : z[i * m + j]) * qm[i * m + k];
+      for (int i = j + lane; i < r; i += 64) w += (i == j ? 1.0 : z[i * lz + j]) * qm[i * lz + k];
       w = wave_sum(w);
       if (lane == 0) wv[k] = w;
     }
     __syncthreads();
     for (int e = tid; e < (r - j) * m; e += nt) {
       const int i = j + e / m, k = e % m;
-      const double vi = (i == j) ? 1.0 : z[i * m + j];
-      qm[i * m + k] -= tj * vi * wv[k];
+      const double vi = (i == j) ? 1.0 : z[i * lz + j];
+      qm[i * lz + k] -= tj * vi * wv[k];
     }
     __syncthreads();
   }
@@ -236,39 +237,39 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   for (int e = tid; e < c * m; e += nt) {
     const int i = e / m, j = e % m;
     double acc = 0.0;
-    for (int k = 0; k < r; ++k) acc += C[(int64_t)i * c + m + k] * qm[k * m + j];
+    for (int k = 0; k < r; ++k) acc += C[(int64_t)i * c + m + k] * qm[k * lz + j];
     G[(int64_t)i * ldg + m + j] = acc;
   }
 }
 
 // Algorithm 2 steps 2 and 4: solve Y U = X row by row (U upper triangular, c x c,
 // row-major), in place, by forward substitution over the columns.  One thread
-// owns one row; 64 rows per workgroup are staged through LDS.
+// owns one row; 64 rows per workgroup sit in LDS column-major (Ws[j*64 + t]),
+// so the lanes of a wave read consecutive words, and U is broadcast from LDS.
 template <typename TU>
 __global__ void __launch_bounds__(64) trsm_rows_kernel(double* W, int64_t ld, int64_t n, int c,
                                                        const TU* __restrict__ U) {
-  __shared__ double Us[64][65];
-  __shared__ double Ws[64][65];
+  extern __shared__ double smem[];
+  double* Us = smem;            // c x c
+  double* Ws = smem + c * c;    // c x 64
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * 64;
-  for (int e = t; e < c * c; e += 64) {
-    const int i = e / c, j = e % c;
-    Us[i][j] = (double)U[e];
-  }
+  for (int e = t; e < c * c; e += 64) Us[e] = (double)U[e];
   for (int e = t; e < 64 * c; e += 64) {
     const int i = e / c, j = e % c;
-    Ws[i][j] = (r0 + i < n) ? W[(r0 + i) * ld + j] : 0.0;
+    Ws[j * 64 + i] = (r0 + i < n) ? W[(r0 + i) * ld + j] : 0.0;
   }
   __syncthreads();
   for (int j = 0; j < c; ++j) {
-    double s = Ws[t][j];
-    for (int i = 0; i < j; ++i) s -= Ws[t][i] * Us[i][j];
-    Ws[t][j] = s / Us[j][j];
+    double s = Ws[j * 64 + t];
+#pragma unroll 4
+    for (int i = 0; i < j; ++i) s -= Ws[i * 64 + t] * Us[i * c + j];
+    Ws[j * 64 + t] = s / Us[j * c + j];
   }
   __syncthreads();
   for (int e = t; e < 64 * c; e += 64) {
     const int i = e / c, j = e % c;
-    if (r0 + i < n) W[(r0 + i) * ld + j] = Ws[i][j];
+    if (r0 + i < n) W[(r0 + i) * ld + j] = Ws[j * 64 + i];
   }
 }
 
@@ -340,7 +341,8 @@ void launch_hl_build(const double* C, int c, int m, double* G, double* work, hip
 template <typename TU>
 void launch_trsm_rows(double* W, int64_t ld, int64_t n, int c, const TU* U, hipStream_t st) {
   if (n <= 0) return;
-  trsm_rows_kernel<TU><<<(unsigned)((n + 63) / 64), 64, 0, st>>>(W, ld, n, c, U);
+  const size_t lds = (size_t)(c * c + 64 * c) * sizeof(double);
+  trsm_rows_kernel<TU><<<(unsigned)((n + 63) / 64), 64, lds, st>>>(W, ld, n, c, U);
 }
 template void launch_trsm_rows<float>(double*, int64_t, int64_t, int, const float*, hipStream_t);
 template void launch_trsm_rows<double>(double*, int64_t, int64_t, int, const double*, hipStream_t);

@@ -1,6 +1,6 @@
 // Preconditioner application W_l = L^{-T} L^{-1} lower(R) in the factor's
 // precision T (Algorithm 3 lines 9-10; section 5.1's two triangular solves),
-// over the supernodal elimination tree, one launch per level and direction.
+// over the supernodal elimination tree, level by level.
 //
 // After factorization each supernode's panel holds P_s = [inv(L11); L21 inv(L11)]
 // (nr x nc, column-major), so with b_s the right-hand side at its own rows
@@ -8,23 +8,27 @@
 //             subtracted from the rows below (passed up the tree in a
 //             per-supernode update vector, pulled by the parent; no atomics);
 //   backward: x_s = P_s^T [y_s; -x_below] = inv(L11)^T (y_s - L21^T x_below).
-// Right-hand sides are n x M row-major blocks (M = padded block size) in the
-// permuted ordering; tiles of 64 rows of P_s are streamed through LDS with the
-// matching rows of the right-hand side.
+// Each level is a batch of independent tile products: an output tile of 64
+// rows x M right-hand sides over a chunk of the reduction dimension.  Tiles
+// whose reduction is split write partial tiles that a finalize pass sums in a
+// fixed order.  P is streamed through LDS with the next stage prefetched into
+// registers while the current one is consumed; each thread owns a 4 x CT
+// register tile.
 #include "common.hpp"
 
 namespace lobpcg {
 
 namespace {
 
-constexpr int RT_ROWS = 64;
-constexpr int KC = 32;
+constexpr int TR = 64;   // output tile rows
 
 template <int M> struct Shape;
-template <> struct Shape<8>  { static constexpr int RT = 2, CT = 1; };
-template <> struct Shape<16> { static constexpr int RT = 2, CT = 2; };
-template <> struct Shape<32> { static constexpr int RT = 4, CT = 2; };
-template <> struct Shape<64> { static constexpr int RT = 4, CT = 4; };
+template <> struct Shape<8>  { static constexpr int CT = 2; };
+template <> struct Shape<16> { static constexpr int CT = 4; };
+template <> struct Shape<32> { static constexpr int CT = 4; };
+template <> struct Shape<64> { static constexpr int CT = 4; };
+
+template <int M> constexpr int threads_for() { return (M / Shape<M>::CT) * (TR / 4); }
 
 template <typename T>
 __global__ void __launch_bounds__(256) fwd_assemble_kernel(FactorDev D, int64_t item_off, int64_t count, T* rhs,
@@ -43,141 +47,257 @@ __global__ void __launch_bounds__(256) fwd_assemble_kernel(FactorDev D, int64_t 
   rhs[(int64_t)(D.begin[s] + r) * M + lane] = v;
 }
 
+// Forward epilogue for one output row of supernode s: own rows -> y, below rows -> update vector.
+template <typename T, int CT>
+__device__ inline void fwd_store(const FactorDev& D, int s, int row, int col0, const T* acc, T* y, T* uvec, int M) {
+  const int nc = D.nc[s];
+  if (row < nc) {
+#pragma unroll
+    for (int j = 0; j < CT; ++j) y[(int64_t)(D.begin[s] + row) * M + col0 + j] = acc[j];
+    return;
+  }
+  T pass[CT];
+#pragma unroll
+  for (int j = 0; j < CT; ++j) pass[j] = 0;
+  for (int q = D.child_ptr[s]; q < D.child_ptr[s + 1]; ++q) {
+    const int c = D.child_list[q];
+    const int jr = D.invmap[D.inv_off[c] + row];
+    if (jr >= 0)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) pass[j] += uvec[(D.uvec_off[c] + jr) * M + col0 + j];
+  }
+#pragma unroll
+  for (int j = 0; j < CT; ++j) uvec[(D.uvec_off[s] + row - nc) * M + col0 + j] = pass[j] - acc[j];
+}
+
+// out tile (64 x M) = P_s[r0:r0+64, k0:k1] * rhs[begin+k0 : begin+k1, :]
 template <typename T, int M>
-__global__ void __launch_bounds__(256) fwd_gemm_kernel(FactorDev D, int64_t item_off, const T* __restrict__ panel,
-                                                       const T* __restrict__ rhs, T* __restrict__ y,
-                                                       T* __restrict__ uvec) {
-  constexpr int RT = Shape<M>::RT, CT = Shape<M>::CT;
-  constexpr int NCG = M / CT, NRG = RT_ROWS / RT;
-  static_assert(NCG * NRG == 256, "thread layout");
-  __shared__ T Ps[KC][RT_ROWS + 1];
+__global__ void __launch_bounds__(threads_for<M>()) fwd_gemm_kernel(FactorDev D, const int32_t* __restrict__ items,
+                                                                    int64_t item_off, const T* __restrict__ panel,
+                                                                    const T* __restrict__ rhs, T* __restrict__ y,
+                                                                    T* __restrict__ uvec, T* __restrict__ part) {
+  constexpr int CT = Shape<M>::CT, NCG = M / CT, NT = threads_for<M>();
+  constexpr int KC = 32;
+  constexpr int PL = KC * TR / NT;   // P values per thread per stage
+  constexpr int BL = KC * M / NT;    // rhs values per thread per stage
+  __shared__ T Ps[KC][TR + 1];
   __shared__ T Bs[KC][M];
   const int tid = threadIdx.x;
-  const int s = D.fwd_items[2 * (item_off + blockIdx.x)];
-  const int tile = D.fwd_items[2 * (item_off + blockIdx.x) + 1];
-  const int begin = D.begin[s], nc = D.nc[s], nr = D.nr[s];
+  const int* it = items + 5 * (item_off + blockIdx.x);
+  const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
+  const int begin = D.begin[s], nr = D.nr[s];
   const int64_t poff = D.panel_off[s];
-  const int r0 = tile * RT_ROWS;
-  const int h = min(RT_ROWS, nr - r0);
-  const int kmax = (r0 < nc) ? min(nc, r0 + RT_ROWS) : nc;
+  const int r0 = tile * TR;
+  const int h = min(TR, nr - r0);
   const int cg = tid % NCG, rg = tid / NCG;
-  T acc[RT][CT];
+  T acc[4][CT];
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = 0;
-  for (int k0 = 0; k0 < kmax; k0 += KC) {
-    for (int e = tid; e < KC * RT_ROWS; e += 256) {
-      const int r = e % RT_ROWS, kk = e / RT_ROWS;
-      Ps[kk][r] = (r < h && k0 + kk < kmax) ? panel[poff + (int64_t)(k0 + kk) * nr + r0 + r] : (T)0;
+  T pr[PL], br[BL];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int e = tid + NT * q;
+      const int r = e % TR, kk = e / TR;
+      pr[q] = (r < h && kc + kk < k1) ? panel[poff + (int64_t)(kc + kk) * nr + r0 + r] : (T)0;
     }
-    for (int e = tid; e < KC * M; e += 256) {
+#pragma unroll
+    for (int q = 0; q < BL; ++q) {
+      const int e = tid + NT * q;
       const int kk = e / M, j = e % M;
-      Bs[kk][j] = (k0 + kk < kmax) ? rhs[(int64_t)(begin + k0 + kk) * M + j] : (T)0;
+      br[q] = (kc + kk < k1) ? rhs[(int64_t)(begin + kc + kk) * M + j] : (T)0;
+    }
+  };
+  load(k0);
+  for (int kc = k0; kc < k1; kc += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int e = tid + NT * q;
+      Ps[e / TR][e % TR] = pr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < BL; ++q) {
+      const int e = tid + NT * q;
+      Bs[e / M][e % M] = br[q];
     }
     __syncthreads();
-#pragma unroll 4
+    if (kc + KC < k1) load(kc + KC);
+#pragma unroll 8
     for (int k = 0; k < KC; ++k) {
-      T a[RT], b[CT];
+      T a[4], b[CT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) a[i] = Ps[k][rg + NRG * i];
+      for (int i = 0; i < 4; ++i) a[i] = Ps[k][rg + 16 * i];
 #pragma unroll
       for (int j = 0; j < CT; ++j) b[j] = Bs[k][cg * CT + j];
 #pragma unroll
-      for (int i = 0; i < RT; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
-    __syncthreads();
   }
-  const int c0 = D.child_ptr[s], c1 = D.child_ptr[s + 1];
-  const int64_t uoff = D.uvec_off[s];
 #pragma unroll
-  for (int i = 0; i < RT; ++i) {
-    const int row = r0 + rg + NRG * i;
-    if (row >= r0 + h) continue;
-    if (row < nc) {
-#pragma unroll
-      for (int j = 0; j < CT; ++j) y[(int64_t)(begin + row) * M + cg * CT + j] = acc[i][j];
+  for (int i = 0; i < 4; ++i) {
+    const int rr = rg + 16 * i;
+    if (rr >= h) continue;
+    if (slot < 0) {
+      fwd_store<T, CT>(D, s, r0 + rr, cg * CT, acc[i], y, uvec, M);
     } else {
-      T pass[CT];
+      T* dst = part + ((int64_t)slot * TR + rr) * M + cg * CT;
 #pragma unroll
-      for (int j = 0; j < CT; ++j) pass[j] = 0;
-      for (int q = c0; q < c1; ++q) {
-        const int c = D.child_list[q];
-        const int jr = D.invmap[D.inv_off[c] + row];
-        if (jr >= 0)
-#pragma unroll
-          for (int j = 0; j < CT; ++j) pass[j] += uvec[(D.uvec_off[c] + jr) * M + cg * CT + j];
-      }
-#pragma unroll
-      for (int j = 0; j < CT; ++j) uvec[(uoff + row - nc) * M + cg * CT + j] = pass[j] - acc[i][j];
+      for (int j = 0; j < CT; ++j) dst[j] = acc[i][j];
     }
   }
 }
 
 template <typename T, int M>
-__global__ void __launch_bounds__(256) bwd_gemm_kernel(FactorDev D, int64_t item_off, const T* __restrict__ panel,
-                                                       const T* __restrict__ y, T* __restrict__ x, double* W,
-                                                       int64_t ldw, int mw) {
-  constexpr int RT = Shape<M>::RT, CT = Shape<M>::CT;
-  constexpr int NCG = M / CT, NRG = RT_ROWS / RT;
-  __shared__ T Ps[KC][RT_ROWS + 1];
+__global__ void __launch_bounds__(threads_for<M>()) fwd_fin_kernel(FactorDev D, const int32_t* __restrict__ fin,
+                                                                   int64_t fin_off, const T* __restrict__ part,
+                                                                   T* __restrict__ y, T* __restrict__ uvec) {
+  constexpr int CT = Shape<M>::CT, NCG = M / CT;
+  const int* f = fin + 4 * (fin_off + blockIdx.x);
+  const int s = f[0], tile = f[1], slot0 = f[2], nch = f[3];
+  const int r0 = tile * TR;
+  const int h = min(TR, D.nr[s] - r0);
+  const int cg = threadIdx.x % NCG, rg = threadIdx.x / NCG;
+  for (int i = 0; i < 4; ++i) {
+    const int rr = rg + 16 * i;
+    if (rr >= h) continue;
+    T acc[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[j] = 0;
+    for (int q = 0; q < nch; ++q) {
+      const T* src = part + ((int64_t)(slot0 + q) * TR + rr) * M + cg * CT;
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[j] += src[j];
+    }
+    fwd_store<T, CT>(D, s, r0 + rr, cg * CT, acc, y, uvec, M);
+  }
+}
+
+// out tile (64 own columns x M) = P_s[k0:k1, j0:j0+64]^T z[k0:k1, :],  z = [y_s; -x_below]
+template <typename T, int M>
+__global__ void __launch_bounds__(threads_for<M>()) bwd_gemm_kernel(FactorDev D, const int32_t* __restrict__ items,
+                                                                    int64_t item_off, const T* __restrict__ panel,
+                                                                    const T* __restrict__ y, T* __restrict__ x,
+                                                                    double* W, int64_t ldw, int mw,
+                                                                    T* __restrict__ part) {
+  constexpr int CT = Shape<M>::CT, NCG = M / CT, NT = threads_for<M>();
+  constexpr int KC = 64;
+  constexpr int PL = KC * TR / NT;
+  constexpr int BL = KC * M / NT;
+  __shared__ T Ps[KC][TR + 1];
   __shared__ T Zs[KC][M];
   const int tid = threadIdx.x;
-  const int s = D.bwd_items[2 * (item_off + blockIdx.x)];
-  const int tile = D.bwd_items[2 * (item_off + blockIdx.x) + 1];
+  const int* it = items + 5 * (item_off + blockIdx.x);
+  const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
   const int begin = D.begin[s], nc = D.nc[s], nr = D.nr[s];
   const int64_t poff = D.panel_off[s];
   const int64_t roff = D.row_off[s];
-  const int j0 = tile * RT_ROWS;
-  const int h = min(RT_ROWS, nc - j0);
+  const int j0 = tile * TR;
+  const int h = min(TR, nc - j0);
   const int cg = tid % NCG, rg = tid / NCG;
-  T acc[RT][CT];
+  T acc[4][CT];
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc[i][j] = 0;
-  for (int k0 = j0; k0 < nr; k0 += KC) {
-    for (int e = tid; e < KC * RT_ROWS; e += 256) {
+  T pr[PL], zr[BL];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int e = tid + NT * q;
       const int kk = e % KC, jj = e / KC;
-      Ps[kk][jj] = (jj < h && k0 + kk < nr) ? panel[poff + (int64_t)(j0 + jj) * nr + k0 + kk] : (T)0;
+      pr[q] = (jj < h && kc + kk < k1) ? panel[poff + (int64_t)(j0 + jj) * nr + kc + kk] : (T)0;
     }
-    for (int e = tid; e < KC * M; e += 256) {
+#pragma unroll
+    for (int q = 0; q < BL; ++q) {
+      const int e = tid + NT * q;
       const int kk = e / M, j = e % M;
-      const int r = k0 + kk;
+      const int r = kc + kk;
       T v = 0;
-      if (r < nc)
-        v = y[(int64_t)(begin + r) * M + j];
-      else if (r < nr)
-        v = -x[(int64_t)D.rows[roff + r] * M + j];
-      Zs[kk][j] = v;
+      if (r < k1) v = (r < nc) ? y[(int64_t)(begin + r) * M + j] : -x[(int64_t)D.rows[roff + r] * M + j];
+      zr[q] = v;
+    }
+  };
+  load(k0);
+  for (int kc = k0; kc < k1; kc += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int e = tid + NT * q;
+      Ps[e % KC][e / KC] = pr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < BL; ++q) {
+      const int e = tid + NT * q;
+      Zs[e / M][e % M] = zr[q];
     }
     __syncthreads();
-#pragma unroll 4
+    if (kc + KC < k1) load(kc + KC);
+#pragma unroll 8
     for (int k = 0; k < KC; ++k) {
-      T a[RT], b[CT];
+      T a[4], b[CT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) a[i] = Ps[k][rg + NRG * i];
+      for (int i = 0; i < 4; ++i) a[i] = Ps[k][rg + 16 * i];
 #pragma unroll
       for (int j = 0; j < CT; ++j) b[j] = Zs[k][cg * CT + j];
 #pragma unroll
-      for (int i = 0; i < RT; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
-    __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < RT; ++i) {
-    const int jj = rg + NRG * i;
+  for (int i = 0; i < 4; ++i) {
+    const int jj = rg + 16 * i;
     if (jj >= h) continue;
-    const int64_t row = begin + j0 + jj;
+    if (slot < 0) {
+      const int64_t row = begin + j0 + jj;
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        const int col = cg * CT + j;
+        x[row * M + col] = acc[i][j];
+        if (W && col < mw) W[row * ldw + col] = (double)acc[i][j];
+      }
+    } else {
+      T* dst = part + ((int64_t)slot * TR + jj) * M + cg * CT;
+#pragma unroll
+      for (int j = 0; j < CT; ++j) dst[j] = acc[i][j];
+    }
+  }
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(threads_for<M>()) bwd_fin_kernel(FactorDev D, const int32_t* __restrict__ fin,
+                                                                   int64_t fin_off, const T* __restrict__ part,
+                                                                   T* __restrict__ x, double* W, int64_t ldw,
+                                                                   int mw) {
+  constexpr int CT = Shape<M>::CT, NCG = M / CT;
+  const int* f = fin + 4 * (fin_off + blockIdx.x);
+  const int s = f[0], tile = f[1], slot0 = f[2], nch = f[3];
+  const int j0 = tile * TR;
+  const int h = min(TR, D.nc[s] - j0);
+  const int cg = threadIdx.x % NCG, rg = threadIdx.x / NCG;
+  for (int i = 0; i < 4; ++i) {
+    const int jj = rg + 16 * i;
+    if (jj >= h) continue;
+    T acc[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[j] = 0;
+    for (int q = 0; q < nch; ++q) {
+      const T* src = part + ((int64_t)(slot0 + q) * TR + jj) * M + cg * CT;
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[j] += src[j];
+    }
+    const int64_t row = D.begin[s] + j0 + jj;
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
       const int col = cg * CT + j;
-      x[row * M + col] = acc[i][j];
-      if (W && col < mw) W[row * ldw + col] = (double)acc[i][j];
+      x[row * M + col] = acc[j];
+      if (W && col < mw) W[row * ldw + col] = (double)acc[j];
     }
   }
 }
@@ -192,37 +312,43 @@ __global__ void cast_to_kernel(const double* __restrict__ src, int64_t lds, T* _
   dst[e] = (j < m) ? (T)src[i * lds + j] : (T)0;
 }
 
-}  // namespace
-
-template <typename T>
-void launch_fwd_assemble(const FactorDev& D, int64_t item_off, int64_t count, T* rhs, const T* uvec, int M,
-                         hipStream_t st) {
-  if (count <= 0) return;
-  fwd_assemble_kernel<T><<<(unsigned)((count + 3) / 4), 256, 0, st>>>(D, item_off, count, rhs, uvec, M);
-}
-
-template <typename T>
-void launch_fwd_gemm(const FactorDev& D, int64_t item_off, int64_t count, const T* panel, const T* rhs, T* y,
-                     T* uvec, int M, hipStream_t st) {
-  if (count <= 0) return;
-  switch (M) {
-    case 8: fwd_gemm_kernel<T, 8><<<(unsigned)count, 256, 0, st>>>(D, item_off, panel, rhs, y, uvec); break;
-    case 16: fwd_gemm_kernel<T, 16><<<(unsigned)count, 256, 0, st>>>(D, item_off, panel, rhs, y, uvec); break;
-    case 32: fwd_gemm_kernel<T, 32><<<(unsigned)count, 256, 0, st>>>(D, item_off, panel, rhs, y, uvec); break;
-    default: fwd_gemm_kernel<T, 64><<<(unsigned)count, 256, 0, st>>>(D, item_off, panel, rhs, y, uvec); break;
+template <typename T, int M>
+void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* panel, T* rhs, T* y, T* x, T* uvec,
+                 T* fpart, T* bpart, double* W, int64_t ldw, int mw, bool forward, hipStream_t st) {
+  constexpr int NT = threads_for<M>();
+  if (forward) {
+    const int64_t a0 = Sd.ownrow_level_off[level], a1 = Sd.ownrow_level_off[level + 1];
+    if (a1 > a0) fwd_assemble_kernel<T><<<(unsigned)((a1 - a0 + 3) / 4), 256, 0, st>>>(D, a0, a1 - a0, rhs, uvec, M);
+    const int64_t f0 = Sd.fwd_level_off[level], f1 = Sd.fwd_level_off[level + 1];
+    if (f1 > f0)
+      fwd_gemm_kernel<T, M><<<(unsigned)(f1 - f0), NT, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);
+    const int64_t g0 = Sd.fwd_fin_level_off[level], g1 = Sd.fwd_fin_level_off[level + 1];
+    if (g1 > g0) fwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), NT, 0, st>>>(D, Sd.fwd_fin, g0, fpart, y, uvec);
+  } else {
+    const int64_t b0 = Sd.bwd_level_off[level], b1 = Sd.bwd_level_off[level + 1];
+    if (b1 > b0)
+      bwd_gemm_kernel<T, M><<<(unsigned)(b1 - b0), NT, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W, ldw, mw, bpart);
+    const int64_t g0 = Sd.bwd_fin_level_off[level], g1 = Sd.bwd_fin_level_off[level + 1];
+    if (g1 > g0) bwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), NT, 0, st>>>(D, Sd.bwd_fin, g0, bpart, x, W, ldw, mw);
   }
 }
 
+}  // namespace
+
 template <typename T>
-void launch_bwd_gemm(const FactorDev& D, int64_t item_off, int64_t count, const T* panel, const T* y, T* x,
-                     double* W, int64_t ldw, int m, hipStream_t st) {
-  if (count <= 0) return;
-  int M = m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64;
-  switch (M) {
-    case 8: bwd_gemm_kernel<T, 8><<<(unsigned)count, 256, 0, st>>>(D, item_off, panel, y, x, W, ldw, m); break;
-    case 16: bwd_gemm_kernel<T, 16><<<(unsigned)count, 256, 0, st>>>(D, item_off, panel, y, x, W, ldw, m); break;
-    case 32: bwd_gemm_kernel<T, 32><<<(unsigned)count, 256, 0, st>>>(D, item_off, panel, y, x, W, ldw, m); break;
-    default: bwd_gemm_kernel<T, 64><<<(unsigned)count, 256, 0, st>>>(D, item_off, panel, y, x, W, ldw, m); break;
+void launch_precond(const FactorDev& D, const SolveDev& Sd, int nlevels, int M, const T* panel, T* rhs, T* y, T* x,
+                    T* uvec, T* fpart, T* bpart, double* W, int64_t ldw, int mw, hipStream_t st) {
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fwd = (pass == 0);
+    for (int q = 0; q < nlevels; ++q) {
+      const int l = fwd ? q : nlevels - 1 - q;
+      switch (M) {
+        case 8: sweep_level<T, 8>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, fwd, st); break;
+        case 16: sweep_level<T, 16>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, fwd, st); break;
+        case 32: sweep_level<T, 32>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, fwd, st); break;
+        default: sweep_level<T, 64>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, fwd, st); break;
+      }
+    }
   }
 }
 
@@ -234,12 +360,9 @@ void launch_cast_to(const double* src, int64_t lds, T* dst, int64_t n, int m, hi
   cast_to_kernel<T><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(src, lds, dst, n, m, M);
 }
 
-#define INST(T)                                                                                                  \
-  template void launch_fwd_assemble<T>(const FactorDev&, int64_t, int64_t, T*, const T*, int, hipStream_t);     \
-  template void launch_fwd_gemm<T>(const FactorDev&, int64_t, int64_t, const T*, const T*, T*, T*, int,         \
-                                   hipStream_t);                                                                \
-  template void launch_bwd_gemm<T>(const FactorDev&, int64_t, int64_t, const T*, const T*, T*, double*, int64_t, \
-                                   int, hipStream_t);                                                           \
+#define INST(T)                                                                                                 \
+  template void launch_precond<T>(const FactorDev&, const SolveDev&, int, int, const T*, T*, T*, T*, T*, T*, T*, \
+                                  double*, int64_t, int, hipStream_t);                                          \
   template void launch_cast_to<T>(const double*, int64_t, T*, int64_t, int, hipStream_t);
 INST(float)
 INST(double)

@@ -456,19 +456,43 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
   }
 }
 
-void build_solve_plan(const Symbolic& S, int rpt, SolvePlan& P) {
+void build_solve_plan(const Symbolic& S, int rpt, int kchunk, SolvePlan& P) {
   P = SolvePlan();
   P.rows_per_tile = rpt;
+  P.kchunk = kchunk;
   P.fwd_level_off.assign(S.nlevels + 1, 0);
   P.bwd_level_off.assign(S.nlevels + 1, 0);
+  P.fwd_fin_level_off.assign(S.nlevels + 1, 0);
+  P.bwd_fin_level_off.assign(S.nlevels + 1, 0);
+  auto emit = [&](std::vector<int32_t>& items, std::vector<int32_t>& fin, int64_t& slots, int s, int t, int k0,
+                  int k1) {
+    const int nch = (k1 - k0 + kchunk - 1) / kchunk;
+    if (nch <= 1) {
+      items.insert(items.end(), {s, t, k0, k1, -1});
+      return;
+    }
+    fin.insert(fin.end(), {s, t, (int32_t)slots, nch});
+    for (int q = 0; q < nch; ++q) {
+      const int a = k0 + q * kchunk, b = std::min(k1, a + kchunk);
+      items.insert(items.end(), {s, t, a, b, (int32_t)(slots + q)});
+    }
+    slots += nch;
+  };
   for (int l = 0; l < S.nlevels; ++l) {
     for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
-      int s = S.level_sn[q];
-      for (int t = 0; t < (S.nr[s] + rpt - 1) / rpt; ++t) { P.fwd_items.push_back(s); P.fwd_items.push_back(t); }
-      for (int t = 0; t < (S.nc[s] + rpt - 1) / rpt; ++t) { P.bwd_items.push_back(s); P.bwd_items.push_back(t); }
+      const int s = S.level_sn[q];
+      const int nc = S.nc[s], nr = S.nr[s];
+      for (int t = 0; t < (nr + rpt - 1) / rpt; ++t) {
+        const int r0 = t * rpt;
+        const int kmax = (r0 < nc) ? std::min(nc, r0 + rpt) : nc;
+        emit(P.fwd_items, P.fwd_fin, P.fwd_slots, s, t, 0, kmax);
+      }
+      for (int t = 0; t < (nc + rpt - 1) / rpt; ++t) emit(P.bwd_items, P.bwd_fin, P.bwd_slots, s, t, t * rpt, nr);
     }
-    P.fwd_level_off[l + 1] = (int64_t)P.fwd_items.size() / 2;
-    P.bwd_level_off[l + 1] = (int64_t)P.bwd_items.size() / 2;
+    P.fwd_level_off[l + 1] = (int64_t)P.fwd_items.size() / 5;
+    P.bwd_level_off[l + 1] = (int64_t)P.bwd_items.size() / 5;
+    P.fwd_fin_level_off[l + 1] = (int64_t)P.fwd_fin.size() / 4;
+    P.bwd_fin_level_off[l + 1] = (int64_t)P.bwd_fin.size() / 4;
   }
 }
 
@@ -553,13 +577,30 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
     const int s = F.ownrow_items[q], r = F.ownrow_items[q + 1];
     if (s < 0 || s >= ns || r < 0 || r >= S.nc[s]) return "own-row item";
   }
-  for (size_t q = 0; q < P.fwd_items.size(); q += 2) {
-    const int s = P.fwd_items[q], t = P.fwd_items[q + 1];
-    if (s < 0 || s >= ns || t < 0 || t * P.rows_per_tile >= S.nr[s]) return "forward item";
-  }
-  for (size_t q = 0; q < P.bwd_items.size(); q += 2) {
-    const int s = P.bwd_items[q], t = P.bwd_items[q + 1];
-    if (s < 0 || s >= ns || t < 0 || t * P.rows_per_tile >= S.nc[s]) return "backward item";
+  auto check_items = [&](const std::vector<int32_t>& items, const std::vector<int32_t>& fin, int64_t slots,
+                         bool fwd) -> std::string {
+    for (size_t q = 0; q < items.size(); q += 5) {
+      const int s = items[q], t = items[q + 1], k0 = items[q + 2], k1 = items[q + 3], slot = items[q + 4];
+      if (s < 0 || s >= ns || t < 0) return "solve item supernode";
+      const int lim = fwd ? S.nr[s] : S.nc[s];
+      if (t * P.rows_per_tile >= lim) return "solve item tile";
+      const int kl = fwd ? S.nc[s] : S.nr[s];
+      if (k0 < 0 || k1 > kl || k0 >= k1) return "solve item K range";
+      if (!fwd && k0 < t * P.rows_per_tile) return "backward K range below the diagonal tile";
+      if (slot < -1 || slot >= slots) return "solve item slot";
+    }
+    for (size_t q = 0; q < fin.size(); q += 4) {
+      const int s = fin[q], t = fin[q + 1], s0 = fin[q + 2], nch = fin[q + 3];
+      if (s < 0 || s >= ns || t < 0 || s0 < 0 || nch < 2 || s0 + nch > slots) return "finalize item";
+      if (t * P.rows_per_tile >= (fwd ? S.nr[s] : S.nc[s])) return "finalize tile";
+    }
+    return "";
+  };
+  {
+    std::string e = check_items(P.fwd_items, P.fwd_fin, P.fwd_slots, true);
+    if (!e.empty()) return "forward " + e;
+    e = check_items(P.bwd_items, P.bwd_fin, P.bwd_slots, false);
+    if (!e.empty()) return "backward " + e;
   }
   if (!prow.empty()) {
     if ((int64_t)prow.size() != n + 1 || apos.size() != (size_t)prow[n]) return "assembly positions size";

@@ -71,13 +71,20 @@ struct FactorPlan {
 enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6 };
 void build_factor_plan(const Symbolic& S, FactorPlan& plan);
 
-// Trisolve work lists: forward row tiles (s, rowtile) and backward column tiles (s, coltile).
+// Trisolve work lists.  Each output tile (64 rows of P_s for the forward sweep, 64
+// own columns for the backward sweep) is split into K chunks of at most kchunk;
+// a tile with one chunk is written directly, otherwise each chunk writes a
+// partial tile to its own slot and a finalize item sums the slots in order.
 struct SolvePlan {
-  std::vector<int32_t> fwd_items;   std::vector<int64_t> fwd_level_off;   // 2 ints per item
-  std::vector<int32_t> bwd_items;   std::vector<int64_t> bwd_level_off;
   int rows_per_tile = 64;
+  int kchunk = 256;
+  std::vector<int32_t> fwd_items;  std::vector<int64_t> fwd_level_off;   // 5 ints: s, tile, k0, k1, slot
+  std::vector<int32_t> fwd_fin;    std::vector<int64_t> fwd_fin_level_off; // 4 ints: s, tile, slot0, nchunks
+  std::vector<int32_t> bwd_items;  std::vector<int64_t> bwd_level_off;
+  std::vector<int32_t> bwd_fin;    std::vector<int64_t> bwd_fin_level_off;
+  int64_t fwd_slots = 0, bwd_slots = 0;
 };
-void build_solve_plan(const Symbolic& S, int rows_per_tile, SolvePlan& plan);
+void build_solve_plan(const Symbolic& S, int rows_per_tile, int kchunk, SolvePlan& plan);
 
 // Check every index the GPU kernels dereference against the buffer it indexes
 // (rows, maps, offsets, task and item lists, assembly positions).  Returns an
