@@ -25,7 +25,7 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
           "-munsafe-fp-atomics"]
 
 SOURCES = ["symbolic.cpp", "k_block.hip", "k_small.hip", "k_tsqr.hip", "k_factor.hip", "k_trisolve.hip",
-           "api.hip"]
+           "k_adjoint.hip", "api.hip"]
 
 
 def _compile(src: str) -> str:

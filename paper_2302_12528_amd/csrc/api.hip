@@ -80,7 +80,12 @@ struct lobpcg_ctx_s {
   bool solved = false;
   double t_symbolic = 0, t_factor = 0;
   int fallbacks = 0;
-  double* d_theta_k = nullptr;
+  // backward (adjoint) buffers, allocated on first use
+  double* bw_g = nullptr;
+  double* bw_blk[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* bw_small = nullptr;
+  double* bw_part = nullptr;
+  int bw_iters = 0;
 
   template <typename X>
   lobpcg_status alloc(X*& p, int64_t count) {
@@ -205,19 +210,28 @@ lobpcg_status factor(lobpcg_ctx c) {
   return LOBPCG_OK;
 }
 
-// W = working(f_T(lower(rhs))): rhs already holds lower(R) (T, n x mp); W (n x m, ldw)
+// W = working(f_T(lower(rhs))): rhs already holds lower(R) (T, n x mp); W (n x mw, ldw)
 template <typename T>
-void precond_t(lobpcg_ctx c, double* W, int64_t ldw) {
+void precond_t(lobpcg_ctx c, double* W, int64_t ldw, int mw) {
   launch_precond<T>(c->FD, c->SD, c->S.nlevels, c->mp, static_cast<const T*>(c->panel), static_cast<T*>(c->rhs),
                     static_cast<T*>(c->ybuf), static_cast<T*>(c->xbuf), static_cast<T*>(c->uvec),
-                    static_cast<T*>(c->fpart), static_cast<T*>(c->bpart), W, ldw, c->m, c->st);
+                    static_cast<T*>(c->fpart), static_cast<T*>(c->bpart), W, ldw, mw, c->st);
 }
 
-void precond(lobpcg_ctx c, double* W, int64_t ldw) {
+void precond(lobpcg_ctx c, double* W, int64_t ldw, int mw = -1) {
+  if (mw < 0) mw = c->m;
   if (c->prec == LOBPCG_FP32)
-    precond_t<float>(c, W, ldw);
+    precond_t<float>(c, W, ldw, mw);
   else
-    precond_t<double>(c, W, ldw);
+    precond_t<double>(c, W, ldw, mw);
+}
+
+// rhs = lower(R) for R (n x cols, ld), zero padded to the solve width
+void load_rhs(lobpcg_ctx c, const double* R, int64_t ld, int cols) {
+  if (c->prec == LOBPCG_FP32)
+    launch_cast_to<float>(R, ld, static_cast<float*>(c->rhs), c->n, cols, c->mp, c->st);
+  else
+    launch_cast_to<double>(R, ld, static_cast<double*>(c->rhs), c->n, cols, c->mp, c->st);
 }
 
 // Algorithm 2 on W (n x cc, ld) in place; flag set on a step-3 breakdown.
@@ -282,6 +296,7 @@ lobpcg_status lobpcg_setup(const lobpcg_matrix* A, int32_t k, int32_t m, double 
   const int64_t n = A->n;
   if (k < 1 || m < k) return fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= k <= m");
   if (m > 64) return fail(LOBPCG_ERR_INVALID_ARG, "block size m must be <= 64");
+  if (A->format == 1 && A->n > 16384) return fail(LOBPCG_ERR_INVALID_ARG, "dense matrices are limited to n <= 16384");
   if (3 * (int64_t)m > n) return fail(LOBPCG_ERR_INVALID_ARG, "need 3m <= n");
   if (!(tol > 0) || !std::isfinite(tol)) return fail(LOBPCG_ERR_INVALID_ARG, "tol must be positive and finite");
   if (factor_precision != LOBPCG_FP32 && factor_precision != LOBPCG_FP64)
@@ -343,6 +358,7 @@ lobpcg_status lobpcg_setup(const lobpcg_matrix* A, int32_t k, int32_t m, double 
   // ---- device structures ----
   const Symbolic& S = C.S;
   FactorDev& D = C.FD;
+  D.max_nr = S.max_nr;
   SETUP_TRY(upload(c, D.begin, S.begin));
   SETUP_TRY(upload(c, D.nc, S.nc));
   SETUP_TRY(upload(c, D.nr, S.nr));
@@ -609,11 +625,117 @@ lobpcg_status lobpcg_solve(lobpcg_ctx c, const double* X0, int32_t maxit, double
   return status;
 }
 
+// Gradient with respect to a diagonal potential (first-order perturbation theory):
+//   g = sum_i dtheta_i x_i o x_i - sum_i y_i o x_i,   y_i = (A - theta_i I)^+ (I - x_i x_i^T) dX_i.
+// With X = [x_1..x_k] the computed eigenvectors, y_i splits into its part in span(X),
+// sum_{l != i} x_l (x_l^T dX_i) / (theta_l - theta_i), and its part z_i in X^perp, where
+// A - theta_i I is positive definite (theta_i <= theta_k < lambda_{k+1}); z_i is found by
+// projected preconditioned CG in FP64 with the factor of A as preconditioner (FP64 residuals,
+// factor in its own precision), all k right-hand sides at once.
 lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double* d_evecs, double* d_diag) {
   if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
-  (void)d_evals; (void)d_evecs; (void)d_diag;
+  if (!d_diag) return fail(LOBPCG_ERR_INVALID_ARG, "d_diag is NULL");
   if (!c->solved) return fail(LOBPCG_ERR_STATE, "backward needs a successful lobpcg_solve first");
-  return fail(LOBPCG_ERR_STATE, "backward is not available in this build");
+  lobpcg_ctx_s& C = *c;
+  hipStream_t st = C.st;
+  const int64_t n = C.n;
+  const int k = C.k, m3 = 3 * C.m;
+  const double* X = C.Sb[C.cur];   // x_i = X(:, i), ld 3m, permuted ordering
+  const double* theta = C.evals;
+  if (!C.bw_g) {
+    ST_TRY(C.alloc(C.bw_g, n));
+    for (double*& b : C.bw_blk) ST_TRY(C.alloc(b, n * k));
+    ST_TRY(C.alloc(C.bw_small, 2 * (int64_t)k * k + 8 * k));
+    ST_TRY(C.alloc(C.bw_part, std::max(coldots_scratch(n, k), gram_scratch(n, k, k))));
+  }
+  double *B = C.bw_blk[0], *Z = C.bw_blk[1], *R = C.bw_blk[2], *P = C.bw_blk[3], *Q = C.bw_blk[4],
+         *Zp = C.bw_blk[5];
+  double* coef = C.bw_small;                 // k x k: X^T dX
+  double* Km = C.bw_small + k * k;           // k x k: span(X) coefficients of y
+  double* dots = C.bw_small + 2 * k * k;     // rz | pq | rr | alpha | beta | bb
+  double *rz = dots, *pq = dots + k, *rr = dots + 2 * k, *alpha = dots + 3 * k, *beta = dots + 4 * k,
+         *bb = dots + 5 * k;
+  int iters = 0;
+  bool conv = true;
+  if (d_evecs) {
+    // B = dX in the permuted ordering; coef = X^T B; B <- (I - X X^T) B
+    launch_gather_rows(d_evecs, k, C.d_perm, B, k, n, k, st);
+    launch_gram(X, m3, B, k, n, k, k, coef, C.bw_part, st);
+    std::vector<double> hc(k * k), th(k), hk(k * k, 0.0);
+    HIP_TRY(hipMemcpyAsync(hc.data(), coef, hc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(th.data(), theta, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int l = 0; l < k; ++l)
+      for (int i = 0; i < k; ++i) {
+        const double gap = th[l] - th[i];
+        if (l != i && std::fabs(gap) > 1e-13 * std::max(std::fabs(th[l]), std::fabs(th[i])))
+          hk[l * k + i] = hc[l * k + i] / gap;
+      }
+    HIP_TRY(hipMemcpyAsync(Km, hk.data(), hk.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_block_update(X, m3, coef, k, B, k, n, k, k, -1.0, 1.0, st);
+    // projected PCG on (A - theta_i I) z_i = b_i in X^perp
+    auto project = [&](double* V) {   // V <- (I - X X^T) V
+      launch_gram(X, m3, V, k, n, k, k, coef, C.bw_part, st);
+      launch_block_update(X, m3, coef, k, V, k, n, k, k, -1.0, 1.0, st);
+    };
+    auto apply_prec = [&](const double* Rin, double* Out) {   // Out = P_X T Rin
+      load_rhs(c, Rin, k, k);
+      precond(c, Out, k, k);
+      project(Out);
+    };
+    HIP_TRY(hipMemsetAsync(Z, 0, n * k * sizeof(double), st));
+    launch_copy_block(B, k, R, k, n, k, st);
+    launch_coldots(B, k, B, k, n, k, bb, C.bw_part, st);
+    apply_prec(R, Zp);
+    launch_copy_block(Zp, k, P, k, n, k, st);
+    launch_coldots(R, k, Zp, k, n, k, rz, C.bw_part, st);
+    std::vector<double> hbb(k), hrz(k), hpq(k), hrr(k), ha(k), hb(k);
+    HIP_TRY(hipMemcpyAsync(hbb.data(), bb, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hrz.data(), rz, k * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double tol = 1e-12;
+    std::vector<char> done(k, 0);
+    for (int i = 0; i < k; ++i) done[i] = (hbb[i] == 0.0);
+    conv = false;
+    for (iters = 0; iters < 500; ++iters) {
+      bool all = true;
+      for (int i = 0; i < k; ++i) all = all && done[i];
+      if (all) { conv = true; break; }
+      apply_a(c, P, k, Q, k, k);                              // Q = (A - theta I) P, projected
+      launch_shift_cols(Q, k, P, k, theta, Q, k, n, k, st);
+      project(Q);
+      launch_coldots(P, k, Q, k, n, k, pq, C.bw_part, st);
+      HIP_TRY(hipMemcpyAsync(hpq.data(), pq, k * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      for (int i = 0; i < k; ++i) ha[i] = (done[i] || hpq[i] == 0.0) ? 0.0 : hrz[i] / hpq[i];
+      HIP_TRY(hipMemcpyAsync(alpha, ha.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_axpy_cols(alpha, 1.0, P, k, Z, k, n, k, st);
+      launch_axpy_cols(alpha, -1.0, Q, k, R, k, n, k, st);
+      launch_coldots(R, k, R, k, n, k, rr, C.bw_part, st);
+      apply_prec(R, Zp);
+      launch_coldots(R, k, Zp, k, n, k, pq, C.bw_part, st);   // new r^T z
+      HIP_TRY(hipMemcpyAsync(hrr.data(), rr, k * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(hpq.data(), pq, k * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      for (int i = 0; i < k; ++i) {
+        if (!std::isfinite(hrr[i])) return fail(LOBPCG_ERR_NONFINITE, "adjoint solve diverged");
+        if (hrr[i] <= tol * tol * hbb[i]) done[i] = 1;
+        hb[i] = (done[i] || hrz[i] == 0.0) ? 0.0 : hpq[i] / hrz[i];
+        hrz[i] = hpq[i];
+      }
+      HIP_TRY(hipMemcpyAsync(beta, hb.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_xpby_cols(beta, Zp, k, P, k, n, k, st);
+    }
+    // y = z + X K
+    launch_block_update(X, m3, Km, k, Z, k, n, k, k, 1.0, 1.0, st);
+  }
+  launch_diag_grad(X, m3, d_evals, d_evecs ? Z : nullptr, k, n, k, C.bw_g, st);
+  launch_gather_rows(C.bw_g, 1, C.d_iperm, d_diag, 1, n, 1, st);
+  ST_TRY(check_launch("backward"));
+  HIP_TRY(hipStreamSynchronize(st));
+  C.bw_iters = iters;
+  if (!conv) return fail(LOBPCG_NOT_CONVERGED, "adjoint PCG did not reach its tolerance in 500 iterations");
+  return LOBPCG_OK;
 }
 
 lobpcg_status lobpcg_destroy(lobpcg_ctx c) {
@@ -674,10 +796,7 @@ lobpcg_status lobpcg_apply_a(lobpcg_ctx c, const double* X, int64_t ldx, double*
 
 lobpcg_status lobpcg_apply_precond(lobpcg_ctx c, const double* R, double* W) {
   if (!c || !R || !W) return fail(LOBPCG_ERR_INVALID_ARG, "NULL argument");
-  if (c->prec == LOBPCG_FP32)
-    launch_cast_to<float>(R, c->m, static_cast<float*>(c->rhs), c->n, c->m, c->st);
-  else
-    launch_cast_to<double>(R, c->m, static_cast<double*>(c->rhs), c->n, c->m, c->st);
+  load_rhs(c, R, c->m, c->m);
   precond(c, W, c->m);
   ST_TRY(check_launch("apply_precond"));
   HIP_TRY(hipStreamSynchronize(c->st));

@@ -71,7 +71,7 @@ struct FactorDev {
   int32_t* child_ptr; int32_t* child_list; int64_t* inv_off; int32_t* invmap;
   int64_t* panel_off; int64_t* upd_off; int64_t* uvec_off; int64_t* dinv_off; int64_t* lcopy_off;
   int32_t* prow; int32_t* pcol; int32_t* apos; double* aval;   // permuted A (CSR)
-  const double* dense; int64_t ld_dense; int is_dense;
+  const double* dense; int64_t ld_dense; int is_dense; int max_nr;
   int32_t* asm_items; int32_t* tasks; int32_t* ownrow_items;
 };
 template <typename T>
@@ -92,6 +92,19 @@ void launch_precond(const FactorDev& D, const SolveDev& Sd, int nlevels, int M, 
                     T* uvec, T* fpart, T* bpart, double* W, int64_t ldw, int mw, hipStream_t st);
 // rhs (T, n x M padded with zeros) = lower(R) given R FP64 (n x m, ld)
 template <typename T>
-void launch_cast_to(const double* src, int64_t lds, T* dst, int64_t n, int m, hipStream_t st);
+void launch_cast_to(const double* src, int64_t lds, T* dst, int64_t n, int m, int M, hipStream_t st);
+
+// ---- adjoint solve helpers (k_adjoint.hip) ----
+int64_t coldots_scratch(int64_t n, int c);
+void launch_coldots(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n, int c, double* out,
+                    double* part, hipStream_t st);
+void launch_axpy_cols(const double* alpha, double sign, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                      int64_t n, int c, hipStream_t st);
+void launch_xpby_cols(const double* beta, const double* Z, int64_t ldz, double* P, int64_t ldp, int64_t n, int c,
+                      hipStream_t st);
+void launch_shift_cols(const double* AP, int64_t lda, const double* P, int64_t ldp, const double* theta, double* Q,
+                       int64_t ldq, int64_t n, int c, hipStream_t st);
+void launch_diag_grad(const double* X, int64_t ldx, const double* dtheta, const double* Y, int64_t ldy, int64_t n,
+                      int k, double* g, hipStream_t st);
 
 }  // namespace lobpcg

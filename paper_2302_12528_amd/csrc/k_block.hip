@@ -98,49 +98,67 @@ __global__ void __launch_bounds__(kThreads) gemm_nn_kernel(const double* A, int6
 }
 
 // ----------------------------------------------------------------------------
-// Gram partials: block (chunk, tile) computes a 32 x 32 tile of X^T Y over its row chunk.
+// Gram partials: block (chunk, tile) computes a (16 RT) x (16 CT) tile of X^T Y over its
+// row chunk; 256 threads in a 16 x 16 grid, each owning RT x CT outputs.  Rows are
+// staged through LDS 16 at a time.  One tile covers c1, c2 <= 96.
 // ----------------------------------------------------------------------------
+template <int RT, int CT>
 __global__ void __launch_bounds__(kThreads) gram_partial_kernel(const double* __restrict__ X, int64_t ldx,
                                                                 const double* __restrict__ Y, int64_t ldy,
                                                                 int64_t n, int c1, int c2, int64_t rows_per_chunk,
                                                                 int tiles_j, double* __restrict__ part) {
-  __shared__ double Xs[16][33];
-  __shared__ double Ys[16][33];
+  constexpr int T1 = 16 * RT, T2 = 16 * CT, KR = 16;
+  __shared__ double Xs[KR][T1 + 1];
+  __shared__ double Ys[KR][T2 + 1];
   const int t = threadIdx.x;
   const int tx = t % 16, ty = t / 16;
   const int chunk = blockIdx.x;
   const int ti = blockIdx.y / tiles_j, tj = blockIdx.y % tiles_j;
-  const int i0 = ti * 32, j0 = tj * 32;
+  const int i0 = ti * T1, j0 = tj * T2;
   const int64_t rbeg = (int64_t)chunk * rows_per_chunk;
   const int64_t rend = min(n, rbeg + rows_per_chunk);
-  double acc00 = 0, acc01 = 0, acc10 = 0, acc11 = 0;
-  const int lk = t / 16, lc = (t % 16) * 2;
-  for (int64_t r0 = rbeg; r0 < rend; r0 += 16) {
-    const int64_t r = r0 + lk;
+  double acc[RT][CT];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int ci = i0 + lc + q, cj = j0 + lc + q;
-      Xs[lk][lc + q] = (r < rend && ci < c1) ? X[r * ldx + ci] : 0.0;
-      Ys[lk][lc + q] = (r < rend && cj < c2) ? Y[r * ldy + cj] : 0.0;
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = 0.0;
+  for (int64_t r0 = rbeg; r0 < rend; r0 += KR) {
+    for (int e = t; e < KR * T1; e += kThreads) {
+      const int k = e / T1, c = e % T1;
+      const int64_t r = r0 + k;
+      Xs[k][c] = (r < rend && i0 + c < c1) ? X[r * ldx + i0 + c] : 0.0;
+    }
+    for (int e = t; e < KR * T2; e += kThreads) {
+      const int k = e / T2, c = e % T2;
+      const int64_t r = r0 + k;
+      Ys[k][c] = (r < rend && j0 + c < c2) ? Y[r * ldy + j0 + c] : 0.0;
     }
     __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < KR; ++k) {
+      double a[RT], b[CT];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const double a0 = Xs[k][ty], a1 = Xs[k][ty + 16];
-      const double b0 = Ys[k][tx], b1 = Ys[k][tx + 16];
-      acc00 = fma(a0, b0, acc00);
-      acc01 = fma(a0, b1, acc01);
-      acc10 = fma(a1, b0, acc10);
-      acc11 = fma(a1, b1, acc11);
+      for (int i = 0; i < RT; ++i) a[i] = Xs[k][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) b[j] = Ys[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
   double* P = part + (int64_t)chunk * c1 * c2;
-  const int ia = i0 + ty, ib = i0 + ty + 16, ja = j0 + tx, jb = j0 + tx + 16;
-  if (ia < c1 && ja < c2) P[ia * c2 + ja] = acc00;
-  if (ia < c1 && jb < c2) P[ia * c2 + jb] = acc01;
-  if (ib < c1 && ja < c2) P[ib * c2 + ja] = acc10;
-  if (ib < c1 && jb < c2) P[ib * c2 + jb] = acc11;
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    const int gi = i0 + ty + 16 * i;
+    if (gi >= c1) continue;
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      const int gj = j0 + tx + 16 * j;
+      if (gj < c2) P[gi * c2 + gj] = acc[i][j];
+    }
+  }
 }
 
 // out[e] = sum_b part[b][e] in a fixed order: four interleaved partial sums per output
@@ -160,10 +178,12 @@ __global__ void __launch_bounds__(256) reduce_parts_kernel(const double* __restr
   if (g == 0 && e < len) out[e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
+inline int gram_rt(int c) { return c <= 16 ? 1 : c <= 32 ? 2 : c <= 48 ? 3 : c <= 64 ? 4 : 6; }
+
 int gram_chunks(int64_t n, int c1, int c2) {
-  const int tiles = ceil_div(c1, 32) * ceil_div(c2, 32);
-  int chunks = ceil_div(n, 256);
-  const int target = (1024 + tiles - 1) / tiles;
+  const int tiles = ceil_div(c1, 16 * gram_rt(c1)) * ceil_div(c2, 16 * gram_rt(c2));
+  int chunks = ceil_div(n, 512);
+  const int target = (384 + tiles - 1) / tiles;
   if (chunks > target) chunks = target;
   if (chunks < 1) chunks = 1;
   return chunks;
@@ -336,14 +356,39 @@ void launch_dense_mm(const double* A, int64_t lda, int64_t n, const double* X, i
 
 int64_t gram_scratch(int64_t n, int c1, int c2) { return (int64_t)gram_chunks(n, c1, c2) * c1 * c2; }
 
+template <int RT, int CT>
+void gram_launch(dim3 g, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n, int c1, int c2,
+                 int64_t rpc, int tj, double* part, hipStream_t st) {
+  gram_partial_kernel<RT, CT><<<g, kThreads, 0, st>>>(X, ldx, Y, ldy, n, c1, c2, rpc, tj, part);
+}
+
+template <int RT>
+void gram_dispatch_ct(int ct, dim3 g, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n, int c1,
+                      int c2, int64_t rpc, int tj, double* part, hipStream_t st) {
+  switch (ct) {
+    case 1: gram_launch<RT, 1>(g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+    case 2: gram_launch<RT, 2>(g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+    case 3: gram_launch<RT, 3>(g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+    case 4: gram_launch<RT, 4>(g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+    default: gram_launch<RT, 6>(g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+  }
+}
+
 void launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n, int c1, int c2, double* G,
                  double* part, hipStream_t st) {
   if (c1 <= 0 || c2 <= 0) return;
   const int chunks = gram_chunks(n, c1, c2);
   const int64_t rpc = n > 0 ? (n + chunks - 1) / chunks : 1;
-  const int tj = ceil_div(c2, 32);
-  dim3 g(chunks, ceil_div(c1, 32) * tj);
-  gram_partial_kernel<<<g, kThreads, 0, st>>>(X, ldx, Y, ldy, n, c1, c2, rpc, tj, part);
+  const int rt = gram_rt(c1), ct = gram_rt(c2);
+  const int tj = ceil_div(c2, 16 * ct);
+  dim3 g(chunks, ceil_div(c1, 16 * rt) * tj);
+  switch (rt) {
+    case 1: gram_dispatch_ct<1>(ct, g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+    case 2: gram_dispatch_ct<2>(ct, g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+    case 3: gram_dispatch_ct<3>(ct, g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+    case 4: gram_dispatch_ct<4>(ct, g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+    default: gram_dispatch_ct<6>(ct, g, X, ldx, Y, ldy, n, c1, c2, rpc, tj, part, st); break;
+  }
   const int len = c1 * c2;
   reduce_parts_kernel<<<ceil_div(len, 64), 256, 0, st>>>(part, chunks, len, G);
 }

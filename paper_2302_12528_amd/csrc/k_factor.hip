@@ -62,63 +62,100 @@ __device__ inline T* front_ptr(T* panel, T* upd, const Sn& S, int r, int c, int6
 }
 
 // ---------------------------------------------------------------------------
-// Assembly, one wave per front column.
+// Assembly, one wave per front column t of supernode s: the column is built in
+// LDS (zero, the entries of A, then each child's Schur-complement column
+// scattered through the child's relative row map; children are added one after
+// another, so every target element has one writer at a time), then written out
+// once.  Every child entry is read exactly once over the whole level.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(256) assemble_kernel(FactorDev D, int64_t item_off, int64_t count, T* panel,
-                                                       T* upd) {
-  const int lane = threadIdx.x % 64;
-  const int64_t item = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+__global__ void __launch_bounds__(64) assemble_kernel(FactorDev D, int64_t item_off, int64_t count, T* panel,
+                                                      T* upd) {
+  extern __shared__ unsigned char asm_smem[];
+  T* colbuf = reinterpret_cast<T*>(asm_smem);
+  const int lane = threadIdx.x;
+  const int64_t item = (int64_t)blockIdx.x;
   if (item >= count) return;
   const int s = D.asm_items[2 * (item_off + item)];
   const int t = D.asm_items[2 * (item_off + item) + 1];
   const Sn S = sn_of(D, s);
-  const int c0 = D.child_ptr[s], c1 = D.child_ptr[s + 1];
   const int rlo = (t < S.nc) ? 0 : t;
   int64_t ld;
-  T* col = front_ptr(panel, upd, S, (t < S.nc) ? 0 : t, t, ld);
-  const int64_t colbase = (t < S.nc) ? 0 : t;   // row index of col[0]
+  T* col = front_ptr(panel, upd, S, rlo, t, ld);   // col[r - rlo] is front element (r, t)
   if (D.is_dense) {
     for (int r = rlo + lane; r < S.nr; r += 64)
-      col[r - colbase] = (r >= t) ? (T)D.dense[(int64_t)r * D.ld_dense + t] : (T)0;
+      col[r - rlo] = (r >= t) ? (T)D.dense[(int64_t)r * D.ld_dense + t] : (T)0;
     return;
   }
-  const int j = S.begin + t;
-  const int e0 = (t < S.nc) ? D.prow[j] : 0;
-  const int e1 = (t < S.nc) ? D.prow[j + 1] : 0;
-  for (int r = rlo + lane; r < S.nr; r += 64) {
-    T v = 0;
-    for (int e = e0; e < e1; ++e)
-      if (D.apos[e] == r) v += (T)D.aval[e];
-    for (int q = c0; q < c1; ++q) {
-      const int c = D.child_list[q];
-      const int64_t io = D.inv_off[c];
-      const int jt = D.invmap[io + t];
-      if (jt < 0) continue;
-      const int jr = D.invmap[io + r];
-      if (jr < jt) continue;
-      const int nbc = D.nr[c] - D.nc[c];
-      v += upd[D.upd_off[c] + (int64_t)jt * nbc + jr];
+  for (int r = rlo + lane; r < S.nr; r += 64) colbuf[r] = (T)0;
+  __syncthreads();
+  if (t < S.nc) {
+    const int j = S.begin + t;
+    for (int e = D.prow[j] + lane; e < D.prow[j + 1]; e += 64) {
+      const int pos = D.apos[e];
+      if (pos >= 0) colbuf[pos] += (T)D.aval[e];
     }
-    col[r - colbase] = v;
   }
+  __syncthreads();
+  for (int q = D.child_ptr[s]; q < D.child_ptr[s + 1]; ++q) {
+    const int c = D.child_list[q];
+    const int jt = D.invmap[D.inv_off[c] + t];
+    if (jt < 0) continue;
+    const int nbc = D.nr[c] - D.nc[c];
+    const T* uc = upd + D.upd_off[c] + (int64_t)jt * nbc;
+    const int32_t* rel = D.relpos + D.row_off[c] + D.nc[c];
+    for (int ic = jt + lane; ic < nbc; ic += 64) colbuf[rel[ic]] += uc[ic];
+    __syncthreads();
+  }
+  for (int r = rlo + lane; r < S.nr; r += 64) col[r - rlo] = colbuf[r];
 }
 
 // ---------------------------------------------------------------------------
 // Tile kernels (one workgroup of 256 threads per task).
 // ---------------------------------------------------------------------------
+// Uniform read of lane l's value (l must be wave-uniform).
+__device__ inline float rdl(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ inline double rdl(double v, int l) {
+  const long long x = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <> struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// acc (transposed) for this wave's 32 x 32 quadrant of the 64 x 64 tile C = As^T Bs, i.e.
+// C[r][c] = sum_k As[k][r] Bs[k][c], with 16x16x4 MFMAs.  The MFMA computes D = C^T so that lane l's
+// outputs (D rows 4(l/16)+q = C columns, D column l%16 = C row) are stored row-contiguously into
+// the column-major panel.  K is zero padded to a multiple of 4 in LDS.
 template <typename T>
-__device__ inline void tile_fma(const T (*As)[TB + 1], const T (*Bs)[TB + 1], int K, T acc[4][4], int tx, int ty) {
-  for (int k = 0; k < K; ++k) {
-    T a[4], b[4];
+__device__ inline void tile_mfma(const T (*As)[TB + 1], const T (*Bs)[TB + 1], int K,
+                                 typename Mfma<T>::v4 acc[2][2]) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int qr = (w / 2) * 32, qc = (w % 2) * 32;
+  const int kl = lane / 16, il = lane % 16;
+  for (int ks = 0; ks < K; ks += 4) {
+    T bf[2], af[2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
+    for (int b = 0; b < 2; ++b) bf[b] = Bs[ks + kl][qc + 16 * b + il];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
+    for (int a = 0; a < 2; ++a) af[a] = As[ks + kl][qr + 16 * a + il];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      for (int a = 0; a < 2; ++a) acc[b][a] = Mfma<T>::op(bf[b], af[a], acc[b][a]);
   }
 }
 
@@ -140,63 +177,59 @@ __device__ inline void load_cm_t(T (*Bs)[TB + 1], const T* M, int64_t ld, int K,
   }
 }
 
+// Cholesky of the h x h diagonal tile (p, p) and the inverse of its factor, by one wave.
+// Lane i holds row i of the tile in registers (rows/columns >= h padded with the identity);
+// column j is eliminated with uniform reads of the pivot and of column j; the inverse is
+// formed column by column (lane j owns column j) from L staged in LDS.
 template <typename T>
-__global__ void __launch_bounds__(256) potrf_kernel(FactorDev D, int64_t task_off, T* panel, T* upd, T* dinv,
-                                                    int* flag) {
-  __shared__ T a[TB][TB + 1];
-  __shared__ T b[TB][TB + 1];
+__global__ void __launch_bounds__(64) potrf_kernel(FactorDev D, int64_t task_off, T* panel, T* upd, T* dinv,
+                                                   int* flag) {
+  __shared__ T Ls[TB][TB + 1];
   const int* tk = D.tasks + 4 * (task_off + blockIdx.x);
   const int s = tk[0], p = tk[3];
   const Sn S = sn_of(D, s);
   const int r0 = p * TB, h = min(TB, S.nc - r0);
   int64_t ld;
   T* tile = front_ptr(panel, upd, S, r0, r0, ld);
-  const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int i = e % TB, j = e / TB;
-    a[i][j] = (i < h && j < h) ? tile[i + (int64_t)j * ld] : (T)0;
+  const int lane = threadIdx.x;
+  T a[TB];
+#pragma unroll
+  for (int j = 0; j < TB; ++j) a[j] = (lane < h && j < h) ? tile[lane + (int64_t)j * ld] : (lane == j ? (T)1 : (T)0);
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    T d = rdl(a[j], j);
+    if (!(d > (T)0) || !isfinite((double)d)) {
+      if (bad == 0) bad = j + 1;
+      d = (T)1;
+    }
+    const T ljj = sqrt(d);
+    const T rinv = (T)1 / ljj;
+    const T l = (lane > j) ? a[j] * rinv : (lane == j ? ljj : (T)0);
+    a[j] = l;
+#pragma unroll
+    for (int k = j + 1; k < TB; ++k) a[k] -= l * rdl(l, k);
+  }
+  if (bad != 0 && lane == 0 && bad <= h) flag[0] = S.begin + r0 + bad;
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    const T v = (j <= lane) ? a[j] : (T)0;
+    Ls[lane][j] = v;
+    if (lane < h && j < h) tile[lane + (int64_t)j * ld] = v;
   }
   __syncthreads();
-  for (int j = 0; j < h; ++j) {
-    if (tid == 0) {
-      T d = a[j][j];
-      if (!(d > (T)0) || !isfinite((double)d)) {
-        flag[0] = S.begin + r0 + j + 1;
-        d = (T)1;
-      }
-      a[j][j] = sqrt(d);
-    }
-    __syncthreads();
-    const T ljj = a[j][j];
-    for (int i = j + 1 + tid; i < h; i += 256) a[i][j] /= ljj;
-    __syncthreads();
-    const int w = h - j - 1;
-    for (int e = tid; e < w * w; e += 256) {
-      const int i = j + 1 + e % w, k = j + 1 + e / w;
-      if (k <= i) a[i][k] -= a[i][j] * a[k][j];
-    }
-    __syncthreads();
+  // column `lane` of inv(L): forward substitution, L read from LDS (uniform addresses)
+  T x[TB];
+#pragma unroll
+  for (int i = 0; i < TB; ++i) {
+    T sacc = (i == lane) ? (T)1 : (T)0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) sacc -= Ls[i][k] * x[k];
+    x[i] = sacc / Ls[i][i];
   }
-  // inverse of the h x h lower factor, one column per thread
-  if (tid < TB) {
-    const int j = tid;
-    for (int i = 0; i < TB; ++i) b[i][j] = (T)0;
-    if (j < h) {
-      b[j][j] = (T)1 / a[j][j];
-      for (int i = j + 1; i < h; ++i) {
-        T s2 = 0;
-        for (int k = j; k < i; ++k) s2 += a[i][k] * b[k][j];
-        b[i][j] = -s2 / a[i][i];
-      }
-    }
-  }
-  __syncthreads();
   T* di = dinv + D.dinv_off[s] + (int64_t)p * TB * TB;
-  for (int e = tid; e < TB * TB; e += 256) {
-    const int i = e % TB, j = e / TB;
-    di[i + TB * j] = b[i][j];
-    if (i < h && j < h) tile[i + (int64_t)j * ld] = (i >= j) ? a[i][j] : (T)0;
-  }
+#pragma unroll
+  for (int i = 0; i < TB; ++i) di[i + TB * lane] = (i < h && lane < h) ? x[i] : (T)0;
 }
 
 // kind 0: trsm   C = C dinv_p^T            (task s, I, p, p)
@@ -212,7 +245,6 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
   const int s = tk[0], I = tk[1], J = tk[2], p = tk[3];
   const Sn S = sn_of(D, s);
   const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
   int rI, hI, rJ, hJ, rP, wP;
   tile_rows(S, I, rI, hI);
   tile_rows(S, J, rJ, hJ);
@@ -220,11 +252,6 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
   int64_t ldc, lda;
   T* C = front_ptr(panel, upd, S, rI, rJ, ldc);            // tile (I, J): rows hI, cols hJ
   const T* di = dinv + D.dinv_off[s] + (int64_t)p * TB * TB;
-  T acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
   int K = 0;
   if (KIND == 0) {              // C(I,p) dinv_p^T, K = wP
     K = wP;
@@ -257,23 +284,33 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
     load_cm_t(Bs, Lc, S.nc, K, hJ);
   }
   __syncthreads();
-  tile_fma<T>(As, Bs, K, acc, tx, ty);
-  __syncthreads();
+  typename Mfma<T>::v4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = ty + 16 * i;
-    if (r >= hI) continue;
+  for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = tx + 16 * j;
-      if (c >= hJ) continue;
-      T* dst = C + r + (int64_t)c * ldc;
-      if (KIND == 0 || KIND == 2)
-        *dst = acc[i][j];
-      else
-        *dst -= acc[i][j];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[b][a][q] = 0;
+  tile_mfma<T>(As, Bs, K, acc);
+  const int lane = tid % 64, w = tid / 64;
+  const int qr = (w / 2) * 32, qc = (w % 2) * 32;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int r = qr + 16 * a + lane % 16;
+      if (r >= hI) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = qc + 16 * b + 4 * (lane / 16) + q;
+        if (c >= hJ) continue;
+        T* dst = C + r + (int64_t)c * ldc;
+        if (KIND == 0 || KIND == 2)
+          *dst = acc[b][a][q];
+        else
+          *dst -= acc[b][a][q];
+      }
     }
-  }
 }
 
 // Copy L11 column t (rows t..nc-1) to the level scratch and clear the panel's own part of column t.
@@ -303,11 +340,16 @@ void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_of
   (void)level;
   switch (kind) {
     case kAssemble:
-      if (asm_count > 0)
-        assemble_kernel<T><<<(unsigned)((asm_count + 3) / 4), 256, 0, st>>>(D, asm_off, asm_count, panel, upd);
+      if (asm_count > 0) {
+        const size_t lds = D.is_dense ? 0 : (size_t)D.max_nr * sizeof(T);
+        if (lds > 65536)
+          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&assemble_kernel<T>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        assemble_kernel<T><<<(unsigned)asm_count, 64, lds, st>>>(D, asm_off, asm_count, panel, upd);
+      }
       break;
     case kPotrf:
-      potrf_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, flag);
+      potrf_kernel<T><<<count, 64, 0, st>>>(D, task_off, panel, upd, dinv, flag);
       break;
     case kTrsm:
       tile_kernel<T, 0><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, lcopy);

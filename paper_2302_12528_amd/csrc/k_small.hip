@@ -1,7 +1,6 @@
 // Small dense FP64 kernels, one workgroup each:
 //  * symmetric eigensolver for the c x c Rayleigh-Ritz matrix (Algorithm 3
-//    line 14), by parallel cyclic Jacobi (round-robin pairing, so the N/2
-//    rotations of a round are disjoint and applied together as J^T A J);
+//    line 14): tridiagonalization, bisection, inverse iteration;
 //  * the Hetmaniuk-Lehoucq step (lines 15-16): V = orthonormal factor of
 //    C(1:m, m+1:c)^T and G = [C(:,1:m), C(:,m+1:c) V];
 //  * Algorithm 2's steps 2-4: row-wise triangular solves with the lower-precision
@@ -14,8 +13,6 @@ namespace lobpcg {
 
 namespace {
 
-constexpr int kEigThreads = 1024;
-constexpr int kLdsMax = 96;   // matrices up to 96 x 96 stay in LDS
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -36,122 +33,244 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Round-robin (circle method) pairing of N (even) indices for round r.
-__device__ inline void rr_pair(int r, int i, int N, int& p, int& q) {
-  if (i == 0) {
-    p = r;
-    q = N - 1;
-  } else {
-    const int M = N - 1;
-    p = (r + i) % M;
-    q = (r - i + M) % M;
-  }
-  if (p > q) { int t = p; p = q; q = t; }
-}
+// Symmetric eigensolver for the c x c Rayleigh-Ritz matrix, one workgroup:
+//  1. Householder reduction to tridiagonal form T = Q^T H Q (reflectors stored
+//     below the subdiagonal, as in LAPACK's sytd2);
+//  2. every eigenvalue of T by bisection on Sturm counts, one thread per
+//     eigenvalue (the count is backward stable, so each eigenvalue is accurate
+//     to a few ulps of ||T||);
+//  3. eigenvectors of T by inverse iteration with a pivoted tridiagonal LU;
+//     eigenvalues closer than 1e-3 ||T||_1 form a cluster whose vectors are
+//     computed one after another, each orthogonalised against the earlier ones;
+//  4. back-transformation C = Q Z.
+// Matrices up to 96 x 96 live in LDS, larger ones in the global scratch.
+constexpr int kSyevThreads = 512;
+constexpr int kSyevLds = 96;
+constexpr int kSyevMax = 192;
 
-__device__ void jacobi_core(double* a, double* v, int c, int N, double* cs, double* sn, int* pp, int* qq,
-                            double* red, int* info) {
+__global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __restrict__ H, int64_t ldh, int c,
+                                                            double* __restrict__ evals, double* __restrict__ C,
+                                                            double* __restrict__ work, int* info) {
+  __shared__ double sa[kSyevLds * (kSyevLds + 1)];
+  __shared__ double sz[kSyevLds * (kSyevLds + 1)];
+  __shared__ double d[kSyevMax], e[kSyevMax], e2[kSyevMax], tau[kSyevMax], v[kSyevMax], p[kSyevMax];
+  __shared__ double lam[kSyevMax];
+  __shared__ double sc[8];
+  __shared__ int crank[kSyevMax];
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int half = N / 2;
-  double fro2 = 0.0;
-  for (int e = tid; e < N * N; e += nt) fro2 += a[e] * a[e];
-  fro2 = block_sum(fro2, red);
-  int sweep = 0;
-  for (; sweep < 60; ++sweep) {
-    double off = 0.0;
-    for (int e = tid; e < N * N; e += nt) {
-      const int i = e / N, j = e % N;
-      if (i != j) off += a[e] * a[e];
-    }
-    off = block_sum(off, red);
-    if (!(off > 1e-32 * fro2)) break;
-    for (int r = 0; r < N - 1; ++r) {
-      if (tid < half) {
-        int p, q;
-        rr_pair(r, tid, N, p, q);
-        const double apq = a[p * N + q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double th = (a[q * N + q] - a[p * N + p]) / (2.0 * apq);
-          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
+  const int lane = tid % 64, wid = tid / 64;
+  const int la = c + 1;
+  const bool in_lds = (c <= kSyevLds);
+  double* a = in_lds ? sa : work;
+  double* Z = in_lds ? sz : work + (int64_t)c * la;
+  double* lu = work + 2 * (int64_t)c * la;   // U0 | U1 | U2 | L | piv, each c x c, index [k * c + j]
+  for (int q = tid; q < c * c; q += nt) {
+    const int i = q / c, j = q % c;
+    a[i * la + j] = 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]);
+  }
+  __syncthreads();
+  // ---- 1. tridiagonalization ----
+  for (int k = 0; k + 2 < c; ++k) {
+    const int nk = c - k - 1;
+    if (wid == 0) {
+      double ss = 0.0;
+      for (int i = k + 2 + lane; i < c; i += 64) ss += a[i * la + k] * a[i * la + k];
+      ss = wave_sum(ss);
+      if (lane == 0) {
+        const double alpha = a[(k + 1) * la + k];
+        double t = 0.0, beta = alpha, scale = 0.0;
+        if (ss > 0.0) {
+          const double xn = sqrt(alpha * alpha + ss);
+          beta = (alpha >= 0.0) ? -xn : xn;
+          t = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
         }
-        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+        sc[0] = t; sc[1] = beta; sc[2] = scale;
+        tau[k] = t; e[k] = beta; d[k] = a[k * la + k];
       }
-      __syncthreads();
-      for (int e = tid; e < half * half; e += nt) {
-        const int bi = e / half, bj = e % half;
-        const int pi = pp[bi], qi = qq[bi], pj = pp[bj], qj = qq[bj];
-        const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
-        const double b00 = a[pi * N + pj], b01 = a[pi * N + qj];
-        const double b10 = a[qi * N + pj], b11 = a[qi * N + qj];
-        // rows: J_i^T B
-        const double t00 = ci * b00 - si * b10, t01 = ci * b01 - si * b11;
-        const double t10 = si * b00 + ci * b10, t11 = si * b01 + ci * b11;
-        // columns: (J_i^T B) J_j
-        double n00 = cj * t00 - sj * t01, n01 = sj * t00 + cj * t01;
-        double n10 = cj * t10 - sj * t11, n11 = sj * t10 + cj * t11;
-        if (bi == bj) { n01 = 0.0; n10 = 0.0; }
-        a[pi * N + pj] = n00; a[pi * N + qj] = n01;
-        a[qi * N + pj] = n10; a[qi * N + qj] = n11;
-      }
-      for (int e = tid; e < N * half; e += nt) {
-        const int row = e / half, bi = e % half;
-        const int p = pp[bi], q = qq[bi];
-        const double c = cs[bi], s = sn[bi];
-        const double vp = v[row * N + p], vq = v[row * N + q];
-        v[row * N + p] = c * vp - s * vq;
-        v[row * N + q] = s * vp + c * vq;
-      }
-      __syncthreads();
     }
-  }
-  if (tid == 0 && info) info[0] = sweep;
-}
-
-template <bool kLds>
-__global__ void __launch_bounds__(kEigThreads) syev_kernel(const double* __restrict__ H, int64_t ldh, int c,
-                                                           double* __restrict__ evals, double* __restrict__ C,
-                                                           double* __restrict__ work, int* info) {
-  __shared__ double sA[kLds ? kLdsMax * kLdsMax : 1];
-  __shared__ double sV[kLds ? kLdsMax * kLdsMax : 1];
-  __shared__ double cs[kLdsMax + 2], sn[kLdsMax + 2];
-  __shared__ int pp[kLdsMax + 2], qq[kLdsMax + 2];
-  __shared__ double red[kEigThreads / 64];
-  __shared__ double dsh[2 * kLdsMax + 2];
-  const int N = c + (c & 1);
-  double* a = kLds ? sA : work;
-  double* v = kLds ? sV : work + (int64_t)N * N;
-  double* cs_ = kLds ? cs : work + 2 * (int64_t)N * N;
-  double* sn_ = kLds ? sn : cs_ + N;
-  int* pp_ = kLds ? pp : (int*)(sn_ + N);
-  int* qq_ = kLds ? qq : pp_ + N;
-  double* d = kLds ? dsh : (double*)(qq_ + N + 2);
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < N * N; e += nt) {
-    const int i = e / N, j = e % N;
-    double x = 0.0;
-    if (i < c && j < c) x = 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]);
-    a[e] = x;
-    v[e] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  jacobi_core(a, v, c, N, cs_, sn_, pp_, qq_, red, info);
-  __syncthreads();
-  for (int i = tid; i < c; i += nt) d[i] = a[i * N + i];
-  __syncthreads();
-  // ascending order by rank (ties broken by index)
-  for (int i = tid; i < c; i += nt) {
-    const double di = d[i];
-    int rank = 0;
-    for (int j = 0; j < c; ++j) {
-      const double dj = d[j];
-      rank += (dj < di || (dj == di && j < i)) ? 1 : 0;
+    __syncthreads();
+    const double t = sc[0];
+    if (t == 0.0) continue;
+    const double beta = sc[1], scale = sc[2];
+    for (int i = tid; i < nk; i += nt) {
+      const double vi = (i == 0) ? 1.0 : a[(k + 1 + i) * la + k] * scale;
+      v[i] = vi;
+      if (i > 0) a[(k + 1 + i) * la + k] = vi;
     }
-    evals[rank] = di;
-    for (int row = 0; row < c; ++row) C[(int64_t)row * c + rank] = v[row * N + i];
+    if (tid == 0) a[(k + 1) * la + k] = beta;
+    __syncthreads();
+    // p = t * A22 v, 8 threads per row
+    for (int i = tid / 8; i < nk; i += nt / 8) {
+      double s8 = 0.0;
+      for (int j = tid % 8; j < nk; j += 8) s8 += a[(k + 1 + i) * la + k + 1 + j] * v[j];
+      s8 += __shfl_xor(s8, 1, 8);
+      s8 += __shfl_xor(s8, 2, 8);
+      s8 += __shfl_xor(s8, 4, 8);
+      if (tid % 8 == 0) p[i] = t * s8;
+    }
+    __syncthreads();
+    if (wid == 0) {
+      double ss = 0.0;
+      for (int i = lane; i < nk; i += 64) ss += p[i] * v[i];
+      ss = wave_sum(ss);
+      if (lane == 0) sc[3] = 0.5 * t * ss;
+    }
+    __syncthreads();
+    const double K = sc[3];
+    for (int i = tid; i < nk; i += nt) p[i] -= K * v[i];
+    __syncthreads();
+    for (int q = tid; q < nk * nk; q += nt) {
+      const int i = q / nk, j = q % nk;
+      a[(k + 1 + i) * la + k + 1 + j] -= v[i] * p[j] + p[i] * v[j];
+    }
+    __syncthreads();
   }
+  if (tid == 0) {
+    for (int k = (c >= 2 ? c - 2 : 0); k < c; ++k) d[k] = a[k * la + k];
+    if (c >= 2) e[c - 2] = a[(c - 1) * la + c - 2];
+    if (c >= 2) tau[c - 2] = 0.0;
+    tau[c - 1] = 0.0;
+    e[c - 1] = 0.0;
+  }
+  __syncthreads();
+  // ---- 2. eigenvalues by bisection ----
+  double gl = 1e300, gu = -1e300, tnorm = 0.0, emax2 = 0.0;
+  for (int i = 0; i < c; ++i) {
+    const double ei = (i < c - 1) ? fabs(e[i]) : 0.0;
+    const double em = (i > 0) ? fabs(e[i - 1]) : 0.0;
+    gl = fmin(gl, d[i] - ei - em);
+    gu = fmax(gu, d[i] + ei + em);
+    tnorm = fmax(tnorm, fabs(d[i]) + ei + em);
+    emax2 = fmax(emax2, ei * ei);
+  }
+  for (int i = tid; i < c; i += nt) e2[i] = (i < c - 1) ? e[i] * e[i] : 0.0;
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  gl -= 2.0 * eps * tnorm * c + 2.0 * pivmin;
+  gu += 2.0 * eps * tnorm * c + 2.0 * pivmin;
+  __syncthreads();
+  for (int j = tid; j < c; j += nt) {
+    double lo = gl, hi = gu;
+    for (int it = 0; it < 120; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (!(hi - lo > 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) || mid == lo || mid == hi) break;
+      int cnt = 0;
+      double q = d[0] - mid;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += (q < 0.0);
+      for (int i = 1; i < c; ++i) {
+        q = (d[i] - mid) - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += (q < 0.0);
+      }
+      if (cnt >= j + 1) hi = mid; else lo = mid;
+    }
+    lam[j] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // ---- 3. eigenvectors of T by inverse iteration ----
+  const double ortol = 1e-3 * tnorm;
+  int maxrank = 0;
+  for (int j = tid; j < c; j += nt) {
+    int r = 0;
+    while (j - r - 1 >= 0 && lam[j - r] - lam[j - r - 1] < ortol) ++r;
+    crank[j] = r;
+  }
+  __syncthreads();
+  for (int j = 0; j < c; ++j) maxrank = max(maxrank, crank[j]);
+  double* U0 = lu;
+  double* U1 = lu + (int64_t)c * c;
+  double* U2 = lu + 2 * (int64_t)c * c;
+  double* Lm = lu + 3 * (int64_t)c * c;
+  double* Pv = lu + 4 * (int64_t)c * c;
+  for (int round = 0; round <= maxrank; ++round) {
+    for (int j = tid; j < c; j += nt) {
+      if (crank[j] != round) continue;
+      const double lj = lam[j];
+      const double tiny = eps * tnorm + pivmin;
+      // pivoted LU of T - lj I (U with two superdiagonals)
+      double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0;
+      for (int k = 0; k + 1 < c; ++k) {
+        const double sub = e[k];
+        const double nd = d[k + 1] - lj;
+        const double ns = (k + 2 < c) ? e[k + 1] : 0.0;
+        if (fabs(cd) >= fabs(sub)) {
+          const double m = (cd != 0.0) ? sub / cd : 0.0;
+          U0[k * c + j] = cd; U1[k * c + j] = cs; U2[k * c + j] = 0.0; Pv[k * c + j] = 0.0; Lm[k * c + j] = m;
+          cd = nd - m * cs;
+          cs = ns;
+        } else {
+          const double m = cd / sub;
+          U0[k * c + j] = sub; U1[k * c + j] = nd; U2[k * c + j] = ns; Pv[k * c + j] = 1.0; Lm[k * c + j] = m;
+          cd = cs - m * nd;
+          cs = -m * ns;
+        }
+      }
+      U0[(c - 1) * c + j] = cd;
+      for (int k = 0; k < c; ++k)
+        if (fabs(U0[k * c + j]) < tiny) U0[k * c + j] = (U0[k * c + j] < 0.0) ? -tiny : tiny;
+      // start vector
+      for (int i = 0; i < c; ++i) Z[i * la + j] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 11) / 11.0;
+      const int start = j - crank[j];
+      for (int itn = 0; itn < 3; ++itn) {
+        // P, L
+        for (int k = 0; k + 1 < c; ++k) {
+          if (Pv[k * c + j] != 0.0) {
+            const double t0 = Z[k * la + j];
+            Z[k * la + j] = Z[(k + 1) * la + j];
+            Z[(k + 1) * la + j] = t0;
+          }
+          Z[(k + 1) * la + j] -= Lm[k * c + j] * Z[k * la + j];
+        }
+        // U
+        for (int k = c - 1; k >= 0; --k) {
+          double y = Z[k * la + j];
+          if (k + 1 < c) y -= U1[k * c + j] * Z[(k + 1) * la + j];
+          if (k + 2 < c) y -= U2[k * c + j] * Z[(k + 2) * la + j];
+          Z[k * la + j] = y / U0[k * c + j];
+        }
+        // orthogonalise against the cluster's earlier vectors, then normalise
+        for (int q = start; q < j; ++q) {
+          double dot = 0.0;
+          for (int i = 0; i < c; ++i) dot += Z[i * la + q] * Z[i * la + j];
+          for (int i = 0; i < c; ++i) Z[i * la + j] -= dot * Z[i * la + q];
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < c; ++i) nrm += Z[i * la + j] * Z[i * la + j];
+        nrm = 1.0 / sqrt(nrm);
+        for (int i = 0; i < c; ++i) Z[i * la + j] *= nrm;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- 4. back-transformation C = Q Z ----
+  for (int k = c - 3; k >= 0; --k) {
+    const double t = tau[k];
+    if (t == 0.0) continue;
+    const int nk = c - k - 1;
+    // w_j = v^T Z(k+1:, j), four threads per column
+    for (int q = tid; q < 4 * c; q += nt) {
+      const int j = q / 4, part = q % 4;
+      double sw = 0.0;
+      for (int i = part; i < nk; i += 4) sw += (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) * Z[(k + 1 + i) * la + j];
+      sw += __shfl_xor(sw, 1, 4);
+      sw += __shfl_xor(sw, 2, 4);
+      if (part == 0) p[j] = t * sw;
+    }
+    __syncthreads();
+    for (int q = tid; q < nk * c; q += nt) {
+      const int i = q / c, j = q % c;
+      Z[(k + 1 + i) * la + j] -= (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) * p[j];
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < c * c; q += nt) {
+    const int i = q / c, j = q % c;
+    C[(int64_t)i * c + j] = Z[i * la + j];
+  }
+  for (int j = tid; j < c; j += nt) evals[j] = lam[j];
+  if (tid == 0 && info) info[0] = maxrank;
 }
 
 // HL: Z = C(0:m, m:c)^T (r x m, r = c - m); Householder QR; Q explicit; G = [C(:,0:m), C(:,m:c) Q].
@@ -320,17 +439,11 @@ __global__ void __launch_bounds__(256) chol_upper_kernel(const double* __restric
 
 }  // namespace
 
-int64_t syev_scratch(int c) {
-  const int64_t N = c + (c & 1);
-  return 2 * N * N + 6 * N + 16;
-}
+int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c + 16; }
 
 void launch_syev(const double* H, int64_t ldh, int c, double* evals, double* C, double* work, int* info,
                  hipStream_t st) {
-  if (c <= kLdsMax)
-    syev_kernel<true><<<1, kEigThreads, 0, st>>>(H, ldh, c, evals, C, work, info);
-  else
-    syev_kernel<false><<<1, kEigThreads, 0, st>>>(H, ldh, c, evals, C, work, info);
+  syev_kernel<<<1, kSyevThreads, 0, st>>>(H, ldh, c, evals, C, work, info);
 }
 
 void launch_hl_build(const double* C, int c, int m, double* G, double* work, hipStream_t st) {

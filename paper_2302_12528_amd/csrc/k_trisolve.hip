@@ -353,8 +353,7 @@ void launch_precond(const FactorDev& D, const SolveDev& Sd, int nlevels, int M, 
 }
 
 template <typename T>
-void launch_cast_to(const double* src, int64_t lds, T* dst, int64_t n, int m, hipStream_t st) {
-  const int M = m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64;
+void launch_cast_to(const double* src, int64_t lds, T* dst, int64_t n, int m, int M, hipStream_t st) {
   const int64_t total = n * M;
   if (total <= 0) return;
   cast_to_kernel<T><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(src, lds, dst, n, m, M);
@@ -363,7 +362,7 @@ void launch_cast_to(const double* src, int64_t lds, T* dst, int64_t n, int m, hi
 #define INST(T)                                                                                                 \
   template void launch_precond<T>(const FactorDev&, const SolveDev&, int, int, const T*, T*, T*, T*, T*, T*, T*, \
                                   double*, int64_t, int, hipStream_t);                                          \
-  template void launch_cast_to<T>(const double*, int64_t, T*, int64_t, int, hipStream_t);
+  template void launch_cast_to<T>(const double*, int64_t, T*, int64_t, int, int, hipStream_t);
 INST(float)
 INST(double)
 #undef INST
