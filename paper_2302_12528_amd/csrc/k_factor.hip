@@ -125,21 +125,25 @@ __device__ inline double rdl(double v, int l) {
 }
 
 template <typename T> struct Mfma;
+// Output row of D held by (lane, register q) of a 16x16x4 MFMA (column is lane % 16);
+// the FP32 and FP64 forms interleave the rows differently (checked on gfx950).
 template <> struct Mfma<float> {
   typedef float v4 __attribute__((ext_vector_type(4)));
   static __device__ inline v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int drow(int lane, int q) { return 4 * (lane / 16) + q; }
 };
 template <> struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
   static __device__ inline v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ inline int drow(int lane, int q) { return 4 * q + lane / 16; }
 };
 
 // acc (transposed) for this wave's 32 x 32 quadrant of the 64 x 64 tile C = As^T Bs, i.e.
 // C[r][c] = sum_k As[k][r] Bs[k][c], with 16x16x4 MFMAs.  The MFMA computes D = C^T so that lane l's
-// outputs (D rows 4(l/16)+q = C columns, D column l%16 = C row) are stored row-contiguously into
-// the column-major panel.  K is zero padded to a multiple of 4 in LDS.
+// outputs (D rows Mfma<T>::drow(l, q) = C columns, D column l%16 = C row) are stored
+// row-contiguously into the column-major panel.  K is zero padded to a multiple of 4 in LDS.
 template <typename T>
 __device__ inline void tile_mfma(const T (*As)[TB + 1], const T (*Bs)[TB + 1], int K,
                                  typename Mfma<T>::v4 acc[2][2]) {
@@ -302,7 +306,7 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
       if (r >= hI) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int c = qc + 16 * b + 4 * (lane / 16) + q;
+        const int c = qc + 16 * b + Mfma<T>::drow(lane, q);
         if (c >= hJ) continue;
         T* dst = C + r + (int64_t)c * ldc;
         if (KIND == 0 || KIND == 2)
