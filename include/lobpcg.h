@@ -126,6 +126,32 @@ lobpcg_status lobpcg_factor(lobpcg_ctx ctx);
 lobpcg_status lobpcg_solve(lobpcg_ctx ctx, const double* X0, int32_t maxit,
                            double* evals, double* evecs, lobpcg_info* info);
 
+/* Batched setup: count independent problems A[0..count-1] (CSR, each with its
+ * own n_b and grid hint) sharing k, m, tol and the factor precision
+ * (section 5.2 solves hundreds of such eigenproblems).  They are stored as one
+ * block-diagonal matrix: one ordering (each problem's rows stay contiguous),
+ * one factorization and one product with A per iteration over all of them;
+ * the dense block steps run per problem.  ||A_b||_2 is estimated per problem.
+ * Dense matrices are not batched.  Errors as lobpcg_setup (INVALID_ARG also
+ * for count < 1 or more than 2^31 nonzeros in total). */
+lobpcg_status lobpcg_setup_batched(const lobpcg_matrix* A, int32_t count, int32_t k, int32_t m,
+                                   double tol, lobpcg_precision factor_precision, void* hip_stream,
+                                   const lobpcg_options* opts, lobpcg_ctx* out);
+
+/* Algorithm 3 lines 2-17 for every problem of a batched context.  X0 (host
+ * array of count device pointers, each n_b x m; NULL array or NULL entry =
+ * seeded N(0,1) block), evals[b] (device, k), evecs[b] (device, n_b x k), and
+ * infos (host array of count, nullable).  Each problem stops at its own
+ * convergence (eq. (stop)) and is then frozen; the iteration ends when none is
+ * active.  Returns OK when all converged, otherwise the first non-OK status
+ * by problem index (outputs of converged and NOT_CONVERGED problems are
+ * written).  Synchronises the stream. */
+lobpcg_status lobpcg_solve_batched(lobpcg_ctx ctx, const double* const* X0, int32_t maxit,
+                                   double* const* evals, double* const* evecs, lobpcg_info* infos);
+
+/* Number of problems held by ctx (1 for lobpcg_setup). */
+int32_t lobpcg_batch_count(lobpcg_ctx ctx);
+
 /* Gradient of a loss L(theta_1..k, x_1..k) with respect to a diagonal
  * potential added to A, given d_evals = dL/dtheta (device, k, nullable) and
  * d_evecs = dL/dX (device, n x k row-major, nullable):

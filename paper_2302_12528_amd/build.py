@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result", f"-I{os.p
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 
-SOURCES = ["symbolic.cpp", "k_block.hip", "k_small.hip", "k_tsqr.hip", "k_factor.hip", "k_trisolve.hip",
+SOURCES = ["symbolic.cpp", "k_block.hip", "k_seg.hip", "k_small.hip", "k_factor.hip", "k_trisolve.hip",
            "k_adjoint.hip", "api.hip"]
 
 

@@ -1,6 +1,11 @@
 // C-ABI of liblobpcg (include/lobpcg.h): context, setup, factorization and the
 // Algorithm 3 working-precision loop driven from the host, with every
 // numerical step in the HIP kernels of k_*.hip.
+//
+// A context holds B >= 1 independent problems stored as one block-diagonal
+// matrix (one problem is B = 1): ordering, factorization, products with A and
+// the triangular solves run on the union; the dense block operations are
+// segmented per instance; converged instances are frozen by an active mask.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,16 +31,16 @@ lobpcg_status fail(lobpcg_status s, const std::string& msg) {
   return s;
 }
 
-#define HIP_TRY(expr)                                                                          \
-  do {                                                                                         \
-    hipError_t e_ = (expr);                                                                    \
+#define HIP_TRY(expr)                                                                                       \
+  do {                                                                                                      \
+    hipError_t e_ = (expr);                                                                                 \
     if (e_ != hipSuccess) return fail(LOBPCG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-#define ST_TRY(expr)                    \
-  do {                                  \
-    lobpcg_status s_ = (expr);          \
-    if (s_ != LOBPCG_OK) return s_;     \
+#define ST_TRY(expr)                \
+  do {                              \
+    lobpcg_status s_ = (expr);      \
+    if (s_ != LOBPCG_OK) return s_; \
   } while (0)
 
 double now_s() {
@@ -44,10 +49,91 @@ double now_s() {
 
 int pad_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64; }
 
+// Host side of an instance segmentation.
+struct SegHost {
+  std::vector<int64_t> inst_off;
+  std::vector<int32_t> tile_inst, tile_rows, chunk_inst, chunk_rows, inst_chunk_off;
+  std::vector<int64_t> tile_r0, chunk_r0;
+};
+
+void build_segments(const std::vector<int64_t>& inst_off, SegHost& H) {
+  H = SegHost();
+  H.inst_off = inst_off;
+  const int B = (int)inst_off.size() - 1;
+  const int64_t N = inst_off[B];
+  int64_t rpc = N / 384;
+  rpc = std::max<int64_t>(256, std::min<int64_t>(4096, rpc));
+  H.inst_chunk_off.push_back(0);
+  for (int b = 0; b < B; ++b) {
+    const int64_t r0 = inst_off[b], nb = inst_off[b + 1] - r0;
+    for (int64_t r = 0; r < nb; r += 64) {
+      H.tile_inst.push_back(b);
+      H.tile_r0.push_back(r0 + r);
+      H.tile_rows.push_back((int32_t)std::min<int64_t>(64, nb - r));
+    }
+    const int64_t cnt = std::max<int64_t>(1, (nb + rpc - 1) / rpc);
+    for (int64_t q = 0; q < cnt; ++q) {
+      const int64_t a = r0 + nb * q / cnt, e = r0 + nb * (q + 1) / cnt;
+      H.chunk_inst.push_back(b);
+      H.chunk_r0.push_back(a);
+      H.chunk_rows.push_back((int32_t)(e - a));
+    }
+    H.inst_chunk_off.push_back((int32_t)H.chunk_inst.size());
+  }
+}
+
+// Householder TSQR reduction tree for instances with row ranges inst_off and row blocks of rb.
+struct TsqrHost {
+  int rb = 0;
+  std::vector<int64_t> level_off;
+  std::vector<int32_t> items;
+  int64_t half = 1;
+};
+
+void build_tsqr(const std::vector<int64_t>& inst_off, int c, int rb, TsqrHost& T) {
+  T = TsqrHost();
+  T.rb = rb;
+  const int B = (int)inst_off.size() - 1;
+  std::vector<int64_t> rows(B), in0(B), cnt(B), newbase(B);
+  for (int b = 0; b < B; ++b) {
+    rows[b] = inst_off[b + 1] - inst_off[b];
+    in0[b] = inst_off[b];
+  }
+  T.level_off.push_back(0);
+  int64_t maxout = 1;
+  for (;;) {
+    bool last = true;
+    for (int b = 0; b < B; ++b) {
+      cnt[b] = (rows[b] + rb - 1) / rb;
+      if (cnt[b] > 1) last = false;
+    }
+    int64_t base = 0;
+    for (int b = 0; b < B; ++b) {
+      for (int64_t q = 0; q < cnt[b]; ++q) {
+        T.items.push_back(b);
+        T.items.push_back((int32_t)(in0[b] + q * rb));
+        T.items.push_back((int32_t)std::min<int64_t>(rb, rows[b] - q * rb));
+        T.items.push_back((int32_t)(last ? b : base + q));
+      }
+      newbase[b] = base;
+      base += cnt[b];
+    }
+    T.level_off.push_back((int64_t)T.items.size() / 4);
+    maxout = std::max(maxout, base);
+    if (last) break;
+    for (int b = 0; b < B; ++b) {
+      in0[b] = newbase[b] * c;
+      rows[b] = cnt[b] * c;
+    }
+  }
+  T.half = maxout * c * c;
+}
+
 }  // namespace
 
 struct lobpcg_ctx_s {
   hipStream_t st = nullptr;
+  int B = 1;
   int64_t n = 0, nnz = 0;
   int k = 0, m = 0, mp = 0;
   double tol = 0;
@@ -59,6 +145,10 @@ struct lobpcg_ctx_s {
   SolvePlan SP;
   FactorDev FD{};
   SolveDev SD{};
+  SegHost SH;
+  SegDev SG{};
+  TsqrHost TQ32, TQ64;
+  TsqrPlanDev TP32{}, TP64{};
   std::vector<void*> allocs;
   // matrix
   int32_t *d_prow = nullptr, *d_pcol = nullptr, *d_vmap = nullptr, *d_perm = nullptr, *d_iperm = nullptr;
@@ -66,16 +156,21 @@ struct lobpcg_ctx_s {
   int64_t ld_dense = 0;
   // factor (T = float or double)
   void *panel = nullptr, *upd = nullptr, *dinv = nullptr, *lcopy = nullptr;
-  int* d_flag = nullptr;   // [0] factor breakdown, [1] alg2 breakdown, [2] syev sweeps
+  int* d_flag = nullptr;      // factor breakdown
+  int* d_qflag = nullptr;     // B: Algorithm 2 step-3 breakdown per instance
+  int* d_info = nullptr;      // B: eigensolver diagnostics
+  int32_t* d_active = nullptr;
+  int32_t* d_active2 = nullptr;
+  std::vector<int32_t> active;
   // iteration
   double* Sb[2] = {nullptr, nullptr};
   double* ASb[2] = {nullptr, nullptr};
   void *rhs = nullptr, *ybuf = nullptr, *xbuf = nullptr, *uvec = nullptr, *fpart = nullptr, *bpart = nullptr;
   double *gpart = nullptr, *H = nullptr, *Cev = nullptr, *evals = nullptr, *Gupd = nullptr, *Gc = nullptr;
-  double *norms = nullptr, *rpart = nullptr, *syev_work = nullptr;
+  double *norms = nullptr, *syev_work = nullptr;
   void *tsqr_ws = nullptr, *Rl = nullptr;
-  double *Gv = nullptr, *Tm = nullptr;
-  double norm_a = 0;
+  double *Gv = nullptr, *Lt = nullptr;
+  std::vector<double> norm_a;
   int cur = 0;
   bool solved = false;
   double t_symbolic = 0, t_factor = 0;
@@ -118,6 +213,40 @@ lobpcg_status upload(lobpcg_ctx c, V*& dst, const std::vector<V>& src) {
   return LOBPCG_OK;
 }
 
+template <typename V>
+lobpcg_status upload_const(lobpcg_ctx c, const V*& dst, const std::vector<V>& src) {
+  V* p = nullptr;
+  ST_TRY(upload(c, p, src));
+  dst = p;
+  return LOBPCG_OK;
+}
+
+lobpcg_status upload_segments(lobpcg_ctx c) {
+  SegHost& H = c->SH;
+  SegDev& D = c->SG;
+  D.B = (int)H.inst_off.size() - 1;
+  ST_TRY(upload_const(c, D.tile_inst, H.tile_inst));
+  ST_TRY(upload_const(c, D.tile_r0, H.tile_r0));
+  ST_TRY(upload_const(c, D.tile_rows, H.tile_rows));
+  ST_TRY(upload_const(c, D.chunk_inst, H.chunk_inst));
+  ST_TRY(upload_const(c, D.chunk_r0, H.chunk_r0));
+  ST_TRY(upload_const(c, D.chunk_rows, H.chunk_rows));
+  ST_TRY(upload_const(c, D.inst_chunk_off, H.inst_chunk_off));
+  D.ntiles = (int64_t)H.tile_inst.size();
+  D.nchunks = (int64_t)H.chunk_inst.size();
+  D.active = c->d_active;
+  return LOBPCG_OK;
+}
+
+lobpcg_status upload_tsqr(lobpcg_ctx c, TsqrHost& H, TsqrPlanDev& D) {
+  D.rb = H.rb;
+  D.nlevels = (int)H.level_off.size() - 1;
+  D.level_off = H.level_off.data();
+  D.half = H.half;
+  ST_TRY(upload_const(c, D.items, H.items));
+  return LOBPCG_OK;
+}
+
 lobpcg_status validate_matrix(const lobpcg_matrix* A) {
   if (!A) return fail(LOBPCG_ERR_INVALID_ARG, "A is NULL");
   if (A->n < 1 || A->n > (int64_t)INT32_MAX - 1) return fail(LOBPCG_ERR_INVALID_ARG, "n out of range");
@@ -153,7 +282,6 @@ lobpcg_status validate_matrix(const lobpcg_matrix* A) {
         diag = true;
         if (!(A->val[e] > 0)) return fail(LOBPCG_ERR_INVALID_ARG, "non-positive diagonal");
       }
-      // symmetric pattern and values
       const int32_t* b = A->colind + A->rowptr[j];
       const int32_t* en = A->colind + A->rowptr[j + 1];
       const int32_t* it = std::lower_bound(b, en, (int32_t)i);
@@ -173,7 +301,7 @@ lobpcg_status check_launch(const char* where) {
   return LOBPCG_OK;
 }
 
-// Y = A X in the permuted basis
+// Y = A X in the permuted basis (the whole union)
 void apply_a(lobpcg_ctx c, const double* X, int64_t ldx, double* Y, int64_t ldy, int cols) {
   if (c->dense)
     launch_dense_mm(c->d_dense, c->ld_dense, c->n, X, ldx, Y, ldy, cols, c->st);
@@ -234,37 +362,538 @@ void load_rhs(lobpcg_ctx c, const double* R, int64_t ld, int cols) {
     launch_cast_to<double>(R, ld, static_cast<double*>(c->rhs), c->n, cols, c->mp, c->st);
 }
 
-// Algorithm 2 on W (n x cc, ld) in place; flag set on a step-3 breakdown.
+// Algorithm 2 on each active instance's block W (rows of the instance, cc columns, ld) in place.
 template <typename T>
-void mixed_qr_t(hipStream_t st, double* W, int64_t ld, int64_t n, int cc, void* ws, void* Rl_, double* Lt,
-                double* Gv, double* gpart, int* flag, double* Rout) {
+void mixed_qr_seg(hipStream_t st, const SegDev& S, const TsqrPlanDev& P, double* W, int64_t ld, int cc, void* ws,
+                  void* Rl_, double* Lt, double* Gv, double* gpart, int* flag, double* Rout) {
   T* Rl = static_cast<T*>(Rl_);
-  launch_tsqr<T>(W, ld, n, cc, static_cast<T*>(ws), Rl, st);      // step 1: lower(W) = Q_l R_l
-  launch_trsm_rows<T>(W, ld, n, cc, Rl, st);                       // step 2: V = W working(R_l)^{-1}
-  launch_gram(W, ld, W, ld, n, cc, cc, Gv, gpart, st);             // step 3: V^T V = L L^T
-  launch_chol_upper<T>(Gv, Rl, cc, Lt, Rout, flag, st);
-  launch_trsm_rows<double>(W, ld, n, cc, Lt, st);                  // step 4: Q = V L^{-T}
+  launch_stsqr<T>(S, P, W, ld, cc, static_cast<T*>(ws), Rl, st);          // step 1: lower(W) = Q_l R_l
+  launch_strsm_rows<T>(S, W, ld, cc, Rl, (int64_t)cc * cc, st);           // step 2: V = W working(R_l)^{-1}
+  launch_sgram(S, W, ld, W, ld, cc, cc, Gv, (int64_t)cc * cc, gpart, st); // step 3: V^T V = L L^T
+  launch_chol_upper<T>(Gv, Rl, cc, Lt, Rout, flag, S.active, S.B, st);
+  launch_strsm_rows<double>(S, W, ld, cc, Lt, (int64_t)cc * cc, st);      // step 4: Q = V L^{-T}
 }
 
-lobpcg_status ortho(lobpcg_ctx c, double* W, int64_t ld, int cc) {
-  int flag = 0;
+// Orthonormalise each active instance's W; an instance whose step-3 Cholesky breaks down is redone
+// with step 1 in FP64 (its W then holds V, a basis of the same span).  Instances that still break
+// down are reported through `failed`.
+lobpcg_status ortho(lobpcg_ctx c, double* W, int64_t ld, int cc, std::vector<int>& failed) {
+  lobpcg_ctx_s& C = *c;
+  failed.clear();
+  std::vector<int32_t> flags(C.B);
+  SegDev S = C.SG;
   for (int attempt = 0; attempt < 2; ++attempt) {
-    const bool lower = (attempt == 0) && c->opt.qr_lower;
-    HIP_TRY(hipMemsetAsync(c->d_flag + 1, 0, sizeof(int), c->st));
+    const bool lower = (attempt == 0) && C.opt.qr_lower;
+    launch_fill_int(C.d_qflag, 0, C.B, C.st);
     if (lower)
-      mixed_qr_t<float>(c->st, W, ld, c->n, cc, c->tsqr_ws, c->Rl, c->Tm, c->Gv, c->gpart, c->d_flag + 1, nullptr);
+      mixed_qr_seg<float>(C.st, S, C.TP32, W, ld, cc, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, C.d_qflag, nullptr);
     else
-      mixed_qr_t<double>(c->st, W, ld, c->n, cc, c->tsqr_ws, c->Rl, c->Tm, c->Gv, c->gpart, c->d_flag + 1,
-                         nullptr);
+      mixed_qr_seg<double>(C.st, S, C.TP64, W, ld, cc, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, C.d_qflag, nullptr);
     ST_TRY(check_launch("mixed QR"));
-    HIP_TRY(hipMemcpyAsync(&flag, c->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    HIP_TRY(hipStreamSynchronize(c->st));
-    if (flag == 0) return LOBPCG_OK;
-    if (!lower) break;
-    c->fallbacks++;
+    HIP_TRY(hipMemcpyAsync(flags.data(), C.d_qflag, C.B * sizeof(int32_t), hipMemcpyDeviceToHost, C.st));
+    HIP_TRY(hipStreamSynchronize(C.st));
+    std::vector<int32_t> redo(C.B, 0);
+    int nredo = 0;
+    for (int b = 0; b < C.B; ++b)
+      if (C.active[b] && flags[b]) {
+        redo[b] = 1;
+        ++nredo;
+      }
+    if (nredo == 0) break;
+    if (!lower) {
+      for (int b = 0; b < C.B; ++b)
+        if (redo[b]) failed.push_back(b);
+      break;
+    }
+    C.fallbacks += nredo;
+    HIP_TRY(hipMemcpyAsync(C.d_active2, redo.data(), C.B * sizeof(int32_t), hipMemcpyHostToDevice, C.st));
+    S.active = C.d_active2;
   }
-  return fail(LOBPCG_ERR_ORTHO_BREAKDOWN, "Algorithm 2 Cholesky of V^T V failed (W rank deficient)");
+  return LOBPCG_OK;
 }
+
+lobpcg_status set_active(lobpcg_ctx c) {
+  HIP_TRY(hipMemcpyAsync(c->d_active, c->active.data(), c->B * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  return LOBPCG_OK;
+}
+
+lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, int32_t m, double tol,
+                         lobpcg_precision factor_precision, void* hip_stream, const lobpcg_options* opts,
+                         lobpcg_ctx* out) {
+  if (!out) return fail(LOBPCG_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!mats || count < 1) return fail(LOBPCG_ERR_INVALID_ARG, "need at least one matrix");
+  for (int b = 0; b < count; ++b) ST_TRY(validate_matrix(&mats[b]));
+  if (k < 1 || m < k) return fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= k <= m");
+  if (m > 64) return fail(LOBPCG_ERR_INVALID_ARG, "block size m must be <= 64");
+  for (int b = 0; b < count; ++b) {
+    if (3 * (int64_t)m > mats[b].n) return fail(LOBPCG_ERR_INVALID_ARG, "need 3m <= n");
+    if (mats[b].format == 1 && count > 1) return fail(LOBPCG_ERR_INVALID_ARG, "dense matrices are not batched");
+    if (mats[b].format == 1 && mats[b].n > 16384)
+      return fail(LOBPCG_ERR_INVALID_ARG, "dense matrices are limited to n <= 16384");
+  }
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(LOBPCG_ERR_INVALID_ARG, "tol must be positive and finite");
+  if (factor_precision != LOBPCG_FP32 && factor_precision != LOBPCG_FP64)
+    return fail(LOBPCG_ERR_INVALID_ARG, "factor_precision must be LOBPCG_FP32 or LOBPCG_FP64");
+  lobpcg_options opt{};
+  opt.leaf_size = 64;
+  opt.stop_rule = LOBPCG_STOP_PAPER;
+  opt.qr_lower = 1;
+  if (opts) {
+    opt = *opts;
+    if (opt.leaf_size <= 0) opt.leaf_size = 64;
+    if (opt.stop_rule != LOBPCG_STOP_PAPER && opt.stop_rule != LOBPCG_STOP_NORMA)
+      return fail(LOBPCG_ERR_INVALID_ARG, "stop_rule");
+    if (opt.norm_a < 0 || !std::isfinite(opt.norm_a)) return fail(LOBPCG_ERR_INVALID_ARG, "norm_a");
+    if (opt.eig_tol < 0 || !std::isfinite(opt.eig_tol)) return fail(LOBPCG_ERR_INVALID_ARG, "eig_tol");
+  }
+  auto c = new lobpcg_ctx_s();
+  lobpcg_ctx_s& C = *c;
+  C.st = static_cast<hipStream_t>(hip_stream);
+  C.B = count;
+  C.k = k;
+  C.m = m;
+  C.mp = pad_m(m);
+  C.tol = tol;
+  C.prec = factor_precision;
+  C.opt = opt;
+  C.dense = (mats[0].format == 1);
+  // ---- union of the instances (block-diagonal), host pattern ----
+  std::vector<int64_t> inst_off(count + 1, 0);
+  for (int b = 0; b < count; ++b) inst_off[b + 1] = inst_off[b] + mats[b].n;
+  const int64_t n = inst_off[count];
+  C.n = n;
+  std::vector<int32_t> urow, ucol;
+  std::vector<double> uval;
+  const int32_t* rowptr = nullptr;
+  const int32_t* colind = nullptr;
+  const double* vals = nullptr;
+  std::vector<Component> comps(count);
+  for (int b = 0; b < count; ++b) {
+    comps[b].off = inst_off[b];
+    comps[b].n = mats[b].n;
+    for (int d = 0; d < 3; ++d) comps[b].grid[d] = mats[b].grid[d];
+  }
+  if (!C.dense) {
+    if (count == 1) {
+      rowptr = mats[0].rowptr;
+      colind = mats[0].colind;
+      vals = mats[0].val;
+      C.nnz = mats[0].nnz;
+    } else {
+      int64_t nnz = 0;
+      for (int b = 0; b < count; ++b) nnz += mats[b].nnz;
+      if (nnz > INT32_MAX) {
+        delete c;
+        return fail(LOBPCG_ERR_INVALID_ARG, "batch has more than 2^31 nonzeros");
+      }
+      urow.reserve(n + 1);
+      ucol.reserve(nnz);
+      uval.reserve(nnz);
+      urow.push_back(0);
+      for (int b = 0; b < count; ++b) {
+        const lobpcg_matrix& A = mats[b];
+        for (int64_t i = 0; i < A.n; ++i) {
+          for (int32_t e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+            ucol.push_back((int32_t)(A.colind[e] + inst_off[b]));
+            uval.push_back(A.val[e]);
+          }
+          urow.push_back((int32_t)ucol.size());
+        }
+      }
+      rowptr = urow.data();
+      colind = ucol.data();
+      vals = uval.data();
+      C.nnz = nnz;
+    }
+  }
+  // ---- host symbolic analysis (pattern only) ----
+  const double t0 = now_s();
+  std::string err = analyze_multi(n, rowptr, colind, comps, C.dense, opt.leaf_size, C.S);
+  if (!err.empty()) {
+    delete c;
+    return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
+  }
+  build_factor_plan(C.S, C.FP);
+  build_solve_plan(C.S, 64, 256, C.SP);
+  std::vector<int32_t> prow, pcol, vmap, apos;
+  if (!C.dense) {
+    permute_pattern(C.S, rowptr, colind, prow, pcol, vmap);
+    assembly_positions(C.S, prow, pcol, apos);
+  }
+  err = verify(C.S, C.FP, C.SP, prow, apos);
+  if (!err.empty()) {
+    delete c;
+    return fail(LOBPCG_ERR_INVALID_ARG, "symbolic structures failed verification: " + err);
+  }
+  for (int b = 0; b < count; ++b)
+    for (int64_t i = inst_off[b]; i < inst_off[b + 1]; ++i)
+      if (C.S.perm[i] < inst_off[b] || C.S.perm[i] >= inst_off[b + 1]) {
+        delete c;
+        return fail(LOBPCG_ERR_INVALID_ARG, "ordering mixed two instances");
+      }
+  build_segments(inst_off, C.SH);
+  build_tsqr(inst_off, m, tsqr_rows_per_block(m, 4), C.TQ32);
+  build_tsqr(inst_off, m, tsqr_rows_per_block(m, 8), C.TQ64);
+  C.t_symbolic = now_s() - t0;
+  auto cleanup = [&](lobpcg_status s) {
+    delete c;
+    return s;
+  };
+#define SETUP_TRY(expr)                      \
+  do {                                       \
+    lobpcg_status s_ = (expr);               \
+    if (s_ != LOBPCG_OK) return cleanup(s_); \
+  } while (0)
+  // ---- device structures ----
+  const Symbolic& S = C.S;
+  FactorDev& D = C.FD;
+  D.max_nr = S.max_nr;
+  SETUP_TRY(upload(c, D.begin, S.begin));
+  SETUP_TRY(upload(c, D.nc, S.nc));
+  SETUP_TRY(upload(c, D.nr, S.nr));
+  SETUP_TRY(upload(c, D.rows, S.rows));
+  SETUP_TRY(upload(c, D.row_off, S.row_off));
+  SETUP_TRY(upload(c, D.relpos, S.relpos));
+  SETUP_TRY(upload(c, D.child_ptr, S.child_ptr));
+  SETUP_TRY(upload(c, D.child_list, S.child_list));
+  SETUP_TRY(upload(c, D.inv_off, S.inv_off));
+  SETUP_TRY(upload(c, D.invmap, S.invmap));
+  SETUP_TRY(upload(c, D.panel_off, S.panel_off));
+  SETUP_TRY(upload(c, D.upd_off, S.upd_off));
+  SETUP_TRY(upload(c, D.uvec_off, S.uvec_off));
+  SETUP_TRY(upload(c, D.dinv_off, S.dinv_off));
+  SETUP_TRY(upload(c, D.lcopy_off, S.lcopy_off));
+  SETUP_TRY(upload(c, D.asm_items, C.FP.asm_items));
+  SETUP_TRY(upload(c, D.tasks, C.FP.tasks));
+  SETUP_TRY(upload(c, D.ownrow_items, C.FP.ownrow_items));
+  SETUP_TRY(upload_const(c, C.SD.fwd_items, C.SP.fwd_items));
+  SETUP_TRY(upload_const(c, C.SD.fwd_fin, C.SP.fwd_fin));
+  SETUP_TRY(upload_const(c, C.SD.bwd_items, C.SP.bwd_items));
+  SETUP_TRY(upload_const(c, C.SD.bwd_fin, C.SP.bwd_fin));
+  C.SD.fwd_level_off = C.SP.fwd_level_off.data();
+  C.SD.fwd_fin_level_off = C.SP.fwd_fin_level_off.data();
+  C.SD.bwd_level_off = C.SP.bwd_level_off.data();
+  C.SD.bwd_fin_level_off = C.SP.bwd_fin_level_off.data();
+  C.SD.ownrow_level_off = C.FP.ownrow_level_off.data();
+  SETUP_TRY(upload(c, C.d_perm, S.perm));
+  SETUP_TRY(upload(c, C.d_iperm, S.iperm));
+  C.active.assign(count, 1);
+  SETUP_TRY(upload(c, C.d_active, C.active));
+  SETUP_TRY(upload(c, C.d_active2, C.active));
+  SETUP_TRY(upload_segments(c));
+  SETUP_TRY(upload_tsqr(c, C.TQ32, C.TP32));
+  SETUP_TRY(upload_tsqr(c, C.TQ64, C.TP64));
+  if (C.dense) {
+    const lobpcg_matrix* A = &mats[0];
+    C.ld_dense = n;
+    SETUP_TRY(C.alloc(C.d_dense, n * n));
+    if (hipMemcpy2D(C.d_dense, n * sizeof(double), A->dense, A->ld * sizeof(double), n * sizeof(double), n,
+                    hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(LOBPCG_ERR_HIP, "copy of dense A failed"));
+    D.dense = C.d_dense;
+    D.ld_dense = n;
+    D.is_dense = 1;
+  } else {
+    SETUP_TRY(upload(c, C.d_prow, prow));
+    SETUP_TRY(upload(c, C.d_pcol, pcol));
+    SETUP_TRY(upload(c, C.d_vmap, vmap));
+    SETUP_TRY(upload(c, D.apos, apos));
+    SETUP_TRY(C.alloc(C.d_aval_orig, C.nnz));
+    SETUP_TRY(C.alloc(C.d_aval, C.nnz));
+    if (hipMemcpy(C.d_aval_orig, vals, C.nnz * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(LOBPCG_ERR_HIP, "copy of A values failed"));
+    launch_gather_values(C.d_aval_orig, C.d_vmap, C.d_aval, C.nnz, C.st);   // Pi^T A Pi, once
+    D.prow = C.d_prow;
+    D.pcol = C.d_pcol;
+    D.aval = C.d_aval;
+    D.is_dense = 0;
+  }
+  // ---- factor storage ----
+  const size_t tsz = (C.prec == LOBPCG_FP32) ? 4 : 8;
+  SETUP_TRY(C.alloc_bytes(C.panel, S.panel_total * tsz));
+  SETUP_TRY(C.alloc_bytes(C.upd, S.upd_total * tsz));
+  SETUP_TRY(C.alloc_bytes(C.dinv, S.dinv_total * tsz));
+  SETUP_TRY(C.alloc_bytes(C.lcopy, S.lcopy_max * tsz));
+  SETUP_TRY(C.alloc(C.d_flag, 4));
+  SETUP_TRY(C.alloc(C.d_qflag, count));
+  SETUP_TRY(C.alloc(C.d_info, count));
+  // ---- iteration buffers ----
+  const int m3 = 3 * m;
+  for (int b = 0; b < 2; ++b) {
+    SETUP_TRY(C.alloc(C.Sb[b], n * m3));
+    SETUP_TRY(C.alloc(C.ASb[b], n * m3));
+  }
+  SETUP_TRY(C.alloc_bytes(C.rhs, n * C.mp * tsz));
+  SETUP_TRY(C.alloc_bytes(C.ybuf, n * C.mp * tsz));
+  SETUP_TRY(C.alloc_bytes(C.xbuf, n * C.mp * tsz));
+  SETUP_TRY(C.alloc_bytes(C.uvec, std::max<int64_t>(1, S.uvec_total) * C.mp * tsz));
+  SETUP_TRY(C.alloc_bytes(C.fpart, std::max<int64_t>(1, C.SP.fwd_slots) * 64 * C.mp * tsz));
+  SETUP_TRY(C.alloc_bytes(C.bpart, std::max<int64_t>(1, C.SP.bwd_slots) * 64 * C.mp * tsz));
+  if (hipMemset(C.rhs, 0, n * C.mp * tsz) != hipSuccess) return cleanup(fail(LOBPCG_ERR_HIP, "memset"));
+  const int64_t nch = C.SG.nchunks;
+  SETUP_TRY(C.alloc(C.gpart, nch * std::max<int64_t>((int64_t)m3 * m3, 2 * m)));
+  SETUP_TRY(C.alloc(C.H, (int64_t)count * m3 * m3));
+  SETUP_TRY(C.alloc(C.Cev, (int64_t)count * m3 * m3));
+  SETUP_TRY(C.alloc(C.evals, (int64_t)count * m3));
+  SETUP_TRY(C.alloc(C.Gupd, (int64_t)count * m3 * 2 * m));
+  SETUP_TRY(C.alloc(C.Gc, (int64_t)count * 2 * m * m));
+  SETUP_TRY(C.alloc(C.norms, (int64_t)count * 2 * m));
+  SETUP_TRY(C.alloc(C.syev_work, (int64_t)count * syev_scratch(m3)));
+  SETUP_TRY(C.alloc_bytes(C.tsqr_ws, 2 * std::max(C.TQ32.half * 4, C.TQ64.half * 8)));
+  SETUP_TRY(C.alloc_bytes(C.Rl, (int64_t)count * m * m * 8));
+  SETUP_TRY(C.alloc(C.Gv, (int64_t)count * m * m));
+  SETUP_TRY(C.alloc(C.Lt, (int64_t)count * m * m));
+  if (check_launch("setup") != LOBPCG_OK) return cleanup(LOBPCG_ERR_HIP);
+  // ---- numeric factorization ----
+  {
+    lobpcg_status s = factor(c);
+    if (s != LOBPCG_OK) return cleanup(s);
+  }
+  // ---- ||A_b||_2 estimates (section 5.1): ||A Omega||_F / ||Omega||_F, Omega Gaussian n x m ----
+  C.norm_a.assign(count, opt.norm_a);
+  if (!(opt.norm_a > 0)) {
+    launch_gaussian_fill(C.Sb[1], n, m, m3, 0x5eed5eedull, C.st);
+    apply_a(c, C.Sb[1], m3, C.ASb[1], m3, m);
+    launch_scolnorms(C.SG, C.Sb[1], m3, m, C.norms, 2 * m, C.gpart, C.st);
+    launch_scolnorms(C.SG, C.ASb[1], m3, m, C.norms + m, 2 * m, C.gpart, C.st);
+    std::vector<double> h((int64_t)count * 2 * m);
+    if (hipMemcpy(h.data(), C.norms, h.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+      return cleanup(fail(LOBPCG_ERR_HIP, "norm estimate readback"));
+    for (int b = 0; b < count; ++b) {
+      double so = 0, sa = 0;
+      for (int j = 0; j < m; ++j) {
+        so += h[(int64_t)b * 2 * m + j];
+        sa += h[(int64_t)b * 2 * m + m + j];
+      }
+      C.norm_a[b] = std::sqrt(sa / so);
+    }
+  }
+  *out = c;
+  return LOBPCG_OK;
+#undef SETUP_TRY
+}
+
+// Algorithm 3 lines 2-17 for every instance of the context.
+lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, double* const* evals_out,
+                         double* const* evecs_out, lobpcg_info* infos) {
+  lobpcg_ctx_s& C = *c;
+  hipStream_t st = C.st;
+  const int B = C.B;
+  const int m = C.m, k = C.k, m3 = 3 * m;
+  const std::vector<int64_t>& off = C.SH.inst_off;
+  C.solved = false;
+  C.fallbacks = 0;
+  const double t_start = now_s();
+  std::vector<double> t_end(B, 0.0);
+  std::vector<int> iters(B, 0), nconv(B, 0);
+  std::vector<lobpcg_status> status(B, LOBPCG_NOT_CONVERGED);
+  std::vector<std::vector<double>> resid(B, std::vector<double>(k, 0.0));
+  C.active.assign(B, 1);
+  ST_TRY(set_active(c));
+  int cur = 0;
+  double* X = C.Sb[cur];
+  // line 2 (reading: orthonormalise X0 and one Rayleigh-Ritz step so Theta is diagonal)
+  for (int b = 0; b < B; ++b) {
+    const int64_t nb = off[b + 1] - off[b];
+    if (X0 && X0[b])
+      launch_gather_rows(X0[b], m, C.d_perm + off[b], off[b], X + off[b] * m3, m3, nb, m, st);
+    else
+      launch_gaussian_fill(X + off[b] * m3, nb, m, m3, 0x1234abcdull + (uint64_t)b, st);
+  }
+  ST_TRY(check_launch("start block"));
+  std::vector<int> failed;
+  ST_TRY(ortho(c, X, m3, m, failed));
+  for (int b : failed) {
+    C.active[b] = 0;
+    status[b] = LOBPCG_ERR_ORTHO_BREAKDOWN;
+  }
+  ST_TRY(set_active(c));
+  apply_a(c, X, m3, C.ASb[cur], m3, m);
+  launch_sgram(C.SG, X, m3, C.ASb[cur], m3, m, m, C.H, (int64_t)m3 * m3, C.gpart, st);
+  launch_syev(C.H, m, (int64_t)m3 * m3, m, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info, C.d_active, B,
+              st);
+  launch_hl_build(C.Cev, (int64_t)m3 * m3, m, m, C.Gupd, (int64_t)m3 * 2 * m, C.d_active, B, st);
+  launch_supdate(C.SG, C.Sb[cur], m3, C.Gupd, m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], m3, m, m, 1.0, 0.0, st);
+  launch_supdate(C.SG, C.ASb[cur], m3, C.Gupd, m, (int64_t)m3 * 2 * m, C.ASb[1 - cur], m3, m, m, 1.0, 0.0, st);
+  cur = 1 - cur;
+  ST_TRY(check_launch("initial Rayleigh-Ritz"));
+  bool haveP = false;
+  std::vector<double> hn((int64_t)B * 2 * m), th((int64_t)B * m3);
+  auto emit = [&](int b) -> lobpcg_status {   // write instance b's current Ritz pairs
+    const int64_t nb = off[b + 1] - off[b];
+    launch_gather_rows(C.Sb[cur], m3, C.d_iperm + off[b], 0, evecs_out[b], k, nb, k, st);
+    HIP_TRY(hipMemcpyAsync(evals_out[b], C.evals + (int64_t)b * m3, k * sizeof(double), hipMemcpyDeviceToDevice,
+                           st));
+    return LOBPCG_OK;
+  };
+  for (int it = 1; it <= maxit; ++it) {
+    double* Sx = C.Sb[cur];
+    double* ASx = C.ASb[cur];
+    // line 4: R = AX - X Theta, lower(R) into the solve buffer, column norms
+    if (C.prec == LOBPCG_FP32)
+      launch_sresidual<float>(C.SG, ASx, m3, Sx, m3, C.evals, m3, m, static_cast<float*>(C.rhs), C.mp, C.norms,
+                              C.gpart, st);
+    else
+      launch_sresidual<double>(C.SG, ASx, m3, Sx, m3, C.evals, m3, m, static_cast<double*>(C.rhs), C.mp, C.norms,
+                               C.gpart, st);
+    ST_TRY(check_launch("residual"));
+    HIP_TRY(hipMemcpyAsync(hn.data(), C.norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(th.data(), C.evals, th.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // line 5: n_c = leading run of columns passing the test, per instance
+    int nactive = 0;
+    for (int b = 0; b < B; ++b) {
+      if (!C.active[b]) continue;
+      iters[b] = it;
+      const double* hb = hn.data() + (int64_t)b * 2 * m;
+      const double* tb = th.data() + (int64_t)b * m3;
+      bool finite = true;
+      std::vector<double> res(m);
+      for (int j = 0; j < m; ++j) {
+        const double rn = std::sqrt(hb[j]), xn = std::sqrt(hb[m + j]);
+        if (!std::isfinite(rn) || !std::isfinite(xn) || !std::isfinite(tb[j])) finite = false;
+        const double denom = (C.opt.stop_rule == LOBPCG_STOP_PAPER) ? (C.norm_a[b] + std::fabs(tb[j])) * xn
+                                                                     : C.norm_a[b] * xn;
+        res[j] = rn / denom;
+      }
+      for (int j = 0; j < k; ++j) resid[b][j] = res[j];
+      if (!finite) {
+        status[b] = LOBPCG_ERR_NONFINITE;
+        C.active[b] = 0;
+        continue;
+      }
+      int nc = 0;
+      for (int j = 0; j < m; ++j) {
+        bool ok = res[j] <= C.tol;
+        if (ok && C.opt.eig_tol > 0) {
+          const double gap = std::max(tb[m - 1] - tb[j], 0.0);
+          ok = hb[j] <= C.opt.eig_tol * std::fabs(tb[j]) * gap;
+        }
+        if (!ok) break;
+        nc++;
+      }
+      nconv[b] = nc;
+      if (nc >= k) {   // lines 6-8
+        status[b] = LOBPCG_OK;
+        C.active[b] = 0;
+        ST_TRY(emit(b));
+        t_end[b] = now_s();
+      } else if (it == maxit) {
+        C.active[b] = 0;
+        ST_TRY(emit(b));
+        t_end[b] = now_s();
+      } else {
+        ++nactive;
+      }
+    }
+    if (nactive == 0) break;
+    ST_TRY(set_active(c));
+    // lines 9-10: W = working(f_T(lower(R)))   (on the union; frozen instances are ignored below)
+    const int wslot = haveP ? 2 * m : m;
+    double* W = Sx + wslot;
+    precond(c, W, m3);
+    ST_TRY(check_launch("preconditioner"));
+    // line 11: orthogonalize W against [X, P] twice
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_sgram(C.SG, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, st);
+      launch_supdate(C.SG, Sx, m3, C.Gc, m, (int64_t)2 * m * m, W, m3, wslot, m, -1.0, 1.0, st);
+    }
+    ST_TRY(check_launch("block Gram-Schmidt"));
+    // line 12: W = Q of Algorithm 2
+    ST_TRY(ortho(c, W, m3, m, failed));
+    if (!failed.empty()) {
+      for (int b : failed) {
+        C.active[b] = 0;
+        status[b] = LOBPCG_ERR_ORTHO_BREAKDOWN;
+        ST_TRY(emit(b));
+      }
+      ST_TRY(set_active(c));
+    }
+    // line 13: A_p = S^T A S, with A W the only new product
+    apply_a(c, W, m3, ASx + wslot, m3, m);
+    const int cc = wslot + m;
+    launch_sgram(C.SG, Sx, m3, ASx, m3, cc, cc, C.H, (int64_t)m3 * m3, C.gpart, st);
+    // line 14: A_p C = C D
+    launch_syev(C.H, cc, (int64_t)m3 * m3, cc, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info,
+                C.d_active, B, st);
+    // lines 15-16: HL basis and the new X, P (and A X, A P by the same combination)
+    launch_hl_build(C.Cev, (int64_t)m3 * m3, cc, m, C.Gupd, (int64_t)m3 * 2 * m, C.d_active, B, st);
+    launch_supdate(C.SG, Sx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
+    launch_supdate(C.SG, ASx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.ASb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
+    ST_TRY(check_launch("Rayleigh-Ritz"));
+    cur = 1 - cur;
+    haveP = true;
+    // frozen instances keep their (already emitted) results; their rows of the new buffers are not used
+  }
+  C.cur = cur;
+  ST_TRY(check_launch("output"));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double t_done = now_s();
+  lobpcg_status overall = LOBPCG_OK;
+  for (int b = 0; b < B; ++b) {
+    if (status[b] != LOBPCG_OK && overall == LOBPCG_OK) overall = status[b];
+    if (infos) {
+      lobpcg_info& I = infos[b];
+      I.iters = iters[b];
+      I.n_conv = nconv[b];
+      I.fallbacks = C.fallbacks;
+      I.nlevels = C.S.nlevels;
+      I.norm_a = C.norm_a[b];
+      I.t_symbolic = C.t_symbolic;
+      I.t_factor = C.t_factor;
+      I.t_solve = (t_end[b] > 0 ? t_end[b] : t_done) - t_start;
+      I.nnz_factor = C.S.nnz_lower;
+      I.factor_flops = C.S.flops;
+      if (I.resid)
+        for (int j = 0; j < k; ++j) I.resid[j] = resid[b][j];
+    }
+  }
+  // the context keeps the final Ritz pairs of a single instance for lobpcg_backward
+  C.solved = (B == 1) && (status[0] == LOBPCG_OK || status[0] == LOBPCG_NOT_CONVERGED);
+  if (overall != LOBPCG_OK && overall != LOBPCG_NOT_CONVERGED && g_last_error.empty())
+    g_last_error = lobpcg_status_string(overall);
+  if (overall == LOBPCG_ERR_NONFINITE) return fail(overall, "non-finite residual or Ritz value");
+  if (overall == LOBPCG_ERR_ORTHO_BREAKDOWN)
+    return fail(overall, "Algorithm 2 Cholesky of V^T V failed (W rank deficient) after the FP64 retry");
+  return overall;
+}
+
+// One-instance segmentation on the fly for the standalone entry points.
+struct TempSeg {
+  std::vector<void*> mem;
+  SegDev S{};
+  SegHost H;
+  template <typename V>
+  bool put(const V*& dst, const std::vector<V>& src) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(8, src.size() * sizeof(V))) != hipSuccess) return false;
+    mem.push_back(p);
+    if (!src.empty() && hipMemcpy(p, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice) != hipSuccess)
+      return false;
+    dst = static_cast<const V*>(p);
+    return true;
+  }
+  bool init(int64_t n) {
+    build_segments(std::vector<int64_t>{0, n}, H);
+    std::vector<int32_t> one{1};
+    S.B = 1;
+    S.ntiles = (int64_t)H.tile_inst.size();
+    S.nchunks = (int64_t)H.chunk_inst.size();
+    return put(S.active, one) && put(S.tile_inst, H.tile_inst) && put(S.tile_r0, H.tile_r0) &&
+           put(S.tile_rows, H.tile_rows) && put(S.chunk_inst, H.chunk_inst) && put(S.chunk_r0, H.chunk_r0) &&
+           put(S.chunk_rows, H.chunk_rows) && put(S.inst_chunk_off, H.inst_chunk_off);
+  }
+  void* get(int64_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, (size_t)std::max<int64_t>(bytes, 8)) != hipSuccess) return nullptr;
+    mem.push_back(p);
+    return p;
+  }
+  ~TempSeg() {
+    for (void* p : mem) (void)hipFree(p);
+  }
+};
 
 }  // namespace
 
@@ -290,194 +919,17 @@ const char* lobpcg_last_error(void) { return g_last_error.c_str(); }
 lobpcg_status lobpcg_setup(const lobpcg_matrix* A, int32_t k, int32_t m, double tol,
                            lobpcg_precision factor_precision, void* hip_stream, const lobpcg_options* opts,
                            lobpcg_ctx* out) {
-  if (!out) return fail(LOBPCG_ERR_INVALID_ARG, "out is NULL");
-  *out = nullptr;
-  ST_TRY(validate_matrix(A));
-  const int64_t n = A->n;
-  if (k < 1 || m < k) return fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= k <= m");
-  if (m > 64) return fail(LOBPCG_ERR_INVALID_ARG, "block size m must be <= 64");
-  if (A->format == 1 && A->n > 16384) return fail(LOBPCG_ERR_INVALID_ARG, "dense matrices are limited to n <= 16384");
-  if (3 * (int64_t)m > n) return fail(LOBPCG_ERR_INVALID_ARG, "need 3m <= n");
-  if (!(tol > 0) || !std::isfinite(tol)) return fail(LOBPCG_ERR_INVALID_ARG, "tol must be positive and finite");
-  if (factor_precision != LOBPCG_FP32 && factor_precision != LOBPCG_FP64)
-    return fail(LOBPCG_ERR_INVALID_ARG, "factor_precision must be LOBPCG_FP32 or LOBPCG_FP64");
-  lobpcg_options opt{};
-  opt.leaf_size = 64;
-  opt.stop_rule = LOBPCG_STOP_PAPER;
-  opt.qr_lower = 1;
-  if (opts) {
-    opt = *opts;
-    if (opt.leaf_size <= 0) opt.leaf_size = 64;
-    if (opt.stop_rule != LOBPCG_STOP_PAPER && opt.stop_rule != LOBPCG_STOP_NORMA)
-      return fail(LOBPCG_ERR_INVALID_ARG, "stop_rule");
-    if (opt.norm_a < 0 || !std::isfinite(opt.norm_a)) return fail(LOBPCG_ERR_INVALID_ARG, "norm_a");
-    if (opt.eig_tol < 0 || !std::isfinite(opt.eig_tol)) return fail(LOBPCG_ERR_INVALID_ARG, "eig_tol");
+  if (!A) {
+    if (out) *out = nullptr;
+    return fail(LOBPCG_ERR_INVALID_ARG, "A is NULL");
   }
-  auto c = new lobpcg_ctx_s();
-  lobpcg_ctx_s& C = *c;
-  C.st = static_cast<hipStream_t>(hip_stream);
-  C.n = n;
-  C.k = k;
-  C.m = m;
-  C.mp = pad_m(m);
-  C.tol = tol;
-  C.prec = factor_precision;
-  C.opt = opt;
-  C.dense = (A->format == 1);
-  // ---- host symbolic analysis (pattern only) ----
-  const double t0 = now_s();
-  std::string err = analyze(n, C.dense ? nullptr : A->rowptr, C.dense ? nullptr : A->colind, A->grid, C.dense,
-                            opt.leaf_size, C.S);
-  if (!err.empty()) {
-    delete c;
-    return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
-  }
-  build_factor_plan(C.S, C.FP);
-  build_solve_plan(C.S, 64, 256, C.SP);
-  std::vector<int32_t> prow, pcol, vmap, apos;
-  if (!C.dense) {
-    permute_pattern(C.S, A->rowptr, A->colind, prow, pcol, vmap);
-    assembly_positions(C.S, prow, pcol, apos);
-    C.nnz = A->nnz;
-  }
-  err = verify(C.S, C.FP, C.SP, prow, apos);
-  if (!err.empty()) {
-    delete c;
-    return fail(LOBPCG_ERR_INVALID_ARG, "symbolic structures failed verification: " + err);
-  }
-  C.t_symbolic = now_s() - t0;
-  auto cleanup = [&](lobpcg_status s) {
-    delete c;
-    return s;
-  };
-#define SETUP_TRY(expr)                 \
-  do {                                  \
-    lobpcg_status s_ = (expr);          \
-    if (s_ != LOBPCG_OK) return cleanup(s_); \
-  } while (0)
-  // ---- device structures ----
-  const Symbolic& S = C.S;
-  FactorDev& D = C.FD;
-  D.max_nr = S.max_nr;
-  SETUP_TRY(upload(c, D.begin, S.begin));
-  SETUP_TRY(upload(c, D.nc, S.nc));
-  SETUP_TRY(upload(c, D.nr, S.nr));
-  SETUP_TRY(upload(c, D.rows, S.rows));
-  SETUP_TRY(upload(c, D.row_off, S.row_off));
-  SETUP_TRY(upload(c, D.relpos, S.relpos));
-  SETUP_TRY(upload(c, D.child_ptr, S.child_ptr));
-  SETUP_TRY(upload(c, D.child_list, S.child_list));
-  SETUP_TRY(upload(c, D.inv_off, S.inv_off));
-  SETUP_TRY(upload(c, D.invmap, S.invmap));
-  SETUP_TRY(upload(c, D.panel_off, S.panel_off));
-  SETUP_TRY(upload(c, D.upd_off, S.upd_off));
-  SETUP_TRY(upload(c, D.uvec_off, S.uvec_off));
-  SETUP_TRY(upload(c, D.dinv_off, S.dinv_off));
-  SETUP_TRY(upload(c, D.lcopy_off, S.lcopy_off));
-  SETUP_TRY(upload(c, D.asm_items, C.FP.asm_items));
-  SETUP_TRY(upload(c, D.tasks, C.FP.tasks));
-  SETUP_TRY(upload(c, D.ownrow_items, C.FP.ownrow_items));
-  {
-    int32_t *fi = nullptr, *ff = nullptr, *bi = nullptr, *bf = nullptr;
-    SETUP_TRY(upload(c, fi, C.SP.fwd_items));
-    SETUP_TRY(upload(c, ff, C.SP.fwd_fin));
-    SETUP_TRY(upload(c, bi, C.SP.bwd_items));
-    SETUP_TRY(upload(c, bf, C.SP.bwd_fin));
-    C.SD.fwd_items = fi;
-    C.SD.fwd_fin = ff;
-    C.SD.bwd_items = bi;
-    C.SD.bwd_fin = bf;
-    C.SD.fwd_level_off = C.SP.fwd_level_off.data();
-    C.SD.fwd_fin_level_off = C.SP.fwd_fin_level_off.data();
-    C.SD.bwd_level_off = C.SP.bwd_level_off.data();
-    C.SD.bwd_fin_level_off = C.SP.bwd_fin_level_off.data();
-    C.SD.ownrow_level_off = C.FP.ownrow_level_off.data();
-  }
-  SETUP_TRY(upload(c, C.d_perm, S.perm));
-  SETUP_TRY(upload(c, C.d_iperm, S.iperm));
-  if (C.dense) {
-    C.ld_dense = n;
-    SETUP_TRY(C.alloc(C.d_dense, n * n));
-    if (hipMemcpy2D(C.d_dense, n * sizeof(double), A->dense, A->ld * sizeof(double), n * sizeof(double), n,
-                    hipMemcpyHostToDevice) != hipSuccess)
-      return cleanup(fail(LOBPCG_ERR_HIP, "copy of dense A failed"));
-    D.dense = C.d_dense;
-    D.ld_dense = n;
-    D.is_dense = 1;
-  } else {
-    SETUP_TRY(upload(c, C.d_prow, prow));
-    SETUP_TRY(upload(c, C.d_pcol, pcol));
-    SETUP_TRY(upload(c, C.d_vmap, vmap));
-    SETUP_TRY(upload(c, D.apos, apos));
-    SETUP_TRY(C.alloc(C.d_aval_orig, C.nnz));
-    SETUP_TRY(C.alloc(C.d_aval, C.nnz));
-    if (hipMemcpy(C.d_aval_orig, A->val, C.nnz * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-      return cleanup(fail(LOBPCG_ERR_HIP, "copy of A values failed"));
-    launch_gather_values(C.d_aval_orig, C.d_vmap, C.d_aval, C.nnz, C.st);   // Pi^T A Pi, once
-    D.prow = C.d_prow;
-    D.pcol = C.d_pcol;
-    D.aval = C.d_aval;
-    D.is_dense = 0;
-  }
-  // ---- factor storage ----
-  const size_t tsz = (C.prec == LOBPCG_FP32) ? 4 : 8;
-  SETUP_TRY(C.alloc_bytes(C.panel, S.panel_total * tsz));
-  SETUP_TRY(C.alloc_bytes(C.upd, S.upd_total * tsz));
-  SETUP_TRY(C.alloc_bytes(C.dinv, S.dinv_total * tsz));
-  SETUP_TRY(C.alloc_bytes(C.lcopy, S.lcopy_max * tsz));
-  SETUP_TRY(C.alloc(C.d_flag, 4));
-  // ---- iteration buffers ----
-  const int m3 = 3 * m;
-  for (int b = 0; b < 2; ++b) {
-    SETUP_TRY(C.alloc(C.Sb[b], n * m3));
-    SETUP_TRY(C.alloc(C.ASb[b], n * m3));
-  }
-  SETUP_TRY(C.alloc_bytes(C.rhs, n * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.ybuf, n * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.xbuf, n * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.uvec, std::max<int64_t>(1, S.uvec_total) * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.fpart, std::max<int64_t>(1, C.SP.fwd_slots) * 64 * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.bpart, std::max<int64_t>(1, C.SP.bwd_slots) * 64 * C.mp * tsz));
-  if (hipMemset(C.rhs, 0, n * C.mp * tsz) != hipSuccess) return cleanup(fail(LOBPCG_ERR_HIP, "memset"));
-  int64_t gp = std::max(gram_scratch(n, m3, m3), gram_scratch(n, m, m));
-  gp = std::max(gp, gram_scratch(n, 2 * m, m));
-  SETUP_TRY(C.alloc(C.gpart, gp));
-  SETUP_TRY(C.alloc(C.H, m3 * m3));
-  SETUP_TRY(C.alloc(C.Cev, m3 * m3));
-  SETUP_TRY(C.alloc(C.evals, m3));
-  SETUP_TRY(C.alloc(C.Gupd, m3 * 2 * m));
-  SETUP_TRY(C.alloc(C.Gc, 2 * m * m));
-  SETUP_TRY(C.alloc(C.norms, 2 * m));
-  SETUP_TRY(C.alloc(C.rpart, std::max(resid_scratch(n, m), resid_scratch(n, m3))));
-  SETUP_TRY(C.alloc(C.syev_work, syev_scratch(m3)));
-  SETUP_TRY(C.alloc_bytes(C.tsqr_ws, tsqr_scratch_elems(n, m) * 8));
-  SETUP_TRY(C.alloc_bytes(C.Rl, (int64_t)m * m * 8));
-  SETUP_TRY(C.alloc(C.Gv, (int64_t)m * m));
-  SETUP_TRY(C.alloc(C.Tm, (int64_t)m * m));
-  if (check_launch("setup") != LOBPCG_OK) return cleanup(LOBPCG_ERR_HIP);
-  // ---- numeric factorization ----
-  {
-    lobpcg_status s = factor(c);
-    if (s != LOBPCG_OK) return cleanup(s);
-  }
-  // ---- ||A||_2 estimate (section 5.1): ||A Omega||_F / ||Omega||_F, Omega Gaussian n x m ----
-  if (opt.norm_a > 0) {
-    C.norm_a = opt.norm_a;
-  } else {
-    launch_gaussian_fill(C.Sb[1], n, m, m3, 0x5eed5eedull, C.st);
-    apply_a(c, C.Sb[1], m3, C.ASb[1], m3, m);
-    launch_colnorms(C.Sb[1], m3, n, m, C.norms, C.rpart, C.st);
-    launch_colnorms(C.ASb[1], m3, n, m, C.norms + m, C.rpart, C.st);
-    std::vector<double> h(2 * m);
-    if (hipMemcpy(h.data(), C.norms, 2 * m * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-      return cleanup(fail(LOBPCG_ERR_HIP, "norm estimate readback"));
-    double so = 0, sa = 0;
-    for (int j = 0; j < m; ++j) { so += h[j]; sa += h[m + j]; }
-    C.norm_a = std::sqrt(sa / so);
-  }
-  *out = c;
-  return LOBPCG_OK;
-#undef SETUP_TRY
+  return setup_core(A, 1, k, m, tol, factor_precision, hip_stream, opts, out);
+}
+
+lobpcg_status lobpcg_setup_batched(const lobpcg_matrix* A, int32_t count, int32_t k, int32_t m, double tol,
+                                   lobpcg_precision factor_precision, void* hip_stream, const lobpcg_options* opts,
+                                   lobpcg_ctx* out) {
+  return setup_core(A, count, k, m, tol, factor_precision, hip_stream, opts, out);
 }
 
 lobpcg_status lobpcg_factor(lobpcg_ctx c) {
@@ -503,127 +955,28 @@ lobpcg_status lobpcg_update_values(lobpcg_ctx c, const double* vals, int32_t val
 lobpcg_status lobpcg_solve(lobpcg_ctx c, const double* X0, int32_t maxit, double* evals, double* evecs,
                            lobpcg_info* info) {
   if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->B != 1) return fail(LOBPCG_ERR_INVALID_ARG, "batched context: use lobpcg_solve_batched");
   if (maxit < 1) return fail(LOBPCG_ERR_INVALID_ARG, "maxit must be >= 1");
   if (!evals || !evecs) return fail(LOBPCG_ERR_INVALID_ARG, "output pointer is NULL");
-  const double t0 = now_s();
-  lobpcg_ctx_s& C = *c;
-  hipStream_t st = C.st;
-  const int64_t n = C.n;
-  const int m = C.m, k = C.k, m3 = 3 * m;
-  C.solved = false;
-  C.fallbacks = 0;
-  int cur = 0;
-  double* X = C.Sb[cur];
-  // line 2 (reading: orthonormalise X0 and one Rayleigh-Ritz step so Theta is diagonal)
-  if (X0)
-    launch_gather_rows(X0, m, C.d_perm, X, m3, n, m, st);
-  else
-    launch_gaussian_fill(X, n, m, m3, 0x1234abcdull, st);
-  ST_TRY(check_launch("start block"));
-  ST_TRY(ortho(c, X, m3, m));
-  apply_a(c, X, m3, C.ASb[cur], m3, m);
-  launch_gram(X, m3, C.ASb[cur], m3, n, m, m, C.H, C.gpart, st);
-  launch_syev(C.H, m, m, C.evals, C.Cev, C.syev_work, C.d_flag + 2, st);
-  launch_hl_build(C.Cev, m, m, C.Gupd, nullptr, st);
-  launch_block_update(C.Sb[cur], m3, C.Gupd, m, C.Sb[1 - cur], m3, n, m, m, 1.0, 0.0, st);
-  launch_block_update(C.ASb[cur], m3, C.Gupd, m, C.ASb[1 - cur], m3, n, m, m, 1.0, 0.0, st);
-  cur = 1 - cur;
-  ST_TRY(check_launch("initial Rayleigh-Ritz"));
-  bool haveP = false;
-  int iters = 0, nconv = 0;
-  std::vector<double> hn(2 * m), th(m3), res(m);
-  lobpcg_status status = LOBPCG_NOT_CONVERGED;
-  for (int it = 1; it <= maxit; ++it) {
-    double* Sx = C.Sb[cur];
-    double* ASx = C.ASb[cur];
-    // line 4: R = AX - X Theta, lower(R) into the solve buffer, column norms
-    if (C.prec == LOBPCG_FP32)
-      launch_residual<float>(ASx, m3, Sx, m3, C.evals, n, m, static_cast<float*>(C.rhs), C.mp, C.norms, C.rpart, st);
-    else
-      launch_residual<double>(ASx, m3, Sx, m3, C.evals, n, m, static_cast<double*>(C.rhs), C.mp, C.norms, C.rpart, st);
-    ST_TRY(check_launch("residual"));
-    HIP_TRY(hipMemcpyAsync(hn.data(), C.norms, 2 * m * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(th.data(), C.evals, m * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    iters = it;
-    // line 5: n_c = leading run of columns passing the test
-    nconv = 0;
-    bool finite = true;
-    for (int j = 0; j < m; ++j) {
-      const double rn = std::sqrt(hn[j]), xn = std::sqrt(hn[m + j]);
-      if (!std::isfinite(rn) || !std::isfinite(xn) || !std::isfinite(th[j])) finite = false;
-      const double denom = (C.opt.stop_rule == LOBPCG_STOP_PAPER) ? (C.norm_a + std::fabs(th[j])) * xn : C.norm_a * xn;
-      res[j] = rn / denom;
-    }
-    if (!finite) {
-      status = fail(LOBPCG_ERR_NONFINITE, "non-finite residual or Ritz value");
-      break;
-    }
-    for (int j = 0; j < m; ++j) {
-      bool ok = res[j] <= C.tol;
-      if (ok && C.opt.eig_tol > 0) {
-        const double rn2 = hn[j], gap = std::max(th[m - 1] - th[j], 0.0);
-        ok = rn2 <= C.opt.eig_tol * std::fabs(th[j]) * gap;
-      }
-      if (!ok) break;
-      nconv++;
-    }
-    if (nconv >= k) {   // lines 6-8
-      status = LOBPCG_OK;
-      break;
-    }
-    if (it == maxit) break;
-    // lines 9-10: W = working(f_T(lower(R)))
-    const int wslot = haveP ? 2 * m : m;
-    double* W = Sx + wslot;
-    precond(c, W, m3);
-    ST_TRY(check_launch("preconditioner"));
-    // line 11: orthogonalize W against [X, P] twice
-    for (int pass = 0; pass < 2; ++pass) {
-      launch_gram(Sx, m3, W, m3, n, wslot, m, C.Gc, C.gpart, st);
-      launch_block_update(Sx, m3, C.Gc, m, W, m3, n, wslot, m, -1.0, 1.0, st);
-    }
-    ST_TRY(check_launch("block Gram-Schmidt"));
-    // line 12: W = Q of Algorithm 2
-    ST_TRY(ortho(c, W, m3, m));
-    // line 13: A_p = S^T A S, with A W the only new product
-    apply_a(c, W, m3, ASx + wslot, m3, m);
-    const int cc = wslot + m;
-    launch_gram(Sx, m3, ASx, m3, n, cc, cc, C.H, C.gpart, st);
-    // line 14: A_p C = C D
-    launch_syev(C.H, cc, cc, C.evals, C.Cev, C.syev_work, C.d_flag + 2, st);
-    // lines 15-16: HL basis and the new X, P (and A X, A P by the same combination)
-    launch_hl_build(C.Cev, cc, m, C.Gupd, nullptr, st);
-    launch_block_update(Sx, m3, C.Gupd, 2 * m, C.Sb[1 - cur], m3, n, cc, 2 * m, 1.0, 0.0, st);
-    launch_block_update(ASx, m3, C.Gupd, 2 * m, C.ASb[1 - cur], m3, n, cc, 2 * m, 1.0, 0.0, st);
-    ST_TRY(check_launch("Rayleigh-Ritz"));
-    cur = 1 - cur;
-    haveP = true;
-  }
-  C.cur = cur;
-  if (status == LOBPCG_OK || status == LOBPCG_NOT_CONVERGED) {
-    launch_gather_rows(C.Sb[cur], m3, C.d_iperm, evecs, k, n, k, st);
-    HIP_TRY(hipMemcpyAsync(evals, C.evals, k * sizeof(double), hipMemcpyDeviceToDevice, st));
-    ST_TRY(check_launch("output"));
-    HIP_TRY(hipStreamSynchronize(st));
-    C.solved = true;
-  }
-  if (info) {
-    info->iters = iters;
-    info->n_conv = nconv;
-    info->fallbacks = C.fallbacks;
-    info->nlevels = C.S.nlevels;
-    info->norm_a = C.norm_a;
-    info->t_symbolic = C.t_symbolic;
-    info->t_factor = C.t_factor;
-    info->t_solve = now_s() - t0;
-    info->nnz_factor = C.S.nnz_lower;
-    info->factor_flops = C.S.flops;
-    if (info->resid)
-      for (int j = 0; j < k; ++j) info->resid[j] = res[j];
-  }
-  return status;
+  g_last_error.clear();
+  const double* x0[1] = {X0};
+  double* ev[1] = {evals};
+  double* ec[1] = {evecs};
+  return solve_core(c, x0, maxit, ev, ec, info);
 }
+
+lobpcg_status lobpcg_solve_batched(lobpcg_ctx c, const double* const* X0, int32_t maxit, double* const* evals,
+                                   double* const* evecs, lobpcg_info* infos) {
+  if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
+  if (maxit < 1) return fail(LOBPCG_ERR_INVALID_ARG, "maxit must be >= 1");
+  if (!evals || !evecs) return fail(LOBPCG_ERR_INVALID_ARG, "output pointer array is NULL");
+  for (int b = 0; b < c->B; ++b)
+    if (!evals[b] || !evecs[b]) return fail(LOBPCG_ERR_INVALID_ARG, "output pointer is NULL");
+  g_last_error.clear();
+  return solve_core(c, X0, maxit, evals, evecs, infos);
+}
+
+int32_t lobpcg_batch_count(lobpcg_ctx c) { return c ? c->B : 0; }
 
 // Gradient with respect to a diagonal potential (first-order perturbation theory):
 //   g = sum_i dtheta_i x_i o x_i - sum_i y_i o x_i,   y_i = (A - theta_i I)^+ (I - x_i x_i^T) dX_i.
@@ -635,6 +988,7 @@ lobpcg_status lobpcg_solve(lobpcg_ctx c, const double* X0, int32_t maxit, double
 lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double* d_evecs, double* d_diag) {
   if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
   if (!d_diag) return fail(LOBPCG_ERR_INVALID_ARG, "d_diag is NULL");
+  if (c->B != 1) return fail(LOBPCG_ERR_INVALID_ARG, "backward supports single-instance contexts");
   if (!c->solved) return fail(LOBPCG_ERR_STATE, "backward needs a successful lobpcg_solve first");
   lobpcg_ctx_s& C = *c;
   hipStream_t st = C.st;
@@ -642,13 +996,16 @@ lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double*
   const int k = C.k, m3 = 3 * C.m;
   const double* X = C.Sb[C.cur];   // x_i = X(:, i), ld 3m, permuted ordering
   const double* theta = C.evals;
+  const SegDev& SG = C.SG;         // one instance, active
   if (!C.bw_g) {
     ST_TRY(C.alloc(C.bw_g, n));
     for (double*& b : C.bw_blk) ST_TRY(C.alloc(b, n * k));
     ST_TRY(C.alloc(C.bw_small, 2 * (int64_t)k * k + 8 * k));
-    ST_TRY(C.alloc(C.bw_part, std::max(coldots_scratch(n, k), gram_scratch(n, k, k))));
+    ST_TRY(C.alloc(C.bw_part, std::max(coldots_scratch(n, k), SG.nchunks * (int64_t)k * k)));
   }
-  double *B = C.bw_blk[0], *Z = C.bw_blk[1], *R = C.bw_blk[2], *P = C.bw_blk[3], *Q = C.bw_blk[4],
+  C.active.assign(1, 1);
+  ST_TRY(set_active(c));
+  double *Bm = C.bw_blk[0], *Z = C.bw_blk[1], *R = C.bw_blk[2], *P = C.bw_blk[3], *Q = C.bw_blk[4],
          *Zp = C.bw_blk[5];
   double* coef = C.bw_small;                 // k x k: X^T dX
   double* Km = C.bw_small + k * k;           // k x k: span(X) coefficients of y
@@ -659,8 +1016,8 @@ lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double*
   bool conv = true;
   if (d_evecs) {
     // B = dX in the permuted ordering; coef = X^T B; B <- (I - X X^T) B
-    launch_gather_rows(d_evecs, k, C.d_perm, B, k, n, k, st);
-    launch_gram(X, m3, B, k, n, k, k, coef, C.bw_part, st);
+    launch_gather_rows(d_evecs, k, C.d_perm, 0, Bm, k, n, k, st);
+    launch_sgram(SG, X, m3, Bm, k, k, k, coef, 0, C.bw_part, st);
     std::vector<double> hc(k * k), th(k), hk(k * k, 0.0);
     HIP_TRY(hipMemcpyAsync(hc.data(), coef, hc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(th.data(), theta, k * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -672,11 +1029,10 @@ lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double*
           hk[l * k + i] = hc[l * k + i] / gap;
       }
     HIP_TRY(hipMemcpyAsync(Km, hk.data(), hk.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_block_update(X, m3, coef, k, B, k, n, k, k, -1.0, 1.0, st);
-    // projected PCG on (A - theta_i I) z_i = b_i in X^perp
+    launch_supdate(SG, X, m3, coef, k, 0, Bm, k, k, k, -1.0, 1.0, st);
     auto project = [&](double* V) {   // V <- (I - X X^T) V
-      launch_gram(X, m3, V, k, n, k, k, coef, C.bw_part, st);
-      launch_block_update(X, m3, coef, k, V, k, n, k, k, -1.0, 1.0, st);
+      launch_sgram(SG, X, m3, V, k, k, k, coef, 0, C.bw_part, st);
+      launch_supdate(SG, X, m3, coef, k, 0, V, k, k, k, -1.0, 1.0, st);
     };
     auto apply_prec = [&](const double* Rin, double* Out) {   // Out = P_X T Rin
       load_rhs(c, Rin, k, k);
@@ -684,8 +1040,8 @@ lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double*
       project(Out);
     };
     HIP_TRY(hipMemsetAsync(Z, 0, n * k * sizeof(double), st));
-    launch_copy_block(B, k, R, k, n, k, st);
-    launch_coldots(B, k, B, k, n, k, bb, C.bw_part, st);
+    launch_copy_block(Bm, k, R, k, n, k, st);
+    launch_coldots(Bm, k, Bm, k, n, k, bb, C.bw_part, st);
     apply_prec(R, Zp);
     launch_copy_block(Zp, k, P, k, n, k, st);
     launch_coldots(R, k, Zp, k, n, k, rz, C.bw_part, st);
@@ -700,8 +1056,11 @@ lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double*
     for (iters = 0; iters < 500; ++iters) {
       bool all = true;
       for (int i = 0; i < k; ++i) all = all && done[i];
-      if (all) { conv = true; break; }
-      apply_a(c, P, k, Q, k, k);                              // Q = (A - theta I) P, projected
+      if (all) {
+        conv = true;
+        break;
+      }
+      apply_a(c, P, k, Q, k, k);   // Q = (A - theta I) P, projected
       launch_shift_cols(Q, k, P, k, theta, Q, k, n, k, st);
       project(Q);
       launch_coldots(P, k, Q, k, n, k, pq, C.bw_part, st);
@@ -727,10 +1086,10 @@ lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double*
       launch_xpby_cols(beta, Zp, k, P, k, n, k, st);
     }
     // y = z + X K
-    launch_block_update(X, m3, Km, k, Z, k, n, k, k, 1.0, 1.0, st);
+    launch_supdate(SG, X, m3, Km, k, 0, Z, k, k, k, 1.0, 1.0, st);
   }
   launch_diag_grad(X, m3, d_evals, d_evecs ? Z : nullptr, k, n, k, C.bw_g, st);
-  launch_gather_rows(C.bw_g, 1, C.d_iperm, d_diag, 1, n, 1, st);
+  launch_gather_rows(C.bw_g, 1, C.d_iperm, 0, d_diag, 1, n, 1, st);
   ST_TRY(check_launch("backward"));
   HIP_TRY(hipStreamSynchronize(st));
   C.bw_iters = iters;
@@ -808,37 +1167,36 @@ lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t cc, int64_t ldw, int
   if (!W || n < 1 || cc < 1 || cc > 64 || ldw < cc || n < cc)
     return fail(LOBPCG_ERR_INVALID_ARG, "bad arguments to lobpcg_mixed_qr");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  std::vector<void*> mem;
-  auto get = [&](int64_t bytes) -> void* {
-    void* p = nullptr;
-    if (hipMalloc(&p, (size_t)std::max<int64_t>(bytes, 8)) != hipSuccess) return nullptr;
-    mem.push_back(p);
-    return p;
-  };
-  void* ws = get(tsqr_scratch_elems(n, cc) * 8);
-  void* Rl = get((int64_t)cc * cc * 8);
-  double* Gv = (double*)get((int64_t)cc * cc * 8);
-  double* Tm = (double*)get((int64_t)cc * cc * 8);
-  double* gp = (double*)get(gram_scratch(n, cc, cc) * 8);
-  int* flag = (int*)get(16);
+  TempSeg T;
+  if (!T.init(n)) return fail(LOBPCG_ERR_ALLOC, "hipMalloc failed");
+  TsqrHost th;
+  build_tsqr(std::vector<int64_t>{0, n}, cc, tsqr_rows_per_block(cc, lower_step1 ? 4 : 8), th);
+  TsqrPlanDev tp{};
+  tp.rb = th.rb;
+  tp.nlevels = (int)th.level_off.size() - 1;
+  tp.level_off = th.level_off.data();
+  tp.half = th.half;
+  void* ws = T.get(2 * th.half * 8);
+  void* Rl = T.get((int64_t)cc * cc * 8);
+  double* Gv = (double*)T.get((int64_t)cc * cc * 8);
+  double* Lt = (double*)T.get((int64_t)cc * cc * 8);
+  double* gp = (double*)T.get(T.S.nchunks * (int64_t)cc * cc * 8);
+  int* flag = (int*)T.get(16);
+  if (!ws || !Rl || !Gv || !Lt || !gp || !flag || !T.put(tp.items, th.items))
+    return fail(LOBPCG_ERR_ALLOC, "hipMalloc failed");
   lobpcg_status s = LOBPCG_OK;
-  if (!ws || !Rl || !Gv || !Tm || !gp || !flag) {
-    s = fail(LOBPCG_ERR_ALLOC, "hipMalloc failed");
-  } else {
-    (void)hipMemsetAsync(flag, 0, 16, st);
-    if (lower_step1)
-      mixed_qr_t<float>(st, W, ldw, n, cc, ws, Rl, Tm, Gv, gp, flag, R);
-    else
-      mixed_qr_t<double>(st, W, ldw, n, cc, ws, Rl, Tm, Gv, gp, flag, R);
-    int h = 0;
-    s = check_launch("mixed_qr");
-    if (s == LOBPCG_OK && hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
-      s = fail(LOBPCG_ERR_HIP, "flag readback");
-    if (s == LOBPCG_OK && hipStreamSynchronize(st) != hipSuccess) s = fail(LOBPCG_ERR_HIP, "sync");
-    if (s == LOBPCG_OK && h) s = fail(LOBPCG_ERR_ORTHO_BREAKDOWN, "Cholesky of V^T V failed");
-  }
+  (void)hipMemsetAsync(flag, 0, 16, st);
+  if (lower_step1)
+    mixed_qr_seg<float>(st, T.S, tp, W, ldw, cc, ws, Rl, Lt, Gv, gp, flag, R);
+  else
+    mixed_qr_seg<double>(st, T.S, tp, W, ldw, cc, ws, Rl, Lt, Gv, gp, flag, R);
+  int h = 0;
+  s = check_launch("mixed_qr");
+  if (s == LOBPCG_OK && hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    s = fail(LOBPCG_ERR_HIP, "flag readback");
+  if (s == LOBPCG_OK && hipStreamSynchronize(st) != hipSuccess) s = fail(LOBPCG_ERR_HIP, "sync");
+  if (s == LOBPCG_OK && h) s = fail(LOBPCG_ERR_ORTHO_BREAKDOWN, "Cholesky of V^T V failed");
   (void)hipStreamSynchronize(st);
-  for (void* p : mem) (void)hipFree(p);
   return s;
 }
 
@@ -847,12 +1205,13 @@ lobpcg_status lobpcg_gram(const double* X, int64_t ldx, const double* Y, int64_t
   if (!X || !Y || !G || n < 1 || c1 < 1 || c2 < 1 || c1 > 256 || c2 > 256 || ldx < c1 || ldy < c2)
     return fail(LOBPCG_ERR_INVALID_ARG, "bad arguments to lobpcg_gram");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  void* part = nullptr;
-  HIP_TRY(hipMalloc(&part, (size_t)gram_scratch(n, c1, c2) * 8));
-  launch_gram(X, ldx, Y, ldy, n, c1, c2, G, static_cast<double*>(part), st);
+  TempSeg T;
+  if (!T.init(n)) return fail(LOBPCG_ERR_ALLOC, "hipMalloc failed");
+  double* part = (double*)T.get(T.S.nchunks * (int64_t)c1 * c2 * 8);
+  if (!part) return fail(LOBPCG_ERR_ALLOC, "hipMalloc failed");
+  launch_sgram(T.S, X, ldx, Y, ldy, c1, c2, G, 0, part, st);
   lobpcg_status s = check_launch("gram");
   (void)hipStreamSynchronize(st);
-  (void)hipFree(part);
   return s;
 }
 
@@ -862,7 +1221,7 @@ lobpcg_status lobpcg_syev_small(const double* H, int32_t cc, double* evals, doub
   void* work = nullptr;
   HIP_TRY(hipMalloc(&work, (size_t)syev_scratch(cc) * 8 + 64));
   int* info = reinterpret_cast<int*>(static_cast<char*>(work) + syev_scratch(cc) * 8);
-  launch_syev(H, cc, cc, evals, evecs, static_cast<double*>(work), info, st);
+  launch_syev(H, cc, 0, cc, evals, 0, evecs, 0, static_cast<double*>(work), info, nullptr, 1, st);
   lobpcg_status s = check_launch("syev");
   (void)hipStreamSynchronize(st);
   (void)hipFree(work);

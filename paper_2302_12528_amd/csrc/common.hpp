@@ -6,64 +6,75 @@
 
 namespace lobpcg {
 
-// ---- block kernels (k_block.hip) ----
+// ---- instance segmentation of tall blocks (k_seg.hip) ----
+// Rows [inst_off[b], inst_off[b+1]) of a tall block belong to instance b.  Row tiles (<= 64 rows)
+// and reduction chunks never straddle instances.  All pointers are device pointers.
+struct SegDev {
+  int B;
+  const int32_t* active;                                                  // B, 0 = skip
+  const int32_t* tile_inst; const int64_t* tile_r0; const int32_t* tile_rows; int64_t ntiles;
+  const int32_t* chunk_inst; const int64_t* chunk_r0; const int32_t* chunk_rows; int64_t nchunks;
+  const int32_t* inst_chunk_off;                                          // B + 1
+};
+// Householder TSQR reduction tree: level l has items [level_off[l], level_off[l+1]) of 4 ints
+// {instance, first row, rows, output slot}; level 0 reads the block, later levels the stacked R's
+// of the previous level (ping-pong halves of `half` elements); the last level writes slot b of R.
+struct TsqrPlanDev {
+  int rb; int nlevels;
+  const int64_t* level_off;   // host, nlevels + 1
+  const int32_t* items;       // device
+  int64_t half;               // elements per scratch half
+};
+
+void launch_sgram(const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1, int c2,
+                  double* G, int64_t gstride, double* part, hipStream_t st);
+void launch_supdate(const SegDev& S, const double* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
+                    double* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st);
+template <typename T>
+void launch_sresidual(const SegDev& S, const double* AX, int64_t ldax, const double* X, int64_t ldx,
+                      const double* theta, int64_t tstride, int m, T* R, int64_t ldr, double* norms, double* part,
+                      hipStream_t st);
+void launch_scolnorms(const SegDev& S, const double* X, int64_t ldx, int c, double* norms, int64_t nstride,
+                      double* part, hipStream_t st);
+template <typename TU>
+void launch_strsm_rows(const SegDev& S, double* W, int64_t ld, int c, const TU* U, int64_t ustride, hipStream_t st);
+template <typename T>
+void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const double* W, int64_t ldw, int c, T* scratch, T* R,
+                  hipStream_t st);
+int tsqr_rows_per_block(int c, int elem_bytes);
+
+// ---- products with A and data movement (k_block.hip) ----
 // Y = A X for permuted CSR A; X, Y n x c row-major (ld), any c >= 1.
 void launch_spmm_csr(const int32_t* rowptr, const int32_t* colind, const double* val, int64_t n,
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int c, hipStream_t st);
 // Y = A X for dense row-major A (n x n, lda).
 void launch_dense_mm(const double* A, int64_t lda, int64_t n, const double* X, int64_t ldx, double* Y,
                      int64_t ldy, int c, hipStream_t st);
-// Gram: G (c1 x c2, row-major, ld c2) = X^T Y; part is scratch of gram_scratch(n, c1, c2) doubles.
-int64_t gram_scratch(int64_t n, int c1, int c2);
-void launch_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n, int c1, int c2,
-                 double* G, double* part, hipStream_t st);
-// Y = alpha X M + beta Y; X n x cin, M cin x cout (row-major, ldm), Y n x cout.
-// Y may alias X only if cout <= 64 and ldy == ldx.
-void launch_block_update(const double* X, int64_t ldx, const double* M, int64_t ldm, double* Y, int64_t ldy,
-                         int64_t n, int cin, int cout, double alpha, double beta, hipStream_t st);
-// R = AX - X diag(theta) cast to T (ld = m); norms[0..m) = ||R_j||^2, norms[m..2m) = ||X_j||^2.
-int64_t resid_scratch(int64_t n, int m);
-template <typename T>
-void launch_residual(const double* AX, int64_t ldax, const double* X, int64_t ldx, const double* theta,
-                     int64_t n, int m, T* R, int64_t ldr, double* norms, double* part, hipStream_t st);
-// Column sums of squares of an n x c block: norms[j] = ||X_j||^2 (deterministic).
-void launch_colnorms(const double* X, int64_t ldx, int64_t n, int c, double* norms, double* part, hipStream_t st);
-// dst[i*ldd + j] = src[idx[i]*lds + j], i < n_rows, j < c (idx NULL = identity); optional scale.
-void launch_gather_rows(const double* src, int64_t lds, const int32_t* idx, double* dst, int64_t ldd,
+// dst[i*ldd + j] = src[(idx[i] - base)*lds + j], i < nrows, j < c (idx NULL = identity)
+void launch_gather_rows(const double* src, int64_t lds, const int32_t* idx, int64_t base, double* dst, int64_t ldd,
                         int64_t nrows, int c, hipStream_t st);
-// vals[e] = src[map[e]] (+ shift[perm_row(e)] on the diagonal if shift != NULL).
 void launch_gather_values(const double* src, const int32_t* map, double* dst, int64_t nnz, hipStream_t st);
 void launch_add_diag_shift(const int32_t* rowptr, const int32_t* colind, double* val, const int32_t* perm,
                            const double* shift, int64_t n, hipStream_t st);
 // Deterministic N(0,1) fill (counter-based splitmix64 + Box-Muller).
 void launch_gaussian_fill(double* X, int64_t n, int c, int64_t ld, uint64_t seed, hipStream_t st);
-// Convert / copy blocks.
 void launch_copy_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int c, hipStream_t st);
-void launch_cast_f64_f32(const double* src, int64_t lds, float* dst, int64_t ldd, int64_t n, int c, hipStream_t st);
-void launch_cast_f32_f64(const float* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int c, hipStream_t st);
-// sum of partial vectors part[nb][len] in fixed order into out[len]
-void launch_reduce_parts(const double* part, int nb, int len, double* out, hipStream_t st);
+void launch_fill_int(int32_t* p, int32_t v, int64_t count, hipStream_t st);
 
-// ---- small dense kernels (k_small.hip), one workgroup each ----
-// Symmetric eigensolver (cyclic Jacobi): H c x c (ld) -> evals (c, ascending), C (c x c, ld c,
-// column j = eigenvector j).  work: syev_scratch(c) doubles of global scratch.
+// ---- small dense kernels (k_small.hip), one workgroup per instance ----
+// Symmetric eigensolver: H (c x c, ldh) -> evals ascending, C (c x c, column j = eigenvector j).
 int64_t syev_scratch(int c);
-void launch_syev(const double* H, int64_t ldh, int c, double* evals, double* C, double* work, int* info,
-                 hipStream_t st);
-// Hetmaniuk-Lehoucq: from C (c x c) of the Rayleigh-Ritz, G (c x 2m, ld 2m) = [C(:,1:m), C(:,m+1:c) V],
-// V = Householder Q of C(1:m, m+1:c)^T.  If c == m, G = C(:, 1:m) (ld m).
-void launch_hl_build(const double* C, int c, int m, double* G, double* work, hipStream_t st);
-// Algorithm 2 steps 2 and 4: W <- W U^{-1} row by row (U c x c upper, row-major, type TU), in place.
-template <typename TU>
-void launch_trsm_rows(double* W, int64_t ld, int64_t n, int c, const TU* U, hipStream_t st);
-// Algorithm 2 step 3: G = V^T V = L L^T; Lt = L^T (c x c row-major); Rout = L^T working(Rl) if non-NULL.
+void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, double* evals, int64_t estride, double* C,
+                 int64_t cstride, double* work, int* info, const int32_t* active, int B, hipStream_t st);
+// Hetmaniuk-Lehoucq: G (c x 2m, ld 2m) = [C(:,1:m), C(:,m+1:c) V], V = Householder Q of C(1:m, m+1:c)^T;
+// if c == m, G = C(:, 1:m) (ld m).
+void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, int64_t gstride,
+                     const int32_t* active, int B, hipStream_t st);
+// Algorithm 2 step 3 per instance: G = V^T V = L L^T; Lt = L^T; Rout = L^T working(Rl) if non-NULL;
+// flag[b] set on a non-positive pivot.  Matrices at stride c*c.
 template <typename T>
-void launch_chol_upper(const double* G, const T* Rl, int c, double* Lt, double* Rout, int* flag, hipStream_t st);
-
-// ---- TSQR (k_tsqr.hip): R factor only of an n x c block, Householder in precision T ----
-int64_t tsqr_scratch_elems(int64_t n, int c);   // elements of T
-template <typename T>
-void launch_tsqr(const double* W, int64_t ldw, int64_t n, int c, T* scratch, T* R, hipStream_t st);
+void launch_chol_upper(const double* G, const T* Rl, int c, double* Lt, double* Rout, int* flag,
+                       const int32_t* active, int B, hipStream_t st);
 
 // ---- factorization (k_factor.hip) ----
 struct FactorDev {

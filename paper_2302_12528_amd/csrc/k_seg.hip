@@ -1,0 +1,434 @@
+// Instance-segmented FP64 block kernels.  A batch of B independent problems is
+// stored as one tall block whose rows [inst_off[b], inst_off[b+1]) belong to
+// instance b (one instance is the case B = 1).  Row tiles and reduction
+// chunks never straddle instances; per-instance small matrices sit at fixed
+// strides; instances whose active flag is 0 are skipped.
+//   gram      G_b = X_b^T Y_b          (deterministic two-stage reduction)
+//   update    Y_b = alpha X_b M_b + beta Y_b
+//   residual  R_b = AX_b - X_b diag(theta_b), lower(R) to the solve buffer, column norms
+//   colnorms  ||X_b(:, j)||^2
+//   trsm      Y_b U_b = X_b row by row (Algorithm 2 steps 2 and 4)
+//   tsqr      R factor of each X_b (Algorithm 2 step 1), Householder in T
+#include "common.hpp"
+
+namespace lobpcg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Gram partials over one chunk of rows (a 16 RT x 16 CT output tile).
+// ---------------------------------------------------------------------------
+template <int RT, int CT>
+__global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const double* __restrict__ X, int64_t ldx,
+                                                                 const double* __restrict__ Y, int64_t ldy, int c1,
+                                                                 int c2, int tiles_j, double* __restrict__ part) {
+  constexpr int T1 = 16 * RT, T2 = 16 * CT, KR = 16;
+  __shared__ double Xs[KR][T1 + 1];
+  __shared__ double Ys[KR][T2 + 1];
+  const int q = blockIdx.x;
+  const int b = S.chunk_inst[q];
+  if (!S.active[b]) return;
+  const int t = threadIdx.x;
+  const int tx = t % 16, ty = t / 16;
+  const int ti = blockIdx.y / tiles_j, tj = blockIdx.y % tiles_j;
+  const int i0 = ti * T1, j0 = tj * T2;
+  const int64_t rbeg = S.chunk_r0[q];
+  const int64_t rend = rbeg + S.chunk_rows[q];
+  double acc[RT][CT];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) acc[i][j] = 0.0;
+  for (int64_t r0 = rbeg; r0 < rend; r0 += KR) {
+    for (int e = t; e < KR * T1; e += kThreads) {
+      const int k = e / T1, c = e % T1;
+      const int64_t r = r0 + k;
+      Xs[k][c] = (r < rend && i0 + c < c1) ? X[r * ldx + i0 + c] : 0.0;
+    }
+    for (int e = t; e < KR * T2; e += kThreads) {
+      const int k = e / T2, c = e % T2;
+      const int64_t r = r0 + k;
+      Ys[k][c] = (r < rend && j0 + c < c2) ? Y[r * ldy + j0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < KR; ++k) {
+      double a[RT], bv[CT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) a[i] = Xs[k][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) bv[j] = Ys[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc[i][j] = fma(a[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  double* P = part + (int64_t)q * c1 * c2;
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    const int gi = i0 + ty + 16 * i;
+    if (gi >= c1) continue;
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      const int gj = j0 + tx + 16 * j;
+      if (gj < c2) P[gi * c2 + gj] = acc[i][j];
+    }
+  }
+}
+
+// out_b[e] = sum over the chunks of instance b of part[chunk][e], in chunk order (four
+// interleaved partial sums combined in a fixed order).
+__global__ void __launch_bounds__(256) sreduce_kernel(SegDev S, const double* __restrict__ part, int len,
+                                                      double* __restrict__ out, int64_t ostride) {
+  __shared__ double red[4][64];
+  const int b = blockIdx.y;
+  if (!S.active[b]) return;
+  const int g = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int e = blockIdx.x * 64 + lane;
+  const int q0 = S.inst_chunk_off[b], q1 = S.inst_chunk_off[b + 1];
+  double s = 0.0;
+  if (e < len)
+    for (int q = q0 + g; q < q1; q += 4) s += part[(int64_t)q * len + e];
+  red[g][lane] = s;
+  __syncthreads();
+  if (g == 0 && e < len) out[(int64_t)b * ostride + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// ---------------------------------------------------------------------------
+// Block update on one 64-row tile: Y = alpha X M_b + beta Y (64 x 64 output tile).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const double* X, int64_t ldx,
+                                                           const double* __restrict__ M, int64_t ldm, int64_t mstride,
+                                                           double* Y, int64_t ldy, int K, int cols, double alpha,
+                                                           double beta) {
+  __shared__ double As[16][65];
+  __shared__ double Bs[16][64];
+  const int q = blockIdx.x;
+  const int b = S.tile_inst[q];
+  if (!S.active[b]) return;
+  const int64_t r0 = S.tile_r0[q];
+  const int rows = S.tile_rows[q];
+  const double* Mb = M + (int64_t)b * mstride;
+  const int t = threadIdx.x;
+  const int tx = t % 16, ty = t / 16;
+  const int c0 = blockIdx.y * 64;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  const int lr = t / 4, lk = (t % 4) * 4;
+  const int bk = t / 16, bc = (t % 16) * 4;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int k = k0 + lk + qq;
+      As[lk + qq][lr] = (lr < rows && k < K) ? X[(r0 + lr) * ldx + k] : 0.0;
+    }
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int k = k0 + bk;
+      const int cc = c0 + bc + qq;
+      Bs[bk][bc + qq] = (k < K && cc < cols) ? Mb[(int64_t)k * ldm + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      double a[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Bs[k][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = ty + 16 * i;
+    if (r >= rows) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = c0 + tx + 16 * j;
+      if (cc >= cols) continue;
+      double v = alpha * acc[i][j];
+      if (beta != 0.0) v = fma(beta, Y[(r0 + r) * ldy + cc], v);
+      Y[(r0 + r) * ldy + cc] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual over one chunk: R = AX - X diag(theta_b) (cast to T), partial column sums of squares.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads) sresidual_kernel(SegDev S, const double* __restrict__ AX, int64_t ldax,
+                                                             const double* __restrict__ X, int64_t ldx,
+                                                             const double* __restrict__ theta, int64_t tstride,
+                                                             int m, T* __restrict__ R, int64_t ldr,
+                                                             double* __restrict__ part) {
+  __shared__ double red[2][4][64];
+  const int q = blockIdx.x;
+  const int b = S.chunk_inst[q];
+  if (!S.active[b]) return;
+  const int t = threadIdx.x;
+  const int j = t % 64, g = t / 64;
+  const int64_t rbeg = S.chunk_r0[q];
+  const int64_t rend = rbeg + S.chunk_rows[q];
+  double rs = 0.0, xs = 0.0;
+  if (j < m) {
+    const double th = theta[(int64_t)b * tstride + j];
+    for (int64_t r = rbeg + g; r < rend; r += 4) {
+      const double x = X[r * ldx + j];
+      const double v = AX[r * ldax + j] - x * th;
+      R[r * ldr + j] = (T)v;
+      rs = fma(v, v, rs);
+      xs = fma(x, x, xs);
+    }
+  }
+  red[0][g][j] = rs;
+  red[1][g][j] = xs;
+  __syncthreads();
+  if (t < m) {
+    part[(int64_t)q * 2 * m + t] = ((red[0][0][t] + red[0][1][t]) + red[0][2][t]) + red[0][3][t];
+    part[(int64_t)q * 2 * m + m + t] = ((red[1][0][t] + red[1][1][t]) + red[1][2][t]) + red[1][3][t];
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) scolnorm_kernel(SegDev S, const double* __restrict__ X, int64_t ldx,
+                                                            int c, double* __restrict__ part) {
+  __shared__ double red[4][64];
+  const int q = blockIdx.x;
+  const int b = S.chunk_inst[q];
+  if (!S.active[b]) return;
+  const int t = threadIdx.x;
+  const int j = t % 64, g = t / 64;
+  const int64_t rbeg = S.chunk_r0[q];
+  const int64_t rend = rbeg + S.chunk_rows[q];
+  double xs = 0.0;
+  if (j < c)
+    for (int64_t r = rbeg + g; r < rend; r += 4) {
+      const double x = X[r * ldx + j];
+      xs = fma(x, x, xs);
+    }
+  red[g][j] = xs;
+  __syncthreads();
+  if (t < c) part[(int64_t)q * c + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+}
+
+// ---------------------------------------------------------------------------
+// Row-wise triangular solve on one 64-row tile: W_b <- W_b U_b^{-1}.
+// ---------------------------------------------------------------------------
+template <typename TU>
+__global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, double* W, int64_t ld, int c,
+                                                        const TU* __restrict__ U, int64_t ustride) {
+  extern __shared__ double smem[];
+  double* Us = smem;            // c x c
+  double* Ws = smem + c * c;    // c x 64, column-major per thread row
+  const int q = blockIdx.x;
+  const int b = S.tile_inst[q];
+  if (!S.active[b]) return;
+  const int64_t r0 = S.tile_r0[q];
+  const int rows = S.tile_rows[q];
+  const TU* Ub = U + (int64_t)b * ustride;
+  const int t = threadIdx.x;
+  for (int e = t; e < c * c; e += 64) Us[e] = (double)Ub[e];
+  for (int e = t; e < 64 * c; e += 64) {
+    const int i = e / c, j = e % c;
+    Ws[j * 64 + i] = (i < rows) ? W[(r0 + i) * ld + j] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < c; ++j) {
+    double s = Ws[j * 64 + t];
+#pragma unroll 4
+    for (int i = 0; i < j; ++i) s -= Ws[i * 64 + t] * Us[i * c + j];
+    Ws[j * 64 + t] = s / Us[j * c + j];
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * c; e += 64) {
+    const int i = e / c, j = e % c;
+    if (i < rows) W[(r0 + i) * ld + j] = Ws[j * 64 + i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// TSQR block: Householder QR (R only) of a block of `rows` rows starting at `in`,
+// one wave per block, LDS row stride c + 1.
+// ---------------------------------------------------------------------------
+template <typename T, typename Tin>
+__global__ void __launch_bounds__(64) stsqr_kernel(SegDev S, const Tin* in, int64_t ldin, const int32_t* __restrict__ items,
+                                                   int c, int rb, T* out) {
+  extern __shared__ unsigned char smem_raw[];
+  T* z = reinterpret_cast<T*>(smem_raw);
+  __shared__ T wv[64];
+  const int* it = items + 4 * blockIdx.x;   // {instance, first row, rows, output slot}
+  const int b = it[0];
+  if (!S.active[b]) return;
+  const int64_t r0 = it[1];
+  const int rows = it[2];
+  const int slot = it[3];
+  const int lane = threadIdx.x;
+  const int ldz = c + 1;
+  for (int e = lane; e < rb * c; e += 64) {
+    const int i = e / c, j = e % c;
+    z[i * ldz + j] = (i < rows) ? (T)in[(r0 + i) * ldin + j] : (T)0;
+  }
+  __syncthreads();
+  const int kmax = (c < rb) ? c : rb;
+  for (int j = 0; j < kmax; ++j) {
+    T s = 0;
+    for (int i = j + 1 + lane; i < rb; i += 64) s += z[i * ldz + j] * z[i * ldz + j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const T alpha = z[j * ldz + j];
+    T tj = 0, beta = alpha, scale = 0;
+    if (s > (T)0) {
+      const T xn = sqrt(alpha * alpha + s);
+      beta = (alpha >= (T)0) ? -xn : xn;
+      tj = (beta - alpha) / beta;
+      scale = (T)1 / (alpha - beta);
+    }
+    __syncthreads();
+    if (s > (T)0)
+      for (int i = j + 1 + lane; i < rb; i += 64) z[i * ldz + j] *= scale;
+    if (lane == 0) z[j * ldz + j] = beta;
+    __syncthreads();
+    for (int k = j + 1; k < c; ++k) {
+      T w = 0;
+      for (int i = j + lane; i < rb; i += 64) w += (i == j ? (T)1 : z[i * ldz + j]) * z[i * ldz + k];
+      for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+      if (lane == 0) wv[k] = w;
+    }
+    __syncthreads();
+    const int wc = c - j - 1;
+    if (wc > 0)
+      for (int e = lane; e < (rb - j) * wc; e += 64) {
+        const int i = j + e / wc, k = j + 1 + e % wc;
+        const T vi = (i == j) ? (T)1 : z[i * ldz + j];
+        z[i * ldz + k] -= tj * vi * wv[k];
+      }
+    __syncthreads();
+  }
+  T* R = out + (int64_t)slot * c * c;
+  for (int e = lane; e < c * c; e += 64) {
+    const int i = e / c, j = e % c;
+    R[e] = (j >= i && i < rb) ? z[i * ldz + j] : (T)0;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+namespace {
+inline int gram_rt(int c) { return c <= 16 ? 1 : c <= 32 ? 2 : c <= 48 ? 3 : c <= 64 ? 4 : 6; }
+
+template <int RT, int CT>
+void sgram_launch(dim3 g, const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1, int c2,
+                  int tj, double* part, hipStream_t st) {
+  sgram_partial_kernel<RT, CT><<<g, kThreads, 0, st>>>(S, X, ldx, Y, ldy, c1, c2, tj, part);
+}
+template <int RT>
+void sgram_ct(int ct, dim3 g, const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1,
+              int c2, int tj, double* part, hipStream_t st) {
+  switch (ct) {
+    case 1: sgram_launch<RT, 1>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    case 2: sgram_launch<RT, 2>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    case 3: sgram_launch<RT, 3>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    case 4: sgram_launch<RT, 4>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    default: sgram_launch<RT, 6>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+  }
+}
+}  // namespace
+
+void launch_sgram(const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1, int c2,
+                  double* G, int64_t gstride, double* part, hipStream_t st) {
+  if (c1 <= 0 || c2 <= 0 || S.nchunks <= 0) return;
+  const int rt = gram_rt(c1), ct = gram_rt(c2);
+  const int tj = cdiv(c2, 16 * ct);
+  dim3 g((unsigned)S.nchunks, cdiv(c1, 16 * rt) * tj);
+  switch (rt) {
+    case 1: sgram_ct<1>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    case 2: sgram_ct<2>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    case 3: sgram_ct<3>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    case 4: sgram_ct<4>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    default: sgram_ct<6>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+  }
+  const int len = c1 * c2;
+  sreduce_kernel<<<dim3(cdiv(len, 64), S.B), 256, 0, st>>>(S, part, len, G, gstride);
+}
+
+void launch_supdate(const SegDev& S, const double* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
+                    double* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st) {
+  if (cout <= 0 || S.ntiles <= 0) return;
+  dim3 g((unsigned)S.ntiles, cdiv(cout, 64));
+  supdate_kernel<<<g, kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin, cout, alpha, beta);
+}
+
+template <typename T>
+void launch_sresidual(const SegDev& S, const double* AX, int64_t ldax, const double* X, int64_t ldx,
+                      const double* theta, int64_t tstride, int m, T* R, int64_t ldr, double* norms, double* part,
+                      hipStream_t st) {
+  if (S.nchunks <= 0) return;
+  sresidual_kernel<T><<<(unsigned)S.nchunks, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, m, R, ldr, part);
+  sreduce_kernel<<<dim3(cdiv(2 * m, 64), S.B), 256, 0, st>>>(S, part, 2 * m, norms, 2 * m);
+}
+template void launch_sresidual<float>(const SegDev&, const double*, int64_t, const double*, int64_t, const double*,
+                                      int64_t, int, float*, int64_t, double*, double*, hipStream_t);
+template void launch_sresidual<double>(const SegDev&, const double*, int64_t, const double*, int64_t, const double*,
+                                       int64_t, int, double*, int64_t, double*, double*, hipStream_t);
+
+void launch_scolnorms(const SegDev& S, const double* X, int64_t ldx, int c, double* norms, int64_t nstride,
+                      double* part, hipStream_t st) {
+  if (S.nchunks <= 0) return;
+  scolnorm_kernel<<<(unsigned)S.nchunks, kThreads, 0, st>>>(S, X, ldx, c, part);
+  sreduce_kernel<<<dim3(cdiv(c, 64), S.B), 256, 0, st>>>(S, part, c, norms, nstride);
+}
+
+template <typename TU>
+void launch_strsm_rows(const SegDev& S, double* W, int64_t ld, int c, const TU* U, int64_t ustride, hipStream_t st) {
+  if (S.ntiles <= 0) return;
+  const size_t lds = (size_t)(c * c + 64 * c) * sizeof(double);
+  strsm_rows_kernel<TU><<<(unsigned)S.ntiles, 64, lds, st>>>(S, W, ld, c, U, ustride);
+}
+template void launch_strsm_rows<float>(const SegDev&, double*, int64_t, int, const float*, int64_t, hipStream_t);
+template void launch_strsm_rows<double>(const SegDev&, double*, int64_t, int, const double*, int64_t, hipStream_t);
+
+template <typename T>
+void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const double* W, int64_t ldw, int c, T* scratch, T* R,
+                  hipStream_t st) {
+  const int rb = P.rb;
+  const size_t lds = (size_t)rb * (c + 1) * sizeof(T);
+  for (int l = 0; l < P.nlevels; ++l) {
+    const int64_t i0 = P.level_off[l], i1 = P.level_off[l + 1];
+    if (i1 <= i0) continue;
+    T* out = (l == P.nlevels - 1) ? R : scratch + (l % 2) * P.half;
+    if (l == 0)
+      stsqr_kernel<T, double><<<(unsigned)(i1 - i0), 64, lds, st>>>(S, W, ldw, P.items + 4 * i0, c, rb, out);
+    else
+      stsqr_kernel<T, T><<<(unsigned)(i1 - i0), 64, lds, st>>>(S, scratch + ((l - 1) % 2) * P.half, c,
+                                                              P.items + 4 * i0, c, rb, out);
+  }
+}
+template void launch_stsqr<float>(const SegDev&, const TsqrPlanDev&, const double*, int64_t, int, float*, float*,
+                                  hipStream_t);
+template void launch_stsqr<double>(const SegDev&, const TsqrPlanDev&, const double*, int64_t, int, double*, double*,
+                                   hipStream_t);
+
+int tsqr_rows_per_block(int c, int elem_bytes) {
+  int rb = 32 * 1024 / ((c + 1) * elem_bytes);
+  if (rb > 1024) rb = 1024;
+  if (rb < 2 * c) rb = 2 * c;
+  return rb;
+}
+
+}  // namespace lobpcg

@@ -3,8 +3,7 @@
 //    line 14): tridiagonalization, bisection, inverse iteration;
 //  * the Hetmaniuk-Lehoucq step (lines 15-16): V = orthonormal factor of
 //    C(1:m, m+1:c)^T and G = [C(:,1:m), C(:,m+1:c) V];
-//  * Algorithm 2's steps 2-4: row-wise triangular solves with the lower-precision
-//    R factor and with L^T, and the Cholesky factorization of V^T V.
+//  * Algorithm 2's step 3: the Cholesky factorization of V^T V.
 #include <cmath>
 
 #include "common.hpp"
@@ -48,9 +47,16 @@ constexpr int kSyevThreads = 512;
 constexpr int kSyevLds = 96;
 constexpr int kSyevMax = 192;
 
-__global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __restrict__ H, int64_t ldh, int c,
-                                                            double* __restrict__ evals, double* __restrict__ C,
-                                                            double* __restrict__ work, int* info) {
+__global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __restrict__ H, int64_t ldh,
+                                                            int64_t hstride, int c, double* __restrict__ evals,
+                                                            int64_t estride, double* __restrict__ C, int64_t cstride,
+                                                            double* __restrict__ work, int64_t wstride, int* info,
+                                                            const int32_t* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
+  H += (int64_t)blockIdx.x * hstride;
+  evals += (int64_t)blockIdx.x * estride;
+  C += (int64_t)blockIdx.x * cstride;
+  work += (int64_t)blockIdx.x * wstride;
   __shared__ double sa[kSyevLds * (kSyevLds + 1)];
   __shared__ double sz[kSyevLds * (kSyevLds + 1)];
   __shared__ double d[kSyevMax], e[kSyevMax], e2[kSyevMax], tau[kSyevMax], v[kSyevMax], p[kSyevMax];
@@ -270,7 +276,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     C[(int64_t)i * c + j] = Z[i * la + j];
   }
   for (int j = tid; j < c; j += nt) evals[j] = lam[j];
-  if (tid == 0 && info) info[0] = maxrank;
+  if (tid == 0 && info) info[blockIdx.x] = maxrank;
 }
 
 // HL: Z = C(0:m, m:c)^T (r x m, r = c - m); Householder QR; Q explicit; G = [C(:,0:m), C(:,m:c) Q].
@@ -278,8 +284,12 @@ constexpr int kHlThreads = 512;
 constexpr int kHlMaxR = 128;
 constexpr int kHlMaxM = 64;
 
-__global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __restrict__ C, int c, int m,
-                                                              double* __restrict__ G) {
+__global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __restrict__ C, int64_t cstride, int c,
+                                                              int m, double* __restrict__ G, int64_t gstride,
+                                                              const int32_t* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
+  C += (int64_t)blockIdx.x * cstride;
+  G += (int64_t)blockIdx.x * gstride;
   __shared__ double z[kHlMaxR * (kHlMaxM + 1)];
   __shared__ double qm[kHlMaxR * (kHlMaxM + 1)];
   __shared__ double tau[kHlMaxM];
@@ -361,44 +371,20 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   }
 }
 
-// Algorithm 2 steps 2 and 4: solve Y U = X row by row (U upper triangular, c x c,
-// row-major), in place, by forward substitution over the columns.  One thread
-// owns one row; 64 rows per workgroup sit in LDS column-major (Ws[j*64 + t]),
-// so the lanes of a wave read consecutive words, and U is broadcast from LDS.
-template <typename TU>
-__global__ void __launch_bounds__(64) trsm_rows_kernel(double* W, int64_t ld, int64_t n, int c,
-                                                       const TU* __restrict__ U) {
-  extern __shared__ double smem[];
-  double* Us = smem;            // c x c
-  double* Ws = smem + c * c;    // c x 64
-  const int t = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  for (int e = t; e < c * c; e += 64) Us[e] = (double)U[e];
-  for (int e = t; e < 64 * c; e += 64) {
-    const int i = e / c, j = e % c;
-    Ws[j * 64 + i] = (r0 + i < n) ? W[(r0 + i) * ld + j] : 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j < c; ++j) {
-    double s = Ws[j * 64 + t];
-#pragma unroll 4
-    for (int i = 0; i < j; ++i) s -= Ws[i * 64 + t] * Us[i * c + j];
-    Ws[j * 64 + t] = s / Us[j * c + j];
-  }
-  __syncthreads();
-  for (int e = t; e < 64 * c; e += 64) {
-    const int i = e / c, j = e % c;
-    if (r0 + i < n) W[(r0 + i) * ld + j] = Ws[j * 64 + i];
-  }
-}
-
 // Algorithm 2 step 3: V^T V = L L^T (FP64).  Writes Lt = L^T (upper, row-major) for
 // the step-4 solve, and Rout = L^T working(Rl) (the R factor) when requested.
 // Flags a non-positive or non-finite pivot (W numerically rank deficient).
 template <typename T>
 __global__ void __launch_bounds__(256) chol_upper_kernel(const double* __restrict__ G, const T* __restrict__ Rl,
                                                          int c, double* __restrict__ Lt, double* __restrict__ Rout,
-                                                         int* flag) {
+                                                         int* flag, const int32_t* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
+  const int64_t off = (int64_t)blockIdx.x * c * c;
+  G += off;
+  Rl += off;
+  Lt += off;
+  if (Rout) Rout += off;
+  flag += blockIdx.x;
   __shared__ double L[64 * 64];
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int e = tid; e < c * c; e += nt) {
@@ -441,30 +427,25 @@ __global__ void __launch_bounds__(256) chol_upper_kernel(const double* __restric
 
 int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c + 16; }
 
-void launch_syev(const double* H, int64_t ldh, int c, double* evals, double* C, double* work, int* info,
-                 hipStream_t st) {
-  syev_kernel<<<1, kSyevThreads, 0, st>>>(H, ldh, c, evals, C, work, info);
+void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, double* evals, int64_t estride, double* C,
+                 int64_t cstride, double* work, int* info, const int32_t* active, int B, hipStream_t st) {
+  syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, evals, estride, C, cstride, work, syev_scratch(c),
+                                          info, active);
 }
 
-void launch_hl_build(const double* C, int c, int m, double* G, double* work, hipStream_t st) {
-  (void)work;
-  hl_build_kernel<<<1, kHlThreads, 0, st>>>(C, c, m, G);
+void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, int64_t gstride,
+                     const int32_t* active, int B, hipStream_t st) {
+  hl_build_kernel<<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
 }
-
-template <typename TU>
-void launch_trsm_rows(double* W, int64_t ld, int64_t n, int c, const TU* U, hipStream_t st) {
-  if (n <= 0) return;
-  const size_t lds = (size_t)(c * c + 64 * c) * sizeof(double);
-  trsm_rows_kernel<TU><<<(unsigned)((n + 63) / 64), 64, lds, st>>>(W, ld, n, c, U);
-}
-template void launch_trsm_rows<float>(double*, int64_t, int64_t, int, const float*, hipStream_t);
-template void launch_trsm_rows<double>(double*, int64_t, int64_t, int, const double*, hipStream_t);
 
 template <typename T>
-void launch_chol_upper(const double* G, const T* Rl, int c, double* Lt, double* Rout, int* flag, hipStream_t st) {
-  chol_upper_kernel<T><<<1, 256, 0, st>>>(G, Rl, c, Lt, Rout, flag);
+void launch_chol_upper(const double* G, const T* Rl, int c, double* Lt, double* Rout, int* flag,
+                       const int32_t* active, int B, hipStream_t st) {
+  chol_upper_kernel<T><<<B, 256, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
 }
-template void launch_chol_upper<float>(const double*, const float*, int, double*, double*, int*, hipStream_t);
-template void launch_chol_upper<double>(const double*, const double*, int, double*, double*, int*, hipStream_t);
+template void launch_chol_upper<float>(const double*, const float*, int, double*, double*, int*, const int32_t*, int,
+                                       hipStream_t);
+template void launch_chol_upper<double>(const double*, const double*, int, double*, double*, int*, const int32_t*,
+                                        int, hipStream_t);
 
 }  // namespace lobpcg

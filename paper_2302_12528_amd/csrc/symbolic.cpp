@@ -14,6 +14,7 @@ struct Builder {
   const int32_t* rowptr;
   const int32_t* colind;
   int leaf;
+  int64_t offset = 0;          // first node of the component being ordered
   std::vector<int32_t> perm;   // filled in emission order
   std::vector<int32_t> begin, nc, parent;
   int32_t next = 0;
@@ -43,7 +44,7 @@ struct Builder {
       nodes.reserve(vol);
       for (int i = lo[0]; i < hi[0]; ++i)
         for (int j = lo[1]; j < hi[1]; ++j)
-          for (int l = lo[2]; l < hi[2]; ++l) nodes.push_back((int32_t)(((int64_t)i * g[1] + j) * g[2] + l));
+          for (int l = lo[2]; l < hi[2]; ++l) nodes.push_back((int32_t)(offset + ((int64_t)i * g[1] + j) * g[2] + l));
       return {new_sn(nodes)};
     }
     int mid = lo[d] + (hi[d] - lo[d]) / 2;
@@ -56,7 +57,7 @@ struct Builder {
     std::vector<int32_t> sep;
     for (int i = ls[0]; i < hs[0]; ++i)
       for (int j = ls[1]; j < hs[1]; ++j)
-        for (int l = ls[2]; l < hs[2]; ++l) sep.push_back((int32_t)(((int64_t)i * g[1] + j) * g[2] + l));
+        for (int l = ls[2]; l < hs[2]; ++l) sep.push_back((int32_t)(offset + ((int64_t)i * g[1] + j) * g[2] + l));
     int s = new_sn(sep);
     for (int c : a) parent[c] = s;
     for (int c : b) parent[c] = s;
@@ -141,6 +142,15 @@ struct Builder {
 
 std::string analyze(int64_t n, const int32_t* rowptr, const int32_t* colind, const int32_t grid[3],
                     bool dense, int leaf_size, Symbolic& S) {
+  Component c;
+  c.off = 0;
+  c.n = n;
+  for (int d = 0; d < 3; ++d) c.grid[d] = grid ? grid[d] : 0;
+  return analyze_multi(n, rowptr, colind, std::vector<Component>{c}, dense, leaf_size, S);
+}
+
+std::string analyze_multi(int64_t n, const int32_t* rowptr, const int32_t* colind, const std::vector<Component>& comps,
+                          bool dense, int leaf_size, Symbolic& S) {
   if (n <= 0) return "n must be positive";
   if (leaf_size < 1) leaf_size = 64;
   Builder B;
@@ -150,22 +160,33 @@ std::string analyze(int64_t n, const int32_t* rowptr, const int32_t* colind, con
   B.leaf = leaf_size;
   B.perm.assign(n, -1);
   if (dense) {
+    if (comps.size() != 1) return "dense matrices are not batched";
     std::vector<int32_t> all(n);
     std::iota(all.begin(), all.end(), 0);
     B.new_sn(all);
   } else {
-    bool use_grid = grid && grid[0] > 0 && grid[1] > 0 && grid[2] > 0 &&
-                    (int64_t)grid[0] * grid[1] * grid[2] == n;
-    if (use_grid) {
-      int g[3] = {grid[0], grid[1], grid[2]};
-      B.box(g, {0, 0, 0}, {g[0], g[1], g[2]});
-    } else {
-      B.stamp.assign(n, 0);
-      B.lvl.assign(n, 0);
-      std::vector<int32_t> all(n);
-      std::iota(all.begin(), all.end(), 0);
-      B.graph(all);
+    int64_t expect = 0;
+    for (const Component& c : comps) {
+      if (c.off != expect || c.n <= 0) return "components must tile the index range in order";
+      expect += c.n;
+      const bool use_grid = c.grid[0] > 0 && c.grid[1] > 0 && c.grid[2] > 0 &&
+                            (int64_t)c.grid[0] * c.grid[1] * c.grid[2] == c.n;
+      B.offset = c.off;
+      if (use_grid) {
+        int g[3] = {c.grid[0], c.grid[1], c.grid[2]};
+        B.box(g, {0, 0, 0}, {g[0], g[1], g[2]});
+      } else {
+        if (B.stamp.empty()) {
+          B.stamp.assign(n, 0);
+          B.lvl.assign(n, 0);
+        }
+        std::vector<int32_t> nodes(c.n);
+        std::iota(nodes.begin(), nodes.end(), (int32_t)c.off);
+        B.graph(nodes);
+      }
+      if (B.next != c.off + c.n) return "component ordering leaked outside its index range";
     }
+    if (expect != n) return "components do not cover all nodes";
   }
   if (B.next != n) return "ordering did not cover all nodes";
   S = Symbolic();

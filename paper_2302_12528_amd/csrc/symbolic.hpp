@@ -49,6 +49,13 @@ struct Symbolic {
 std::string analyze(int64_t n, const int32_t* rowptr, const int32_t* colind, const int32_t grid[3],
                     bool dense, int leaf_size, Symbolic& out);
 
+// Several independent problems stored as one block-diagonal matrix: component c owns
+// the index range [off, off + n) and is ordered on its own (its own grid hint), so each
+// component's new indices stay in its range and the supernodal tree is a forest.
+struct Component { int64_t off; int64_t n; int32_t grid[3]; };
+std::string analyze_multi(int64_t n, const int32_t* rowptr, const int32_t* colind, const std::vector<Component>& comps,
+                          bool dense, int leaf_size, Symbolic& out);
+
 // Permuted CSR pattern: for new row i, entries sorted by new column; map[e'] = old entry index.
 void permute_pattern(const Symbolic& S, const int32_t* rowptr, const int32_t* colind,
                      std::vector<int32_t>& prow, std::vector<int32_t>& pcol, std::vector<int32_t>& map);

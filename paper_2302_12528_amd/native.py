@@ -53,6 +53,11 @@ SIGNATURES = {
     "lobpcg_update_values": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p]),
     "lobpcg_factor": (ct.c_int, [ct.c_void_p]),
     "lobpcg_solve": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.POINTER(Info)]),
+    "lobpcg_setup_batched": (ct.c_int, [ct.POINTER(Matrix), ct.c_int32, ct.c_int32, ct.c_int32, ct.c_double,
+                                        ct.c_int, ct.c_void_p, ct.POINTER(Options), ct.POINTER(ct.c_void_p)]),
+    "lobpcg_solve_batched": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                        ct.POINTER(Info)]),
+    "lobpcg_batch_count": (ct.c_int32, [ct.c_void_p]),
     "lobpcg_backward": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "lobpcg_destroy": (ct.c_int, [ct.c_void_p]),
     "lobpcg_status_string": (ct.c_char_p, [ct.c_int]),

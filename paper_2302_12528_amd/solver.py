@@ -172,6 +172,78 @@ class Solver:
         return W
 
 
+class BatchedSolver:
+    """k smallest eigenpairs of each of several SPD matrices (one context, one factorization of their
+    block-diagonal union, per-problem convergence)."""
+
+    def __init__(self, mats, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
+                 grids=None, leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
+                 eig_tol: float = 0.0):
+        self.lib = nv.load()
+        _torch()
+        count = len(mats)
+        if count < 1:
+            raise ValueError("need at least one matrix")
+        grids = grids if grids is not None else [(0, 0, 0)] * count
+        arr = (nv.Matrix * count)()
+        keep = []
+        for b, A in enumerate(mats):
+            M, kp = make_matrix(A, grids[b])
+            arr[b] = M
+            keep.append(kp)
+        opt = nv.Options()
+        opt.leaf_size = leaf_size
+        opt.stop_rule = _STOP[stop]
+        opt.qr_lower = 1 if qr_lower else 0
+        opt.eig_tol = eig_tol
+        ctx = ct.c_void_p()
+        self.ctx = None
+        st = self.lib.lobpcg_setup_batched(arr, count, k, m, tol, _PREC[factor_precision], _stream(),
+                                           ct.byref(opt), ct.byref(ctx))
+        del keep
+        nv.check(st)
+        self.ctx = ctx
+        self.sizes = [int(arr[b].n) for b in range(count)]
+        self.count, self.k, self.m = count, k, m
+
+    def close(self):
+        if self.ctx is not None:
+            self.lib.lobpcg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, X0s=None, maxit: int = 1000, allow_not_converged: bool = False):
+        """Returns (list of evals, list of evecs, list of info dicts, overall status)."""
+        torch = _torch()
+        B = self.count
+        x0 = [(_dev_f64(X0s[b], (self.sizes[b], self.m)) if X0s is not None and X0s[b] is not None else None)
+              for b in range(B)]
+        evals = [torch.empty(self.k, dtype=torch.float64, device="cuda") for _ in range(B)]
+        evecs = [torch.empty((self.sizes[b], self.k), dtype=torch.float64, device="cuda") for b in range(B)]
+        P = ct.c_void_p * B
+        px0 = P(*[(t.data_ptr() if t is not None else None) for t in x0])
+        pev = P(*[t.data_ptr() for t in evals])
+        pec = P(*[t.data_ptr() for t in evecs])
+        infos = (nv.Info * B)()
+        res = [np.zeros(self.k, dtype=np.float64) for _ in range(B)]
+        for b in range(B):
+            infos[b].resid = res[b].ctypes.data
+        allow = (nv.LOBPCG_OK, nv.LOBPCG_NOT_CONVERGED) if allow_not_converged else (nv.LOBPCG_OK,)
+        st = self.lib.lobpcg_solve_batched(self.ctx, px0, maxit, pev, pec, infos)
+        nv.check(st, allow)
+        outs = []
+        for b in range(B):
+            o = {f: getattr(infos[b], f) for f, _ in nv.Info._fields_ if f != "resid"}
+            o["resid"] = res[b].copy()
+            outs.append(o)
+        return evals, evecs, outs, st
+
+
 def mixed_qr(W, lower: bool = True):
     """Algorithm 2 on a device block W (n x c); returns (Q, R)."""
     torch = _torch()

@@ -1,0 +1,104 @@
+"""Batched solves: many independent Schrodinger operators of uneven size in one context.
+
+Each problem is checked against the oracle's dense eigensolver (its k smallest
+eigenpairs), its normalised residuals against tol, and against the same problem
+solved alone (batch invariance of the per-problem arithmetic, up to the order
+of the row reductions).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense as odense
+from helpers import residuals, subspace_cos
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _small_batch(count, k=8, m=16):
+    # the sizes of the workload's recipe shrunk to sides 22..32 so that the dense oracle is quick
+    return synth.cfg4(count, k=k, m=m, side_override=lambda s: 16 + s // 8)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_vs_dense_oracle(torch_cuda, prec):
+    import paper_2302_12528_amd as pk
+    probs = _small_batch(12)
+    print(f"batched count={len(probs)} sizes={[p.A.shape[0] for p in probs]} prec={prec}", flush=True)
+    bs = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, factor_precision=prec,
+                          grids=[p.grid for p in probs])
+    evals, evecs, infos, st = bs.solve([p.X0 for p in probs])
+    for b, p in enumerate(probs):
+        lam_ref, V_ref = odense.smallest_eigenpairs(p.A.toarray(), p.k)
+        lam = evals[b].cpu().numpy()
+        X = evecs[b].cpu().numpy()
+        rel = np.max(np.abs(lam - lam_ref) / np.abs(lam_ref))
+        res = residuals(p.A, X, lam, infos[b]["norm_a"])
+        print(f"  problem {b} n={p.A.shape[0]} iters={infos[b]['iters']} eig rel err {rel:.2e} "
+              f"max resid {res.max():.2e}", flush=True)
+        assert rel <= 1e-10
+        # eq. (stop): ||r|| <= tol (||A|| + |theta|) ||x||
+        assert np.all(res <= 1e-10 * (1 + np.abs(lam) / infos[b]["norm_a"]) * 1.001)
+        assert np.allclose(X.T @ X, np.eye(p.k), atol=1e-12)
+        assert subspace_cos(X, V_ref) >= 1 - 1e-8
+    bs.close()
+
+
+def test_batch_invariance(torch_cuda):
+    import paper_2302_12528_amd as pk
+    probs = _small_batch(6)
+    bs = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, grids=[p.grid for p in probs])
+    evals, evecs, infos, _ = bs.solve([p.X0 for p in probs])
+    bs.close()
+    for b in (0, 3, 5):
+        p = probs[b]
+        s = pk.Solver(p.A, 8, 16, 1e-10, grid=p.grid)
+        lam1, X1, info1 = s.solve(p.X0)
+        s.close()
+        d = np.max(np.abs(lam1.cpu().numpy() - evals[b].cpu().numpy()) / np.abs(lam1.cpu().numpy()))
+        print(f"problem {b}: alone {info1['iters']} iters, batched {infos[b]['iters']} iters, "
+              f"eig rel diff {d:.2e}", flush=True)
+        assert d <= 1e-11
+        assert abs(info1["iters"] - infos[b]["iters"]) <= 1
+
+
+def test_batched_uneven_and_graph_ordering(torch_cuda):
+    """Different sizes, one problem without a grid hint (graph nested dissection), default start blocks."""
+    import paper_2302_12528_amd as pk
+    sides = [20, 37, 25]
+    r = np.random.default_rng(7)
+    mats, grids = [], []
+    for i, s in enumerate(sides):
+        mats.append(synth.schrodinger((s, s), r.uniform(0, 1, (8, 2)), r.uniform(0.05, 0.2, 8),
+                                      r.uniform(0, 50, 8)))
+        grids.append((s, s, 1) if i != 1 else (0, 0, 0))
+    bs = pk.BatchedSolver(mats, 4, 8, 1e-10, grids=grids)
+    evals, evecs, infos, st = bs.solve(None)
+    for b, A in enumerate(mats):
+        lam_ref, _ = odense.smallest_eigenpairs(A.toarray(), 4)
+        rel = np.max(np.abs(evals[b].cpu().numpy() - lam_ref) / lam_ref)
+        assert rel <= 1e-10, (b, rel)
+    bs.close()
+
+
+def test_batched_not_converged_outputs(torch_cuda):
+    import paper_2302_12528_amd as pk
+    from paper_2302_12528_amd import native as nv
+    probs = _small_batch(4)
+    bs = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, grids=[p.grid for p in probs])
+    evals, evecs, infos, st = bs.solve([p.X0 for p in probs], maxit=2, allow_not_converged=True)
+    assert st == nv.LOBPCG_NOT_CONVERGED
+    for b in range(4):
+        assert infos[b]["iters"] == 2
+        assert np.all(np.isfinite(evals[b].cpu().numpy()))
+        X = evecs[b].cpu().numpy()
+        assert np.allclose(X.T @ X, np.eye(8), atol=1e-10)
+    bs.close()
