@@ -94,6 +94,12 @@ typedef struct {
   double nnz_factor;         /* stored entries of the supernodal factor */
   double factor_flops;       /* flops of the numeric factorization */
   double* resid;             /* host array of k final normalised residuals, nullable */
+  /* GPU time measured with HIP events on the context's stream during this solve
+   * (lobpcg_solve only; zero for batched solves and backward): */
+  double t_precond_gpu;      /* s, sum over the preconditioner applications (lines 9-10) */
+  double t_spmm_gpu;         /* s, sum over the products A W (line 13) */
+  int32_t n_precond;         /* number of preconditioner applications timed */
+  int32_t n_spmm;            /* number of products A W timed */
 } lobpcg_info;
 
 /* Set up a solver for the k smallest eigenpairs with block size m (Algorithm 3
@@ -127,8 +133,9 @@ lobpcg_status lobpcg_solve(lobpcg_ctx ctx, const double* X0, int32_t maxit,
                            double* evals, double* evecs, lobpcg_info* info);
 
 /* Batched setup: count independent problems A[0..count-1] (CSR, each with its
- * own n_b and grid hint) sharing k, m, tol and the factor precision
- * (section 5.2 solves hundreds of such eigenproblems).  They are stored as one
+ * own n_b and grid hint) sharing k, m, tol and the factor precision; each is
+ * solved by Algorithm 3 exactly as lobpcg_solve would (batching is an addition
+ * to the method, not part of it).  They are stored as one
  * block-diagonal matrix: one ordering (each problem's rows stay contiguous),
  * one factorization and one product with A per iteration over all of them;
  * the dense block steps run per problem.  ||A_b||_2 is estimated per problem.

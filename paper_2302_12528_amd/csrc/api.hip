@@ -157,7 +157,7 @@ struct lobpcg_ctx_s {
   // factor (T = float or double)
   void *panel = nullptr, *upd = nullptr, *dinv = nullptr, *lcopy = nullptr;
   int* d_flag = nullptr;      // factor breakdown
-  int* d_qflag = nullptr;     // B: Algorithm 2 step-3 breakdown per instance
+  int* d_qflag = nullptr;     // 2B: Algorithm 2 step-3 breakdown per instance, FP32 try | FP64 retry
   int* d_info = nullptr;      // B: eigensolver diagnostics
   int32_t* d_active = nullptr;
   int32_t* d_active2 = nullptr;
@@ -181,6 +181,8 @@ struct lobpcg_ctx_s {
   double* bw_small = nullptr;
   double* bw_part = nullptr;
   int bw_iters = 0;
+  // events around the preconditioner and A W of one iteration (timed solves)
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
   template <typename X>
   lobpcg_status alloc(X*& p, int64_t count) {
@@ -200,6 +202,8 @@ struct lobpcg_ctx_s {
     return s;
   }
   ~lobpcg_ctx_s() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -374,42 +378,24 @@ void mixed_qr_seg(hipStream_t st, const SegDev& S, const TsqrPlanDev& P, double*
   launch_strsm_rows<double>(S, W, ld, cc, Lt, (int64_t)cc * cc, st);      // step 4: Q = V L^{-T}
 }
 
-// Orthonormalise each active instance's W; an instance whose step-3 Cholesky breaks down is redone
-// with step 1 in FP64 (its W then holds V, a basis of the same span).  Instances that still break
-// down are reported through `failed`.
-lobpcg_status ortho(lobpcg_ctx c, double* W, int64_t ld, int cc, std::vector<int>& failed) {
+// Orthonormalise each active instance's W with Algorithm 2, without a host round trip: with
+// step 1 in FP32, an instance whose step-3 Cholesky breaks down (flag qflag[b]) is redone with
+// step 1 in FP64 by kernels that take qflag as their active mask (its W then holds V, a basis of
+// the same span); a breakdown of that retry sets qflag2[b].  The host reads both flags at its
+// next synchronisation.
+lobpcg_status ortho(lobpcg_ctx c, double* W, int64_t ld, int cc) {
   lobpcg_ctx_s& C = *c;
-  failed.clear();
-  std::vector<int32_t> flags(C.B);
-  SegDev S = C.SG;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    const bool lower = (attempt == 0) && C.opt.qr_lower;
-    launch_fill_int(C.d_qflag, 0, C.B, C.st);
-    if (lower)
-      mixed_qr_seg<float>(C.st, S, C.TP32, W, ld, cc, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, C.d_qflag, nullptr);
-    else
-      mixed_qr_seg<double>(C.st, S, C.TP64, W, ld, cc, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, C.d_qflag, nullptr);
-    ST_TRY(check_launch("mixed QR"));
-    HIP_TRY(hipMemcpyAsync(flags.data(), C.d_qflag, C.B * sizeof(int32_t), hipMemcpyDeviceToHost, C.st));
-    HIP_TRY(hipStreamSynchronize(C.st));
-    std::vector<int32_t> redo(C.B, 0);
-    int nredo = 0;
-    for (int b = 0; b < C.B; ++b)
-      if (C.active[b] && flags[b]) {
-        redo[b] = 1;
-        ++nredo;
-      }
-    if (nredo == 0) break;
-    if (!lower) {
-      for (int b = 0; b < C.B; ++b)
-        if (redo[b]) failed.push_back(b);
-      break;
-    }
-    C.fallbacks += nredo;
-    HIP_TRY(hipMemcpyAsync(C.d_active2, redo.data(), C.B * sizeof(int32_t), hipMemcpyHostToDevice, C.st));
-    S.active = C.d_active2;
+  launch_fill_int(C.d_qflag, 0, 2 * C.B, C.st);
+  int* qflag2 = C.d_qflag + C.B;
+  if (C.opt.qr_lower) {
+    mixed_qr_seg<float>(C.st, C.SG, C.TP32, W, ld, cc, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, C.d_qflag, nullptr);
+    SegDev R = C.SG;
+    R.active = C.d_qflag;
+    mixed_qr_seg<double>(C.st, R, C.TP64, W, ld, cc, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, qflag2, nullptr);
+  } else {
+    mixed_qr_seg<double>(C.st, C.SG, C.TP64, W, ld, cc, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, qflag2, nullptr);
   }
-  return LOBPCG_OK;
+  return check_launch("mixed QR");
 }
 
 lobpcg_status set_active(lobpcg_ctx c) {
@@ -616,7 +602,7 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   SETUP_TRY(C.alloc_bytes(C.dinv, S.dinv_total * tsz));
   SETUP_TRY(C.alloc_bytes(C.lcopy, S.lcopy_max * tsz));
   SETUP_TRY(C.alloc(C.d_flag, 4));
-  SETUP_TRY(C.alloc(C.d_qflag, count));
+  SETUP_TRY(C.alloc(C.d_qflag, 2 * count));
   SETUP_TRY(C.alloc(C.d_info, count));
   // ---- iteration buffers ----
   const int m3 = 3 * m;
@@ -644,6 +630,8 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   SETUP_TRY(C.alloc_bytes(C.Rl, (int64_t)count * m * m * 8));
   SETUP_TRY(C.alloc(C.Gv, (int64_t)count * m * m));
   SETUP_TRY(C.alloc(C.Lt, (int64_t)count * m * m));
+  for (hipEvent_t& e : C.ev)
+    if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(LOBPCG_ERR_HIP, "hipEventCreate failed"));
   if (check_launch("setup") != LOBPCG_OK) return cleanup(LOBPCG_ERR_HIP);
   // ---- numeric factorization ----
   {
@@ -702,13 +690,7 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
       launch_gaussian_fill(X + off[b] * m3, nb, m, m3, 0x1234abcdull + (uint64_t)b, st);
   }
   ST_TRY(check_launch("start block"));
-  std::vector<int> failed;
-  ST_TRY(ortho(c, X, m3, m, failed));
-  for (int b : failed) {
-    C.active[b] = 0;
-    status[b] = LOBPCG_ERR_ORTHO_BREAKDOWN;
-  }
-  ST_TRY(set_active(c));
+  ST_TRY(ortho(c, X, m3, m));
   apply_a(c, X, m3, C.ASb[cur], m3, m);
   launch_sgram(C.SG, X, m3, C.ASb[cur], m3, m, m, C.H, (int64_t)m3 * m3, C.gpart, st);
   launch_syev(C.H, m, (int64_t)m3 * m3, m, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info, C.d_active, B,
@@ -720,6 +702,24 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
   ST_TRY(check_launch("initial Rayleigh-Ritz"));
   bool haveP = false;
   std::vector<double> hn((int64_t)B * 2 * m), th((int64_t)B * m3);
+  std::vector<int32_t> qf(2 * (size_t)B);
+  const bool timed = (B == 1);
+  bool pending = false;
+  double t_pc = 0, t_sp = 0;
+  int n_pc = 0, n_sp = 0;
+  auto harvest = [&]() {   // events of the previous iteration, complete after a stream sync
+    if (!pending) return;
+    float a = 0, b = 0;
+    if (hipEventElapsedTime(&a, C.ev[0], C.ev[1]) == hipSuccess) {
+      t_pc += 1e-3 * a;
+      ++n_pc;
+    }
+    if (hipEventElapsedTime(&b, C.ev[2], C.ev[3]) == hipSuccess) {
+      t_sp += 1e-3 * b;
+      ++n_sp;
+    }
+    pending = false;
+  };
   auto emit = [&](int b) -> lobpcg_status {   // write instance b's current Ritz pairs
     const int64_t nb = off[b + 1] - off[b];
     launch_gather_rows(C.Sb[cur], m3, C.d_iperm + off[b], 0, evecs_out[b], k, nb, k, st);
@@ -740,7 +740,19 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
     ST_TRY(check_launch("residual"));
     HIP_TRY(hipMemcpyAsync(hn.data(), C.norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(th.data(), C.evals, th.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(qf.data(), C.d_qflag, qf.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    harvest();
+    // the previous Algorithm 2 call: FP64 retries taken, and retries that broke down as well
+    for (int b = 0; b < B; ++b) {
+      if (!C.active[b]) continue;
+      C.fallbacks += qf[b];
+      if (qf[B + b]) {
+        status[b] = LOBPCG_ERR_ORTHO_BREAKDOWN;
+        C.active[b] = 0;
+        iters[b] = it - 1;
+      }
+    }
     // line 5: n_c = leading run of columns passing the test, per instance
     int nactive = 0;
     for (int b = 0; b < B; ++b) {
@@ -792,7 +804,9 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
     // lines 9-10: W = working(f_T(lower(R)))   (on the union; frozen instances are ignored below)
     const int wslot = haveP ? 2 * m : m;
     double* W = Sx + wslot;
+    if (timed) HIP_TRY(hipEventRecord(C.ev[0], st));
     precond(c, W, m3);
+    if (timed) HIP_TRY(hipEventRecord(C.ev[1], st));
     ST_TRY(check_launch("preconditioner"));
     // line 11: orthogonalize W against [X, P] twice
     for (int pass = 0; pass < 2; ++pass) {
@@ -801,17 +815,14 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
     }
     ST_TRY(check_launch("block Gram-Schmidt"));
     // line 12: W = Q of Algorithm 2
-    ST_TRY(ortho(c, W, m3, m, failed));
-    if (!failed.empty()) {
-      for (int b : failed) {
-        C.active[b] = 0;
-        status[b] = LOBPCG_ERR_ORTHO_BREAKDOWN;
-        ST_TRY(emit(b));
-      }
-      ST_TRY(set_active(c));
-    }
+    ST_TRY(ortho(c, W, m3, m));
     // line 13: A_p = S^T A S, with A W the only new product
+    if (timed) HIP_TRY(hipEventRecord(C.ev[2], st));
     apply_a(c, W, m3, ASx + wslot, m3, m);
+    if (timed) {
+      HIP_TRY(hipEventRecord(C.ev[3], st));
+      pending = true;
+    }
     const int cc = wslot + m;
     launch_sgram(C.SG, Sx, m3, ASx, m3, cc, cc, C.H, (int64_t)m3 * m3, C.gpart, st);
     // line 14: A_p C = C D
@@ -829,6 +840,7 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
   C.cur = cur;
   ST_TRY(check_launch("output"));
   HIP_TRY(hipStreamSynchronize(st));
+  harvest();
   const double t_done = now_s();
   lobpcg_status overall = LOBPCG_OK;
   for (int b = 0; b < B; ++b) {
@@ -847,6 +859,10 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
       I.factor_flops = C.S.flops;
       if (I.resid)
         for (int j = 0; j < k; ++j) I.resid[j] = resid[b][j];
+      I.t_precond_gpu = t_pc;
+      I.t_spmm_gpu = t_sp;
+      I.n_precond = n_pc;
+      I.n_spmm = n_sp;
     }
   }
   // the context keeps the final Ritz pairs of a single instance for lobpcg_backward

@@ -31,6 +31,49 @@ __global__ void __launch_bounds__(kThreads) spmm_csr_kernel(const int32_t* __res
   Y[row * ldy + col] = acc;
 }
 
+// Two columns per lane with 16-byte loads and stores (c, ldx, ldy even, X and Y 16-byte aligned):
+// a group of G lanes covers 2G columns of one row; the entries of a row are fetched four at a
+// time so that four row gathers of X are in flight per lane.  Each output is the same fma chain
+// in entry order as the one-column kernel.
+template <int G>
+__global__ void __launch_bounds__(kThreads) spmm_csr2_kernel(const int32_t* __restrict__ rowptr,
+                                                             const int32_t* __restrict__ colind,
+                                                             const double* __restrict__ val, int64_t n,
+                                                             const double* __restrict__ X, int64_t ldx,
+                                                             double* __restrict__ Y, int64_t ldy, int c) {
+  const int lane = threadIdx.x % G;
+  const int64_t row = (int64_t)blockIdx.x * (kThreads / G) + threadIdx.x / G;
+  const int col = (blockIdx.y * G + lane) * 2;
+  if (row >= n || col >= c) return;
+  const int32_t e0 = rowptr[row], e1 = rowptr[row + 1];
+  double ax = 0.0, ay = 0.0;
+  int32_t e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    int32_t j[4];
+    double v[4];
+    double2 x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      j[q] = colind[e + q];
+      v[q] = val[e + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = *reinterpret_cast<const double2*>(X + (int64_t)j[q] * ldx + col);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ax = fma(v[q], x[q].x, ax);
+      ay = fma(v[q], x[q].y, ay);
+    }
+  }
+  for (; e < e1; ++e) {
+    const double v = val[e];
+    const double2 x = *reinterpret_cast<const double2*>(X + (int64_t)colind[e] * ldx + col);
+    ax = fma(v, x.x, ax);
+    ay = fma(v, x.y, ay);
+  }
+  *reinterpret_cast<double2*>(Y + row * ldy + col) = make_double2(ax, ay);
+}
+
 // ----------------------------------------------------------------------------
 // 64 x 64 output tile of C = alpha * A B + beta * C with A (rows x K) and B (K x cols)
 // both row-major.  256 threads, 4 x 4 outputs each, K staged through LDS 16 at a time.
@@ -160,6 +203,25 @@ inline dim3 grid1(int64_t total) { return dim3((unsigned)((total + kThreads - 1)
 void launch_spmm_csr(const int32_t* rowptr, const int32_t* colind, const double* val, int64_t n, const double* X,
                      int64_t ldx, double* Y, int64_t ldy, int c, hipStream_t st) {
   if (n <= 0 || c <= 0) return;
+  const bool pairs = (c % 2 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) && ((uintptr_t)X % 16 == 0) &&
+                     ((uintptr_t)Y % 16 == 0);
+  if (pairs) {
+    const int half = c / 2;
+    if (half <= 4) {
+      spmm_csr2_kernel<4><<<dim3(ceil_div(n, kThreads / 4), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx,
+                                                                                 Y, ldy, c);
+    } else if (half <= 8) {
+      spmm_csr2_kernel<8><<<dim3(ceil_div(n, kThreads / 8), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx,
+                                                                                 Y, ldy, c);
+    } else if (half <= 16) {
+      spmm_csr2_kernel<16><<<dim3(ceil_div(n, kThreads / 16), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X,
+                                                                                   ldx, Y, ldy, c);
+    } else {
+      spmm_csr2_kernel<32><<<dim3(ceil_div(n, kThreads / 32), ceil_div(half, 32)), kThreads, 0, st>>>(
+          rowptr, colind, val, n, X, ldx, Y, ldy, c);
+    }
+    return;
+  }
   if (c <= 8) {
     dim3 g(ceil_div(n, kThreads / 8), 1);
     spmm_csr_kernel<8><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);

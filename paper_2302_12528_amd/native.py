@@ -43,7 +43,8 @@ class Info(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("n_conv", ct.c_int32), ("fallbacks", ct.c_int32), ("nlevels", ct.c_int32),
                 ("norm_a", ct.c_double), ("t_symbolic", ct.c_double), ("t_factor", ct.c_double),
                 ("t_solve", ct.c_double), ("nnz_factor", ct.c_double), ("factor_flops", ct.c_double),
-                ("resid", ct.c_void_p)]
+                ("resid", ct.c_void_p), ("t_precond_gpu", ct.c_double), ("t_spmm_gpu", ct.c_double),
+                ("n_precond", ct.c_int32), ("n_spmm", ct.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/lobpcg.h
