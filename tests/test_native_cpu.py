@@ -18,7 +18,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:lobpcg_status|const char\*)\s+(lobpcg_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:lobpcg_status|const char\*|int32_t)\s+(lobpcg_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol(lib):
@@ -71,6 +71,35 @@ def test_setup_rejects_bad_matrices(lib):
     assert st == nv.LOBPCG_ERR_INVALID_ARG and "symmetric" in nv.last_error()
     st, _ = _setup(synth.laplace2d(10), 2, 4, 1e-8, prec=7)
     assert st == nv.LOBPCG_ERR_INVALID_ARG
+
+
+def _setup_batched(mats, k, m, tol, prec=nv.LOBPCG_FP32):
+    lib = nv.load()
+    arr = (nv.Matrix * max(1, len(mats)))()
+    keep = []
+    for b, A in enumerate(mats):
+        M, kp = sv.make_matrix(A)
+        arr[b] = M
+        keep.append(kp)
+    ctx = ct.c_void_p()
+    st = lib.lobpcg_setup_batched(arr, len(mats), k, m, tol, prec, None, None, ct.byref(ctx))
+    return st, ctx
+
+
+def test_batched_setup_rejects_bad_arguments(lib):
+    L = synth.laplace2d(10)
+    st, ctx = _setup_batched([], 2, 4, 1e-8)
+    assert st == nv.LOBPCG_ERR_INVALID_ARG and not ctx.value and "at least one" in nv.last_error()
+    st, ctx = _setup_batched([L, np.eye(40) * 2.0], 2, 4, 1e-8)
+    assert st == nv.LOBPCG_ERR_INVALID_ARG and "not batched" in nv.last_error()
+    st, ctx = _setup_batched([L, synth.laplace2d(3)], 2, 4, 1e-8)   # n = 9 < 3m for the second
+    assert st == nv.LOBPCG_ERR_INVALID_ARG and "3m <= n" in nv.last_error()
+    bad = synth.laplace2d(6).copy()
+    bad.data[0] = np.inf
+    st, ctx = _setup_batched([L, bad], 2, 4, 1e-8)
+    assert st == nv.LOBPCG_ERR_INVALID_ARG and "non-finite" in nv.last_error()
+    assert lib.lobpcg_solve_batched(None, None, 10, None, None, None) == nv.LOBPCG_ERR_INVALID_ARG
+    assert lib.lobpcg_batch_count(None) == 0
 
 
 def test_solve_and_backward_reject_null_context(lib):
