@@ -72,6 +72,43 @@ def event_time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def batched_run(torch, pk, steps, count):
+    """Batched Schrodinger workload: `count` 2D operators (side U{48..128}), k=8, m=16, FP32 factors, one
+    context; a step = numeric factorization of the union + lobpcg_solve_batched to tol for all of them."""
+    import numpy as np
+    import synth
+    probs = synth.cfg4(count)
+    log(f"batched: setup {count} problems, n total {sum(p.n for p in probs)}")
+    t0 = time.perf_counter()
+    bs = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, factor_precision="fp32",
+                          grids=[p.grid for p in probs])
+    t_setup = time.perf_counter() - t0
+    X0s = [torch.from_numpy(np.ascontiguousarray(p.X0)).cuda() for p in probs]
+    from paper_2302_12528_amd import native as nv
+    bs.solve(X0s)   # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        nv.check(bs.lib.lobpcg_factor(bs.ctx))
+        evals, evecs, infos, st = bs.solve(X0s)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # parity: host FP64 residuals of every problem against the estimate the test used
+    worst = 0.0
+    for b, p in enumerate(probs):
+        lam = evals[b].cpu().numpy()
+        X = evecs[b].cpu().numpy()
+        r = np.linalg.norm(p.A @ X - X * lam, axis=0) / ((infos[b]["norm_a"] + np.abs(lam)) * np.linalg.norm(X, axis=0))
+        worst = max(worst, float(r.max()))
+    iters = [i["iters"] for i in infos]
+    bs.close()
+    return {"workload": f"schrodinger2d_batch{count}: {count} 2D -Laplacian+V operators, side U{{48..128}}, "
+                        f"k=8, m=16, tol=1e-10, FP32 factors; step = factorization + batched solve",
+            "time_to_tol_s": round(dt, 5), "problems_per_s": round(count / dt, 2), "t_setup_s": round(t_setup, 3),
+            "iters_min": int(min(iters)), "iters_max": int(max(iters)), "iters_mean": float(np.mean(iters)),
+            "max_stop_residual": worst, "n_total": int(sum(p.n for p in probs))}
+
+
 def cpu_baseline():
     """The oracle on a bounded sample: the same generator at 32^3, factor + solve to tol."""
     import synth
@@ -102,6 +139,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--batched", type=int, default=256, help="problems in the batched run (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how it would "
@@ -194,6 +232,8 @@ def main():
                  "launches": n_sp, "algorithmic_bytes": bytes_spmm},
         "parity": parity,
     }
+    if args.batched > 0:
+        out["batched"] = batched_run(torch, pk, 1, args.batched)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a 32^3 sample)")
         out["cpu_baseline"] = cpu_baseline()

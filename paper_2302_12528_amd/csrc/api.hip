@@ -598,6 +598,8 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   // ---- factor storage ----
   const size_t tsz = (C.prec == LOBPCG_FP32) ? 4 : 8;
   SETUP_TRY(C.alloc_bytes(C.panel, S.panel_total * tsz));
+  // the padding rows of every panel column stay zero (the factorization writes rows < nr only)
+  if (hipMemset(C.panel, 0, S.panel_total * tsz) != hipSuccess) return cleanup(fail(LOBPCG_ERR_HIP, "memset"));
   SETUP_TRY(C.alloc_bytes(C.upd, S.upd_total * tsz));
   SETUP_TRY(C.alloc_bytes(C.dinv, S.dinv_total * tsz));
   SETUP_TRY(C.alloc_bytes(C.lcopy, S.lcopy_max * tsz));

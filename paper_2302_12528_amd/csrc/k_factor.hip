@@ -15,6 +15,7 @@
 //   inverse   panel <- [I; L21] inv(L11) = [inv(L11); L21 inv(L11)], so that
 //             each solve is one product per supernode (see k_trisolve.hip).
 #include "common.hpp"
+#include "mfma.hpp"
 #include "symbolic.hpp"
 
 namespace lobpcg {
@@ -54,8 +55,8 @@ __device__ inline void tile_rows(const Sn& S, int I, int& r0, int& h) {
 template <typename T>
 __device__ inline T* front_ptr(T* panel, T* upd, const Sn& S, int r, int c, int64_t& ld) {
   if (c < S.nc) {
-    ld = S.nr;
-    return panel + S.panel + (int64_t)c * S.nr + r;
+    ld = panel_ld(S.nr);
+    return panel + S.panel + (int64_t)c * ld + r;
   }
   ld = S.nb;
   return upd + S.upd + (int64_t)(c - S.nc) * S.nb + (r - S.nc);
@@ -123,22 +124,6 @@ __device__ inline double rdl(double v, int l) {
   const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
-
-template <typename T> struct Mfma;
-// Output row of D held by (lane, register q) of a 16x16x4 MFMA (column is lane % 16);
-// the FP32 and FP64 forms interleave the rows differently (checked on gfx950).
-template <> struct Mfma<float> {
-  typedef float v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  static __device__ inline int drow(int lane, int q) { return 4 * (lane / 16) + q; }
-};
-template <> struct Mfma<double> {
-  typedef double v4 __attribute__((ext_vector_type(4)));
-  static __device__ inline v4 op(double a, double b, v4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ inline int drow(int lane, int q) { return 4 * q + lane / 16; }
-};
 
 // acc (transposed) for this wave's 32 x 32 quadrant of the 64 x 64 tile C = As^T Bs, i.e.
 // C[r][c] = sum_k As[k][r] Bs[k][c], with 16x16x4 MFMAs.  The MFMA computes D = C^T so that lane l's
@@ -327,7 +312,7 @@ __global__ void __launch_bounds__(256) invprep_kernel(FactorDev D, int64_t task_
   const int* tk = D.tasks + 4 * (task_off + item);
   const int s = tk[0], t = tk[1];
   const Sn S = sn_of(D, s);
-  T* col = panel + S.panel + (int64_t)t * S.nr;
+  T* col = panel + S.panel + (int64_t)t * panel_ld(S.nr);
   T* lc = lcopy + D.lcopy_off[s] + (int64_t)t * S.nc;
   for (int r = lane; r < S.nc; r += 64) {
     if (r >= t) lc[r] = col[r];

@@ -14,7 +14,11 @@
 // fixed order.  P is streamed through LDS with the next stage prefetched into
 // registers while the current one is consumed; each thread owns a 4 x CT
 // register tile.
+#include <cstdlib>
+
 #include "common.hpp"
+#include "mfma.hpp"
+#include "symbolic.hpp"
 
 namespace lobpcg {
 
@@ -86,7 +90,7 @@ __global__ void __launch_bounds__(threads_for<M>()) fwd_gemm_kernel(FactorDev D,
   const int* it = items + 5 * (item_off + blockIdx.x);
   const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
   const int begin = D.begin[s], nr = D.nr[s];
-  const int64_t poff = D.panel_off[s];
+  const int64_t poff = D.panel_off[s], ldp = panel_ld(nr);
   const int r0 = tile * TR;
   const int h = min(TR, nr - r0);
   const int cg = tid % NCG, rg = tid / NCG;
@@ -101,7 +105,7 @@ __global__ void __launch_bounds__(threads_for<M>()) fwd_gemm_kernel(FactorDev D,
     for (int q = 0; q < PL; ++q) {
       const int e = tid + NT * q;
       const int r = e % TR, kk = e / TR;
-      pr[q] = (r < h && kc + kk < k1) ? panel[poff + (int64_t)(kc + kk) * nr + r0 + r] : (T)0;
+      pr[q] = (r < h && kc + kk < k1) ? panel[poff + (int64_t)(kc + kk) * ldp + r0 + r] : (T)0;
     }
 #pragma unroll
     for (int q = 0; q < BL; ++q) {
@@ -152,6 +156,214 @@ __global__ void __launch_bounds__(threads_for<M>()) fwd_gemm_kernel(FactorDev D,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core forms of the two tile products, one wave per item.  16-byte vector loads of the
+// panel feed 16x16x4 MFMAs directly (each panel element is used once per item, so it is not
+// staged through LDS); the right-hand-side operand is reused from registers by the 4 row blocks.
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; };
+template <> struct Vec16<double> { typedef double2 type; };
+
+template <typename T, int N>
+__device__ inline void load16(const T* p, T (&v)[N]) {
+  static_assert(N * sizeof(T) == 16, "16-byte vector");
+  const typename Vec16<T>::type q = *reinterpret_cast<const typename Vec16<T>::type*>(p);
+  if constexpr (N == 4) {
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else {
+    v[0] = q.x; v[1] = q.y;
+  }
+}
+
+// Forward: out tile (64 rows x M) = P_s[r0:r0+64, k0:k1] * b_s[k0:k1, :].  Lane (i = l % 16, g = l / 16)
+// reads VW consecutive panel rows of column k = kc + g; element w of its p-th vector is row
+// 16 VW p + VW i + w, the A operand of row block q = VW p + w.  Output row rb of block q is tile
+// row 16 VW p + VW rb + w.
+template <typename T, int M>
+__global__ void __launch_bounds__(64) fwd_mfma_kernel(FactorDev D, const int32_t* __restrict__ items,
+                                                      int64_t item_off, const T* __restrict__ panel,
+                                                      const T* __restrict__ rhs, T* __restrict__ y,
+                                                      T* __restrict__ uvec, T* __restrict__ part) {
+  typedef Mfma<T> MF;
+  typedef typename MF::v4 V4;
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int NP = 4 / VW;
+  constexpr int NCB = (M + 15) / 16;
+  const int lane = threadIdx.x;
+  const int i = lane % 16, g = lane / 16;
+  const int* it = items + 5 * (item_off + blockIdx.x);
+  const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
+  const int begin = D.begin[s], nr = D.nr[s], nc = D.nc[s];
+  const int64_t ldp = panel_ld(nr);
+  const int r0 = tile * TR;
+  const int h = min(TR, nr - r0);
+  const T* pbase = panel + D.panel_off[s] + r0 + VW * i;
+  V4 acc[4][NCB];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int kc = k0; kc < k1; kc += 4) {
+    const int k = kc + g;
+    const bool kok = k < k1;
+    T a[NP][VW];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      if (kok && 16 * VW * p + VW * i < h) {
+        load16(pbase + 16 * VW * p + (int64_t)k * ldp, a[p]);
+      } else {
+#pragma unroll
+        for (int w = 0; w < VW; ++w) a[p][w] = 0;
+      }
+    }
+    T b[NCB];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      const int col = 16 * c + i;
+      b[c] = (kok && col < M) ? rhs[(int64_t)(begin + k) * M + col] : (T)0;
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int w = 0; w < VW; ++w)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) acc[VW * p + w][c] = MF::op(a[p][w], b[c], acc[VW * p + w][c]);
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int w = 0; w < VW; ++w)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = 16 * VW * p + VW * MF::drow(lane, v) + w;
+        if (rr >= h) continue;
+        const int row = r0 + rr;
+        if (slot >= 0) {
+#pragma unroll
+          for (int c = 0; c < NCB; ++c) {
+            const int col = 16 * c + i;
+            if (col < M) part[((int64_t)slot * TR + rr) * M + col] = acc[VW * p + w][c][v];
+          }
+        } else if (row < nc) {
+#pragma unroll
+          for (int c = 0; c < NCB; ++c) {
+            const int col = 16 * c + i;
+            if (col < M) y[(int64_t)(begin + row) * M + col] = acc[VW * p + w][c][v];
+          }
+        } else {
+          T pass[NCB];
+#pragma unroll
+          for (int c = 0; c < NCB; ++c) pass[c] = 0;
+          for (int q = D.child_ptr[s]; q < D.child_ptr[s + 1]; ++q) {
+            const int ch = D.child_list[q];
+            const int jr = D.invmap[D.inv_off[ch] + row];
+            if (jr < 0) continue;
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+              const int col = 16 * c + i;
+              if (col < M) pass[c] += uvec[(D.uvec_off[ch] + jr) * M + col];
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < NCB; ++c) {
+            const int col = 16 * c + i;
+            if (col < M) uvec[(D.uvec_off[s] + row - nc) * M + col] = pass[c] - acc[VW * p + w][c][v];
+          }
+        }
+      }
+}
+
+// Backward: out tile (64 own columns x M) = P_s[k0:k1, j0:j0+64]^T z[k0:k1, :], z = [y_s; -x_below].
+// Lane (i, g) reads VW consecutive k (k = kc + VW g + t) of panel column j0 + 16 jb + i; MFMA t
+// pairs them with z row kc + VW g + t, so the 4 VW values of k in a step are reduced in VW MFMAs.
+template <typename T, int M>
+__global__ void __launch_bounds__(64) bwd_mfma_kernel(FactorDev D, const int32_t* __restrict__ items,
+                                                      int64_t item_off, const T* __restrict__ panel,
+                                                      const T* __restrict__ y, T* __restrict__ x, double* W,
+                                                      int64_t ldw, int mw, T* __restrict__ part) {
+  typedef Mfma<T> MF;
+  typedef typename MF::v4 V4;
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int NCB = (M + 15) / 16;
+  const int lane = threadIdx.x;
+  const int i = lane % 16, g = lane / 16;
+  const int* it = items + 5 * (item_off + blockIdx.x);
+  const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
+  const int begin = D.begin[s], nc = D.nc[s], nr = D.nr[s];
+  const int64_t ldp = panel_ld(nr);
+  const int64_t roff = D.row_off[s];
+  const int j0 = tile * TR;
+  const int h = min(TR, nc - j0);
+  const T* pbase = panel + D.panel_off[s] + (int64_t)(j0 + i) * ldp + VW * g;
+  V4 acc[4][NCB];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
+#pragma unroll 2
+  for (int kc = k0; kc < k1; kc += 4 * VW) {
+    const int kk = kc + VW * g;
+    T a[4][VW];
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      if (kk < k1 && 16 * jb + i < h) {
+        load16(pbase + (int64_t)(16 * jb) * ldp + kc, a[jb]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < VW; ++t) a[jb][t] = 0;
+      }
+    }
+    T b[VW][NCB];
+#pragma unroll
+    for (int t = 0; t < VW; ++t) {
+      const int k = kk + t;
+      const T* src = nullptr;
+      T sign = 1;
+      if (k < k1) {
+        if (k < nc) {
+          src = y + (int64_t)(begin + k) * M;
+        } else {
+          src = x + (int64_t)D.rows[roff + k] * M;
+          sign = -1;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) {
+        const int col = 16 * c + i;
+        b[t][c] = (src && col < M) ? sign * src[col] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < VW; ++t)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) acc[jb][c] = MF::op(a[jb][t], b[t][c], acc[jb][c]);
+  }
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int jj = 16 * jb + MF::drow(lane, v);
+      if (jj >= h) continue;
+      const int64_t row = begin + j0 + jj;
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) {
+        const int col = 16 * c + i;
+        if (col >= M) continue;
+        const T val = acc[jb][c][v];
+        if (slot >= 0) {
+          part[((int64_t)slot * TR + jj) * M + col] = val;
+        } else {
+          x[row * M + col] = val;
+          if (W && col < mw) W[row * ldw + col] = (double)val;
+        }
+      }
+    }
+}
+
 template <typename T, int M>
 __global__ void __launch_bounds__(threads_for<M>()) fwd_fin_kernel(FactorDev D, const int32_t* __restrict__ fin,
                                                                    int64_t fin_off, const T* __restrict__ part,
@@ -194,7 +406,7 @@ __global__ void __launch_bounds__(threads_for<M>()) bwd_gemm_kernel(FactorDev D,
   const int* it = items + 5 * (item_off + blockIdx.x);
   const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
   const int begin = D.begin[s], nc = D.nc[s], nr = D.nr[s];
-  const int64_t poff = D.panel_off[s];
+  const int64_t poff = D.panel_off[s], ldp = panel_ld(nr);
   const int64_t roff = D.row_off[s];
   const int j0 = tile * TR;
   const int h = min(TR, nc - j0);
@@ -210,7 +422,7 @@ __global__ void __launch_bounds__(threads_for<M>()) bwd_gemm_kernel(FactorDev D,
     for (int q = 0; q < PL; ++q) {
       const int e = tid + NT * q;
       const int kk = e % KC, jj = e / KC;
-      pr[q] = (jj < h && kc + kk < k1) ? panel[poff + (int64_t)(j0 + jj) * nr + kc + kk] : (T)0;
+      pr[q] = (jj < h && kc + kk < k1) ? panel[poff + (int64_t)(j0 + jj) * ldp + kc + kk] : (T)0;
     }
 #pragma unroll
     for (int q = 0; q < BL; ++q) {
@@ -312,6 +524,15 @@ __global__ void cast_to_kernel(const double* __restrict__ src, int64_t lds, T* _
   dst[e] = (j < m) ? (T)src[i * lds + j] : (T)0;
 }
 
+// Development switch between the matrix-core and the vector-ALU tile products.
+inline bool use_mfma() {
+  static const bool on = [] {
+    const char* e = getenv("LOBPCG_TRISOLVE_VALU");
+    return !(e && e[0] == '1');
+  }();
+  return on;
+}
+
 template <typename T, int M>
 void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* panel, T* rhs, T* y, T* x, T* uvec,
                  T* fpart, T* bpart, double* W, int64_t ldw, int mw, bool forward, hipStream_t st) {
@@ -320,14 +541,24 @@ void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* pan
     const int64_t a0 = Sd.ownrow_level_off[level], a1 = Sd.ownrow_level_off[level + 1];
     if (a1 > a0) fwd_assemble_kernel<T><<<(unsigned)((a1 - a0 + 3) / 4), 256, 0, st>>>(D, a0, a1 - a0, rhs, uvec, M);
     const int64_t f0 = Sd.fwd_level_off[level], f1 = Sd.fwd_level_off[level + 1];
-    if (f1 > f0)
-      fwd_gemm_kernel<T, M><<<(unsigned)(f1 - f0), NT, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);
+    if (f1 > f0) {
+      if (use_mfma())
+        fwd_mfma_kernel<T, M><<<(unsigned)(f1 - f0), 64, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);
+      else
+        fwd_gemm_kernel<T, M><<<(unsigned)(f1 - f0), NT, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);
+    }
     const int64_t g0 = Sd.fwd_fin_level_off[level], g1 = Sd.fwd_fin_level_off[level + 1];
     if (g1 > g0) fwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), NT, 0, st>>>(D, Sd.fwd_fin, g0, fpart, y, uvec);
   } else {
     const int64_t b0 = Sd.bwd_level_off[level], b1 = Sd.bwd_level_off[level + 1];
-    if (b1 > b0)
-      bwd_gemm_kernel<T, M><<<(unsigned)(b1 - b0), NT, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W, ldw, mw, bpart);
+    if (b1 > b0) {
+      if (use_mfma())
+        bwd_mfma_kernel<T, M><<<(unsigned)(b1 - b0), 64, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W, ldw, mw,
+                                                                  bpart);
+      else
+        bwd_gemm_kernel<T, M><<<(unsigned)(b1 - b0), NT, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W, ldw, mw,
+                                                                  bpart);
+    }
     const int64_t g0 = Sd.bwd_fin_level_off[level], g1 = Sd.bwd_fin_level_off[level + 1];
     if (g1 > g0) bwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), NT, 0, st>>>(D, Sd.bwd_fin, g0, bpart, x, W, ldw, mw);
   }

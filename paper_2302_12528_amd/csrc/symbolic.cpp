@@ -307,7 +307,7 @@ std::string analyze_multi(int64_t n, const int32_t* rowptr, const int32_t* colin
   for (int s = 0; s < ns; ++s) {
     int64_t r = S.nr[s], c = S.nc[s], b = r - c;
     int64_t np = (c + kTile - 1) / kTile;
-    S.panel_off[s + 1] = S.panel_off[s] + r * c;
+    S.panel_off[s + 1] = S.panel_off[s] + panel_ld(r) * c;
     S.upd_off[s + 1] = S.upd_off[s] + b * b;
     S.uvec_off[s + 1] = S.uvec_off[s] + b;
     S.dinv_off[s + 1] = S.dinv_off[s] + np * kTile * kTile;
@@ -543,7 +543,7 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
       if (r[j] < S.begin[s] + nc || r[j] >= n) return "below row out of range";
       if (j > nc && r[j] <= r[j - 1]) return "below rows not increasing";
     }
-    if (S.panel_off[s + 1] - S.panel_off[s] != (int64_t)nr * nc) return "panel_off";
+    if (S.panel_off[s + 1] - S.panel_off[s] != panel_ld(nr) * nc) return "panel_off";
     if (S.upd_off[s + 1] - S.upd_off[s] != (int64_t)nb * nb) return "upd_off";
     if (S.uvec_off[s + 1] - S.uvec_off[s] != nb) return "uvec_off";
     if (S.dinv_off[s + 1] - S.dinv_off[s] != (int64_t)ntiles(nc) * kTile * kTile) return "dinv_off";

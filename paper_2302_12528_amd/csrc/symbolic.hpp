@@ -14,6 +14,9 @@
 namespace lobpcg {
 
 constexpr int kTile = 64;   // tile edge of the factor kernels
+// Leading dimension of a supernode panel with nr rows: nr rounded up to a multiple of 4, so that
+// every panel column starts 16-byte aligned (FP32) and 4-row groups can be read as one vector.
+constexpr int64_t panel_ld(int64_t nr) { return (nr + 3) & ~(int64_t)3; }
 
 struct Symbolic {
   int64_t n = 0;
@@ -32,7 +35,7 @@ struct Symbolic {
   std::vector<int64_t> inv_off;
   std::vector<int32_t> invmap;
   // storage plans
-  std::vector<int64_t> panel_off; int64_t panel_total = 0;   // nr*nc each (col-major, ld = nr)
+  std::vector<int64_t> panel_off; int64_t panel_total = 0;   // panel_ld(nr)*nc each (col-major)
   std::vector<int64_t> upd_off;   int64_t upd_total = 0;     // nb*nb each (col-major, ld = nb)
   std::vector<int64_t> uvec_off;  int64_t uvec_total = 0;    // nb rows each (trisolve update vectors)
   std::vector<int64_t> dinv_off;  int64_t dinv_total = 0;    // np*kTile*kTile each
