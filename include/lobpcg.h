@@ -72,12 +72,18 @@ typedef struct {
   int64_t ld;                /* dense leading dimension (>= n) */
 } lobpcg_matrix;
 
+/* LOBPCG_FLAG_GRAPH: run each steady-state iteration (Algorithm 3 lines 9-16) as one
+ * replay of a HIP graph captured on a private stream of the context (two graphs, one per
+ * buffer parity, captured on first use and kept until lobpcg_destroy).  Results are bitwise
+ * identical to the eager launches; the per-step GPU timings of lobpcg_info are then zero. */
+#define LOBPCG_FLAG_GRAPH 1
+
 /* Optional tuning of setup (pass NULL for defaults). */
 typedef struct {
   int32_t leaf_size;         /* nested-dissection leaf volume (default 64) */
   int32_t stop_rule;         /* lobpcg_stop_rule (default LOBPCG_STOP_PAPER) */
   int32_t qr_lower;          /* 1 = Algorithm 2 step 1 in FP32 (default), 0 = in FP64 */
-  int32_t reserved;
+  int32_t flags;             /* bit field of LOBPCG_FLAG_* (default 0) */
   double norm_a;             /* > 0: use this ||A||_2 instead of the section 5.1 estimate */
   double eig_tol;            /* > 0: also require ||r_j||^2 <= eig_tol |theta_j| (theta_m - theta_j) */
 } lobpcg_options;

@@ -183,6 +183,10 @@ struct lobpcg_ctx_s {
   int bw_iters = 0;
   // events around the preconditioner and A W of one iteration (timed solves)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // graph mode: private stream, ordering event, one executable graph per buffer parity
+  hipStream_t gst = nullptr;
+  hipEvent_t ev_order = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
 
   template <typename X>
   lobpcg_status alloc(X*& p, int64_t count) {
@@ -202,6 +206,10 @@ struct lobpcg_ctx_s {
     return s;
   }
   ~lobpcg_ctx_s() {
+    for (hipGraphExec_t g : gexec)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (ev_order) (void)hipEventDestroy(ev_order);
+    if (gst) (void)hipStreamDestroy(gst);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
@@ -432,6 +440,7 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
       return fail(LOBPCG_ERR_INVALID_ARG, "stop_rule");
     if (opt.norm_a < 0 || !std::isfinite(opt.norm_a)) return fail(LOBPCG_ERR_INVALID_ARG, "norm_a");
     if (opt.eig_tol < 0 || !std::isfinite(opt.eig_tol)) return fail(LOBPCG_ERR_INVALID_ARG, "eig_tol");
+    if (opt.flags & ~LOBPCG_FLAG_GRAPH) return fail(LOBPCG_ERR_INVALID_ARG, "unknown flags");
   }
   auto c = new lobpcg_ctx_s();
   lobpcg_ctx_s& C = *c;
@@ -634,6 +643,11 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   SETUP_TRY(C.alloc(C.Lt, (int64_t)count * m * m));
   for (hipEvent_t& e : C.ev)
     if (hipEventCreate(&e) != hipSuccess) return cleanup(fail(LOBPCG_ERR_HIP, "hipEventCreate failed"));
+  if (opt.flags & LOBPCG_FLAG_GRAPH) {
+    if (hipStreamCreateWithFlags(&C.gst, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&C.ev_order, hipEventDisableTiming) != hipSuccess)
+      return cleanup(fail(LOBPCG_ERR_HIP, "graph stream setup failed"));
+  }
   if (check_launch("setup") != LOBPCG_OK) return cleanup(LOBPCG_ERR_HIP);
   // ---- numeric factorization ----
   {
@@ -664,10 +678,84 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
 #undef SETUP_TRY
 }
 
+// Algorithm 3 lines 9-16 of one steady-state or first iteration on the context's current stream:
+// S = [X | P | W] in Sb[cur] (W at column wslot), AS likewise; the new X, P, AX, AP go to Sb[1 - cur].
+// With `timed`, events ev[0..3] bracket the preconditioner and the product A W.
+lobpcg_status iteration_body(lobpcg_ctx c, int cur, bool haveP, bool timed) {
+  lobpcg_ctx_s& C = *c;
+  hipStream_t st = C.st;
+  const int B = C.B, m = C.m, m3 = 3 * m;
+  double* Sx = C.Sb[cur];
+  double* ASx = C.ASb[cur];
+  // lines 9-10: W = working(f_T(lower(R)))   (on the union; frozen instances are ignored below)
+  const int wslot = haveP ? 2 * m : m;
+  double* W = Sx + wslot;
+  if (timed) HIP_TRY(hipEventRecord(C.ev[0], st));
+  precond(c, W, m3);
+  if (timed) HIP_TRY(hipEventRecord(C.ev[1], st));
+  ST_TRY(check_launch("preconditioner"));
+  // line 11: orthogonalize W against [X, P] twice
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_sgram(C.SG, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, st);
+    launch_supdate(C.SG, Sx, m3, C.Gc, m, (int64_t)2 * m * m, W, m3, wslot, m, -1.0, 1.0, st);
+  }
+  ST_TRY(check_launch("block Gram-Schmidt"));
+  // line 12: W = Q of Algorithm 2
+  ST_TRY(ortho(c, W, m3, m));
+  // line 13: A_p = S^T A S, with A W the only new product
+  if (timed) HIP_TRY(hipEventRecord(C.ev[2], st));
+  apply_a(c, W, m3, ASx + wslot, m3, m);
+  if (timed) HIP_TRY(hipEventRecord(C.ev[3], st));
+  const int cc = wslot + m;
+  launch_sgram(C.SG, Sx, m3, ASx, m3, cc, cc, C.H, (int64_t)m3 * m3, C.gpart, st);
+  // line 14: A_p C = C D
+  launch_syev(C.H, cc, (int64_t)m3 * m3, cc, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info,
+              C.d_active, B, st);
+  // lines 15-16: HL basis and the new X, P (and A X, A P by the same combination)
+  launch_hl_build(C.Cev, (int64_t)m3 * m3, cc, m, C.Gupd, (int64_t)m3 * 2 * m, C.d_active, B, st);
+  launch_supdate(C.SG, Sx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
+  launch_supdate(C.SG, ASx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.ASb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
+  return check_launch("Rayleigh-Ritz");
+}
+
+// Capture iteration_body(cur, haveP = true) as an executable graph on the context's stream.
+lobpcg_status capture_iteration(lobpcg_ctx c, int cur) {
+  hipGraph_t g = nullptr;
+  HIP_TRY(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+  const lobpcg_status s = iteration_body(c, cur, true, false);
+  const hipError_t e = hipStreamEndCapture(c->st, &g);
+  if (s != LOBPCG_OK) {
+    if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(LOBPCG_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&c->gexec[cur], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->gexec[cur] = nullptr;
+    return fail(LOBPCG_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  return LOBPCG_OK;
+}
+
+// Runs the solve on the context's private stream (graph mode), ordered after the caller's stream.
+struct StreamSwap {
+  lobpcg_ctx c;
+  hipStream_t saved;
+  ~StreamSwap() { c->st = saved; }
+};
+
 // Algorithm 3 lines 2-17 for every instance of the context.
 lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, double* const* evals_out,
                          double* const* evecs_out, lobpcg_info* infos) {
   lobpcg_ctx_s& C = *c;
+  const bool graph = (C.gst != nullptr);
+  StreamSwap swap{c, C.st};
+  if (graph) {
+    HIP_TRY(hipEventRecord(C.ev_order, C.st));
+    HIP_TRY(hipStreamWaitEvent(C.gst, C.ev_order, 0));
+    C.st = C.gst;
+  }
   hipStream_t st = C.st;
   const int B = C.B;
   const int m = C.m, k = C.k, m3 = 3 * m;
@@ -705,7 +793,7 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
   bool haveP = false;
   std::vector<double> hn((int64_t)B * 2 * m), th((int64_t)B * m3);
   std::vector<int32_t> qf(2 * (size_t)B);
-  const bool timed = (B == 1);
+  const bool timed = (B == 1) && !graph;
   bool pending = false;
   double t_pc = 0, t_sp = 0;
   int n_pc = 0, n_sp = 0;
@@ -803,38 +891,13 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
     }
     if (nactive == 0) break;
     ST_TRY(set_active(c));
-    // lines 9-10: W = working(f_T(lower(R)))   (on the union; frozen instances are ignored below)
-    const int wslot = haveP ? 2 * m : m;
-    double* W = Sx + wslot;
-    if (timed) HIP_TRY(hipEventRecord(C.ev[0], st));
-    precond(c, W, m3);
-    if (timed) HIP_TRY(hipEventRecord(C.ev[1], st));
-    ST_TRY(check_launch("preconditioner"));
-    // line 11: orthogonalize W against [X, P] twice
-    for (int pass = 0; pass < 2; ++pass) {
-      launch_sgram(C.SG, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, st);
-      launch_supdate(C.SG, Sx, m3, C.Gc, m, (int64_t)2 * m * m, W, m3, wslot, m, -1.0, 1.0, st);
+    if (graph && haveP) {
+      if (!C.gexec[cur]) ST_TRY(capture_iteration(c, cur));
+      HIP_TRY(hipGraphLaunch(C.gexec[cur], st));
+    } else {
+      ST_TRY(iteration_body(c, cur, haveP, timed));
+      pending = timed;
     }
-    ST_TRY(check_launch("block Gram-Schmidt"));
-    // line 12: W = Q of Algorithm 2
-    ST_TRY(ortho(c, W, m3, m));
-    // line 13: A_p = S^T A S, with A W the only new product
-    if (timed) HIP_TRY(hipEventRecord(C.ev[2], st));
-    apply_a(c, W, m3, ASx + wslot, m3, m);
-    if (timed) {
-      HIP_TRY(hipEventRecord(C.ev[3], st));
-      pending = true;
-    }
-    const int cc = wslot + m;
-    launch_sgram(C.SG, Sx, m3, ASx, m3, cc, cc, C.H, (int64_t)m3 * m3, C.gpart, st);
-    // line 14: A_p C = C D
-    launch_syev(C.H, cc, (int64_t)m3 * m3, cc, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info,
-                C.d_active, B, st);
-    // lines 15-16: HL basis and the new X, P (and A X, A P by the same combination)
-    launch_hl_build(C.Cev, (int64_t)m3 * m3, cc, m, C.Gupd, (int64_t)m3 * 2 * m, C.d_active, B, st);
-    launch_supdate(C.SG, Sx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
-    launch_supdate(C.SG, ASx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.ASb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
-    ST_TRY(check_launch("Rayleigh-Ritz"));
     cur = 1 - cur;
     haveP = true;
     // frozen instances keep their (already emitted) results; their rows of the new buffers are not used

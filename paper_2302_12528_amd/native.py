@@ -24,6 +24,7 @@ LOBPCG_ERR_STATE = 8
 
 LOBPCG_FP64 = 0
 LOBPCG_FP32 = 1
+LOBPCG_FLAG_GRAPH = 1
 LOBPCG_STOP_PAPER = 0
 LOBPCG_STOP_NORMA = 1
 
@@ -36,7 +37,7 @@ class Matrix(ct.Structure):
 
 class Options(ct.Structure):
     _fields_ = [("leaf_size", ct.c_int32), ("stop_rule", ct.c_int32), ("qr_lower", ct.c_int32),
-                ("reserved", ct.c_int32), ("norm_a", ct.c_double), ("eig_tol", ct.c_double)]
+                ("flags", ct.c_int32), ("norm_a", ct.c_double), ("eig_tol", ct.c_double)]
 
 
 class Info(ct.Structure):

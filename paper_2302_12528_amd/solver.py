@@ -86,7 +86,7 @@ class Solver:
 
     def __init__(self, A, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
                  grid=(0, 0, 0), leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
-                 norm_a: float = 0.0, eig_tol: float = 0.0):
+                 norm_a: float = 0.0, eig_tol: float = 0.0, graph: bool = False):
         self.lib = nv.load()
         _torch()
         M, keep = make_matrix(A, grid)
@@ -96,6 +96,7 @@ class Solver:
         opt.qr_lower = 1 if qr_lower else 0
         opt.norm_a = norm_a
         opt.eig_tol = eig_tol
+        opt.flags = nv.LOBPCG_FLAG_GRAPH if graph else 0
         ctx = ct.c_void_p()
         self.ctx = None
         st = self.lib.lobpcg_setup(ct.byref(M), k, m, tol, _PREC[factor_precision], _stream(), ct.byref(opt),
@@ -178,7 +179,7 @@ class BatchedSolver:
 
     def __init__(self, mats, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
                  grids=None, leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
-                 eig_tol: float = 0.0):
+                 eig_tol: float = 0.0, graph: bool = False):
         self.lib = nv.load()
         _torch()
         count = len(mats)
@@ -196,6 +197,7 @@ class BatchedSolver:
         opt.stop_rule = _STOP[stop]
         opt.qr_lower = 1 if qr_lower else 0
         opt.eig_tol = eig_tol
+        opt.flags = nv.LOBPCG_FLAG_GRAPH if graph else 0
         ctx = ct.c_void_p()
         self.ctx = None
         st = self.lib.lobpcg_setup_batched(arr, count, k, m, tol, _PREC[factor_precision], _stream(),
