@@ -77,6 +77,15 @@ typedef struct {
  * buffer parity, captured on first use and kept until lobpcg_destroy).  Results are bitwise
  * identical to the eager launches; the per-step GPU timings of lobpcg_info are then zero. */
 #define LOBPCG_FLAG_GRAPH 1
+/* LOBPCG_FLAG_AUTOTUNE: at setup, time the candidate launch shapes on this context's own
+ * buffers and keep the fastest: the split-K chunk of the triangular-solve plan (128, 256,
+ * 512 or 1024 reduction rows per tile item) and the rows per reduction chunk of the
+ * instance-segmented Gram and norm kernels (512 to 8192).  If the environment variable
+ * LOBPCG_TUNE_CACHE names a file, results are appended to it keyed by device architecture
+ * and problem structure, and later setups with the same key read them instead of timing.
+ * The choice changes the order of floating-point reductions, so results may differ in the
+ * last bits from an untuned context. */
+#define LOBPCG_FLAG_AUTOTUNE 2
 
 /* Optional tuning of setup (pass NULL for defaults). */
 typedef struct {
@@ -190,6 +199,10 @@ const char* lobpcg_last_error(void);
  *  largest front rows, largest supernode columns, update-matrix entries,
  *  panel entries}. */
 lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t* perm_host, double* stats);
+
+/* Launch shapes in use: out3 = {split-K chunk of the triangular solves, rows per reduction
+ * chunk, 0 = defaults / 1 = tuned at setup / 2 = read from the tuning cache}. */
+lobpcg_status lobpcg_get_tuning(lobpcg_ctx ctx, int32_t* out3);
 
 /* Host copy of the permutation: perm[new] = old (n entries). */
 lobpcg_status lobpcg_get_permutation(lobpcg_ctx ctx, int32_t* perm_host);

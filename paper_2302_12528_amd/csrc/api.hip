@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -56,13 +57,13 @@ struct SegHost {
   std::vector<int64_t> tile_r0, chunk_r0;
 };
 
-void build_segments(const std::vector<int64_t>& inst_off, SegHost& H) {
+// Default rows per reduction chunk: about 384 chunks over the union, within [256, 4096].
+int64_t default_chunk_rows(int64_t N) { return std::max<int64_t>(256, std::min<int64_t>(4096, N / 384)); }
+
+void build_segments(const std::vector<int64_t>& inst_off, int64_t rpc, SegHost& H) {
   H = SegHost();
   H.inst_off = inst_off;
   const int B = (int)inst_off.size() - 1;
-  const int64_t N = inst_off[B];
-  int64_t rpc = N / 384;
-  rpc = std::max<int64_t>(256, std::min<int64_t>(4096, rpc));
   H.inst_chunk_off.push_back(0);
   for (int b = 0; b < B; ++b) {
     const int64_t r0 = inst_off[b], nb = inst_off[b + 1] - r0;
@@ -187,6 +188,11 @@ struct lobpcg_ctx_s {
   hipStream_t gst = nullptr;
   hipEvent_t ev_order = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // tuning: split-K chunk of the triangular solves, rows per reduction chunk, how they were chosen
+  int kchunk = 256;
+  int64_t chunk_rows = 0;
+  int tuned = 0;   // 0 defaults, 1 measured at setup, 2 read from the cache file
+  int64_t gpart_bytes = 0, fpart_bytes = 0, bpart_bytes = 0;
 
   template <typename X>
   lobpcg_status alloc(X*& p, int64_t count) {
@@ -256,6 +262,20 @@ lobpcg_status upload_tsqr(lobpcg_ctx c, TsqrHost& H, TsqrPlanDev& D) {
   D.level_off = H.level_off.data();
   D.half = H.half;
   ST_TRY(upload_const(c, D.items, H.items));
+  return LOBPCG_OK;
+}
+
+lobpcg_status install_solve_plan(lobpcg_ctx c) {
+  lobpcg_ctx_s& C = *c;
+  ST_TRY(upload_const(c, C.SD.fwd_items, C.SP.fwd_items));
+  ST_TRY(upload_const(c, C.SD.fwd_fin, C.SP.fwd_fin));
+  ST_TRY(upload_const(c, C.SD.bwd_items, C.SP.bwd_items));
+  ST_TRY(upload_const(c, C.SD.bwd_fin, C.SP.bwd_fin));
+  C.SD.fwd_level_off = C.SP.fwd_level_off.data();
+  C.SD.fwd_fin_level_off = C.SP.fwd_fin_level_off.data();
+  C.SD.bwd_level_off = C.SP.bwd_level_off.data();
+  C.SD.bwd_fin_level_off = C.SP.bwd_fin_level_off.data();
+  C.SD.ownrow_level_off = C.FP.ownrow_level_off.data();
   return LOBPCG_OK;
 }
 
@@ -411,6 +431,8 @@ lobpcg_status set_active(lobpcg_ctx c) {
   return LOBPCG_OK;
 }
 
+lobpcg_status autotune(lobpcg_ctx c);
+
 lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, int32_t m, double tol,
                          lobpcg_precision factor_precision, void* hip_stream, const lobpcg_options* opts,
                          lobpcg_ctx* out) {
@@ -440,7 +462,7 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
       return fail(LOBPCG_ERR_INVALID_ARG, "stop_rule");
     if (opt.norm_a < 0 || !std::isfinite(opt.norm_a)) return fail(LOBPCG_ERR_INVALID_ARG, "norm_a");
     if (opt.eig_tol < 0 || !std::isfinite(opt.eig_tol)) return fail(LOBPCG_ERR_INVALID_ARG, "eig_tol");
-    if (opt.flags & ~LOBPCG_FLAG_GRAPH) return fail(LOBPCG_ERR_INVALID_ARG, "unknown flags");
+    if (opt.flags & ~(LOBPCG_FLAG_GRAPH | LOBPCG_FLAG_AUTOTUNE)) return fail(LOBPCG_ERR_INVALID_ARG, "unknown flags");
   }
   auto c = new lobpcg_ctx_s();
   lobpcg_ctx_s& C = *c;
@@ -527,7 +549,8 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
         delete c;
         return fail(LOBPCG_ERR_INVALID_ARG, "ordering mixed two instances");
       }
-  build_segments(inst_off, C.SH);
+  C.chunk_rows = default_chunk_rows(n);
+  build_segments(inst_off, C.chunk_rows, C.SH);
   build_tsqr(inst_off, m, tsqr_rows_per_block(m, 4), C.TQ32);
   build_tsqr(inst_off, m, tsqr_rows_per_block(m, 8), C.TQ64);
   C.t_symbolic = now_s() - t0;
@@ -562,15 +585,7 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   SETUP_TRY(upload(c, D.asm_items, C.FP.asm_items));
   SETUP_TRY(upload(c, D.tasks, C.FP.tasks));
   SETUP_TRY(upload(c, D.ownrow_items, C.FP.ownrow_items));
-  SETUP_TRY(upload_const(c, C.SD.fwd_items, C.SP.fwd_items));
-  SETUP_TRY(upload_const(c, C.SD.fwd_fin, C.SP.fwd_fin));
-  SETUP_TRY(upload_const(c, C.SD.bwd_items, C.SP.bwd_items));
-  SETUP_TRY(upload_const(c, C.SD.bwd_fin, C.SP.bwd_fin));
-  C.SD.fwd_level_off = C.SP.fwd_level_off.data();
-  C.SD.fwd_fin_level_off = C.SP.fwd_fin_level_off.data();
-  C.SD.bwd_level_off = C.SP.bwd_level_off.data();
-  C.SD.bwd_fin_level_off = C.SP.bwd_fin_level_off.data();
-  C.SD.ownrow_level_off = C.FP.ownrow_level_off.data();
+  SETUP_TRY(install_solve_plan(c));
   SETUP_TRY(upload(c, C.d_perm, S.perm));
   SETUP_TRY(upload(c, C.d_iperm, S.iperm));
   C.active.assign(count, 1);
@@ -625,11 +640,14 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   SETUP_TRY(C.alloc_bytes(C.ybuf, n * C.mp * tsz));
   SETUP_TRY(C.alloc_bytes(C.xbuf, n * C.mp * tsz));
   SETUP_TRY(C.alloc_bytes(C.uvec, std::max<int64_t>(1, S.uvec_total) * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.fpart, std::max<int64_t>(1, C.SP.fwd_slots) * 64 * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.bpart, std::max<int64_t>(1, C.SP.bwd_slots) * 64 * C.mp * tsz));
+  C.fpart_bytes = std::max<int64_t>(1, C.SP.fwd_slots) * 64 * C.mp * tsz;
+  C.bpart_bytes = std::max<int64_t>(1, C.SP.bwd_slots) * 64 * C.mp * tsz;
+  SETUP_TRY(C.alloc_bytes(C.fpart, C.fpart_bytes));
+  SETUP_TRY(C.alloc_bytes(C.bpart, C.bpart_bytes));
   if (hipMemset(C.rhs, 0, n * C.mp * tsz) != hipSuccess) return cleanup(fail(LOBPCG_ERR_HIP, "memset"));
   const int64_t nch = C.SG.nchunks;
-  SETUP_TRY(C.alloc(C.gpart, nch * std::max<int64_t>((int64_t)m3 * m3, 2 * m)));
+  C.gpart_bytes = nch * std::max<int64_t>((int64_t)m3 * m3, 2 * m) * 8;
+  SETUP_TRY(C.alloc(C.gpart, C.gpart_bytes / 8));
   SETUP_TRY(C.alloc(C.H, (int64_t)count * m3 * m3));
   SETUP_TRY(C.alloc(C.Cev, (int64_t)count * m3 * m3));
   SETUP_TRY(C.alloc(C.evals, (int64_t)count * m3));
@@ -653,6 +671,10 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   {
     lobpcg_status s = factor(c);
     if (s != LOBPCG_OK) return cleanup(s);
+    if (opt.flags & LOBPCG_FLAG_AUTOTUNE) {
+      s = autotune(c);
+      if (s != LOBPCG_OK) return cleanup(s);
+    }
   }
   // ---- ||A_b||_2 estimates (section 5.1): ||A Omega||_F / ||Omega||_F, Omega Gaussian n x m ----
   C.norm_a.assign(count, opt.norm_a);
@@ -676,6 +698,151 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   *out = c;
   return LOBPCG_OK;
 #undef SETUP_TRY
+}
+
+// ---- setup-time autotuning (LOBPCG_FLAG_AUTOTUNE) ----
+uint64_t fnv_mix(uint64_t h, uint64_t v) {
+  for (int i = 0; i < 8; ++i) {
+    h ^= (v >> (8 * i)) & 0xff;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Key of a tuning result: the device architecture and everything that shapes the launches.
+uint64_t tune_key(const lobpcg_ctx_s& C) {
+  uint64_t h = 1469598103934665603ull;
+  int dev = 0;
+  hipDeviceProp_t p{};
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+    for (const char* q = p.gcnArchName; *q; ++q) h = fnv_mix(h, (uint64_t)(unsigned char)*q);
+  for (int64_t v : {C.n, C.nnz, (int64_t)C.B, (int64_t)C.m, (int64_t)C.prec, (int64_t)C.S.nsuper,
+                    (int64_t)C.S.nlevels, C.S.panel_total, C.S.upd_total})
+    h = fnv_mix(h, (uint64_t)v);
+  return h;
+}
+
+// The cache is a text file named by the environment variable LOBPCG_TUNE_CACHE (unset = no cache),
+// one line per key: "<key, 16 hex digits> <kchunk> <rows per chunk>".
+bool tune_cache_lookup(uint64_t key, int& kchunk, int64_t& rpc) {
+  const char* path = getenv("LOBPCG_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  unsigned long long k = 0;
+  int kc = 0;
+  long long r = 0;
+  bool found = false;
+  while (fscanf(f, "%llx %d %lld", &k, &kc, &r) == 3)
+    if (k == key && kc >= 16 && kc % 16 == 0 && r >= 64) {   // the last entry for a key wins
+      kchunk = kc;
+      rpc = r;
+      found = true;
+    }
+  fclose(f);
+  return found;
+}
+
+void tune_cache_store(uint64_t key, int kchunk, int64_t rpc) {
+  const char* path = getenv("LOBPCG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%016llx %d %lld\n", (unsigned long long)key, kchunk, (long long)rpc);
+  fclose(f);
+}
+
+// Mean GPU time (ms) of fn() over reps launches on the context's stream, after one warm-up call.
+template <typename F>
+float time_launches(lobpcg_ctx c, F fn, int reps) {
+  fn();
+  if (hipEventRecord(c->ev[0], c->st) != hipSuccess) return 1e30f;
+  for (int r = 0; r < reps; ++r) fn();
+  if (hipEventRecord(c->ev[1], c->st) != hipSuccess || hipEventSynchronize(c->ev[1]) != hipSuccess) return 1e30f;
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) != hipSuccess) return 1e30f;
+  return ms / reps;
+}
+
+lobpcg_status ensure_bytes(lobpcg_ctx c, void*& buf, int64_t& have, int64_t need) {
+  if (need <= have) return LOBPCG_OK;
+  ST_TRY(c->alloc_bytes(buf, need));
+  have = need;
+  return LOBPCG_OK;
+}
+
+lobpcg_status apply_chunk_rows(lobpcg_ctx c, int64_t rpc) {
+  c->chunk_rows = rpc;
+  build_segments(c->SH.inst_off, rpc, c->SH);
+  ST_TRY(upload_segments(c));
+  const int m3 = 3 * c->m;
+  void* g = c->gpart;
+  ST_TRY(ensure_bytes(c, g, c->gpart_bytes, c->SG.nchunks * std::max<int64_t>((int64_t)m3 * m3, 2 * c->m) * 8));
+  c->gpart = static_cast<double*>(g);
+  return LOBPCG_OK;
+}
+
+lobpcg_status apply_kchunk(lobpcg_ctx c, int kchunk) {
+  c->kchunk = kchunk;
+  build_solve_plan(c->S, 64, kchunk, c->SP);
+  const std::string err = verify_solve_plan(c->S, c->SP);
+  if (!err.empty()) return fail(LOBPCG_ERR_INVALID_ARG, "solve plan failed verification: " + err);
+  ST_TRY(install_solve_plan(c));
+  const int64_t tsz = (c->prec == LOBPCG_FP32) ? 4 : 8;
+  ST_TRY(ensure_bytes(c, c->fpart, c->fpart_bytes, std::max<int64_t>(1, c->SP.fwd_slots) * 64 * c->mp * tsz));
+  ST_TRY(ensure_bytes(c, c->bpart, c->bpart_bytes, std::max<int64_t>(1, c->SP.bwd_slots) * 64 * c->mp * tsz));
+  return LOBPCG_OK;
+}
+
+// Pick the split-K chunk of the triangular-solve plan by timing the preconditioner, and the rows per
+// reduction chunk by timing the Rayleigh-Ritz Gram matrix and the residual, on the context's buffers.
+lobpcg_status autotune(lobpcg_ctx c) {
+  lobpcg_ctx_s& C = *c;
+  const uint64_t key = tune_key(C);
+  int kc = 0;
+  int64_t rpc = 0;
+  if (tune_cache_lookup(key, kc, rpc)) {
+    ST_TRY(apply_kchunk(c, kc));
+    ST_TRY(apply_chunk_rows(c, rpc));
+    C.tuned = 2;
+    return LOBPCG_OK;
+  }
+  const int m = C.m, m3 = 3 * m;
+  launch_gaussian_fill(C.Sb[1], C.n, m3, m3, 0x7a11eull, C.st);
+  launch_gaussian_fill(C.ASb[1], C.n, m3, m3, 0x7a11full, C.st);
+  float best = 1e30f;
+  int best_kc = C.kchunk;
+  for (int cand : {128, 256, 512, 1024}) {
+    ST_TRY(apply_kchunk(c, cand));
+    const float t = time_launches(c, [&] { precond(c, C.Sb[1], m3); }, 3);
+    ST_TRY(check_launch("autotune preconditioner"));
+    if (t < best) {
+      best = t;
+      best_kc = cand;
+    }
+  }
+  ST_TRY(apply_kchunk(c, best_kc));
+  best = 1e30f;
+  int64_t best_rpc = C.chunk_rows;
+  for (int64_t cand : {512, 1024, 2048, 4096, 8192}) {
+    ST_TRY(apply_chunk_rows(c, cand));
+    const float t = time_launches(
+        c,
+        [&] {
+          launch_sgram(C.SG, C.Sb[1], m3, C.ASb[1], m3, m3, m3, C.H, (int64_t)m3 * m3, C.gpart, C.st);
+          launch_scolnorms(C.SG, C.Sb[1], m3, m, C.norms, 2 * m, C.gpart, C.st);
+        },
+        3);
+    ST_TRY(check_launch("autotune reductions"));
+    if (t < best) {
+      best = t;
+      best_rpc = cand;
+    }
+  }
+  ST_TRY(apply_chunk_rows(c, best_rpc));
+  C.tuned = 1;
+  tune_cache_store(key, best_kc, best_rpc);
+  return LOBPCG_OK;
 }
 
 // Algorithm 3 lines 9-16 of one steady-state or first iteration on the context's current stream:
@@ -956,7 +1123,7 @@ struct TempSeg {
     return true;
   }
   bool init(int64_t n) {
-    build_segments(std::vector<int64_t>{0, n}, H);
+    build_segments(std::vector<int64_t>{0, n}, default_chunk_rows(n), H);
     std::vector<int32_t> one{1};
     S.B = 1;
     S.ntiles = (int64_t)H.tile_inst.size();
@@ -1216,6 +1383,14 @@ lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t
     stats[6] = (double)S.upd_total;
     stats[7] = (double)S.panel_total;
   }
+  return LOBPCG_OK;
+}
+
+lobpcg_status lobpcg_get_tuning(lobpcg_ctx c, int32_t* out3) {
+  if (!c || !out3) return fail(LOBPCG_ERR_INVALID_ARG, "NULL argument");
+  out3[0] = c->kchunk;
+  out3[1] = (int32_t)c->chunk_rows;
+  out3[2] = c->tuned;
   return LOBPCG_OK;
 }
 

@@ -521,6 +521,38 @@ void build_solve_plan(const Symbolic& S, int rpt, int kchunk, SolvePlan& P) {
 
 namespace lobpcg {
 
+std::string verify_solve_plan(const Symbolic& S, const SolvePlan& P) {
+  const int ns = S.nsuper;
+  // the solve kernels use 64-row tiles and step the reduction 16 rows at a time from k0
+  if (P.rows_per_tile != 64) return "solve plan tile rows";
+  auto check_items = [&](const std::vector<int32_t>& items, const std::vector<int32_t>& fin, int64_t slots,
+                         bool fwd) -> std::string {
+    for (size_t q = 0; q < items.size(); q += 5) {
+      const int s = items[q], t = items[q + 1], k0 = items[q + 2], k1 = items[q + 3], slot = items[q + 4];
+      if (s < 0 || s >= ns || t < 0) return "solve item supernode";
+      const int lim = fwd ? S.nr[s] : S.nc[s];
+      if (t * P.rows_per_tile >= lim) return "solve item tile";
+      const int kl = fwd ? S.nc[s] : S.nr[s];
+      if (k0 < 0 || k1 > kl || k0 >= k1 || k0 % 16 != 0) return "solve item K range";
+      if (!fwd && k0 < t * P.rows_per_tile) return "backward K range below the diagonal tile";
+      if (slot < -1 || slot >= slots) return "solve item slot";
+    }
+    for (size_t q = 0; q < fin.size(); q += 4) {
+      const int s = fin[q], t = fin[q + 1], s0 = fin[q + 2], nch = fin[q + 3];
+      if (s < 0 || s >= ns || t < 0 || s0 < 0 || nch < 2 || s0 + nch > slots) return "finalize item";
+      if (t * P.rows_per_tile >= (fwd ? S.nr[s] : S.nc[s])) return "finalize tile";
+    }
+    return "";
+  };
+  {
+    std::string e = check_items(P.fwd_items, P.fwd_fin, P.fwd_slots, true);
+    if (!e.empty()) return "forward " + e;
+    e = check_items(P.bwd_items, P.bwd_fin, P.bwd_slots, false);
+    if (!e.empty()) return "backward " + e;
+  }
+  return "";
+}
+
 std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, const std::vector<int32_t>& prow,
                    const std::vector<int32_t>& apos) {
   const int64_t n = S.n;
@@ -598,30 +630,9 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
     const int s = F.ownrow_items[q], r = F.ownrow_items[q + 1];
     if (s < 0 || s >= ns || r < 0 || r >= S.nc[s]) return "own-row item";
   }
-  auto check_items = [&](const std::vector<int32_t>& items, const std::vector<int32_t>& fin, int64_t slots,
-                         bool fwd) -> std::string {
-    for (size_t q = 0; q < items.size(); q += 5) {
-      const int s = items[q], t = items[q + 1], k0 = items[q + 2], k1 = items[q + 3], slot = items[q + 4];
-      if (s < 0 || s >= ns || t < 0) return "solve item supernode";
-      const int lim = fwd ? S.nr[s] : S.nc[s];
-      if (t * P.rows_per_tile >= lim) return "solve item tile";
-      const int kl = fwd ? S.nc[s] : S.nr[s];
-      if (k0 < 0 || k1 > kl || k0 >= k1) return "solve item K range";
-      if (!fwd && k0 < t * P.rows_per_tile) return "backward K range below the diagonal tile";
-      if (slot < -1 || slot >= slots) return "solve item slot";
-    }
-    for (size_t q = 0; q < fin.size(); q += 4) {
-      const int s = fin[q], t = fin[q + 1], s0 = fin[q + 2], nch = fin[q + 3];
-      if (s < 0 || s >= ns || t < 0 || s0 < 0 || nch < 2 || s0 + nch > slots) return "finalize item";
-      if (t * P.rows_per_tile >= (fwd ? S.nr[s] : S.nc[s])) return "finalize tile";
-    }
-    return "";
-  };
   {
-    std::string e = check_items(P.fwd_items, P.fwd_fin, P.fwd_slots, true);
-    if (!e.empty()) return "forward " + e;
-    e = check_items(P.bwd_items, P.bwd_fin, P.bwd_slots, false);
-    if (!e.empty()) return "backward " + e;
+    const std::string e = verify_solve_plan(S, P);
+    if (!e.empty()) return e;
   }
   if (!prow.empty()) {
     if ((int64_t)prow.size() != n + 1 || apos.size() != (size_t)prow[n]) return "assembly positions size";

@@ -99,6 +99,8 @@ void build_solve_plan(const Symbolic& S, int rows_per_tile, int kchunk, SolvePla
 // Check every index the GPU kernels dereference against the buffer it indexes
 // (rows, maps, offsets, task and item lists, assembly positions).  Returns an
 // empty string when all are in range, else the first violation.
+// The solve-plan part of verify().
+std::string verify_solve_plan(const Symbolic& S, const SolvePlan& P);
 std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, const std::vector<int32_t>& prow,
                    const std::vector<int32_t>& apos);
 

@@ -25,6 +25,7 @@ LOBPCG_ERR_STATE = 8
 LOBPCG_FP64 = 0
 LOBPCG_FP32 = 1
 LOBPCG_FLAG_GRAPH = 1
+LOBPCG_FLAG_AUTOTUNE = 2
 LOBPCG_STOP_PAPER = 0
 LOBPCG_STOP_NORMA = 1
 
@@ -66,6 +67,7 @@ SIGNATURES = {
     "lobpcg_last_error": (ct.c_char_p, []),
     "lobpcg_symbolic": (ct.c_int, [ct.POINTER(Matrix), ct.c_int32, ct.c_void_p, ct.c_void_p]),
     "lobpcg_get_permutation": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "lobpcg_get_tuning": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "lobpcg_apply_a": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32]),
     "lobpcg_apply_precond": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "lobpcg_mixed_qr": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_void_p,

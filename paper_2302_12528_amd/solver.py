@@ -86,7 +86,7 @@ class Solver:
 
     def __init__(self, A, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
                  grid=(0, 0, 0), leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
-                 norm_a: float = 0.0, eig_tol: float = 0.0, graph: bool = False):
+                 norm_a: float = 0.0, eig_tol: float = 0.0, graph: bool = False, autotune: bool = False):
         self.lib = nv.load()
         _torch()
         M, keep = make_matrix(A, grid)
@@ -96,7 +96,7 @@ class Solver:
         opt.qr_lower = 1 if qr_lower else 0
         opt.norm_a = norm_a
         opt.eig_tol = eig_tol
-        opt.flags = nv.LOBPCG_FLAG_GRAPH if graph else 0
+        opt.flags = (nv.LOBPCG_FLAG_GRAPH if graph else 0) | (nv.LOBPCG_FLAG_AUTOTUNE if autotune else 0)
         ctx = ct.c_void_p()
         self.ctx = None
         st = self.lib.lobpcg_setup(ct.byref(M), k, m, tol, _PREC[factor_precision], _stream(), ct.byref(opt),
@@ -111,6 +111,12 @@ class Solver:
         if self.ctx is not None:
             self.lib.lobpcg_destroy(self.ctx)
             self.ctx = None
+
+    def tuning(self) -> dict:
+        out = np.zeros(3, dtype=np.int32)
+        nv.check(self.lib.lobpcg_get_tuning(self.ctx, out.ctypes.data))
+        return {"kchunk": int(out[0]), "chunk_rows": int(out[1]),
+                "source": ("default", "measured", "cache")[int(out[2])]}
 
     def __del__(self):
         try:
@@ -179,7 +185,7 @@ class BatchedSolver:
 
     def __init__(self, mats, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
                  grids=None, leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
-                 eig_tol: float = 0.0, graph: bool = False):
+                 eig_tol: float = 0.0, graph: bool = False, autotune: bool = False):
         self.lib = nv.load()
         _torch()
         count = len(mats)
@@ -197,7 +203,7 @@ class BatchedSolver:
         opt.stop_rule = _STOP[stop]
         opt.qr_lower = 1 if qr_lower else 0
         opt.eig_tol = eig_tol
-        opt.flags = nv.LOBPCG_FLAG_GRAPH if graph else 0
+        opt.flags = (nv.LOBPCG_FLAG_GRAPH if graph else 0) | (nv.LOBPCG_FLAG_AUTOTUNE if autotune else 0)
         ctx = ct.c_void_p()
         self.ctx = None
         st = self.lib.lobpcg_setup_batched(arr, count, k, m, tol, _PREC[factor_precision], _stream(),
@@ -212,6 +218,12 @@ class BatchedSolver:
         if self.ctx is not None:
             self.lib.lobpcg_destroy(self.ctx)
             self.ctx = None
+
+    def tuning(self) -> dict:
+        out = np.zeros(3, dtype=np.int32)
+        nv.check(self.lib.lobpcg_get_tuning(self.ctx, out.ctypes.data))
+        return {"kchunk": int(out[0]), "chunk_rows": int(out[1]),
+                "source": ("default", "measured", "cache")[int(out[2])]}
 
     def __del__(self):
         try:

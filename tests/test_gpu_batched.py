@@ -102,3 +102,28 @@ def test_batched_not_converged_outputs(torch_cuda):
         X = evecs[b].cpu().numpy()
         assert np.allclose(X.T @ X, np.eye(8), atol=1e-10)
     bs.close()
+
+
+def test_autotune_and_cache(torch_cuda, tmp_path, monkeypatch):
+    """Tuned launch shapes keep the results correct; a second setup with the same key reads the cache."""
+    import paper_2302_12528_amd as pk
+    monkeypatch.setenv("LOBPCG_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    probs = _small_batch(5)
+    kw = dict(grids=[p.grid for p in probs], autotune=True)
+    bs = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, **kw)
+    t1 = bs.tuning()
+    print(f"tuned: {t1}", flush=True)
+    assert t1["source"] == "measured"
+    assert t1["kchunk"] in (128, 256, 512, 1024) and t1["chunk_rows"] in (512, 1024, 2048, 4096, 8192)
+    evals, evecs, infos, st = bs.solve([p.X0 for p in probs])
+    bs.close()
+    for b, p in enumerate(probs):
+        lam_ref, _ = odense.smallest_eigenpairs(p.A.toarray(), p.k)
+        assert np.max(np.abs(evals[b].cpu().numpy() - lam_ref) / lam_ref) <= 1e-10
+    bs2 = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, **kw)
+    t2 = bs2.tuning()
+    assert t2["source"] == "cache" and t2["kchunk"] == t1["kchunk"] and t2["chunk_rows"] == t1["chunk_rows"]
+    ev2, _, _, _ = bs2.solve([p.X0 for p in probs])
+    for b in range(len(probs)):
+        assert np.array_equal(ev2[b].cpu().numpy(), evals[b].cpu().numpy())
+    bs2.close()
