@@ -773,7 +773,8 @@ lobpcg_status ensure_bytes(lobpcg_ctx c, void*& buf, int64_t& have, int64_t need
 
 lobpcg_status apply_chunk_rows(lobpcg_ctx c, int64_t rpc) {
   c->chunk_rows = rpc;
-  build_segments(c->SH.inst_off, rpc, c->SH);
+  const std::vector<int64_t> off = c->SH.inst_off;   // build_segments resets SH
+  build_segments(off, rpc, c->SH);
   ST_TRY(upload_segments(c));
   const int m3 = 3 * c->m;
   void* g = c->gpart;
