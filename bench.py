@@ -140,6 +140,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched run (0 = skip)")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first copy a 256 MiB buffer once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how it would "
@@ -150,6 +152,13 @@ def main():
     import paper_2302_12528_amd as pk
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.calibration_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
     log(f"generating {args.workload}")
     p = workload(args.workload)
     X0 = torch.from_numpy(np.ascontiguousarray(p.X0)).cuda()

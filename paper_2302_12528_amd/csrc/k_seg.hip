@@ -261,66 +261,80 @@ __global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, double* W, int
 }
 
 // ---------------------------------------------------------------------------
-// TSQR block: Householder QR (R only) of a block of `rows` rows starting at `in`,
-// one wave per block, LDS row stride c + 1.
+// TSQR block: Householder QR (R only) of a block of at most 256 rows starting at `in`.
+// Thread t holds row t in registers (columns padded to CP); for each column j the sums
+// over rows (the norm below the diagonal and w_k = v^T A(:, k) for k > j) are wave
+// reductions combined across the 4 waves through LDS, one barrier each.
 // ---------------------------------------------------------------------------
-template <typename T, typename Tin>
-__global__ void __launch_bounds__(64) stsqr_kernel(SegDev S, const Tin* in, int64_t ldin, const int32_t* __restrict__ items,
-                                                   int c, int rb, T* out) {
-  extern __shared__ unsigned char smem_raw[];
-  T* z = reinterpret_cast<T*>(smem_raw);
-  __shared__ T wv[64];
+constexpr int kTsqrRows = 256;
+
+template <typename T>
+__device__ inline T wave_reduce(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename T, typename Tin, int CP>
+__global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* in, int64_t ldin,
+                                                          const int32_t* __restrict__ items, int c, T* out) {
+  __shared__ T red[2][4][CP + 1];   // [norm | w] partials per wave, double-buffered by column parity
   const int* it = items + 4 * blockIdx.x;   // {instance, first row, rows, output slot}
   const int b = it[0];
   if (!S.active[b]) return;
   const int64_t r0 = it[1];
   const int rows = it[2];
   const int slot = it[3];
-  const int lane = threadIdx.x;
-  const int ldz = c + 1;
-  for (int e = lane; e < rb * c; e += 64) {
-    const int i = e / c, j = e % c;
-    z[i * ldz + j] = (i < rows) ? (T)in[(r0 + i) * ldin + j] : (T)0;
-  }
-  __syncthreads();
-  const int kmax = (c < rb) ? c : rb;
+  const int t = threadIdx.x, lane = t % 64, w = t / 64;
+  T a[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) a[k] = (t < rows && k < c) ? (T)in[(r0 + t) * ldin + k] : (T)0;
+  const int kmax = (c < rows) ? c : rows;
   for (int j = 0; j < kmax; ++j) {
-    T s = 0;
-    for (int i = j + 1 + lane; i < rb; i += 64) s += z[i * ldz + j] * z[i * ldz + j];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    const T alpha = z[j * ldz + j];
-    T tj = 0, beta = alpha, scale = 0;
-    if (s > (T)0) {
-      const T xn = sqrt(alpha * alpha + s);
-      beta = (alpha >= (T)0) ? -xn : xn;
-      tj = (beta - alpha) / beta;
-      scale = (T)1 / (alpha - beta);
-    }
+    T (*rd)[CP + 1] = red[j & 1];
+    T aj = 0;
+#pragma unroll
+    for (int k = 0; k < CP; ++k)
+      if (k == j) aj = a[k];
+    // column j: sigma = sum of squares below the diagonal, alpha = diagonal entry
+    T sq = wave_reduce((t > j) ? aj * aj : (T)0);
+    if (lane == 0) rd[w][CP] = sq;
+    if (t == j) rd[0][j] = aj;   // slot j of wave 0 is free until the w sums below
     __syncthreads();
-    if (s > (T)0)
-      for (int i = j + 1 + lane; i < rb; i += 64) z[i * ldz + j] *= scale;
-    if (lane == 0) z[j * ldz + j] = beta;
-    __syncthreads();
-    for (int k = j + 1; k < c; ++k) {
-      T w = 0;
-      for (int i = j + lane; i < rb; i += 64) w += (i == j ? (T)1 : z[i * ldz + j]) * z[i * ldz + k];
-      for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
-      if (lane == 0) wv[k] = w;
-    }
-    __syncthreads();
-    const int wc = c - j - 1;
-    if (wc > 0)
-      for (int e = lane; e < (rb - j) * wc; e += 64) {
-        const int i = j + e / wc, k = j + 1 + e % wc;
-        const T vi = (i == j) ? (T)1 : z[i * ldz + j];
-        z[i * ldz + k] -= tj * vi * wv[k];
+    const T sigma = ((rd[0][CP] + rd[1][CP]) + rd[2][CP]) + rd[3][CP];
+    const T alpha = rd[0][j];
+    if (!(sigma > (T)0)) continue;   // nothing below the diagonal: H_j = I (sigma is uniform)
+    const T xn = sqrt(alpha * alpha + sigma);
+    const T beta = (alpha >= (T)0) ? -xn : xn;
+    const T tau = (beta - alpha) / beta;
+    const T scale = (T)1 / (alpha - beta);
+    const T v = (t > j) ? aj * scale : (t == j ? (T)1 : (T)0);
+    // (the w sums go to slots k > j of this column's buffer; the buffer of column j - 2, which
+    // held the same slots, was last read before the barrier of column j - 1)
+    // w_k = v^T A(:, k) for k > j
+#pragma unroll
+    for (int k = 0; k < CP; ++k) {
+      if (k > j && k < c) {
+        const T pk = wave_reduce(v * a[k]);
+        if (lane == 0) rd[w][k] = pk;
       }
+    }
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < CP; ++k) {
+      if (k > j && k < c) {
+        const T wk = ((rd[0][k] + rd[1][k]) + rd[2][k]) + rd[3][k];
+        a[k] -= tau * v * wk;
+      } else if (k == j) {
+        a[k] = (t == j) ? beta : (t > j ? (T)0 : a[k]);
+      }
+    }
   }
   T* R = out + (int64_t)slot * c * c;
-  for (int e = lane; e < c * c; e += 64) {
-    const int i = e / c, j = e % c;
-    R[e] = (j >= i && i < rb) ? z[i * ldz + j] : (T)0;
+  if (t < c) {
+#pragma unroll
+    for (int k = 0; k < CP; ++k)
+      if (k < c) R[(int64_t)t * c + k] = (k >= t && t < rows) ? a[k] : (T)0;
   }
 }
 
@@ -403,20 +417,32 @@ void launch_strsm_rows(const SegDev& S, double* W, int64_t ld, int c, const TU* 
 template void launch_strsm_rows<float>(const SegDev&, double*, int64_t, int, const float*, int64_t, hipStream_t);
 template void launch_strsm_rows<double>(const SegDev&, double*, int64_t, int, const double*, int64_t, hipStream_t);
 
+template <typename T, typename Tin, int CP>
+void stsqr_go(unsigned grid, const SegDev& S, const Tin* in, int64_t ld, const int32_t* items, int c, T* out,
+              hipStream_t st) {
+  stsqr_kernel<T, Tin, CP><<<grid, kTsqrRows, 0, st>>>(S, in, ld, items, c, out);
+}
+
+template <typename T, typename Tin>
+void stsqr_launch(unsigned grid, const SegDev& S, const Tin* in, int64_t ld, const int32_t* items, int c, T* out,
+                  hipStream_t st) {
+  if (c <= 8) stsqr_go<T, Tin, 8>(grid, S, in, ld, items, c, out, st);
+  else if (c <= 16) stsqr_go<T, Tin, 16>(grid, S, in, ld, items, c, out, st);
+  else if (c <= 32) stsqr_go<T, Tin, 32>(grid, S, in, ld, items, c, out, st);
+  else stsqr_go<T, Tin, 64>(grid, S, in, ld, items, c, out, st);
+}
+
 template <typename T>
 void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const double* W, int64_t ldw, int c, T* scratch, T* R,
                   hipStream_t st) {
-  const int rb = P.rb;
-  const size_t lds = (size_t)rb * (c + 1) * sizeof(T);
   for (int l = 0; l < P.nlevels; ++l) {
     const int64_t i0 = P.level_off[l], i1 = P.level_off[l + 1];
     if (i1 <= i0) continue;
     T* out = (l == P.nlevels - 1) ? R : scratch + (l % 2) * P.half;
     if (l == 0)
-      stsqr_kernel<T, double><<<(unsigned)(i1 - i0), 64, lds, st>>>(S, W, ldw, P.items + 4 * i0, c, rb, out);
+      stsqr_launch<T, double>((unsigned)(i1 - i0), S, W, ldw, P.items + 4 * i0, c, out, st);
     else
-      stsqr_kernel<T, T><<<(unsigned)(i1 - i0), 64, lds, st>>>(S, scratch + ((l - 1) % 2) * P.half, c,
-                                                              P.items + 4 * i0, c, rb, out);
+      stsqr_launch<T, T>((unsigned)(i1 - i0), S, scratch + ((l - 1) % 2) * P.half, c, P.items + 4 * i0, c, out, st);
   }
 }
 template void launch_stsqr<float>(const SegDev&, const TsqrPlanDev&, const double*, int64_t, int, float*, float*,
@@ -425,10 +451,9 @@ template void launch_stsqr<double>(const SegDev&, const TsqrPlanDev&, const doub
                                    hipStream_t);
 
 int tsqr_rows_per_block(int c, int elem_bytes) {
-  int rb = 32 * 1024 / ((c + 1) * elem_bytes);
-  if (rb > 1024) rb = 1024;
-  if (rb < 2 * c) rb = 2 * c;
-  return rb;
+  (void)c;
+  (void)elem_bytes;
+  return kTsqrRows;
 }
 
 }  // namespace lobpcg

@@ -32,18 +32,21 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Symmetric eigensolver for the c x c Rayleigh-Ritz matrix, one workgroup:
+// Symmetric eigensolver for the c x c Rayleigh-Ritz matrix, one wave per matrix:
 //  1. Householder reduction to tridiagonal form T = Q^T H Q (reflectors stored
 //     below the subdiagonal, as in LAPACK's sytd2);
-//  2. every eigenvalue of T by bisection on Sturm counts, one thread per
+//  2. every eigenvalue of T by bisection on Sturm counts, one lane per
 //     eigenvalue (the count is backward stable, so each eigenvalue is accurate
 //     to a few ulps of ||T||);
-//  3. eigenvectors of T by inverse iteration with a pivoted tridiagonal LU;
-//     eigenvalues closer than 1e-3 ||T||_1 form a cluster whose vectors are
-//     computed one after another, each orthogonalised against the earlier ones;
-//  4. back-transformation C = Q Z.
-// Matrices up to 96 x 96 live in LDS, larger ones in the global scratch.
-constexpr int kSyevThreads = 512;
+//  3. eigenvectors of T by three sweeps of inverse iteration with a pivoted
+//     tridiagonal LU, one lane per eigenvector; after each sweep the vectors of
+//     every cluster (a chain of eigenvalues whose consecutive gaps are below
+//     1e-3 ||T||_1) are re-orthonormalised by modified Gram-Schmidt in eigenvalue
+//     order, so the next sweep purifies what the orthogonalisation mixed in;
+//  4. back-transformation C = Q Z, one lane per column.
+// Matrices up to 96 x 96 live in LDS, larger ones in the global scratch.  With a
+// single wave the barriers below only order LDS traffic between lanes.
+constexpr int kSyevThreads = 64;
 constexpr int kSyevLds = 96;
 constexpr int kSyevMax = 192;
 
@@ -61,16 +64,14 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   __shared__ double sz[kSyevLds * (kSyevLds + 1)];
   __shared__ double d[kSyevMax], e[kSyevMax], e2[kSyevMax], tau[kSyevMax], v[kSyevMax], p[kSyevMax];
   __shared__ double lam[kSyevMax];
-  __shared__ double sc[8];
-  __shared__ int crank[kSyevMax];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid % 64, wid = tid / 64;
+  __shared__ int cstart[kSyevMax], cend[kSyevMax];
+  const int lane = threadIdx.x;
   const int la = c + 1;
   const bool in_lds = (c <= kSyevLds);
   double* a = in_lds ? sa : work;
   double* Z = in_lds ? sz : work + (int64_t)c * la;
   double* lu = work + 2 * (int64_t)c * la;   // U0 | U1 | U2 | L | piv, each c x c, index [k * c + j]
-  for (int q = tid; q < c * c; q += nt) {
+  for (int q = lane; q < c * c; q += 64) {
     const int i = q / c, j = q % c;
     a[i * la + j] = 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]);
   }
@@ -78,61 +79,50 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   // ---- 1. tridiagonalization ----
   for (int k = 0; k + 2 < c; ++k) {
     const int nk = c - k - 1;
-    if (wid == 0) {
-      double ss = 0.0;
-      for (int i = k + 2 + lane; i < c; i += 64) ss += a[i * la + k] * a[i * la + k];
-      ss = wave_sum(ss);
-      if (lane == 0) {
-        const double alpha = a[(k + 1) * la + k];
-        double t = 0.0, beta = alpha, scale = 0.0;
-        if (ss > 0.0) {
-          const double xn = sqrt(alpha * alpha + ss);
-          beta = (alpha >= 0.0) ? -xn : xn;
-          t = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
-        }
-        sc[0] = t; sc[1] = beta; sc[2] = scale;
-        tau[k] = t; e[k] = beta; d[k] = a[k * la + k];
-      }
+    double ss = 0.0;
+    for (int i = k + 2 + lane; i < c; i += 64) ss += a[i * la + k] * a[i * la + k];
+    ss = wave_sum(ss);
+    const double alpha = a[(k + 1) * la + k];
+    double t = 0.0, beta = alpha, scale = 0.0;
+    if (ss > 0.0) {
+      const double xn = sqrt(alpha * alpha + ss);
+      beta = (alpha >= 0.0) ? -xn : xn;
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
     }
+    if (lane == 0) {
+      tau[k] = t;
+      e[k] = beta;
+      d[k] = a[k * la + k];
+    }
+    if (t == 0.0) continue;   // uniform
     __syncthreads();
-    const double t = sc[0];
-    if (t == 0.0) continue;
-    const double beta = sc[1], scale = sc[2];
-    for (int i = tid; i < nk; i += nt) {
+    for (int i = lane; i < nk; i += 64) {
       const double vi = (i == 0) ? 1.0 : a[(k + 1 + i) * la + k] * scale;
       v[i] = vi;
       if (i > 0) a[(k + 1 + i) * la + k] = vi;
     }
-    if (tid == 0) a[(k + 1) * la + k] = beta;
+    if (lane == 0) a[(k + 1) * la + k] = beta;
     __syncthreads();
-    // p = t * A22 v, 8 threads per row
-    for (int i = tid / 8; i < nk; i += nt / 8) {
-      double s8 = 0.0;
-      for (int j = tid % 8; j < nk; j += 8) s8 += a[(k + 1 + i) * la + k + 1 + j] * v[j];
-      s8 += __shfl_xor(s8, 1, 8);
-      s8 += __shfl_xor(s8, 2, 8);
-      s8 += __shfl_xor(s8, 4, 8);
-      if (tid % 8 == 0) p[i] = t * s8;
+    // p = t A22 v, by columns of the symmetric A22 (lane i reads row j's entry i: contiguous)
+    for (int i = lane; i < nk; i += 64) {
+      double s = 0.0;
+      for (int j = 0; j < nk; ++j) s += a[(k + 1 + j) * la + k + 1 + i] * v[j];
+      p[i] = t * s;
     }
+    double pv = 0.0;
+    for (int i = lane; i < nk; i += 64) pv += p[i] * v[i];
+    const double K = 0.5 * t * wave_sum(pv);
+    for (int i = lane; i < nk; i += 64) p[i] -= K * v[i];
     __syncthreads();
-    if (wid == 0) {
-      double ss = 0.0;
-      for (int i = lane; i < nk; i += 64) ss += p[i] * v[i];
-      ss = wave_sum(ss);
-      if (lane == 0) sc[3] = 0.5 * t * ss;
-    }
-    __syncthreads();
-    const double K = sc[3];
-    for (int i = tid; i < nk; i += nt) p[i] -= K * v[i];
-    __syncthreads();
-    for (int q = tid; q < nk * nk; q += nt) {
+    for (int q = lane; q < nk * nk; q += 64) {
       const int i = q / nk, j = q % nk;
       a[(k + 1 + i) * la + k + 1 + j] -= v[i] * p[j] + p[i] * v[j];
     }
     __syncthreads();
   }
-  if (tid == 0) {
+  __syncthreads();
+  if (lane == 0) {
     for (int k = (c >= 2 ? c - 2 : 0); k < c; ++k) d[k] = a[k * la + k];
     if (c >= 2) e[c - 2] = a[(c - 1) * la + c - 2];
     if (c >= 2) tau[c - 2] = 0.0;
@@ -150,13 +140,13 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     tnorm = fmax(tnorm, fabs(d[i]) + ei + em);
     emax2 = fmax(emax2, ei * ei);
   }
-  for (int i = tid; i < c; i += nt) e2[i] = (i < c - 1) ? e[i] * e[i] : 0.0;
+  for (int i = lane; i < c; i += 64) e2[i] = (i < c - 1) ? e[i] * e[i] : 0.0;
   const double eps = 2.220446049250313e-16;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   gl -= 2.0 * eps * tnorm * c + 2.0 * pivmin;
   gu += 2.0 * eps * tnorm * c + 2.0 * pivmin;
   __syncthreads();
-  for (int j = tid; j < c; j += nt) {
+  for (int j = lane; j < c; j += 64) {
     double lo = gl, hi = gu;
     for (int it = 0; it < 120; ++it) {
       const double mid = 0.5 * (lo + hi);
@@ -178,109 +168,112 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   // ---- 3. eigenvectors of T by inverse iteration ----
   const double ortol = 1e-3 * tnorm;
   int maxrank = 0;
-  for (int j = tid; j < c; j += nt) {
-    int r = 0;
-    while (j - r - 1 >= 0 && lam[j - r] - lam[j - r - 1] < ortol) ++r;
-    crank[j] = r;
+  if (lane == 0) {
+    cstart[0] = 0;
+    for (int j = 1; j < c; ++j) cstart[j] = (lam[j] - lam[j - 1] < ortol) ? cstart[j - 1] : j;
+    cend[c - 1] = c;
+    for (int j = c - 2; j >= 0; --j) cend[j] = (cstart[j + 1] == cstart[j]) ? cend[j + 1] : j + 1;
   }
   __syncthreads();
-  for (int j = 0; j < c; ++j) maxrank = max(maxrank, crank[j]);
+  for (int j = 0; j < c; ++j) maxrank = max(maxrank, j - cstart[j]);
   double* U0 = lu;
   double* U1 = lu + (int64_t)c * c;
   double* U2 = lu + 2 * (int64_t)c * c;
   double* Lm = lu + 3 * (int64_t)c * c;
   double* Pv = lu + 4 * (int64_t)c * c;
-  for (int round = 0; round <= maxrank; ++round) {
-    for (int j = tid; j < c; j += nt) {
-      if (crank[j] != round) continue;
-      const double lj = lam[j];
-      const double tiny = eps * tnorm + pivmin;
-      // pivoted LU of T - lj I (U with two superdiagonals)
-      double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0;
-      for (int k = 0; k + 1 < c; ++k) {
-        const double sub = e[k];
-        const double nd = d[k + 1] - lj;
-        const double ns = (k + 2 < c) ? e[k + 1] : 0.0;
-        if (fabs(cd) >= fabs(sub)) {
-          const double m = (cd != 0.0) ? sub / cd : 0.0;
-          U0[k * c + j] = cd; U1[k * c + j] = cs; U2[k * c + j] = 0.0; Pv[k * c + j] = 0.0; Lm[k * c + j] = m;
-          cd = nd - m * cs;
-          cs = ns;
-        } else {
-          const double m = cd / sub;
-          U0[k * c + j] = sub; U1[k * c + j] = nd; U2[k * c + j] = ns; Pv[k * c + j] = 1.0; Lm[k * c + j] = m;
-          cd = cs - m * nd;
-          cs = -m * ns;
-        }
-      }
-      U0[(c - 1) * c + j] = cd;
-      for (int k = 0; k < c; ++k)
-        if (fabs(U0[k * c + j]) < tiny) U0[k * c + j] = (U0[k * c + j] < 0.0) ? -tiny : tiny;
-      // start vector
-      for (int i = 0; i < c; ++i) Z[i * la + j] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 11) / 11.0;
-      const int start = j - crank[j];
-      for (int itn = 0; itn < 3; ++itn) {
-        // P, L
-        for (int k = 0; k + 1 < c; ++k) {
-          if (Pv[k * c + j] != 0.0) {
-            const double t0 = Z[k * la + j];
-            Z[k * la + j] = Z[(k + 1) * la + j];
-            Z[(k + 1) * la + j] = t0;
-          }
-          Z[(k + 1) * la + j] -= Lm[k * c + j] * Z[k * la + j];
-        }
-        // U
-        for (int k = c - 1; k >= 0; --k) {
-          double y = Z[k * la + j];
-          if (k + 1 < c) y -= U1[k * c + j] * Z[(k + 1) * la + j];
-          if (k + 2 < c) y -= U2[k * c + j] * Z[(k + 2) * la + j];
-          Z[k * la + j] = y / U0[k * c + j];
-        }
-        // orthogonalise against the cluster's earlier vectors, then normalise
-        for (int q = start; q < j; ++q) {
-          double dot = 0.0;
-          for (int i = 0; i < c; ++i) dot += Z[i * la + q] * Z[i * la + j];
-          for (int i = 0; i < c; ++i) Z[i * la + j] -= dot * Z[i * la + q];
-        }
-        double nrm = 0.0;
-        for (int i = 0; i < c; ++i) nrm += Z[i * la + j] * Z[i * la + j];
-        nrm = 1.0 / sqrt(nrm);
-        for (int i = 0; i < c; ++i) Z[i * la + j] *= nrm;
+  const double tiny = eps * tnorm + pivmin;
+  for (int j = lane; j < c; j += 64) {
+    const double lj = lam[j];
+    // pivoted LU of T - lj I (U with two superdiagonals)
+    double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0;
+    for (int k = 0; k + 1 < c; ++k) {
+      const double sub = e[k];
+      const double nd = d[k + 1] - lj;
+      const double ns = (k + 2 < c) ? e[k + 1] : 0.0;
+      if (fabs(cd) >= fabs(sub)) {
+        const double m = (cd != 0.0) ? sub / cd : 0.0;
+        U0[k * c + j] = cd; U1[k * c + j] = cs; U2[k * c + j] = 0.0; Pv[k * c + j] = 0.0; Lm[k * c + j] = m;
+        cd = nd - m * cs;
+        cs = ns;
+      } else {
+        const double m = cd / sub;
+        U0[k * c + j] = sub; U1[k * c + j] = nd; U2[k * c + j] = ns; Pv[k * c + j] = 1.0; Lm[k * c + j] = m;
+        cd = cs - m * nd;
+        cs = -m * ns;
       }
     }
-    __syncthreads();
+    U0[(c - 1) * c + j] = cd;
+    for (int k = 0; k < c; ++k)
+      if (fabs(U0[k * c + j]) < tiny) U0[k * c + j] = (U0[k * c + j] < 0.0) ? -tiny : tiny;
+    for (int i = 0; i < c; ++i) Z[i * la + j] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 11) / 11.0;
   }
-  // ---- 4. back-transformation C = Q Z ----
+  for (int itn = 0; itn < 3; ++itn) {
+    // one inverse-iteration step per column (lane j owns column j), then normalise
+    for (int j = lane; j < c; j += 64) {
+      for (int k = 0; k + 1 < c; ++k) {
+        if (Pv[k * c + j] != 0.0) {
+          const double t0 = Z[k * la + j];
+          Z[k * la + j] = Z[(k + 1) * la + j];
+          Z[(k + 1) * la + j] = t0;
+        }
+        Z[(k + 1) * la + j] -= Lm[k * c + j] * Z[k * la + j];
+      }
+      double nrm = 0.0;
+      for (int k = c - 1; k >= 0; --k) {
+        double y = Z[k * la + j];
+        if (k + 1 < c) y -= U1[k * c + j] * Z[(k + 1) * la + j];
+        if (k + 2 < c) y -= U2[k * c + j] * Z[(k + 2) * la + j];
+        y /= U0[k * c + j];
+        Z[k * la + j] = y;
+        nrm += y * y;
+      }
+      nrm = 1.0 / sqrt(nrm);
+      for (int i = 0; i < c; ++i) Z[i * la + j] *= nrm;
+    }
+    __syncthreads();
+    // modified Gram-Schmidt inside each cluster, in eigenvalue order
+    for (int q = 0; q + 1 < c; ++q) {
+      const int qe = cend[q];
+      if (qe - q < 2) continue;   // uniform: no later member of q's cluster
+      for (int r = q + 1 + lane; r < qe; r += 64) {
+        double dot = 0.0;
+        for (int i = 0; i < c; ++i) dot += Z[i * la + q] * Z[i * la + r];
+        for (int i = 0; i < c; ++i) Z[i * la + r] -= dot * Z[i * la + q];
+      }
+      __syncthreads();
+      double nn = 0.0;
+      for (int i = lane; i < c; i += 64) nn += Z[i * la + q + 1] * Z[i * la + q + 1];
+      nn = 1.0 / sqrt(wave_sum(nn));
+      for (int i = lane; i < c; i += 64) Z[i * la + q + 1] *= nn;
+      __syncthreads();
+    }
+  }
+  // ---- 4. back-transformation C = Q Z (lane j owns column j) ----
   for (int k = c - 3; k >= 0; --k) {
     const double t = tau[k];
     if (t == 0.0) continue;
     const int nk = c - k - 1;
-    // w_j = v^T Z(k+1:, j), four threads per column
-    for (int q = tid; q < 4 * c; q += nt) {
-      const int j = q / 4, part = q % 4;
-      double sw = 0.0;
-      for (int i = part; i < nk; i += 4) sw += (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) * Z[(k + 1 + i) * la + j];
-      sw += __shfl_xor(sw, 1, 4);
-      sw += __shfl_xor(sw, 2, 4);
-      if (part == 0) p[j] = t * sw;
+    for (int j = lane; j < c; j += 64) {
+      double sw = Z[(k + 1) * la + j];
+      for (int i = 1; i < nk; ++i) sw += a[(k + 1 + i) * la + k] * Z[(k + 1 + i) * la + j];
+      sw *= t;
+      Z[(k + 1) * la + j] -= sw;
+      for (int i = 1; i < nk; ++i) Z[(k + 1 + i) * la + j] -= a[(k + 1 + i) * la + k] * sw;
     }
-    __syncthreads();
-    for (int q = tid; q < nk * c; q += nt) {
-      const int i = q / c, j = q % c;
-      Z[(k + 1 + i) * la + j] -= (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) * p[j];
-    }
-    __syncthreads();
   }
-  for (int q = tid; q < c * c; q += nt) {
+  __syncthreads();
+  for (int q = lane; q < c * c; q += 64) {
     const int i = q / c, j = q % c;
     C[(int64_t)i * c + j] = Z[i * la + j];
   }
-  for (int j = tid; j < c; j += nt) evals[j] = lam[j];
-  if (tid == 0 && info) info[blockIdx.x] = maxrank;
+  for (int j = lane; j < c; j += 64) evals[j] = lam[j];
+  if (lane == 0 && info) info[blockIdx.x] = maxrank;
 }
 
 // HL: Z = C(0:m, m:c)^T (r x m, r = c - m); Householder QR; Q explicit; G = [C(:,0:m), C(:,m:c) Q].
-constexpr int kHlThreads = 512;
+// One wave per matrix; in the QR and in forming Q each lane owns columns of Z or Q, so the only
+// cross-lane traffic is the reflector vector (one barrier before and one after it is formed).
+constexpr int kHlThreads = 64;
 constexpr int kHlMaxR = 128;
 constexpr int kHlMaxM = 64;
 
@@ -293,20 +286,17 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   __shared__ double z[kHlMaxR * (kHlMaxM + 1)];
   __shared__ double qm[kHlMaxR * (kHlMaxM + 1)];
   __shared__ double tau[kHlMaxM];
-  __shared__ double wv[kHlMaxM];
-  __shared__ double red[kHlThreads / 64];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid % 64, wid = tid / 64, nw = nt / 64;
+  const int lane = threadIdx.x;
   const int r = c - m;
   const int lz = m + 1;   // odd LDS row stride
   const int ldg = (r > 0) ? 2 * m : m;
   // copy C(:, 0:m)
-  for (int e = tid; e < c * m; e += nt) {
+  for (int e = lane; e < c * m; e += 64) {
     const int i = e / m, j = e % m;
     G[(int64_t)i * ldg + j] = C[(int64_t)i * c + j];
   }
   if (r <= 0) return;
-  for (int e = tid; e < r * m; e += nt) {
+  for (int e = lane; e < r * m; e += 64) {
     const int i = e / m, j = e % m;
     z[i * lz + j] = C[(int64_t)j * c + m + i];
     qm[i * lz + j] = (i == j) ? 1.0 : 0.0;
@@ -315,55 +305,50 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   const int kmax = (m < r) ? m : r;
   for (int j = 0; j < kmax; ++j) {
     double s = 0.0;
-    for (int i = j + 1 + tid; i < r; i += nt) s += z[i * lz + j] * z[i * lz + j];
-    s = block_sum(s, red);
+    for (int i = j + 1 + lane; i < r; i += 64) s += z[i * lz + j] * z[i * lz + j];
+    s = wave_sum(s);
     const double alpha = z[j * lz + j];
-    const double xn = sqrt(alpha * alpha + s);
     double tj = 0.0, beta = alpha, scale = 0.0;
     if (s > 0.0) {
+      const double xn = sqrt(alpha * alpha + s);
       beta = (alpha >= 0.0) ? -xn : xn;
       tj = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    __syncthreads();
+    __syncthreads();   // every lane has read column j before it is overwritten by v
     if (s > 0.0)
-      for (int i = j + 1 + tid; i < r; i += nt) z[i * lz + j] *= scale;
-    if (tid == 0) { tau[j] = tj; z[j * lz + j] = beta; }
-    __syncthreads();
-    // apply H_j = I - tau v v^T (v_j = 1) to columns k > j
-    for (int k = j + 1 + wid; k < m; k += nw) {
-      double w = 0.0;
-      for (int i = j + lane; i < r; i += 64) w += (i == j ? 1.0 : z[i * lz + j]) * z[i * lz + k];
-      w = wave_sum(w);
-      if (lane == 0) wv[k] = w;
+      for (int i = j + 1 + lane; i < r; i += 64) z[i * lz + j] *= scale;
+    if (lane == 0) {
+      tau[j] = tj;
+      z[j * lz + j] = beta;
     }
     __syncthreads();
-    for (int e = tid; e < (r - j) * (m - j - 1); e += nt) {
-      const int i = j + e / (m - j - 1), k = j + 1 + e % (m - j - 1);
-      const double vi = (i == j) ? 1.0 : z[i * lz + j];
-      z[i * lz + k] -= tj * vi * wv[k];
-    }
+    // apply H_j = I - tau v v^T (v_j = 1) to columns k > j; lane owns column k
+    if (tj != 0.0)
+      for (int k = j + 1 + lane; k < m; k += 64) {
+        double w = z[j * lz + k];
+        for (int i = j + 1; i < r; ++i) w += z[i * lz + j] * z[i * lz + k];
+        w *= tj;
+        z[j * lz + k] -= w;
+        for (int i = j + 1; i < r; ++i) z[i * lz + k] -= z[i * lz + j] * w;
+      }
     __syncthreads();
   }
-  // Q = H_0 ... H_{kmax-1} [I; 0]
+  // Q = H_0 ... H_{kmax-1} [I; 0], lane owns column k of Q
   for (int j = kmax - 1; j >= 0; --j) {
     const double tj = tau[j];
-    for (int k = wid; k < m; k += nw) {
-      double w = 0.0;
-      for (int i = j + lane; i < r; i += 64) w += (i == j ? 1.0 : z[i * lz + j]) * qm[i * lz + k];
-      w = wave_sum(w);
-      if (lane == 0) wv[k] = w;
+    if (tj == 0.0) continue;
+    for (int k = lane; k < m; k += 64) {
+      double w = qm[j * lz + k];
+      for (int i = j + 1; i < r; ++i) w += z[i * lz + j] * qm[i * lz + k];
+      w *= tj;
+      qm[j * lz + k] -= w;
+      for (int i = j + 1; i < r; ++i) qm[i * lz + k] -= z[i * lz + j] * w;
     }
-    __syncthreads();
-    for (int e = tid; e < (r - j) * m; e += nt) {
-      const int i = j + e / m, k = e % m;
-      const double vi = (i == j) ? 1.0 : z[i * lz + j];
-      qm[i * lz + k] -= tj * vi * wv[k];
-    }
-    __syncthreads();
   }
+  __syncthreads();
   // G(:, m:2m) = C(:, m:c) Q
-  for (int e = tid; e < c * m; e += nt) {
+  for (int e = lane; e < c * m; e += 64) {
     const int i = e / m, j = e % m;
     double acc = 0.0;
     for (int k = 0; k < r; ++k) acc += C[(int64_t)i * c + m + k] * qm[k * lz + j];
