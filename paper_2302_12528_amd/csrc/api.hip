@@ -877,7 +877,7 @@ lobpcg_status iteration_body(lobpcg_ctx c, int cur, bool haveP, bool timed) {
   const int cc = wslot + m;
   launch_sgram(C.SG, Sx, m3, ASx, m3, cc, cc, C.H, (int64_t)m3 * m3, C.gpart, st);
   // line 14: A_p C = C D
-  launch_syev(C.H, cc, (int64_t)m3 * m3, cc, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info,
+  launch_syev(C.H, cc, (int64_t)m3 * m3, cc, m, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info,
               C.d_active, B, st);
   // lines 15-16: HL basis and the new X, P (and A X, A P by the same combination)
   launch_hl_build(C.Cev, (int64_t)m3 * m3, cc, m, C.Gupd, (int64_t)m3 * 2 * m, C.d_active, B, st);
@@ -951,7 +951,7 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
   ST_TRY(ortho(c, X, m3, m));
   apply_a(c, X, m3, C.ASb[cur], m3, m);
   launch_sgram(C.SG, X, m3, C.ASb[cur], m3, m, m, C.H, (int64_t)m3 * m3, C.gpart, st);
-  launch_syev(C.H, m, (int64_t)m3 * m3, m, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info, C.d_active, B,
+  launch_syev(C.H, m, (int64_t)m3 * m3, m, m, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info, C.d_active, B,
               st);
   launch_hl_build(C.Cev, (int64_t)m3 * m3, m, m, C.Gupd, (int64_t)m3 * 2 * m, C.d_active, B, st);
   launch_supdate(C.SG, C.Sb[cur], m3, C.Gupd, m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], m3, m, m, 1.0, 0.0, st);
@@ -1478,7 +1478,7 @@ lobpcg_status lobpcg_syev_small(const double* H, int32_t cc, double* evals, doub
   void* work = nullptr;
   HIP_TRY(hipMalloc(&work, (size_t)syev_scratch(cc) * 8 + 64));
   int* info = reinterpret_cast<int*>(static_cast<char*>(work) + syev_scratch(cc) * 8);
-  launch_syev(H, cc, 0, cc, evals, 0, evecs, 0, static_cast<double*>(work), info, nullptr, 1, st);
+  launch_syev(H, cc, 0, cc, cc, evals, 0, evecs, 0, static_cast<double*>(work), info, nullptr, 1, st);
   lobpcg_status s = check_launch("syev");
   (void)hipStreamSynchronize(st);
   (void)hipFree(work);

@@ -62,12 +62,13 @@ void launch_copy_block(const double* src, int64_t lds, double* dst, int64_t ldd,
 void launch_fill_int(int32_t* p, int32_t v, int64_t count, hipStream_t st);
 
 // ---- small dense kernels (k_small.hip), one workgroup per instance ----
-// Symmetric eigensolver: H (c x c, ldh) -> evals ascending, C (c x c, column j = eigenvector j).
+// Symmetric eigensolver: the nev smallest eigenpairs of H (c x c, ldh): evals ascending, columns 0..nev-1
+// of C (c x c, row stride c) the eigenvectors.  work: syev_scratch(c) doubles per instance.
 int64_t syev_scratch(int c);
-void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, double* evals, int64_t estride, double* C,
-                 int64_t cstride, double* work, int* info, const int32_t* active, int B, hipStream_t st);
-// Hetmaniuk-Lehoucq: G (c x 2m, ld 2m) = [C(:,1:m), C(:,m+1:c) V], V = Householder Q of C(1:m, m+1:c)^T;
-// if c == m, G = C(:, 1:m) (ld m).
+void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, int nev, double* evals, int64_t estride,
+                 double* C, int64_t cstride, double* work, int* info, const int32_t* active, int B, hipStream_t st);
+// Hetmaniuk-Lehoucq: G (c x 2m, ld 2m) = [C1, Pc] with C1 = C(:, 0:m) and Pc an orthonormal basis of
+// (I - C1 C1^T) E1 (the span of C(:, m:c) C(0:m, m:c)^T); if c == m, G = C1 (ld m).
 void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, int64_t gstride,
                      const int32_t* active, int B, hipStream_t st);
 // Algorithm 2 step 3 per instance: G = V^T V = L L^T; Lt = L^T; Rout = L^T working(Rl) if non-NULL;

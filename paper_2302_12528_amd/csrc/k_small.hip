@@ -32,27 +32,40 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Symmetric eigensolver for the c x c Rayleigh-Ritz matrix, one wave per matrix:
-//  1. Householder reduction to tridiagonal form T = Q^T H Q (reflectors stored
-//     below the subdiagonal, as in LAPACK's sytd2);
-//  2. every eigenvalue of T by bisection on Sturm counts, one lane per
-//     eigenvalue (the count is backward stable, so each eigenvalue is accurate
-//     to a few ulps of ||T||);
-//  3. eigenvectors of T by three sweeps of inverse iteration with a pivoted
-//     tridiagonal LU, one lane per eigenvector; after each sweep the vectors of
-//     every cluster (a chain of eigenvalues whose consecutive gaps are below
-//     1e-3 ||T||_1) are re-orthonormalised by modified Gram-Schmidt in eigenvalue
-//     order, so the next sweep purifies what the orthogonalisation mixed in;
-//  4. back-transformation C = Q Z, one lane per column.
-// Matrices up to 96 x 96 live in LDS, larger ones in the global scratch.  With a
-// single wave the barriers below only order LDS traffic between lanes.
-constexpr int kSyevThreads = 64;
+// Symmetric eigensolver for the c x c Rayleigh-Ritz matrix: the nev smallest eigenpairs, one
+// workgroup of four waves per matrix.
+//  1. Householder reduction to tridiagonal form T = Q^T H Q (reflectors stored below the
+//     subdiagonal, as in LAPACK's sytd2);
+//  2. the nev smallest eigenvalues of T by multisection on Sturm counts: every round, each
+//     eigenvalue's bracket is cut at P interior points evaluated by P threads (the Sturm count is
+//     backward stable, so each eigenvalue is accurate to a few ulps of ||T||);
+//  3. their eigenvectors by two sweeps of inverse iteration with a pivoted tridiagonal LU, one
+//     thread per vector; after each sweep the vectors of every cluster (a chain of eigenvalues
+//     whose consecutive gaps are below 1e-3 ||T||_1) are re-orthonormalised by modified
+//     Gram-Schmidt in eigenvalue order, so the next sweep purifies what that mixed in;
+//  4. back-transformation C = Q Z of the nev vectors, several threads per column.
+// Matrices up to 96 x 96 live in LDS, larger ones in the global scratch.
+constexpr int kSyevThreads = 256;
 constexpr int kSyevLds = 96;
 constexpr int kSyevMax = 192;
 
+__device__ inline int sturm_count(const double* d, const double* e2, int c, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += (q < 0.0);
+  for (int i = 1; i < c; ++i) {
+    q = (d[i] - x) - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+  }
+  return cnt;
+}
+
 __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __restrict__ H, int64_t ldh,
-                                                            int64_t hstride, int c, double* __restrict__ evals,
-                                                            int64_t estride, double* __restrict__ C, int64_t cstride,
+                                                            int64_t hstride, int c, int nev,
+                                                            double* __restrict__ evals, int64_t estride,
+                                                            double* __restrict__ C, int64_t cstride,
                                                             double* __restrict__ work, int64_t wstride, int* info,
                                                             const int32_t* __restrict__ active) {
   if (active && !active[blockIdx.x]) return;
@@ -62,26 +75,36 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   work += (int64_t)blockIdx.x * wstride;
   __shared__ double sa[kSyevLds * (kSyevLds + 1)];
   __shared__ double sz[kSyevLds * (kSyevLds + 1)];
-  __shared__ double d[kSyevMax], e[kSyevMax], e2[kSyevMax], tau[kSyevMax], v[kSyevMax], p[kSyevMax];
-  __shared__ double lam[kSyevMax];
-  __shared__ int cstart[kSyevMax], cend[kSyevMax];
-  const int lane = threadIdx.x;
+  __shared__ double d[kSyevMax], e[kSyevMax], tau[kSyevMax];
+  __shared__ double s1[kSyevMax], s2[kSyevMax];   // v, p (step 1) | e^2, bracket lows (step 2)
+  __shared__ double lam[kSyevMax];                // bracket highs, then eigenvalues
+  __shared__ int cnt[kSyevThreads];
+  __shared__ short cend[kSyevMax];
+  __shared__ double sc[8];
+  const int tid = threadIdx.x, lane = tid % 64, wid = tid / 64;
   const int la = c + 1;
   const bool in_lds = (c <= kSyevLds);
   double* a = in_lds ? sa : work;
-  double* Z = in_lds ? sz : work + (int64_t)c * la;
-  double* lu = work + 2 * (int64_t)c * la;   // U0 | U1 | U2 | L | piv, each c x c, index [k * c + j]
-  for (int q = lane; q < c * c; q += 64) {
+  double* Z = in_lds ? sz : work + (int64_t)c * la;   // c x nev, row stride la
+  double* lu = work + 2 * (int64_t)c * la;            // U0 | U1 | U2 | L | piv, each c x nev, index [k * nev + j]
+  for (int q = tid; q < c * c; q += kSyevThreads) {
     const int i = q / c, j = q % c;
     a[i * la + j] = 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]);
   }
   __syncthreads();
   // ---- 1. tridiagonalization ----
+  double* v = s1;
+  double* p = s2;
   for (int k = 0; k + 2 < c; ++k) {
     const int nk = c - k - 1;
-    double ss = 0.0;
-    for (int i = k + 2 + lane; i < c; i += 64) ss += a[i * la + k] * a[i * la + k];
-    ss = wave_sum(ss);
+    if (wid == 0) {
+      double ss = 0.0;
+      for (int i = k + 2 + lane; i < c; i += 64) ss += a[i * la + k] * a[i * la + k];
+      ss = wave_sum(ss);
+      if (lane == 0) sc[k & 1] = ss;
+    }
+    __syncthreads();
+    const double ss = sc[k & 1];
     const double alpha = a[(k + 1) * la + k];
     double t = 0.0, beta = alpha, scale = 0.0;
     if (ss > 0.0) {
@@ -90,39 +113,52 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
       t = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    if (lane == 0) {
+    if (tid == 0) {
       tau[k] = t;
       e[k] = beta;
       d[k] = a[k * la + k];
     }
-    if (t == 0.0) continue;   // uniform
+    if (t == 0.0) continue;   // uniform; sc is double-buffered across this barrier-free skip
+    for (int i = tid; i < nk; i += kSyevThreads) v[i] = (i == 0) ? 1.0 : a[(k + 1 + i) * la + k] * scale;
     __syncthreads();
-    for (int i = lane; i < nk; i += 64) {
-      const double vi = (i == 0) ? 1.0 : a[(k + 1 + i) * la + k] * scale;
-      v[i] = vi;
-      if (i > 0) a[(k + 1 + i) * la + k] = vi;
+    for (int i = tid + 1; i < nk; i += kSyevThreads) a[(k + 1 + i) * la + k] = v[i];
+    if (tid == 0) a[(k + 1) * la + k] = beta;
+    // p = t A22 v: two threads per row, each half of the columns of the symmetric A22 (read by
+    // columns so that consecutive threads read consecutive addresses), four partial sums each
+    for (int i = tid >> 1; i < nk; i += kSyevThreads / 2) {
+      const int h = tid & 1;
+      double s0 = 0.0, s1p = 0.0, s2p = 0.0, s3 = 0.0;
+      int j = h;
+      for (; j + 6 < nk; j += 8) {
+        s0 += a[(k + 1 + j) * la + k + 1 + i] * v[j];
+        s1p += a[(k + 3 + j) * la + k + 1 + i] * v[j + 2];
+        s2p += a[(k + 5 + j) * la + k + 1 + i] * v[j + 4];
+        s3 += a[(k + 7 + j) * la + k + 1 + i] * v[j + 6];
+      }
+      for (; j < nk; j += 2) s0 += a[(k + 1 + j) * la + k + 1 + i] * v[j];
+      double sum = (s0 + s1p) + (s2p + s3);
+      sum += __shfl_xor(sum, 1, 64);
+      if (h == 0) p[i] = t * sum;
     }
-    if (lane == 0) a[(k + 1) * la + k] = beta;
     __syncthreads();
-    // p = t A22 v, by columns of the symmetric A22 (lane i reads row j's entry i: contiguous)
-    for (int i = lane; i < nk; i += 64) {
-      double s = 0.0;
-      for (int j = 0; j < nk; ++j) s += a[(k + 1 + j) * la + k + 1 + i] * v[j];
-      p[i] = t * s;
+    if (wid == 0) {
+      double pv = 0.0;
+      for (int i = lane; i < nk; i += 64) pv += p[i] * v[i];
+      pv = wave_sum(pv);
+      if (lane == 0) sc[2 + (k & 1)] = pv;
     }
-    double pv = 0.0;
-    for (int i = lane; i < nk; i += 64) pv += p[i] * v[i];
-    const double K = 0.5 * t * wave_sum(pv);
-    for (int i = lane; i < nk; i += 64) p[i] -= K * v[i];
     __syncthreads();
-    for (int q = lane; q < nk * nk; q += 64) {
-      const int i = q / nk, j = q % nk;
-      a[(k + 1 + i) * la + k + 1 + j] -= v[i] * p[j] + p[i] * v[j];
+    const double K = 0.5 * t * sc[2 + (k & 1)];
+    // A22 -= v w^T + w v^T with w = p - K v
+    for (int i = wid; i < nk; i += 4) {
+      const double vi = v[i], wi = p[i] - K * vi;
+      for (int j = lane; j < nk; j += 64)
+        a[(k + 1 + i) * la + k + 1 + j] -= vi * (p[j] - K * v[j]) + wi * v[j];
     }
     __syncthreads();
   }
   __syncthreads();
-  if (lane == 0) {
+  if (tid == 0) {
     for (int k = (c >= 2 ? c - 2 : 0); k < c; ++k) d[k] = a[k * la + k];
     if (c >= 2) e[c - 2] = a[(c - 1) * la + c - 2];
     if (c >= 2) tau[c - 2] = 0.0;
@@ -130,7 +166,10 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     e[c - 1] = 0.0;
   }
   __syncthreads();
-  // ---- 2. eigenvalues by bisection ----
+  // ---- 2. the nev smallest eigenvalues by multisection ----
+  double* e2 = s1;
+  double* lo = s2;
+  double* hi = lam;
   double gl = 1e300, gu = -1e300, tnorm = 0.0, emax2 = 0.0;
   for (int i = 0; i < c; ++i) {
     const double ei = (i < c - 1) ? fabs(e[i]) : 0.0;
@@ -140,51 +179,65 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     tnorm = fmax(tnorm, fabs(d[i]) + ei + em);
     emax2 = fmax(emax2, ei * ei);
   }
-  for (int i = lane; i < c; i += 64) e2[i] = (i < c - 1) ? e[i] * e[i] : 0.0;
   const double eps = 2.220446049250313e-16;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   gl -= 2.0 * eps * tnorm * c + 2.0 * pivmin;
   gu += 2.0 * eps * tnorm * c + 2.0 * pivmin;
-  __syncthreads();
-  for (int j = lane; j < c; j += 64) {
-    double lo = gl, hi = gu;
-    for (int it = 0; it < 120; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (!(hi - lo > 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) || mid == lo || mid == hi) break;
-      int cnt = 0;
-      double q = d[0] - mid;
-      if (fabs(q) < pivmin) q = -pivmin;
-      cnt += (q < 0.0);
-      for (int i = 1; i < c; ++i) {
-        q = (d[i] - mid) - e2[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        cnt += (q < 0.0);
-      }
-      if (cnt >= j + 1) hi = mid; else lo = mid;
-    }
-    lam[j] = 0.5 * (lo + hi);
+  for (int i = tid; i < c; i += kSyevThreads) e2[i] = (i < c - 1) ? e[i] * e[i] : 0.0;
+  for (int j = tid; j < nev; j += kSyevThreads) {
+    lo[j] = gl;
+    hi[j] = gu;
   }
+  __syncthreads();
+  const int P = max(1, kSyevThreads / nev);   // interior points per bracket
+  for (int round = 0; round < 200; ++round) {
+    const int j = tid / P, q = tid % P;
+    bool open = false;
+    if (j < nev) {
+      const double l = lo[j], h = hi[j];
+      open = (h - l > 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin);
+      const double x = l + (h - l) * (double)(q + 1) / (double)(P + 1);
+      cnt[tid] = (open && x > l && x < h) ? sturm_count(d, e2, c, x, pivmin) : -1;
+    }
+    if (!__syncthreads_or(open)) break;
+    if (j < nev && q == 0) {
+      const double l = lo[j], h = hi[j];
+      if (h - l > 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin) {
+        double nl = l, nh = h;
+        for (int r = 0; r < P; ++r) {
+          const int cr = cnt[tid + r];
+          if (cr < 0) continue;
+          const double x = l + (h - l) * (double)(r + 1) / (double)(P + 1);
+          if (cr >= j + 1) {
+            nh = x;
+            break;
+          }
+          nl = x;
+        }
+        if (nl == l && nh == h) nh = nl;   // no interior point strictly inside: the bracket is at ulp level
+        lo[j] = nl;
+        hi[j] = nh;
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < nev; j += kSyevThreads) lam[j] = 0.5 * (lo[j] + hi[j]);
   __syncthreads();
   // ---- 3. eigenvectors of T by inverse iteration ----
   const double ortol = 1e-3 * tnorm;
-  int maxrank = 0;
-  if (lane == 0) {
-    cstart[0] = 0;
-    for (int j = 1; j < c; ++j) cstart[j] = (lam[j] - lam[j - 1] < ortol) ? cstart[j - 1] : j;
-    cend[c - 1] = c;
-    for (int j = c - 2; j >= 0; --j) cend[j] = (cstart[j + 1] == cstart[j]) ? cend[j + 1] : j + 1;
+  if (tid == 0) {
+    cend[nev - 1] = (short)nev;
+    for (int j = nev - 2; j >= 0; --j) cend[j] = (lam[j + 1] - lam[j] < ortol) ? cend[j + 1] : (short)(j + 1);
   }
-  __syncthreads();
-  for (int j = 0; j < c; ++j) maxrank = max(maxrank, j - cstart[j]);
   double* U0 = lu;
-  double* U1 = lu + (int64_t)c * c;
-  double* U2 = lu + 2 * (int64_t)c * c;
-  double* Lm = lu + 3 * (int64_t)c * c;
-  double* Pv = lu + 4 * (int64_t)c * c;
+  double* U1 = lu + (int64_t)c * nev;
+  double* U2 = lu + 2 * (int64_t)c * nev;
+  double* Lm = lu + 3 * (int64_t)c * nev;
+  double* Pv = lu + 4 * (int64_t)c * nev;
   const double tiny = eps * tnorm + pivmin;
-  for (int j = lane; j < c; j += 64) {
+  const int lz = in_lds ? la : nev;   // row stride of Z
+  for (int j = tid; j < nev; j += kSyevThreads) {
     const double lj = lam[j];
-    // pivoted LU of T - lj I (U with two superdiagonals)
     double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0;
     for (int k = 0; k + 1 < c; ++k) {
       const double sub = e[k];
@@ -192,89 +245,106 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
       const double ns = (k + 2 < c) ? e[k + 1] : 0.0;
       if (fabs(cd) >= fabs(sub)) {
         const double m = (cd != 0.0) ? sub / cd : 0.0;
-        U0[k * c + j] = cd; U1[k * c + j] = cs; U2[k * c + j] = 0.0; Pv[k * c + j] = 0.0; Lm[k * c + j] = m;
+        U0[k * nev + j] = cd; U1[k * nev + j] = cs; U2[k * nev + j] = 0.0; Pv[k * nev + j] = 0.0;
+        Lm[k * nev + j] = m;
         cd = nd - m * cs;
         cs = ns;
       } else {
         const double m = cd / sub;
-        U0[k * c + j] = sub; U1[k * c + j] = nd; U2[k * c + j] = ns; Pv[k * c + j] = 1.0; Lm[k * c + j] = m;
+        U0[k * nev + j] = sub; U1[k * nev + j] = nd; U2[k * nev + j] = ns; Pv[k * nev + j] = 1.0;
+        Lm[k * nev + j] = m;
         cd = cs - m * nd;
         cs = -m * ns;
       }
     }
-    U0[(c - 1) * c + j] = cd;
+    U0[(c - 1) * nev + j] = cd;
     for (int k = 0; k < c; ++k)
-      if (fabs(U0[k * c + j]) < tiny) U0[k * c + j] = (U0[k * c + j] < 0.0) ? -tiny : tiny;
-    for (int i = 0; i < c; ++i) Z[i * la + j] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 11) / 11.0;
+      if (fabs(U0[k * nev + j]) < tiny) U0[k * nev + j] = (U0[k * nev + j] < 0.0) ? -tiny : tiny;
+    for (int i = 0; i < c; ++i) Z[i * lz + j] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 11) / 11.0;
   }
-  for (int itn = 0; itn < 3; ++itn) {
-    // one inverse-iteration step per column (lane j owns column j), then normalise
-    for (int j = lane; j < c; j += 64) {
+  __syncthreads();
+  int maxrank = 0;
+  for (int j = 0; j < nev; ++j) maxrank = max(maxrank, (int)cend[j] - j - 1);
+  for (int itn = 0; itn < 2; ++itn) {
+    for (int j = tid; j < nev; j += kSyevThreads) {
       for (int k = 0; k + 1 < c; ++k) {
-        if (Pv[k * c + j] != 0.0) {
-          const double t0 = Z[k * la + j];
-          Z[k * la + j] = Z[(k + 1) * la + j];
-          Z[(k + 1) * la + j] = t0;
+        if (Pv[k * nev + j] != 0.0) {
+          const double t0 = Z[k * lz + j];
+          Z[k * lz + j] = Z[(k + 1) * lz + j];
+          Z[(k + 1) * lz + j] = t0;
         }
-        Z[(k + 1) * la + j] -= Lm[k * c + j] * Z[k * la + j];
+        Z[(k + 1) * lz + j] -= Lm[k * nev + j] * Z[k * lz + j];
       }
       double nrm = 0.0;
       for (int k = c - 1; k >= 0; --k) {
-        double y = Z[k * la + j];
-        if (k + 1 < c) y -= U1[k * c + j] * Z[(k + 1) * la + j];
-        if (k + 2 < c) y -= U2[k * c + j] * Z[(k + 2) * la + j];
-        y /= U0[k * c + j];
-        Z[k * la + j] = y;
+        double y = Z[k * lz + j];
+        if (k + 1 < c) y -= U1[k * nev + j] * Z[(k + 1) * lz + j];
+        if (k + 2 < c) y -= U2[k * nev + j] * Z[(k + 2) * lz + j];
+        y /= U0[k * nev + j];
+        Z[k * lz + j] = y;
         nrm += y * y;
       }
       nrm = 1.0 / sqrt(nrm);
-      for (int i = 0; i < c; ++i) Z[i * la + j] *= nrm;
+      for (int i = 0; i < c; ++i) Z[i * lz + j] *= nrm;
     }
     __syncthreads();
-    // modified Gram-Schmidt inside each cluster, in eigenvalue order
-    for (int q = 0; q + 1 < c; ++q) {
+    // modified Gram-Schmidt inside each cluster, in eigenvalue order: wave w takes the later
+    // members r = q + 1 + w, q + 5 + w, ...; lanes split the rows
+    for (int q = 0; q + 1 < nev; ++q) {
       const int qe = cend[q];
-      if (qe - q < 2) continue;   // uniform: no later member of q's cluster
-      for (int r = q + 1 + lane; r < qe; r += 64) {
+      if (qe - q < 2) continue;   // uniform
+      for (int r = q + 1 + wid; r < qe; r += 4) {
         double dot = 0.0;
-        for (int i = 0; i < c; ++i) dot += Z[i * la + q] * Z[i * la + r];
-        for (int i = 0; i < c; ++i) Z[i * la + r] -= dot * Z[i * la + q];
+        for (int i = lane; i < c; i += 64) dot += Z[i * lz + q] * Z[i * lz + r];
+        dot = wave_sum(dot);
+        for (int i = lane; i < c; i += 64) Z[i * lz + r] -= dot * Z[i * lz + q];
       }
       __syncthreads();
-      double nn = 0.0;
-      for (int i = lane; i < c; i += 64) nn += Z[i * la + q + 1] * Z[i * la + q + 1];
-      nn = 1.0 / sqrt(wave_sum(nn));
-      for (int i = lane; i < c; i += 64) Z[i * la + q + 1] *= nn;
+      if (wid == 0) {
+        double nn = 0.0;
+        for (int i = lane; i < c; i += 64) nn += Z[i * lz + q + 1] * Z[i * lz + q + 1];
+        nn = 1.0 / sqrt(wave_sum(nn));
+        for (int i = lane; i < c; i += 64) Z[i * lz + q + 1] *= nn;
+      }
       __syncthreads();
     }
   }
-  // ---- 4. back-transformation C = Q Z (lane j owns column j) ----
-  for (int k = c - 3; k >= 0; --k) {
-    const double t = tau[k];
-    if (t == 0.0) continue;
-    const int nk = c - k - 1;
-    for (int j = lane; j < c; j += 64) {
-      double sw = Z[(k + 1) * la + j];
-      for (int i = 1; i < nk; ++i) sw += a[(k + 1 + i) * la + k] * Z[(k + 1 + i) * la + j];
+  // ---- 4. back-transformation C = Q Z: G threads per column (a power of two), each a row segment ----
+  int G = 1;
+  while (G * 2 * nev <= kSyevThreads && G < 64) G *= 2;
+  {
+    const int j = tid / G, g = tid % G;
+    for (int k = c - 3; k >= 0; --k) {
+      const double t = tau[k];
+      if (t == 0.0) continue;
+      const int nk = c - k - 1;
+      double sw = 0.0;
+      if (j < nev)
+        for (int i = g; i < nk; i += G) sw += (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) * Z[(k + 1 + i) * lz + j];
+      for (int off = G / 2; off > 0; off >>= 1) sw += __shfl_xor(sw, off, 64);
       sw *= t;
-      Z[(k + 1) * la + j] -= sw;
-      for (int i = 1; i < nk; ++i) Z[(k + 1 + i) * la + j] -= a[(k + 1 + i) * la + k] * sw;
+      if (j < nev)
+        for (int i = g; i < nk; i += G) Z[(k + 1 + i) * lz + j] -= (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) * sw;
+      __syncthreads();   // the next reflector reads rows another thread of the group wrote
     }
   }
   __syncthreads();
-  for (int q = lane; q < c * c; q += 64) {
-    const int i = q / c, j = q % c;
-    C[(int64_t)i * c + j] = Z[i * la + j];
+  for (int q = tid; q < c * nev; q += kSyevThreads) {
+    const int i = q / nev, j = q % nev;
+    C[(int64_t)i * c + j] = Z[i * lz + j];
   }
-  for (int j = lane; j < c; j += 64) evals[j] = lam[j];
-  if (lane == 0 && info) info[blockIdx.x] = maxrank;
+  for (int j = tid; j < nev; j += kSyevThreads) evals[j] = lam[j];
+  if (tid == 0 && info) info[blockIdx.x] = maxrank;
 }
 
-// HL: Z = C(0:m, m:c)^T (r x m, r = c - m); Householder QR; Q explicit; G = [C(:,0:m), C(:,m:c) Q].
-// One wave per matrix; in the QR and in forming Q each lane owns columns of Z or Q, so the only
-// cross-lane traffic is the reflector vector (one barrier before and one after it is formed).
-constexpr int kHlThreads = 64;
-constexpr int kHlMaxR = 128;
+// Hetmaniuk-Lehoucq basis from the m leading eigenvectors C1 = C(:, 0:m) (c x m, row stride c):
+// G = [C1, Pc] with Pc an orthonormal basis of (I - C1 C1^T) E1, E1 the first m unit vectors.
+// Since C2 C2^T = I - C1 C1^T, this is the span of C(:, m:c) C(0:m, m:c)^T, so S Pc spans the same
+// P as S C(:, m:c) V with V the orthonormal factor of C(0:m, m:c)^T, without the c - m other
+// eigenvectors.  Pc is projected against C1 and orthonormalised by modified Gram-Schmidt, twice,
+// then projected and orthonormalised once more so that Pc^T C1 is at rounding level.
+constexpr int kHlThreads = 256;
+constexpr int kHlMaxC = 192;
 constexpr int kHlMaxM = 64;
 
 __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __restrict__ C, int64_t cstride, int c,
@@ -283,76 +353,62 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   if (active && !active[blockIdx.x]) return;
   C += (int64_t)blockIdx.x * cstride;
   G += (int64_t)blockIdx.x * gstride;
-  __shared__ double z[kHlMaxR * (kHlMaxM + 1)];
-  __shared__ double qm[kHlMaxR * (kHlMaxM + 1)];
-  __shared__ double tau[kHlMaxM];
-  const int lane = threadIdx.x;
-  const int r = c - m;
-  const int lz = m + 1;   // odd LDS row stride
-  const int ldg = (r > 0) ? 2 * m : m;
-  // copy C(:, 0:m)
-  for (int e = lane; e < c * m; e += 64) {
-    const int i = e / m, j = e % m;
+  __shared__ double w[kHlMaxC * (kHlMaxM + 1)];
+  __shared__ double tm[kHlMaxM * (kHlMaxM + 1)];
+  const int tid = threadIdx.x, lane = tid % 64, wid = tid / 64;
+  const int lw = m + 1;
+  const int ldg = (c > m) ? 2 * m : m;
+  for (int q = tid; q < c * m; q += kHlThreads) {
+    const int i = q / m, j = q % m;
     G[(int64_t)i * ldg + j] = C[(int64_t)i * c + j];
   }
-  if (r <= 0) return;
-  for (int e = lane; e < r * m; e += 64) {
-    const int i = e / m, j = e % m;
-    z[i * lz + j] = C[(int64_t)j * c + m + i];
-    qm[i * lz + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  const int kmax = (m < r) ? m : r;
-  for (int j = 0; j < kmax; ++j) {
+  if (c <= m) return;
+  // W = E1 - C1 C1(0:m, :)^T
+  for (int q = tid; q < c * m; q += kHlThreads) {
+    const int i = q / m, j = q % m;
     double s = 0.0;
-    for (int i = j + 1 + lane; i < r; i += 64) s += z[i * lz + j] * z[i * lz + j];
-    s = wave_sum(s);
-    const double alpha = z[j * lz + j];
-    double tj = 0.0, beta = alpha, scale = 0.0;
-    if (s > 0.0) {
-      const double xn = sqrt(alpha * alpha + s);
-      beta = (alpha >= 0.0) ? -xn : xn;
-      tj = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    __syncthreads();   // every lane has read column j before it is overwritten by v
-    if (s > 0.0)
-      for (int i = j + 1 + lane; i < r; i += 64) z[i * lz + j] *= scale;
-    if (lane == 0) {
-      tau[j] = tj;
-      z[j * lz + j] = beta;
-    }
-    __syncthreads();
-    // apply H_j = I - tau v v^T (v_j = 1) to columns k > j; lane owns column k
-    if (tj != 0.0)
-      for (int k = j + 1 + lane; k < m; k += 64) {
-        double w = z[j * lz + k];
-        for (int i = j + 1; i < r; ++i) w += z[i * lz + j] * z[i * lz + k];
-        w *= tj;
-        z[j * lz + k] -= w;
-        for (int i = j + 1; i < r; ++i) z[i * lz + k] -= z[i * lz + j] * w;
-      }
-    __syncthreads();
-  }
-  // Q = H_0 ... H_{kmax-1} [I; 0], lane owns column k of Q
-  for (int j = kmax - 1; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj == 0.0) continue;
-    for (int k = lane; k < m; k += 64) {
-      double w = qm[j * lz + k];
-      for (int i = j + 1; i < r; ++i) w += z[i * lz + j] * qm[i * lz + k];
-      w *= tj;
-      qm[j * lz + k] -= w;
-      for (int i = j + 1; i < r; ++i) qm[i * lz + k] -= z[i * lz + j] * w;
-    }
+    for (int l = 0; l < m; ++l) s += C[(int64_t)i * c + l] * C[(int64_t)j * c + l];
+    w[i * lw + j] = ((i == j) ? 1.0 : 0.0) - s;
   }
   __syncthreads();
-  // G(:, m:2m) = C(:, m:c) Q
-  for (int e = lane; e < c * m; e += 64) {
-    const int i = e / m, j = e % m;
-    double acc = 0.0;
-    for (int k = 0; k < r; ++k) acc += C[(int64_t)i * c + m + k] * qm[k * lz + j];
-    G[(int64_t)i * ldg + m + j] = acc;
+  for (int pass = 0; pass < 3; ++pass) {
+    // W -= C1 (C1^T W)
+    for (int q = tid; q < m * m; q += kHlThreads) {
+      const int l = q / m, j = q % m;
+      double s = 0.0;
+      for (int i = 0; i < c; ++i) s += C[(int64_t)i * c + l] * w[i * lw + j];
+      tm[l * lw + j] = s;
+    }
+    __syncthreads();
+    for (int q = tid; q < c * m; q += kHlThreads) {
+      const int i = q / m, j = q % m;
+      double s = 0.0;
+      for (int l = 0; l < m; ++l) s += C[(int64_t)i * c + l] * tm[l * lw + j];
+      w[i * lw + j] -= s;
+    }
+    __syncthreads();
+    // modified Gram-Schmidt on the columns of W
+    for (int j = 0; j < m; ++j) {
+      if (wid == 0) {
+        double nn = 0.0;
+        for (int i = lane; i < c; i += 64) nn += w[i * lw + j] * w[i * lw + j];
+        nn = wave_sum(nn);
+        const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+        for (int i = lane; i < c; i += 64) w[i * lw + j] *= inv;
+      }
+      __syncthreads();
+      for (int r = j + 1 + wid; r < m; r += 4) {
+        double dot = 0.0;
+        for (int i = lane; i < c; i += 64) dot += w[i * lw + j] * w[i * lw + r];
+        dot = wave_sum(dot);
+        for (int i = lane; i < c; i += 64) w[i * lw + r] -= dot * w[i * lw + j];
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = tid; q < c * m; q += kHlThreads) {
+    const int i = q / m, j = q % m;
+    G[(int64_t)i * ldg + m + j] = w[i * lw + j];
   }
 }
 
@@ -412,10 +468,10 @@ __global__ void __launch_bounds__(256) chol_upper_kernel(const double* __restric
 
 int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c + 16; }
 
-void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, double* evals, int64_t estride, double* C,
-                 int64_t cstride, double* work, int* info, const int32_t* active, int B, hipStream_t st) {
-  syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, evals, estride, C, cstride, work, syev_scratch(c),
-                                          info, active);
+void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, int nev, double* evals, int64_t estride,
+                 double* C, int64_t cstride, double* work, int* info, const int32_t* active, int B, hipStream_t st) {
+  syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work,
+                                          syev_scratch(c), info, active);
 }
 
 void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, int64_t gstride,
