@@ -262,73 +262,83 @@ __global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, double* W, int
 
 // ---------------------------------------------------------------------------
 // TSQR block: Householder QR (R only) of a block of at most 256 rows starting at `in`.
-// Thread t holds row t in registers (columns padded to CP); for each column j the sums
-// over rows (the norm below the diagonal and w_k = v^T A(:, k) for k > j) are wave
-// reductions combined across the 4 waves through LDS, one barrier each.
+// Thread t holds row t in registers (columns padded to CP).  For column j one pass over the
+// block gives every sum the step needs: S_k = sum_{t > j} a_tj a_tk for k >= j (S_j is the
+// squared norm below the diagonal) through an LDS transpose, each column summed by 256 / CP
+// threads and a shuffle; with v = e_j + scale * a(j+1:, j), w_k = v^T a(:, k) = a_jk + scale S_k.
 // ---------------------------------------------------------------------------
 constexpr int kTsqrRows = 256;
-
-template <typename T>
-__device__ inline T wave_reduce(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 template <typename T, typename Tin, int CP>
 __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* in, int64_t ldin,
                                                           const int32_t* __restrict__ items, int c, T* out) {
-  __shared__ T red[2][4][CP + 1];   // [norm | w] partials per wave, double-buffered by column parity
+  constexpr int NR = kTsqrRows;
+  constexpr int PARTS = NR / CP;        // threads per column sum
+  constexpr int LP = NR + 4;            // padded LDS row of the transpose
+  __shared__ T pr[CP * LP];             // pr[k * LP + t] = a_tj a_tk (t > j)
+  __shared__ T sk[CP];                  // S_k
+  __shared__ T rj[CP];                  // row j
   const int* it = items + 4 * blockIdx.x;   // {instance, first row, rows, output slot}
   const int b = it[0];
   if (!S.active[b]) return;
   const int64_t r0 = it[1];
   const int rows = it[2];
   const int slot = it[3];
-  const int t = threadIdx.x, lane = t % 64, w = t / 64;
+  const int t = threadIdx.x;
   T a[CP];
 #pragma unroll
   for (int k = 0; k < CP; ++k) a[k] = (t < rows && k < c) ? (T)in[(r0 + t) * ldin + k] : (T)0;
   const int kmax = (c < rows) ? c : rows;
+  const int sk_k = t / PARTS, sk_part = t % PARTS;
   for (int j = 0; j < kmax; ++j) {
-    T (*rd)[CP + 1] = red[j & 1];
     T aj = 0;
 #pragma unroll
     for (int k = 0; k < CP; ++k)
       if (k == j) aj = a[k];
-    // column j: sigma = sum of squares below the diagonal, alpha = diagonal entry
-    T sq = wave_reduce((t > j) ? aj * aj : (T)0);
-    if (lane == 0) rd[w][CP] = sq;
-    if (t == j) rd[0][j] = aj;   // slot j of wave 0 is free until the w sums below
+    const T m = (t > j) ? aj : (T)0;
+#pragma unroll
+    for (int k = 0; k < CP; ++k)
+      if (k >= j) pr[k * LP + t] = m * a[k];
+    if (t == j) {
+#pragma unroll
+      for (int k = 0; k < CP; ++k) rj[k] = a[k];
+    }
     __syncthreads();
-    const T sigma = ((rd[0][CP] + rd[1][CP]) + rd[2][CP]) + rd[3][CP];
-    const T alpha = rd[0][j];
-    if (!(sigma > (T)0)) continue;   // nothing below the diagonal: H_j = I (sigma is uniform)
+    if (sk_k >= j && sk_k < c) {
+      const T* col = pr + sk_k * LP + sk_part * CP;
+      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+      for (int q = 0; q < CP; q += 4) {
+        s0 += col[q];
+        s1 += col[q + 1];
+        s2 += col[q + 2];
+        s3 += col[q + 3];
+      }
+      T sum = (s0 + s1) + (s2 + s3);
+#pragma unroll
+      for (int off = PARTS / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+      if (sk_part == 0) sk[sk_k] = sum;   // (the PARTS threads of a column are consecutive lanes)
+    }
+    __syncthreads();
+    const T sigma = sk[j];
+    if (!(sigma > (T)0)) continue;   // nothing below the diagonal: H_j = I (uniform)
+    const T alpha = rj[j];
     const T xn = sqrt(alpha * alpha + sigma);
     const T beta = (alpha >= (T)0) ? -xn : xn;
     const T tau = (beta - alpha) / beta;
     const T scale = (T)1 / (alpha - beta);
     const T v = (t > j) ? aj * scale : (t == j ? (T)1 : (T)0);
-    // (the w sums go to slots k > j of this column's buffer; the buffer of column j - 2, which
-    // held the same slots, was last read before the barrier of column j - 1)
-    // w_k = v^T A(:, k) for k > j
 #pragma unroll
     for (int k = 0; k < CP; ++k) {
       if (k > j && k < c) {
-        const T pk = wave_reduce(v * a[k]);
-        if (lane == 0) rd[w][k] = pk;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < CP; ++k) {
-      if (k > j && k < c) {
-        const T wk = ((rd[0][k] + rd[1][k]) + rd[2][k]) + rd[3][k];
+        const T wk = rj[k] + scale * sk[k];
         a[k] -= tau * v * wk;
       } else if (k == j) {
         a[k] = (t == j) ? beta : (t > j ? (T)0 : a[k]);
       }
     }
+    // (pr, sk and rj are rewritten only after the next column's first barrier, which every
+    // thread reaches after its reads above)
   }
   T* R = out + (int64_t)slot * c * c;
   if (t < c) {

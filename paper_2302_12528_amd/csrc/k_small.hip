@@ -49,13 +49,24 @@ constexpr int kSyevThreads = 256;
 constexpr int kSyevLds = 96;
 constexpr int kSyevMax = 192;
 
+// 1/q from the hardware reciprocal refined by two Newton steps (about one ulp), a shorter
+// dependency chain than the IEEE division sequence.
+__device__ inline double rcp_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
+// Number of eigenvalues of T (diagonal d, squared off-diagonal e2) below x: negative pivots of the
+// LDL^T factorization of T - x I, with tiny pivots replaced by -pivmin.
 __device__ inline int sturm_count(const double* d, const double* e2, int c, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += (q < 0.0);
   for (int i = 1; i < c; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
+    q = fma(-e2[i - 1], rcp_nr(q), d[i] - x);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += (q < 0.0);
   }
@@ -149,11 +160,25 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     }
     __syncthreads();
     const double K = 0.5 * t * sc[2 + (k & 1)];
-    // A22 -= v w^T + w v^T with w = p - K v
-    for (int i = wid; i < nk; i += 4) {
-      const double vi = v[i], wi = p[i] - K * vi;
-      for (int j = lane; j < nk; j += 64)
-        a[(k + 1 + i) * la + k + 1 + j] -= vi * (p[j] - K * v[j]) + wi * v[j];
+    // A22 -= v w^T + w v^T with w = p - K v: lane owns columns j, wave w rows i = w mod 4,
+    // four rows per step so that their loads are in flight together
+    for (int j = lane; j < nk; j += 64) {
+      const double vj = v[j], wj = p[j] - K * vj;
+      double* col = a + (k + 1) * la + k + 1 + j;
+      int i = wid;
+      for (; i + 12 < nk; i += 16) {
+        const double v0 = v[i], v1 = v[i + 4], v2 = v[i + 8], v3 = v[i + 12];
+        const double w0 = p[i] - K * v0, w1 = p[i + 4] - K * v1, w2 = p[i + 8] - K * v2, w3 = p[i + 12] - K * v3;
+        const double a0 = col[i * la], a1 = col[(i + 4) * la], a2 = col[(i + 8) * la], a3 = col[(i + 12) * la];
+        col[i * la] = a0 - (v0 * wj + w0 * vj);
+        col[(i + 4) * la] = a1 - (v1 * wj + w1 * vj);
+        col[(i + 8) * la] = a2 - (v2 * wj + w2 * vj);
+        col[(i + 12) * la] = a3 - (v3 * wj + w3 * vj);
+      }
+      for (; i < nk; i += 4) {
+        const double vi = v[i], wi = p[i] - K * vi;
+        col[i * la] -= vi * wj + wi * vj;
+      }
     }
     __syncthreads();
   }
@@ -267,22 +292,58 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   for (int j = 0; j < nev; ++j) maxrank = max(maxrank, (int)cend[j] - j - 1);
   for (int itn = 0; itn < 2; ++itn) {
     for (int j = tid; j < nev; j += kSyevThreads) {
-      for (int k = 0; k + 1 < c; ++k) {
-        if (Pv[k * nev + j] != 0.0) {
-          const double t0 = Z[k * lz + j];
-          Z[k * lz + j] = Z[(k + 1) * lz + j];
-          Z[(k + 1) * lz + j] = t0;
+      // forward: P and L, carrying the running entry in a register; factors fetched 4 steps ahead
+      double zk = Z[j];
+      for (int k0 = 0; k0 + 1 < c; k0 += 4) {
+        double pv[4], lm[4], zn[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u;
+          const bool ok = k + 1 < c;
+          pv[u] = ok ? Pv[k * nev + j] : 0.0;
+          lm[u] = ok ? Lm[k * nev + j] : 0.0;
+          zn[u] = ok ? Z[(k + 1) * lz + j] : 0.0;
         }
-        Z[(k + 1) * lz + j] -= Lm[k * nev + j] * Z[k * lz + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u;
+          if (k + 1 >= c) break;
+          double lo_ = zk, hi_ = zn[u];
+          if (pv[u] != 0.0) {
+            lo_ = zn[u];
+            hi_ = zk;
+          }
+          Z[k * lz + j] = lo_;
+          zk = hi_ - lm[u] * lo_;
+        }
       }
-      double nrm = 0.0;
-      for (int k = c - 1; k >= 0; --k) {
-        double y = Z[k * lz + j];
-        if (k + 1 < c) y -= U1[k * nev + j] * Z[(k + 1) * lz + j];
-        if (k + 2 < c) y -= U2[k * nev + j] * Z[(k + 2) * lz + j];
-        y /= U0[k * nev + j];
-        Z[k * lz + j] = y;
-        nrm += y * y;
+      Z[(c - 1) * lz + j] = zk;
+      // backward: U with two superdiagonals, factors fetched 4 steps ahead
+      double nrm = 0.0, z1 = 0.0, z2 = 0.0;   // Z[k + 1], Z[k + 2]
+      for (int k0 = c - 1; k0 >= 0; k0 -= 4) {
+        double u0[4], u1[4], u2[4], zz[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 - u;
+          const bool ok = k >= 0;
+          u0[u] = ok ? U0[k * nev + j] : 1.0;
+          u1[u] = ok ? U1[k * nev + j] : 0.0;
+          u2[u] = ok ? U2[k * nev + j] : 0.0;
+          zz[u] = ok ? Z[k * lz + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 - u;
+          if (k < 0) break;
+          double y = zz[u];
+          if (k + 1 < c) y -= u1[u] * z1;
+          if (k + 2 < c) y -= u2[u] * z2;
+          y /= u0[u];
+          Z[k * lz + j] = y;
+          nrm += y * y;
+          z2 = z1;
+          z1 = y;
+        }
       }
       nrm = 1.0 / sqrt(nrm);
       for (int i = 0; i < c; ++i) Z[i * lz + j] *= nrm;
@@ -342,10 +403,9 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
 // Since C2 C2^T = I - C1 C1^T, this is the span of C(:, m:c) C(0:m, m:c)^T, so S Pc spans the same
 // P as S C(:, m:c) V with V the orthonormal factor of C(0:m, m:c)^T, without the c - m other
 // eigenvectors.  Pc is projected against C1 and orthonormalised by modified Gram-Schmidt, twice,
-// then projected and orthonormalised once more so that Pc^T C1 is at rounding level.
+// so that Pc^T Pc - I and Pc^T C1 are at rounding level.  C1 is staged in LDS when it fits.
 constexpr int kHlThreads = 256;
-constexpr int kHlMaxC = 192;
-constexpr int kHlMaxM = 64;
+constexpr int kHlLds = 20224;   // doubles
 
 __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __restrict__ C, int64_t cstride, int c,
                                                               int m, double* __restrict__ G, int64_t gstride,
@@ -353,38 +413,61 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   if (active && !active[blockIdx.x]) return;
   C += (int64_t)blockIdx.x * cstride;
   G += (int64_t)blockIdx.x * gstride;
-  __shared__ double w[kHlMaxC * (kHlMaxM + 1)];
-  __shared__ double tm[kHlMaxM * (kHlMaxM + 1)];
+  __shared__ double lds[kHlLds];
   const int tid = threadIdx.x, lane = tid % 64, wid = tid / 64;
   const int lw = m + 1;
   const int ldg = (c > m) ? 2 * m : m;
+  double* w = lds;                  // c x m (row stride lw)
+  double* tm = lds + c * lw;        // m x m
+  const bool c1_lds = (2 * c * lw + m * lw <= kHlLds);
+  double* c1 = c1_lds ? tm + m * lw : nullptr;
+  const int ldc1 = c1_lds ? lw : c;
+  const double* C1 = c1_lds ? c1 : C;
   for (int q = tid; q < c * m; q += kHlThreads) {
     const int i = q / m, j = q % m;
-    G[(int64_t)i * ldg + j] = C[(int64_t)i * c + j];
+    const double x = C[(int64_t)i * c + j];
+    G[(int64_t)i * ldg + j] = x;
+    if (c1_lds) c1[i * lw + j] = x;
   }
   if (c <= m) return;
+  __syncthreads();
   // W = E1 - C1 C1(0:m, :)^T
   for (int q = tid; q < c * m; q += kHlThreads) {
     const int i = q / m, j = q % m;
-    double s = 0.0;
-    for (int l = 0; l < m; ++l) s += C[(int64_t)i * c + l] * C[(int64_t)j * c + l];
-    w[i * lw + j] = ((i == j) ? 1.0 : 0.0) - s;
+    double s0 = 0.0, s1 = 0.0;
+    int l = 0;
+    for (; l + 1 < m; l += 2) {
+      s0 += C1[i * ldc1 + l] * C1[j * ldc1 + l];
+      s1 += C1[i * ldc1 + l + 1] * C1[j * ldc1 + l + 1];
+    }
+    if (l < m) s0 += C1[i * ldc1 + l] * C1[j * ldc1 + l];
+    w[i * lw + j] = ((i == j) ? 1.0 : 0.0) - (s0 + s1);
   }
   __syncthreads();
-  for (int pass = 0; pass < 3; ++pass) {
+  for (int pass = 0; pass < 2; ++pass) {
     // W -= C1 (C1^T W)
     for (int q = tid; q < m * m; q += kHlThreads) {
       const int l = q / m, j = q % m;
-      double s = 0.0;
-      for (int i = 0; i < c; ++i) s += C[(int64_t)i * c + l] * w[i * lw + j];
-      tm[l * lw + j] = s;
+      double s0 = 0.0, s1 = 0.0;
+      int i = 0;
+      for (; i + 1 < c; i += 2) {
+        s0 += C1[i * ldc1 + l] * w[i * lw + j];
+        s1 += C1[(i + 1) * ldc1 + l] * w[(i + 1) * lw + j];
+      }
+      if (i < c) s0 += C1[i * ldc1 + l] * w[i * lw + j];
+      tm[l * lw + j] = s0 + s1;
     }
     __syncthreads();
     for (int q = tid; q < c * m; q += kHlThreads) {
       const int i = q / m, j = q % m;
-      double s = 0.0;
-      for (int l = 0; l < m; ++l) s += C[(int64_t)i * c + l] * tm[l * lw + j];
-      w[i * lw + j] -= s;
+      double s0 = 0.0, s1 = 0.0;
+      int l = 0;
+      for (; l + 1 < m; l += 2) {
+        s0 += C1[i * ldc1 + l] * tm[l * lw + j];
+        s1 += C1[i * ldc1 + l + 1] * tm[(l + 1) * lw + j];
+      }
+      if (l < m) s0 += C1[i * ldc1 + l] * tm[l * lw + j];
+      w[i * lw + j] -= s0 + s1;
     }
     __syncthreads();
     // modified Gram-Schmidt on the columns of W
