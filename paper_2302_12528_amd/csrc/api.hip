@@ -193,6 +193,8 @@ struct lobpcg_ctx_s {
   int64_t chunk_rows = 0;
   int tuned = 0;   // 0 defaults, 1 measured at setup, 2 read from the cache file
   int64_t gpart_bytes = 0, fpart_bytes = 0, bpart_bytes = 0;
+  void* h_rb = nullptr;       // pinned host copy of the norms | evals | flags block
+  int64_t rb_bytes = 0;
 
   template <typename X>
   lobpcg_status alloc(X*& p, int64_t count) {
@@ -212,6 +214,7 @@ struct lobpcg_ctx_s {
     return s;
   }
   ~lobpcg_ctx_s() {
+    if (h_rb) (void)hipHostFree(h_rb);
     for (hipGraphExec_t g : gexec)
       if (g) (void)hipGraphExecDestroy(g);
     if (ev_order) (void)hipEventDestroy(ev_order);
@@ -628,7 +631,18 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   SETUP_TRY(C.alloc_bytes(C.dinv, S.dinv_total * tsz));
   SETUP_TRY(C.alloc_bytes(C.lcopy, S.lcopy_max * tsz));
   SETUP_TRY(C.alloc(C.d_flag, 4));
-  SETUP_TRY(C.alloc(C.d_qflag, 2 * count));
+  // one device block read back to pinned host memory once per iteration: norms | evals | flags
+  {
+    const int64_t nd = (int64_t)count * 2 * m + (int64_t)count * 3 * m;
+    C.rb_bytes = nd * 8 + 2 * (int64_t)count * 4;
+    void* blk = nullptr;
+    SETUP_TRY(C.alloc_bytes(blk, C.rb_bytes));
+    C.norms = static_cast<double*>(blk);
+    C.evals = C.norms + (int64_t)count * 2 * m;
+    C.d_qflag = reinterpret_cast<int*>(C.evals + (int64_t)count * 3 * m);
+    if (hipHostMalloc(&C.h_rb, C.rb_bytes, hipHostMallocDefault) != hipSuccess)
+      return cleanup(fail(LOBPCG_ERR_ALLOC, "hipHostMalloc failed"));
+  }
   SETUP_TRY(C.alloc(C.d_info, count));
   // ---- iteration buffers ----
   const int m3 = 3 * m;
@@ -650,10 +664,8 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   SETUP_TRY(C.alloc(C.gpart, C.gpart_bytes / 8));
   SETUP_TRY(C.alloc(C.H, (int64_t)count * m3 * m3));
   SETUP_TRY(C.alloc(C.Cev, (int64_t)count * m3 * m3));
-  SETUP_TRY(C.alloc(C.evals, (int64_t)count * m3));
   SETUP_TRY(C.alloc(C.Gupd, (int64_t)count * m3 * 2 * m));
   SETUP_TRY(C.alloc(C.Gc, (int64_t)count * 2 * m * m));
-  SETUP_TRY(C.alloc(C.norms, (int64_t)count * 2 * m));
   SETUP_TRY(C.alloc(C.syev_work, (int64_t)count * syev_scratch(m3)));
   SETUP_TRY(C.alloc_bytes(C.tsqr_ws, 2 * std::max(C.TQ32.half * 4, C.TQ64.half * 8)));
   SETUP_TRY(C.alloc_bytes(C.Rl, (int64_t)count * m * m * 8));
@@ -959,8 +971,6 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
   cur = 1 - cur;
   ST_TRY(check_launch("initial Rayleigh-Ritz"));
   bool haveP = false;
-  std::vector<double> hn((int64_t)B * 2 * m), th((int64_t)B * m3);
-  std::vector<int32_t> qf(2 * (size_t)B);
   const bool timed = (B == 1) && !graph;
   bool pending = false;
   double t_pc = 0, t_sp = 0;
@@ -996,10 +1006,13 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
       launch_sresidual<double>(C.SG, ASx, m3, Sx, m3, C.evals, m3, m, static_cast<double*>(C.rhs), C.mp, C.norms,
                                C.gpart, st);
     ST_TRY(check_launch("residual"));
-    HIP_TRY(hipMemcpyAsync(hn.data(), C.norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(th.data(), C.evals, th.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(qf.data(), C.d_qflag, qf.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    int active_before = 0;
+    for (int b = 0; b < B; ++b) active_before += C.active[b];
+    HIP_TRY(hipMemcpyAsync(C.h_rb, C.norms, C.rb_bytes, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    const double* hn = static_cast<const double*>(C.h_rb);
+    const double* th = hn + (int64_t)B * 2 * m;
+    const int32_t* qf = reinterpret_cast<const int32_t*>(th + (int64_t)B * m3);
     harvest();
     // the previous Algorithm 2 call: FP64 retries taken, and retries that broke down as well
     for (int b = 0; b < B; ++b) {
@@ -1016,8 +1029,8 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
     for (int b = 0; b < B; ++b) {
       if (!C.active[b]) continue;
       iters[b] = it;
-      const double* hb = hn.data() + (int64_t)b * 2 * m;
-      const double* tb = th.data() + (int64_t)b * m3;
+      const double* hb = hn + (int64_t)b * 2 * m;
+      const double* tb = th + (int64_t)b * m3;
       bool finite = true;
       std::vector<double> res(m);
       for (int j = 0; j < m; ++j) {
@@ -1058,7 +1071,7 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
       }
     }
     if (nactive == 0) break;
-    ST_TRY(set_active(c));
+    if (nactive != active_before) ST_TRY(set_active(c));   // the device mask is stale only after a change
     if (graph && haveP) {
       if (!C.gexec[cur]) ST_TRY(capture_iteration(c, cur));
       HIP_TRY(hipGraphLaunch(C.gexec[cur], st));
