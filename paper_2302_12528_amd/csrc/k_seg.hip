@@ -262,10 +262,11 @@ __global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, double* W, int
 
 // ---------------------------------------------------------------------------
 // TSQR block: Householder QR (R only) of a block of at most 256 rows starting at `in`.
-// Thread t holds row t in registers (columns padded to CP).  For column j one pass over the
-// block gives every sum the step needs: S_k = sum_{t > j} a_tj a_tk for k >= j (S_j is the
-// squared norm below the diagonal) through an LDS transpose, each column summed by 256 / CP
-// threads and a shuffle; with v = e_j + scale * a(j+1:, j), w_k = v^T a(:, k) = a_jk + scale S_k.
+// The block is held column-major in LDS (A[k][t], row t = thread t).  For column j one pass
+// gives every sum the step needs, S_k = sum_{t > j} a_tj a_tk for k >= j (S_j is the squared
+// norm below the diagonal), each column pair summed by 256 / CP threads and a shuffle; with
+// v = e_j + scale * a(j+1:, j), w_k = v^T a(:, k) = a_jk + scale S_k, and thread t then
+// updates its own row.
 // ---------------------------------------------------------------------------
 constexpr int kTsqrRows = 256;
 
@@ -274,10 +275,9 @@ __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* i
                                                           const int32_t* __restrict__ items, int c, T* out) {
   constexpr int NR = kTsqrRows;
   constexpr int PARTS = NR / CP;        // threads per column sum
-  constexpr int LP = NR + 4;            // padded LDS row of the transpose
-  __shared__ T pr[CP * LP];             // pr[k * LP + t] = a_tj a_tk (t > j)
+  constexpr int LP = NR + 4;            // padded LDS column
+  __shared__ T A[CP * LP];              // A[k * LP + t] = element (t, k)
   __shared__ T sk[CP];                  // S_k
-  __shared__ T rj[CP];                  // row j
   const int* it = items + 4 * blockIdx.x;   // {instance, first row, rows, output slot}
   const int b = it[0];
   if (!S.active[b]) return;
@@ -285,67 +285,51 @@ __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* i
   const int rows = it[2];
   const int slot = it[3];
   const int t = threadIdx.x;
-  T a[CP];
-#pragma unroll
-  for (int k = 0; k < CP; ++k) a[k] = (t < rows && k < c) ? (T)in[(r0 + t) * ldin + k] : (T)0;
+  for (int k = 0; k < c; ++k) A[k * LP + t] = (t < rows) ? (T)in[(r0 + t) * ldin + k] : (T)0;
+  __syncthreads();
   const int kmax = (c < rows) ? c : rows;
   const int sk_k = t / PARTS, sk_part = t % PARTS;
   for (int j = 0; j < kmax; ++j) {
-    T aj = 0;
-#pragma unroll
-    for (int k = 0; k < CP; ++k)
-      if (k == j) aj = a[k];
-    const T m = (t > j) ? aj : (T)0;
-#pragma unroll
-    for (int k = 0; k < CP; ++k)
-      if (k >= j) pr[k * LP + t] = m * a[k];
-    if (t == j) {
-#pragma unroll
-      for (int k = 0; k < CP; ++k) rj[k] = a[k];
-    }
-    __syncthreads();
+    // S_k for k >= j over the rows below the diagonal (the PARTS threads of a column are
+    // consecutive lanes of one wave)
     if (sk_k >= j && sk_k < c) {
-      const T* col = pr + sk_k * LP + sk_part * CP;
-      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+      const T* cj = A + j * LP + sk_part * CP;
+      const T* ck = A + sk_k * LP + sk_part * CP;
+      const int base = sk_part * CP;
+      T s0 = 0, s1 = 0;
 #pragma unroll
-      for (int q = 0; q < CP; q += 4) {
-        s0 += col[q];
-        s1 += col[q + 1];
-        s2 += col[q + 2];
-        s3 += col[q + 3];
+      for (int q = 0; q < CP; q += 2) {
+        if (base + q > j) s0 += cj[q] * ck[q];
+        if (base + q + 1 > j) s1 += cj[q + 1] * ck[q + 1];
       }
-      T sum = (s0 + s1) + (s2 + s3);
+      T sum = s0 + s1;
 #pragma unroll
       for (int off = PARTS / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
-      if (sk_part == 0) sk[sk_k] = sum;   // (the PARTS threads of a column are consecutive lanes)
+      if (sk_part == 0) sk[sk_k] = sum;
     }
     __syncthreads();
     const T sigma = sk[j];
-    if (!(sigma > (T)0)) continue;   // nothing below the diagonal: H_j = I (uniform)
-    const T alpha = rj[j];
-    const T xn = sqrt(alpha * alpha + sigma);
-    const T beta = (alpha >= (T)0) ? -xn : xn;
-    const T tau = (beta - alpha) / beta;
-    const T scale = (T)1 / (alpha - beta);
-    const T v = (t > j) ? aj * scale : (t == j ? (T)1 : (T)0);
-#pragma unroll
-    for (int k = 0; k < CP; ++k) {
-      if (k > j && k < c) {
-        const T wk = rj[k] + scale * sk[k];
-        a[k] -= tau * v * wk;
-      } else if (k == j) {
-        a[k] = (t == j) ? beta : (t > j ? (T)0 : a[k]);
+    if (sigma > (T)0) {   // otherwise nothing below the diagonal: H_j = I (uniform)
+      const T alpha = A[j * LP + j];
+      const T xn = sqrt(alpha * alpha + sigma);
+      const T beta = (alpha >= (T)0) ? -xn : xn;
+      const T tau = (beta - alpha) / beta;
+      const T scale = (T)1 / (alpha - beta);
+      if (t > j) {
+        const T tv = tau * scale * A[j * LP + t];
+        for (int k = j + 1; k < c; ++k) A[k * LP + t] -= tv * (A[k * LP + j] + scale * sk[k]);
+      }
+      __syncthreads();   // every thread has read row j before thread j updates it
+      if (t == j) {
+        for (int k = j + 1; k < c; ++k) A[k * LP + j] -= tau * (A[k * LP + j] + scale * sk[k]);
+        A[j * LP + j] = beta;
       }
     }
-    // (pr, sk and rj are rewritten only after the next column's first barrier, which every
-    // thread reaches after its reads above)
+    __syncthreads();
   }
   T* R = out + (int64_t)slot * c * c;
-  if (t < c) {
-#pragma unroll
-    for (int k = 0; k < CP; ++k)
-      if (k < c) R[(int64_t)t * c + k] = (k >= t && t < rows) ? a[k] : (T)0;
-  }
+  if (t < c)
+    for (int k = 0; k < c; ++k) R[(int64_t)t * c + k] = (k >= t && t < rows) ? A[k * LP + t] : (T)0;
 }
 
 }  // namespace

@@ -180,11 +180,14 @@ __device__ inline void load16(const T* p, T (&v)[N]) {
 // reads VW consecutive panel rows of column k = kc + g; element w of its p-th vector is row
 // 16 VW p + VW i + w, the A operand of row block q = VW p + w.  Output row rb of block q is tile
 // row 16 VW p + VW rb + w.
-constexpr int kSolveWaves = 4;   // waves per tile item; wave w takes every kSolveWaves-th reduction step
+// Waves per tile item; wave w takes every NW-th reduction step.  FP64 items keep one wave: their
+// accumulators already fill the register file.
+template <typename T> constexpr int solve_waves() { return sizeof(T) == 4 ? 4 : 1; }
 
 // Sum of the per-wave accumulators into wave 0 (fixed order w = 0, 1, ..., so deterministic).
-template <typename V4, int NQ>
+template <int NW, typename V4, int NQ>
 __device__ inline bool reduce_waves(V4 (&acc)[NQ], V4* red) {
+  if (NW == 1) return true;
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   if (w > 0) {
 #pragma unroll
@@ -193,14 +196,14 @@ __device__ inline bool reduce_waves(V4 (&acc)[NQ], V4* red) {
   __syncthreads();
   if (w > 0) return false;
 #pragma unroll
-  for (int v = 1; v < kSolveWaves; ++v)
+  for (int v = 1; v < NW; ++v)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] += red[((v - 1) * NQ + q) * 64 + lane];
   return true;
 }
 
 template <typename T, int M>
-__global__ void __launch_bounds__(64 * kSolveWaves) fwd_mfma_kernel(FactorDev D, const int32_t* __restrict__ items,
+__global__ void __launch_bounds__(64 * solve_waves<T>()) fwd_mfma_kernel(FactorDev D, const int32_t* __restrict__ items,
                                                       int64_t item_off, const T* __restrict__ panel,
                                                       const T* __restrict__ rhs, T* __restrict__ y,
                                                       T* __restrict__ uvec, T* __restrict__ part) {
@@ -209,7 +212,8 @@ __global__ void __launch_bounds__(64 * kSolveWaves) fwd_mfma_kernel(FactorDev D,
   constexpr int VW = 16 / sizeof(T);
   constexpr int NP = 4 / VW;
   constexpr int NCB = (M + 15) / 16;
-  __shared__ V4 red[(kSolveWaves - 1) * 4 * NCB * 64];
+  constexpr int NW = solve_waves<T>();
+  __shared__ V4 red[(NW > 1 ? NW - 1 : 1) * 4 * NCB * 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int i = lane % 16, g = lane / 16;
   const int* it = items + 5 * (item_off + blockIdx.x);
@@ -224,8 +228,9 @@ __global__ void __launch_bounds__(64 * kSolveWaves) fwd_mfma_kernel(FactorDev D,
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int kc = k0 + 4 * wave; kc < k1; kc += 4 * kSolveWaves) {
+  constexpr int UNR = 4;
+#pragma unroll UNR
+  for (int kc = k0 + 4 * wave; kc < k1; kc += 4 * NW) {
     const int k = kc + g;
     const bool kok = k < k1;
     T a[NP][VW];
@@ -251,7 +256,7 @@ __global__ void __launch_bounds__(64 * kSolveWaves) fwd_mfma_kernel(FactorDev D,
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[VW * p + w][c] = MF::op(a[p][w], b[c], acc[VW * p + w][c]);
   }
-  if (!reduce_waves(reinterpret_cast<V4(&)[4 * NCB]>(acc), red)) return;
+  if (!reduce_waves<NW>(reinterpret_cast<V4(&)[4 * NCB]>(acc), red)) return;
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -300,7 +305,7 @@ __global__ void __launch_bounds__(64 * kSolveWaves) fwd_mfma_kernel(FactorDev D,
 // Lane (i, g) reads VW consecutive k (k = kc + VW g + t) of panel column j0 + 16 jb + i; MFMA t
 // pairs them with z row kc + VW g + t, so the 4 VW values of k in a step are reduced in VW MFMAs.
 template <typename T, int M>
-__global__ void __launch_bounds__(64 * kSolveWaves) bwd_mfma_kernel(FactorDev D, const int32_t* __restrict__ items,
+__global__ void __launch_bounds__(64 * solve_waves<T>()) bwd_mfma_kernel(FactorDev D, const int32_t* __restrict__ items,
                                                       int64_t item_off, const T* __restrict__ panel,
                                                       const T* __restrict__ y, T* __restrict__ x, double* W,
                                                       int64_t ldw, int mw, T* __restrict__ part) {
@@ -308,7 +313,8 @@ __global__ void __launch_bounds__(64 * kSolveWaves) bwd_mfma_kernel(FactorDev D,
   typedef typename MF::v4 V4;
   constexpr int VW = 16 / sizeof(T);
   constexpr int NCB = (M + 15) / 16;
-  __shared__ V4 red[(kSolveWaves - 1) * 4 * NCB * 64];
+  constexpr int NW = solve_waves<T>();
+  __shared__ V4 red[(NW > 1 ? NW - 1 : 1) * 4 * NCB * 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int i = lane % 16, g = lane / 16;
   const int* it = items + 5 * (item_off + blockIdx.x);
@@ -324,8 +330,9 @@ __global__ void __launch_bounds__(64 * kSolveWaves) bwd_mfma_kernel(FactorDev D,
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
-#pragma unroll 2
-  for (int kc = k0 + 4 * VW * wave; kc < k1; kc += 4 * VW * kSolveWaves) {
+  constexpr int UNR = 2;
+#pragma unroll UNR
+  for (int kc = k0 + 4 * VW * wave; kc < k1; kc += 4 * VW * NW) {
     const int kk = kc + VW * g;
     T a[4][VW];
 #pragma unroll
@@ -364,7 +371,7 @@ __global__ void __launch_bounds__(64 * kSolveWaves) bwd_mfma_kernel(FactorDev D,
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[jb][c] = MF::op(a[jb][t], b[t][c], acc[jb][c]);
   }
-  if (!reduce_waves(reinterpret_cast<V4(&)[4 * NCB]>(acc), red)) return;
+  if (!reduce_waves<NW>(reinterpret_cast<V4(&)[4 * NCB]>(acc), red)) return;
 #pragma unroll
   for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
@@ -566,7 +573,7 @@ void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* pan
     const int64_t f0 = Sd.fwd_level_off[level], f1 = Sd.fwd_level_off[level + 1];
     if (f1 > f0) {
       if (use_mfma())
-        fwd_mfma_kernel<T, M><<<(unsigned)(f1 - f0), 64 * kSolveWaves, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y,
+        fwd_mfma_kernel<T, M><<<(unsigned)(f1 - f0), 64 * solve_waves<T>(), 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y,
                                                                              uvec, fpart);
       else
         fwd_gemm_kernel<T, M><<<(unsigned)(f1 - f0), NT, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);
@@ -577,7 +584,7 @@ void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* pan
     const int64_t b0 = Sd.bwd_level_off[level], b1 = Sd.bwd_level_off[level + 1];
     if (b1 > b0) {
       if (use_mfma())
-        bwd_mfma_kernel<T, M><<<(unsigned)(b1 - b0), 64 * kSolveWaves, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W,
+        bwd_mfma_kernel<T, M><<<(unsigned)(b1 - b0), 64 * solve_waves<T>(), 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W,
                                                                                ldw, mw, bpart);
       else
         bwd_gemm_kernel<T, M><<<(unsigned)(b1 - b0), NT, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W, ldw, mw,
