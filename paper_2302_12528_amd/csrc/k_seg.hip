@@ -317,7 +317,19 @@ __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* i
       const T scale = (T)1 / (alpha - beta);
       if (t > j) {
         const T tv = tau * scale * A[j * LP + t];
-        for (int k = j + 1; k < c; ++k) A[k * LP + t] -= tv * (A[k * LP + j] + scale * sk[k]);
+        // loads of 8 columns first, then the stores (the compiler cannot reorder them itself)
+        for (int k0 = j + 1; k0 < c; k0 += 8) {
+          T x[8], w[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u < c ? k0 + u : c - 1;
+            x[u] = A[k * LP + t];
+            w[u] = A[k * LP + j] + scale * sk[k];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (k0 + u < c) A[(k0 + u) * LP + t] = x[u] - tv * w[u];
+        }
       }
       __syncthreads();   // every thread has read row j before thread j updates it
       if (t == j) {

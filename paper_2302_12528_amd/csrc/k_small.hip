@@ -346,7 +346,14 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
         }
       }
       nrm = 1.0 / sqrt(nrm);
-      for (int i = 0; i < c; ++i) Z[i * lz + j] *= nrm;
+      for (int i0 = 0; i0 < c; i0 += 8) {
+        double zz[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) zz[u] = (i0 + u < c) ? Z[(i0 + u) * lz + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (i0 + u < c) Z[(i0 + u) * lz + j] = zz[u] * nrm;
+      }
     }
     __syncthreads();
     // modified Gram-Schmidt inside each cluster, in eigenvalue order: wave w takes the later
@@ -355,17 +362,30 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
       const int qe = cend[q];
       if (qe - q < 2) continue;   // uniform
       for (int r = q + 1 + wid; r < qe; r += 4) {
-        double dot = 0.0;
-        for (int i = lane; i < c; i += 64) dot += Z[i * lz + q] * Z[i * lz + r];
-        dot = wave_sum(dot);
-        for (int i = lane; i < c; i += 64) Z[i * lz + r] -= dot * Z[i * lz + q];
+        // a lane holds at most 3 rows (c <= 192): load them, reduce, then store
+        double zq[3], zr[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int i = lane + 64 * u;
+          zq[u] = (i < c) ? Z[i * lz + q] : 0.0;
+          zr[u] = (i < c) ? Z[i * lz + r] : 0.0;
+        }
+        const double dot = wave_sum((zq[0] * zr[0] + zq[1] * zr[1]) + zq[2] * zr[2]);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int i = lane + 64 * u;
+          if (i < c) Z[i * lz + r] = zr[u] - dot * zq[u];
+        }
       }
       __syncthreads();
       if (wid == 0) {
-        double nn = 0.0;
-        for (int i = lane; i < c; i += 64) nn += Z[i * lz + q + 1] * Z[i * lz + q + 1];
-        nn = 1.0 / sqrt(wave_sum(nn));
-        for (int i = lane; i < c; i += 64) Z[i * lz + q + 1] *= nn;
+        double z[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) z[u] = (lane + 64 * u < c) ? Z[(lane + 64 * u) * lz + q + 1] : 0.0;
+        const double nn = 1.0 / sqrt(wave_sum((z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]));
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (lane + 64 * u < c) Z[(lane + 64 * u) * lz + q + 1] = z[u] * nn;
       }
       __syncthreads();
     }
@@ -379,13 +399,36 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
       const double t = tau[k];
       if (t == 0.0) continue;
       const int nk = c - k - 1;
+      // a thread's rows of this column: at most ceil(191 / G) <= 192 / G; held in registers in
+      // chunks of 8 so that the loads are issued before the stores
       double sw = 0.0;
       if (j < nev)
-        for (int i = g; i < nk; i += G) sw += (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) * Z[(k + 1 + i) * lz + j];
+        for (int i0 = g; i0 < nk; i0 += 8 * G) {
+          double vv[8], zz[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * G;
+            vv[u] = (i < nk) ? (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) : 0.0;
+            zz[u] = (i < nk) ? Z[(k + 1 + i) * lz + j] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) sw += vv[u] * zz[u];
+        }
       for (int off = G / 2; off > 0; off >>= 1) sw += __shfl_xor(sw, off, 64);
       sw *= t;
       if (j < nev)
-        for (int i = g; i < nk; i += G) Z[(k + 1 + i) * lz + j] -= (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) * sw;
+        for (int i0 = g; i0 < nk; i0 += 8 * G) {
+          double vv[8], zz[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * G;
+            vv[u] = (i < nk) ? (i == 0 ? 1.0 : a[(k + 1 + i) * la + k]) : 0.0;
+            zz[u] = (i < nk) ? Z[(k + 1 + i) * lz + j] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (i0 + u * G < nk) Z[(k + 1 + i0 + u * G) * lz + j] = zz[u] - vv[u] * sw;
+        }
       __syncthreads();   // the next reflector reads rows another thread of the group wrote
     }
   }
@@ -472,19 +515,29 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
     __syncthreads();
     // modified Gram-Schmidt on the columns of W
     for (int j = 0; j < m; ++j) {
+      // a lane holds at most 3 rows (c <= 192): loads first, then stores
       if (wid == 0) {
-        double nn = 0.0;
-        for (int i = lane; i < c; i += 64) nn += w[i * lw + j] * w[i * lw + j];
-        nn = wave_sum(nn);
+        double z[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) z[u] = (lane + 64 * u < c) ? w[(lane + 64 * u) * lw + j] : 0.0;
+        const double nn = wave_sum((z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]);
         const double inv = (nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-        for (int i = lane; i < c; i += 64) w[i * lw + j] *= inv;
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (lane + 64 * u < c) w[(lane + 64 * u) * lw + j] = z[u] * inv;
       }
       __syncthreads();
+      double zj[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) zj[u] = (lane + 64 * u < c) ? w[(lane + 64 * u) * lw + j] : 0.0;
       for (int r = j + 1 + wid; r < m; r += 4) {
-        double dot = 0.0;
-        for (int i = lane; i < c; i += 64) dot += w[i * lw + j] * w[i * lw + r];
-        dot = wave_sum(dot);
-        for (int i = lane; i < c; i += 64) w[i * lw + r] -= dot * w[i * lw + j];
+        double zr[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) zr[u] = (lane + 64 * u < c) ? w[(lane + 64 * u) * lw + r] : 0.0;
+        const double dot = wave_sum((zj[0] * zr[0] + zj[1] * zr[1]) + zj[2] * zr[2]);
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (lane + 64 * u < c) w[(lane + 64 * u) * lw + r] = zr[u] - dot * zj[u];
       }
       __syncthreads();
     }
