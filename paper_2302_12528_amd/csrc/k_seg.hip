@@ -296,11 +296,17 @@ __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* i
       const T* cj = A + j * LP + sk_part * CP;
       const T* ck = A + sk_k * LP + sk_part * CP;
       const int base = sk_part * CP;
+      T x[CP], y[CP];
+#pragma unroll
+      for (int q = 0; q < CP; ++q) {
+        x[q] = cj[q];
+        y[q] = ck[q];
+      }
       T s0 = 0, s1 = 0;
 #pragma unroll
       for (int q = 0; q < CP; q += 2) {
-        if (base + q > j) s0 += cj[q] * ck[q];
-        if (base + q + 1 > j) s1 += cj[q + 1] * ck[q + 1];
+        s0 += (base + q > j) ? x[q] * y[q] : (T)0;
+        s1 += (base + q + 1 > j) ? x[q + 1] * y[q + 1] : (T)0;
       }
       T sum = s0 + s1;
 #pragma unroll
@@ -331,11 +337,10 @@ __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* i
             if (k0 + u < c) A[(k0 + u) * LP + t] = x[u] - tv * w[u];
         }
       }
-      __syncthreads();   // every thread has read row j before thread j updates it
-      if (t == j) {
-        for (int k = j + 1; k < c; ++k) A[k * LP + j] -= tau * (A[k * LP + j] + scale * sk[k]);
-        A[j * LP + j] = beta;
-      }
+      __syncthreads();   // every thread has read row j before it is updated
+      // row j itself (v_j = 1): thread k updates element (j, k)
+      if (t > j && t < c) A[t * LP + j] -= tau * (A[t * LP + j] + scale * sk[t]);
+      if (t == j) A[j * LP + j] = beta;
     }
     __syncthreads();
   }
