@@ -57,8 +57,8 @@ struct SegHost {
   std::vector<int64_t> tile_r0, chunk_r0;
 };
 
-// Default rows per reduction chunk: about 384 chunks over the union, within [256, 4096].
-int64_t default_chunk_rows(int64_t N) { return std::max<int64_t>(256, std::min<int64_t>(4096, N / 384)); }
+// Default rows per reduction chunk: about 512 chunks over the union (two per compute unit), within [256, 4096].
+int64_t default_chunk_rows(int64_t N) { return std::max<int64_t>(256, std::min<int64_t>(4096, N / 512)); }
 
 void build_segments(const std::vector<int64_t>& inst_off, int64_t rpc, SegHost& H) {
   H = SegHost();

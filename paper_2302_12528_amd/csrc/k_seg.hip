@@ -10,6 +10,7 @@
 //   trsm      Y_b U_b = X_b row by row (Algorithm 2 steps 2 and 4)
 //   tsqr      R factor of each X_b (Algorithm 2 step 1), Householder in T
 #include "common.hpp"
+#include "mfma.hpp"
 
 namespace lobpcg {
 
@@ -20,66 +21,70 @@ constexpr int kThreads = 256;
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
-// Gram partials over one chunk of rows (a 16 RT x 16 CT output tile).
+// Gram partials over one chunk of rows with FP64 matrix cores: the (32 RB) x (32 CB) output tile
+// is split 2 x 2 over the four waves, each wave RB x CB blocks of 16 x 16 accumulated by
+// v_mfma_f64_16x16x4f64 over 4 rows at a time.  Lane (i, g) = (l % 16, l / 16) reads row r + g,
+// columns 16 b + i, of X and Y directly (16 consecutive doubles per row and lane group).
 // ---------------------------------------------------------------------------
-template <int RT, int CT>
+template <int RB, int CB>
 __global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const double* __restrict__ X, int64_t ldx,
                                                                  const double* __restrict__ Y, int64_t ldy, int c1,
                                                                  int c2, int tiles_j, double* __restrict__ part) {
-  constexpr int T1 = 16 * RT, T2 = 16 * CT, KR = 16;
-  __shared__ double Xs[KR][T1 + 1];
-  __shared__ double Ys[KR][T2 + 1];
+  typedef Mfma<double> MF;
+  typedef MF::v4 V4;
+  constexpr int T1 = 32 * RB, T2 = 32 * CB;
   const int q = blockIdx.x;
   const int b = S.chunk_inst[q];
   if (!S.active[b]) return;
-  const int t = threadIdx.x;
-  const int tx = t % 16, ty = t / 16;
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int i = lane % 16, g = lane / 16;
   const int ti = blockIdx.y / tiles_j, tj = blockIdx.y % tiles_j;
-  const int i0 = ti * T1, j0 = tj * T2;
+  const int ci0 = ti * T1 + (w / 2) * 16 * RB;   // first X column of this wave
+  const int cj0 = tj * T2 + (w % 2) * 16 * CB;   // first Y column of this wave
   const int64_t rbeg = S.chunk_r0[q];
   const int64_t rend = rbeg + S.chunk_rows[q];
-  double acc[RT][CT];
+  V4 acc[RB][CB];
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+  for (int u = 0; u < RB; ++u)
 #pragma unroll
-    for (int j = 0; j < CT; ++j) acc[i][j] = 0.0;
-  for (int64_t r0 = rbeg; r0 < rend; r0 += KR) {
-    for (int e = t; e < KR * T1; e += kThreads) {
-      const int k = e / T1, c = e % T1;
-      const int64_t r = r0 + k;
-      Xs[k][c] = (r < rend && i0 + c < c1) ? X[r * ldx + i0 + c] : 0.0;
+    for (int v = 0; v < CB; ++v) acc[u][v] = V4{0, 0, 0, 0};
+  bool xc[RB], yc[CB];
+#pragma unroll
+  for (int u = 0; u < RB; ++u) xc[u] = (ci0 + 16 * u + i < c1);
+#pragma unroll
+  for (int v = 0; v < CB; ++v) yc[v] = (cj0 + 16 * v + i < c2);
+  const double* xp = X + ci0 + i;
+  const double* yp = Y + cj0 + i;
+  constexpr int U = 4;   // 4-row steps whose loads are issued together
+  for (int64_t r0 = rbeg; r0 < rend; r0 += 4 * U) {
+    double xa[U][RB], yb[U][CB];
+#pragma unroll
+    for (int s = 0; s < U; ++s) {
+      const int64_t r = r0 + 4 * s + g;
+      const bool rok = r < rend;
+#pragma unroll
+      for (int u = 0; u < RB; ++u) xa[s][u] = (rok && xc[u]) ? xp[r * ldx + 16 * u] : 0.0;
+#pragma unroll
+      for (int v = 0; v < CB; ++v) yb[s][v] = (rok && yc[v]) ? yp[r * ldy + 16 * v] : 0.0;
     }
-    for (int e = t; e < KR * T2; e += kThreads) {
-      const int k = e / T2, c = e % T2;
-      const int64_t r = r0 + k;
-      Ys[k][c] = (r < rend && j0 + c < c2) ? Y[r * ldy + j0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < KR; ++k) {
-      double a[RT], bv[CT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) a[i] = Xs[k][ty + 16 * i];
+    for (int s = 0; s < U; ++s)
 #pragma unroll
-      for (int j = 0; j < CT; ++j) bv[j] = Ys[k][tx + 16 * j];
+      for (int u = 0; u < RB; ++u)
 #pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int j = 0; j < CT; ++j) acc[i][j] = fma(a[i], bv[j], acc[i][j]);
-    }
-    __syncthreads();
+        for (int v = 0; v < CB; ++v) acc[u][v] = MF::op(xa[s][u], yb[s][v], acc[u][v]);
   }
   double* P = part + (int64_t)q * c1 * c2;
 #pragma unroll
-  for (int i = 0; i < RT; ++i) {
-    const int gi = i0 + ty + 16 * i;
-    if (gi >= c1) continue;
+  for (int u = 0; u < RB; ++u)
 #pragma unroll
-    for (int j = 0; j < CT; ++j) {
-      const int gj = j0 + tx + 16 * j;
-      if (gj < c2) P[gi * c2 + gj] = acc[i][j];
-    }
-  }
+    for (int v = 0; v < CB; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = ci0 + 16 * u + MF::drow(lane, e);
+        const int gj = cj0 + 16 * v + i;
+        if (gi < c1 && gj < c2) P[gi * c2 + gj] = acc[u][v][e];
+      }
 }
 
 // out_b[e] = sum over the chunks of instance b of part[chunk][e], in chunk order (four
@@ -101,14 +106,19 @@ __global__ void __launch_bounds__(256) sreduce_kernel(SegDev S, const double* __
 }
 
 // ---------------------------------------------------------------------------
-// Block update on one 64-row tile: Y = alpha X M_b + beta Y (64 x 64 output tile).
+// Block update on one 64-row tile: Y = alpha X M_b + beta Y (64 x 64 output tile).  X (64 rows x
+// 16 reduction columns) and M (16 x 64) are staged through LDS with coalesced loads; wave w
+// accumulates output rows 16 w .. 16 w + 15 over all four 16-column blocks with
+// v_mfma_f64_16x16x4f64.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const double* X, int64_t ldx,
                                                            const double* __restrict__ M, int64_t ldm, int64_t mstride,
                                                            double* Y, int64_t ldy, int K, int cols, double alpha,
                                                            double beta) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][64];
+  typedef Mfma<double> MF;
+  typedef MF::v4 V4;
+  __shared__ double As[16][65];   // As[k][row]
+  __shared__ double Bs[16][65];   // Bs[k][col]
   const int q = blockIdx.x;
   const int b = S.tile_inst[q];
   if (!S.active[b]) return;
@@ -116,55 +126,48 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const doubl
   const int rows = S.tile_rows[q];
   const double* Mb = M + (int64_t)b * mstride;
   const int t = threadIdx.x;
-  const int tx = t % 16, ty = t / 16;
+  const int lane = t % 64, w = t / 64;
+  const int i = lane % 16, g = lane / 16;
   const int c0 = blockIdx.y * 64;
-  double acc[4][4];
+  V4 acc[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  const int lr = t / 4, lk = (t % 4) * 4;
-  const int bk = t / 16, bc = (t % 16) * 4;
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = V4{0, 0, 0, 0};
+  const int lr = t / 4, lk = (t % 4) * 4;   // X loader: row lr, reduction columns lk .. lk + 3
+  const int bk = t / 16, bc = (t % 16) * 4; // M loader: reduction row bk, columns bc .. bc + 3
   for (int k0 = 0; k0 < K; k0 += 16) {
+    double xa[4], mb[4];
 #pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int k = k0 + lk + qq;
-      As[lk + qq][lr] = (lr < rows && k < K) ? X[(r0 + lr) * ldx + k] : 0.0;
-    }
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int k = k0 + bk;
-      const int cc = c0 + bc + qq;
-      Bs[bk][bc + qq] = (k < K && cc < cols) ? Mb[(int64_t)k * ldm + cc] : 0.0;
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + lk + u;
+      xa[u] = (lr < rows && k < K) ? X[(r0 + lr) * ldx + k] : 0.0;
+      const int kb = k0 + bk, cc = c0 + bc + u;
+      mb[u] = (kb < K && cc < cols) ? Mb[(int64_t)kb * ldm + cc] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      double a[4], bv[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = Bs[k][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bv[j], acc[i][j]);
+    for (int u = 0; u < 4; ++u) {
+      As[lk + u][lr] = xa[u];
+      Bs[bk][bc + u] = mb[u];
     }
     __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const double av = As[kk + g][16 * w + i];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = MF::op(av, Bs[kk + g][16 * cb + i], acc[cb]);
+    }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = ty + 16 * i;
-    if (r >= rows) continue;
+  for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cc = c0 + tx + 16 * j;
-      if (cc >= cols) continue;
-      double v = alpha * acc[i][j];
+    for (int e = 0; e < 4; ++e) {
+      const int r = 16 * w + MF::drow(lane, e);
+      const int cc = c0 + 16 * cb + i;
+      if (r >= rows || cc >= cols) continue;
+      double v = alpha * acc[cb][e];
       if (beta != 0.0) v = fma(beta, Y[(r0 + r) * ldy + cc], v);
       Y[(r0 + r) * ldy + cc] = v;
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -355,22 +358,20 @@ __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* i
 // host launchers
 // ---------------------------------------------------------------------------
 namespace {
-inline int gram_rt(int c) { return c <= 16 ? 1 : c <= 32 ? 2 : c <= 48 ? 3 : c <= 64 ? 4 : 6; }
+inline int gram_rt(int c) { return c <= 32 ? 1 : c <= 64 ? 2 : 3; }
 
-template <int RT, int CT>
+template <int RB, int CB>
 void sgram_launch(dim3 g, const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1, int c2,
                   int tj, double* part, hipStream_t st) {
-  sgram_partial_kernel<RT, CT><<<g, kThreads, 0, st>>>(S, X, ldx, Y, ldy, c1, c2, tj, part);
+  sgram_partial_kernel<RB, CB><<<g, kThreads, 0, st>>>(S, X, ldx, Y, ldy, c1, c2, tj, part);
 }
-template <int RT>
+template <int RB>
 void sgram_ct(int ct, dim3 g, const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1,
               int c2, int tj, double* part, hipStream_t st) {
   switch (ct) {
-    case 1: sgram_launch<RT, 1>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
-    case 2: sgram_launch<RT, 2>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
-    case 3: sgram_launch<RT, 3>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
-    case 4: sgram_launch<RT, 4>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
-    default: sgram_launch<RT, 6>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    case 1: sgram_launch<RB, 1>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    case 2: sgram_launch<RB, 2>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    default: sgram_launch<RB, 3>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
   }
 }
 }  // namespace
@@ -379,14 +380,12 @@ void launch_sgram(const SegDev& S, const double* X, int64_t ldx, const double* Y
                   double* G, int64_t gstride, double* part, hipStream_t st) {
   if (c1 <= 0 || c2 <= 0 || S.nchunks <= 0) return;
   const int rt = gram_rt(c1), ct = gram_rt(c2);
-  const int tj = cdiv(c2, 16 * ct);
-  dim3 g((unsigned)S.nchunks, cdiv(c1, 16 * rt) * tj);
+  const int tj = cdiv(c2, 32 * ct);
+  dim3 g((unsigned)S.nchunks, cdiv(c1, 32 * rt) * tj);
   switch (rt) {
     case 1: sgram_ct<1>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
     case 2: sgram_ct<2>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
-    case 3: sgram_ct<3>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
-    case 4: sgram_ct<4>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
-    default: sgram_ct<6>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
+    default: sgram_ct<3>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
   }
   const int len = c1 * c2;
   sreduce_kernel<<<dim3(cdiv(len, 64), S.B), 256, 0, st>>>(S, part, len, G, gstride);
