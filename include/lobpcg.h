@@ -78,8 +78,8 @@ typedef struct {
  * identical to the eager launches; the per-step GPU timings of lobpcg_info are then zero. */
 #define LOBPCG_FLAG_GRAPH 1
 /* LOBPCG_FLAG_AUTOTUNE: at setup, time the candidate launch shapes on this context's own
- * buffers and keep the fastest: the split-K chunk of the triangular-solve plan (128, 256,
- * 512 or 1024 reduction rows per tile item) and the rows per reduction chunk of the
+ * buffers and keep the fastest: the split-K chunk of the triangular-solve plan (256, 1024,
+ * 4096 reduction rows per tile item, or no split) and the rows per reduction chunk of the
  * instance-segmented Gram and norm kernels (512 to 8192).  If the environment variable
  * LOBPCG_TUNE_CACHE names a file, results are appended to it keyed by device architecture
  * and problem structure, and later setups with the same key read them instead of timing.

@@ -50,6 +50,10 @@ double now_s() {
 
 int pad_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64; }
 
+// Split-K chunk of the triangular-solve plan that never splits: every output tile is one
+// workgroup over its whole reduction range (its four waves split that range between them).
+constexpr int kNoSplit = 1 << 24;
+
 // Host side of an instance segmentation.
 struct SegHost {
   std::vector<int64_t> inst_off;
@@ -189,7 +193,7 @@ struct lobpcg_ctx_s {
   hipEvent_t ev_order = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // tuning: split-K chunk of the triangular solves, rows per reduction chunk, how they were chosen
-  int kchunk = 256;
+  int kchunk = kNoSplit;
   int64_t chunk_rows = 0;
   int tuned = 0;   // 0 defaults, 1 measured at setup, 2 read from the cache file
   int64_t gpart_bytes = 0, fpart_bytes = 0, bpart_bytes = 0;
@@ -278,7 +282,8 @@ lobpcg_status install_solve_plan(lobpcg_ctx c) {
   C.SD.fwd_fin_level_off = C.SP.fwd_fin_level_off.data();
   C.SD.bwd_level_off = C.SP.bwd_level_off.data();
   C.SD.bwd_fin_level_off = C.SP.bwd_fin_level_off.data();
-  C.SD.ownrow_level_off = C.FP.ownrow_level_off.data();
+  ST_TRY(upload_const(c, C.SD.gather_items, C.SP.gather_items));
+  C.SD.gather_level_off = C.SP.gather_level_off.data();
   return LOBPCG_OK;
 }
 
@@ -535,7 +540,7 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
     return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
   }
   build_factor_plan(C.S, C.FP);
-  build_solve_plan(C.S, 64, 256, C.SP);
+  build_solve_plan(C.S, 64, kNoSplit, C.SP);
   std::vector<int32_t> prow, pcol, vmap, apos;
   if (!C.dense) {
     permute_pattern(C.S, rowptr, colind, prow, pcol, vmap);
@@ -587,7 +592,6 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   SETUP_TRY(upload(c, D.lcopy_off, S.lcopy_off));
   SETUP_TRY(upload(c, D.asm_items, C.FP.asm_items));
   SETUP_TRY(upload(c, D.tasks, C.FP.tasks));
-  SETUP_TRY(upload(c, D.ownrow_items, C.FP.ownrow_items));
   SETUP_TRY(install_solve_plan(c));
   SETUP_TRY(upload(c, C.d_perm, S.perm));
   SETUP_TRY(upload(c, C.d_iperm, S.iperm));
@@ -825,7 +829,7 @@ lobpcg_status autotune(lobpcg_ctx c) {
   launch_gaussian_fill(C.ASb[1], C.n, m3, m3, 0x7a11full, C.st);
   float best = 1e30f;
   int best_kc = C.kchunk;
-  for (int cand : {128, 256, 512, 1024}) {
+  for (int cand : {256, 1024, 4096, kNoSplit}) {
     ST_TRY(apply_kchunk(c, cand));
     const float t = time_launches(c, [&] { precond(c, C.Sb[1], m3); }, 3);
     ST_TRY(check_launch("autotune preconditioner"));
@@ -1377,7 +1381,7 @@ lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t
     FactorPlan F;
     SolvePlan P;
     build_factor_plan(S, F);
-    build_solve_plan(S, 64, 256, P);
+    build_solve_plan(S, 64, kNoSplit, P);
     std::vector<int32_t> prow, pcol, vmap, apos;
     if (!dense) {
       permute_pattern(S, A->rowptr, A->colind, prow, pcol, vmap);

@@ -84,7 +84,7 @@ struct FactorDev {
   int64_t* panel_off; int64_t* upd_off; int64_t* uvec_off; int64_t* dinv_off; int64_t* lcopy_off;
   int32_t* prow; int32_t* pcol; int32_t* apos; double* aval;   // permuted A (CSR)
   const double* dense; int64_t ld_dense; int is_dense; int max_nr;
-  int32_t* asm_items; int32_t* tasks; int32_t* ownrow_items;
+  int32_t* asm_items; int32_t* tasks;
 };
 template <typename T>
 void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_off, int count,
@@ -94,8 +94,9 @@ void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_of
 // ---- supernodal triangular solves (k_trisolve.hip) ----
 struct SolveDev {
   const int32_t* fwd_items; const int32_t* fwd_fin; const int32_t* bwd_items; const int32_t* bwd_fin;  // device
+  const int32_t* gather_items;                                                                          // device
   const int64_t* fwd_level_off; const int64_t* fwd_fin_level_off;                                       // host
-  const int64_t* bwd_level_off; const int64_t* bwd_fin_level_off; const int64_t* ownrow_level_off;      // host
+  const int64_t* bwd_level_off; const int64_t* bwd_fin_level_off; const int64_t* gather_level_off;      // host
 };
 // Both sweeps: rhs (T, n x M, permuted, overwritten by the forward assembly) -> y -> x, and W (FP64, n x mw,
 // ld ldw) = working(x).  fpart / bpart: partial tiles (slots x 64 x M).

@@ -8,14 +8,12 @@
 //             subtracted from the rows below (passed up the tree in a
 //             per-supernode update vector, pulled by the parent; no atomics);
 //   backward: x_s = P_s^T [y_s; -x_below] = inv(L11)^T (y_s - L21^T x_below).
-// Each level is a batch of independent tile products: an output tile of 64
-// rows x M right-hand sides over a chunk of the reduction dimension.  Tiles
-// whose reduction is split write partial tiles that a finalize pass sums in a
-// fixed order.  P is streamed through LDS with the next stage prefetched into
-// registers while the current one is consumed; each thread owns a 4 x CT
-// register tile.
-#include <cstdlib>
-
+// Per level, a gather pass first adds the children's update vectors to the own
+// rows of the right-hand side and passes them through to the supernode's own
+// update vector; then every output tile (64 rows x M right-hand sides) is one
+// workgroup that streams its panel block into matrix-core products.  A tile whose
+// reduction range is split over several items writes partial tiles that a
+// finalize pass sums in a fixed order.
 #include "common.hpp"
 #include "mfma.hpp"
 #include "symbolic.hpp"
@@ -26,134 +24,28 @@ namespace {
 
 constexpr int TR = 64;   // output tile rows
 
-template <int M> struct Shape;
-template <> struct Shape<8>  { static constexpr int CT = 2; };
-template <> struct Shape<16> { static constexpr int CT = 4; };
-template <> struct Shape<32> { static constexpr int CT = 4; };
-template <> struct Shape<64> { static constexpr int CT = 4; };
-
-template <int M> constexpr int threads_for() { return (M / Shape<M>::CT) * (TR / 4); }
-
+// Forward gather, one (supernode s, row r) item per 64 lanes (lane = right-hand side): own rows of
+// a supernode with children get the children's contributions added to the right-hand side; below
+// rows get the update vector initialised with them (zero for a leaf).
 template <typename T>
-__global__ void __launch_bounds__(256) fwd_assemble_kernel(FactorDev D, int64_t item_off, int64_t count, T* rhs,
-                                                           const T* __restrict__ uvec, int M) {
+__global__ void __launch_bounds__(256) fwd_gather_kernel(FactorDev D, const int32_t* __restrict__ items,
+                                                         int64_t item_off, int64_t count, T* rhs, T* uvec, int M) {
   const int lane = threadIdx.x % 64;
   const int64_t item = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (item >= count || lane >= M) return;
-  const int s = D.ownrow_items[2 * (item_off + item)];
-  const int r = D.ownrow_items[2 * (item_off + item) + 1];
-  T v = rhs[(int64_t)(D.begin[s] + r) * M + lane];
+  const int s = items[2 * (item_off + item)];
+  const int r = items[2 * (item_off + item) + 1];
+  const int nc = D.nc[s];
+  T v = 0;
   for (int q = D.child_ptr[s]; q < D.child_ptr[s + 1]; ++q) {
     const int c = D.child_list[q];
     const int jr = D.invmap[D.inv_off[c] + r];
     if (jr >= 0) v += uvec[(D.uvec_off[c] + jr) * M + lane];
   }
-  rhs[(int64_t)(D.begin[s] + r) * M + lane] = v;
-}
-
-// Forward epilogue for one output row of supernode s: own rows -> y, below rows -> update vector.
-template <typename T, int CT>
-__device__ inline void fwd_store(const FactorDev& D, int s, int row, int col0, const T* acc, T* y, T* uvec, int M) {
-  const int nc = D.nc[s];
-  if (row < nc) {
-#pragma unroll
-    for (int j = 0; j < CT; ++j) y[(int64_t)(D.begin[s] + row) * M + col0 + j] = acc[j];
-    return;
-  }
-  T pass[CT];
-#pragma unroll
-  for (int j = 0; j < CT; ++j) pass[j] = 0;
-  for (int q = D.child_ptr[s]; q < D.child_ptr[s + 1]; ++q) {
-    const int c = D.child_list[q];
-    const int jr = D.invmap[D.inv_off[c] + row];
-    if (jr >= 0)
-#pragma unroll
-      for (int j = 0; j < CT; ++j) pass[j] += uvec[(D.uvec_off[c] + jr) * M + col0 + j];
-  }
-#pragma unroll
-  for (int j = 0; j < CT; ++j) uvec[(D.uvec_off[s] + row - nc) * M + col0 + j] = pass[j] - acc[j];
-}
-
-// out tile (64 x M) = P_s[r0:r0+64, k0:k1] * rhs[begin+k0 : begin+k1, :]
-template <typename T, int M>
-__global__ void __launch_bounds__(threads_for<M>()) fwd_gemm_kernel(FactorDev D, const int32_t* __restrict__ items,
-                                                                    int64_t item_off, const T* __restrict__ panel,
-                                                                    const T* __restrict__ rhs, T* __restrict__ y,
-                                                                    T* __restrict__ uvec, T* __restrict__ part) {
-  constexpr int CT = Shape<M>::CT, NCG = M / CT, NT = threads_for<M>();
-  constexpr int KC = 32;
-  constexpr int PL = KC * TR / NT;   // P values per thread per stage
-  constexpr int BL = KC * M / NT;    // rhs values per thread per stage
-  __shared__ T Ps[KC][TR + 1];
-  __shared__ T Bs[KC][M];
-  const int tid = threadIdx.x;
-  const int* it = items + 5 * (item_off + blockIdx.x);
-  const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
-  const int begin = D.begin[s], nr = D.nr[s];
-  const int64_t poff = D.panel_off[s], ldp = panel_ld(nr);
-  const int r0 = tile * TR;
-  const int h = min(TR, nr - r0);
-  const int cg = tid % NCG, rg = tid / NCG;
-  T acc[4][CT];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < CT; ++j) acc[i][j] = 0;
-  T pr[PL], br[BL];
-  auto load = [&](int kc) {
-#pragma unroll
-    for (int q = 0; q < PL; ++q) {
-      const int e = tid + NT * q;
-      const int r = e % TR, kk = e / TR;
-      pr[q] = (r < h && kc + kk < k1) ? panel[poff + (int64_t)(kc + kk) * ldp + r0 + r] : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < BL; ++q) {
-      const int e = tid + NT * q;
-      const int kk = e / M, j = e % M;
-      br[q] = (kc + kk < k1) ? rhs[(int64_t)(begin + kc + kk) * M + j] : (T)0;
-    }
-  };
-  load(k0);
-  for (int kc = k0; kc < k1; kc += KC) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PL; ++q) {
-      const int e = tid + NT * q;
-      Ps[e / TR][e % TR] = pr[q];
-    }
-#pragma unroll
-    for (int q = 0; q < BL; ++q) {
-      const int e = tid + NT * q;
-      Bs[e / M][e % M] = br[q];
-    }
-    __syncthreads();
-    if (kc + KC < k1) load(kc + KC);
-#pragma unroll 8
-    for (int k = 0; k < KC; ++k) {
-      T a[4], b[CT];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = Ps[k][rg + 16 * i];
-#pragma unroll
-      for (int j = 0; j < CT; ++j) b[j] = Bs[k][cg * CT + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < CT; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int rr = rg + 16 * i;
-    if (rr >= h) continue;
-    if (slot < 0) {
-      fwd_store<T, CT>(D, s, r0 + rr, cg * CT, acc[i], y, uvec, M);
-    } else {
-      T* dst = part + ((int64_t)slot * TR + rr) * M + cg * CT;
-#pragma unroll
-      for (int j = 0; j < CT; ++j) dst[j] = acc[i][j];
-    }
-  }
+  if (r < nc)
+    rhs[(int64_t)(D.begin[s] + r) * M + lane] += v;
+  else
+    uvec[(D.uvec_off[s] + r - nc) * M + lane] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -279,23 +171,13 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) fwd_mfma_kernel(FactorD
             if (col < M) y[(int64_t)(begin + row) * M + col] = acc[VW * p + w][c][v];
           }
         } else {
-          T pass[NCB];
-#pragma unroll
-          for (int c = 0; c < NCB; ++c) pass[c] = 0;
-          for (int q = D.child_ptr[s]; q < D.child_ptr[s + 1]; ++q) {
-            const int ch = D.child_list[q];
-            const int jr = D.invmap[D.inv_off[ch] + row];
-            if (jr < 0) continue;
-#pragma unroll
-            for (int c = 0; c < NCB; ++c) {
-              const int col = 16 * c + i;
-              if (col < M) pass[c] += uvec[(D.uvec_off[ch] + jr) * M + col];
-            }
-          }
+          // the gather pass initialised this row of the update vector with the children's
+          // contributions passed through; subtract d = L21 y_s
+          T* u = uvec + (D.uvec_off[s] + row - nc) * M;
 #pragma unroll
           for (int c = 0; c < NCB; ++c) {
             const int col = 16 * c + i;
-            if (col < M) uvec[(D.uvec_off[s] + row - nc) * M + col] = pass[c] - acc[VW * p + w][c][v];
+            if (col < M) u[col] -= acc[VW * p + w][c][v];
           }
         }
       }
@@ -394,153 +276,45 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) bwd_mfma_kernel(FactorD
     }
 }
 
+
+// Sum of a split tile's partial tiles in slot order, then the same epilogue as an unsplit item.
 template <typename T, int M>
-__global__ void __launch_bounds__(threads_for<M>()) fwd_fin_kernel(FactorDev D, const int32_t* __restrict__ fin,
-                                                                   int64_t fin_off, const T* __restrict__ part,
-                                                                   T* __restrict__ y, T* __restrict__ uvec) {
-  constexpr int CT = Shape<M>::CT, NCG = M / CT;
+__global__ void __launch_bounds__(256) fwd_fin_kernel(FactorDev D, const int32_t* __restrict__ fin, int64_t fin_off,
+                                                      const T* __restrict__ part, T* __restrict__ y,
+                                                      T* __restrict__ uvec) {
   const int* f = fin + 4 * (fin_off + blockIdx.x);
   const int s = f[0], tile = f[1], slot0 = f[2], nch = f[3];
   const int r0 = tile * TR;
   const int h = min(TR, D.nr[s] - r0);
-  const int cg = threadIdx.x % NCG, rg = threadIdx.x / NCG;
-  for (int i = 0; i < 4; ++i) {
-    const int rr = rg + 16 * i;
-    if (rr >= h) continue;
-    T acc[CT];
-#pragma unroll
-    for (int j = 0; j < CT; ++j) acc[j] = 0;
-    for (int q = 0; q < nch; ++q) {
-      const T* src = part + ((int64_t)(slot0 + q) * TR + rr) * M + cg * CT;
-#pragma unroll
-      for (int j = 0; j < CT; ++j) acc[j] += src[j];
-    }
-    fwd_store<T, CT>(D, s, r0 + rr, cg * CT, acc, y, uvec, M);
-  }
-}
-
-// out tile (64 own columns x M) = P_s[k0:k1, j0:j0+64]^T z[k0:k1, :],  z = [y_s; -x_below]
-template <typename T, int M>
-__global__ void __launch_bounds__(threads_for<M>()) bwd_gemm_kernel(FactorDev D, const int32_t* __restrict__ items,
-                                                                    int64_t item_off, const T* __restrict__ panel,
-                                                                    const T* __restrict__ y, T* __restrict__ x,
-                                                                    double* W, int64_t ldw, int mw,
-                                                                    T* __restrict__ part) {
-  constexpr int CT = Shape<M>::CT, NCG = M / CT, NT = threads_for<M>();
-  constexpr int KC = 64;
-  constexpr int PL = KC * TR / NT;
-  constexpr int BL = KC * M / NT;
-  __shared__ T Ps[KC][TR + 1];
-  __shared__ T Zs[KC][M];
-  const int tid = threadIdx.x;
-  const int* it = items + 5 * (item_off + blockIdx.x);
-  const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
-  const int begin = D.begin[s], nc = D.nc[s], nr = D.nr[s];
-  const int64_t poff = D.panel_off[s], ldp = panel_ld(nr);
-  const int64_t roff = D.row_off[s];
-  const int j0 = tile * TR;
-  const int h = min(TR, nc - j0);
-  const int cg = tid % NCG, rg = tid / NCG;
-  T acc[4][CT];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < CT; ++j) acc[i][j] = 0;
-  T pr[PL], zr[BL];
-  auto load = [&](int kc) {
-#pragma unroll
-    for (int q = 0; q < PL; ++q) {
-      const int e = tid + NT * q;
-      const int kk = e % KC, jj = e / KC;
-      pr[q] = (jj < h && kc + kk < k1) ? panel[poff + (int64_t)(j0 + jj) * ldp + kc + kk] : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < BL; ++q) {
-      const int e = tid + NT * q;
-      const int kk = e / M, j = e % M;
-      const int r = kc + kk;
-      T v = 0;
-      if (r < k1) v = (r < nc) ? y[(int64_t)(begin + r) * M + j] : -x[(int64_t)D.rows[roff + r] * M + j];
-      zr[q] = v;
-    }
-  };
-  load(k0);
-  for (int kc = k0; kc < k1; kc += KC) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PL; ++q) {
-      const int e = tid + NT * q;
-      Ps[e % KC][e / KC] = pr[q];
-    }
-#pragma unroll
-    for (int q = 0; q < BL; ++q) {
-      const int e = tid + NT * q;
-      Zs[e / M][e % M] = zr[q];
-    }
-    __syncthreads();
-    if (kc + KC < k1) load(kc + KC);
-#pragma unroll 8
-    for (int k = 0; k < KC; ++k) {
-      T a[4], b[CT];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = Ps[k][rg + 16 * i];
-#pragma unroll
-      for (int j = 0; j < CT; ++j) b[j] = Zs[k][cg * CT + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < CT; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int jj = rg + 16 * i;
-    if (jj >= h) continue;
-    if (slot < 0) {
-      const int64_t row = begin + j0 + jj;
-#pragma unroll
-      for (int j = 0; j < CT; ++j) {
-        const int col = cg * CT + j;
-        x[row * M + col] = acc[i][j];
-        if (W && col < mw) W[row * ldw + col] = (double)acc[i][j];
-      }
-    } else {
-      T* dst = part + ((int64_t)slot * TR + jj) * M + cg * CT;
-#pragma unroll
-      for (int j = 0; j < CT; ++j) dst[j] = acc[i][j];
-    }
+  const int nc = D.nc[s], begin = D.begin[s];
+  for (int e = threadIdx.x; e < h * M; e += 256) {
+    const int rr = e / M, col = e % M;
+    T acc = 0;
+    for (int q = 0; q < nch; ++q) acc += part[((int64_t)(slot0 + q) * TR + rr) * M + col];
+    const int row = r0 + rr;
+    if (row < nc)
+      y[(int64_t)(begin + row) * M + col] = acc;
+    else
+      uvec[(D.uvec_off[s] + row - nc) * M + col] -= acc;
   }
 }
 
 template <typename T, int M>
-__global__ void __launch_bounds__(threads_for<M>()) bwd_fin_kernel(FactorDev D, const int32_t* __restrict__ fin,
-                                                                   int64_t fin_off, const T* __restrict__ part,
-                                                                   T* __restrict__ x, double* W, int64_t ldw,
-                                                                   int mw) {
-  constexpr int CT = Shape<M>::CT, NCG = M / CT;
+__global__ void __launch_bounds__(256) bwd_fin_kernel(FactorDev D, const int32_t* __restrict__ fin, int64_t fin_off,
+                                                      const T* __restrict__ part, T* __restrict__ x, double* W,
+                                                      int64_t ldw, int mw) {
   const int* f = fin + 4 * (fin_off + blockIdx.x);
   const int s = f[0], tile = f[1], slot0 = f[2], nch = f[3];
   const int j0 = tile * TR;
   const int h = min(TR, D.nc[s] - j0);
-  const int cg = threadIdx.x % NCG, rg = threadIdx.x / NCG;
-  for (int i = 0; i < 4; ++i) {
-    const int jj = rg + 16 * i;
-    if (jj >= h) continue;
-    T acc[CT];
-#pragma unroll
-    for (int j = 0; j < CT; ++j) acc[j] = 0;
-    for (int q = 0; q < nch; ++q) {
-      const T* src = part + ((int64_t)(slot0 + q) * TR + jj) * M + cg * CT;
-#pragma unroll
-      for (int j = 0; j < CT; ++j) acc[j] += src[j];
-    }
-    const int64_t row = D.begin[s] + j0 + jj;
-#pragma unroll
-    for (int j = 0; j < CT; ++j) {
-      const int col = cg * CT + j;
-      x[row * M + col] = acc[j];
-      if (W && col < mw) W[row * ldw + col] = (double)acc[j];
-    }
+  const int begin = D.begin[s];
+  for (int e = threadIdx.x; e < h * M; e += 256) {
+    const int jj = e / M, col = e % M;
+    T acc = 0;
+    for (int q = 0; q < nch; ++q) acc += part[((int64_t)(slot0 + q) * TR + jj) * M + col];
+    const int64_t row = begin + j0 + jj;
+    x[row * M + col] = acc;
+    if (W && col < mw) W[row * ldw + col] = (double)acc;
   }
 }
 
@@ -554,44 +328,27 @@ __global__ void cast_to_kernel(const double* __restrict__ src, int64_t lds, T* _
   dst[e] = (j < m) ? (T)src[i * lds + j] : (T)0;
 }
 
-// Development switch between the matrix-core and the vector-ALU tile products.
-inline bool use_mfma() {
-  static const bool on = [] {
-    const char* e = getenv("LOBPCG_TRISOLVE_VALU");
-    return !(e && e[0] == '1');
-  }();
-  return on;
-}
 
 template <typename T, int M>
 void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* panel, T* rhs, T* y, T* x, T* uvec,
                  T* fpart, T* bpart, double* W, int64_t ldw, int mw, bool forward, hipStream_t st) {
-  constexpr int NT = threads_for<M>();
+  constexpr unsigned NT = 64 * solve_waves<T>();
   if (forward) {
-    const int64_t a0 = Sd.ownrow_level_off[level], a1 = Sd.ownrow_level_off[level + 1];
-    if (a1 > a0) fwd_assemble_kernel<T><<<(unsigned)((a1 - a0 + 3) / 4), 256, 0, st>>>(D, a0, a1 - a0, rhs, uvec, M);
+    const int64_t a0 = Sd.gather_level_off[level], a1 = Sd.gather_level_off[level + 1];
+    if (a1 > a0)
+      fwd_gather_kernel<T><<<(unsigned)((a1 - a0 + 3) / 4), 256, 0, st>>>(D, Sd.gather_items, a0, a1 - a0, rhs, uvec,
+                                                                          M);
     const int64_t f0 = Sd.fwd_level_off[level], f1 = Sd.fwd_level_off[level + 1];
-    if (f1 > f0) {
-      if (use_mfma())
-        fwd_mfma_kernel<T, M><<<(unsigned)(f1 - f0), 64 * solve_waves<T>(), 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y,
-                                                                             uvec, fpart);
-      else
-        fwd_gemm_kernel<T, M><<<(unsigned)(f1 - f0), NT, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);
-    }
+    if (f1 > f0)
+      fwd_mfma_kernel<T, M><<<(unsigned)(f1 - f0), NT, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);
     const int64_t g0 = Sd.fwd_fin_level_off[level], g1 = Sd.fwd_fin_level_off[level + 1];
-    if (g1 > g0) fwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), NT, 0, st>>>(D, Sd.fwd_fin, g0, fpart, y, uvec);
+    if (g1 > g0) fwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), 256, 0, st>>>(D, Sd.fwd_fin, g0, fpart, y, uvec);
   } else {
     const int64_t b0 = Sd.bwd_level_off[level], b1 = Sd.bwd_level_off[level + 1];
-    if (b1 > b0) {
-      if (use_mfma())
-        bwd_mfma_kernel<T, M><<<(unsigned)(b1 - b0), 64 * solve_waves<T>(), 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W,
-                                                                               ldw, mw, bpart);
-      else
-        bwd_gemm_kernel<T, M><<<(unsigned)(b1 - b0), NT, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W, ldw, mw,
-                                                                  bpart);
-    }
+    if (b1 > b0)
+      bwd_mfma_kernel<T, M><<<(unsigned)(b1 - b0), NT, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W, ldw, mw, bpart);
     const int64_t g0 = Sd.bwd_fin_level_off[level], g1 = Sd.bwd_fin_level_off[level + 1];
-    if (g1 > g0) bwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), NT, 0, st>>>(D, Sd.bwd_fin, g0, bpart, x, W, ldw, mw);
+    if (g1 > g0) bwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), 256, 0, st>>>(D, Sd.bwd_fin, g0, bpart, x, W, ldw, mw);
   }
 }
 

@@ -392,17 +392,13 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
   };
   auto ntiles = [](int x) { return (x + kTile - 1) / kTile; };
   P.asm_level_off.assign(S.nlevels + 1, 0);
-  P.ownrow_level_off.assign(S.nlevels + 1, 0);
   for (int l = 0; l < S.nlevels; ++l) {
     const int32_t q0 = S.level_ptr[l], q1 = S.level_ptr[l + 1];
     for (int32_t q = q0; q < q1; ++q) {
       int s = S.level_sn[q];
       for (int t = 0; t < S.nr[s]; ++t) { P.asm_items.push_back(s); P.asm_items.push_back(t); }
-      if (S.child_ptr[s + 1] > S.child_ptr[s])
-        for (int t = 0; t < S.nc[s]; ++t) { P.ownrow_items.push_back(s); P.ownrow_items.push_back(t); }
     }
     P.asm_level_off[l + 1] = (int64_t)P.asm_items.size() / 2;
-    P.ownrow_level_off[l + 1] = (int64_t)P.ownrow_items.size() / 2;
     int maxnp = 0;
     for (int32_t q = q0; q < q1; ++q) maxnp = std::max(maxnp, ntiles(S.nc[S.level_sn[q]]));
     auto begin_step = [&](int kind) {
@@ -481,6 +477,7 @@ void build_solve_plan(const Symbolic& S, int rpt, int kchunk, SolvePlan& P) {
   P = SolvePlan();
   P.rows_per_tile = rpt;
   P.kchunk = kchunk;
+  P.gather_level_off.assign(S.nlevels + 1, 0);
   P.fwd_level_off.assign(S.nlevels + 1, 0);
   P.bwd_level_off.assign(S.nlevels + 1, 0);
   P.fwd_fin_level_off.assign(S.nlevels + 1, 0);
@@ -503,6 +500,11 @@ void build_solve_plan(const Symbolic& S, int rpt, int kchunk, SolvePlan& P) {
     for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
       const int s = S.level_sn[q];
       const int nc = S.nc[s], nr = S.nr[s];
+      const bool parent = S.child_ptr[s + 1] > S.child_ptr[s];
+      for (int r = parent ? 0 : nc; r < nr; ++r) {
+        P.gather_items.push_back(s);
+        P.gather_items.push_back(r);
+      }
       for (int t = 0; t < (nr + rpt - 1) / rpt; ++t) {
         const int r0 = t * rpt;
         const int kmax = (r0 < nc) ? std::min(nc, r0 + rpt) : nc;
@@ -510,6 +512,7 @@ void build_solve_plan(const Symbolic& S, int rpt, int kchunk, SolvePlan& P) {
       }
       for (int t = 0; t < (nc + rpt - 1) / rpt; ++t) emit(P.bwd_items, P.bwd_fin, P.bwd_slots, s, t, t * rpt, nr);
     }
+    P.gather_level_off[l + 1] = (int64_t)P.gather_items.size() / 2;
     P.fwd_level_off[l + 1] = (int64_t)P.fwd_items.size() / 5;
     P.bwd_level_off[l + 1] = (int64_t)P.bwd_items.size() / 5;
     P.fwd_fin_level_off[l + 1] = (int64_t)P.fwd_fin.size() / 4;
@@ -544,6 +547,11 @@ std::string verify_solve_plan(const Symbolic& S, const SolvePlan& P) {
     }
     return "";
   };
+  for (size_t q = 0; q < P.gather_items.size(); q += 2) {
+    const int s = P.gather_items[q], r = P.gather_items[q + 1];
+    if (s < 0 || s >= ns || r < 0 || r >= S.nr[s]) return "gather item";
+    if (r < S.nc[s] && S.child_ptr[s + 1] == S.child_ptr[s]) return "gather item on a leaf's own row";
+  }
   {
     std::string e = check_items(P.fwd_items, P.fwd_fin, P.fwd_slots, true);
     if (!e.empty()) return "forward " + e;
@@ -625,10 +633,6 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
   for (size_t q = 0; q < F.asm_items.size(); q += 2) {
     const int s = F.asm_items[q], t = F.asm_items[q + 1];
     if (s < 0 || s >= ns || t < 0 || t >= S.nr[s]) return "assembly item";
-  }
-  for (size_t q = 0; q < F.ownrow_items.size(); q += 2) {
-    const int s = F.ownrow_items[q], r = F.ownrow_items[q + 1];
-    if (s < 0 || s >= ns || r < 0 || r >= S.nc[s]) return "own-row item";
   }
   {
     const std::string e = verify_solve_plan(S, P);

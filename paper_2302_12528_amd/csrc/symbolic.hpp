@@ -75,8 +75,6 @@ struct FactorPlan {
   std::vector<Step> steps;           // in execution order
   std::vector<int32_t> asm_items;    // 2 ints (s, t) per assembly work item, grouped per level
   std::vector<int64_t> asm_level_off;  // nlevels+1
-  std::vector<int32_t> ownrow_items;   // 2 ints (s, r) per own row (forward assembly), per level
-  std::vector<int64_t> ownrow_level_off;
 };
 enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6 };
 void build_factor_plan(const Symbolic& S, FactorPlan& plan);
@@ -88,6 +86,9 @@ void build_factor_plan(const Symbolic& S, FactorPlan& plan);
 struct SolvePlan {
   int rows_per_tile = 64;
   int kchunk = 256;
+  // forward gather: (s, r) for every below row of every supernode and every own row of a
+  // supernode with children, per level
+  std::vector<int32_t> gather_items; std::vector<int64_t> gather_level_off;
   std::vector<int32_t> fwd_items;  std::vector<int64_t> fwd_level_off;   // 5 ints: s, tile, k0, k1, slot
   std::vector<int32_t> fwd_fin;    std::vector<int64_t> fwd_fin_level_off; // 4 ints: s, tile, slot0, nchunks
   std::vector<int32_t> bwd_items;  std::vector<int64_t> bwd_level_off;

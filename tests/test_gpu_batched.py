@@ -114,7 +114,7 @@ def test_autotune_and_cache(torch_cuda, tmp_path, monkeypatch):
     t1 = bs.tuning()
     print(f"tuned: {t1}", flush=True)
     assert t1["source"] == "measured"
-    assert t1["kchunk"] in (128, 256, 512, 1024) and t1["chunk_rows"] in (512, 1024, 2048, 4096, 8192)
+    assert t1["kchunk"] in (256, 1024, 4096, 1 << 24) and t1["chunk_rows"] in (512, 1024, 2048, 4096, 8192)
     evals, evecs, infos, st = bs.solve([p.X0 for p in probs])
     bs.close()
     for b, p in enumerate(probs):
