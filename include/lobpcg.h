@@ -78,8 +78,9 @@ typedef struct {
  * identical to the eager launches; the per-step GPU timings of lobpcg_info are then zero. */
 #define LOBPCG_FLAG_GRAPH 1
 /* LOBPCG_FLAG_AUTOTUNE: at setup, time the candidate launch shapes on this context's own
- * buffers and keep the fastest: the split-K chunk of the triangular-solve plan (256, 1024,
- * 4096 reduction rows per tile item, or no split) and the rows per reduction chunk of the
+ * buffers and keep the fastest: the split target of the triangular-solve plan (levels
+ * with fewer output tiles split their reduction ranges until they have about 256, 1024,
+ * 2048 or 4096 tile items) and the rows per reduction chunk of the
  * instance-segmented Gram and norm kernels (512 to 8192).  If the environment variable
  * LOBPCG_TUNE_CACHE names a file, results are appended to it keyed by device architecture
  * and problem structure, and later setups with the same key read them instead of timing.
@@ -200,7 +201,7 @@ const char* lobpcg_last_error(void);
  *  panel entries}. */
 lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t* perm_host, double* stats);
 
-/* Launch shapes in use: out3 = {split-K chunk of the triangular solves, rows per reduction
+/* Launch shapes in use: out3 = {split target of the triangular-solve plan, rows per reduction
  * chunk, 0 = defaults / 1 = tuned at setup / 2 = read from the tuning cache}. */
 lobpcg_status lobpcg_get_tuning(lobpcg_ctx ctx, int32_t* out3);
 

@@ -50,9 +50,9 @@ double now_s() {
 
 int pad_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64; }
 
-// Split-K chunk of the triangular-solve plan that never splits: every output tile is one
-// workgroup over its whole reduction range (its four waves split that range between them).
-constexpr int kNoSplit = 1 << 24;
+// Tile items aimed at per level of the triangular-solve plan: levels with fewer output tiles split
+// their reduction ranges until they have about this many.
+constexpr int kSplitTarget = 1024;
 
 // Host side of an instance segmentation.
 struct SegHost {
@@ -192,8 +192,8 @@ struct lobpcg_ctx_s {
   hipStream_t gst = nullptr;
   hipEvent_t ev_order = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  // tuning: split-K chunk of the triangular solves, rows per reduction chunk, how they were chosen
-  int kchunk = kNoSplit;
+  // tuning: split target of the triangular-solve plan, rows per reduction chunk, how they were chosen
+  int split_target = kSplitTarget;   // tile items per level the solve plan aims at
   int64_t chunk_rows = 0;
   int tuned = 0;   // 0 defaults, 1 measured at setup, 2 read from the cache file
   int64_t gpart_bytes = 0, fpart_bytes = 0, bpart_bytes = 0;
@@ -282,7 +282,9 @@ lobpcg_status install_solve_plan(lobpcg_ctx c) {
   C.SD.fwd_fin_level_off = C.SP.fwd_fin_level_off.data();
   C.SD.bwd_level_off = C.SP.bwd_level_off.data();
   C.SD.bwd_fin_level_off = C.SP.bwd_fin_level_off.data();
-  ST_TRY(upload_const(c, C.SD.gather_items, C.SP.gather_items));
+  ST_TRY(upload_const(c, C.SD.gather_dst, C.SP.gather_dst));
+  ST_TRY(upload_const(c, C.SD.gather_ptr, C.SP.gather_ptr));
+  ST_TRY(upload_const(c, C.SD.gather_src, C.SP.gather_src));
   C.SD.gather_level_off = C.SP.gather_level_off.data();
   return LOBPCG_OK;
 }
@@ -540,7 +542,7 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
     return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
   }
   build_factor_plan(C.S, C.FP);
-  build_solve_plan(C.S, 64, kNoSplit, C.SP);
+  build_solve_plan(C.S, 64, kSplitTarget, C.SP);
   std::vector<int32_t> prow, pcol, vmap, apos;
   if (!C.dense) {
     permute_pattern(C.S, rowptr, colind, prow, pcol, vmap);
@@ -739,8 +741,8 @@ uint64_t tune_key(const lobpcg_ctx_s& C) {
 }
 
 // The cache is a text file named by the environment variable LOBPCG_TUNE_CACHE (unset = no cache),
-// one line per key: "<key, 16 hex digits> <kchunk> <rows per chunk>".
-bool tune_cache_lookup(uint64_t key, int& kchunk, int64_t& rpc) {
+// one line per key: "<key, 16 hex digits> <split target> <rows per chunk>".
+bool tune_cache_lookup(uint64_t key, int& target, int64_t& rpc) {
   const char* path = getenv("LOBPCG_TUNE_CACHE");
   if (!path || !*path) return false;
   FILE* f = fopen(path, "r");
@@ -751,7 +753,7 @@ bool tune_cache_lookup(uint64_t key, int& kchunk, int64_t& rpc) {
   bool found = false;
   while (fscanf(f, "%llx %d %lld", &k, &kc, &r) == 3)
     if (k == key && kc >= 16 && kc % 16 == 0 && r >= 64) {   // the last entry for a key wins
-      kchunk = kc;
+      target = kc;
       rpc = r;
       found = true;
     }
@@ -759,12 +761,12 @@ bool tune_cache_lookup(uint64_t key, int& kchunk, int64_t& rpc) {
   return found;
 }
 
-void tune_cache_store(uint64_t key, int kchunk, int64_t rpc) {
+void tune_cache_store(uint64_t key, int target, int64_t rpc) {
   const char* path = getenv("LOBPCG_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%016llx %d %lld\n", (unsigned long long)key, kchunk, (long long)rpc);
+  fprintf(f, "%016llx %d %lld\n", (unsigned long long)key, target, (long long)rpc);
   fclose(f);
 }
 
@@ -799,9 +801,9 @@ lobpcg_status apply_chunk_rows(lobpcg_ctx c, int64_t rpc) {
   return LOBPCG_OK;
 }
 
-lobpcg_status apply_kchunk(lobpcg_ctx c, int kchunk) {
-  c->kchunk = kchunk;
-  build_solve_plan(c->S, 64, kchunk, c->SP);
+lobpcg_status apply_split_target(lobpcg_ctx c, int target) {
+  c->split_target = target;
+  build_solve_plan(c->S, 64, target, c->SP);
   const std::string err = verify_solve_plan(c->S, c->SP);
   if (!err.empty()) return fail(LOBPCG_ERR_INVALID_ARG, "solve plan failed verification: " + err);
   ST_TRY(install_solve_plan(c));
@@ -811,7 +813,7 @@ lobpcg_status apply_kchunk(lobpcg_ctx c, int kchunk) {
   return LOBPCG_OK;
 }
 
-// Pick the split-K chunk of the triangular-solve plan by timing the preconditioner, and the rows per
+// Pick the split target of the triangular-solve plan by timing the preconditioner, and the rows per
 // reduction chunk by timing the Rayleigh-Ritz Gram matrix and the residual, on the context's buffers.
 lobpcg_status autotune(lobpcg_ctx c) {
   lobpcg_ctx_s& C = *c;
@@ -819,7 +821,7 @@ lobpcg_status autotune(lobpcg_ctx c) {
   int kc = 0;
   int64_t rpc = 0;
   if (tune_cache_lookup(key, kc, rpc)) {
-    ST_TRY(apply_kchunk(c, kc));
+    ST_TRY(apply_split_target(c, kc));
     ST_TRY(apply_chunk_rows(c, rpc));
     C.tuned = 2;
     return LOBPCG_OK;
@@ -828,17 +830,17 @@ lobpcg_status autotune(lobpcg_ctx c) {
   launch_gaussian_fill(C.Sb[1], C.n, m3, m3, 0x7a11eull, C.st);
   launch_gaussian_fill(C.ASb[1], C.n, m3, m3, 0x7a11full, C.st);
   float best = 1e30f;
-  int best_kc = C.kchunk;
-  for (int cand : {256, 1024, 4096, kNoSplit}) {
-    ST_TRY(apply_kchunk(c, cand));
+  int best_st = C.split_target;
+  for (int cand : {256, 1024, 2048, 4096}) {
+    ST_TRY(apply_split_target(c, cand));
     const float t = time_launches(c, [&] { precond(c, C.Sb[1], m3); }, 3);
     ST_TRY(check_launch("autotune preconditioner"));
     if (t < best) {
       best = t;
-      best_kc = cand;
+      best_st = cand;
     }
   }
-  ST_TRY(apply_kchunk(c, best_kc));
+  ST_TRY(apply_split_target(c, best_st));
   best = 1e30f;
   int64_t best_rpc = C.chunk_rows;
   for (int64_t cand : {512, 1024, 2048, 4096, 8192}) {
@@ -858,7 +860,7 @@ lobpcg_status autotune(lobpcg_ctx c) {
   }
   ST_TRY(apply_chunk_rows(c, best_rpc));
   C.tuned = 1;
-  tune_cache_store(key, best_kc, best_rpc);
+  tune_cache_store(key, best_st, best_rpc);
   return LOBPCG_OK;
 }
 
@@ -1381,7 +1383,7 @@ lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t
     FactorPlan F;
     SolvePlan P;
     build_factor_plan(S, F);
-    build_solve_plan(S, 64, kNoSplit, P);
+    build_solve_plan(S, 64, kSplitTarget, P);
     std::vector<int32_t> prow, pcol, vmap, apos;
     if (!dense) {
       permute_pattern(S, A->rowptr, A->colind, prow, pcol, vmap);
@@ -1406,7 +1408,7 @@ lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t
 
 lobpcg_status lobpcg_get_tuning(lobpcg_ctx c, int32_t* out3) {
   if (!c || !out3) return fail(LOBPCG_ERR_INVALID_ARG, "NULL argument");
-  out3[0] = c->kchunk;
+  out3[0] = c->split_target;
   out3[1] = (int32_t)c->chunk_rows;
   out3[2] = c->tuned;
   return LOBPCG_OK;

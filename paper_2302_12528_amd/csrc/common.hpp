@@ -94,7 +94,7 @@ void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_of
 // ---- supernodal triangular solves (k_trisolve.hip) ----
 struct SolveDev {
   const int32_t* fwd_items; const int32_t* fwd_fin; const int32_t* bwd_items; const int32_t* bwd_fin;  // device
-  const int32_t* gather_items;                                                                          // device
+  const int32_t* gather_dst; const int32_t* gather_ptr; const int32_t* gather_src;                     // device
   const int64_t* fwd_level_off; const int64_t* fwd_fin_level_off;                                       // host
   const int64_t* bwd_level_off; const int64_t* bwd_fin_level_off; const int64_t* gather_level_off;      // host
 };

@@ -24,28 +24,25 @@ namespace {
 
 constexpr int TR = 64;   // output tile rows
 
-// Forward gather, one (supernode s, row r) item per 64 lanes (lane = right-hand side): own rows of
-// a supernode with children get the children's contributions added to the right-hand side; below
-// rows get the update vector initialised with them (zero for a leaf).
+// Forward gather, one destination row per 64 lanes (lane = right-hand side): the sum of the
+// children's update-vector rows listed for it is added to an own row of the right-hand side or
+// initialises a below row of the supernode's update vector.
 template <typename T>
-__global__ void __launch_bounds__(256) fwd_gather_kernel(FactorDev D, const int32_t* __restrict__ items,
-                                                         int64_t item_off, int64_t count, T* rhs, T* uvec, int M) {
+__global__ void __launch_bounds__(256) fwd_gather_kernel(const int32_t* __restrict__ dst,
+                                                         const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ src, int64_t item_off,
+                                                         int64_t count, T* rhs, T* uvec, int M) {
   const int lane = threadIdx.x % 64;
-  const int64_t item = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (item >= count || lane >= M) return;
-  const int s = items[2 * (item_off + item)];
-  const int r = items[2 * (item_off + item) + 1];
-  const int nc = D.nc[s];
+  const int64_t item = item_off + (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (item >= item_off + count || lane >= M) return;
+  const int32_t d = dst[item];
+  const int32_t p0 = ptr[item], p1 = ptr[item + 1];
   T v = 0;
-  for (int q = D.child_ptr[s]; q < D.child_ptr[s + 1]; ++q) {
-    const int c = D.child_list[q];
-    const int jr = D.invmap[D.inv_off[c] + r];
-    if (jr >= 0) v += uvec[(D.uvec_off[c] + jr) * M + lane];
-  }
-  if (r < nc)
-    rhs[(int64_t)(D.begin[s] + r) * M + lane] += v;
+  for (int32_t q = p0; q < p1; ++q) v += uvec[(int64_t)src[q] * M + lane];
+  if (d >= 0)
+    rhs[(int64_t)d * M + lane] += v;
   else
-    uvec[(D.uvec_off[s] + r - nc) * M + lane] = v;
+    uvec[(int64_t)(-d - 1) * M + lane] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -111,6 +108,7 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) fwd_mfma_kernel(FactorD
   const int* it = items + 5 * (item_off + blockIdx.x);
   const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
   const int begin = D.begin[s], nr = D.nr[s], nc = D.nc[s];
+  const bool parent = D.child_ptr[s + 1] > D.child_ptr[s];
   const int64_t ldp = panel_ld(nr);
   const int r0 = tile * TR;
   const int h = min(TR, nr - r0);
@@ -171,13 +169,13 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) fwd_mfma_kernel(FactorD
             if (col < M) y[(int64_t)(begin + row) * M + col] = acc[VW * p + w][c][v];
           }
         } else {
-          // the gather pass initialised this row of the update vector with the children's
-          // contributions passed through; subtract d = L21 y_s
+          // below row: -d = -L21 y_s, added to the children's contributions the gather pass put
+          // there when s has children
           T* u = uvec + (D.uvec_off[s] + row - nc) * M;
 #pragma unroll
           for (int c = 0; c < NCB; ++c) {
             const int col = 16 * c + i;
-            if (col < M) u[col] -= acc[VW * p + w][c][v];
+            if (col < M) u[col] = (parent ? u[col] : (T)0) - acc[VW * p + w][c][v];
           }
         }
       }
@@ -287,15 +285,18 @@ __global__ void __launch_bounds__(256) fwd_fin_kernel(FactorDev D, const int32_t
   const int r0 = tile * TR;
   const int h = min(TR, D.nr[s] - r0);
   const int nc = D.nc[s], begin = D.begin[s];
+  const bool parent = D.child_ptr[s + 1] > D.child_ptr[s];
   for (int e = threadIdx.x; e < h * M; e += 256) {
     const int rr = e / M, col = e % M;
     T acc = 0;
     for (int q = 0; q < nch; ++q) acc += part[((int64_t)(slot0 + q) * TR + rr) * M + col];
     const int row = r0 + rr;
-    if (row < nc)
+    if (row < nc) {
       y[(int64_t)(begin + row) * M + col] = acc;
-    else
-      uvec[(D.uvec_off[s] + row - nc) * M + col] -= acc;
+    } else {
+      T* u = uvec + (D.uvec_off[s] + row - nc) * M + col;
+      *u = (parent ? *u : (T)0) - acc;
+    }
   }
 }
 
@@ -336,8 +337,8 @@ void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* pan
   if (forward) {
     const int64_t a0 = Sd.gather_level_off[level], a1 = Sd.gather_level_off[level + 1];
     if (a1 > a0)
-      fwd_gather_kernel<T><<<(unsigned)((a1 - a0 + 3) / 4), 256, 0, st>>>(D, Sd.gather_items, a0, a1 - a0, rhs, uvec,
-                                                                          M);
+      fwd_gather_kernel<T><<<(unsigned)((a1 - a0 + 3) / 4), 256, 0, st>>>(Sd.gather_dst, Sd.gather_ptr, Sd.gather_src,
+                                                                          a0, a1 - a0, rhs, uvec, M);
     const int64_t f0 = Sd.fwd_level_off[level], f1 = Sd.fwd_level_off[level + 1];
     if (f1 > f0)
       fwd_mfma_kernel<T, M><<<(unsigned)(f1 - f0), NT, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);

@@ -473,46 +473,68 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
   }
 }
 
-void build_solve_plan(const Symbolic& S, int rpt, int kchunk, SolvePlan& P) {
+void build_solve_plan(const Symbolic& S, int rpt, int split_target, SolvePlan& P) {
   P = SolvePlan();
   P.rows_per_tile = rpt;
-  P.kchunk = kchunk;
+  P.split_target = split_target;
   P.gather_level_off.assign(S.nlevels + 1, 0);
   P.fwd_level_off.assign(S.nlevels + 1, 0);
   P.bwd_level_off.assign(S.nlevels + 1, 0);
   P.fwd_fin_level_off.assign(S.nlevels + 1, 0);
   P.bwd_fin_level_off.assign(S.nlevels + 1, 0);
+  P.gather_ptr.push_back(0);
+  // chunks of the reduction range [k0, k1) for a tile, nch wanted
   auto emit = [&](std::vector<int32_t>& items, std::vector<int32_t>& fin, int64_t& slots, int s, int t, int k0,
-                  int k1) {
-    const int nch = (k1 - k0 + kchunk - 1) / kchunk;
+                  int k1, int nch) {
+    const int len = k1 - k0;
+    int chunk = (len + nch - 1) / nch;
+    chunk = std::max(64, (chunk + 15) / 16 * 16);
+    nch = (len + chunk - 1) / chunk;
     if (nch <= 1) {
       items.insert(items.end(), {s, t, k0, k1, -1});
       return;
     }
     fin.insert(fin.end(), {s, t, (int32_t)slots, nch});
     for (int q = 0; q < nch; ++q) {
-      const int a = k0 + q * kchunk, b = std::min(k1, a + kchunk);
+      const int a = k0 + q * chunk, b = std::min(k1, a + chunk);
       items.insert(items.end(), {s, t, a, b, (int32_t)(slots + q)});
     }
     slots += nch;
   };
   for (int l = 0; l < S.nlevels; ++l) {
+    int64_t ftiles = 0, btiles = 0;
+    for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+      const int s = S.level_sn[q];
+      ftiles += (S.nr[s] + rpt - 1) / rpt;
+      btiles += (S.nc[s] + rpt - 1) / rpt;
+    }
+    const int fsplit = (int)std::max<int64_t>(1, split_target / std::max<int64_t>(1, ftiles));
+    const int bsplit = (int)std::max<int64_t>(1, split_target / std::max<int64_t>(1, btiles));
     for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
       const int s = S.level_sn[q];
       const int nc = S.nc[s], nr = S.nr[s];
-      const bool parent = S.child_ptr[s + 1] > S.child_ptr[s];
-      for (int r = parent ? 0 : nc; r < nr; ++r) {
-        P.gather_items.push_back(s);
-        P.gather_items.push_back(r);
+      if (S.child_ptr[s + 1] > S.child_ptr[s]) {
+        for (int r = 0; r < nr; ++r) {
+          const size_t before = P.gather_src.size();
+          for (int32_t cq = S.child_ptr[s]; cq < S.child_ptr[s + 1]; ++cq) {
+            const int c = S.child_list[cq];
+            const int32_t jr = S.invmap[S.inv_off[c] + r];
+            if (jr >= 0) P.gather_src.push_back((int32_t)(S.uvec_off[c] + jr));
+          }
+          if (r < nc && P.gather_src.size() == before) continue;   // own row nobody contributes to
+          P.gather_dst.push_back(r < nc ? S.begin[s] + r : -(int32_t)(S.uvec_off[s] + r - nc) - 1);
+          P.gather_ptr.push_back((int32_t)P.gather_src.size());
+        }
       }
       for (int t = 0; t < (nr + rpt - 1) / rpt; ++t) {
         const int r0 = t * rpt;
         const int kmax = (r0 < nc) ? std::min(nc, r0 + rpt) : nc;
-        emit(P.fwd_items, P.fwd_fin, P.fwd_slots, s, t, 0, kmax);
+        emit(P.fwd_items, P.fwd_fin, P.fwd_slots, s, t, 0, kmax, fsplit);
       }
-      for (int t = 0; t < (nc + rpt - 1) / rpt; ++t) emit(P.bwd_items, P.bwd_fin, P.bwd_slots, s, t, t * rpt, nr);
+      for (int t = 0; t < (nc + rpt - 1) / rpt; ++t)
+        emit(P.bwd_items, P.bwd_fin, P.bwd_slots, s, t, t * rpt, nr, bsplit);
     }
-    P.gather_level_off[l + 1] = (int64_t)P.gather_items.size() / 2;
+    P.gather_level_off[l + 1] = (int64_t)P.gather_dst.size();
     P.fwd_level_off[l + 1] = (int64_t)P.fwd_items.size() / 5;
     P.bwd_level_off[l + 1] = (int64_t)P.bwd_items.size() / 5;
     P.fwd_fin_level_off[l + 1] = (int64_t)P.fwd_fin.size() / 4;
@@ -547,11 +569,16 @@ std::string verify_solve_plan(const Symbolic& S, const SolvePlan& P) {
     }
     return "";
   };
-  for (size_t q = 0; q < P.gather_items.size(); q += 2) {
-    const int s = P.gather_items[q], r = P.gather_items[q + 1];
-    if (s < 0 || s >= ns || r < 0 || r >= S.nr[s]) return "gather item";
-    if (r < S.nc[s] && S.child_ptr[s + 1] == S.child_ptr[s]) return "gather item on a leaf's own row";
+  if (P.gather_ptr.size() != P.gather_dst.size() + 1 || P.gather_ptr[0] != 0 ||
+      (size_t)P.gather_ptr.back() != P.gather_src.size())
+    return "gather list sizes";
+  for (size_t i = 0; i < P.gather_dst.size(); ++i) {
+    const int32_t d = P.gather_dst[i];
+    if (d >= 0 ? d >= S.n : (int64_t)(-d - 1) >= S.uvec_total) return "gather destination";
+    if (P.gather_ptr[i + 1] < P.gather_ptr[i]) return "gather pointers";
   }
+  for (int32_t v : P.gather_src)
+    if (v < 0 || v >= S.uvec_total) return "gather source";
   {
     std::string e = check_items(P.fwd_items, P.fwd_fin, P.fwd_slots, true);
     if (!e.empty()) return "forward " + e;

@@ -80,22 +80,26 @@ enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4,
 void build_factor_plan(const Symbolic& S, FactorPlan& plan);
 
 // Trisolve work lists.  Each output tile (64 rows of P_s for the forward sweep, 64
-// own columns for the backward sweep) is split into K chunks of at most kchunk;
-// a tile with one chunk is written directly, otherwise each chunk writes a
-// partial tile to its own slot and a finalize item sums the slots in order.
+// own columns for the backward sweep) is one item, or, on levels with fewer tiles
+// than split_target, its reduction range is split into chunks (multiples of 16 rows)
+// so that the level has about split_target items; a tile with one chunk is written
+// directly, otherwise each chunk writes a partial tile to its own slot and a
+// finalize item sums the slots in order.
 struct SolvePlan {
   int rows_per_tile = 64;
-  int kchunk = 256;
-  // forward gather: (s, r) for every below row of every supernode and every own row of a
-  // supernode with children, per level
-  std::vector<int32_t> gather_items; std::vector<int64_t> gather_level_off;
+  int split_target = 1024;   // tile items aimed at per level when splitting reduction ranges
+  // forward gather, per level, one item per row of a supernode with children that receives
+  // contributions (own rows) or passes them on (all below rows): gather_dst = right-hand-side
+  // row (>= 0) or -(update-vector row) - 1; sources gather_src[gather_ptr[i] .. gather_ptr[i+1])
+  // are update-vector rows of the children
+  std::vector<int32_t> gather_dst, gather_ptr, gather_src; std::vector<int64_t> gather_level_off;
   std::vector<int32_t> fwd_items;  std::vector<int64_t> fwd_level_off;   // 5 ints: s, tile, k0, k1, slot
   std::vector<int32_t> fwd_fin;    std::vector<int64_t> fwd_fin_level_off; // 4 ints: s, tile, slot0, nchunks
   std::vector<int32_t> bwd_items;  std::vector<int64_t> bwd_level_off;
   std::vector<int32_t> bwd_fin;    std::vector<int64_t> bwd_fin_level_off;
   int64_t fwd_slots = 0, bwd_slots = 0;
 };
-void build_solve_plan(const Symbolic& S, int rows_per_tile, int kchunk, SolvePlan& plan);
+void build_solve_plan(const Symbolic& S, int rows_per_tile, int split_target, SolvePlan& plan);
 
 // Check every index the GPU kernels dereference against the buffer it indexes
 // (rows, maps, offsets, task and item lists, assembly positions).  Returns an

@@ -115,7 +115,7 @@ class Solver:
     def tuning(self) -> dict:
         out = np.zeros(3, dtype=np.int32)
         nv.check(self.lib.lobpcg_get_tuning(self.ctx, out.ctypes.data))
-        return {"kchunk": int(out[0]), "chunk_rows": int(out[1]),
+        return {"split_target": int(out[0]), "chunk_rows": int(out[1]),
                 "source": ("default", "measured", "cache")[int(out[2])]}
 
     def __del__(self):
@@ -222,7 +222,7 @@ class BatchedSolver:
     def tuning(self) -> dict:
         out = np.zeros(3, dtype=np.int32)
         nv.check(self.lib.lobpcg_get_tuning(self.ctx, out.ctypes.data))
-        return {"kchunk": int(out[0]), "chunk_rows": int(out[1]),
+        return {"split_target": int(out[0]), "chunk_rows": int(out[1]),
                 "source": ("default", "measured", "cache")[int(out[2])]}
 
     def __del__(self):

@@ -114,7 +114,7 @@ def test_autotune_and_cache(torch_cuda, tmp_path, monkeypatch):
     t1 = bs.tuning()
     print(f"tuned: {t1}", flush=True)
     assert t1["source"] == "measured"
-    assert t1["kchunk"] in (256, 1024, 4096, 1 << 24) and t1["chunk_rows"] in (512, 1024, 2048, 4096, 8192)
+    assert t1["split_target"] in (256, 1024, 2048, 4096) and t1["chunk_rows"] in (512, 1024, 2048, 4096, 8192)
     evals, evecs, infos, st = bs.solve([p.X0 for p in probs])
     bs.close()
     for b, p in enumerate(probs):
@@ -122,7 +122,7 @@ def test_autotune_and_cache(torch_cuda, tmp_path, monkeypatch):
         assert np.max(np.abs(evals[b].cpu().numpy() - lam_ref) / lam_ref) <= 1e-10
     bs2 = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, **kw)
     t2 = bs2.tuning()
-    assert t2["source"] == "cache" and t2["kchunk"] == t1["kchunk"] and t2["chunk_rows"] == t1["chunk_rows"]
+    assert t2["source"] == "cache" and t2["split_target"] == t1["split_target"] and t2["chunk_rows"] == t1["chunk_rows"]
     ev2, _, _, _ = bs2.solve([p.X0 for p in probs])
     for b in range(len(probs)):
         assert np.array_equal(ev2[b].cpu().numpy(), evals[b].cpu().numpy())
