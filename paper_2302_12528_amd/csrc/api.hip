@@ -286,6 +286,8 @@ lobpcg_status install_solve_plan(lobpcg_ctx c) {
   ST_TRY(upload_const(c, C.SD.gather_ptr, C.SP.gather_ptr));
   ST_TRY(upload_const(c, C.SD.gather_src, C.SP.gather_src));
   C.SD.gather_level_off = C.SP.gather_level_off.data();
+  C.SD.fwd_wide = C.SP.fwd_wide.data();
+  C.SD.bwd_wide = C.SP.bwd_wide.data();
   return LOBPCG_OK;
 }
 

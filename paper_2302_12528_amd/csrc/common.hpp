@@ -97,6 +97,7 @@ struct SolveDev {
   const int32_t* gather_dst; const int32_t* gather_ptr; const int32_t* gather_src;                     // device
   const int64_t* fwd_level_off; const int64_t* fwd_fin_level_off;                                       // host
   const int64_t* bwd_level_off; const int64_t* bwd_fin_level_off; const int64_t* gather_level_off;      // host
+  const char* fwd_wide; const char* bwd_wide;                                                           // host
 };
 // Both sweeps: rhs (T, n x M, permuted, overwritten by the forward assembly) -> y -> x, and W (FP64, n x mw,
 // ld ldw) = working(x).  fpart / bpart: partial tiles (slots x 64 x M).

@@ -69,9 +69,30 @@ __device__ inline void load16(const T* p, T (&v)[N]) {
 // reads VW consecutive panel rows of column k = kc + g; element w of its p-th vector is row
 // 16 VW p + VW i + w, the A operand of row block q = VW p + w.  Output row rb of block q is tile
 // row 16 VW p + VW rb + w.
-// Waves per tile item; wave w takes every NW-th reduction step.  FP64 items keep one wave: their
-// accumulators already fill the register file.
-template <typename T> constexpr int solve_waves() { return sizeof(T) == 4 ? 4 : 1; }
+// Waves per tile item; wave w takes every NW-th reduction step.  Items of levels whose reduction
+// ranges are short run one wave each (four items per block, no combine); FP64 items always do:
+// their accumulators already fill the register file.
+template <typename T, bool WIDE> constexpr int solve_waves() { return (WIDE && sizeof(T) == 4) ? 4 : 1; }
+
+struct SolveItem {
+  int s, tile, k0, k1, slot, begin, nr, nc;
+  int64_t poff;
+  int aux;      // update-vector offset (forward) or row-list offset (backward)
+  bool parent;  // s has children
+};
+
+// Item `item` of a level, or nullptr-equivalent (false) past the end; wave-uniform.
+__device__ inline SolveItem read_item(const int32_t* items, int64_t item) {
+  const int4* p = reinterpret_cast<const int4*>(items + (int64_t)kSolveItemInts * item);
+  const int4 a = p[0], b = p[1], c = p[2];
+  SolveItem it;
+  it.s = a.x; it.tile = a.y; it.k0 = a.z; it.k1 = a.w;
+  it.slot = b.x; it.begin = b.y; it.nr = b.z; it.nc = b.w;
+  it.poff = (int64_t)(uint32_t)c.x | ((int64_t)c.y << 32);
+  it.aux = c.z;
+  it.parent = (c.w & 1) != 0;
+  return it;
+}
 
 // Sum of the per-wave accumulators into wave 0 (fixed order w = 0, 1, ..., so deterministic).
 template <int NW, typename V4, int NQ>
@@ -91,28 +112,31 @@ __device__ inline bool reduce_waves(V4 (&acc)[NQ], V4* red) {
   return true;
 }
 
-template <typename T, int M>
-__global__ void __launch_bounds__(64 * solve_waves<T>()) fwd_mfma_kernel(FactorDev D, const int32_t* __restrict__ items,
-                                                      int64_t item_off, const T* __restrict__ panel,
-                                                      const T* __restrict__ rhs, T* __restrict__ y,
-                                                      T* __restrict__ uvec, T* __restrict__ part) {
+template <typename T, int M, bool WIDE>
+__global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict__ items, int64_t item_off,
+                                                       int64_t count, const T* __restrict__ panel,
+                                                       const T* __restrict__ rhs, T* __restrict__ y,
+                                                       T* __restrict__ uvec, T* __restrict__ part) {
   typedef Mfma<T> MF;
   typedef typename MF::v4 V4;
   constexpr int VW = 16 / sizeof(T);
   constexpr int NP = 4 / VW;
   constexpr int NCB = (M + 15) / 16;
-  constexpr int NW = solve_waves<T>();
+  constexpr int NW = solve_waves<T, WIDE>();
   __shared__ V4 red[(NW > 1 ? NW - 1 : 1) * 4 * NCB * 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int i = lane % 16, g = lane / 16;
-  const int* it = items + 5 * (item_off + blockIdx.x);
-  const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
-  const int begin = D.begin[s], nr = D.nr[s], nc = D.nc[s];
-  const bool parent = D.child_ptr[s + 1] > D.child_ptr[s];
+  const int64_t item = (NW > 1) ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
+  if (item >= count) return;   // whole waves (NW == 1) or never (NW > 1)
+  const int ksub = (NW > 1) ? wave : 0;
+  const SolveItem it = read_item(items, item_off + item);
+  const int tile = it.tile, k0 = it.k0, k1 = it.k1, slot = it.slot;
+  const int begin = it.begin, nr = it.nr, nc = it.nc;
+  const bool parent = it.parent;
   const int64_t ldp = panel_ld(nr);
   const int r0 = tile * TR;
   const int h = min(TR, nr - r0);
-  const T* pbase = panel + D.panel_off[s] + r0 + VW * i;
+  const T* pbase = panel + it.poff + r0 + VW * i;
   V4 acc[4][NCB];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
@@ -120,7 +144,7 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) fwd_mfma_kernel(FactorD
     for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
   constexpr int UNR = 4;
 #pragma unroll UNR
-  for (int kc = k0 + 4 * wave; kc < k1; kc += 4 * NW) {
+  for (int kc = k0 + 4 * ksub; kc < k1; kc += 4 * NW) {
     const int k = kc + g;
     const bool kok = k < k1;
     T a[NP][VW];
@@ -171,7 +195,7 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) fwd_mfma_kernel(FactorD
         } else {
           // below row: -d = -L21 y_s, added to the children's contributions the gather pass put
           // there when s has children
-          T* u = uvec + (D.uvec_off[s] + row - nc) * M;
+          T* u = uvec + ((int64_t)it.aux + row - nc) * M;
 #pragma unroll
           for (int c = 0; c < NCB; ++c) {
             const int col = 16 * c + i;
@@ -184,27 +208,30 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) fwd_mfma_kernel(FactorD
 // Backward: out tile (64 own columns x M) = P_s[k0:k1, j0:j0+64]^T z[k0:k1, :], z = [y_s; -x_below].
 // Lane (i, g) reads VW consecutive k (k = kc + VW g + t) of panel column j0 + 16 jb + i; MFMA t
 // pairs them with z row kc + VW g + t, so the 4 VW values of k in a step are reduced in VW MFMAs.
-template <typename T, int M>
-__global__ void __launch_bounds__(64 * solve_waves<T>()) bwd_mfma_kernel(FactorDev D, const int32_t* __restrict__ items,
-                                                      int64_t item_off, const T* __restrict__ panel,
-                                                      const T* __restrict__ y, T* __restrict__ x, double* W,
-                                                      int64_t ldw, int mw, T* __restrict__ part) {
+template <typename T, int M, bool WIDE>
+__global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict__ rows, const int32_t* __restrict__ items,
+                                                       int64_t item_off, int64_t count, const T* __restrict__ panel,
+                                                       const T* __restrict__ y, T* __restrict__ x, double* W,
+                                                       int64_t ldw, int mw, T* __restrict__ part) {
   typedef Mfma<T> MF;
   typedef typename MF::v4 V4;
   constexpr int VW = 16 / sizeof(T);
   constexpr int NCB = (M + 15) / 16;
-  constexpr int NW = solve_waves<T>();
+  constexpr int NW = solve_waves<T, WIDE>();
   __shared__ V4 red[(NW > 1 ? NW - 1 : 1) * 4 * NCB * 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int i = lane % 16, g = lane / 16;
-  const int* it = items + 5 * (item_off + blockIdx.x);
-  const int s = it[0], tile = it[1], k0 = it[2], k1 = it[3], slot = it[4];
-  const int begin = D.begin[s], nc = D.nc[s], nr = D.nr[s];
+  const int64_t item = (NW > 1) ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
+  if (item >= count) return;
+  const int ksub = (NW > 1) ? wave : 0;
+  const SolveItem it = read_item(items, item_off + item);
+  const int tile = it.tile, k0 = it.k0, k1 = it.k1, slot = it.slot;
+  const int begin = it.begin, nc = it.nc, nr = it.nr;
   const int64_t ldp = panel_ld(nr);
-  const int64_t roff = D.row_off[s];
+  const int64_t roff = it.aux;
   const int j0 = tile * TR;
   const int h = min(TR, nc - j0);
-  const T* pbase = panel + D.panel_off[s] + (int64_t)(j0 + i) * ldp + VW * g;
+  const T* pbase = panel + it.poff + (int64_t)(j0 + i) * ldp + VW * g;
   V4 acc[4][NCB];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
@@ -212,7 +239,7 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) bwd_mfma_kernel(FactorD
     for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
   constexpr int UNR = 2;
 #pragma unroll UNR
-  for (int kc = k0 + 4 * VW * wave; kc < k1; kc += 4 * VW * NW) {
+  for (int kc = k0 + 4 * VW * ksub; kc < k1; kc += 4 * VW * NW) {
     const int kk = kc + VW * g;
     T a[4][VW];
 #pragma unroll
@@ -234,7 +261,7 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) bwd_mfma_kernel(FactorD
         if (k < nc) {
           src = y + (int64_t)(begin + k) * M;
         } else {
-          src = x + (int64_t)D.rows[roff + k] * M;
+          src = x + (int64_t)rows[roff + k] * M;
           sign = -1;
         }
       }
@@ -276,6 +303,7 @@ __global__ void __launch_bounds__(64 * solve_waves<T>()) bwd_mfma_kernel(FactorD
 
 
 // Sum of a split tile's partial tiles in slot order, then the same epilogue as an unsplit item.
+// One block per 256 / M rows of a split tile (grid.y = 64 M / 256), one thread per element.
 template <typename T, int M>
 __global__ void __launch_bounds__(256) fwd_fin_kernel(FactorDev D, const int32_t* __restrict__ fin, int64_t fin_off,
                                                       const T* __restrict__ part, T* __restrict__ y,
@@ -286,8 +314,10 @@ __global__ void __launch_bounds__(256) fwd_fin_kernel(FactorDev D, const int32_t
   const int h = min(TR, D.nr[s] - r0);
   const int nc = D.nc[s], begin = D.begin[s];
   const bool parent = D.child_ptr[s + 1] > D.child_ptr[s];
-  for (int e = threadIdx.x; e < h * M; e += 256) {
+  {
+    const int e = blockIdx.y * 256 + threadIdx.x;
     const int rr = e / M, col = e % M;
+    if (rr >= h) return;
     T acc = 0;
     for (int q = 0; q < nch; ++q) acc += part[((int64_t)(slot0 + q) * TR + rr) * M + col];
     const int row = r0 + rr;
@@ -309,8 +339,10 @@ __global__ void __launch_bounds__(256) bwd_fin_kernel(FactorDev D, const int32_t
   const int j0 = tile * TR;
   const int h = min(TR, D.nc[s] - j0);
   const int begin = D.begin[s];
-  for (int e = threadIdx.x; e < h * M; e += 256) {
+  {
+    const int e = blockIdx.y * 256 + threadIdx.x;
     const int jj = e / M, col = e % M;
+    if (jj >= h) return;
     T acc = 0;
     for (int q = 0; q < nch; ++q) acc += part[((int64_t)(slot0 + q) * TR + jj) * M + col];
     const int64_t row = begin + j0 + jj;
@@ -333,23 +365,35 @@ __global__ void cast_to_kernel(const double* __restrict__ src, int64_t lds, T* _
 template <typename T, int M>
 void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* panel, T* rhs, T* y, T* x, T* uvec,
                  T* fpart, T* bpart, double* W, int64_t ldw, int mw, bool forward, hipStream_t st) {
-  constexpr unsigned NT = 64 * solve_waves<T>();
   if (forward) {
     const int64_t a0 = Sd.gather_level_off[level], a1 = Sd.gather_level_off[level + 1];
     if (a1 > a0)
       fwd_gather_kernel<T><<<(unsigned)((a1 - a0 + 3) / 4), 256, 0, st>>>(Sd.gather_dst, Sd.gather_ptr, Sd.gather_src,
                                                                           a0, a1 - a0, rhs, uvec, M);
     const int64_t f0 = Sd.fwd_level_off[level], f1 = Sd.fwd_level_off[level + 1];
-    if (f1 > f0)
-      fwd_mfma_kernel<T, M><<<(unsigned)(f1 - f0), NT, 0, st>>>(D, Sd.fwd_items, f0, panel, rhs, y, uvec, fpart);
+    const int64_t fn = f1 - f0;
+    if (fn > 0 && Sd.fwd_wide[level])
+      fwd_mfma_kernel<T, M, true><<<(unsigned)(solve_waves<T, true>() > 1 ? fn : (fn + 3) / 4), 256, 0, st>>>(
+          Sd.fwd_items, f0, fn, panel, rhs, y, uvec, fpart);
+    else if (fn > 0)
+      fwd_mfma_kernel<T, M, false><<<(unsigned)((fn + 3) / 4), 256, 0, st>>>(Sd.fwd_items, f0, fn, panel, rhs, y,
+                                                                              uvec, fpart);
     const int64_t g0 = Sd.fwd_fin_level_off[level], g1 = Sd.fwd_fin_level_off[level + 1];
-    if (g1 > g0) fwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), 256, 0, st>>>(D, Sd.fwd_fin, g0, fpart, y, uvec);
+    if (g1 > g0)
+      fwd_fin_kernel<T, M><<<dim3((unsigned)(g1 - g0), TR * M / 256), 256, 0, st>>>(D, Sd.fwd_fin, g0, fpart, y, uvec);
   } else {
     const int64_t b0 = Sd.bwd_level_off[level], b1 = Sd.bwd_level_off[level + 1];
-    if (b1 > b0)
-      bwd_mfma_kernel<T, M><<<(unsigned)(b1 - b0), NT, 0, st>>>(D, Sd.bwd_items, b0, panel, y, x, W, ldw, mw, bpart);
+    const int64_t bn = b1 - b0;
+    if (bn > 0 && Sd.bwd_wide[level])
+      bwd_mfma_kernel<T, M, true><<<(unsigned)(solve_waves<T, true>() > 1 ? bn : (bn + 3) / 4), 256, 0, st>>>(
+          D.rows, Sd.bwd_items, b0, bn, panel, y, x, W, ldw, mw, bpart);
+    else if (bn > 0)
+      bwd_mfma_kernel<T, M, false><<<(unsigned)((bn + 3) / 4), 256, 0, st>>>(D.rows, Sd.bwd_items, b0, bn, panel, y,
+                                                                              x, W, ldw, mw, bpart);
     const int64_t g0 = Sd.bwd_fin_level_off[level], g1 = Sd.bwd_fin_level_off[level + 1];
-    if (g1 > g0) bwd_fin_kernel<T, M><<<(unsigned)(g1 - g0), 256, 0, st>>>(D, Sd.bwd_fin, g0, bpart, x, W, ldw, mw);
+    if (g1 > g0)
+      bwd_fin_kernel<T, M><<<dim3((unsigned)(g1 - g0), TR * M / 256), 256, 0, st>>>(D, Sd.bwd_fin, g0, bpart, x, W,
+                                                                                   ldw, mw);
   }
 }
 

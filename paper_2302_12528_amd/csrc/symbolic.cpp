@@ -484,20 +484,30 @@ void build_solve_plan(const Symbolic& S, int rpt, int split_target, SolvePlan& P
   P.bwd_fin_level_off.assign(S.nlevels + 1, 0);
   P.gather_ptr.push_back(0);
   // chunks of the reduction range [k0, k1) for a tile, nch wanted
+  int maxk = 0;   // longest reduction range of the level being built
   auto emit = [&](std::vector<int32_t>& items, std::vector<int32_t>& fin, int64_t& slots, int s, int t, int k0,
-                  int k1, int nch) {
+                  int k1, int nch, bool fwd) {
     const int len = k1 - k0;
     int chunk = (len + nch - 1) / nch;
     chunk = std::max(64, (chunk + 15) / 16 * 16);
     nch = (len + chunk - 1) / chunk;
+    const int64_t po = S.panel_off[s];
+    const int32_t meta[7] = {S.begin[s], S.nr[s], S.nc[s], (int32_t)(po & 0xffffffff), (int32_t)(po >> 32),
+                             (int32_t)(fwd ? S.uvec_off[s] : S.row_off[s]),
+                             (int32_t)(S.child_ptr[s + 1] > S.child_ptr[s] ? 1 : 0)};
+    auto push = [&](int a, int b, int slot) {
+      items.insert(items.end(), {s, t, a, b, slot});
+      items.insert(items.end(), meta, meta + 7);
+      maxk = std::max(maxk, b - a);
+    };
     if (nch <= 1) {
-      items.insert(items.end(), {s, t, k0, k1, -1});
+      push(k0, k1, -1);
       return;
     }
     fin.insert(fin.end(), {s, t, (int32_t)slots, nch});
     for (int q = 0; q < nch; ++q) {
       const int a = k0 + q * chunk, b = std::min(k1, a + chunk);
-      items.insert(items.end(), {s, t, a, b, (int32_t)(slots + q)});
+      push(a, b, (int32_t)(slots + q));
     }
     slots += nch;
   };
@@ -526,17 +536,29 @@ void build_solve_plan(const Symbolic& S, int rpt, int split_target, SolvePlan& P
           P.gather_ptr.push_back((int32_t)P.gather_src.size());
         }
       }
+    }
+    maxk = 0;
+    for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+      const int s = S.level_sn[q];
+      const int nc = S.nc[s], nr = S.nr[s];
       for (int t = 0; t < (nr + rpt - 1) / rpt; ++t) {
         const int r0 = t * rpt;
         const int kmax = (r0 < nc) ? std::min(nc, r0 + rpt) : nc;
-        emit(P.fwd_items, P.fwd_fin, P.fwd_slots, s, t, 0, kmax, fsplit);
+        emit(P.fwd_items, P.fwd_fin, P.fwd_slots, s, t, 0, kmax, fsplit, true);
       }
-      for (int t = 0; t < (nc + rpt - 1) / rpt; ++t)
-        emit(P.bwd_items, P.bwd_fin, P.bwd_slots, s, t, t * rpt, nr, bsplit);
     }
+    P.fwd_wide.push_back(maxk > kSolveWideK);
+    maxk = 0;
+    for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
+      const int s = S.level_sn[q];
+      const int nc = S.nc[s], nr = S.nr[s];
+      for (int t = 0; t < (nc + rpt - 1) / rpt; ++t)
+        emit(P.bwd_items, P.bwd_fin, P.bwd_slots, s, t, t * rpt, nr, bsplit, false);
+    }
+    P.bwd_wide.push_back(maxk > kSolveWideK);
     P.gather_level_off[l + 1] = (int64_t)P.gather_dst.size();
-    P.fwd_level_off[l + 1] = (int64_t)P.fwd_items.size() / 5;
-    P.bwd_level_off[l + 1] = (int64_t)P.bwd_items.size() / 5;
+    P.fwd_level_off[l + 1] = (int64_t)P.fwd_items.size() / kSolveItemInts;
+    P.bwd_level_off[l + 1] = (int64_t)P.bwd_items.size() / kSolveItemInts;
     P.fwd_fin_level_off[l + 1] = (int64_t)P.fwd_fin.size() / 4;
     P.bwd_fin_level_off[l + 1] = (int64_t)P.bwd_fin.size() / 4;
   }
@@ -550,10 +572,19 @@ std::string verify_solve_plan(const Symbolic& S, const SolvePlan& P) {
   const int ns = S.nsuper;
   // the solve kernels use 64-row tiles and step the reduction 16 rows at a time from k0
   if (P.rows_per_tile != 64) return "solve plan tile rows";
+  if ((int)P.fwd_wide.size() != S.nlevels || (int)P.bwd_wide.size() != S.nlevels) return "solve plan level modes";
   auto check_items = [&](const std::vector<int32_t>& items, const std::vector<int32_t>& fin, int64_t slots,
                          bool fwd) -> std::string {
-    for (size_t q = 0; q < items.size(); q += 5) {
+    if (items.size() % kSolveItemInts != 0) return "solve item list size";
+    for (size_t q = 0; q < items.size(); q += kSolveItemInts) {
       const int s = items[q], t = items[q + 1], k0 = items[q + 2], k1 = items[q + 3], slot = items[q + 4];
+      if (s >= 0 && s < ns) {
+        const int64_t po = (int64_t)(uint32_t)items[q + 8] | ((int64_t)items[q + 9] << 32);
+        if (items[q + 5] != S.begin[s] || items[q + 6] != S.nr[s] || items[q + 7] != S.nc[s] ||
+            po != S.panel_off[s] || items[q + 10] != (fwd ? S.uvec_off[s] : S.row_off[s]) ||
+            items[q + 11] != (S.child_ptr[s + 1] > S.child_ptr[s] ? 1 : 0))
+          return "solve item metadata";
+      }
       if (s < 0 || s >= ns || t < 0) return "solve item supernode";
       const int lim = fwd ? S.nr[s] : S.nc[s];
       if (t * P.rows_per_tile >= lim) return "solve item tile";

@@ -14,6 +14,8 @@
 namespace lobpcg {
 
 constexpr int kTile = 64;   // tile edge of the factor kernels
+constexpr int kSolveItemInts = 12;   // ints per triangular-solve item
+constexpr int kSolveWideK = 256;     // items with longer reduction ranges use four waves
 // Leading dimension of a supernode panel with nr rows: nr rounded up to a multiple of 4, so that
 // every panel column starts 16-byte aligned (FP32) and 4-row groups can be read as one vector.
 constexpr int64_t panel_ld(int64_t nr) { return (nr + 3) & ~(int64_t)3; }
@@ -93,7 +95,11 @@ struct SolvePlan {
   // row (>= 0) or -(update-vector row) - 1; sources gather_src[gather_ptr[i] .. gather_ptr[i+1])
   // are update-vector rows of the children
   std::vector<int32_t> gather_dst, gather_ptr, gather_src; std::vector<int64_t> gather_level_off;
-  std::vector<int32_t> fwd_items;  std::vector<int64_t> fwd_level_off;   // 5 ints: s, tile, k0, k1, slot
+  // items: kSolveItemInts ints each: s, tile, k0, k1, slot, begin, nr, nc, panel offset (low,
+  // high 32 bits), update-vector offset (forward) or row-list offset (backward), flags (bit 0: s
+  // has children)
+  std::vector<int32_t> fwd_items;  std::vector<int64_t> fwd_level_off;
+  std::vector<char> fwd_wide, bwd_wide;   // per level: items long enough to split over four waves
   std::vector<int32_t> fwd_fin;    std::vector<int64_t> fwd_fin_level_off; // 4 ints: s, tile, slot0, nchunks
   std::vector<int32_t> bwd_items;  std::vector<int64_t> bwd_level_off;
   std::vector<int32_t> bwd_fin;    std::vector<int64_t> bwd_fin_level_off;
