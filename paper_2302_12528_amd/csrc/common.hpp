@@ -6,6 +6,17 @@
 
 namespace lobpcg {
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2): block b runs on XCD
+// b % 8.  xcd_block(b, G) renumbers the G blocks so that each XCD receives a contiguous range of
+// logical block indices, and work items that share operands (the tiles of one supernode) share an
+// L2.  A bijection on [0, G).
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t G) {
+  const int64_t q = G / kXcds, r = G % kXcds;
+  const int64_t x = b % kXcds, j = b / kXcds;
+  return x * q + (x < r ? x : r) + j;
+}
+
 // ---- instance segmentation of tall blocks (k_seg.hip) ----
 // Rows [inst_off[b], inst_off[b+1]) of a tall block belong to instance b.  Row tiles (<= 64 rows)
 // and reduction chunks never straddle instances.  All pointers are device pointers.

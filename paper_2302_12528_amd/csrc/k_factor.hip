@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
                                                    T* lcopy) {
   __shared__ T As[TB][TB + 1];
   __shared__ T Bs[TB][TB + 1];
-  const int* tk = D.tasks + 4 * (task_off + blockIdx.x);
+  const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
   const int s = tk[0], I = tk[1], J = tk[2], p = tk[3];
   const Sn S = sn_of(D, s);
   const int tid = threadIdx.x;

@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict
   __shared__ V4 red[(NW > 1 ? NW - 1 : 1) * 4 * NCB * 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int i = lane % 16, g = lane / 16;
-  const int64_t item = (NW > 1) ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t item = (NW > 1) ? blk : blk * 4 + wave;
   if (item >= count) return;   // whole waves (NW == 1) or never (NW > 1)
   const int ksub = (NW > 1) ? wave : 0;
   const SolveItem it = read_item(items, item_off + item);
@@ -221,7 +222,8 @@ __global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict
   __shared__ V4 red[(NW > 1 ? NW - 1 : 1) * 4 * NCB * 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int i = lane % 16, g = lane / 16;
-  const int64_t item = (NW > 1) ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t item = (NW > 1) ? blk : blk * 4 + wave;
   if (item >= count) return;
   const int ksub = (NW > 1) ? wave : 0;
   const SolveItem it = read_item(items, item_off + item);
