@@ -143,33 +143,39 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
-  constexpr int UNR = 4;
-#pragma unroll UNR
-  for (int kc = k0 + 4 * ksub; kc < k1; kc += 4 * NW) {
-    const int k = kc + g;
-    const bool kok = k < k1;
-    T a[NP][VW];
+  // U reduction steps per batch: all their loads are issued before the first MFMA of the batch
+  constexpr int U = (sizeof(T) == 4) ? 8 : 4;
+  for (int kb = k0 + 4 * ksub; kb < k1; kb += 4 * NW * U) {
+    T a[U][NP][VW];
+    T b[U][NCB];
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      if (kok && 16 * VW * p + VW * i < h) {
-        load16(pbase + 16 * VW * p + (int64_t)k * ldp, a[p]);
-      } else {
+    for (int u = 0; u < U; ++u) {
+      const int k = kb + 4 * NW * u + g;
+      const bool kok = k < k1;
 #pragma unroll
-        for (int w = 0; w < VW; ++w) a[p][w] = 0;
+      for (int p = 0; p < NP; ++p) {
+        if (kok && 16 * VW * p + VW * i < h) {
+          load16(pbase + 16 * VW * p + (int64_t)k * ldp, a[u][p]);
+        } else {
+#pragma unroll
+          for (int w = 0; w < VW; ++w) a[u][p][w] = 0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) {
+        const int col = 16 * c + i;
+        b[u][c] = (kok && col < M) ? rhs[(int64_t)(begin + k) * M + col] : (T)0;
       }
     }
-    T b[NCB];
 #pragma unroll
-    for (int c = 0; c < NCB; ++c) {
-      const int col = 16 * c + i;
-      b[c] = (kok && col < M) ? rhs[(int64_t)(begin + k) * M + col] : (T)0;
-    }
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
+      for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int w = 0; w < VW; ++w)
+        for (int w = 0; w < VW; ++w)
 #pragma unroll
-        for (int c = 0; c < NCB; ++c) acc[VW * p + w][c] = MF::op(a[p][w], b[c], acc[VW * p + w][c]);
+          for (int c = 0; c < NCB; ++c)
+            acc[VW * p + w][c] = MF::op(a[u][p][w], b[u][c], acc[VW * p + w][c]);
   }
   if (!reduce_waves<NW>(reinterpret_cast<V4(&)[4 * NCB]>(acc), red)) return;
 #pragma unroll
@@ -239,46 +245,57 @@ __global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
-  constexpr int UNR = 2;
-#pragma unroll UNR
-  for (int kc = k0 + 4 * VW * ksub; kc < k1; kc += 4 * VW * NW) {
-    const int kk = kc + VW * g;
-    T a[4][VW];
+  // U reduction steps (of 4 VW rows) per batch: panel loads and the row indices of the gathered
+  // operand first, then the operand rows, then the MFMAs
+  constexpr int U = (sizeof(T) == 4) ? 4 : 2;
+  for (int kb = k0 + 4 * VW * ksub; kb < k1; kb += 4 * VW * NW * U) {
+    T a[U][4][VW];
+    int src_row[U][VW];
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
-      if (kk < k1 && 16 * jb + i < h) {
-        load16(pbase + (int64_t)(16 * jb) * ldp + kc, a[jb]);
-      } else {
+    for (int u = 0; u < U; ++u) {
+      const int kc = kb + 4 * VW * NW * u;
+      const int kk = kc + VW * g;
 #pragma unroll
-        for (int t = 0; t < VW; ++t) a[jb][t] = 0;
-      }
-    }
-    T b[VW][NCB];
-#pragma unroll
-    for (int t = 0; t < VW; ++t) {
-      const int k = kk + t;
-      const T* src = nullptr;
-      T sign = 1;
-      if (k < k1) {
-        if (k < nc) {
-          src = y + (int64_t)(begin + k) * M;
+      for (int jb = 0; jb < 4; ++jb) {
+        if (kk < k1 && 16 * jb + i < h) {
+          load16(pbase + (int64_t)(16 * jb) * ldp + kc, a[u][jb]);
         } else {
-          src = x + (int64_t)rows[roff + k] * M;
-          sign = -1;
+#pragma unroll
+          for (int t = 0; t < VW; ++t) a[u][jb][t] = 0;
         }
       }
 #pragma unroll
-      for (int c = 0; c < NCB; ++c) {
-        const int col = 16 * c + i;
-        b[t][c] = (src && col < M) ? sign * src[col] : (T)0;
+      for (int t = 0; t < VW; ++t) {
+        const int k = kk + t;
+        // own rows read y at begin + k; below rows read -x at the listed row; -1 = past the range
+        src_row[u][t] = (k >= k1) ? -1 : (k < nc ? begin + k : rows[roff + k]);
+      }
+    }
+    T b[U][VW][NCB];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = kb + 4 * VW * NW * u + VW * g;
+#pragma unroll
+      for (int t = 0; t < VW; ++t) {
+        const int r = src_row[u][t];
+        const bool own = (kk + t < nc);
+        const T* src = own ? y : x;
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+          const int col = 16 * c + i;
+          const T v = (r >= 0 && col < M) ? src[(int64_t)r * M + col] : (T)0;
+          b[u][t][c] = own ? v : -v;
+        }
       }
     }
 #pragma unroll
-    for (int t = 0; t < VW; ++t)
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
+      for (int t = 0; t < VW; ++t)
 #pragma unroll
-        for (int c = 0; c < NCB; ++c) acc[jb][c] = MF::op(a[jb][t], b[t][c], acc[jb][c]);
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+          for (int c = 0; c < NCB; ++c) acc[jb][c] = MF::op(a[u][jb][t], b[u][t][c], acc[jb][c]);
   }
   if (!reduce_waves<NW>(reinterpret_cast<V4(&)[4 * NCB]>(acc), red)) return;
 #pragma unroll
