@@ -53,6 +53,7 @@ int pad_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64; }
 // Tile items aimed at per level of the triangular-solve plan: levels with fewer output tiles split
 // their reduction ranges until they have about this many.
 constexpr int kSplitTarget = 1024;
+constexpr int64_t kMaxBufferBytes = ((int64_t)1 << 31) - 64;   // buffer-resource extent limit of the solve kernels
 
 // Host side of an instance segmentation.
 struct SegHost {
@@ -288,6 +289,8 @@ lobpcg_status install_solve_plan(lobpcg_ctx c) {
   C.SD.gather_level_off = C.SP.gather_level_off.data();
   C.SD.fwd_wide = C.SP.fwd_wide.data();
   C.SD.bwd_wide = C.SP.bwd_wide.data();
+  ST_TRY(upload_const(c, C.SD.bwd_src, C.SP.bwd_src));
+  C.SD.n = C.n;
   return LOBPCG_OK;
 }
 
@@ -659,8 +662,15 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
     SETUP_TRY(C.alloc(C.ASb[b], n * m3));
   }
   SETUP_TRY(C.alloc_bytes(C.rhs, n * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.ybuf, n * C.mp * tsz));
-  SETUP_TRY(C.alloc_bytes(C.xbuf, n * C.mp * tsz));
+  // the solve kernels address y, x = y + n mp and each supernode panel with 32-bit byte offsets
+  {
+    int64_t max_panel = 0;
+    for (int s = 0; s < S.nsuper; ++s) max_panel = std::max(max_panel, panel_ld(S.nr[s]) * S.nc[s]);
+    if (2 * n * C.mp * tsz >= kMaxBufferBytes || max_panel * tsz >= kMaxBufferBytes)
+      return cleanup(fail(LOBPCG_ERR_INVALID_ARG, "problem too large for the solve kernels' 32-bit buffer offsets"));
+  }
+  SETUP_TRY(C.alloc_bytes(C.ybuf, 2 * n * C.mp * tsz));
+  C.xbuf = static_cast<char*>(C.ybuf) + n * C.mp * tsz;
   SETUP_TRY(C.alloc_bytes(C.uvec, std::max<int64_t>(1, S.uvec_total) * C.mp * tsz));
   C.fpart_bytes = std::max<int64_t>(1, C.SP.fwd_slots) * 64 * C.mp * tsz;
   C.bpart_bytes = std::max<int64_t>(1, C.SP.bwd_slots) * 64 * C.mp * tsz;

@@ -109,9 +109,13 @@ struct SolveDev {
   const int64_t* fwd_level_off; const int64_t* fwd_fin_level_off;                                       // host
   const int64_t* bwd_level_off; const int64_t* bwd_fin_level_off; const int64_t* gather_level_off;      // host
   const char* fwd_wide; const char* bwd_wide;                                                           // host
+  // backward operand rows: for item aux a and panel row k, bwd_src[a + k] indexes [y; x] (2n rows)
+  const int32_t* bwd_src;                                                                                // device
+  int64_t n;
 };
 // Both sweeps: rhs (T, n x M, permuted, overwritten by the forward assembly) -> y -> x, and W (FP64, n x mw,
-// ld ldw) = working(x).  fpart / bpart: partial tiles (slots x 64 x M).
+// ld ldw) = working(x).  x must equal y + n M (one allocation of 2 n M elements, fewer than 2^31 bytes).
+// fpart / bpart: partial tiles (slots x 64 x M).
 template <typename T>
 void launch_precond(const FactorDev& D, const SolveDev& Sd, int nlevels, int M, const T* panel, T* rhs, T* y, T* x,
                     T* uvec, T* fpart, T* bpart, double* W, int64_t ldw, int mw, hipStream_t st);

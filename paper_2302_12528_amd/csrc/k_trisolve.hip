@@ -14,6 +14,7 @@
 // workgroup that streams its panel block into matrix-core products.  A tile whose
 // reduction range is split over several items writes partial tiles that a
 // finalize pass sums in a fixed order.
+#include "bufload.hpp"
 #include "common.hpp"
 #include "mfma.hpp"
 #include "symbolic.hpp"
@@ -24,64 +25,67 @@ namespace {
 
 constexpr int TR = 64;   // output tile rows
 
-// Forward gather, one destination row per 64 lanes (lane = right-hand side): the sum of the
-// children's update-vector rows listed for it is added to an own row of the right-hand side or
-// initialises a below row of the supernode's update vector.
-template <typename T>
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef f32x4_t type; };
+template <> struct Vec16<double> { typedef f64x2_t type; };
+
+// Forward gather: each destination row takes the sum of the children's update-vector rows listed
+// for it, added to an own row of the right-hand side or initialising a below row of the
+// supernode's update vector.  A row of M values is read and written as 16-byte vectors by
+// LPR = M sizeof(T) / 16 lanes, so a wave handles 64 / LPR rows.
+template <typename T, int M>
 __global__ void __launch_bounds__(256) fwd_gather_kernel(const int32_t* __restrict__ dst,
                                                          const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ src, int64_t item_off,
-                                                         int64_t count, T* rhs, T* uvec, int M) {
+                                                         int64_t count, T* rhs, T* uvec) {
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int LPR = M / VW;
+  constexpr int RPW = 64 / LPR;
+  typedef typename Vec16<T>::type V;
   const int lane = threadIdx.x % 64;
-  const int64_t item = item_off + (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
-  if (item >= item_off + count || lane >= M) return;
+  const int64_t r = ((int64_t)blockIdx.x * 4 + threadIdx.x / 64) * RPW + lane / LPR;
+  if (r >= count) return;
+  const int64_t item = item_off + r;
+  const int cl = (lane % LPR) * VW;
   const int32_t d = dst[item];
   const int32_t p0 = ptr[item], p1 = ptr[item + 1];
-  T v = 0;
-  for (int32_t q = p0; q < p1; ++q) v += uvec[(int64_t)src[q] * M + lane];
-  if (d >= 0)
-    rhs[(int64_t)d * M + lane] += v;
-  else
-    uvec[(int64_t)(-d - 1) * M + lane] = v;
-}
-
-// ---------------------------------------------------------------------------
-// Matrix-core forms of the two tile products, one wave per item.  16-byte vector loads of the
-// panel feed 16x16x4 MFMAs directly (each panel element is used once per item, so it is not
-// staged through LDS); the right-hand-side operand is reused from registers by the 4 row blocks.
-// ---------------------------------------------------------------------------
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { typedef float4 type; };
-template <> struct Vec16<double> { typedef double2 type; };
-
-template <typename T, int N>
-__device__ inline void load16(const T* p, T (&v)[N]) {
-  static_assert(N * sizeof(T) == 16, "16-byte vector");
-  const typename Vec16<T>::type q = *reinterpret_cast<const typename Vec16<T>::type*>(p);
-  if constexpr (N == 4) {
-    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  V v = {};
+  int32_t q = p0;
+  for (; q + 1 < p1; q += 2) {   // two children's rows in flight at a time
+    const V a = *reinterpret_cast<const V*>(uvec + (int64_t)src[q] * M + cl);
+    const V b = *reinterpret_cast<const V*>(uvec + (int64_t)src[q + 1] * M + cl);
+    v += a;
+    v += b;
+  }
+  if (q < p1) v += *reinterpret_cast<const V*>(uvec + (int64_t)src[q] * M + cl);
+  if (d >= 0) {
+    V* o = reinterpret_cast<V*>(rhs + (int64_t)d * M + cl);
+    *o += v;
   } else {
-    v[0] = q.x; v[1] = q.y;
+    *reinterpret_cast<V*>(uvec + (int64_t)(-d - 1) * M + cl) = v;
   }
 }
 
-// Forward: out tile (64 rows x M) = P_s[r0:r0+64, k0:k1] * b_s[k0:k1, :].  Lane (i = l % 16, g = l / 16)
-// reads VW consecutive panel rows of column k = kc + g; element w of its p-th vector is row
-// 16 VW p + VW i + w, the A operand of row block q = VW p + w.  Output row rb of block q is tile
-// row 16 VW p + VW rb + w.
-// Waves per tile item; wave w takes every NW-th reduction step.  Items of levels whose reduction
-// ranges are short run one wave each (four items per block, no combine); FP64 items always do:
-// their accumulators already fill the register file.
+// ---------------------------------------------------------------------------
+// Matrix-core forms of the two tile products.  Panel blocks are streamed with 16-byte buffer loads
+// straight into 16x16x4 MFMA operands (each panel element is used once per item, so it is not
+// staged through LDS); the right-hand-side operand is reused from registers by the 4 row blocks.
+// The reduction range is walked in stages of U steps; the loads of stage j + 1 are issued before
+// the MFMAs of stage j, so every wave keeps a stage of panel data in flight while it computes.
+// ---------------------------------------------------------------------------
+// Waves per tile item; wave w takes every NW-th stage.  Items of levels whose reduction ranges are
+// short run one wave each (four items per block, no combine); FP64 items always do: their
+// accumulators already fill most of the register file.
 template <typename T, bool WIDE> constexpr int solve_waves() { return (WIDE && sizeof(T) == 4) ? 4 : 1; }
 
 struct SolveItem {
   int s, tile, k0, k1, slot, begin, nr, nc;
   int64_t poff;
-  int aux;      // update-vector offset (forward) or row-list offset (backward)
+  int aux;      // update-vector offset (forward) or source-row list offset (backward)
   bool parent;  // s has children
 };
 
-// Item `item` of a level, or nullptr-equivalent (false) past the end; wave-uniform.
+// Item `item` of a level (wave-uniform).
 __device__ inline SolveItem read_item(const int32_t* items, int64_t item) {
   const int4* p = reinterpret_cast<const int4*>(items + (int64_t)kSolveItemInts * item);
   const int4 a = p[0], b = p[1], c = p[2];
@@ -94,23 +98,84 @@ __device__ inline SolveItem read_item(const int32_t* items, int64_t item) {
   return it;
 }
 
-// Sum of the per-wave accumulators into wave 0 (fixed order w = 0, 1, ..., so deterministic).
-template <int NW, typename V4, int NQ>
-__device__ inline bool reduce_waves(V4 (&acc)[NQ], V4* red) {
-  if (NW == 1) return true;
-  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
-  if (w > 0) {
+// Four waves that split one item's reduction range: each writes its accumulators to LDS, then wave w
+// sums accumulator block w over the waves in the fixed order 0, 1, 2, 3 (deterministic) into
+// out[0..NCB) and writes that block of the tile.
+template <typename V4, int NCB>
+__device__ inline void reduce_blocks(const V4 (&acc)[4][NCB], V4 (&out)[NCB], V4* red, int wave) {
+  const int lane = threadIdx.x % 64;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) red[((w - 1) * NQ + q) * 64 + lane] = acc[q];
-  }
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) red[((wave * 4 + q) * NCB + c) * 64 + lane] = acc[q][c];
   __syncthreads();
-  if (w > 0) return false;
 #pragma unroll
-  for (int v = 1; v < NW; ++v)
+  for (int c = 0; c < NCB; ++c) {
+    V4 sum = red[((0 * 4 + wave) * NCB + c) * 64 + lane];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] += red[((v - 1) * NQ + q) * 64 + lane];
-  return true;
+    for (int v = 1; v < 4; ++v) sum += red[((v * 4 + wave) * NCB + c) * 64 + lane];
+    out[c] = sum;
+  }
 }
+
+// Store of the 4 values a lane holds for one output row: columns c0 + drow(lane, v), v = 0..3.  In
+// FP32 these are 4 consecutive columns (one 16-byte store); sub: dst = (load ? dst : 0) - val.
+template <typename T, int M>
+__device__ inline void store_cols(T* row, int c0, const typename Mfma<T>::v4& val, bool sub, bool load) {
+  const int lane = threadIdx.x % 64;
+  if constexpr (sizeof(T) == 4) {
+    const int col = c0 + 4 * (lane / 16);
+    if (col >= M) return;
+    f32x4_t* d = reinterpret_cast<f32x4_t*>(row + col);
+    f32x4_t v = val;
+    if (sub) v = (load ? *d : f32x4_t{0, 0, 0, 0}) - v;
+    *d = v;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = c0 + Mfma<T>::drow(lane, q);
+      if (col >= M) continue;
+      T v = val[q];
+      if (sub) v = (load ? row[col] : (T)0) - v;
+      row[col] = v;
+    }
+  }
+}
+
+// The same values widened to FP64 into the working-precision block (columns < mw).
+template <typename T>
+__device__ inline void store_cols_f64(double* row, int c0, const typename Mfma<T>::v4& val, int mw) {
+  const int lane = threadIdx.x % 64;
+  if constexpr (sizeof(T) == 4) {
+    const int col = c0 + 4 * (lane / 16);
+    if (col + 3 < mw && (reinterpret_cast<uintptr_t>(row + col) & 15) == 0) {
+      f64x2_t* d = reinterpret_cast<f64x2_t*>(row + col);
+      d[0] = f64x2_t{(double)val[0], (double)val[1]};
+      d[1] = f64x2_t{(double)val[2], (double)val[3]};
+      return;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (col + q < mw) row[col + q] = (double)val[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = c0 + Mfma<T>::drow(lane, q);
+      if (col < mw) row[col] = val[q];
+    }
+  }
+}
+
+// Forward: out tile (64 rows x M) = P_s[r0:r0+64, k0:k1] * b_s[k0:k1, :].  A reduction step covers
+// 4 panel columns: lane (i = l % 16, g = l / 16) reads VW consecutive rows of column kc + g; element
+// w of its p-th vector is row 16 VW p + VW i + w, the A operand of row block q = VW p + w, and the
+// B operand is b_s row kc + g, columns 16 c + i.  Output row rb of block q is tile row
+// 16 VW p + VW rb + w.
+template <typename T, int M, int NP, int NCB, int U>
+struct FwdStage {
+  T a[U][NP][16 / sizeof(T)];
+  T b[U][NCB];
+};
 
 template <typename T, int M, bool WIDE>
 __global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict__ items, int64_t item_off,
@@ -123,13 +188,15 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict
   constexpr int NP = 4 / VW;
   constexpr int NCB = (M + 15) / 16;
   constexpr int NW = solve_waves<T, WIDE>();
-  __shared__ V4 red[(NW > 1 ? NW - 1 : 1) * 4 * NCB * 64];
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  constexpr int U = (sizeof(T) == 4) ? 4 : 2;   // reduction steps per stage
+  constexpr int SC = 4 * U;                       // panel columns per stage
+  __shared__ V4 red[(NW > 1 ? NW : 0) * 4 * NCB * 64 + 1];
+  // the wave index is uniform: item fields and buffer resources then live in scalar registers
+  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int i = lane % 16, g = lane / 16;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t item = (NW > 1) ? blk : blk * 4 + wave;
   if (item >= count) return;   // whole waves (NW == 1) or never (NW > 1)
-  const int ksub = (NW > 1) ? wave : 0;
   const SolveItem it = read_item(items, item_off + item);
   const int tile = it.tile, k0 = it.k0, k1 = it.k1, slot = it.slot;
   const int begin = it.begin, nr = it.nr, nc = it.nc;
@@ -137,187 +204,236 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict
   const int64_t ldp = panel_ld(nr);
   const int r0 = tile * TR;
   const int h = min(TR, nr - r0);
-  const T* pbase = panel + it.poff + r0 + VW * i;
+  const i32x4_t prs = make_rsrc(panel + it.poff, ldp * nc * (int64_t)sizeof(T));
+  const i32x4_t brs = make_rsrc(rhs + (int64_t)begin * M, (int64_t)nc * M * sizeof(T));
+  int32_t va[NP], vb[NCB];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+    va[p] = (16 * VW * p + VW * i < h) ? (int32_t)((r0 + 16 * VW * p + VW * i + g * ldp) * (int64_t)sizeof(T)) : kOob;
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) vb[c] = (16 * c + i < M) ? (int32_t)((g * M + 16 * c + i) * sizeof(T)) : kOob;
   V4 acc[4][NCB];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
-  // U reduction steps per batch: all their loads are issued before the first MFMA of the batch
-  constexpr int U = (sizeof(T) == 4) ? 8 : 4;
-  for (int kb = k0 + 4 * ksub; kb < k1; kb += 4 * NW * U) {
-    T a[U][NP][VW];
-    T b[U][NCB];
+  typedef FwdStage<T, M, NP, NCB, U> St;
+  auto load = [&](St& S, int kc) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = kb + 4 * NW * u + g;
-      const bool kok = k < k1;
+      const int ku = kc + 4 * u;
+      const bool kok = ku + g < k1;
+      const int32_t sa = (int32_t)(ku * ldp * (int64_t)sizeof(T));
+      const int32_t sb = (int32_t)((int64_t)ku * M * sizeof(T));
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        if (kok && 16 * VW * p + VW * i < h) {
-          load16(pbase + 16 * VW * p + (int64_t)k * ldp, a[u][p]);
-        } else {
+      for (int p = 0; p < NP; ++p) Buf<T>::load16(prs, kok ? va[p] : kOob, sa, S.a[u][p]);
 #pragma unroll
-          for (int w = 0; w < VW; ++w) a[u][p][w] = 0;
-        }
-      }
+      for (int c = 0; c < NCB; ++c) S.b[u][c] = Buf<T>::load1(brs, kok ? vb[c] : kOob, sb);
+    }
+  };
+  // one accumulator's U products back to back (an MFMA whose C operand is the previous MFMA's
+  // result issues without a stall), accumulators one after another
+  auto compute = [&](const St& S) {
 #pragma unroll
-      for (int c = 0; c < NCB; ++c) {
-        const int col = 16 * c + i;
-        b[u][c] = (kok && col < M) ? rhs[(int64_t)(begin + k) * M + col] : (T)0;
-      }
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int w = 0; w < VW; ++w)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+          for (int u = 0; u < U; ++u) acc[VW * p + w][c] = MF::op(S.b[u][c], S.a[u][p][w], acc[VW * p + w][c]);
+  };
+  constexpr int stride = SC * NW;
+  St cur, nxt;
+  int kc = k0 + SC * (NW > 1 ? wave : 0);
+  if (kc < k1) load(cur, kc);
+  for (; kc < k1; kc += stride) {
+    load(nxt, kc + stride);   // zeros, without memory traffic, past the end of the range
+    __builtin_amdgcn_sched_barrier(0);
+    compute(cur);
+    __builtin_amdgcn_sched_barrier(0);
+    cur = nxt;
+  }
+  // The MFMA computed D = b^T P^T: register v of lane (i, g) in block (p, w, c) is output row
+  // 16 VW p + VW i + w, column 16 c + drow(lane, v) (4 consecutive columns in FP32).
+  auto emit = [&](int p, int w, const V4 (&blk)[NCB]) {
+    const int rr = 16 * VW * p + VW * i + w;
+    if (rr >= h) return;
+    const int row = r0 + rr;
+    T* base;
+    bool sub = false;   // below row: -d = -L21 y_s, added to the gathered children's contributions
+    if (slot >= 0) {
+      base = part + ((int64_t)slot * TR + rr) * M;
+    } else if (row < nc) {
+      base = y + (int64_t)(begin + row) * M;
+    } else {
+      base = uvec + ((int64_t)it.aux + row - nc) * M;
+      sub = true;
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int c = 0; c < NCB; ++c) store_cols<T, M>(base, 16 * c, blk[c], sub, sub && parent);
+  };
+  if constexpr (NW > 1) {
+    V4 blk[NCB];
+    reduce_blocks<V4, NCB>(acc, blk, red, wave);
+    emit(wave / VW, wave % VW, blk);
+  } else {
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+    for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int w = 0; w < VW; ++w)
-#pragma unroll
-          for (int c = 0; c < NCB; ++c)
-            acc[VW * p + w][c] = MF::op(a[u][p][w], b[u][c], acc[VW * p + w][c]);
+      for (int w = 0; w < VW; ++w) emit(p, w, acc[VW * p + w]);
   }
-  if (!reduce_waves<NW>(reinterpret_cast<V4(&)[4 * NCB]>(acc), red)) return;
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-#pragma unroll
-    for (int w = 0; w < VW; ++w)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rr = 16 * VW * p + VW * MF::drow(lane, v) + w;
-        if (rr >= h) continue;
-        const int row = r0 + rr;
-        if (slot >= 0) {
-#pragma unroll
-          for (int c = 0; c < NCB; ++c) {
-            const int col = 16 * c + i;
-            if (col < M) part[((int64_t)slot * TR + rr) * M + col] = acc[VW * p + w][c][v];
-          }
-        } else if (row < nc) {
-#pragma unroll
-          for (int c = 0; c < NCB; ++c) {
-            const int col = 16 * c + i;
-            if (col < M) y[(int64_t)(begin + row) * M + col] = acc[VW * p + w][c][v];
-          }
-        } else {
-          // below row: -d = -L21 y_s, added to the children's contributions the gather pass put
-          // there when s has children
-          T* u = uvec + ((int64_t)it.aux + row - nc) * M;
-#pragma unroll
-          for (int c = 0; c < NCB; ++c) {
-            const int col = 16 * c + i;
-            if (col < M) u[col] = (parent ? u[col] : (T)0) - acc[VW * p + w][c][v];
-          }
-        }
-      }
 }
 
 // Backward: out tile (64 own columns x M) = P_s[k0:k1, j0:j0+64]^T z[k0:k1, :], z = [y_s; -x_below].
-// Lane (i, g) reads VW consecutive k (k = kc + VW g + t) of panel column j0 + 16 jb + i; MFMA t
-// pairs them with z row kc + VW g + t, so the 4 VW values of k in a step are reduced in VW MFMAs.
+// A reduction step covers 4 VW panel rows: lane (i, g) reads VW consecutive rows (k = kc + VW g + t)
+// of panel column j0 + 16 jb + i, and MFMA t pairs them with z row kc + VW g + t.  The rows of z are
+// read through the supernode's source-row list (an index into yx = [y; x]: own rows point into y,
+// below rows into x); the list entries of stage j + 2 are loaded while stage j computes, so each
+// stage's z loads can be issued as soon as the previous stage's MFMAs start.
+template <typename T, int NCB, int U>
+struct BwdStage {
+  T a[U][4][16 / sizeof(T)];
+  T b[U][16 / sizeof(T)][NCB];
+};
+template <typename T, int U>
+struct BwdIdx {
+  int32_t r[U][16 / sizeof(T)];
+};
+
 template <typename T, int M, bool WIDE>
-__global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict__ rows, const int32_t* __restrict__ items,
-                                                       int64_t item_off, int64_t count, const T* __restrict__ panel,
-                                                       const T* __restrict__ y, T* __restrict__ x, double* W,
-                                                       int64_t ldw, int mw, T* __restrict__ part) {
+__global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict__ srcrows,
+                                                       const int32_t* __restrict__ items, int64_t item_off,
+                                                       int64_t count, const T* __restrict__ panel,
+                                                       const T* __restrict__ yx, int64_t yx_rows,
+                                                       T* __restrict__ x, double* W, int64_t ldw, int mw,
+                                                       T* __restrict__ part) {
   typedef Mfma<T> MF;
   typedef typename MF::v4 V4;
   constexpr int VW = 16 / sizeof(T);
   constexpr int NCB = (M + 15) / 16;
   constexpr int NW = solve_waves<T, WIDE>();
-  __shared__ V4 red[(NW > 1 ? NW - 1 : 1) * 4 * NCB * 64];
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  constexpr int U = 1;             // reduction steps per stage
+  constexpr int SR = 4 * VW * U;   // panel rows per stage
+  __shared__ V4 red[(NW > 1 ? NW : 0) * 4 * NCB * 64 + 1];
+  // the wave index is uniform: item fields and buffer resources then live in scalar registers
+  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int i = lane % 16, g = lane / 16;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t item = (NW > 1) ? blk : blk * 4 + wave;
   if (item >= count) return;
-  const int ksub = (NW > 1) ? wave : 0;
   const SolveItem it = read_item(items, item_off + item);
   const int tile = it.tile, k0 = it.k0, k1 = it.k1, slot = it.slot;
   const int begin = it.begin, nc = it.nc, nr = it.nr;
   const int64_t ldp = panel_ld(nr);
-  const int64_t roff = it.aux;
   const int j0 = tile * TR;
   const int h = min(TR, nc - j0);
-  const T* pbase = panel + it.poff + (int64_t)(j0 + i) * ldp + VW * g;
+  const i32x4_t prs = make_rsrc(panel + it.poff, ldp * nc * (int64_t)sizeof(T));
+  const i32x4_t irs = make_rsrc(srcrows + it.aux, panel_ld(nr) * (int64_t)sizeof(int32_t));
+  const i32x4_t zrs = make_rsrc(yx, yx_rows * M * (int64_t)sizeof(T));
+  int32_t va[4];
+#pragma unroll
+  for (int jb = 0; jb < 4; ++jb)
+    va[jb] = (16 * jb + i < h) ? (int32_t)(((j0 + 16 * jb + i) * ldp + VW * g) * (int64_t)sizeof(T)) : kOob;
+  const int32_t vi = VW * g * (int32_t)sizeof(int32_t);
   V4 acc[4][NCB];
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[q][c] = V4{0, 0, 0, 0};
-  // U reduction steps (of 4 VW rows) per batch: panel loads and the row indices of the gathered
-  // operand first, then the operand rows, then the MFMAs
-  constexpr int U = (sizeof(T) == 4) ? 4 : 2;
-  for (int kb = k0 + 4 * VW * ksub; kb < k1; kb += 4 * VW * NW * U) {
-    T a[U][4][VW];
-    int src_row[U][VW];
+  typedef BwdStage<T, NCB, U> St;
+  typedef BwdIdx<T, U> Ix;
+  auto load_idx = [&](Ix& I, int kc) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int kc = kb + 4 * VW * NW * u;
-      const int kk = kc + VW * g;
-#pragma unroll
-      for (int jb = 0; jb < 4; ++jb) {
-        if (kk < k1 && 16 * jb + i < h) {
-          load16(pbase + (int64_t)(16 * jb) * ldp + kc, a[u][jb]);
-        } else {
-#pragma unroll
-          for (int t = 0; t < VW; ++t) a[u][jb][t] = 0;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < VW; ++t) {
-        const int k = kk + t;
-        // own rows read y at begin + k; below rows read -x at the listed row; -1 = past the range
-        src_row[u][t] = (k >= k1) ? -1 : (k < nc ? begin + k : rows[roff + k]);
-      }
+      const int ku = kc + 4 * VW * u;
+      Buf<T>::load_idx(irs, ku + VW * g < k1 ? vi : kOob, ku * (int32_t)sizeof(int32_t), I.r[u]);
     }
-    T b[U][VW][NCB];
+  };
+  auto load = [&](St& S, const Ix& I, int kc) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int kk = kb + 4 * VW * NW * u + VW * g;
+      const int ku = kc + 4 * VW * u;
+      const bool kok = ku + VW * g < k1;
+      const int32_t sa = ku * (int32_t)sizeof(T);
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) Buf<T>::load16(prs, kok ? va[jb] : kOob, sa, S.a[u][jb]);
 #pragma unroll
       for (int t = 0; t < VW; ++t) {
-        const int r = src_row[u][t];
-        const bool own = (kk + t < nc);
-        const T* src = own ? y : x;
+        const bool ok = ku + VW * g + t < k1;
 #pragma unroll
         for (int c = 0; c < NCB; ++c) {
           const int col = 16 * c + i;
-          const T v = (r >= 0 && col < M) ? src[(int64_t)r * M + col] : (T)0;
-          b[u][t][c] = own ? v : -v;
+          const int32_t off = (ok && col < M) ? (int32_t)(((int64_t)I.r[u][t] * M + col) * sizeof(T)) : kOob;
+          S.b[u][t][c] = Buf<T>::load1(zrs, off, 0);
         }
       }
     }
+  };
+  auto compute = [&](St& S, int kc) {
+    // own rows (k < nc) contribute +y, below rows -x
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int t = 0; t < VW; ++t)
+      for (int t = 0; t < VW; ++t) {
+        const bool own = kc + 4 * VW * u + VW * g + t < nc;
 #pragma unroll
-        for (int jb = 0; jb < 4; ++jb)
+        for (int c = 0; c < NCB; ++c) S.b[u][t][c] = own ? S.b[u][t][c] : -S.b[u][t][c];
+      }
+    // one accumulator's products back to back, accumulators one after another
 #pragma unroll
-          for (int c = 0; c < NCB; ++c) acc[jb][c] = MF::op(a[u][jb][t], b[u][t][c], acc[jb][c]);
+    for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+      for (int c = 0; c < NCB; ++c)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int t = 0; t < VW; ++t) acc[jb][c] = MF::op(S.b[u][t][c], S.a[u][jb][t], acc[jb][c]);
+  };
+  constexpr int stride = SR * NW;
+  St cur, nxt;
+  Ix i1, i2;   // source rows of the next stage and of the one after
+  int kc = k0 + SR * (NW > 1 ? wave : 0);
+  if (kc < k1) {
+    load_idx(i1, kc);
+    load_idx(i2, kc + stride);
+    load(cur, i1, kc);
+    i1 = i2;
+    load_idx(i2, kc + 2 * stride);
   }
-  if (!reduce_waves<NW>(reinterpret_cast<V4(&)[4 * NCB]>(acc), red)) return;
+  for (; kc < k1; kc += stride) {
+    load(nxt, i1, kc + stride);
+    i1 = i2;
+    load_idx(i2, kc + 3 * stride);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(cur, kc);
+    __builtin_amdgcn_sched_barrier(0);
+    cur = nxt;
+  }
+  // D = z^T P: register v of lane (i, g) in block (jb, c) is own column 16 jb + i of the tile,
+  // right-hand side 16 c + drow(lane, v)
+  auto emit = [&](int jb, const V4 (&blk)[NCB]) {
+    const int jj = 16 * jb + i;
+    if (jj >= h) return;
+    const int64_t row = begin + j0 + jj;
 #pragma unroll
-  for (int jb = 0; jb < 4; ++jb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int jj = 16 * jb + MF::drow(lane, v);
-      if (jj >= h) continue;
-      const int64_t row = begin + j0 + jj;
-#pragma unroll
-      for (int c = 0; c < NCB; ++c) {
-        const int col = 16 * c + i;
-        if (col >= M) continue;
-        const T val = acc[jb][c][v];
-        if (slot >= 0) {
-          part[((int64_t)slot * TR + jj) * M + col] = val;
-        } else {
-          x[row * M + col] = val;
-          if (W && col < mw) W[row * ldw + col] = (double)val;
-        }
+    for (int c = 0; c < NCB; ++c) {
+      if (slot >= 0) {
+        store_cols<T, M>(part + ((int64_t)slot * TR + jj) * M, 16 * c, blk[c], false, false);
+      } else {
+        store_cols<T, M>(x + row * M, 16 * c, blk[c], false, false);
+        if (W) store_cols_f64<T>(W + row * ldw, 16 * c, blk[c], mw);
       }
     }
+  };
+  if constexpr (NW > 1) {
+    V4 blk[NCB];
+    reduce_blocks<V4, NCB>(acc, blk, red, wave);
+    emit(wave, blk);
+  } else {
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) emit(jb, acc[jb]);
+  }
 }
 
 
@@ -386,9 +502,10 @@ void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* pan
                  T* fpart, T* bpart, double* W, int64_t ldw, int mw, bool forward, hipStream_t st) {
   if (forward) {
     const int64_t a0 = Sd.gather_level_off[level], a1 = Sd.gather_level_off[level + 1];
+    constexpr int rows_per_block = 4 * 64 / (M * (int)sizeof(T) / 16);
     if (a1 > a0)
-      fwd_gather_kernel<T><<<(unsigned)((a1 - a0 + 3) / 4), 256, 0, st>>>(Sd.gather_dst, Sd.gather_ptr, Sd.gather_src,
-                                                                          a0, a1 - a0, rhs, uvec, M);
+      fwd_gather_kernel<T, M><<<(unsigned)((a1 - a0 + rows_per_block - 1) / rows_per_block), 256, 0, st>>>(
+          Sd.gather_dst, Sd.gather_ptr, Sd.gather_src, a0, a1 - a0, rhs, uvec);
     const int64_t f0 = Sd.fwd_level_off[level], f1 = Sd.fwd_level_off[level + 1];
     const int64_t fn = f1 - f0;
     if (fn > 0 && Sd.fwd_wide[level])
@@ -403,12 +520,14 @@ void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* pan
   } else {
     const int64_t b0 = Sd.bwd_level_off[level], b1 = Sd.bwd_level_off[level + 1];
     const int64_t bn = b1 - b0;
+    // x follows y in one allocation: the backward operand z is read through one buffer resource
+    const int64_t yx_rows = 2 * Sd.n;
     if (bn > 0 && Sd.bwd_wide[level])
       bwd_mfma_kernel<T, M, true><<<(unsigned)(solve_waves<T, true>() > 1 ? bn : (bn + 3) / 4), 256, 0, st>>>(
-          D.rows, Sd.bwd_items, b0, bn, panel, y, x, W, ldw, mw, bpart);
+          Sd.bwd_src, Sd.bwd_items, b0, bn, panel, y, yx_rows, x, W, ldw, mw, bpart);
     else if (bn > 0)
-      bwd_mfma_kernel<T, M, false><<<(unsigned)((bn + 3) / 4), 256, 0, st>>>(D.rows, Sd.bwd_items, b0, bn, panel, y,
-                                                                              x, W, ldw, mw, bpart);
+      bwd_mfma_kernel<T, M, false><<<(unsigned)((bn + 3) / 4), 256, 0, st>>>(
+          Sd.bwd_src, Sd.bwd_items, b0, bn, panel, y, yx_rows, x, W, ldw, mw, bpart);
     const int64_t g0 = Sd.bwd_fin_level_off[level], g1 = Sd.bwd_fin_level_off[level + 1];
     if (g1 > g0)
       bwd_fin_kernel<T, M><<<dim3((unsigned)(g1 - g0), TR * M / 256), 256, 0, st>>>(D, Sd.bwd_fin, g0, bpart, x, W,

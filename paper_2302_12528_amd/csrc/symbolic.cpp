@@ -483,6 +483,14 @@ void build_solve_plan(const Symbolic& S, int rpt, int split_target, SolvePlan& P
   P.fwd_fin_level_off.assign(S.nlevels + 1, 0);
   P.bwd_fin_level_off.assign(S.nlevels + 1, 0);
   P.gather_ptr.push_back(0);
+  P.bwd_src_off.assign(S.nsuper, 0);
+  for (int s = 0; s < S.nsuper; ++s) {
+    P.bwd_src_off[s] = (int64_t)P.bwd_src.size();
+    const int nc = S.nc[s], nr = S.nr[s];
+    for (int k = 0; k < nr; ++k)
+      P.bwd_src.push_back(k < nc ? S.begin[s] + k : (int32_t)(S.n + S.rows[S.row_off[s] + k]));
+    P.bwd_src.resize((size_t)(P.bwd_src_off[s] + panel_ld(nr)), 0);
+  }
   // chunks of the reduction range [k0, k1) for a tile, nch wanted
   int maxk = 0;   // longest reduction range of the level being built
   auto emit = [&](std::vector<int32_t>& items, std::vector<int32_t>& fin, int64_t& slots, int s, int t, int k0,
@@ -493,7 +501,7 @@ void build_solve_plan(const Symbolic& S, int rpt, int split_target, SolvePlan& P
     nch = (len + chunk - 1) / chunk;
     const int64_t po = S.panel_off[s];
     const int32_t meta[7] = {S.begin[s], S.nr[s], S.nc[s], (int32_t)(po & 0xffffffff), (int32_t)(po >> 32),
-                             (int32_t)(fwd ? S.uvec_off[s] : S.row_off[s]),
+                             (int32_t)(fwd ? S.uvec_off[s] : P.bwd_src_off[s]),
                              (int32_t)(S.child_ptr[s + 1] > S.child_ptr[s] ? 1 : 0)};
     auto push = [&](int a, int b, int slot) {
       items.insert(items.end(), {s, t, a, b, slot});
@@ -581,7 +589,7 @@ std::string verify_solve_plan(const Symbolic& S, const SolvePlan& P) {
       if (s >= 0 && s < ns) {
         const int64_t po = (int64_t)(uint32_t)items[q + 8] | ((int64_t)items[q + 9] << 32);
         if (items[q + 5] != S.begin[s] || items[q + 6] != S.nr[s] || items[q + 7] != S.nc[s] ||
-            po != S.panel_off[s] || items[q + 10] != (fwd ? S.uvec_off[s] : S.row_off[s]) ||
+            po != S.panel_off[s] || items[q + 10] != (fwd ? S.uvec_off[s] : P.bwd_src_off[s]) ||
             items[q + 11] != (S.child_ptr[s + 1] > S.child_ptr[s] ? 1 : 0))
           return "solve item metadata";
       }
@@ -600,6 +608,15 @@ std::string verify_solve_plan(const Symbolic& S, const SolvePlan& P) {
     }
     return "";
   };
+  if ((int)P.bwd_src_off.size() != ns) return "backward source list offsets";
+  for (int s = 0; s < ns; ++s) {
+    const int64_t o = P.bwd_src_off[s];
+    if (o % 4 != 0 || o < 0 || o + panel_ld(S.nr[s]) > (int64_t)P.bwd_src.size()) return "backward source list range";
+    for (int k = 0; k < S.nr[s]; ++k) {
+      const int32_t v = P.bwd_src[o + k];
+      if (v < 0 || v >= 2 * S.n || (k < S.nc[s]) != (v < S.n)) return "backward source row";
+    }
+  }
   if (P.gather_ptr.size() != P.gather_dst.size() + 1 || P.gather_ptr[0] != 0 ||
       (size_t)P.gather_ptr.back() != P.gather_src.size())
     return "gather list sizes";

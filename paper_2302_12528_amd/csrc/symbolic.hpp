@@ -96,14 +96,18 @@ struct SolvePlan {
   // are update-vector rows of the children
   std::vector<int32_t> gather_dst, gather_ptr, gather_src; std::vector<int64_t> gather_level_off;
   // items: kSolveItemInts ints each: s, tile, k0, k1, slot, begin, nr, nc, panel offset (low,
-  // high 32 bits), update-vector offset (forward) or row-list offset (backward), flags (bit 0: s
-  // has children)
+  // high 32 bits), update-vector offset (forward) or source-row list offset (backward), flags
+  // (bit 0: s has children)
   std::vector<int32_t> fwd_items;  std::vector<int64_t> fwd_level_off;
   std::vector<char> fwd_wide, bwd_wide;   // per level: items long enough to split over four waves
   std::vector<int32_t> fwd_fin;    std::vector<int64_t> fwd_fin_level_off; // 4 ints: s, tile, slot0, nchunks
   std::vector<int32_t> bwd_items;  std::vector<int64_t> bwd_level_off;
   std::vector<int32_t> bwd_fin;    std::vector<int64_t> bwd_fin_level_off;
   int64_t fwd_slots = 0, bwd_slots = 0;
+  // backward operand source rows: supernode s owns panel_ld(nr) entries from bwd_src_off[s] (a
+  // multiple of 4, the backward items' aux field); entry k < nc is begin + k (a row of y), entry
+  // nc <= k < nr is n + rows[row_off + k] (a row of x, stored after y), the padding is 0
+  std::vector<int32_t> bwd_src; std::vector<int64_t> bwd_src_off;
 };
 void build_solve_plan(const Symbolic& S, int rows_per_tile, int split_target, SolvePlan& plan);
 
