@@ -364,8 +364,8 @@ lobpcg_status factor_t(lobpcg_ctx c) {
   T* lcopy = static_cast<T*>(c->lcopy);
   for (const FactorPlan::Step& s : c->FP.steps) {
     const int64_t a0 = c->FP.asm_level_off[s.level], a1 = c->FP.asm_level_off[s.level + 1];
-    launch_factor_step<T>(c->FD, s.kind, s.level, s.off, s.count, a0, a1 - a0, panel, upd, dinv, lcopy, c->d_flag,
-                          c->st);
+    launch_factor_step<T>(c->FD, s.kind, c->FP.level_max_nr[s.level], s.off, s.count, a0, a1 - a0, panel, upd, dinv,
+                          lcopy, c->d_flag, c->st);
   }
   return check_launch("factorization");
 }

@@ -97,8 +97,9 @@ struct FactorDev {
   const double* dense; int64_t ld_dense; int is_dense; int max_nr;
   int32_t* asm_items; int32_t* tasks;
 };
+// level_max_nr: the largest front of the step's level (sizes the assembly's LDS column buffer)
 template <typename T>
-void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_off, int count,
+void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t task_off, int count,
                         int64_t asm_off, int64_t asm_count, T* panel, T* upd, T* dinv, T* lcopy, int* flag,
                         hipStream_t st);
 

@@ -14,6 +14,7 @@
 //             the tiles below it, symmetric update of the trailing tiles;
 //   inverse   panel <- [I; L21] inv(L11) = [inv(L11); L21 inv(L11)], so that
 //             each solve is one product per supernode (see k_trisolve.hip).
+#include "bufload.hpp"
 #include "common.hpp"
 #include "mfma.hpp"
 #include "symbolic.hpp"
@@ -166,63 +167,146 @@ __device__ inline void load_cm_t(T (*Bs)[TB + 1], const T* M, int64_t ld, int K,
   }
 }
 
-// Cholesky of the h x h diagonal tile (p, p) and the inverse of its factor, by one wave.
-// Lane i holds row i of the tile in registers (rows/columns >= h padded with the identity);
-// column j is eliminated with uniform reads of the pivot and of column j; the inverse is
-// formed column by column (lane j owns column j) from L staged in LDS.
+// Task (s, I, p) of a panel step: the Cholesky factor L_pp of diagonal tile (p, p) and its inverse
+// are formed in the workgroup (every task of the step repeats this small computation, so the step
+// needs one launch); the task with I == p writes L_pp and inv(L_pp), every other task replaces its
+// tile (I, p) by C inv(L_pp)^T.  Rows and columns of the tile at or beyond h are padded with the
+// identity.
+//   factorization: thread (row i, quarter w) holds row i, columns 16 w .. 16 w + 15 in registers;
+//     column j is published through LDS by the owning quarter and every thread applies the rank-1
+//     update to its columns past j (one barrier per column);
+//   inverse: X = inv(L) by forward substitution on the identity inside the same column loop, each
+//     quarter for its 16 columns, row j broadcast across the wave with readlane.
 template <typename T>
-__global__ void __launch_bounds__(64) potrf_kernel(FactorDev D, int64_t task_off, T* panel, T* upd, T* dinv,
-                                                   int* flag) {
-  __shared__ T Ls[TB][TB + 1];
-  const int* tk = D.tasks + 4 * (task_off + blockIdx.x);
-  const int s = tk[0], p = tk[3];
+__global__ void __launch_bounds__(256) potrf_trsm_kernel(FactorDev D, int64_t task_off, T* panel, T* upd,
+                                                         T* dinv, int* flag) {
+  __shared__ T Ls[TB][TB + 1];   // the K-major tile C(I, p)
+  __shared__ T Xs[TB][TB + 1];   // Xs[k][c] = inv(L)[c][k]
+  __shared__ T colbuf[2][TB];
+  const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
+  const int s = tk[0], I = tk[1], p = tk[3];
   const Sn S = sn_of(D, s);
   const int r0 = p * TB, h = min(TB, S.nc - r0);
   int64_t ld;
   T* tile = front_ptr(panel, upd, S, r0, r0, ld);
-  const int lane = threadIdx.x;
-  T a[TB];
+  const int tid = threadIdx.x, i = tid % 64, w = __builtin_amdgcn_readfirstlane(tid / 64);
+  // tile (I, p) of the trsm, loaded early so that its latency hides behind the factorization
+  int rI, hI;
+  tile_rows(S, I, rI, hI);
+  int64_t ldc;
+  T* C = front_ptr(panel, upd, S, rI, r0, ldc);
+  T cv[16];
+  if (I != p) {
 #pragma unroll
-  for (int j = 0; j < TB; ++j) a[j] = (lane < h && j < h) ? tile[lane + (int64_t)j * ld] : (lane == j ? (T)1 : (T)0);
-  int bad = 0;
-#pragma unroll
-  for (int j = 0; j < TB; ++j) {
-    T d = rdl(a[j], j);
-    if (!(d > (T)0) || !isfinite((double)d)) {
-      if (bad == 0) bad = j + 1;
-      d = (T)1;
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q, r = e % TB, k = e / TB;
+      cv[q] = (r < hI && k < h) ? C[r + (int64_t)k * ldc] : (T)0;
     }
-    const T ljj = sqrt(d);
-    const T rinv = (T)1 / ljj;
-    const T l = (lane > j) ? a[j] * rinv : (lane == j ? ljj : (T)0);
-    a[j] = l;
-#pragma unroll
-    for (int k = j + 1; k < TB; ++k) a[k] -= l * rdl(l, k);
   }
-  if (bad != 0 && lane == 0 && bad <= h) flag[0] = S.begin + r0 + bad;
+  T a[16];
 #pragma unroll
-  for (int j = 0; j < TB; ++j) {
-    const T v = (j <= lane) ? a[j] : (T)0;
-    Ls[lane][j] = v;
-    if (lane < h && j < h) tile[lane + (int64_t)j * ld] = v;
+  for (int kk = 0; kk < 16; ++kk) {
+    const int c = 16 * w + kk;
+    a[kk] = (i < h && c < h) ? tile[i + (int64_t)c * ld] : (i == c ? (T)1 : (T)0);
+  }
+  int bad = 0;
+  // the outer loop stays rolled: this kernel runs once per panel step, so its code is fetched cold
+  // each time and must stay short
+  // x: row i, columns 16 w .. 16 w + 15 of X = inv(L), formed alongside: step j scales row j of X by
+  // 1 / L[j][j] and subtracts L[i][j] times it from the rows below (forward substitution on the
+  // identity); only quarters w <= j / 16 hold nonzero columns of row j
+  T x[16];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) x[kk] = (i == 16 * w + kk) ? (T)1 : (T)0;
+#pragma unroll 1
+  for (int jb = 0; jb < 4; ++jb) {
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * jb + jj;
+      T* cb = colbuf[jj & 1];
+      if (w == jb) cb[i] = a[jj];
+      __syncthreads();
+      T d = cb[j];
+      const bool ok = (d > (T)0) && (d < (T)INFINITY);
+      if (!ok) d = (T)1;
+      const T ljj = sqrt(d);
+      const T rinv = (T)1 / ljj;
+      const T li = cb[i] * rinv;
+      const T lb = (i > j) ? li : (T)0;
+      if (w > jb) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) a[kk] -= li * (cb[16 * w + kk] * rinv);
+      } else if (w == jb) {
+        if (!ok && bad == 0) bad = j + 1;
+#pragma unroll
+        for (int kk = jj + 1; kk < 16; ++kk) a[kk] -= li * (cb[16 * w + kk] * rinv);
+        a[jj] = (i > j) ? li : (i == j ? ljj : (T)0);
+#pragma unroll
+        for (int kk = 0; kk <= jj; ++kk) {
+          if (i == j) x[kk] *= rinv;
+          x[kk] -= lb * rdl(x[kk], j);
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          if (i == j) x[kk] *= rinv;
+          x[kk] -= lb * rdl(x[kk], j);
+        }
+      }
+    }
+  }
+  if (I == p && bad != 0 && i == 0 && bad <= h) flag[0] = S.begin + r0 + bad;
+  // L_pp goes to its staging slot (column-major, ld 64); the update step moves it into the panel
+  T* lstage = dinv + D.dinv_off[s] + (int64_t)(S.np + p) * TB * TB;
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    const int c = 16 * w + kk;
+    if (I == p) lstage[i + TB * c] = (c <= i) ? a[kk] : (T)0;
+  }
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) Xs[16 * w + kk][i] = x[kk];
+  if (I == p) {
+    T* di = dinv + D.dinv_off[s] + (int64_t)p * TB * TB;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int c = 16 * w + kk;
+      di[i + TB * c] = (i < h && c < h) ? x[kk] : (T)0;
+    }
+    return;
+  }
+  auto& As = Ls;   // As[k][r] = C(r, k)
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, r = e % TB, k = e / TB;
+    As[k][r] = cv[q];
   }
   __syncthreads();
-  // column `lane` of inv(L): forward substitution, L read from LDS (uniform addresses)
-  T x[TB];
+  typename Mfma<T>::v4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < TB; ++i) {
-    T sacc = (i == lane) ? (T)1 : (T)0;
+  for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int k = 0; k < i; ++k) sacc -= Ls[i][k] * x[k];
-    x[i] = sacc / Ls[i][i];
-  }
-  T* di = dinv + D.dinv_off[s] + (int64_t)p * TB * TB;
+    for (int a2 = 0; a2 < 2; ++a2)
 #pragma unroll
-  for (int i = 0; i < TB; ++i) di[i + TB * lane] = (i < h && lane < h) ? x[i] : (T)0;
+      for (int q = 0; q < 4; ++q) acc[b][a2][q] = 0;
+  tile_mfma<T>(As, Xs, (h + 3) & ~3, acc);
+  const int lane = tid % 64;
+  const int qr = (w / 2) * 32, qc = (w % 2) * 32;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a2 = 0; a2 < 2; ++a2) {
+      const int r = qr + 16 * a2 + lane % 16;
+      if (r >= hI) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = qc + 16 * b + Mfma<T>::drow(lane, q);
+        if (c < h) C[r + (int64_t)c * ldc] = acc[b][a2][q];
+      }
+    }
 }
 
 // kind 0: trsm   C = C dinv_p^T            (task s, I, p, p)
-// kind 1: update C(I,J) -= C(I,p) C(J,p)^T   (task s, I, J, p)
+// kind 1: update C(I,J) -= C(I,p) C(J,p)^T   (task s, I, J, p); task (s, p, p, p) stores L_pp
 // kind 2: invscale C(I,q) = C(I,q) dinv_q, or dinv_q itself when I == q
 // kind 3: invupdate C(I,r) -= C(I,q) Lcopy(q, r)
 template <typename T, int KIND>
@@ -241,6 +325,14 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
   int64_t ldc, lda;
   T* C = front_ptr(panel, upd, S, rI, rJ, ldc);            // tile (I, J): rows hI, cols hJ
   const T* di = dinv + D.dinv_off[s] + (int64_t)p * TB * TB;
+  if (KIND == 1 && I == p && J == p) {   // L_pp from its staging slot into tile (p, p)
+    const T* ls = di + (int64_t)S.np * TB * TB;
+    for (int e = tid; e < TB * TB; e += 256) {
+      const int r = e % TB, c = e / TB;
+      if (r < hI && c < hJ) C[r + (int64_t)c * ldc] = ls[r + TB * c];
+    }
+    return;
+  }
   int K = 0;
   if (KIND == 0) {              // C(I,p) dinv_p^T, K = wP
     K = wP;
@@ -302,6 +394,105 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
     }
 }
 
+// Schur complement tile (I, J) of U_s (I >= J >= np): C -= L(I, :) L(J, :)^T over all nc panel
+// columns, 64 at a time through LDS, accumulated in registers; C is read and written once.  The
+// next 64-column chunk is loaded into registers (16-byte loads of 4 consecutive rows) while the
+// current one is multiplied.
+template <typename T>
+struct Chunk4 {
+  T v[4][4];   // 4 vectors of 4 consecutive rows: element e = tid + 256 q is rows 4 (e % 16) .. + 3 of column e / 16
+};
+// vec: M and ld * sizeof(T) are multiples of 16 bytes (rows below the own columns start at nc,
+// which need not be a multiple of 4; such tiles take scalar loads)
+template <typename T>
+__device__ inline void chunk_load(Chunk4<T>& c, const T* M, int64_t ld, int h, int K, bool vec) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q, k = e / 16, r = 4 * (e % 16);
+    if (k < K && r < h) {
+      const T* src = M + r + (int64_t)k * ld;
+      if (!vec) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c.v[q][j] = (r + j < h) ? src[j] : (T)0;
+      } else if constexpr (sizeof(T) == 4) {
+        const f32x4_t x = *reinterpret_cast<const f32x4_t*>(src);
+        c.v[q][0] = x.x; c.v[q][1] = x.y; c.v[q][2] = x.z; c.v[q][3] = x.w;
+      } else {
+        const f64x2_t x0 = *reinterpret_cast<const f64x2_t*>(src), x1 = *reinterpret_cast<const f64x2_t*>(src + 2);
+        c.v[q][0] = x0.x; c.v[q][1] = x0.y; c.v[q][2] = x1.x; c.v[q][3] = x1.y;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c.v[q][j] = (T)0;
+    }
+  }
+}
+template <typename T>
+__device__ inline void chunk_store(const Chunk4<T>& c, T (*As)[TB + 1]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q, k = e / 16, r = 4 * (e % 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) As[k][r + j] = c.v[q][j];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) schur_kernel(FactorDev D, int64_t task_off, T* panel, T* upd) {
+  __shared__ T As[TB][TB + 1];
+  __shared__ T Bs[TB][TB + 1];
+  const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
+  const int s = tk[0], I = tk[1], J = tk[2];
+  const Sn S = sn_of(D, s);
+  int rI, hI, rJ, hJ;
+  tile_rows(S, I, rI, hI);
+  tile_rows(S, J, rJ, hJ);
+  int64_t ldc;
+  T* C = front_ptr(panel, upd, S, rI, rJ, ldc);
+  const int64_t ldp = panel_ld(S.nr);
+  const T* Ap = panel + S.panel + rI;   // L(rI + r, k) = Ap[r + k ldp]
+  const T* Bp = panel + S.panel + rJ;
+  typename Mfma<T>::v4 acc[2][2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[b][a][q] = 0;
+  const bool va = ((reinterpret_cast<uintptr_t>(Ap) | (uintptr_t)(ldp * sizeof(T))) & 15) == 0;
+  const bool vb = ((reinterpret_cast<uintptr_t>(Bp) | (uintptr_t)(ldp * sizeof(T))) & 15) == 0;
+  Chunk4<T> na, nb;
+  chunk_load(na, Ap, ldp, hI, min(TB, S.nc), va);
+  chunk_load(nb, Bp, ldp, hJ, min(TB, S.nc), vb);
+  for (int k0 = 0; k0 < S.nc; k0 += TB) {
+    const int K = min(TB, S.nc - k0);
+    __syncthreads();   // the previous chunk's products are done with As, Bs
+    chunk_store(na, As);
+    chunk_store(nb, Bs);
+    __syncthreads();
+    if (k0 + TB < S.nc) {
+      const int K2 = min(TB, S.nc - k0 - TB);
+      chunk_load(na, Ap + (int64_t)(k0 + TB) * ldp, ldp, hI, K2, va);
+      chunk_load(nb, Bp + (int64_t)(k0 + TB) * ldp, ldp, hJ, K2, vb);
+    }
+    tile_mfma<T>(As, Bs, (K + 3) & ~3, acc);
+  }
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int qr = (w / 2) * 32, qc = (w % 2) * 32;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int r = qr + 16 * a + lane % 16;
+      if (r >= hI) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = qc + 16 * b + Mfma<T>::drow(lane, q);
+        if (c < hJ) C[r + (int64_t)c * ldc] -= acc[b][a][q];
+      }
+    }
+}
+
 // Copy L11 column t (rows t..nc-1) to the level scratch and clear the panel's own part of column t.
 template <typename T>
 __global__ void __launch_bounds__(256) invprep_kernel(FactorDev D, int64_t task_off, int64_t count, T* panel,
@@ -324,13 +515,12 @@ __global__ void __launch_bounds__(256) invprep_kernel(FactorDev D, int64_t task_
 }  // namespace
 
 template <typename T>
-void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_off, int count, int64_t asm_off,
+void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t task_off, int count, int64_t asm_off,
                         int64_t asm_count, T* panel, T* upd, T* dinv, T* lcopy, int* flag, hipStream_t st) {
-  (void)level;
   switch (kind) {
     case kAssemble:
       if (asm_count > 0) {
-        const size_t lds = D.is_dense ? 0 : (size_t)D.max_nr * sizeof(T);
+        const size_t lds = D.is_dense ? 0 : (size_t)level_max_nr * sizeof(T);
         if (lds > 65536)
           (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&assemble_kernel<T>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -338,13 +528,16 @@ void launch_factor_step(const FactorDev& D, int kind, int level, int64_t task_of
       }
       break;
     case kPotrf:
-      potrf_kernel<T><<<count, 64, 0, st>>>(D, task_off, panel, upd, dinv, flag);
+      potrf_trsm_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, flag);
       break;
     case kTrsm:
       tile_kernel<T, 0><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, lcopy);
       break;
     case kUpdate:
       tile_kernel<T, 1><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, lcopy);
+      break;
+    case kSchur:
+      schur_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd);
       break;
     case kInvPrep:
       invprep_kernel<T><<<(unsigned)((count + 3) / 4), 256, 0, st>>>(D, task_off, count, panel, lcopy);

@@ -310,7 +310,7 @@ std::string analyze_multi(int64_t n, const int32_t* rowptr, const int32_t* colin
     S.panel_off[s + 1] = S.panel_off[s] + panel_ld(r) * c;
     S.upd_off[s + 1] = S.upd_off[s] + b * b;
     S.uvec_off[s + 1] = S.uvec_off[s] + b;
-    S.dinv_off[s + 1] = S.dinv_off[s] + np * kTile * kTile;
+    S.dinv_off[s + 1] = S.dinv_off[s] + 2 * np * kTile * kTile;   // inv(L_pp) tiles, then L_pp tiles
     S.nnz_lower += (double)c * (c + 1) / 2 + (double)b * c;
     for (int64_t j = 0; j < c; ++j) {
       double cj = (double)(r - j - 1);
@@ -399,6 +399,9 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
       for (int t = 0; t < S.nr[s]; ++t) { P.asm_items.push_back(s); P.asm_items.push_back(t); }
     }
     P.asm_level_off[l + 1] = (int64_t)P.asm_items.size() / 2;
+    int lmax = 0;
+    for (int32_t q = q0; q < q1; ++q) lmax = std::max(lmax, S.nr[S.level_sn[q]]);
+    P.level_max_nr.push_back(lmax);
     int maxnp = 0;
     for (int32_t q = q0; q < q1; ++q) maxnp = std::max(maxnp, ntiles(S.nc[S.level_sn[q]]));
     auto begin_step = [&](int kind) {
@@ -418,30 +421,40 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
     push(l, 0, 0, 0);   // one marker task: the assembly kernel reads asm_items of level l
     end_step();
     for (int p = 0; p < maxnp; ++p) {
+      // diagonal tile p and the tiles below it in one step: task (s, p, p, p) writes L_pp and its
+      // inverse, tasks (s, I > p, p, p) the trsm of tile (I, p)
       begin_step(kPotrf);
-      for (int32_t q = q0; q < q1; ++q) {
-        int s = S.level_sn[q];
-        if (ntiles(S.nc[s]) > p) push(s, p, p, p);
-      }
-      end_step();
-      begin_step(kTrsm);
       for (int32_t q = q0; q < q1; ++q) {
         int s = S.level_sn[q];
         int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
         if (np > p)
-          for (int I = p + 1; I < rt; ++I) push(s, I, p, p);
+          for (int I = p; I < rt; ++I) push(s, I, p, p);
       }
       end_step();
+      // trailing update of the panel columns; task (s, p, p, p) moves L_pp from its staging slot
+      // into the panel (the panel step's other tasks read the unfactored tile (p, p) while it is
+      // formed)
       begin_step(kUpdate);
       for (int32_t q = q0; q < q1; ++q) {
         int s = S.level_sn[q];
         int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
-        if (np > p)
-          for (int J = p + 1; J < rt; ++J)
+        if (np > p) {
+          push(s, p, p, p);
+          for (int J = p + 1; J < np; ++J)
             for (int I = J; I < rt; ++I) push(s, I, J, p);
+        }
       }
       end_step();
     }
+    // Schur complement U_s -= L21 L21^T, once, with the whole reduction range nc per tile
+    begin_step(kSchur);
+    for (int32_t q = q0; q < q1; ++q) {
+      int s = S.level_sn[q];
+      int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+      for (int J = np; J < rt; ++J)
+        for (int I = J; I < rt; ++I) push(s, I, J, 0);
+    }
+    end_step();
     // inverse phase: P_s = [I; L21] inv(L11)
     begin_step(kInvPrep);
     for (int32_t q = q0; q < q1; ++q) {
@@ -661,7 +674,7 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
     if (S.panel_off[s + 1] - S.panel_off[s] != panel_ld(nr) * nc) return "panel_off";
     if (S.upd_off[s + 1] - S.upd_off[s] != (int64_t)nb * nb) return "upd_off";
     if (S.uvec_off[s + 1] - S.uvec_off[s] != nb) return "uvec_off";
-    if (S.dinv_off[s + 1] - S.dinv_off[s] != (int64_t)ntiles(nc) * kTile * kTile) return "dinv_off";
+    if (S.dinv_off[s + 1] - S.dinv_off[s] != 2 * (int64_t)ntiles(nc) * kTile * kTile) return "dinv_off";
     if (S.lcopy_off[s] < 0 || S.lcopy_off[s] + (int64_t)nc * nc > S.lcopy_max) return "lcopy_off";
     const int p = S.parent[s];
     if (p >= 0) {
@@ -700,8 +713,10 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
         continue;
       }
       if (p < 0 || p >= np || I < 0 || I >= rt || J < 0 || J >= rt) return "task tile";
-      if (st.kind == kUpdate && !(J > p && I >= J)) return "update tile order";
-      if ((st.kind == kTrsm || st.kind == kInvScale) && !(J == p && I >= p)) return "trsm tile order";
+      if (st.kind == kSchur && !(J >= np && I >= J)) return "Schur tile order";
+      if (st.kind == kUpdate && !((J > p && J < np && I >= J) || (I == p && J == p))) return "update tile order";
+      if ((st.kind == kPotrf || st.kind == kTrsm || st.kind == kInvScale) && !(J == p && I >= p))
+        return "trsm tile order";
       if (st.kind == kInvUpdate && !(J < p && I >= p)) return "inverse update tile order";
     }
   }

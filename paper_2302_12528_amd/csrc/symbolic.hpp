@@ -40,7 +40,7 @@ struct Symbolic {
   std::vector<int64_t> panel_off; int64_t panel_total = 0;   // panel_ld(nr)*nc each (col-major)
   std::vector<int64_t> upd_off;   int64_t upd_total = 0;     // nb*nb each (col-major, ld = nb)
   std::vector<int64_t> uvec_off;  int64_t uvec_total = 0;    // nb rows each (trisolve update vectors)
-  std::vector<int64_t> dinv_off;  int64_t dinv_total = 0;    // np*kTile*kTile each
+  std::vector<int64_t> dinv_off;  int64_t dinv_total = 0;    // 2*np*kTile*kTile each: inv(L_pp), then L_pp
   std::vector<int64_t> lcopy_off; int64_t lcopy_max = 0;     // nc*nc within the level scratch
   double nnz_lower = 0;    // sum over supernodes of nc(nc+1)/2 + nb*nc
   double flops = 0;        // numeric factorization flops (Cholesky part)
@@ -77,8 +77,12 @@ struct FactorPlan {
   std::vector<Step> steps;           // in execution order
   std::vector<int32_t> asm_items;    // 2 ints (s, t) per assembly work item, grouped per level
   std::vector<int64_t> asm_level_off;  // nlevels+1
+  std::vector<int32_t> level_max_nr;   // per level: the largest front (rows) of the level
 };
-enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6 };
+// kPotrf: Cholesky of diagonal tile p with the trsm of the tiles below it (kTrsm: the trsm alone);
+// kUpdate: trailing update of the panel columns; kSchur: U_s -= L21 L21^T after the last panel step.
+enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6,
+                kSchur = 7 };
 void build_factor_plan(const Symbolic& S, FactorPlan& plan);
 
 // Trisolve work lists.  Each output tile (64 rows of P_s for the forward sweep, 64
