@@ -149,22 +149,69 @@ __device__ inline void tile_mfma(const T (*As)[TB + 1], const T (*Bs)[TB + 1], i
   }
 }
 
-// As[k][r] = M[r + k*ld] for r < h, k < K (column-major tile), zero elsewhere.
+
 template <typename T>
-__device__ inline void load_cm(T (*As)[TB + 1], const T* M, int64_t ld, int h, int K) {
-  for (int e = threadIdx.x; e < TB * TB; e += 256) {
-    const int r = e % TB, k = e / TB;
-    As[k][r] = (r < h && k < K) ? M[r + (int64_t)k * ld] : (T)0;
+struct Chunk4 {
+  T v[4][4];   // 4 vectors of 4 consecutive rows: element e = tid + 256 q is rows 4 (e % 16) .. + 3 of column e / 16
+};
+// vec: M and ld * sizeof(T) are multiples of 16 bytes (rows below the own columns start at nc,
+// which need not be a multiple of 4; such tiles take scalar loads)
+template <typename T>
+__device__ inline void chunk_load(Chunk4<T>& c, const T* M, int64_t ld, int h, int K, bool vec) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q, k = e / 16, r = 4 * (e % 16);
+    if (k < K && r < h) {
+      const T* src = M + r + (int64_t)k * ld;
+      if (!vec) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c.v[q][j] = (r + j < h) ? src[j] : (T)0;
+      } else {
+        if constexpr (sizeof(T) == 4) {
+          const f32x4_t x = *reinterpret_cast<const f32x4_t*>(src);
+          c.v[q][0] = x.x; c.v[q][1] = x.y; c.v[q][2] = x.z; c.v[q][3] = x.w;
+        } else {
+          const f64x2_t x0 = *reinterpret_cast<const f64x2_t*>(src), x1 = *reinterpret_cast<const f64x2_t*>(src + 2);
+          c.v[q][0] = x0.x; c.v[q][1] = x0.y; c.v[q][2] = x1.x; c.v[q][3] = x1.y;
+        }
+#pragma unroll
+        for (int j = 1; j < 4; ++j)
+          if (r + j >= h) c.v[q][j] = (T)0;   // rows past the tile (padding or the next block)
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c.v[q][j] = (T)0;
+    }
+  }
+}
+template <typename T>
+__device__ inline void chunk_store(const Chunk4<T>& c, T (*As)[TB + 1]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q, k = e / 16, r = 4 * (e % 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) As[k][r + j] = c.v[q][j];
   }
 }
 
-// Bs[k][c] = M[k + c*ld] (element (k, c) of a column-major matrix) for k < K, c < w.
+// The chunk transposed: Bs[r][k] = element (row r, column k) of the loaded block.
 template <typename T>
-__device__ inline void load_cm_t(T (*Bs)[TB + 1], const T* M, int64_t ld, int K, int w) {
-  for (int e = threadIdx.x; e < TB * TB; e += 256) {
-    const int k = e % TB, c = e / TB;
-    Bs[k][c] = (k < K && c < w) ? M[k + (int64_t)c * ld] : (T)0;
+__device__ inline void chunk_store_t(const Chunk4<T>& c, T (*Bs)[TB + 1]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q, k = e / 16, r = 4 * (e % 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bs[r + j][k] = c.v[q][j];
   }
+}
+
+// As[k][r] = M[r + k ld] for r < h, k < K, zero elsewhere, with 16-byte loads when M and ld allow.
+template <typename T>
+__device__ inline void load_cm_vec(T (*As)[TB + 1], const T* M, int64_t ld, int h, int K) {
+  const bool vec = ((reinterpret_cast<uintptr_t>(M) | (uintptr_t)(ld * sizeof(T))) & 15) == 0;
+  Chunk4<T> c;
+  chunk_load(c, M, ld, h, K, vec);
+  chunk_store(c, As);
 }
 
 // Task (s, I, p) of a panel step: the Cholesky factor L_pp of diagonal tile (p, p) and its inverse
@@ -305,13 +352,10 @@ __global__ void __launch_bounds__(256) potrf_trsm_kernel(FactorDev D, int64_t ta
     }
 }
 
-// kind 0: trsm   C = C dinv_p^T            (task s, I, p, p)
-// kind 1: update C(I,J) -= C(I,p) C(J,p)^T   (task s, I, J, p); task (s, p, p, p) stores L_pp
-// kind 2: invscale C(I,q) = C(I,q) dinv_q, or dinv_q itself when I == q
-// kind 3: invupdate C(I,r) -= C(I,q) Lcopy(q, r)
-template <typename T, int KIND>
-__global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off, T* panel, T* upd, T* dinv,
-                                                   T* lcopy) {
+// Trailing update of a panel step, C(I,J) -= C(I,p) C(J,p)^T for p < J < np (task s, I, J, p); the
+// task (s, p, p, p) instead stores L_pp from its staging slot into tile (p, p).
+template <typename T>
+__global__ void __launch_bounds__(256) update_kernel(FactorDev D, int64_t task_off, T* panel, T* upd, T* dinv) {
   __shared__ T As[TB][TB + 1];
   __shared__ T Bs[TB][TB + 1];
   const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
@@ -322,48 +366,21 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
   tile_rows(S, I, rI, hI);
   tile_rows(S, J, rJ, hJ);
   tile_rows(S, p, rP, wP);
-  int64_t ldc, lda;
+  int64_t ldc, lda, ldb;
   T* C = front_ptr(panel, upd, S, rI, rJ, ldc);            // tile (I, J): rows hI, cols hJ
-  const T* di = dinv + D.dinv_off[s] + (int64_t)p * TB * TB;
-  if (KIND == 1 && I == p && J == p) {   // L_pp from its staging slot into tile (p, p)
-    const T* ls = di + (int64_t)S.np * TB * TB;
+  if (I == p && J == p) {
+    const T* ls = dinv + D.dinv_off[s] + (int64_t)(S.np + p) * TB * TB;
     for (int e = tid; e < TB * TB; e += 256) {
       const int r = e % TB, c = e / TB;
       if (r < hI && c < hJ) C[r + (int64_t)c * ldc] = ls[r + TB * c];
     }
     return;
   }
-  int K = 0;
-  if (KIND == 0) {              // C(I,p) dinv_p^T, K = wP
-    K = wP;
-    load_cm(As, C, ldc, hI, K);
-    load_cm(Bs, di, TB, hJ, K);   // Bs[k][c] = dinv[c + 64k] = dinv(c, k)
-  } else if (KIND == 1) {
-    K = wP;
-    const T* Ap = front_ptr(panel, upd, S, rI, rP, lda);
-    int64_t ldb;
-    const T* Bp = front_ptr(panel, upd, S, rJ, rP, ldb);
-    load_cm(As, Ap, lda, hI, K);
-    load_cm(Bs, Bp, ldb, hJ, K);
-  } else if (KIND == 2) {
-    if (I == p) {
-      for (int e = tid; e < TB * TB; e += 256) {
-        const int i = e % TB, j = e / TB;
-        if (i < hI && j < hJ) C[i + (int64_t)j * ldc] = di[i + TB * j];
-      }
-      return;
-    }
-    K = wP;
-    load_cm(As, C, ldc, hI, K);
-    load_cm_t(Bs, di, TB, K, hJ);   // Bs[k][c] = dinv(k, c)
-  } else {
-    int64_t ldq;
-    const T* Aq = front_ptr(panel, upd, S, rI, rP, ldq);   // X(I, q), q = p
-    K = wP;
-    load_cm(As, Aq, ldq, hI, K);
-    const T* Lc = lcopy + D.lcopy_off[s] + (int64_t)rJ * S.nc + rP;   // element (rP + k, rJ + c)
-    load_cm_t(Bs, Lc, S.nc, K, hJ);
-  }
+  const int K = wP;
+  const T* Ap = front_ptr(panel, upd, S, rI, rP, lda);
+  const T* Bp = front_ptr(panel, upd, S, rJ, rP, ldb);
+  load_cm_vec(As, Ap, lda, hI, K);
+  load_cm_vec(Bs, Bp, ldb, hJ, K);
   __syncthreads();
   typename Mfma<T>::v4 acc[2][2];
 #pragma unroll
@@ -372,7 +389,7 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[b][a][q] = 0;
-  tile_mfma<T>(As, Bs, K, acc);
+  tile_mfma<T>(As, Bs, (K + 3) & ~3, acc);
   const int lane = tid % 64, w = tid / 64;
   const int qr = (w / 2) * 32, qc = (w % 2) * 32;
 #pragma unroll
@@ -384,12 +401,7 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = qc + 16 * b + Mfma<T>::drow(lane, q);
-        if (c >= hJ) continue;
-        T* dst = C + r + (int64_t)c * ldc;
-        if (KIND == 0 || KIND == 2)
-          *dst = acc[b][a][q];
-        else
-          *dst -= acc[b][a][q];
+        if (c < hJ) C[r + (int64_t)c * ldc] -= acc[b][a][q];
       }
     }
 }
@@ -398,45 +410,6 @@ __global__ void __launch_bounds__(256) tile_kernel(FactorDev D, int64_t task_off
 // columns, 64 at a time through LDS, accumulated in registers; C is read and written once.  The
 // next 64-column chunk is loaded into registers (16-byte loads of 4 consecutive rows) while the
 // current one is multiplied.
-template <typename T>
-struct Chunk4 {
-  T v[4][4];   // 4 vectors of 4 consecutive rows: element e = tid + 256 q is rows 4 (e % 16) .. + 3 of column e / 16
-};
-// vec: M and ld * sizeof(T) are multiples of 16 bytes (rows below the own columns start at nc,
-// which need not be a multiple of 4; such tiles take scalar loads)
-template <typename T>
-__device__ inline void chunk_load(Chunk4<T>& c, const T* M, int64_t ld, int h, int K, bool vec) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = threadIdx.x + 256 * q, k = e / 16, r = 4 * (e % 16);
-    if (k < K && r < h) {
-      const T* src = M + r + (int64_t)k * ld;
-      if (!vec) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c.v[q][j] = (r + j < h) ? src[j] : (T)0;
-      } else if constexpr (sizeof(T) == 4) {
-        const f32x4_t x = *reinterpret_cast<const f32x4_t*>(src);
-        c.v[q][0] = x.x; c.v[q][1] = x.y; c.v[q][2] = x.z; c.v[q][3] = x.w;
-      } else {
-        const f64x2_t x0 = *reinterpret_cast<const f64x2_t*>(src), x1 = *reinterpret_cast<const f64x2_t*>(src + 2);
-        c.v[q][0] = x0.x; c.v[q][1] = x0.y; c.v[q][2] = x1.x; c.v[q][3] = x1.y;
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) c.v[q][j] = (T)0;
-    }
-  }
-}
-template <typename T>
-__device__ inline void chunk_store(const Chunk4<T>& c, T (*As)[TB + 1]) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = threadIdx.x + 256 * q, k = e / 16, r = 4 * (e % 16);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) As[k][r + j] = c.v[q][j];
-  }
-}
-
 template <typename T>
 __global__ void __launch_bounds__(256) schur_kernel(FactorDev D, int64_t task_off, T* panel, T* upd) {
   __shared__ T As[TB][TB + 1];
@@ -493,10 +466,12 @@ __global__ void __launch_bounds__(256) schur_kernel(FactorDev D, int64_t task_of
     }
 }
 
-// Copy L11 column t (rows t..nc-1) to the level scratch and clear the panel's own part of column t.
+// Inverse phase, column t of supernode s: L11 column t (rows t..nc-1) and L21 column t go to the
+// level scratch, and the panel's own part of column t becomes column t of the block-diagonal
+// start of X = inv(L11): the inverse of the diagonal tile holding t, zero elsewhere.
 template <typename T>
 __global__ void __launch_bounds__(256) invprep_kernel(FactorDev D, int64_t task_off, int64_t count, T* panel,
-                                                      T* lcopy) {
+                                                      T* dinv, T* lcopy) {
   const int lane = threadIdx.x % 64;
   const int64_t item = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (item >= count) return;
@@ -504,12 +479,109 @@ __global__ void __launch_bounds__(256) invprep_kernel(FactorDev D, int64_t task_
   const int s = tk[0], t = tk[1];
   const Sn S = sn_of(D, s);
   T* col = panel + S.panel + (int64_t)t * panel_ld(S.nr);
-  T* lc = lcopy + D.lcopy_off[s] + (int64_t)t * S.nc;
-  for (int r = lane; r < S.nc; r += 64) {
-    if (r >= t) lc[r] = col[r];
+  T* lc = lcopy + D.lcopy_off[s];
+  T* l21 = lc + 2 * (int64_t)S.nc * S.nc;
+  for (int r = lane; r < S.nr; r += 64) {
+    if (r < S.nc) {
+      if (r >= t) lc[(int64_t)t * S.nc + r] = col[r];
+    } else {
+      l21[(int64_t)t * S.nb + (r - S.nc)] = col[r];
+    }
   }
   __threadfence_block();
-  for (int r = lane; r < S.nc; r += 64) col[r] = (T)0;
+  const int qt = t / TB;
+  const T* di = dinv + D.dinv_off[s] + (int64_t)qt * TB * TB + (int64_t)(t - qt * TB) * TB;   // column of inv(L_qq)
+  for (int r = lane; r < S.nc; r += 64) col[r] = (r / TB == qt) ? di[r - qt * TB] : (T)0;
+}
+
+// One 64 x 64 output tile of the inverse phase, C = alpha sum_k A(:, k) B(k, :) over the task's
+// nonzero reduction tiles, 64 columns of A (rows of B) at a time through LDS, the next chunk
+// loaded while the current one is multiplied.  For a task (s, I, J, t):
+//   kInvT1:  T1(I, J) = sum_{J <= k < m} L(I, k) X(k, J)   (L from the L11 copy, T1 to the scratch)
+//   kInvX21: X(I, J) = -sum_{m <= k <= I} X(I, k) T1(k, J)
+//   kInvP21: P(I, J) = sum_{J <= k < np} L21(I, k) X(k, J)   (L21 from its copy, I >= np)
+// with m the first tile of the lower half of the 2^t-tile block holding I and J.  X lives in the
+// panel's own rows (column-major, ld panel_ld(nr)).
+template <typename T, int KIND>
+__global__ void __launch_bounds__(256) inv_gemm_kernel(FactorDev D, int64_t task_off, T* panel, T* lcopy) {
+  __shared__ T As[TB][TB + 1];
+  __shared__ T Bs[TB][TB + 1];
+  const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
+  const int s = tk[0], I = tk[1], J = tk[2], t = tk[3];
+  const Sn S = sn_of(D, s);
+  const int nc = S.nc;
+  const int64_t ldp = panel_ld(S.nr);
+  T* X = panel + S.panel;
+  T* Lc = lcopy + D.lcopy_off[s];
+  T* Tc = Lc + (int64_t)nc * nc;
+  T* L21c = Lc + 2 * (int64_t)nc * nc;
+  int rI, hI;
+  tile_rows(S, I, rI, hI);
+  const int hJ = min(TB, nc - J * TB);
+  const T *A, *B;
+  int64_t lda, ldb, ldc;
+  T* C;
+  int k0, k1;   // reduction range (rows of B)
+  T alpha = (T)1;
+  if (KIND == kInvT1) {
+    const int m = ((I >> t) << t) + (1 << (t - 1));
+    k0 = J * TB; k1 = m * TB;
+    A = Lc + rI; lda = nc;
+    B = X + (int64_t)J * TB * ldp; ldb = ldp;
+    C = Tc + rI + (int64_t)J * TB * nc; ldc = nc;
+  } else if (KIND == kInvX21) {
+    const int m = ((I >> t) << t) + (1 << (t - 1));
+    k0 = m * TB; k1 = min(nc, (I + 1) * TB);
+    A = X + rI; lda = ldp;
+    B = Tc + (int64_t)J * TB * nc; ldb = nc;
+    C = X + rI + (int64_t)J * TB * ldp; ldc = ldp;
+    alpha = (T)-1;
+  } else {
+    k0 = J * TB; k1 = nc;
+    A = L21c + (rI - nc); lda = S.nb;
+    B = X + (int64_t)J * TB * ldp; ldb = ldp;
+    C = X + rI + (int64_t)J * TB * ldp; ldc = ldp;
+  }
+  const bool va = ((reinterpret_cast<uintptr_t>(A) | (uintptr_t)(lda * sizeof(T))) & 15) == 0;
+  const bool vb = ((reinterpret_cast<uintptr_t>(B) | (uintptr_t)(ldb * sizeof(T))) & 15) == 0;
+  typename Mfma<T>::v4 acc[2][2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[b][a][q] = 0;
+  // A chunk: As[k][r] = A(r, k); B chunk loaded as (rows k, columns c) and stored transposed
+  Chunk4<T> na, nb;
+  chunk_load(na, A + (int64_t)k0 * lda, lda, hI, min(TB, k1 - k0), va);
+  chunk_load(nb, B + k0, ldb, min(TB, k1 - k0), hJ, vb);
+  for (int kc = k0; kc < k1; kc += TB) {
+    const int K = min(TB, k1 - kc);
+    __syncthreads();
+    chunk_store(na, As);
+    chunk_store_t(nb, Bs);
+    __syncthreads();
+    if (kc + TB < k1) {
+      const int K2 = min(TB, k1 - kc - TB);
+      chunk_load(na, A + (int64_t)(kc + TB) * lda, lda, hI, K2, va);
+      chunk_load(nb, B + kc + TB, ldb, K2, hJ, vb);
+    }
+    tile_mfma<T>(As, Bs, (K + 3) & ~3, acc);
+  }
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int qr = (w / 2) * 32, qc = (w % 2) * 32;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int r = qr + 16 * a + lane % 16;
+      if (r >= hI) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = qc + 16 * b + Mfma<T>::drow(lane, q);
+        if (c < hJ) C[r + (int64_t)c * ldc] = alpha * acc[b][a][q];
+      }
+    }
 }
 
 }  // namespace
@@ -530,24 +602,26 @@ void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t 
     case kPotrf:
       potrf_trsm_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, flag);
       break;
-    case kTrsm:
-      tile_kernel<T, 0><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, lcopy);
-      break;
+
     case kUpdate:
-      tile_kernel<T, 1><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, lcopy);
+      update_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv);
       break;
     case kSchur:
       schur_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd);
       break;
     case kInvPrep:
-      invprep_kernel<T><<<(unsigned)((count + 3) / 4), 256, 0, st>>>(D, task_off, count, panel, lcopy);
+      invprep_kernel<T><<<(unsigned)((count + 3) / 4), 256, 0, st>>>(D, task_off, count, panel, dinv, lcopy);
       break;
-    case kInvScale:
-      tile_kernel<T, 2><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, lcopy);
+    case kInvT1:
+      inv_gemm_kernel<T, kInvT1><<<count, 256, 0, st>>>(D, task_off, panel, lcopy);
       break;
-    case kInvUpdate:
-      tile_kernel<T, 3><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv, lcopy);
+    case kInvX21:
+      inv_gemm_kernel<T, kInvX21><<<count, 256, 0, st>>>(D, task_off, panel, lcopy);
       break;
+    case kInvP21:
+      inv_gemm_kernel<T, kInvP21><<<count, 256, 0, st>>>(D, task_off, panel, lcopy);
+      break;
+
     default:
       break;
   }

@@ -46,6 +46,7 @@ __device__ double block_sum(double v, double* red) {
 //  4. back-transformation C = Q Z of the nev vectors, several threads per column.
 // Matrices up to 96 x 96 live in LDS, larger ones in the global scratch.
 constexpr int kSyevThreads = 256;
+constexpr int kSyevWaves = kSyevThreads / 64;
 constexpr int kSyevLds = 96;
 constexpr int kSyevMax = 192;
 
@@ -160,22 +161,25 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     }
     __syncthreads();
     const double K = 0.5 * t * sc[2 + (k & 1)];
-    // A22 -= v w^T + w v^T with w = p - K v: lane owns columns j, wave w rows i = w mod 4,
-    // four rows per step so that their loads are in flight together
+    // A22 -= v w^T + w v^T with w = p - K v: lane owns columns j, wave w the rows i = w mod
+    // kSyevWaves, four rows per step so that their loads are in flight together
     for (int j = lane; j < nk; j += 64) {
       const double vj = v[j], wj = p[j] - K * vj;
       double* col = a + (k + 1) * la + k + 1 + j;
+      constexpr int NV = kSyevWaves;
       int i = wid;
-      for (; i + 12 < nk; i += 16) {
-        const double v0 = v[i], v1 = v[i + 4], v2 = v[i + 8], v3 = v[i + 12];
-        const double w0 = p[i] - K * v0, w1 = p[i + 4] - K * v1, w2 = p[i + 8] - K * v2, w3 = p[i + 12] - K * v3;
-        const double a0 = col[i * la], a1 = col[(i + 4) * la], a2 = col[(i + 8) * la], a3 = col[(i + 12) * la];
+      for (; i + 3 * NV < nk; i += 4 * NV) {
+        const double v0 = v[i], v1 = v[i + NV], v2 = v[i + 2 * NV], v3 = v[i + 3 * NV];
+        const double w0 = p[i] - K * v0, w1 = p[i + NV] - K * v1, w2 = p[i + 2 * NV] - K * v2,
+                     w3 = p[i + 3 * NV] - K * v3;
+        const double a0 = col[i * la], a1 = col[(i + NV) * la], a2 = col[(i + 2 * NV) * la],
+                     a3 = col[(i + 3 * NV) * la];
         col[i * la] = a0 - (v0 * wj + w0 * vj);
-        col[(i + 4) * la] = a1 - (v1 * wj + w1 * vj);
-        col[(i + 8) * la] = a2 - (v2 * wj + w2 * vj);
-        col[(i + 12) * la] = a3 - (v3 * wj + w3 * vj);
+        col[(i + NV) * la] = a1 - (v1 * wj + w1 * vj);
+        col[(i + 2 * NV) * la] = a2 - (v2 * wj + w2 * vj);
+        col[(i + 3 * NV) * la] = a3 - (v3 * wj + w3 * vj);
       }
-      for (; i < nk; i += 4) {
+      for (; i < nk; i += NV) {
         const double vi = v[i], wi = p[i] - K * vi;
         col[i * la] -= vi * wj + wi * vj;
       }
@@ -357,11 +361,11 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     }
     __syncthreads();
     // modified Gram-Schmidt inside each cluster, in eigenvalue order: wave w takes the later
-    // members r = q + 1 + w, q + 5 + w, ...; lanes split the rows
+    // members r = q + 1 + w, q + 1 + w + kSyevWaves, ...; lanes split the rows
     for (int q = 0; q + 1 < nev; ++q) {
       const int qe = cend[q];
       if (qe - q < 2) continue;   // uniform
-      for (int r = q + 1 + wid; r < qe; r += 4) {
+      for (int r = q + 1 + wid; r < qe; r += kSyevWaves) {
         // a lane holds at most 3 rows (c <= 192): load them, reduce, then store
         double zq[3], zr[3];
 #pragma unroll

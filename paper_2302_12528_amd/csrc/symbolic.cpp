@@ -328,8 +328,8 @@ std::string analyze_multi(int64_t n, const int32_t* rowptr, const int32_t* colin
     int64_t acc = 0;
     for (int32_t q = S.level_ptr[l]; q < S.level_ptr[l + 1]; ++q) {
       int s = S.level_sn[q];
-      S.lcopy_off[s] = acc;
-      acc += (int64_t)S.nc[s] * S.nc[s];
+      S.lcopy_off[s] = acc;   // L11 copy (nc x nc), inversion scratch (nc x nc), L21 copy (nb x nc)
+      acc += 2 * (int64_t)S.nc[s] * S.nc[s] + (int64_t)(S.nr[s] - S.nc[s]) * S.nc[s];
     }
     S.lcopy_max = std::max(S.lcopy_max, acc);
   }
@@ -455,34 +455,41 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
         for (int I = J; I < rt; ++I) push(s, I, J, 0);
     }
     end_step();
-    // inverse phase: P_s = [I; L21] inv(L11)
+    // inverse phase: P_s = [inv(L11); L21 inv(L11)].  X = inv(L11) by recursive doubling over
+    // diagonal blocks of 2^t tiles: with a block split into halves [[A, 0], [B, C]] whose inverses
+    // are known, the lower-left block of its inverse is -inv(C) (B inv(A)); level t forms
+    // T1 = B inv(A) (kInvT1) and then -inv(C) T1 (kInvX21) for every block at once.  Finally the
+    // rows below: L21 X (kInvP21), from a copy of L21.
     begin_step(kInvPrep);
     for (int32_t q = q0; q < q1; ++q) {
       int s = S.level_sn[q];
       for (int t = 0; t < S.nc[s]; ++t) push(s, t, 0, 0);
     }
     end_step();
-    for (int st = 0; st < maxnp; ++st) {
-      begin_step(kInvScale);
-      for (int32_t q = q0; q < q1; ++q) {
-        int s = S.level_sn[q];
-        int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
-        int qc = np - 1 - st;
-        if (qc < 0) continue;
-        for (int I = qc; I < rt; ++I) push(s, I, qc, qc);
+    for (int t = 1; (1 << (t - 1)) < maxnp; ++t) {
+      for (int kind : {kInvT1, kInvX21}) {
+        begin_step(kind);
+        for (int32_t q = q0; q < q1; ++q) {
+          int s = S.level_sn[q];
+          int np = ntiles(S.nc[s]);
+          for (int j0 = 0; j0 < np; j0 += (1 << t)) {
+            const int m = j0 + (1 << (t - 1));
+            const int i1 = std::min(np, j0 + (1 << t));
+            for (int I = m; I < i1; ++I)
+              for (int J = j0; J < m; ++J) push(s, I, J, t);
+          }
+        }
+        end_step();
       }
-      end_step();
-      begin_step(kInvUpdate);
-      for (int32_t q = q0; q < q1; ++q) {
-        int s = S.level_sn[q];
-        int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
-        int qc = np - 1 - st;
-        if (qc < 1) continue;
-        for (int r = 0; r < qc; ++r)
-          for (int I = qc; I < rt; ++I) push(s, I, r, qc);
-      }
-      end_step();
     }
+    begin_step(kInvP21);
+    for (int32_t q = q0; q < q1; ++q) {
+      int s = S.level_sn[q];
+      int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+      for (int I = np; I < rt; ++I)
+        for (int J = 0; J < np; ++J) push(s, I, J, 0);
+    }
+    end_step();
   }
 }
 
@@ -675,7 +682,8 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
     if (S.upd_off[s + 1] - S.upd_off[s] != (int64_t)nb * nb) return "upd_off";
     if (S.uvec_off[s + 1] - S.uvec_off[s] != nb) return "uvec_off";
     if (S.dinv_off[s + 1] - S.dinv_off[s] != 2 * (int64_t)ntiles(nc) * kTile * kTile) return "dinv_off";
-    if (S.lcopy_off[s] < 0 || S.lcopy_off[s] + (int64_t)nc * nc > S.lcopy_max) return "lcopy_off";
+    if (S.lcopy_off[s] < 0 || S.lcopy_off[s] + 2 * (int64_t)nc * nc + (int64_t)(S.nr[s] - nc) * nc > S.lcopy_max)
+      return "lcopy_off";
     const int p = S.parent[s];
     if (p >= 0) {
       if (p <= s || p >= ns) return "parent";
@@ -712,12 +720,19 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
         if (I < 0 || I >= S.nc[s]) return "invprep column";
         continue;
       }
-      if (p < 0 || p >= np || I < 0 || I >= rt || J < 0 || J >= rt) return "task tile";
+      const bool plevel = (st.kind == kInvT1 || st.kind == kInvX21);   // p holds the recursion level
+      if (p < 0 || (!plevel && p >= np) || I < 0 || I >= rt || J < 0 || J >= rt) return "task tile";
       if (st.kind == kSchur && !(J >= np && I >= J)) return "Schur tile order";
       if (st.kind == kUpdate && !((J > p && J < np && I >= J) || (I == p && J == p))) return "update tile order";
       if ((st.kind == kPotrf || st.kind == kTrsm || st.kind == kInvScale) && !(J == p && I >= p))
         return "trsm tile order";
       if (st.kind == kInvUpdate && !(J < p && I >= p)) return "inverse update tile order";
+      if (st.kind == kInvT1 || st.kind == kInvX21) {
+        if (p < 1 || p > 30 || I >= np || J >= np) return "inversion task";
+        const int m = ((I >> p) << p) + (1 << (p - 1));
+        if ((I >> p) != (J >> p) || !(J < m && m <= I)) return "inversion task blocks";
+      }
+      if (st.kind == kInvP21 && !(I >= np && J < np)) return "inverse product task";
     }
   }
   for (size_t q = 0; q < F.asm_items.size(); q += 2) {

@@ -41,7 +41,7 @@ struct Symbolic {
   std::vector<int64_t> upd_off;   int64_t upd_total = 0;     // nb*nb each (col-major, ld = nb)
   std::vector<int64_t> uvec_off;  int64_t uvec_total = 0;    // nb rows each (trisolve update vectors)
   std::vector<int64_t> dinv_off;  int64_t dinv_total = 0;    // 2*np*kTile*kTile each: inv(L_pp), then L_pp
-  std::vector<int64_t> lcopy_off; int64_t lcopy_max = 0;     // nc*nc within the level scratch
+  std::vector<int64_t> lcopy_off; int64_t lcopy_max = 0;     // 2*nc*nc + nb*nc within the level scratch
   double nnz_lower = 0;    // sum over supernodes of nc(nc+1)/2 + nb*nc
   double flops = 0;        // numeric factorization flops (Cholesky part)
   int32_t max_nr = 0, max_nc = 0;
@@ -81,8 +81,10 @@ struct FactorPlan {
 };
 // kPotrf: Cholesky of diagonal tile p with the trsm of the tiles below it (kTrsm: the trsm alone);
 // kUpdate: trailing update of the panel columns; kSchur: U_s -= L21 L21^T after the last panel step.
+// kInvPrep / kInvT1 / kInvX21 / kInvP21: the inverse phase P_s = [inv(L11); L21 inv(L11)] (kInvScale and
+// kInvUpdate: the column sweep it replaces, no longer planned).
 enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6,
-                kSchur = 7 };
+                kSchur = 7, kInvT1 = 8, kInvX21 = 9, kInvP21 = 10 };
 void build_factor_plan(const Symbolic& S, FactorPlan& plan);
 
 // Trisolve work lists.  Each output tile (64 rows of P_s for the forward sweep, 64
