@@ -87,22 +87,37 @@ __global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const
       }
 }
 
-// out_b[e] = sum over the chunks of instance b of part[chunk][e], in chunk order (four
-// interleaved partial sums combined in a fixed order).
+// out_b[e] = sum over the chunks of instance b of part[chunk][e]: a block takes 16 elements, its 16
+// thread groups every 16th chunk each with four independent partial sums (so that loads overlap),
+// and the 64 partial sums of an element are combined in a fixed order (deterministic).
+constexpr int kRedElems = 16, kRedGroups = 16;
 __global__ void __launch_bounds__(256) sreduce_kernel(SegDev S, const double* __restrict__ part, int len,
                                                       double* __restrict__ out, int64_t ostride) {
-  __shared__ double red[4][64];
+  __shared__ double red[kRedGroups][kRedElems];
   const int b = blockIdx.y;
   if (!S.active[b]) return;
-  const int g = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int e = blockIdx.x * 64 + lane;
+  const int g = threadIdx.x / kRedElems, l = threadIdx.x % kRedElems;
+  const int e = blockIdx.x * kRedElems + l;
   const int q0 = S.inst_chunk_off[b], q1 = S.inst_chunk_off[b + 1];
-  double s = 0.0;
-  if (e < len)
-    for (int q = q0 + g; q < q1; q += 4) s += part[(int64_t)q * len + e];
-  red[g][lane] = s;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (e < len) {
+    int q = q0 + g;
+    for (; q + 3 * kRedGroups < q1; q += 4 * kRedGroups) {
+      s0 += part[(int64_t)q * len + e];
+      s1 += part[(int64_t)(q + kRedGroups) * len + e];
+      s2 += part[(int64_t)(q + 2 * kRedGroups) * len + e];
+      s3 += part[(int64_t)(q + 3 * kRedGroups) * len + e];
+    }
+    for (; q < q1; q += kRedGroups) s0 += part[(int64_t)q * len + e];
+  }
+  red[g][l] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  if (g == 0 && e < len) out[(int64_t)b * ostride + e] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  if (g == 0 && e < len) {
+    double t = 0.0;
+#pragma unroll
+    for (int h = 0; h < kRedGroups; ++h) t += red[h][l];
+    out[(int64_t)b * ostride + e] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -388,7 +403,7 @@ void launch_sgram(const SegDev& S, const double* X, int64_t ldx, const double* Y
     default: sgram_ct<3>(ct, g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
   }
   const int len = c1 * c2;
-  sreduce_kernel<<<dim3(cdiv(len, 64), S.B), 256, 0, st>>>(S, part, len, G, gstride);
+  sreduce_kernel<<<dim3(cdiv(len, kRedElems), S.B), 256, 0, st>>>(S, part, len, G, gstride);
 }
 
 void launch_supdate(const SegDev& S, const double* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
@@ -404,7 +419,7 @@ void launch_sresidual(const SegDev& S, const double* AX, int64_t ldax, const dou
                       hipStream_t st) {
   if (S.nchunks <= 0) return;
   sresidual_kernel<T><<<(unsigned)S.nchunks, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, m, R, ldr, part);
-  sreduce_kernel<<<dim3(cdiv(2 * m, 64), S.B), 256, 0, st>>>(S, part, 2 * m, norms, 2 * m);
+  sreduce_kernel<<<dim3(cdiv(2 * m, kRedElems), S.B), 256, 0, st>>>(S, part, 2 * m, norms, 2 * m);
 }
 template void launch_sresidual<float>(const SegDev&, const double*, int64_t, const double*, int64_t, const double*,
                                       int64_t, int, float*, int64_t, double*, double*, hipStream_t);
@@ -415,7 +430,7 @@ void launch_scolnorms(const SegDev& S, const double* X, int64_t ldx, int c, doub
                       double* part, hipStream_t st) {
   if (S.nchunks <= 0) return;
   scolnorm_kernel<<<(unsigned)S.nchunks, kThreads, 0, st>>>(S, X, ldx, c, part);
-  sreduce_kernel<<<dim3(cdiv(c, 64), S.B), 256, 0, st>>>(S, part, c, norms, nstride);
+  sreduce_kernel<<<dim3(cdiv(c, kRedElems), S.B), 256, 0, st>>>(S, part, c, norms, nstride);
 }
 
 template <typename TU>
