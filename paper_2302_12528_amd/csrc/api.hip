@@ -291,6 +291,18 @@ lobpcg_status install_solve_plan(lobpcg_ctx c) {
   C.SD.bwd_wide = C.SP.bwd_wide.data();
   ST_TRY(upload_const(c, C.SD.bwd_src, C.SP.bwd_src));
   C.SD.n = C.n;
+  C.SD.sub_levels = C.SP.sub_levels;
+  C.SD.nsub = C.SP.nsub;
+  if (C.SP.nsub > 0) {
+    ST_TRY(upload_const(c, C.SD.sub_gather_dst, C.SP.sub_gather_dst));
+    ST_TRY(upload_const(c, C.SD.sub_gather_ptr, C.SP.sub_gather_ptr));
+    ST_TRY(upload_const(c, C.SD.sub_gather_src, C.SP.sub_gather_src));
+    ST_TRY(upload_const(c, C.SD.sub_gather_off, C.SP.sub_gather_off));
+    ST_TRY(upload_const(c, C.SD.sub_fwd_items, C.SP.sub_fwd_items));
+    ST_TRY(upload_const(c, C.SD.sub_fwd_off, C.SP.sub_fwd_off));
+    ST_TRY(upload_const(c, C.SD.sub_bwd_items, C.SP.sub_bwd_items));
+    ST_TRY(upload_const(c, C.SD.sub_bwd_off, C.SP.sub_bwd_off));
+  }
   return LOBPCG_OK;
 }
 

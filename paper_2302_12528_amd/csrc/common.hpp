@@ -113,6 +113,11 @@ struct SolveDev {
   // backward operand rows: for item aux a and panel row k, bwd_src[a + k] indexes [y; x] (2n rows)
   const int32_t* bwd_src;                                                                                // device
   int64_t n;
+  // bottom levels 0 .. sub_levels - 1 as nsub subtrees (lists and offsets as in SolvePlan; device)
+  int sub_levels; int64_t nsub;
+  const int32_t* sub_gather_dst; const int32_t* sub_gather_ptr; const int32_t* sub_gather_src;
+  const int64_t* sub_gather_off;
+  const int32_t* sub_fwd_items; const int64_t* sub_fwd_off; const int32_t* sub_bwd_items; const int64_t* sub_bwd_off;
 };
 // Both sweeps: rhs (T, n x M, permuted, overwritten by the forward assembly) -> y -> x, and W (FP64, n x mw,
 // ld ldw) = working(x).  x must equal y + n M (one allocation of 2 n M elements, fewer than 2^31 bytes).

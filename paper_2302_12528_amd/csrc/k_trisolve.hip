@@ -34,19 +34,9 @@ template <> struct Vec16<double> { typedef f64x2_t type; };
 // supernode's update vector.  A row of M values is read and written as 16-byte vectors by
 // LPR = M sizeof(T) / 16 lanes, so a wave handles 64 / LPR rows.
 template <typename T, int M>
-__global__ void __launch_bounds__(256) fwd_gather_kernel(const int32_t* __restrict__ dst,
-                                                         const int32_t* __restrict__ ptr,
-                                                         const int32_t* __restrict__ src, int64_t item_off,
-                                                         int64_t count, T* rhs, T* uvec) {
-  constexpr int VW = 16 / sizeof(T);
-  constexpr int LPR = M / VW;
-  constexpr int RPW = 64 / LPR;
+__device__ inline void gather_row(const int32_t* __restrict__ dst, const int32_t* __restrict__ ptr,
+                                  const int32_t* __restrict__ src, int64_t item, int cl, T* rhs, T* uvec) {
   typedef typename Vec16<T>::type V;
-  const int lane = threadIdx.x % 64;
-  const int64_t r = ((int64_t)blockIdx.x * 4 + threadIdx.x / 64) * RPW + lane / LPR;
-  if (r >= count) return;
-  const int64_t item = item_off + r;
-  const int cl = (lane % LPR) * VW;
   const int32_t d = dst[item];
   const int32_t p0 = ptr[item], p1 = ptr[item + 1];
   V v = {};
@@ -64,6 +54,20 @@ __global__ void __launch_bounds__(256) fwd_gather_kernel(const int32_t* __restri
   } else {
     *reinterpret_cast<V*>(uvec + (int64_t)(-d - 1) * M + cl) = v;
   }
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(256) fwd_gather_kernel(const int32_t* __restrict__ dst,
+                                                         const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ src, int64_t item_off,
+                                                         int64_t count, T* rhs, T* uvec) {
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int LPR = M / VW;
+  constexpr int RPW = 64 / LPR;
+  const int lane = threadIdx.x % 64;
+  const int64_t r = ((int64_t)blockIdx.x * 4 + threadIdx.x / 64) * RPW + lane / LPR;
+  if (r >= count) return;
+  gather_row<T, M>(dst, ptr, src, item_off + r, (lane % LPR) * VW, rhs, uvec);
 }
 
 // ---------------------------------------------------------------------------
@@ -177,27 +181,20 @@ struct FwdStage {
   T b[U][NCB];
 };
 
-template <typename T, int M, bool WIDE>
-__global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict__ items, int64_t item_off,
-                                                       int64_t count, const T* __restrict__ panel,
-                                                       const T* __restrict__ rhs, T* __restrict__ y,
-                                                       T* __restrict__ uvec, T* __restrict__ part) {
+// One forward tile item by NW waves (wave = this wave's index among them; red: LDS for NW > 1).
+template <typename T, int M, int NW>
+__device__ inline void fwd_tile(const SolveItem& it, int wave, typename Mfma<T>::v4* red, const T* __restrict__ panel,
+                                const T* __restrict__ rhs, T* __restrict__ y, T* __restrict__ uvec,
+                                T* __restrict__ part) {
   typedef Mfma<T> MF;
   typedef typename MF::v4 V4;
   constexpr int VW = 16 / sizeof(T);
   constexpr int NP = 4 / VW;
   constexpr int NCB = (M + 15) / 16;
-  constexpr int NW = solve_waves<T, WIDE>();
   constexpr int U = (sizeof(T) == 4) ? 4 : 2;   // reduction steps per stage
   constexpr int SC = 4 * U;                       // panel columns per stage
-  __shared__ V4 red[(NW > 1 ? NW : 0) * 4 * NCB * 64 + 1];
-  // the wave index is uniform: item fields and buffer resources then live in scalar registers
-  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
   const int i = lane % 16, g = lane / 16;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t item = (NW > 1) ? blk : blk * 4 + wave;
-  if (item >= count) return;   // whole waves (NW == 1) or never (NW > 1)
-  const SolveItem it = read_item(items, item_off + item);
   const int tile = it.tile, k0 = it.k0, k1 = it.k1, slot = it.slot;
   const int begin = it.begin, nr = it.nr, nc = it.nc;
   const bool parent = it.parent;
@@ -245,7 +242,7 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict
   };
   constexpr int stride = SC * NW;
   St cur, nxt;
-  int kc = k0 + SC * (NW > 1 ? wave : 0);
+  int kc = k0 + SC * wave;
   if (kc < k1) load(cur, kc);
   for (; kc < k1; kc += stride) {
     load(nxt, kc + stride);   // zeros, without memory traffic, past the end of the range
@@ -285,6 +282,23 @@ __global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict
   }
 }
 
+template <typename T, int M, bool WIDE>
+__global__ void __launch_bounds__(256) fwd_mfma_kernel(const int32_t* __restrict__ items, int64_t item_off,
+                                                       int64_t count, const T* __restrict__ panel,
+                                                       const T* __restrict__ rhs, T* __restrict__ y,
+                                                       T* __restrict__ uvec, T* __restrict__ part) {
+  typedef typename Mfma<T>::v4 V4;
+  constexpr int NCB = (M + 15) / 16;
+  constexpr int NW = solve_waves<T, WIDE>();
+  __shared__ V4 red[(NW > 1 ? NW : 0) * 4 * NCB * 64 + 1];
+  // the wave index is uniform: item fields and buffer resources then live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t item = (NW > 1) ? blk : blk * 4 + wave;
+  if (item >= count) return;   // whole waves (NW == 1) or never (NW > 1)
+  fwd_tile<T, M, NW>(read_item(items, item_off + item), NW > 1 ? wave : 0, red, panel, rhs, y, uvec, part);
+}
+
 // Backward: out tile (64 own columns x M) = P_s[k0:k1, j0:j0+64]^T z[k0:k1, :], z = [y_s; -x_below].
 // A reduction step covers 4 VW panel rows: lane (i, g) reads VW consecutive rows (k = kc + VW g + t)
 // of panel column j0 + 16 jb + i, and MFMA t pairs them with z row kc + VW g + t.  The rows of z are
@@ -301,28 +315,20 @@ struct BwdIdx {
   int32_t r[U][16 / sizeof(T)];
 };
 
-template <typename T, int M, bool WIDE>
-__global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict__ srcrows,
-                                                       const int32_t* __restrict__ items, int64_t item_off,
-                                                       int64_t count, const T* __restrict__ panel,
-                                                       const T* __restrict__ yx, int64_t yx_rows,
-                                                       T* __restrict__ x, double* W, int64_t ldw, int mw,
-                                                       T* __restrict__ part) {
+// One backward tile item by NW waves.
+template <typename T, int M, int NW>
+__device__ inline void bwd_tile(const SolveItem& it, int wave, typename Mfma<T>::v4* red,
+                                const int32_t* __restrict__ srcrows, const T* __restrict__ panel,
+                                const T* __restrict__ yx, int64_t yx_rows, T* __restrict__ x, double* W, int64_t ldw,
+                                int mw, T* __restrict__ part) {
   typedef Mfma<T> MF;
   typedef typename MF::v4 V4;
   constexpr int VW = 16 / sizeof(T);
   constexpr int NCB = (M + 15) / 16;
-  constexpr int NW = solve_waves<T, WIDE>();
   constexpr int U = 1;             // reduction steps per stage
   constexpr int SR = 4 * VW * U;   // panel rows per stage
-  __shared__ V4 red[(NW > 1 ? NW : 0) * 4 * NCB * 64 + 1];
-  // the wave index is uniform: item fields and buffer resources then live in scalar registers
-  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int lane = threadIdx.x % 64;
   const int i = lane % 16, g = lane / 16;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t item = (NW > 1) ? blk : blk * 4 + wave;
-  if (item >= count) return;
-  const SolveItem it = read_item(items, item_off + item);
   const int tile = it.tile, k0 = it.k0, k1 = it.k1, slot = it.slot;
   const int begin = it.begin, nc = it.nc, nr = it.nr;
   const int64_t ldp = panel_ld(nr);
@@ -393,7 +399,7 @@ __global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict
   constexpr int stride = SR * NW;
   St cur, nxt;
   Ix i1, i2;   // source rows of the next stage and of the one after
-  int kc = k0 + SR * (NW > 1 ? wave : 0);
+  int kc = k0 + SR * wave;
   if (kc < k1) {
     load_idx(i1, kc);
     load_idx(i2, kc + stride);
@@ -433,6 +439,72 @@ __global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict
   } else {
 #pragma unroll
     for (int jb = 0; jb < 4; ++jb) emit(jb, acc[jb]);
+  }
+}
+
+template <typename T, int M, bool WIDE>
+__global__ void __launch_bounds__(256) bwd_mfma_kernel(const int32_t* __restrict__ srcrows,
+                                                       const int32_t* __restrict__ items, int64_t item_off,
+                                                       int64_t count, const T* __restrict__ panel,
+                                                       const T* __restrict__ yx, int64_t yx_rows,
+                                                       T* __restrict__ x, double* W, int64_t ldw, int mw,
+                                                       T* __restrict__ part) {
+  typedef typename Mfma<T>::v4 V4;
+  constexpr int NCB = (M + 15) / 16;
+  constexpr int NW = solve_waves<T, WIDE>();
+  __shared__ V4 red[(NW > 1 ? NW : 0) * 4 * NCB * 64 + 1];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t item = (NW > 1) ? blk : blk * 4 + wave;
+  if (item >= count) return;
+  bwd_tile<T, M, NW>(read_item(items, item_off + item), NW > 1 ? wave : 0, red, srcrows, panel, yx, yx_rows, x, W,
+                     ldw, mw, part);
+}
+
+// ---------------------------------------------------------------------------
+// Bottom subtrees: workgroup q runs subtree q level by level (forward: gather rows, then tile
+// items, bottom-up; backward: tile items top-down), its waves sharing each level's work, with a
+// workgroup barrier between levels instead of a launch.  Items are unsplit, one wave each.
+// ---------------------------------------------------------------------------
+constexpr int kSubWaves = 8;
+
+template <typename T, int M>
+__global__ void __launch_bounds__(64 * kSubWaves) fwd_subtree_kernel(
+    const int32_t* __restrict__ gdst, const int32_t* __restrict__ gptr, const int32_t* __restrict__ gsrc,
+    const int64_t* __restrict__ goff, const int32_t* __restrict__ items, const int64_t* __restrict__ ioff, int L,
+    const T* __restrict__ panel, T* rhs, T* y, T* uvec) {
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int LPR = M / VW;
+  constexpr int RPW = 64 / LPR;
+  const int q = blockIdx.x;
+  const int lane = threadIdx.x % 64, wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  for (int l = 0; l < L; ++l) {
+    const int64_t e = (int64_t)q * L + l;
+    const int64_t g1 = goff[e + 1];
+    for (int64_t base = goff[e] + (int64_t)wave * RPW; base < g1; base += kSubWaves * RPW) {
+      const int64_t r = base + lane / LPR;
+      if (r < g1) gather_row<T, M>(gdst, gptr, gsrc, r, (lane % LPR) * VW, rhs, uvec);
+    }
+    __syncthreads();
+    const int64_t i1 = ioff[e + 1];
+    for (int64_t it = ioff[e] + wave; it < i1; it += kSubWaves)
+      fwd_tile<T, M, 1>(read_item(items, it), 0, nullptr, panel, rhs, y, uvec, y);   // unsplit: no partial tile
+    __syncthreads();
+  }
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(64 * kSubWaves) bwd_subtree_kernel(
+    const int32_t* __restrict__ srcrows, const int32_t* __restrict__ items, const int64_t* __restrict__ ioff, int L,
+    const T* __restrict__ panel, const T* __restrict__ yx, int64_t yx_rows, T* x, double* W, int64_t ldw, int mw) {
+  const int q = blockIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  for (int l = L - 1; l >= 0; --l) {
+    const int64_t e = (int64_t)q * L + l;
+    const int64_t i1 = ioff[e + 1];
+    for (int64_t it = ioff[e] + wave; it < i1; it += kSubWaves)
+      bwd_tile<T, M, 1>(read_item(items, it), 0, nullptr, srcrows, panel, yx, yx_rows, x, W, ldw, mw, x);   // unsplit
+    __syncthreads();
   }
 }
 
@@ -535,22 +607,33 @@ void sweep_level(const FactorDev& D, const SolveDev& Sd, int level, const T* pan
   }
 }
 
+template <typename T, int M>
+void precond_m(const FactorDev& D, const SolveDev& Sd, int nlevels, const T* panel, T* rhs, T* y, T* x, T* uvec,
+               T* fpart, T* bpart, double* W, int64_t ldw, int mw, hipStream_t st) {
+  const int L = (Sd.nsub > 0) ? Sd.sub_levels : 0;
+  if (L > 0)
+    fwd_subtree_kernel<T, M><<<(unsigned)Sd.nsub, 64 * kSubWaves, 0, st>>>(
+        Sd.sub_gather_dst, Sd.sub_gather_ptr, Sd.sub_gather_src, Sd.sub_gather_off, Sd.sub_fwd_items, Sd.sub_fwd_off,
+        L, panel, rhs, y, uvec);
+  for (int l = L; l < nlevels; ++l)
+    sweep_level<T, M>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, true, st);
+  for (int l = nlevels - 1; l >= L; --l)
+    sweep_level<T, M>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, false, st);
+  if (L > 0)
+    bwd_subtree_kernel<T, M><<<(unsigned)Sd.nsub, 64 * kSubWaves, 0, st>>>(
+        Sd.bwd_src, Sd.sub_bwd_items, Sd.sub_bwd_off, L, panel, y, 2 * Sd.n, x, W, ldw, mw);
+}
+
 }  // namespace
 
 template <typename T>
 void launch_precond(const FactorDev& D, const SolveDev& Sd, int nlevels, int M, const T* panel, T* rhs, T* y, T* x,
                     T* uvec, T* fpart, T* bpart, double* W, int64_t ldw, int mw, hipStream_t st) {
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool fwd = (pass == 0);
-    for (int q = 0; q < nlevels; ++q) {
-      const int l = fwd ? q : nlevels - 1 - q;
-      switch (M) {
-        case 8: sweep_level<T, 8>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, fwd, st); break;
-        case 16: sweep_level<T, 16>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, fwd, st); break;
-        case 32: sweep_level<T, 32>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, fwd, st); break;
-        default: sweep_level<T, 64>(D, Sd, l, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, fwd, st); break;
-      }
-    }
+  switch (M) {
+    case 8: precond_m<T, 8>(D, Sd, nlevels, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, st); break;
+    case 16: precond_m<T, 16>(D, Sd, nlevels, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, st); break;
+    case 32: precond_m<T, 32>(D, Sd, nlevels, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, st); break;
+    default: precond_m<T, 64>(D, Sd, nlevels, panel, rhs, y, x, uvec, fpart, bpart, W, ldw, mw, st); break;
   }
 }
 

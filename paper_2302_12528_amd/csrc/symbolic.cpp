@@ -493,7 +493,95 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
   }
 }
 
-void build_solve_plan(const Symbolic& S, int rpt, int split_target, SolvePlan& P) {
+namespace {
+
+// Item metadata shared by the per-level and the subtree lists (see SolvePlan).
+void push_item(const Symbolic& S, const SolvePlan& P, std::vector<int32_t>& items, int s, int t, int k0, int k1,
+               int slot, bool fwd) {
+  const int64_t po = S.panel_off[s];
+  items.insert(items.end(), {s, t, k0, k1, slot, S.begin[s], S.nr[s], S.nc[s], (int32_t)(po & 0xffffffff),
+                             (int32_t)(po >> 32), (int32_t)(fwd ? S.uvec_off[s] : P.bwd_src_off[s]),
+                             (int32_t)(S.child_ptr[s + 1] > S.child_ptr[s] ? 1 : 0)});
+}
+
+// Gather rows of supernode s (with children): own rows somebody contributes to, and every below row.
+void push_gather(const Symbolic& S, std::vector<int32_t>& dst, std::vector<int32_t>& ptr, std::vector<int32_t>& src,
+                 int s) {
+  const int nc = S.nc[s], nr = S.nr[s];
+  if (S.child_ptr[s + 1] == S.child_ptr[s]) return;
+  for (int r = 0; r < nr; ++r) {
+    const size_t before = src.size();
+    for (int32_t cq = S.child_ptr[s]; cq < S.child_ptr[s + 1]; ++cq) {
+      const int c = S.child_list[cq];
+      const int32_t jr = S.invmap[S.inv_off[c] + r];
+      if (jr >= 0) src.push_back((int32_t)(S.uvec_off[c] + jr));
+    }
+    if (r < nc && src.size() == before) continue;   // own row nobody contributes to
+    dst.push_back(r < nc ? S.begin[s] + r : -(int32_t)(S.uvec_off[s] + r - nc) - 1);
+    ptr.push_back((int32_t)src.size());
+  }
+}
+
+void build_subtree_lists(const Symbolic& S, int rpt, int sub_levels, SolvePlan& P) {
+  const int ns = S.nsuper;
+  auto roots_for = [&](int L, std::vector<int>& roots) {
+    roots.clear();
+    for (int s = 0; s < ns; ++s)
+      if (S.level[s] < L && (S.parent[s] < 0 || S.level[S.parent[s]] >= L)) roots.push_back(s);
+  };
+  std::vector<int> roots;
+  if (sub_levels < 0) {
+    // the whole tree when its panels are small: its levels are then launch-latency bound.  Larger
+    // trees keep one launch per level: a level's tiles spread over the whole chip finish sooner
+    // than a subtree's levels run one after another inside a workgroup (measured on the 64^3
+    // diffusion problem for cuts of 1 to 4 levels).
+    double bytes = 0;
+    for (int s = 0; s < ns; ++s) bytes += (double)S.nr[s] * S.nc[s] * 4;
+    sub_levels = (bytes <= 4e6) ? S.nlevels : 0;
+  }
+  sub_levels = std::max(0, std::min(sub_levels, S.nlevels));
+  P.sub_levels = sub_levels;
+  P.nsub = 0;
+  P.sub_gather_ptr.assign(1, 0);
+  if (sub_levels == 0) return;
+  roots_for(sub_levels, roots);
+  P.nsub = (int64_t)roots.size();
+  const int L = sub_levels;
+  P.sub_gather_off.assign(P.nsub * L + 1, 0);
+  P.sub_fwd_off.assign(P.nsub * L + 1, 0);
+  P.sub_bwd_off.assign(P.nsub * L + 1, 0);
+  std::vector<std::vector<int>> by_level(L);
+  std::vector<int> stack;
+  for (int64_t q = 0; q < P.nsub; ++q) {
+    for (auto& v : by_level) v.clear();
+    stack.assign(1, roots[q]);
+    while (!stack.empty()) {
+      const int s = stack.back();
+      stack.pop_back();
+      by_level[S.level[s]].push_back(s);
+      for (int32_t cq = S.child_ptr[s]; cq < S.child_ptr[s + 1]; ++cq) stack.push_back(S.child_list[cq]);
+    }
+    for (int l = 0; l < L; ++l) {
+      std::sort(by_level[l].begin(), by_level[l].end());
+      const int64_t e = q * L + l;
+      for (int s : by_level[l]) push_gather(S, P.sub_gather_dst, P.sub_gather_ptr, P.sub_gather_src, s);
+      P.sub_gather_off[e + 1] = (int64_t)P.sub_gather_dst.size();
+      for (int s : by_level[l])
+        for (int t = 0; t < (S.nr[s] + rpt - 1) / rpt; ++t) {
+          const int r0 = t * rpt;
+          push_item(S, P, P.sub_fwd_items, s, t, 0, (r0 < S.nc[s]) ? std::min(S.nc[s], r0 + rpt) : S.nc[s], -1, true);
+        }
+      P.sub_fwd_off[e + 1] = (int64_t)P.sub_fwd_items.size() / kSolveItemInts;
+      for (int s : by_level[l])
+        for (int t = 0; t < (S.nc[s] + rpt - 1) / rpt; ++t) push_item(S, P, P.sub_bwd_items, s, t, t * rpt, S.nr[s], -1, false);
+      P.sub_bwd_off[e + 1] = (int64_t)P.sub_bwd_items.size() / kSolveItemInts;
+    }
+  }
+}
+
+}  // namespace
+
+void build_solve_plan(const Symbolic& S, int rpt, int split_target, SolvePlan& P, int sub_levels) {
   P = SolvePlan();
   P.rows_per_tile = rpt;
   P.split_target = split_target;
@@ -590,6 +678,7 @@ void build_solve_plan(const Symbolic& S, int rpt, int split_target, SolvePlan& P
     P.fwd_fin_level_off[l + 1] = (int64_t)P.fwd_fin.size() / 4;
     P.bwd_fin_level_off[l + 1] = (int64_t)P.bwd_fin.size() / 4;
   }
+  build_subtree_lists(S, rpt, sub_levels, P);
 }
 
 }  // namespace lobpcg
@@ -652,6 +741,41 @@ std::string verify_solve_plan(const Symbolic& S, const SolvePlan& P) {
     if (!e.empty()) return "forward " + e;
     e = check_items(P.bwd_items, P.bwd_fin, P.bwd_slots, false);
     if (!e.empty()) return "backward " + e;
+  }
+  // subtree lists
+  if (P.sub_levels < 0 || P.sub_levels > S.nlevels) return "subtree levels";
+  if (P.sub_levels > 0) {
+    const int64_t ne = P.nsub * P.sub_levels + 1;
+    if ((int64_t)P.sub_gather_off.size() != ne || (int64_t)P.sub_fwd_off.size() != ne ||
+        (int64_t)P.sub_bwd_off.size() != ne)
+      return "subtree offsets";
+    for (int64_t e = 0; e + 1 < ne; ++e)
+      if (P.sub_gather_off[e + 1] < P.sub_gather_off[e] || P.sub_fwd_off[e + 1] < P.sub_fwd_off[e] ||
+          P.sub_bwd_off[e + 1] < P.sub_bwd_off[e])
+        return "subtree offsets order";
+    if (P.sub_gather_off[ne - 1] != (int64_t)P.sub_gather_dst.size() ||
+        P.sub_fwd_off[ne - 1] * kSolveItemInts != (int64_t)P.sub_fwd_items.size() ||
+        P.sub_bwd_off[ne - 1] * kSolveItemInts != (int64_t)P.sub_bwd_items.size())
+      return "subtree list sizes";
+    if (P.sub_gather_ptr.size() != P.sub_gather_dst.size() + 1 || P.sub_gather_ptr[0] != 0 ||
+        (size_t)P.sub_gather_ptr.back() != P.sub_gather_src.size())
+      return "subtree gather sizes";
+    for (size_t i = 0; i < P.sub_gather_dst.size(); ++i) {
+      const int32_t d = P.sub_gather_dst[i];
+      if (d >= 0 ? d >= S.n : (int64_t)(-d - 1) >= S.uvec_total) return "subtree gather destination";
+      if (P.sub_gather_ptr[i + 1] < P.sub_gather_ptr[i]) return "subtree gather pointers";
+    }
+    for (int32_t v : P.sub_gather_src)
+      if (v < 0 || v >= S.uvec_total) return "subtree gather source";
+    const std::vector<int32_t> nofin;
+    std::string e = check_items(P.sub_fwd_items, nofin, 0, true);
+    if (!e.empty()) return "subtree forward " + e;
+    e = check_items(P.sub_bwd_items, nofin, 0, false);
+    if (!e.empty()) return "subtree backward " + e;
+    for (size_t q = 0; q < P.sub_fwd_items.size(); q += kSolveItemInts)
+      if (S.level[P.sub_fwd_items[q]] >= P.sub_levels) return "subtree item level";
+    for (size_t q = 0; q < P.sub_bwd_items.size(); q += kSolveItemInts)
+      if (S.level[P.sub_bwd_items[q]] >= P.sub_levels) return "subtree item level";
   }
   return "";
 }

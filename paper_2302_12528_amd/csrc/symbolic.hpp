@@ -114,8 +114,22 @@ struct SolvePlan {
   // multiple of 4, the backward items' aux field); entry k < nc is begin + k (a row of y), entry
   // nc <= k < nr is n + rows[row_off + k] (a row of x, stored after y), the padding is 0
   std::vector<int32_t> bwd_src; std::vector<int64_t> bwd_src_off;
+  // Bottom levels 0 .. sub_levels - 1 as whole subtrees: a subtree is a supernode of level <
+  // sub_levels whose parent is above (or absent) together with all its descendants, and one
+  // workgroup runs it level by level (no launch per level).  For subtree q and local level l,
+  // entries [sub_*_off[q * sub_levels + l], sub_*_off[q * sub_levels + l + 1]) of the lists below
+  // are its gather rows (same encoding as gather_*, sources in sub_gather_src) and its unsplit
+  // tile items (kSolveItemInts ints each, slot -1).  The per-level lists of these levels are kept
+  // but not launched.
+  int sub_levels = 0;
+  int64_t nsub = 0;
+  std::vector<int32_t> sub_gather_dst, sub_gather_ptr, sub_gather_src; std::vector<int64_t> sub_gather_off;
+  std::vector<int32_t> sub_fwd_items; std::vector<int64_t> sub_fwd_off;
+  std::vector<int32_t> sub_bwd_items; std::vector<int64_t> sub_bwd_off;
 };
-void build_solve_plan(const Symbolic& S, int rows_per_tile, int split_target, SolvePlan& plan);
+// sub_levels < 0: chosen from the tree (the deepest bottom cut that still has enough subtrees to
+// occupy the chip, or the whole tree when it is small); otherwise as given (0: no subtree pass).
+void build_solve_plan(const Symbolic& S, int rows_per_tile, int split_target, SolvePlan& plan, int sub_levels = -1);
 
 // Check every index the GPU kernels dereference against the buffer it indexes
 // (rows, maps, offsets, task and item lists, assembly positions).  Returns an
