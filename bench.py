@@ -130,6 +130,30 @@ def cpu_baseline():
                       f"not scaled to 64^3"}
 
 
+def traffic_from_profile():
+    """HBM bytes per preconditioner application from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE passes, each scaled by a copy of known size), or None once the solve sources differ
+    from the ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "precond_traffic_diffusion3d_64.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ": " in line and line.split(": ", 1)[0] in ("traffic_bytes_per_application", "solve_sources_sha256",
+                                                           "solve_sources"):
+                k, v = line.rstrip("\n").split(": ", 1)
+                fields[k] = v
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    for src in fields["solve_sources"].split():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return float(fields["traffic_bytes_per_application"]) if h.hexdigest() == fields["solve_sources_sha256"] else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,7 +256,7 @@ def main():
         "fp64": fp64,
         "speedup_vs_fp64": round(fp64["time_to_tol_s"] / dt, 3) if fp64 else None,
         "roofline": {"bound": "hbm", "achieved": round(gbs_pc, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs_pc / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs_pc / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
                      "kernel": "preconditioner application (forward + backward supernodal sweeps, FP32 factor), "
                                "HIP events around each application in the timed solves",
                      "ms": round(ms_pc, 4), "applications": n_pc, "algorithmic_bytes": bytes_pc,
