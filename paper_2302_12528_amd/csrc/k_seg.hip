@@ -367,6 +367,122 @@ __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* i
     for (int k = 0; k < c; ++k) R[(int64_t)t * c + k] = (k >= t && t < rows) ? A[k * LP + t] : (T)0;
 }
 
+// Sum over the 64 lanes of a wave of each of the CP values q[0..CP) (CP = 8, 16 or 32), returned
+// in out[] as wave-uniform values.  Recursive halving: at each exchange a lane keeps half of its
+// vector and adds the partner lane's copy of that half (CP - 1 shuffles), the lane bits left over
+// are summed directly, and value k then sits in lane k << (6 - log2 CP).
+template <int CP>
+__device__ inline void wave_allreduce(float (&q)[CP], float (&out)[CP]) {
+  constexpr int LOG = (CP == 32) ? 5 : (CP == 16) ? 4 : 3;
+  static_assert((1 << LOG) == CP, "CP must be 8, 16 or 32");
+  const int lane = threadIdx.x % 64;
+#pragma unroll
+  for (int st = 0; st < LOG; ++st) {
+    const int m = 32 >> st;
+    const int half = CP >> (st + 1);
+    // lane-dependent choice between q[i] and q[i + half] by bit masks (a select between two array
+    // elements would be folded into a lane-dependent array index)
+    const uint32_t hm = (lane & m) ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const uint32_t lo_b = __builtin_bit_cast(uint32_t, q[i]), hi_b = __builtin_bit_cast(uint32_t, q[i + half]);
+      const float keep = __builtin_bit_cast(float, (hi_b & hm) | (lo_b & ~hm));
+      const float send = __builtin_bit_cast(float, (lo_b & hm) | (hi_b & ~hm));
+      q[i] = keep + __shfl_xor(send, m, 64);
+    }
+  }
+#pragma unroll
+  for (int m = 32 >> LOG; m >= 1; m >>= 1) q[0] += __shfl_xor(q[0], m, 64);
+#pragma unroll
+  for (int k = 0; k < CP; ++k)
+    out[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, q[0]), k << (6 - LOG)));
+}
+
+__device__ inline float lane_value(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// TSQR block in FP32 by one wave, four blocks per workgroup, no barriers: lane l holds rows l, l + 64,
+// l + 128, l + 192 of the block in registers.  Column j is always register column 0: after each
+// Householder step the remaining columns move one register to the left.  For column j the wave
+// all-reduce gives sigma = sum_{r > j} a_rj^2 and S_k = sum_{r > j} a_rj a_rk together; with
+// v = e_j + scale a(j+1:, j), w_k = a_jk + scale S_k and every row is updated in place.  Row j of R
+// is staged in LDS as it is produced.
+template <typename Tin, int CP>
+__global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in, int64_t ldin,
+                                                         const int32_t* __restrict__ items, int64_t nitems, int c,
+                                                         float* out) {
+  __shared__ float Rs[4][CP][CP + 1];
+  const int lane = threadIdx.x % 64, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+  const int64_t item = (int64_t)blockIdx.x * 4 + wv;
+  if (item >= nitems) return;   // whole wave
+  const int* it = items + 4 * item;   // {instance, first row, rows, output slot}
+  const int b = it[0];
+  if (!S.active[b]) return;
+  const int64_t r0 = it[1];
+  const int rows = it[2];
+  const int slot = it[3];
+  float a[4][CP];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int r = 64 * s + lane;
+#pragma unroll
+    for (int k = 0; k < CP; ++k) a[s][k] = (r < rows && k < c) ? (float)in[(r0 + r) * ldin + k] : 0.f;
+  }
+  float (*R)[CP + 1] = Rs[wv];
+  for (int e = lane; e < CP * (CP + 1); e += 64) (&R[0][0])[e] = 0.f;
+  const int kmax = (c < rows) ? c : rows;
+  for (int j = 0; j < kmax; ++j) {
+    float q[CP];
+#pragma unroll
+    for (int k = 0; k < CP; ++k) q[k] = 0.f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float x = (64 * s + lane > j) ? a[s][0] : 0.f;
+#pragma unroll
+      for (int k = 0; k < CP; ++k) q[k] += x * a[s][k];
+    }
+    float qs[CP];
+    wave_allreduce<CP>(q, qs);
+    const float sigma = qs[0];
+    const float alpha = lane_value(a[0][0], j);
+    float beta = alpha;
+    if (sigma > 0.f) {   // otherwise nothing below the diagonal: H_j = I (uniform)
+      const float xn = sqrtf(alpha * alpha + sigma);
+      beta = (alpha >= 0.f) ? -xn : xn;
+      const float tau = (beta - alpha) / beta;
+      const float scale = 1.f / (alpha - beta);
+      float w[CP];
+#pragma unroll
+      for (int k = 1; k < CP; ++k) w[k] = lane_value(a[0][k], j) + scale * qs[k];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int r = 64 * s + lane;
+        const float coef = (r > j) ? tau * scale * a[s][0] : ((r == j) ? tau : 0.f);
+#pragma unroll
+        for (int k = 1; k < CP; ++k) a[s][k] -= coef * w[k];
+      }
+    }
+    if (lane == j) {
+      R[j][j] = beta;
+#pragma unroll
+      for (int k = 1; k < CP; ++k)
+        if (j + k < CP) R[j][j + k] = a[0][k];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int k = 0; k + 1 < CP; ++k) a[s][k] = a[s][k + 1];
+      a[s][CP - 1] = 0.f;
+    }
+  }
+  float* Ro = out + (int64_t)slot * c * c;
+  for (int e = lane; e < c * c; e += 64) {
+    const int rr = e / c, cc = e % c;
+    Ro[e] = (cc >= rr) ? R[rr][cc] : 0.f;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -451,6 +567,12 @@ void stsqr_go(unsigned grid, const SegDev& S, const Tin* in, int64_t ld, const i
 template <typename T, typename Tin>
 void stsqr_launch(unsigned grid, const SegDev& S, const Tin* in, int64_t ld, const int32_t* items, int c, T* out,
                   hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {   // FP32 blocks of up to 32 columns: one wave per block
+    const unsigned g4 = (grid + 3) / 4;
+    if (c <= 8) { stsqr_wave_kernel<Tin, 8><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
+    if (c <= 16) { stsqr_wave_kernel<Tin, 16><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
+    if (c <= 32) { stsqr_wave_kernel<Tin, 32><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
+  }
   if (c <= 8) stsqr_go<T, Tin, 8>(grid, S, in, ld, items, c, out, st);
   else if (c <= 16) stsqr_go<T, Tin, 16>(grid, S, in, ld, items, c, out, st);
   else if (c <= 32) stsqr_go<T, Tin, 32>(grid, S, in, ld, items, c, out, st);
