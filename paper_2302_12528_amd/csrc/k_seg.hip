@@ -567,11 +567,15 @@ void stsqr_go(unsigned grid, const SegDev& S, const Tin* in, int64_t ld, const i
 template <typename T, typename Tin>
 void stsqr_launch(unsigned grid, const SegDev& S, const Tin* in, int64_t ld, const int32_t* items, int c, T* out,
                   hipStream_t st) {
-  if constexpr (sizeof(T) == 4) {   // FP32 blocks of up to 32 columns: one wave per block
-    const unsigned g4 = (grid + 3) / 4;
-    if (c <= 8) { stsqr_wave_kernel<Tin, 8><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
-    if (c <= 16) { stsqr_wave_kernel<Tin, 16><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
-    if (c <= 32) { stsqr_wave_kernel<Tin, 32><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
+  // FP32 blocks of up to 32 columns, many of them (a level that fills the chip): one wave per block.
+  // A few blocks (the top of the tree) finish sooner with a whole workgroup on each.
+  if constexpr (sizeof(T) == 4) {
+    if (grid >= 256) {
+      const unsigned g4 = (grid + 3) / 4;
+      if (c <= 8) { stsqr_wave_kernel<Tin, 8><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
+      if (c <= 16) { stsqr_wave_kernel<Tin, 16><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
+      if (c <= 32) { stsqr_wave_kernel<Tin, 32><<<g4, 256, 0, st>>>(S, in, ld, items, grid, c, out); return; }
+    }
   }
   if (c <= 8) stsqr_go<T, Tin, 8>(grid, S, in, ld, items, c, out, st);
   else if (c <= 16) stsqr_go<T, Tin, 16>(grid, S, in, ld, items, c, out, st);
