@@ -278,6 +278,34 @@ __global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, double* W, int
   }
 }
 
+// The same solve for c == CP columns with the row in registers (fully unrolled), one row per
+// thread: U_b is read through the scalar cache (all lanes use the same element), so nothing is
+// staged in LDS and many tiles share a compute unit.
+template <typename TU, int CP>
+__global__ void __launch_bounds__(64) strsm_rows_reg_kernel(SegDev S, double* W, int64_t ld,
+                                                            const TU* __restrict__ U, int64_t ustride) {
+  const int q = blockIdx.x;
+  const int b = S.tile_inst[q];
+  if (!S.active[b]) return;
+  const int64_t r0 = S.tile_r0[q];
+  const int rows = S.tile_rows[q];
+  const TU* Ub = U + (int64_t)b * ustride;
+  const int t = threadIdx.x;
+  if (t >= rows) return;
+  double* row = W + (r0 + t) * ld;
+  double x[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) x[k] = row[k];
+#pragma unroll
+  for (int j = 0; j < CP; ++j) {
+    x[j] /= (double)Ub[j * CP + j];
+#pragma unroll
+    for (int k = j + 1; k < CP; ++k) x[k] -= x[j] * (double)Ub[j * CP + k];
+  }
+#pragma unroll
+  for (int k = 0; k < CP; ++k) row[k] = x[k];
+}
+
 // ---------------------------------------------------------------------------
 // TSQR block: Householder QR (R only) of a block of at most 256 rows starting at `in`.
 // The block is held column-major in LDS (A[k][t], row t = thread t).  For column j one pass
@@ -553,7 +581,11 @@ template <typename TU>
 void launch_strsm_rows(const SegDev& S, double* W, int64_t ld, int c, const TU* U, int64_t ustride, hipStream_t st) {
   if (S.ntiles <= 0) return;
   const size_t lds = (size_t)(c * c + 64 * c) * sizeof(double);
-  strsm_rows_kernel<TU><<<(unsigned)S.ntiles, 64, lds, st>>>(S, W, ld, c, U, ustride);
+  const unsigned g = (unsigned)S.ntiles;
+  if (c == 8) strsm_rows_reg_kernel<TU, 8><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
+  else if (c == 16) strsm_rows_reg_kernel<TU, 16><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
+  else if (c == 32) strsm_rows_reg_kernel<TU, 32><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
+  else strsm_rows_kernel<TU><<<g, 64, lds, st>>>(S, W, ld, c, U, ustride);
 }
 template void launch_strsm_rows<float>(const SegDev&, double*, int64_t, int, const float*, int64_t, hipStream_t);
 template void launch_strsm_rows<double>(const SegDev&, double*, int64_t, int, const double*, int64_t, hipStream_t);
