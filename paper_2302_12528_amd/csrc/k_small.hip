@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "mfma.hpp"
 
 namespace lobpcg {
 
@@ -72,6 +73,216 @@ __device__ inline int sturm_count(const double* d, const double* e2, int c, doub
     cnt += (q < 0.0);
   }
   return cnt;
+}
+
+// Steps 2 and 3 for the tridiagonal T (diagonal d, off-diagonal e in LDS, e[c - 1] = 0): the nev
+// smallest eigenvalues in lam and the eigenvectors of T in Z (c x nev, row stride lz).  s1, s2:
+// kSyevMax doubles of LDS each; cnt: one int per thread; lu: 5 c nev doubles of global scratch.
+// Returns the largest number of later members of a cluster (0 when every eigenvalue is isolated);
+// Z and lam are complete and visible to the whole workgroup on return.
+__device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, const double* e, int c, int nev, double* s1, double* s2,
+                            double* lam, int* cnt, short* cend, double* Z, int lz, double* lu) {
+  const int tid = threadIdx.x, lane = tid % 64, wid = tid / 64;
+  // ---- 2. the nev smallest eigenvalues by multisection ----
+  double* e2 = s1;
+  double* lo = s2;
+  double* hi = lam;
+  double gl = 1e300, gu = -1e300, tnorm = 0.0, emax2 = 0.0;
+  for (int i = 0; i < c; ++i) {
+    const double ei = (i < c - 1) ? fabs(e[i]) : 0.0;
+    const double em = (i > 0) ? fabs(e[i - 1]) : 0.0;
+    gl = fmin(gl, d[i] - ei - em);
+    gu = fmax(gu, d[i] + ei + em);
+    tnorm = fmax(tnorm, fabs(d[i]) + ei + em);
+    emax2 = fmax(emax2, ei * ei);
+  }
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  gl -= 2.0 * eps * tnorm * c + 2.0 * pivmin;
+  gu += 2.0 * eps * tnorm * c + 2.0 * pivmin;
+  for (int i = tid; i < c; i += kSyevThreads) e2[i] = (i < c - 1) ? e[i] * e[i] : 0.0;
+  for (int j = tid; j < nev; j += kSyevThreads) {
+    lo[j] = gl;
+    hi[j] = gu;
+  }
+  __syncthreads();
+  const int P = max(1, kSyevThreads / nev);   // interior points per bracket
+  for (int round = 0; round < 200; ++round) {
+    const int j = tid / P, q = tid % P;
+    bool open = false;
+    if (j < nev) {
+      const double l = lo[j], h = hi[j];
+      open = (h - l > 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin);
+      const double x = l + (h - l) * (double)(q + 1) / (double)(P + 1);
+      cnt[tid] = (open && x > l && x < h) ? sturm_count(d, e2, c, x, pivmin) : -1;
+    }
+    if (!__syncthreads_or(open)) break;
+    if (j < nev && q == 0) {
+      const double l = lo[j], h = hi[j];
+      if (h - l > 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin) {
+        double nl = l, nh = h;
+        for (int r = 0; r < P; ++r) {
+          const int cr = cnt[tid + r];
+          if (cr < 0) continue;
+          const double x = l + (h - l) * (double)(r + 1) / (double)(P + 1);
+          if (cr >= j + 1) {
+            nh = x;
+            break;
+          }
+          nl = x;
+        }
+        if (nl == l && nh == h) nh = nl;   // no interior point strictly inside: the bracket is at ulp level
+        lo[j] = nl;
+        hi[j] = nh;
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < nev; j += kSyevThreads) lam[j] = 0.5 * (lo[j] + hi[j]);
+  __syncthreads();
+  // ---- 3. eigenvectors of T by inverse iteration ----
+  const double ortol = 1e-3 * tnorm;
+  if (tid == 0) {
+    cend[nev - 1] = (short)nev;
+    for (int j = nev - 2; j >= 0; --j) cend[j] = (lam[j + 1] - lam[j] < ortol) ? cend[j + 1] : (short)(j + 1);
+  }
+  double* U0 = lu;
+  double* U1 = lu + (int64_t)c * nev;
+  double* U2 = lu + 2 * (int64_t)c * nev;
+  double* Lm = lu + 3 * (int64_t)c * nev;
+  double* Pv = lu + 4 * (int64_t)c * nev;
+  const double tiny = eps * tnorm + pivmin;
+  // the diagonal of U with entries below tiny replaced by +-tiny (the elimination itself keeps the
+  // unreplaced pivots)
+  auto clamp_tiny = [tiny](double u) { return (fabs(u) < tiny) ? ((u < 0.0) ? -tiny : tiny) : u; };
+  for (int j = tid; j < nev; j += kSyevThreads) {
+    const double lj = lam[j];
+    double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0;
+    for (int k = 0; k + 1 < c; ++k) {
+      const double sub = e[k];
+      const double nd = d[k + 1] - lj;
+      const double ns = (k + 2 < c) ? e[k + 1] : 0.0;
+      if (fabs(cd) >= fabs(sub)) {
+        const double m = (cd != 0.0) ? sub / cd : 0.0;
+        U0[k * nev + j] = clamp_tiny(cd); U1[k * nev + j] = cs; U2[k * nev + j] = 0.0; Pv[k * nev + j] = 0.0;
+        Lm[k * nev + j] = m;
+        cd = nd - m * cs;
+        cs = ns;
+      } else {
+        const double m = cd / sub;
+        U0[k * nev + j] = clamp_tiny(sub); U1[k * nev + j] = nd; U2[k * nev + j] = ns; Pv[k * nev + j] = 1.0;
+        Lm[k * nev + j] = m;
+        cd = cs - m * nd;
+        cs = -m * ns;
+      }
+    }
+    U0[(c - 1) * nev + j] = clamp_tiny(cd);
+    for (int i = 0; i < c; ++i) Z[i * lz + j] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 11) / 11.0;
+  }
+  __syncthreads();
+  int maxrank = 0;
+  for (int j = 0; j < nev; ++j) maxrank = max(maxrank, (int)cend[j] - j - 1);
+  for (int itn = 0; itn < 2; ++itn) {
+    for (int j = tid; j < nev; j += kSyevThreads) {
+      // forward: P and L, carrying the running entry in a register; factors fetched 4 steps ahead
+      double zk = Z[j];
+      for (int k0 = 0; k0 + 1 < c; k0 += 4) {
+        double pv[4], lm[4], zn[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u;
+          const bool ok = k + 1 < c;
+          pv[u] = ok ? Pv[k * nev + j] : 0.0;
+          lm[u] = ok ? Lm[k * nev + j] : 0.0;
+          zn[u] = ok ? Z[(k + 1) * lz + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 + u;
+          if (k + 1 >= c) break;
+          double lo_ = zk, hi_ = zn[u];
+          if (pv[u] != 0.0) {
+            lo_ = zn[u];
+            hi_ = zk;
+          }
+          Z[k * lz + j] = lo_;
+          zk = hi_ - lm[u] * lo_;
+        }
+      }
+      Z[(c - 1) * lz + j] = zk;
+      // backward: U with two superdiagonals, factors fetched 4 steps ahead
+      double nrm = 0.0, z1 = 0.0, z2 = 0.0;   // Z[k + 1], Z[k + 2]
+      for (int k0 = c - 1; k0 >= 0; k0 -= 4) {
+        double u0[4], u1[4], u2[4], zz[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 - u;
+          const bool ok = k >= 0;
+          u0[u] = ok ? U0[k * nev + j] : 1.0;
+          u1[u] = ok ? U1[k * nev + j] : 0.0;
+          u2[u] = ok ? U2[k * nev + j] : 0.0;
+          zz[u] = ok ? Z[k * lz + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int k = k0 - u;
+          if (k < 0) break;
+          double y = zz[u];
+          if (k + 1 < c) y -= u1[u] * z1;
+          if (k + 2 < c) y -= u2[u] * z2;
+          y /= u0[u];
+          Z[k * lz + j] = y;
+          nrm += y * y;
+          z2 = z1;
+          z1 = y;
+        }
+      }
+      nrm = 1.0 / sqrt(nrm);
+      for (int i0 = 0; i0 < c; i0 += 8) {
+        double zz[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) zz[u] = (i0 + u < c) ? Z[(i0 + u) * lz + j] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (i0 + u < c) Z[(i0 + u) * lz + j] = zz[u] * nrm;
+      }
+    }
+    __syncthreads();
+    // modified Gram-Schmidt inside each cluster, in eigenvalue order: wave w takes the later
+    // members r = q + 1 + w, q + 1 + w + kSyevWaves, ...; lanes split the rows
+    for (int q = 0; q + 1 < nev; ++q) {
+      const int qe = cend[q];
+      if (qe - q < 2) continue;   // uniform
+      for (int r = q + 1 + wid; r < qe; r += kSyevWaves) {
+        // a lane holds at most 3 rows (c <= 192): load them, reduce, then store
+        double zq[3], zr[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int i = lane + 64 * u;
+          zq[u] = (i < c) ? Z[i * lz + q] : 0.0;
+          zr[u] = (i < c) ? Z[i * lz + r] : 0.0;
+        }
+        const double dot = wave_sum((zq[0] * zr[0] + zq[1] * zr[1]) + zq[2] * zr[2]);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int i = lane + 64 * u;
+          if (i < c) Z[i * lz + r] = zr[u] - dot * zq[u];
+        }
+      }
+      __syncthreads();
+      if (wid == 0) {
+        double z[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) z[u] = (lane + 64 * u < c) ? Z[(lane + 64 * u) * lz + q + 1] : 0.0;
+        const double nn = 1.0 / sqrt(wave_sum((z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]));
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          if (lane + 64 * u < c) Z[(lane + 64 * u) * lz + q + 1] = z[u] * nn;
+      }
+      __syncthreads();
+    }
+  }
+  return maxrank;
 }
 
 __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __restrict__ H, int64_t ldh,
@@ -195,205 +406,8 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     e[c - 1] = 0.0;
   }
   __syncthreads();
-  // ---- 2. the nev smallest eigenvalues by multisection ----
-  double* e2 = s1;
-  double* lo = s2;
-  double* hi = lam;
-  double gl = 1e300, gu = -1e300, tnorm = 0.0, emax2 = 0.0;
-  for (int i = 0; i < c; ++i) {
-    const double ei = (i < c - 1) ? fabs(e[i]) : 0.0;
-    const double em = (i > 0) ? fabs(e[i - 1]) : 0.0;
-    gl = fmin(gl, d[i] - ei - em);
-    gu = fmax(gu, d[i] + ei + em);
-    tnorm = fmax(tnorm, fabs(d[i]) + ei + em);
-    emax2 = fmax(emax2, ei * ei);
-  }
-  const double eps = 2.220446049250313e-16;
-  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
-  gl -= 2.0 * eps * tnorm * c + 2.0 * pivmin;
-  gu += 2.0 * eps * tnorm * c + 2.0 * pivmin;
-  for (int i = tid; i < c; i += kSyevThreads) e2[i] = (i < c - 1) ? e[i] * e[i] : 0.0;
-  for (int j = tid; j < nev; j += kSyevThreads) {
-    lo[j] = gl;
-    hi[j] = gu;
-  }
-  __syncthreads();
-  const int P = max(1, kSyevThreads / nev);   // interior points per bracket
-  for (int round = 0; round < 200; ++round) {
-    const int j = tid / P, q = tid % P;
-    bool open = false;
-    if (j < nev) {
-      const double l = lo[j], h = hi[j];
-      open = (h - l > 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin);
-      const double x = l + (h - l) * (double)(q + 1) / (double)(P + 1);
-      cnt[tid] = (open && x > l && x < h) ? sturm_count(d, e2, c, x, pivmin) : -1;
-    }
-    if (!__syncthreads_or(open)) break;
-    if (j < nev && q == 0) {
-      const double l = lo[j], h = hi[j];
-      if (h - l > 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin) {
-        double nl = l, nh = h;
-        for (int r = 0; r < P; ++r) {
-          const int cr = cnt[tid + r];
-          if (cr < 0) continue;
-          const double x = l + (h - l) * (double)(r + 1) / (double)(P + 1);
-          if (cr >= j + 1) {
-            nh = x;
-            break;
-          }
-          nl = x;
-        }
-        if (nl == l && nh == h) nh = nl;   // no interior point strictly inside: the bracket is at ulp level
-        lo[j] = nl;
-        hi[j] = nh;
-      }
-    }
-    __syncthreads();
-  }
-  for (int j = tid; j < nev; j += kSyevThreads) lam[j] = 0.5 * (lo[j] + hi[j]);
-  __syncthreads();
-  // ---- 3. eigenvectors of T by inverse iteration ----
-  const double ortol = 1e-3 * tnorm;
-  if (tid == 0) {
-    cend[nev - 1] = (short)nev;
-    for (int j = nev - 2; j >= 0; --j) cend[j] = (lam[j + 1] - lam[j] < ortol) ? cend[j + 1] : (short)(j + 1);
-  }
-  double* U0 = lu;
-  double* U1 = lu + (int64_t)c * nev;
-  double* U2 = lu + 2 * (int64_t)c * nev;
-  double* Lm = lu + 3 * (int64_t)c * nev;
-  double* Pv = lu + 4 * (int64_t)c * nev;
-  const double tiny = eps * tnorm + pivmin;
+  const int maxrank = tridiag_eigs(d, e, c, nev, s1, s2, lam, cnt, cend, Z, in_lds ? la : nev, lu);
   const int lz = in_lds ? la : nev;   // row stride of Z
-  for (int j = tid; j < nev; j += kSyevThreads) {
-    const double lj = lam[j];
-    double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0;
-    for (int k = 0; k + 1 < c; ++k) {
-      const double sub = e[k];
-      const double nd = d[k + 1] - lj;
-      const double ns = (k + 2 < c) ? e[k + 1] : 0.0;
-      if (fabs(cd) >= fabs(sub)) {
-        const double m = (cd != 0.0) ? sub / cd : 0.0;
-        U0[k * nev + j] = cd; U1[k * nev + j] = cs; U2[k * nev + j] = 0.0; Pv[k * nev + j] = 0.0;
-        Lm[k * nev + j] = m;
-        cd = nd - m * cs;
-        cs = ns;
-      } else {
-        const double m = cd / sub;
-        U0[k * nev + j] = sub; U1[k * nev + j] = nd; U2[k * nev + j] = ns; Pv[k * nev + j] = 1.0;
-        Lm[k * nev + j] = m;
-        cd = cs - m * nd;
-        cs = -m * ns;
-      }
-    }
-    U0[(c - 1) * nev + j] = cd;
-    for (int k = 0; k < c; ++k)
-      if (fabs(U0[k * nev + j]) < tiny) U0[k * nev + j] = (U0[k * nev + j] < 0.0) ? -tiny : tiny;
-    for (int i = 0; i < c; ++i) Z[i * lz + j] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 11) / 11.0;
-  }
-  __syncthreads();
-  int maxrank = 0;
-  for (int j = 0; j < nev; ++j) maxrank = max(maxrank, (int)cend[j] - j - 1);
-  for (int itn = 0; itn < 2; ++itn) {
-    for (int j = tid; j < nev; j += kSyevThreads) {
-      // forward: P and L, carrying the running entry in a register; factors fetched 4 steps ahead
-      double zk = Z[j];
-      for (int k0 = 0; k0 + 1 < c; k0 += 4) {
-        double pv[4], lm[4], zn[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + u;
-          const bool ok = k + 1 < c;
-          pv[u] = ok ? Pv[k * nev + j] : 0.0;
-          lm[u] = ok ? Lm[k * nev + j] : 0.0;
-          zn[u] = ok ? Z[(k + 1) * lz + j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + u;
-          if (k + 1 >= c) break;
-          double lo_ = zk, hi_ = zn[u];
-          if (pv[u] != 0.0) {
-            lo_ = zn[u];
-            hi_ = zk;
-          }
-          Z[k * lz + j] = lo_;
-          zk = hi_ - lm[u] * lo_;
-        }
-      }
-      Z[(c - 1) * lz + j] = zk;
-      // backward: U with two superdiagonals, factors fetched 4 steps ahead
-      double nrm = 0.0, z1 = 0.0, z2 = 0.0;   // Z[k + 1], Z[k + 2]
-      for (int k0 = c - 1; k0 >= 0; k0 -= 4) {
-        double u0[4], u1[4], u2[4], zz[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 - u;
-          const bool ok = k >= 0;
-          u0[u] = ok ? U0[k * nev + j] : 1.0;
-          u1[u] = ok ? U1[k * nev + j] : 0.0;
-          u2[u] = ok ? U2[k * nev + j] : 0.0;
-          zz[u] = ok ? Z[k * lz + j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 - u;
-          if (k < 0) break;
-          double y = zz[u];
-          if (k + 1 < c) y -= u1[u] * z1;
-          if (k + 2 < c) y -= u2[u] * z2;
-          y /= u0[u];
-          Z[k * lz + j] = y;
-          nrm += y * y;
-          z2 = z1;
-          z1 = y;
-        }
-      }
-      nrm = 1.0 / sqrt(nrm);
-      for (int i0 = 0; i0 < c; i0 += 8) {
-        double zz[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) zz[u] = (i0 + u < c) ? Z[(i0 + u) * lz + j] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (i0 + u < c) Z[(i0 + u) * lz + j] = zz[u] * nrm;
-      }
-    }
-    __syncthreads();
-    // modified Gram-Schmidt inside each cluster, in eigenvalue order: wave w takes the later
-    // members r = q + 1 + w, q + 1 + w + kSyevWaves, ...; lanes split the rows
-    for (int q = 0; q + 1 < nev; ++q) {
-      const int qe = cend[q];
-      if (qe - q < 2) continue;   // uniform
-      for (int r = q + 1 + wid; r < qe; r += kSyevWaves) {
-        // a lane holds at most 3 rows (c <= 192): load them, reduce, then store
-        double zq[3], zr[3];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          const int i = lane + 64 * u;
-          zq[u] = (i < c) ? Z[i * lz + q] : 0.0;
-          zr[u] = (i < c) ? Z[i * lz + r] : 0.0;
-        }
-        const double dot = wave_sum((zq[0] * zr[0] + zq[1] * zr[1]) + zq[2] * zr[2]);
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          const int i = lane + 64 * u;
-          if (i < c) Z[i * lz + r] = zr[u] - dot * zq[u];
-        }
-      }
-      __syncthreads();
-      if (wid == 0) {
-        double z[3];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) z[u] = (lane + 64 * u < c) ? Z[(lane + 64 * u) * lz + q + 1] : 0.0;
-        const double nn = 1.0 / sqrt(wave_sum((z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]));
-#pragma unroll
-        for (int u = 0; u < 3; ++u)
-          if (lane + 64 * u < c) Z[(lane + 64 * u) * lz + q + 1] = z[u] * nn;
-      }
-      __syncthreads();
-    }
-  }
   // ---- 4. back-transformation C = Q Z: G threads per column (a power of two), each a row segment ----
   int G = 1;
   while (G * 2 * nev <= kSyevThreads && G < 64) G *= 2;
@@ -440,6 +454,219 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   for (int q = tid; q < c * nev; q += kSyevThreads) {
     const int i = q / nev, j = q % nev;
     C[(int64_t)i * c + j] = Z[i * lz + j];
+  }
+  for (int j = tid; j < nev; j += kSyevThreads) evals[j] = lam[j];
+  if (tid == 0 && info) info[blockIdx.x] = maxrank;
+}
+
+// 64-bit DPP move (one 32-bit DPP move per half); CTRL = 0x120 + r rotates each 16-lane row by r.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 16 lanes of a row (lanes 16 r .. 16 r + 15).  Rotations by 8, 4, 2, 1: at each
+// stage the two lanes of a pair add the same two values, so every lane ends with the same bits.
+__device__ inline double row16_sum(double x) {
+  x += dpp_f64<0x128>(x);
+  x += dpp_f64<0x124>(x);
+  x += dpp_f64<0x122>(x);
+  x += dpp_f64<0x121>(x);
+  return x;
+}
+
+// Reflectors k = 16 AK .. 16 AK + 15 of the register tridiagonalization (see syev_reg_kernel);
+// AK is static so that the owner's row A[AK] and the finished blocks below AK are known at compile
+// time.  vb, pb: 2 x 16 NB doubles of LDS, pvp: 2 x 16, tb: 2 (double-buffered by step parity).
+template <int NB, int AK>
+__device__ __attribute__((always_inline)) void tridiag_rows(double (&A)[NB][NB], double (&Q)[NB][NB], int c, int ti,
+                                                            int tj, double* vb, double* pb, double* pvp, double* tb,
+                                                            double* d, double* e) {
+  constexpr int CM = 16 * NB;
+#pragma unroll 1
+  for (int r = 0; r < 16; ++r) {
+    const int k = 16 * AK + r;
+    if (k + 2 >= c) break;   // uniform
+    const int buf = k & 1;
+    if (ti == r) {
+      double ss = 0.0, al = 0.0;
+#pragma unroll
+      for (int b = AK; b < NB; ++b) {
+        const int j = tj + 16 * b;
+        const double x = A[AK][b];
+        ss += (j >= k + 2) ? x * x : 0.0;
+        al += (j == k + 1) ? x : 0.0;
+        if (j == k) d[k] = x;
+      }
+      ss = row16_sum(ss);
+      al = row16_sum(al);
+      double t = 0.0, beta = al, scale = 0.0;
+      if (ss > 0.0) {
+        const double xn = sqrt(al * al + ss);
+        beta = (al >= 0.0) ? -xn : xn;
+        t = (beta - al) / beta;
+        scale = 1.0 / (al - beta);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = tj + 16 * b;
+        vb[buf * CM + j] = (b >= AK && j > k + 1) ? A[AK][b] * scale : (j == k + 1 ? 1.0 : 0.0);
+      }
+      if (tj == 0) {
+        tb[buf] = t;
+        e[k] = beta;
+      }
+    }
+    __syncthreads();
+    const double t = tb[buf];
+    if (t == 0.0) continue;   // uniform; every buffer is double-buffered by step parity
+    // rows and columns below 16 AK are finished: their blocks are skipped (AK is static here)
+    double vc[NB], vr[NB], pp[NB], qq[NB];
+#pragma unroll
+    for (int b = AK; b < NB; ++b) vc[b] = vb[buf * CM + tj + 16 * b];
+#pragma unroll
+    for (int a = AK; a < NB; ++a) vr[a] = vb[buf * CM + ti + 16 * a];
+    double pv = 0.0;
+#pragma unroll
+    for (int a = AK; a < NB; ++a) {
+      double sp = 0.0;
+#pragma unroll
+      for (int b = AK; b < NB; ++b) sp = fma(A[a][b], vc[b], sp);
+      pp[a] = t * row16_sum(sp);
+      pv = fma(pp[a], vr[a], pv);
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      double sq_ = 0.0;
+#pragma unroll
+      for (int b = AK; b < NB; ++b) sq_ = fma(Q[a][b], vc[b], sq_);
+      qq[a] = t * row16_sum(sq_);
+    }
+    if (tj == 0) {
+#pragma unroll
+      for (int a = AK; a < NB; ++a) pb[buf * CM + ti + 16 * a] = pp[a];
+      pvp[buf * 16 + ti] = pv;
+    }
+    __syncthreads();
+    double K = 0.0;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) K += pvp[buf * 16 + g];
+    K *= 0.5 * t;
+    double wc[NB];
+#pragma unroll
+    for (int b = AK; b < NB; ++b) wc[b] = pb[buf * CM + tj + 16 * b] - K * vc[b];
+#pragma unroll
+    for (int a = AK; a < NB; ++a) {
+      const double wr = pp[a] - K * vr[a];
+#pragma unroll
+      for (int b = AK; b < NB; ++b) A[a][b] -= vr[a] * wc[b] + wr * vc[b];
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = AK; b < NB; ++b) Q[a][b] -= qq[a] * vc[b];
+  }
+  if constexpr (AK + 1 < NB) tridiag_rows<NB, AK + 1>(A, Q, c, ti, tj, vb, pb, pvp, tb, d, e);
+}
+
+// The eigensolver above for c <= 16 NB with the matrix in registers.  Thread (ti, tj) of a 16 x 16
+// grid (wave ti / 4, lanes 16 (ti % 4) .. 16 (ti % 4) + 15) holds H(ti + 16 a, tj + 16 b),
+// a, b < NB, and the same entries of Q = H_0 H_1 ... H_{c-3}, the product of the reflectors.
+// Reflector k (step 1): the 16 lanes of row k form v and t from that row and publish them; after
+// a barrier every row forms its entries of p = t H v and Q v by a 16-lane sum and publishes p and
+// its share of p^T v; after a second barrier every thread applies H -= v w^T + w v^T,
+// w = p - (t / 2) (p^T v) v, and Q -= t (Q v) v^T to its own entries.  Steps 2 and 3 are those of
+// the LDS form; step 4 is C = Q Z, one matrix-core product of Q and Z from LDS.
+template <int NB>
+__global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __restrict__ H, int64_t ldh,
+                                                                int64_t hstride, int c, int nev,
+                                                                double* __restrict__ evals, int64_t estride,
+                                                                double* __restrict__ C, int64_t cstride,
+                                                                double* __restrict__ work, int64_t wstride,
+                                                                int* info, const int32_t* __restrict__ active) {
+  static_assert(kSyevThreads == 256, "a 16 x 16 thread grid");
+  constexpr int CM = 16 * NB;
+  constexpr int LQ = CM + 1;
+  if (active && !active[blockIdx.x]) return;
+  H += (int64_t)blockIdx.x * hstride;
+  evals += (int64_t)blockIdx.x * estride;
+  C += (int64_t)blockIdx.x * cstride;
+  work += (int64_t)blockIdx.x * wstride;
+  // Z (c x nev, row stride nev + 1), then the inverse-iteration factors (5 c nev) and Q (c x c,
+  // row stride c + 1) where they fit; what does not fit goes to the global scratch
+  constexpr int POOL = (NB <= 3) ? 2 * CM * LQ + 5 * CM * CM : 2 * CM * LQ;
+  __shared__ double pool[POOL];
+  __shared__ double vb[2][CM], pb[2][CM], pvp[2][16], tb[2];
+  __shared__ double d[CM], e[CM], s1[CM], s2[CM], lam[CM];
+  __shared__ int cnt[kSyevThreads];
+  __shared__ short cend[CM];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int ti = wid * 4 + (lane >> 4), tj = lane & 15;
+  double A[NB][NB], Q[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      A[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
+      Q[a][b] = (i == j) ? 1.0 : 0.0;
+    }
+  // ---- 1. tridiagonalization, accumulating Q ----
+  tridiag_rows<NB, 0>(A, Q, c, ti, tj, &vb[0][0], &pb[0][0], &pvp[0][0], tb, d, e);
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      if (i == j && i + 2 >= c && i < c) d[i] = A[a][b];
+      if (c >= 2 && i == c - 1 && j == c - 2) e[c - 2] = A[a][b];
+    }
+  const int lz = nev + 1;
+  double* Z = pool;
+  int64_t used = (int64_t)c * lz;
+  double* lu;
+  double* sq;
+  if (used + 5 * (int64_t)c * nev <= POOL) {
+    lu = pool + used;
+    used += 5 * (int64_t)c * nev;
+  } else {
+    lu = work;
+  }
+  if (used + (int64_t)c * (c + 1) <= POOL) sq = pool + used;
+  else sq = work + 5 * (int64_t)c * nev;
+  const int lq = c + 1;
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      if (i < c && j < c) sq[i * lq + j] = Q[a][b];
+    }
+  if (tid == 0) e[c - 1] = 0.0;
+  __syncthreads();
+  // ---- 2, 3. eigenvalues and eigenvectors of T ----
+  const int maxrank = tridiag_eigs(d, e, c, nev, s1, s2, lam, cnt, cend, Z, lz, lu);
+  // ---- 4. C = Q Z (c x nev): 16 x 16 tiles, one wave per tile, 16x16x4 FP64 MFMAs ----
+  typedef Mfma<double>::v4 v4;
+  const int tn = (nev + 15) / 16, c4 = (c + 3) & ~3;
+  for (int tile = wid; tile < NB * tn; tile += kSyevThreads / 64) {
+    const int i0 = 16 * (tile / tn), j0 = 16 * (tile % tn);
+    v4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int ia = i0 + (lane & 15), jb = j0 + (lane & 15);
+    for (int l0 = 0; l0 < c4; l0 += 4) {
+      const int l = l0 + (lane >> 4);
+      const double qa = (l < c && ia < c) ? sq[ia * lq + l] : 0.0;
+      const double zb = (l < c && jb < nev) ? Z[l * lz + jb] : 0.0;
+      acc = Mfma<double>::op(qa, zb, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + Mfma<double>::drow(lane, q);
+      if (i < c && jb < nev) C[(int64_t)i * c + jb] = acc[q];
+    }
   }
   for (int j = tid; j < nev; j += kSyevThreads) evals[j] = lam[j];
   if (tid == 0 && info) info[blockIdx.x] = maxrank;
@@ -610,8 +837,17 @@ int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c *
 
 void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, int nev, double* evals, int64_t estride,
                  double* C, int64_t cstride, double* work, int* info, const int32_t* active, int B, hipStream_t st) {
-  syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work,
-                                          syev_scratch(c), info, active);
+  const int64_t ws = syev_scratch(c);
+  if (c <= 16)
+    syev_reg_kernel<1><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+  else if (c <= 32)
+    syev_reg_kernel<2><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+  else if (c <= 48)
+    syev_reg_kernel<3><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+  else if (c <= 96)
+    syev_reg_kernel<6><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+  else
+    syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
 }
 
 void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, int64_t gstride,

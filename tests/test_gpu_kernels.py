@@ -49,14 +49,15 @@ def test_gram_deterministic(torch_cuda):
     assert np.array_equal(G1, G2)
 
 
-@pytest.mark.parametrize("c", [8, 24, 47, 48, 96, 128, 192])
+@pytest.mark.parametrize("c", [1, 2, 3, 8, 16, 17, 24, 33, 47, 48, 95, 96, 128, 192])
 def test_syev_small(torch_cuda, c):
     import paper_2302_12528_amd as pk
     print(f"syev c={c}", flush=True)
     rng = np.random.default_rng(c)
     Q, _ = np.linalg.qr(rng.standard_normal((c, c)))
     lam = np.sort(rng.standard_normal(c))
-    lam[1] = lam[2]                       # an exact double eigenvalue
+    if c >= 3:
+        lam[1] = lam[2]                   # an exact double eigenvalue
     H = (Q * lam) @ Q.T
     H = 0.5 * (H + H.T)
     w, V = pk.syev_small(H)
