@@ -779,6 +779,147 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
   }
 }
 
+// One 16x16 output tile of D = A B on the matrix cores (FP64, 16x16x4 steps over k < K, K padded
+// to a multiple of 4 with zeros); lda/ldb: element (r, k) of A at A[r * ars + k * aks], (k, n) of
+// B at B[k * bks + n * bns], rows of A at or beyond ra and columns of B at or beyond nb read as
+// zero.  Returns the lane's four entries (rows Mfma<double>::drow(lane, q), column lane % 16).
+__device__ inline Mfma<double>::v4 tile_mm(const double* A, int ars, int aks, int ra, const double* B, int bks,
+                                            int bns, int nb, int K) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, kk = lane >> 4;
+  Mfma<double>::v4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + kk;
+    const double a = (k < K && r < ra) ? A[r * ars + k * aks] : 0.0;
+    const double b = (k < K && r < nb) ? B[k * bks + r * bns] : 0.0;
+    acc = Mfma<double>::op(a, b, acc);
+  }
+  return acc;
+}
+
+// The Hetmaniuk-Lehoucq step above for m <= 16 NCOL and c <= 16 RC.  The three products (W =
+// E1 - C1 C1(0:m, :)^T, T = C1^T W, W -= C1 T) run on the matrix cores from LDS; modified
+// Gram-Schmidt keeps W in registers: thread (slot s, lane q of its 16-lane row) holds rows
+// q + 16 u (u < RC) of columns s + 16 h (h < NCOL), so every column sum is a 16-lane DPP sum, and a
+// column step needs one barrier (the owners of column j normalise it and publish it; every later
+// column then subtracts its projection on it, with the next column's owners already done).
+template <int NCOL, int RC>
+__global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __restrict__ C, int64_t cstride, int c,
+                                                            int m, double* __restrict__ G, int64_t gstride,
+                                                            const int32_t* __restrict__ active) {
+  static_assert(kHlThreads == 256, "16 slots of 16 lanes");
+  constexpr int MM = 16 * NCOL, CM = 16 * RC, LD = MM + 1;
+  if (active && !active[blockIdx.x]) return;
+  C += (int64_t)blockIdx.x * cstride;
+  G += (int64_t)blockIdx.x * gstride;
+  __shared__ double c1[CM * LD], w[CM * LD], tm[MM * LD], wb[2][CM];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int ldg = (c > m) ? 2 * m : m;
+  for (int q = tid; q < c * m; q += kHlThreads) {
+    const int i = q / m, j = q % m;
+    const double x = C[(int64_t)i * c + j];
+    G[(int64_t)i * ldg + j] = x;
+    c1[i * LD + j] = x;
+  }
+  if (c <= m) return;
+  __syncthreads();
+  const int tr = (c + 15) / 16, tcm = (m + 15) / 16;
+  // W = E1 - C1 C1(0:m, :)^T
+  for (int tile = wid; tile < tr * tcm; tile += 4) {
+    const int i0 = 16 * (tile / tcm), j0 = 16 * (tile % tcm);
+    const Mfma<double>::v4 acc = tile_mm(c1 + i0 * LD, LD, 1, c - i0, c1 + j0 * LD, 1, LD, m - j0, m);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + Mfma<double>::drow(lane, q), j = j0 + (lane & 15);
+      if (i < c && j < m) w[i * LD + j] = ((i == j) ? 1.0 : 0.0) - acc[q];
+    }
+  }
+  __syncthreads();
+  const int q16 = lane & 15, slot = tid >> 4;
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    // T = C1^T W, then W -= C1 T
+    for (int tile = wid; tile < tcm * tcm; tile += 4) {
+      const int l0 = 16 * (tile / tcm), j0 = 16 * (tile % tcm);
+      const Mfma<double>::v4 acc = tile_mm(c1 + l0, 1, LD, m - l0, w + j0, LD, 1, m - j0, c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int l = l0 + Mfma<double>::drow(lane, q), j = j0 + (lane & 15);
+        if (l < m && j < m) tm[l * LD + j] = acc[q];
+      }
+    }
+    __syncthreads();
+    for (int tile = wid; tile < tr * tcm; tile += 4) {
+      const int i0 = 16 * (tile / tcm), j0 = 16 * (tile % tcm);
+      const Mfma<double>::v4 acc = tile_mm(c1 + i0 * LD, LD, 1, c - i0, tm + j0, LD, 1, m - j0, m);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + Mfma<double>::drow(lane, q), j = j0 + (lane & 15);
+        if (i < c && j < m) w[i * LD + j] -= acc[q];
+      }
+    }
+    __syncthreads();
+    // modified Gram-Schmidt on the columns of W, in registers
+    double W[NCOL][RC];
+#pragma unroll
+    for (int h = 0; h < NCOL; ++h)
+#pragma unroll
+      for (int u = 0; u < RC; ++u) {
+        const int i = q16 + 16 * u, j = slot + 16 * h;
+        W[h][u] = (i < c && j < m) ? w[i * LD + j] : 0.0;
+      }
+#pragma unroll
+    for (int hj = 0; hj < NCOL; ++hj) {
+#pragma unroll 1
+      for (int sj = 0; sj < 16; ++sj) {
+        const int j = 16 * hj + sj;
+        if (j >= m) break;   // uniform
+        const int buf = j & 1;
+        if (slot == sj) {
+          double ss = 0.0;
+#pragma unroll
+          for (int u = 0; u < RC; ++u) ss = fma(W[hj][u], W[hj][u], ss);
+          ss = row16_sum(ss);
+          const double inv = (ss > 0.0) ? 1.0 / sqrt(ss) : 0.0;
+#pragma unroll
+          for (int u = 0; u < RC; ++u) {
+            W[hj][u] *= inv;
+            wb[buf][q16 + 16 * u] = W[hj][u];
+          }
+        }
+        __syncthreads();
+        double wj[RC];
+#pragma unroll
+        for (int u = 0; u < RC; ++u) wj[u] = wb[buf][q16 + 16 * u];
+#pragma unroll
+        for (int h = hj; h < NCOL; ++h) {
+          const int col = slot + 16 * h;
+          if (col > j && col < m) {   // uniform over the 16 lanes of a slot
+            double dt = 0.0;
+#pragma unroll
+            for (int u = 0; u < RC; ++u) dt = fma(W[h][u], wj[u], dt);
+            dt = row16_sum(dt);
+#pragma unroll
+            for (int u = 0; u < RC; ++u) W[h][u] = fma(-dt, wj[u], W[h][u]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < NCOL; ++h)
+#pragma unroll
+      for (int u = 0; u < RC; ++u) {
+        const int i = q16 + 16 * u, j = slot + 16 * h;
+        if (i < c && j < m) w[i * LD + j] = W[h][u];
+      }
+    __syncthreads();
+  }
+  for (int q = tid; q < c * m; q += kHlThreads) {
+    const int i = q / m, j = q % m;
+    G[(int64_t)i * ldg + m + j] = w[i * LD + j];
+  }
+}
+
 // Algorithm 2 step 3: V^T V = L L^T (FP64).  Writes Lt = L^T (upper, row-major) for
 // the step-4 solve, and Rout = L^T working(Rl) (the R factor) when requested.
 // Flags a non-positive or non-finite pivot (W numerically rank deficient).
@@ -852,7 +993,9 @@ void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, int nev, 
 
 void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, int64_t gstride,
                      const int32_t* active, int B, hipStream_t st) {
-  hl_build_kernel<<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
+  if (m <= 16 && c <= 48) hl_reg_kernel<1, 3><<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
+  else if (m <= 32 && c <= 96) hl_reg_kernel<2, 6><<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
+  else hl_build_kernel<<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
 }
 
 template <typename T>
