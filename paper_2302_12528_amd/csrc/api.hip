@@ -90,15 +90,17 @@ void build_segments(const std::vector<int64_t>& inst_off, int64_t rpc, SegHost& 
 
 // Householder TSQR reduction tree for instances with row ranges inst_off and row blocks of rb.
 struct TsqrHost {
-  int rb = 0;
+  int rb = 0, rbu = 0;
   std::vector<int64_t> level_off;
   std::vector<int32_t> items;
   int64_t half = 1;
 };
 
-void build_tsqr(const std::vector<int64_t>& inst_off, int c, int rb, TsqrHost& T) {
+// rb rows per item at level 0, rbu (a multiple of c) at the levels above
+void build_tsqr(const std::vector<int64_t>& inst_off, int c, int rb, int rbu, TsqrHost& T) {
   T = TsqrHost();
   T.rb = rb;
+  T.rbu = rbu;
   const int B = (int)inst_off.size() - 1;
   std::vector<int64_t> rows(B), in0(B), cnt(B), newbase(B);
   for (int b = 0; b < B; ++b) {
@@ -131,6 +133,7 @@ void build_tsqr(const std::vector<int64_t>& inst_off, int c, int rb, TsqrHost& T
       in0[b] = newbase[b] * c;
       rows[b] = cnt[b] * c;
     }
+    rb = rbu;
   }
   T.half = maxout * c * c;
 }
@@ -266,6 +269,7 @@ lobpcg_status upload_segments(lobpcg_ctx c) {
 
 lobpcg_status upload_tsqr(lobpcg_ctx c, TsqrHost& H, TsqrPlanDev& D) {
   D.rb = H.rb;
+  D.rbu = H.rbu;
   D.nlevels = (int)H.level_off.size() - 1;
   D.level_off = H.level_off.data();
   D.half = H.half;
@@ -578,8 +582,8 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
       }
   C.chunk_rows = default_chunk_rows(n);
   build_segments(inst_off, C.chunk_rows, C.SH);
-  build_tsqr(inst_off, m, tsqr_rows_per_block(m, 4), C.TQ32);
-  build_tsqr(inst_off, m, tsqr_rows_per_block(m, 8), C.TQ64);
+  build_tsqr(inst_off, m, tsqr_rows_per_block(m, 4), tsqr_upper_rows_per_block(m, 4), C.TQ32);
+  build_tsqr(inst_off, m, tsqr_rows_per_block(m, 8), tsqr_upper_rows_per_block(m, 8), C.TQ64);
   C.t_symbolic = now_s() - t0;
   auto cleanup = [&](lobpcg_status s) {
     delete c;
@@ -1470,9 +1474,11 @@ lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t cc, int64_t ldw, int
   TempSeg T;
   if (!T.init(n)) return fail(LOBPCG_ERR_ALLOC, "hipMalloc failed");
   TsqrHost th;
-  build_tsqr(std::vector<int64_t>{0, n}, cc, tsqr_rows_per_block(cc, lower_step1 ? 4 : 8), th);
+  build_tsqr(std::vector<int64_t>{0, n}, cc, tsqr_rows_per_block(cc, lower_step1 ? 4 : 8),
+             tsqr_upper_rows_per_block(cc, lower_step1 ? 4 : 8), th);
   TsqrPlanDev tp{};
   tp.rb = th.rb;
+  tp.rbu = th.rbu;
   tp.nlevels = (int)th.level_off.size() - 1;
   tp.level_off = th.level_off.data();
   tp.half = th.half;

@@ -28,10 +28,11 @@ struct SegDev {
   const int32_t* inst_chunk_off;                                          // B + 1
 };
 // Householder TSQR reduction tree: level l has items [level_off[l], level_off[l+1]) of 4 ints
-// {instance, first row, rows, output slot}; level 0 reads the block, later levels the stacked R's
-// of the previous level (ping-pong halves of `half` elements); the last level writes slot b of R.
+// {instance, first row, rows, output slot}; level 0 reads the block (rb rows per item), later levels
+// the stacked R's of the previous level (rbu rows per item; ping-pong halves of `half` elements);
+// the last level writes slot b of R.
 struct TsqrPlanDev {
-  int rb; int nlevels;
+  int rb; int rbu; int nlevels;
   const int64_t* level_off;   // host, nlevels + 1
   const int32_t* items;       // device
   int64_t half;               // elements per scratch half
@@ -53,6 +54,7 @@ template <typename T>
 void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const double* W, int64_t ldw, int c, T* scratch, T* R,
                   hipStream_t st);
 int tsqr_rows_per_block(int c, int elem_bytes);
+int tsqr_upper_rows_per_block(int c, int elem_bytes);
 
 // ---- products with A and data movement (k_block.hip) ----
 // Y = A X for permuted CSR A; X, Y n x c row-major (ld), any c >= 1.

@@ -307,21 +307,21 @@ __global__ void __launch_bounds__(64) strsm_rows_reg_kernel(SegDev S, double* W,
 }
 
 // ---------------------------------------------------------------------------
-// TSQR block: Householder QR (R only) of a block of at most 256 rows starting at `in`.
+// TSQR block: Householder QR (R only) of a block of at most NR rows starting at `in`.
 // The block is held column-major in LDS (A[k][t], row t = thread t).  For column j one pass
 // gives every sum the step needs, S_k = sum_{t > j} a_tj a_tk for k >= j (S_j is the squared
-// norm below the diagonal), each column pair summed by 256 / CP threads and a shuffle; with
+// norm below the diagonal), each column pair summed by NR / CP threads and a shuffle; with
 // v = e_j + scale * a(j+1:, j), w_k = v^T a(:, k) = a_jk + scale S_k, and thread t then
 // updates its own row.
 // ---------------------------------------------------------------------------
 constexpr int kTsqrRows = 256;
+constexpr int kTsqrRowsWide = 1024;   // FP32 blocks of the upper levels (stacked R factors), c <= 32
 
-template <typename T, typename Tin, int CP>
-__global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* in, int64_t ldin,
-                                                          const int32_t* __restrict__ items, int c, T* out) {
-  constexpr int NR = kTsqrRows;
+template <typename T, typename Tin, int CP, int NR = kTsqrRows>
+__global__ void __launch_bounds__(NR) stsqr_kernel(SegDev S, const Tin* in, int64_t ldin,
+                                                   const int32_t* __restrict__ items, int c, T* out) {
   constexpr int PARTS = NR / CP;        // threads per column sum
-  constexpr int LP = NR + 4;            // padded LDS column
+  constexpr int LP = NR + 8;            // padded LDS column (columns of a sum group in other banks)
   __shared__ T A[CP * LP];              // A[k * LP + t] = element (t, k)
   __shared__ T sk[CP];                  // S_k
   const int* it = items + 4 * blockIdx.x;   // {instance, first row, rows, output slot}
@@ -339,20 +339,20 @@ __global__ void __launch_bounds__(kTsqrRows) stsqr_kernel(SegDev S, const Tin* i
     // S_k for k >= j over the rows below the diagonal (the PARTS threads of a column are
     // consecutive lanes of one wave)
     if (sk_k >= j && sk_k < c) {
-      const T* cj = A + j * LP + sk_part * CP;
-      const T* ck = A + sk_k * LP + sk_part * CP;
-      const int base = sk_part * CP;
+      // part p sums rows p, p + PARTS, ...: the lanes of a column read consecutive words
+      const T* cj = A + j * LP + sk_part;
+      const T* ck = A + sk_k * LP + sk_part;
       T x[CP], y[CP];
 #pragma unroll
       for (int q = 0; q < CP; ++q) {
-        x[q] = cj[q];
-        y[q] = ck[q];
+        x[q] = cj[q * PARTS];
+        y[q] = ck[q * PARTS];
       }
       T s0 = 0, s1 = 0;
 #pragma unroll
       for (int q = 0; q < CP; q += 2) {
-        s0 += (base + q > j) ? x[q] * y[q] : (T)0;
-        s1 += (base + q + 1 > j) ? x[q + 1] * y[q + 1] : (T)0;
+        s0 += (sk_part + q * PARTS > j) ? x[q] * y[q] : (T)0;
+        s1 += (sk_part + (q + 1) * PARTS > j) ? x[q + 1] * y[q + 1] : (T)0;
       }
       T sum = s0 + s1;
 #pragma unroll
@@ -622,10 +622,21 @@ void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const double* W, int64_
     const int64_t i0 = P.level_off[l], i1 = P.level_off[l + 1];
     if (i1 <= i0) continue;
     T* out = (l == P.nlevels - 1) ? R : scratch + (l % 2) * P.half;
-    if (l == 0)
-      stsqr_launch<T, double>((unsigned)(i1 - i0), S, W, ldw, P.items + 4 * i0, c, out, st);
-    else
-      stsqr_launch<T, T>((unsigned)(i1 - i0), S, scratch + ((l - 1) % 2) * P.half, c, P.items + 4 * i0, c, out, st);
+    const unsigned grid = (unsigned)(i1 - i0);
+    if (l == 0) {
+      stsqr_launch<T, double>(grid, S, W, ldw, P.items + 4 * i0, c, out, st);
+      continue;
+    }
+    const T* in = scratch + ((l - 1) % 2) * P.half;
+    if constexpr (sizeof(T) == 4) {
+      if (P.rbu == kTsqrRowsWide) {   // plan guarantees c <= 32
+        if (c <= 8) stsqr_kernel<T, T, 8, kTsqrRowsWide><<<grid, kTsqrRowsWide, 0, st>>>(S, in, c, P.items + 4 * i0, c, out);
+        else if (c <= 16) stsqr_kernel<T, T, 16, kTsqrRowsWide><<<grid, kTsqrRowsWide, 0, st>>>(S, in, c, P.items + 4 * i0, c, out);
+        else stsqr_kernel<T, T, 32, kTsqrRowsWide><<<grid, kTsqrRowsWide, 0, st>>>(S, in, c, P.items + 4 * i0, c, out);
+        continue;
+      }
+    }
+    stsqr_launch<T, T>(grid, S, in, c, P.items + 4 * i0, c, out, st);
   }
 }
 template void launch_stsqr<float>(const SegDev&, const TsqrPlanDev&, const double*, int64_t, int, float*, float*,
@@ -638,5 +649,7 @@ int tsqr_rows_per_block(int c, int elem_bytes) {
   (void)elem_bytes;
   return kTsqrRows;
 }
+
+int tsqr_upper_rows_per_block(int c, int elem_bytes) { return (elem_bytes == 4 && c <= 32) ? kTsqrRowsWide : kTsqrRows; }
 
 }  // namespace lobpcg
