@@ -219,17 +219,20 @@ __device__ inline void load_cm_vec(T (*As)[TB + 1], const T* M, int64_t ld, int 
 // needs one launch); the task with I == p writes L_pp and inv(L_pp), every other task replaces its
 // tile (I, p) by C inv(L_pp)^T.  Rows and columns of the tile at or beyond h are padded with the
 // identity.
-//   factorization: thread (row i, quarter w) holds row i, columns 16 w .. 16 w + 15 in registers;
-//     column j is published through LDS by the owning quarter and every thread applies the rank-1
-//     update to its columns past j (one barrier per column);
-//   inverse: X = inv(L) by forward substitution on the identity inside the same column loop, each
-//     quarter for its 16 columns, row j broadcast across the wave with readlane.
+//   factorization: thread (row i, quarter w) holds row i, columns 16 w .. 16 w + 15 in registers,
+//     so wave w holds 16 whole columns.  Quarter by quarter, the owning wave factors its 16 columns
+//     alone (L[c][j] of another row c is a readlane) and publishes them through LDS; after one
+//     barrier the waves to its right subtract the rank-16 product from their columns;
+//   inverse: X = inv(L) by forward substitution on the identity, each quarter for its 16 columns:
+//     the waves at or left of the published quarter take its 16 row steps (row j of X broadcast
+//     across the wave with readlane) while the waves to its right update.
 template <typename T>
 __global__ void __launch_bounds__(256) potrf_trsm_kernel(FactorDev D, int64_t task_off, T* panel, T* upd,
                                                          T* dinv, int* flag) {
   __shared__ T Ls[TB][TB + 1];   // the K-major tile C(I, p)
   __shared__ T Xs[TB][TB + 1];   // Xs[k][c] = inv(L)[c][k]
-  __shared__ T colbuf[2][TB];
+  constexpr int LBS = (sizeof(T) == 4) ? 20 : 18;   // 16-byte aligned rows
+  __shared__ T Lb[2][TB][LBS];   // the published quarter of L, double-buffered
   const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
   const int s = tk[0], I = tk[1], p = tk[3];
   const Sn S = sn_of(D, s);
@@ -259,45 +262,54 @@ __global__ void __launch_bounds__(256) potrf_trsm_kernel(FactorDev D, int64_t ta
   int bad = 0;
   // the outer loop stays rolled: this kernel runs once per panel step, so its code is fetched cold
   // each time and must stay short
-  // x: row i, columns 16 w .. 16 w + 15 of X = inv(L), formed alongside: step j scales row j of X by
-  // 1 / L[j][j] and subtracts L[i][j] times it from the rows below (forward substitution on the
-  // identity); only quarters w <= j / 16 hold nonzero columns of row j
+  // x: row i, columns 16 w .. 16 w + 15 of X = inv(L): step j scales row j of X by 1 / L[j][j] and
+  // subtracts L[i][j] times it from the rows below; only quarters w <= j / 16 hold nonzero columns
+  // of row j
   T x[16];
 #pragma unroll
   for (int kk = 0; kk < 16; ++kk) x[kk] = (i == 16 * w + kk) ? (T)1 : (T)0;
 #pragma unroll 1
   for (int jb = 0; jb < 4; ++jb) {
+    T (*lb)[LBS] = Lb[jb & 1];
+    if (w == jb) {
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      const int j = 16 * jb + jj;
-      T* cb = colbuf[jj & 1];
-      if (w == jb) cb[i] = a[jj];
-      __syncthreads();
-      T d = cb[j];
-      const bool ok = (d > (T)0) && (d < (T)INFINITY);
-      if (!ok) d = (T)1;
-      const T ljj = sqrt(d);
-      const T rinv = (T)1 / ljj;
-      const T li = cb[i] * rinv;
-      const T lb = (i > j) ? li : (T)0;
-      if (w > jb) {
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) a[kk] -= li * (cb[16 * w + kk] * rinv);
-      } else if (w == jb) {
-        if (!ok && bad == 0) bad = j + 1;
-#pragma unroll
-        for (int kk = jj + 1; kk < 16; ++kk) a[kk] -= li * (cb[16 * w + kk] * rinv);
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * jb + jj;
+        T d = rdl(a[jj], j);
+        const bool ok = (d > (T)0) && (d < (T)INFINITY);
+        if (!ok) {
+          d = (T)1;
+          if (bad == 0) bad = j + 1;
+        }
+        const T ljj = sqrt(d);
+        const T rinv = (T)1 / ljj;
+        const T li = a[jj] * rinv;
         a[jj] = (i > j) ? li : (i == j ? ljj : (T)0);
 #pragma unroll
-        for (int kk = 0; kk <= jj; ++kk) {
-          if (i == j) x[kk] *= rinv;
-          x[kk] -= lb * rdl(x[kk], j);
-        }
-      } else {
+        for (int kk = jj + 1; kk < 16; ++kk) a[kk] -= li * rdl(a[jj], 16 * jb + kk);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) lb[i][jj] = a[jj];
+    }
+    __syncthreads();
+    if (w > jb) {
+      T lrow[16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) lrow[jj] = lb[i][jj];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj)
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) a[kk] -= lrow[jj] * lb[16 * w + kk][jj];
+    } else {
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * jb + jj;
+        const T rinv = (T)1 / lb[j][jj];
+        const T lbi = (i > j) ? lb[i][jj] : (T)0;
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
           if (i == j) x[kk] *= rinv;
-          x[kk] -= lb * rdl(x[kk], j);
+          x[kk] -= lbi * rdl(x[kk], j);
         }
       }
     }

@@ -60,28 +60,59 @@ __device__ inline double rcp_nr(double q) {
   return r;
 }
 
-// Number of eigenvalues of T (diagonal d, squared off-diagonal e2) below x: negative pivots of the
-// LDL^T factorization of T - x I, with tiny pivots replaced by -pivmin.
-__device__ inline int sturm_count(const double* d, const double* e2, int c, double x, double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += (q < 0.0);
-  for (int i = 1; i < c; ++i) {
-    q = fma(-e2[i - 1], rcp_nr(q), d[i] - x);
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += (q < 0.0);
+// Number of eigenvalues of T below x, from T scaled by a power of two to norm about one (diagonal
+// ds, squared off-diagonal e2s, shift xs).  The leading principal minors
+// p_i = (ds_i - xs) p_{i-1} - e2s_{i-1} p_{i-2} (p_{-1} = 1) are the products of the LDL^T pivots
+// q_i = p_i / p_{i-1}, so a sign change from p_{i-1} to p_i is a negative pivot; a pivot below pmin
+// in magnitude is replaced by -pmin (p_i = -pmin p_{i-1}).  The only dependent operation per step is
+// one FMA and the pivot test (e2s_{i-1} p_{i-2} is ready a step earlier, and no reciprocal is
+// needed); p_{i-1} and p_i are rescaled by a power of two every four steps.  The arrays are padded
+// to c + 8 entries with ds = 8 and e2s = 0 (|xs| < 4): steps past the end change no sign, so the
+// four-step groups need no exit test and the next group's loads overlap the current one.
+__device__ inline int sturm_count_scaled(const double* ds, const double* e2s, int c, double xs, double pmin) {
+  double pm2 = 1.0, pm1 = ds[0] - xs;
+  if (fabs(pm1) < pmin) pm1 = -pmin;
+  int cnt = (pm1 < 0.0);
+  double dd[4], ee[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    dd[u] = ds[1 + u];
+    ee[u] = e2s[u];
+  }
+  for (int i0 = 1; i0 < c; i0 += 4) {
+    double dn[4], en[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      dn[u] = ds[i0 + 4 + u];
+      en[u] = e2s[i0 + 3 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double p = fma(dd[u] - xs, pm1, -ee[u] * pm2);
+      if (fabs(p) < pmin * fabs(pm1)) p = -pmin * pm1;
+      cnt += ((p < 0.0) != (pm1 < 0.0));
+      pm2 = pm1;
+      pm1 = p;
+    }
+    const int k = __builtin_amdgcn_frexp_exp(pm1);
+    pm1 = ldexp(pm1, -k);
+    pm2 = ldexp(pm2, -k);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      dd[u] = dn[u];
+      ee[u] = en[u];
+    }
   }
   return cnt;
 }
 
 // Steps 2 and 3 for the tridiagonal T (diagonal d, off-diagonal e in LDS, e[c - 1] = 0): the nev
-// smallest eigenvalues in lam and the eigenvectors of T in Z (c x nev, row stride lz).  s1, s2:
-// kSyevMax doubles of LDS each; cnt: one int per thread; lu: 5 c nev doubles of global scratch.
+// smallest eigenvalues in lam and the eigenvectors of T in Z (c x nev, row stride lz).  s1, s3:
+// c + 8 doubles of LDS each, s2: c; cnt: one int per thread; lu: 5 c nev doubles of global scratch.
 // Returns the largest number of later members of a cluster (0 when every eigenvalue is isolated);
 // Z and lam are complete and visible to the whole workgroup on return.
 __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, const double* e, int c, int nev, double* s1, double* s2,
-                            double* lam, int* cnt, short* cend, double* Z, int lz, double* lu) {
+                            double* s3, double* lam, int* cnt, short* cend, double* Z, int lz, double* lu) {
   const int tid = threadIdx.x, lane = tid % 64, wid = tid / 64;
   // ---- 2. the nev smallest eigenvalues by multisection ----
   double* e2 = s1;
@@ -100,7 +131,16 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   gl -= 2.0 * eps * tnorm * c + 2.0 * pivmin;
   gu += 2.0 * eps * tnorm * c + 2.0 * pivmin;
-  for (int i = tid; i < c; i += kSyevThreads) e2[i] = (i < c - 1) ? e[i] * e[i] : 0.0;
+  // T scaled by sc = 2^-ilogb(||T||) for the Sturm counts (s3: scaled diagonal; both padded to
+  // c + 8 entries, ds = 8 and e2 = 0 past the end)
+  const double sc = (tnorm > 0.0) ? ldexp(1.0, -ilogb(tnorm)) : 1.0;
+  const double pmin = fmax(sc * pivmin, 0x1p-100);
+  double* ds = s3;
+  for (int i = tid; i < c + 8; i += kSyevThreads) {
+    const double es = (i < c - 1) ? sc * e[i] : 0.0;
+    e2[i] = es * es;
+    ds[i] = (i < c) ? sc * d[i] : 8.0;
+  }
   for (int j = tid; j < nev; j += kSyevThreads) {
     lo[j] = gl;
     hi[j] = gu;
@@ -114,7 +154,7 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
       const double l = lo[j], h = hi[j];
       open = (h - l > 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin);
       const double x = l + (h - l) * (double)(q + 1) / (double)(P + 1);
-      cnt[tid] = (open && x > l && x < h) ? sturm_count(d, e2, c, x, pivmin) : -1;
+      cnt[tid] = (open && x > l && x < h) ? sturm_count_scaled(ds, e2, c, sc * x, pmin) : -1;
     }
     if (!__syncthreads_or(open)) break;
     if (j < nev && q == 0) {
@@ -299,7 +339,8 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   __shared__ double sa[kSyevLds * (kSyevLds + 1)];
   __shared__ double sz[kSyevLds * (kSyevLds + 1)];
   __shared__ double d[kSyevMax], e[kSyevMax], tau[kSyevMax];
-  __shared__ double s1[kSyevMax], s2[kSyevMax];   // v, p (step 1) | e^2, bracket lows (step 2)
+  __shared__ double s1[kSyevMax + 8], s2[kSyevMax];   // v, p (step 1) | e^2, bracket lows (step 2)
+  __shared__ double s3[kSyevMax + 8];
   __shared__ double lam[kSyevMax];                // bracket highs, then eigenvalues
   __shared__ int cnt[kSyevThreads];
   __shared__ short cend[kSyevMax];
@@ -406,7 +447,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     e[c - 1] = 0.0;
   }
   __syncthreads();
-  const int maxrank = tridiag_eigs(d, e, c, nev, s1, s2, lam, cnt, cend, Z, in_lds ? la : nev, lu);
+  const int maxrank = tridiag_eigs(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, in_lds ? la : nev, lu);
   const int lz = in_lds ? la : nev;   // row stride of Z
   // ---- 4. back-transformation C = Q Z: G threads per column (a power of two), each a row segment ----
   int G = 1;
@@ -600,7 +641,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   constexpr int POOL = (NB <= 3) ? 2 * CM * LQ + 5 * CM * CM : 2 * CM * LQ;
   __shared__ double pool[POOL];
   __shared__ double vb[2][CM], pb[2][CM], pvp[2][16], tb[2];
-  __shared__ double d[CM], e[CM], s1[CM], s2[CM], lam[CM];
+  __shared__ double d[CM], e[CM], s1[CM + 8], s2[CM], s3[CM + 8], lam[CM];
   __shared__ int cnt[kSyevThreads];
   __shared__ short cend[CM];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -648,7 +689,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   if (tid == 0) e[c - 1] = 0.0;
   __syncthreads();
   // ---- 2, 3. eigenvalues and eigenvectors of T ----
-  const int maxrank = tridiag_eigs(d, e, c, nev, s1, s2, lam, cnt, cend, Z, lz, lu);
+  const int maxrank = tridiag_eigs(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu);
   // ---- 4. C = Q Z (c x nev): 16 x 16 tiles, one wave per tile, 16x16x4 FP64 MFMAs ----
   typedef Mfma<double>::v4 v4;
   const int tn = (nev + 15) / 16, c4 = (c + 3) & ~3;
