@@ -11,6 +11,7 @@
 //   tsqr      R factor of each X_b (Algorithm 2 step 1), Householder in T
 #include "common.hpp"
 #include "mfma.hpp"
+#include "bufload.hpp"
 
 namespace lobpcg {
 
@@ -219,6 +220,67 @@ __global__ void __launch_bounds__(kThreads) sresidual_kernel(SegDev S, const dou
   if (t < m) {
     part[(int64_t)q * 2 * m + t] = ((red[0][0][t] + red[0][1][t]) + red[0][2][t]) + red[0][3][t];
     part[(int64_t)q * 2 * m + m + t] = ((red[1][0][t] + red[1][1][t]) + red[1][2][t]) + red[1][3][t];
+  }
+}
+
+// The same residual with two columns per lane (16-byte loads of X and AX, 8-byte stores of R): a
+// row is read by CPL = m / 2 consecutive lanes, a wave covers 64 / CPL rows per step and four steps
+// are loaded together.  Per-lane partial sums go through LDS and are added in a fixed order.
+template <typename T, int CPL>
+__global__ void __launch_bounds__(kThreads) sresidual2_kernel(SegDev S, const double* __restrict__ AX, int64_t ldax,
+                                                              const double* __restrict__ X, int64_t ldx,
+                                                              const double* __restrict__ theta, int64_t tstride,
+                                                              T* __restrict__ R, int64_t ldr,
+                                                              double* __restrict__ part) {
+  constexpr int M = 2 * CPL, RPW = 64 / CPL, RPB = 4 * RPW, U = 4;
+  __shared__ double red[4][RPW][M][2];
+  const int q = blockIdx.x;
+  const int b = S.chunk_inst[q];
+  if (!S.active[b]) return;
+  const int t = threadIdx.x, lane = t % 64, w = t / 64;
+  const int jp = lane % CPL, rl = lane / CPL;
+  const int64_t rbeg = S.chunk_r0[q];
+  const int64_t rend = rbeg + S.chunk_rows[q];
+  const double th0 = theta[(int64_t)b * tstride + 2 * jp], th1 = theta[(int64_t)b * tstride + 2 * jp + 1];
+  double rs0 = 0.0, rs1 = 0.0, xs0 = 0.0, xs1 = 0.0;
+  for (int64_t r0 = rbeg + w * RPW + rl; r0 < rend; r0 += (int64_t)U * RPB) {
+    f64x2_t xv[U], av[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * RPB;
+      if (r < rend) {
+        xv[u] = *reinterpret_cast<const f64x2_t*>(X + r * ldx + 2 * jp);
+        av[u] = *reinterpret_cast<const f64x2_t*>(AX + r * ldax + 2 * jp);
+      } else {
+        xv[u] = f64x2_t{0.0, 0.0};
+        av[u] = f64x2_t{0.0, 0.0};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = r0 + (int64_t)u * RPB;
+      const double v0 = av[u].x - xv[u].x * th0, v1 = av[u].y - xv[u].y * th1;
+      if (r < rend) {
+        R[r * ldr + 2 * jp] = (T)v0;
+        R[r * ldr + 2 * jp + 1] = (T)v1;
+      }
+      rs0 = fma(v0, v0, rs0);
+      rs1 = fma(v1, v1, rs1);
+      xs0 = fma(xv[u].x, xv[u].x, xs0);
+      xs1 = fma(xv[u].y, xv[u].y, xs1);
+    }
+  }
+  red[w][rl][2 * jp][0] = rs0;
+  red[w][rl][2 * jp + 1][0] = rs1;
+  red[w][rl][2 * jp][1] = xs0;
+  red[w][rl][2 * jp + 1][1] = xs1;
+  __syncthreads();
+  if (t < 2 * M) {
+    const int j = t % M, k = t / M;
+    double sum = 0.0;
+    for (int ww = 0; ww < 4; ++ww)
+      for (int g = 0; g < RPW; ++g) sum += red[ww][g][j][k];
+    part[(int64_t)q * 2 * M + k * M + j] = sum;
   }
 }
 
@@ -562,7 +624,13 @@ void launch_sresidual(const SegDev& S, const double* AX, int64_t ldax, const dou
                       const double* theta, int64_t tstride, int m, T* R, int64_t ldr, double* norms, double* part,
                       hipStream_t st) {
   if (S.nchunks <= 0) return;
-  sresidual_kernel<T><<<(unsigned)S.nchunks, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, m, R, ldr, part);
+  const bool vec = (ldx % 2 == 0) && (ldax % 2 == 0) && (ldr % 2 == 0) &&
+                   ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(AX)) % 16 == 0);
+  const unsigned g = (unsigned)S.nchunks;
+  if (vec && m == 32) sresidual2_kernel<T, 16><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
+  else if (vec && m == 16) sresidual2_kernel<T, 8><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
+  else if (vec && m == 8) sresidual2_kernel<T, 4><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
+  else sresidual_kernel<T><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, m, R, ldr, part);
   sreduce_kernel<<<dim3(cdiv(2 * m, kRedElems), S.B), 256, 0, st>>>(S, part, 2 * m, norms, 2 * m);
 }
 template void launch_sresidual<float>(const SegDev&, const double*, int64_t, const double*, int64_t, const double*,
