@@ -14,6 +14,13 @@ namespace lobpcg {
 namespace {
 
 
+__device__ inline double rdl64(double v, int l) {
+  const uint64_t x = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -1013,6 +1020,60 @@ __global__ void __launch_bounds__(256) chol_upper_kernel(const double* __restric
   }
 }
 
+// The same factorization by one wave for c <= CP: lane i holds row i of the symmetrised G, so the
+// diagonal and L[k][j] of another row k are readlanes and no barrier is needed.  Rout = L^T Rl with
+// lane j forming column j.
+template <typename T, int CP>
+__global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __restrict__ G, const T* __restrict__ Rl,
+                                                             int c, double* __restrict__ Lt, double* __restrict__ Rout,
+                                                             int* flag, const int32_t* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
+  const int64_t off = (int64_t)blockIdx.x * c * c;
+  G += off;
+  Rl += off;
+  Lt += off;
+  if (Rout) Rout += off;
+  flag += blockIdx.x;
+  const int i = threadIdx.x;
+  double a[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) a[k] = (i < c && k < c) ? 0.5 * (G[i * c + k] + G[k * c + i]) : 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < CP; ++j) {
+    if (j < c) {   // uniform
+      double d = rdl64(a[j], j);
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = true;
+        d = 1.0;
+      }
+      const double ljj = sqrt(d);
+      a[j] = (i == j) ? ljj : a[j] / ljj;
+#pragma unroll
+      for (int k = j + 1; k < CP; ++k) a[k] -= a[j] * rdl64(a[j], k);
+    }
+  }
+  if (bad && i == 0) flag[0] = 1;
+  // column i of Lt = row i of L (zeros below the diagonal of Lt)
+  if (i < c)
+    for (int k = 0; k < c; ++k) Lt[k * c + i] = 0.0;
+#pragma unroll
+  for (int k = 0; k < CP; ++k)
+    if (i < c && k <= i) Lt[k * c + i] = a[k];
+  if (Rout) {
+    double rl[CP];
+#pragma unroll
+    for (int k = 0; k < CP; ++k) rl[k] = (i < c && k < c) ? (double)Rl[k * c + i] : 0.0;
+#pragma unroll
+    for (int r = 0; r < CP; ++r) {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = r; k < CP; ++k) sum += rdl64(a[r], k) * rl[k];
+      if (i < c && r < c) Rout[r * c + i] = sum;
+    }
+  }
+}
+
 }  // namespace
 
 int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c + 16; }
@@ -1042,7 +1103,9 @@ void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, 
 template <typename T>
 void launch_chol_upper(const double* G, const T* Rl, int c, double* Lt, double* Rout, int* flag,
                        const int32_t* active, int B, hipStream_t st) {
-  chol_upper_kernel<T><<<B, 256, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
+  if (c <= 32) chol_upper_wave_kernel<T, 32><<<B, 64, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
+  else if (c <= 64) chol_upper_wave_kernel<T, 64><<<B, 64, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
+  else chol_upper_kernel<T><<<B, 256, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
 }
 template void launch_chol_upper<float>(const double*, const float*, int, double*, double*, int*, const int32_t*, int,
                                        hipStream_t);
