@@ -125,14 +125,22 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   double* e2 = s1;
   double* lo = s2;
   double* hi = lam;
+  // Gershgorin bounds, ||T||_inf and max e^2: every wave reduces them over its lanes (min / max are
+  // exact, so every wave gets the same values)
   double gl = 1e300, gu = -1e300, tnorm = 0.0, emax2 = 0.0;
-  for (int i = 0; i < c; ++i) {
+  for (int i = lane; i < c; i += 64) {
     const double ei = (i < c - 1) ? fabs(e[i]) : 0.0;
     const double em = (i > 0) ? fabs(e[i - 1]) : 0.0;
     gl = fmin(gl, d[i] - ei - em);
     gu = fmax(gu, d[i] + ei + em);
     tnorm = fmax(tnorm, fabs(d[i]) + ei + em);
     emax2 = fmax(emax2, ei * ei);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, off, 64));
+    gu = fmax(gu, __shfl_xor(gu, off, 64));
+    tnorm = fmax(tnorm, __shfl_xor(tnorm, off, 64));
+    emax2 = fmax(emax2, __shfl_xor(emax2, off, 64));
   }
   const double eps = 2.220446049250313e-16;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
@@ -148,9 +156,22 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
     e2[i] = es * es;
     ds[i] = (i < c) ? sc * d[i] : 8.0;
   }
+  __syncthreads();
+  // first round, shared by all brackets: kSyevThreads points spread over [gl, gu]; the bracket of
+  // eigenvalue j is then found by bisection on the counts, keeping count(lo) <= j < count(hi)
+  // (index -1 stands for gl and kSyevThreads for gu)
+  auto point = [gl, gu](int t) { return gl + (gu - gl) * (double)(t + 1) / (double)(kSyevThreads + 1); };
+  cnt[tid] = sturm_count_scaled(ds, e2, c, sc * point(tid), pmin);
+  __syncthreads();
   for (int j = tid; j < nev; j += kSyevThreads) {
-    lo[j] = gl;
-    hi[j] = gu;
+    int a = -1, b = kSyevThreads;
+    while (b - a > 1) {
+      const int mid = (a + b) / 2;
+      if (cnt[mid] <= j) a = mid;
+      else b = mid;
+    }
+    lo[j] = (a < 0) ? gl : point(a);
+    hi[j] = (b >= kSyevThreads) ? gu : point(b);
   }
   __syncthreads();
   const int P = max(1, kSyevThreads / nev);   // interior points per bracket
