@@ -21,6 +21,25 @@ __device__ inline double rdl64(double v, int l) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// 64-bit DPP move (one 32-bit DPP move per half); CTRL = 0x120 + r rotates each 16-lane row by r.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over the 16 lanes of a row (lanes 16 r .. 16 r + 15).  Rotations by 8, 4, 2, 1: at each
+// stage the two lanes of a pair add the same two values, so every lane ends with the same bits.
+__device__ inline double row16_sum(double x) {
+  x += dpp_f64<0x128>(x);
+  x += dpp_f64<0x124>(x);
+  x += dpp_f64<0x122>(x);
+  x += dpp_f64<0x121>(x);
+  return x;
+}
+
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -113,11 +132,62 @@ __device__ inline int sturm_count_scaled(const double* ds, const double* e2s, in
   return cnt;
 }
 
+// Modified Gram-Schmidt inside the clusters of eigenvectors (eigenvalue order) with Z (c x nev,
+// c, nev <= 16 NB) in registers: thread (slot s = tid / 16, lane q16 of its 16-lane row) holds rows
+// q16 + 16 u of columns s + 16 h, so column sums are 16-lane DPP sums.  Column q is published by its
+// owners (one barrier, buffers alternating per executed step); the later members of its cluster
+// subtract their projections on it and the owners of q + 1 normalise it right away.  HQ is static
+// (column block of q), so register indices are static.
+template <int NB, int HQ>
+__device__ __attribute__((always_inline)) void cluster_mgs_cols(double (&z)[NB][NB], int nev, const short* cend,
+                                                                double* wb0, double* wb1, int& ns) {
+  const int tid = threadIdx.x, q16 = tid & 15, slot = tid >> 4;
+#pragma unroll 1
+  for (int sq = 0; sq < 16; ++sq) {
+    const int q = 16 * HQ + sq;
+    if (q + 1 >= nev) break;   // uniform
+    const int qe = cend[q];
+    if (qe - q < 2) continue;   // uniform
+    double* wb = (ns & 1) ? wb1 : wb0;
+    ++ns;
+    if (slot == sq) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) wb[q16 + 16 * u] = z[HQ][u];
+    }
+    __syncthreads();
+    double wq[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) wq[u] = wb[q16 + 16 * u];
+#pragma unroll
+    for (int h = HQ; h < NB; ++h) {
+      const int col = slot + 16 * h;
+      if (col > q && col < qe) {   // uniform over the 16 lanes of a slot
+        double dt = 0.0;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) dt = fma(z[h][u], wq[u], dt);
+        dt = row16_sum(dt);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) z[h][u] = fma(-dt, wq[u], z[h][u]);
+        if (col == q + 1) {
+          double nn = 0.0;
+#pragma unroll
+          for (int u = 0; u < NB; ++u) nn = fma(z[h][u], z[h][u], nn);
+          const double inv = 1.0 / sqrt(row16_sum(nn));
+#pragma unroll
+          for (int u = 0; u < NB; ++u) z[h][u] *= inv;
+        }
+      }
+    }
+  }
+  if constexpr (HQ + 1 < NB) cluster_mgs_cols<NB, HQ + 1>(z, nev, cend, wb0, wb1, ns);
+}
+
 // Steps 2 and 3 for the tridiagonal T (diagonal d, off-diagonal e in LDS, e[c - 1] = 0): the nev
 // smallest eigenvalues in lam and the eigenvectors of T in Z (c x nev, row stride lz).  s1, s3:
 // c + 8 doubles of LDS each, s2: c; cnt: one int per thread; lu: 5 c nev doubles of global scratch.
 // Returns the largest number of later members of a cluster (0 when every eigenvalue is isolated);
 // Z and lam are complete and visible to the whole workgroup on return.
+template <int NB>
 __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, const double* e, int c, int nev, double* s1, double* s2,
                             double* s3, double* lam, int* cnt, short* cend, double* Z, int lz, double* lu) {
   const int tid = threadIdx.x, lane = tid % 64, wid = tid / 64;
@@ -316,38 +386,62 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
       }
     }
     __syncthreads();
-    // modified Gram-Schmidt inside each cluster, in eigenvalue order: wave w takes the later
-    // members r = q + 1 + w, q + 1 + w + kSyevWaves, ...; lanes split the rows
-    for (int q = 0; q + 1 < nev; ++q) {
-      const int qe = cend[q];
-      if (qe - q < 2) continue;   // uniform
-      for (int r = q + 1 + wid; r < qe; r += kSyevWaves) {
-        // a lane holds at most 3 rows (c <= 192): load them, reduce, then store
-        double zq[3], zr[3];
+    if constexpr (NB > 0) {
+      if (maxrank > 0) {   // uniform
+        const int q16 = tid & 15, slot = tid >> 4;
+        double z[NB][NB];
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          const int i = lane + 64 * u;
-          zq[u] = (i < c) ? Z[i * lz + q] : 0.0;
-          zr[u] = (i < c) ? Z[i * lz + r] : 0.0;
-        }
-        const double dot = wave_sum((zq[0] * zr[0] + zq[1] * zr[1]) + zq[2] * zr[2]);
+        for (int h = 0; h < NB; ++h)
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          const int i = lane + 64 * u;
-          if (i < c) Z[i * lz + r] = zr[u] - dot * zq[u];
-        }
+          for (int u = 0; u < NB; ++u) {
+            const int i = q16 + 16 * u, j = slot + 16 * h;
+            z[h][u] = (i < c && j < nev) ? Z[i * lz + j] : 0.0;
+          }
+        int ns = 0;
+        cluster_mgs_cols<NB, 0>(z, nev, cend, s1, s3, ns);
+#pragma unroll
+        for (int h = 0; h < NB; ++h)
+#pragma unroll
+          for (int u = 0; u < NB; ++u) {
+            const int i = q16 + 16 * u, j = slot + 16 * h;
+            if (i < c && j < nev) Z[i * lz + j] = z[h][u];
+          }
+        __syncthreads();
       }
-      __syncthreads();
-      if (wid == 0) {
-        double z[3];
+    } else {
+      // modified Gram-Schmidt inside each cluster, in eigenvalue order: wave w takes the later
+      // members r = q + 1 + w, q + 1 + w + kSyevWaves, ...; lanes split the rows
+      for (int q = 0; q + 1 < nev; ++q) {
+        const int qe = cend[q];
+        if (qe - q < 2) continue;   // uniform
+        for (int r = q + 1 + wid; r < qe; r += kSyevWaves) {
+          // a lane holds at most 3 rows (c <= 192): load them, reduce, then store
+          double zq[3], zr[3];
 #pragma unroll
-        for (int u = 0; u < 3; ++u) z[u] = (lane + 64 * u < c) ? Z[(lane + 64 * u) * lz + q + 1] : 0.0;
-        const double nn = 1.0 / sqrt(wave_sum((z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]));
+          for (int u = 0; u < 3; ++u) {
+            const int i = lane + 64 * u;
+            zq[u] = (i < c) ? Z[i * lz + q] : 0.0;
+            zr[u] = (i < c) ? Z[i * lz + r] : 0.0;
+          }
+          const double dot = wave_sum((zq[0] * zr[0] + zq[1] * zr[1]) + zq[2] * zr[2]);
 #pragma unroll
-        for (int u = 0; u < 3; ++u)
-          if (lane + 64 * u < c) Z[(lane + 64 * u) * lz + q + 1] = z[u] * nn;
+          for (int u = 0; u < 3; ++u) {
+            const int i = lane + 64 * u;
+            if (i < c) Z[i * lz + r] = zr[u] - dot * zq[u];
+          }
+        }
+        __syncthreads();
+        if (wid == 0) {
+          double z[3];
+#pragma unroll
+          for (int u = 0; u < 3; ++u) z[u] = (lane + 64 * u < c) ? Z[(lane + 64 * u) * lz + q + 1] : 0.0;
+          const double nn = 1.0 / sqrt(wave_sum((z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]));
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+            if (lane + 64 * u < c) Z[(lane + 64 * u) * lz + q + 1] = z[u] * nn;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   return maxrank;
@@ -475,7 +569,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     e[c - 1] = 0.0;
   }
   __syncthreads();
-  const int maxrank = tridiag_eigs(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, in_lds ? la : nev, lu);
+  const int maxrank = tridiag_eigs<0>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, in_lds ? la : nev, lu);
   const int lz = in_lds ? la : nev;   // row stride of Z
   // ---- 4. back-transformation C = Q Z: G threads per column (a power of two), each a row segment ----
   int G = 1;
@@ -528,24 +622,6 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   if (tid == 0 && info) info[blockIdx.x] = maxrank;
 }
 
-// 64-bit DPP move (one 32-bit DPP move per half); CTRL = 0x120 + r rotates each 16-lane row by r.
-template <int CTRL>
-__device__ inline double dpp_f64(double x) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, x);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Sum over the 16 lanes of a row (lanes 16 r .. 16 r + 15).  Rotations by 8, 4, 2, 1: at each
-// stage the two lanes of a pair add the same two values, so every lane ends with the same bits.
-__device__ inline double row16_sum(double x) {
-  x += dpp_f64<0x128>(x);
-  x += dpp_f64<0x124>(x);
-  x += dpp_f64<0x122>(x);
-  x += dpp_f64<0x121>(x);
-  return x;
-}
 
 // Reflectors k = 16 AK .. 16 AK + 15 of the register tridiagonalization (see syev_reg_kernel);
 // AK is static so that the owner's row A[AK] and the finished blocks below AK are known at compile
@@ -717,7 +793,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   if (tid == 0) e[c - 1] = 0.0;
   __syncthreads();
   // ---- 2, 3. eigenvalues and eigenvectors of T ----
-  const int maxrank = tridiag_eigs(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu);
+  const int maxrank = tridiag_eigs<NB>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu);
   // ---- 4. C = Q Z (c x nev): 16 x 16 tiles, one wave per tile, 16x16x4 FP64 MFMAs ----
   typedef Mfma<double>::v4 v4;
   const int tn = (nev + 15) / 16, c4 = (c + 3) & ~3;
