@@ -164,6 +164,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched run (0 = skip)")
+    ap.add_argument("--pinvit-maxit", type=int, default=400, help="iteration cap of the PINVIT run (0 = skip)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first copy a 256 MiB buffer once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -226,6 +227,18 @@ def main():
     rng = np.random.default_rng(7)
     R = torch.from_numpy(rng.standard_normal((p.n, p.m))).cuda()
     ms_pc_iso = event_time(torch, lambda: mixed.apply_precond(R), args.reps)
+    # Algorithm 1 (mixed-precision block PINVIT) on the same context and start block, one run to tol
+    # (solve only: it reuses this context's FP32 factor)
+    pinvit = None
+    if args.pinvit_maxit > 0:
+        log("pinvit")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam_pv, _, info_pv = mixed.pinvit(X0, maxit=args.pinvit_maxit, allow_not_converged=True)
+        torch.cuda.synchronize()
+        pinvit = {"t_solve_s": round(time.perf_counter() - t0, 5), "iters": info_pv["iters"],
+                  "converged": info_pv["status"] == 0, "lobpcg_iters": info["iters"],
+                  "max_eig_rel_diff_vs_lobpcg": float(np.max(np.abs(lam_pv.cpu().numpy() - lam_np) / lam_np))}
     mixed.close()
 
     fp64 = None
@@ -264,6 +277,7 @@ def main():
         "spmm": {"ms": round(ms_spmm, 4), "GBs": round(gbs_spmm, 1), "frac": round(gbs_spmm / HBM_PEAK_GBS, 4),
                  "launches": n_sp, "algorithmic_bytes": bytes_spmm},
         "parity": parity,
+        "pinvit": pinvit,
     }
     if args.batched > 0:
         out["batched"] = batched_run(torch, pk, 1, args.batched)

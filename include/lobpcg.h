@@ -148,6 +148,22 @@ lobpcg_status lobpcg_factor(lobpcg_ctx ctx);
 lobpcg_status lobpcg_solve(lobpcg_ctx ctx, const double* X0, int32_t maxit,
                            double* evals, double* evecs, lobpcg_info* info);
 
+/* Algorithm 1 (section 3.1): mixed-precision block PINVIT on the context's
+ * matrix, factor and preconditioner.  Per iteration: X = Q of X~ (the QR is
+ * Algorithm 2), Theta = X^T A X, R = A X - X Theta, return once the k leading
+ * columns pass the test of lobpcg_solve (eq. (stop)), W = working(f_T(lower(R))),
+ * X~ = X - W.  Theta is diagonalised every iteration (X <- X C, A X <- A X C
+ * with Theta = C D C^T; the span of X and hence the iteration are unchanged)
+ * so that the test and the outputs are per Ritz pair.  X0, maxit, evals, evecs
+ * and info as lobpcg_solve; theta_hist (host, nullable) receives the k
+ * smallest Ritz values of every iteration, k per row, maxit rows (rows after
+ * the last iteration are left untouched).  Single-problem contexts only
+ * (INVALID_ARG otherwise).  Returns OK, NOT_CONVERGED (outputs still
+ * written), NONFINITE, ORTHO_BREAKDOWN or HIP.  Synchronises the stream;
+ * afterwards lobpcg_backward needs a new lobpcg_solve. */
+lobpcg_status lobpcg_pinvit(lobpcg_ctx ctx, const double* X0, int32_t maxit, double* evals,
+                            double* evecs, lobpcg_info* info, double* theta_hist);
+
 /* Batched setup: count independent problems A[0..count-1] (CSR, each with its
  * own n_b and grid hint) sharing k, m, tol and the factor precision; each is
  * solved by Algorithm 3 exactly as lobpcg_solve would (batching is an addition

@@ -1155,6 +1155,138 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
   return overall;
 }
 
+// Algorithm 1 (mixed-precision block PINVIT) for a single-problem context; see lobpcg_pinvit.
+// X~, then X and A X, live in columns 0 .. m - 1 of Sb[cur] / ASb[cur]; the diagonalised X and A X
+// go to Sb[1 - cur] / ASb[1 - cur], whose columns m .. 2m - 1 take W.
+lobpcg_status pinvit_core(lobpcg_ctx c, const double* X0, int32_t maxit, double* evals_out, double* evecs_out,
+                          lobpcg_info* info, double* theta_hist) {
+  lobpcg_ctx_s& C = *c;
+  hipStream_t st = C.st;
+  const int m = C.m, k = C.k, m3 = 3 * m;
+  const int64_t n = C.n;
+  C.solved = false;
+  C.fallbacks = 0;
+  const double t_start = now_s();
+  C.active.assign(1, 1);
+  ST_TRY(set_active(c));
+  int cur = 0;
+  // line 1: X~ = X0
+  if (X0)
+    launch_gather_rows(X0, m, C.d_perm, 0, C.Sb[cur], m3, n, m, st);
+  else
+    launch_gaussian_fill(C.Sb[cur], n, m, m3, 0x1234abcdull, st);
+  ST_TRY(check_launch("start block"));
+  lobpcg_status status = LOBPCG_NOT_CONVERGED;
+  int iters = 0, nconv = 0;
+  std::vector<double> resid(k, 0.0);
+  auto emit = [&](const double* Xr) -> lobpcg_status {
+    launch_gather_rows(Xr, m3, C.d_iperm, 0, evecs_out, k, n, k, st);
+    HIP_TRY(hipMemcpyAsync(evals_out, C.evals, k * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return LOBPCG_OK;
+  };
+  for (int it = 1; it <= maxit; ++it) {
+    double* X = C.Sb[cur];
+    double* AX = C.ASb[cur];
+    double* Xr = C.Sb[1 - cur];
+    double* AXr = C.ASb[1 - cur];
+    // line 3: X = Q of X~ (Algorithm 2)
+    ST_TRY(ortho(c, X, m3, m));
+    // line 4: Theta = X^T A X, diagonalised (Theta = C D C^T; X <- X C, A X <- A X C)
+    apply_a(c, X, m3, AX, m3, m);
+    launch_sgram(C.SG, X, m3, AX, m3, m, m, C.H, (int64_t)m3 * m3, C.gpart, st);
+    launch_syev(C.H, m, (int64_t)m3 * m3, m, m, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info,
+                C.d_active, 1, st);
+    launch_supdate(C.SG, X, m3, C.Cev, m, (int64_t)m3 * m3, Xr, m3, m, m, 1.0, 0.0, st);
+    launch_supdate(C.SG, AX, m3, C.Cev, m, (int64_t)m3 * m3, AXr, m3, m, m, 1.0, 0.0, st);
+    // line 5: R = A X - X Theta, lower(R) into the solve buffer, column norms
+    if (C.prec == LOBPCG_FP32)
+      launch_sresidual<float>(C.SG, AXr, m3, Xr, m3, C.evals, m3, m, static_cast<float*>(C.rhs), C.mp, C.norms,
+                              C.gpart, st);
+    else
+      launch_sresidual<double>(C.SG, AXr, m3, Xr, m3, C.evals, m3, m, static_cast<double*>(C.rhs), C.mp, C.norms,
+                               C.gpart, st);
+    ST_TRY(check_launch("PINVIT Rayleigh quotient and residual"));
+    HIP_TRY(hipMemcpyAsync(C.h_rb, C.norms, C.rb_bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double* hn = static_cast<const double*>(C.h_rb);
+    const double* th = hn + 2 * m;
+    const int32_t* qf = reinterpret_cast<const int32_t*>(th + m3);
+    iters = it;
+    C.fallbacks += qf[0];
+    if (qf[1]) {
+      status = LOBPCG_ERR_ORTHO_BREAKDOWN;
+      break;
+    }
+    if (theta_hist)
+      for (int j = 0; j < k; ++j) theta_hist[(int64_t)(it - 1) * k + j] = th[j];
+    // lines 6-8: the test of Algorithm 3 (eq. (stop)) on the leading columns
+    bool finite = true;
+    std::vector<double> res(m);
+    for (int j = 0; j < m; ++j) {
+      const double rn = std::sqrt(hn[j]), xn = std::sqrt(hn[m + j]);
+      if (!std::isfinite(rn) || !std::isfinite(xn) || !std::isfinite(th[j])) finite = false;
+      const double denom = (C.opt.stop_rule == LOBPCG_STOP_PAPER) ? (C.norm_a[0] + std::fabs(th[j])) * xn
+                                                                   : C.norm_a[0] * xn;
+      res[j] = rn / denom;
+    }
+    for (int j = 0; j < k; ++j) resid[j] = res[j];
+    if (!finite) {
+      status = LOBPCG_ERR_NONFINITE;
+      break;
+    }
+    int nc = 0;
+    for (int j = 0; j < m; ++j) {
+      bool ok = res[j] <= C.tol;
+      if (ok && C.opt.eig_tol > 0) {
+        const double gap = std::max(th[m - 1] - th[j], 0.0);
+        ok = hn[j] <= C.opt.eig_tol * std::fabs(th[j]) * gap;
+      }
+      if (!ok) break;
+      nc++;
+    }
+    nconv = nc;
+    if (nc >= k) {
+      status = LOBPCG_OK;
+      ST_TRY(emit(Xr));
+      break;
+    }
+    if (it == maxit) {
+      ST_TRY(emit(Xr));
+      break;
+    }
+    // lines 9-10: W = working(f_T(lower(R))) into columns m .. 2m - 1 of Xr
+    precond(c, Xr + m, m3);
+    ST_TRY(check_launch("PINVIT preconditioner"));
+    // line 11: X~ = X - W
+    launch_sub_block(Xr + m, m3, Xr, m3, n, m, st);
+    cur = 1 - cur;
+  }
+  ST_TRY(check_launch("PINVIT output"));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (info) {
+    info->iters = iters;
+    info->n_conv = nconv;
+    info->fallbacks = C.fallbacks;
+    info->nlevels = C.S.nlevels;
+    info->norm_a = C.norm_a[0];
+    info->t_symbolic = C.t_symbolic;
+    info->t_factor = C.t_factor;
+    info->t_solve = now_s() - t_start;
+    info->nnz_factor = C.S.nnz_lower;
+    info->factor_flops = C.S.flops;
+    if (info->resid)
+      for (int j = 0; j < k; ++j) info->resid[j] = resid[j];
+    info->t_precond_gpu = 0;
+    info->t_spmm_gpu = 0;
+    info->n_precond = 0;
+    info->n_spmm = 0;
+  }
+  if (status == LOBPCG_ERR_NONFINITE) return fail(status, "non-finite residual or Ritz value");
+  if (status == LOBPCG_ERR_ORTHO_BREAKDOWN)
+    return fail(status, "Algorithm 2 Cholesky of V^T V failed (X~ rank deficient) after the FP64 retry");
+  return status;
+}
+
 // One-instance segmentation on the fly for the standalone entry points.
 struct TempSeg {
   std::vector<void*> mem;
@@ -1259,6 +1391,16 @@ lobpcg_status lobpcg_solve(lobpcg_ctx c, const double* X0, int32_t maxit, double
   double* ev[1] = {evals};
   double* ec[1] = {evecs};
   return solve_core(c, x0, maxit, ev, ec, info);
+}
+
+lobpcg_status lobpcg_pinvit(lobpcg_ctx c, const double* X0, int32_t maxit, double* evals, double* evecs,
+                            lobpcg_info* info, double* theta_hist) {
+  if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->B != 1) return fail(LOBPCG_ERR_INVALID_ARG, "PINVIT supports single-problem contexts");
+  if (maxit < 1) return fail(LOBPCG_ERR_INVALID_ARG, "maxit must be >= 1");
+  if (!evals || !evecs) return fail(LOBPCG_ERR_INVALID_ARG, "output pointer is NULL");
+  g_last_error.clear();
+  return pinvit_core(c, X0, maxit, evals, evecs, info, theta_hist);
 }
 
 lobpcg_status lobpcg_solve_batched(lobpcg_ctx c, const double* const* X0, int32_t maxit, double* const* evals,

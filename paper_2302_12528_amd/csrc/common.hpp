@@ -72,6 +72,8 @@ void launch_add_diag_shift(const int32_t* rowptr, const int32_t* colind, double*
 // Deterministic N(0,1) fill (counter-based splitmix64 + Box-Muller).
 void launch_gaussian_fill(double* X, int64_t n, int c, int64_t ld, uint64_t seed, hipStream_t st);
 void launch_copy_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int c, hipStream_t st);
+// dst[i*ldd + j] -= src[i*lds + j], i < n, j < c
+void launch_sub_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int c, hipStream_t st);
 void launch_fill_int(int32_t* p, int32_t v, int64_t count, hipStream_t st);
 
 // ---- small dense kernels (k_small.hip), one workgroup per instance ----

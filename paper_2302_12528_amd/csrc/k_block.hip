@@ -196,6 +196,15 @@ __global__ void copy_block_kernel(const double* __restrict__ src, int64_t lds, d
   dst[i * ldd + j] = src[i * lds + j];
 }
 
+__global__ void sub_block_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                                 int64_t ldd, int64_t n, int c) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * c) return;
+  const int64_t i = e / c;
+  const int j = (int)(e % c);
+  dst[i * ldd + j] -= src[i * lds + j];
+}
+
 inline dim3 grid1(int64_t total) { return dim3((unsigned)((total + kThreads - 1) / kThreads)); }
 
 }  // namespace
@@ -272,6 +281,11 @@ void launch_gaussian_fill(double* X, int64_t n, int c, int64_t ld, uint64_t seed
 void launch_copy_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int c, hipStream_t st) {
   if (n * c <= 0) return;
   copy_block_kernel<<<grid1(n * c), kThreads, 0, st>>>(src, lds, dst, ldd, n, c);
+}
+
+void launch_sub_block(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n, int c, hipStream_t st) {
+  if (n * c <= 0) return;
+  sub_block_kernel<<<grid1(n * c), kThreads, 0, st>>>(src, lds, dst, ldd, n, c);
 }
 
 }  // namespace lobpcg

@@ -61,6 +61,8 @@ SIGNATURES = {
     "lobpcg_solve_batched": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                         ct.POINTER(Info)]),
     "lobpcg_batch_count": (ct.c_int32, [ct.c_void_p]),
+    "lobpcg_pinvit": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.POINTER(Info),
+                                 ct.c_void_p]),
     "lobpcg_backward": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "lobpcg_destroy": (ct.c_int, [ct.c_void_p]),
     "lobpcg_status_string": (ct.c_char_p, [ct.c_int]),

@@ -140,6 +140,28 @@ class Solver:
         out["status"] = st
         return evals, evecs, out
 
+    def pinvit(self, X0=None, maxit: int = 1000, allow_not_converged: bool = False, history: bool = False):
+        """Algorithm 1 (mixed-precision block PINVIT) with this context's factor; returns evals, evecs, info
+        (info["theta_hist"]: the k smallest Ritz values of each iteration when history is set)."""
+        torch = _torch()
+        x0 = _dev_f64(X0, (self.n, self.m)) if X0 is not None else None
+        evals = torch.empty(self.k, dtype=torch.float64, device="cuda")
+        evecs = torch.empty((self.n, self.k), dtype=torch.float64, device="cuda")
+        info = nv.Info()
+        res = np.zeros(self.k, dtype=np.float64)
+        info.resid = res.ctypes.data
+        hist = np.full((maxit, self.k), np.nan) if history else None
+        allow = (nv.LOBPCG_OK, nv.LOBPCG_NOT_CONVERGED) if allow_not_converged else (nv.LOBPCG_OK,)
+        st = self.lib.lobpcg_pinvit(self.ctx, _ptr(x0), maxit, _ptr(evals), _ptr(evecs), ct.byref(info),
+                                    hist.ctypes.data if hist is not None else None)
+        nv.check(st, allow)
+        out = {f: getattr(info, f) for f, _ in nv.Info._fields_ if f != "resid"}
+        out["resid"] = res.copy()
+        out["status"] = st
+        if hist is not None:
+            out["theta_hist"] = hist[: out["iters"]].copy()
+        return evals, evecs, out
+
     def factor(self):
         nv.check(self.lib.lobpcg_factor(self.ctx))
 

@@ -104,6 +104,7 @@ def test_batched_setup_rejects_bad_arguments(lib):
 
 def test_solve_and_backward_reject_null_context(lib):
     assert lib.lobpcg_solve(None, None, 10, None, None, None) == nv.LOBPCG_ERR_INVALID_ARG
+    assert lib.lobpcg_pinvit(None, None, 10, None, None, None, None) == nv.LOBPCG_ERR_INVALID_ARG
     assert lib.lobpcg_backward(None, None, None, None) == nv.LOBPCG_ERR_INVALID_ARG
     assert lib.lobpcg_destroy(None) == nv.LOBPCG_OK
 
