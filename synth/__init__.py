@@ -72,6 +72,29 @@ def laplace2d(s: int) -> sp.csr_matrix:
     return _csr_sorted(A)
 
 
+def laplace2d_rect(p: int, q: int) -> sp.csr_matrix:
+    """5-point Dirichlet Laplacian on a p x q interior grid (index i q + j), diagonal 4, off-diagonal -1."""
+    n = p * q
+    idx = np.arange(n).reshape(p, q)
+    rows, cols, vals = [idx.ravel()], [idx.ravel()], [np.full(n, 4.0)]
+    for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        i0, i1 = max(0, -di), p - max(0, di)
+        j0, j1 = max(0, -dj), q - max(0, dj)
+        a = idx[i0:i1, j0:j1].ravel()
+        b = idx[i0 + di:i1 + di, j0 + dj:j1 + dj].ravel()
+        rows.append(a); cols.append(b); vals.append(np.full(a.size, -1.0))
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    return _csr_sorted(A)
+
+
+def laplace2d_rect_eigs(p: int, q: int) -> np.ndarray:
+    """All eigenvalues of laplace2d_rect(p, q), ascending: 4 - 2 cos(a pi/(p+1)) - 2 cos(b pi/(q+1))."""
+    a = np.arange(1, p + 1)[:, None]
+    b = np.arange(1, q + 1)[None, :]
+    lam = 4.0 - 2.0 * np.cos(a * np.pi / (p + 1)) - 2.0 * np.cos(b * np.pi / (q + 1))
+    return np.sort(lam.ravel())
+
+
 def diffusion3d(a: np.ndarray) -> sp.csr_matrix:
     """Cell-centred 7-point diffusion on an N^3 grid with cell coefficients a (N,N,N).
 
@@ -226,6 +249,17 @@ def cfg5(N: int = 48, k: int = 8, m: int = 16) -> Problem:
     L0 = laplace_scaled((N, N, N))
     return Problem(f"schrodinger3d_{N}", A, X0, k, m, 1e-10, "fp32", (N, N, N),
                    extra={"centers": c, "widths": w, "amps": a0, "g": g, "phi": phi, "L0": L0})
+
+
+def paper2d(x0_seed: int = 106) -> Problem:
+    """The 2D-Laplace matrix of the paper's sparse tests, reconstructed from its size: n = 25,000 and
+    nnz = 114,990 are those of a 5 x 5000 Dirichlet 5-point grid (5pq - 2(p + q) with pq = 25,000);
+    k = 30, m = 45, tol = 1e-12 under the paper's stopping rule.  The start block is a seeded N(0,1)
+    block (the paper's is not given)."""
+    A = laplace2d_rect(5, 5000)
+    X0 = np.random.default_rng(x0_seed).standard_normal((25000, 45))
+    return Problem("laplace2d_5x5000", A, X0, 30, 45, 1e-12, "fp32", (0, 0, 0),
+                   extra={"eigs": laplace2d_rect_eigs(5, 5000)})
 
 
 def random_block(n: int, m: int, seed: int) -> np.ndarray:

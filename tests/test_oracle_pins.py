@@ -215,6 +215,15 @@ def test_table3_laplace_shape():
     p, q = 5, 5000
     nnz = 5 * p * q - 2 * (p + q)
     assert p * q == 25000 and nnz == 114990
+    A = synth.paper2d().A
+    assert A.shape == (25000, 25000) and A.nnz == 114990
+
+
+def test_rect_laplace_closed_form():
+    # the separable spectrum of the p x q grid against a dense symmetric eigensolver
+    A = synth.laplace2d_rect(5, 60).toarray()
+    np.testing.assert_allclose(np.linalg.eigvalsh(A), synth.laplace2d_rect_eigs(5, 60), rtol=0, atol=1e-12)
+    assert np.allclose(A, A.T) and np.all(np.diag(A) == 4.0)
 
 
 # ---------------------------------------------------------------------------
