@@ -192,6 +192,9 @@ struct lobpcg_ctx_s {
   int bw_iters = 0;
   // events around the preconditioner and A W of one iteration (timed solves)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // factorization: side stream for the inverse phase of each level, and its ordering events
+  hipStream_t fst = nullptr;
+  std::vector<hipEvent_t> fev;
   // graph mode: private stream, ordering event, one executable graph per buffer parity
   hipStream_t gst = nullptr;
   hipEvent_t ev_order = nullptr;
@@ -227,6 +230,9 @@ struct lobpcg_ctx_s {
       if (g) (void)hipGraphExecDestroy(g);
     if (ev_order) (void)hipEventDestroy(ev_order);
     if (gst) (void)hipStreamDestroy(gst);
+    for (hipEvent_t e : fev)
+      if (e) (void)hipEventDestroy(e);
+    if (fst) (void)hipStreamDestroy(fst);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
@@ -378,11 +384,56 @@ lobpcg_status factor_t(lobpcg_ctx c) {
   T* upd = static_cast<T*>(c->upd);
   T* dinv = static_cast<T*>(c->dinv);
   T* lcopy = static_cast<T*>(c->lcopy);
-  for (const FactorPlan::Step& s : c->FP.steps) {
+  const std::vector<FactorPlan::Step>& steps = c->FP.steps;
+  size_t groups = 0;   // runs of steps of one level
+  for (size_t q = 0; q < steps.size(); ++q)
+    if (q == 0 || steps[q].level != steps[q - 1].level) ++groups;
+  if (!c->fst) HIP_TRY(hipStreamCreateWithFlags(&c->fst, hipStreamNonBlocking));
+  while (c->fev.size() < 2 * groups + 2) {
+    hipEvent_t ev = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    c->fev.push_back(ev);
+  }
+  hipStream_t ms = c->st, ss = c->fst;
+  auto launch = [&](const FactorPlan::Step& s, hipStream_t st) {
     const int64_t a0 = c->FP.asm_level_off[s.level], a1 = c->FP.asm_level_off[s.level + 1];
     launch_factor_step<T>(c->FD, s.kind, c->FP.level_max_nr[s.level], s.off, s.count, a0, a1 - a0, panel, upd, dinv,
-                          lcopy, c->d_flag, c->st);
+                          lcopy, c->d_flag, st);
+  };
+  auto is_inv = [](int k) { return k == kInvPrep || k == kInvT1 || k == kInvX21 || k == kInvP21; };
+  // Per level, the main stream runs the assembly, the panel steps and then the Schur complement;
+  // the inverse phase (P_s = [inv(L11); L21 inv(L11)]) runs on the side stream once the panel steps
+  // are done, concurrently with the Schur complement and the levels above: it reads the panel and
+  // the diagonal-tile inverses, writes inv(L11) over the panel's own rows (which the Schur
+  // complement does not read) and the level scratch lcopy (reused level after level, so the side
+  // stream keeps the levels in order), and only L21 inv(L11) overwrites rows that the Schur
+  // complement reads, so that step waits for it.
+  int e = 0;
+  HIP_TRY(hipEventRecord(c->fev[e], ms));
+  HIP_TRY(hipStreamWaitEvent(ss, c->fev[e++], 0));
+  size_t i = 0;
+  while (i < steps.size()) {
+    const int l = steps[i].level;
+    size_t j = i;
+    while (j < steps.size() && steps[j].level == l) ++j;
+    for (size_t q = i; q < j; ++q)
+      if (!is_inv(steps[q].kind) && steps[q].kind != kSchur) launch(steps[q], ms);
+    hipEvent_t panels_done = c->fev[e++];
+    HIP_TRY(hipEventRecord(panels_done, ms));
+    for (size_t q = i; q < j; ++q)
+      if (steps[q].kind == kSchur) launch(steps[q], ms);
+    hipEvent_t schur_done = c->fev[e++];
+    HIP_TRY(hipEventRecord(schur_done, ms));
+    HIP_TRY(hipStreamWaitEvent(ss, panels_done, 0));
+    for (size_t q = i; q < j; ++q)
+      if (is_inv(steps[q].kind) && steps[q].kind != kInvP21) launch(steps[q], ss);
+    HIP_TRY(hipStreamWaitEvent(ss, schur_done, 0));
+    for (size_t q = i; q < j; ++q)
+      if (steps[q].kind == kInvP21) launch(steps[q], ss);
+    i = j;
   }
+  HIP_TRY(hipEventRecord(c->fev[e], ss));
+  HIP_TRY(hipStreamWaitEvent(ms, c->fev[e], 0));
   return check_launch("factorization");
 }
 
