@@ -391,6 +391,19 @@ __global__ void __launch_bounds__(256) update_kernel(FactorDev D, int64_t task_o
   const int K = wP;
   const T* Ap = front_ptr(panel, upd, S, rI, rP, lda);
   const T* Bp = front_ptr(panel, upd, S, rJ, rP, ldb);
+  // this thread's 16 entries of C are requested first, so that their latency overlaps the panel loads
+  const int lane = tid % 64, w = tid / 64;
+  const int qr = (w / 2) * 32, qc = (w % 2) * 32;
+  T cv[2][2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = qr + 16 * a + lane % 16, c = qc + 16 * b + Mfma<T>::drow(lane, q);
+        cv[b][a][q] = (r < hI && c < hJ) ? C[r + (int64_t)c * ldc] : (T)0;
+      }
   load_cm_vec(As, Ap, lda, hI, K);
   load_cm_vec(Bs, Bp, ldb, hJ, K);
   __syncthreads();
@@ -402,8 +415,6 @@ __global__ void __launch_bounds__(256) update_kernel(FactorDev D, int64_t task_o
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[b][a][q] = 0;
   tile_mfma<T>(As, Bs, (K + 3) & ~3, acc);
-  const int lane = tid % 64, w = tid / 64;
-  const int qr = (w / 2) * 32, qc = (w % 2) * 32;
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -413,7 +424,7 @@ __global__ void __launch_bounds__(256) update_kernel(FactorDev D, int64_t task_o
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = qc + 16 * b + Mfma<T>::drow(lane, q);
-        if (c < hJ) C[r + (int64_t)c * ldc] -= acc[b][a][q];
+        if (c < hJ) C[r + (int64_t)c * ldc] = cv[b][a][q] - acc[b][a][q];
       }
     }
 }
