@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched run (0 = skip)")
     ap.add_argument("--pinvit-maxit", type=int, default=400, help="iteration cap of the PINVIT run (0 = skip)")
+    ap.add_argument("--autotune", action="store_true", help="time the solve-plan split and reduction chunk at setup")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first copy a 256 MiB buffer once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -189,7 +190,7 @@ def main():
     X0 = torch.from_numpy(np.ascontiguousarray(p.X0)).cuda()
     log(f"setup mixed (fp32 factor), n={p.n}")
     t0 = time.perf_counter()
-    mixed = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp32", grid=p.grid)
+    mixed = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp32", grid=p.grid, autotune=args.autotune)
     t_setup = time.perf_counter() - t0
     dt, infos, lam, X = time_steps(torch, mixed, X0, args.steps, args.warmup, "mixed")
     info = infos[-1]
@@ -244,7 +245,8 @@ def main():
     fp64 = None
     if not args.no_fp64:
         log("setup fp64 factor")
-        s64 = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp64", grid=p.grid, qr_lower=False)
+        s64 = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp64", grid=p.grid, qr_lower=False,
+                        autotune=args.autotune)
         dt64, infos64, lam64, _ = time_steps(torch, s64, X0, max(1, min(args.steps, 2)), 1, "fp64")
         n64 = sum(i["n_precond"] for i in infos64)
         ms_pc64 = 1e3 * sum(i["t_precond_gpu"] for i in infos64) / max(1, n64)
