@@ -64,14 +64,15 @@ __device__ inline T* front_ptr(T* panel, T* upd, const Sn& S, int r, int c, int6
 }
 
 // ---------------------------------------------------------------------------
-// Assembly, one wave per front column t of supernode s: the column is built in
-// LDS (zero, the entries of A, then each child's Schur-complement column
-// scattered through the child's relative row map; children are added one after
-// another, so every target element has one writer at a time), then written out
-// once.  Every child entry is read exactly once over the whole level.
+// Assembly, one workgroup of NT threads per front column t of supernode s: the
+// column is built in LDS (zero, the entries of A, then each child's
+// Schur-complement column scattered through the child's relative row map;
+// children are added one after another, so every target element has one writer
+// at a time), then written out once.  Every child entry is read exactly once over
+// the whole level.  Levels of tall fronts take NT = 256, the others NT = 64.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(64) assemble_kernel(FactorDev D, int64_t item_off, int64_t count, T* panel,
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) assemble_kernel(FactorDev D, int64_t item_off, int64_t count, T* panel,
                                                       T* upd) {
   extern __shared__ unsigned char asm_smem[];
   T* colbuf = reinterpret_cast<T*>(asm_smem);
@@ -85,15 +86,15 @@ __global__ void __launch_bounds__(64) assemble_kernel(FactorDev D, int64_t item_
   int64_t ld;
   T* col = front_ptr(panel, upd, S, rlo, t, ld);   // col[r - rlo] is front element (r, t)
   if (D.is_dense) {
-    for (int r = rlo + lane; r < S.nr; r += 64)
+    for (int r = rlo + lane; r < S.nr; r += NT)
       col[r - rlo] = (r >= t) ? (T)D.dense[(int64_t)r * D.ld_dense + t] : (T)0;
     return;
   }
-  for (int r = rlo + lane; r < S.nr; r += 64) colbuf[r] = (T)0;
+  for (int r = rlo + lane; r < S.nr; r += NT) colbuf[r] = (T)0;
   __syncthreads();
   if (t < S.nc) {
     const int j = S.begin + t;
-    for (int e = D.prow[j] + lane; e < D.prow[j + 1]; e += 64) {
+    for (int e = D.prow[j] + lane; e < D.prow[j + 1]; e += NT) {
       const int pos = D.apos[e];
       if (pos >= 0) colbuf[pos] += (T)D.aval[e];
     }
@@ -106,10 +107,10 @@ __global__ void __launch_bounds__(64) assemble_kernel(FactorDev D, int64_t item_
     const int nbc = D.nr[c] - D.nc[c];
     const T* uc = upd + D.upd_off[c] + (int64_t)jt * nbc;
     const int32_t* rel = D.relpos + D.row_off[c] + D.nc[c];
-    for (int ic = jt + lane; ic < nbc; ic += 64) colbuf[rel[ic]] += uc[ic];
+    for (int ic = jt + lane; ic < nbc; ic += NT) colbuf[rel[ic]] += uc[ic];
     __syncthreads();
   }
-  for (int r = rlo + lane; r < S.nr; r += 64) col[r - rlo] = colbuf[r];
+  for (int r = rlo + lane; r < S.nr; r += NT) col[r - rlo] = colbuf[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -616,10 +617,17 @@ void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t 
     case kAssemble:
       if (asm_count > 0) {
         const size_t lds = D.is_dense ? 0 : (size_t)level_max_nr * sizeof(T);
-        if (lds > 65536)
-          (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&assemble_kernel<T>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        assemble_kernel<T><<<(unsigned)asm_count, 64, lds, st>>>(D, asm_off, asm_count, panel, upd);
+        if (level_max_nr >= 1024) {
+          if (lds > 65536)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&assemble_kernel<T, 256>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          assemble_kernel<T, 256><<<(unsigned)asm_count, 256, lds, st>>>(D, asm_off, asm_count, panel, upd);
+        } else {
+          if (lds > 65536)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&assemble_kernel<T, 64>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          assemble_kernel<T, 64><<<(unsigned)asm_count, 64, lds, st>>>(D, asm_off, asm_count, panel, upd);
+        }
       }
       break;
     case kPotrf:
