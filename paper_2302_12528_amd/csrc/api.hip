@@ -50,9 +50,6 @@ double now_s() {
 
 int pad_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64; }
 
-// Tile items aimed at per level of the triangular-solve plan: levels with fewer output tiles split
-// their reduction ranges until they have about this many.
-constexpr int kSplitTarget = 1024;
 constexpr int64_t kMaxBufferBytes = ((int64_t)1 << 31) - 64;   // buffer-resource extent limit of the solve kernels
 
 // Host side of an instance segmentation.
@@ -200,7 +197,7 @@ struct lobpcg_ctx_s {
   hipEvent_t ev_order = nullptr;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // tuning: split target of the triangular-solve plan, rows per reduction chunk, how they were chosen
-  int split_target = kSplitTarget;   // tile items per level the solve plan aims at
+  int split_target = default_split_target(4);   // tile items per level the solve plan aims at
   int64_t chunk_rows = 0;
   int tuned = 0;   // 0 defaults, 1 measured at setup, 2 read from the cache file
   int64_t gpart_bytes = 0, fpart_bytes = 0, bpart_bytes = 0;
@@ -614,7 +611,8 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
     return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
   }
   build_factor_plan(C.S, C.FP);
-  build_solve_plan(C.S, 64, kSplitTarget, C.SP);
+  C.split_target = default_split_target(factor_precision == LOBPCG_FP32 ? 4 : 8);
+  build_solve_plan(C.S, 64, C.split_target, C.SP);
   std::vector<int32_t> prow, pcol, vmap, apos;
   if (!C.dense) {
     permute_pattern(C.S, rowptr, colind, prow, pcol, vmap);
@@ -1604,7 +1602,7 @@ lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t
     FactorPlan F;
     SolvePlan P;
     build_factor_plan(S, F);
-    build_solve_plan(S, 64, kSplitTarget, P);
+    build_solve_plan(S, 64, default_split_target(4), P);
     std::vector<int32_t> prow, pcol, vmap, apos;
     if (!dense) {
       permute_pattern(S, A->rowptr, A->colind, prow, pcol, vmap);

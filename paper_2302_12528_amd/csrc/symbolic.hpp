@@ -16,6 +16,10 @@ namespace lobpcg {
 constexpr int kTile = 64;   // tile edge of the factor kernels
 constexpr int kSolveItemInts = 12;   // ints per triangular-solve item
 constexpr int kSolveWideK = 256;     // items with longer reduction ranges use four waves
+// Tile items aimed at per level of the triangular-solve plan by default: levels with fewer output tiles
+// split their reduction ranges until they have about this many (the autotuner may choose another).
+// Items of an FP64 factor stream twice the bytes, so they are split further.
+constexpr int default_split_target(int elem_bytes) { return elem_bytes == 4 ? 256 : 1024; }
 // Leading dimension of a supernode panel with nr rows: nr rounded up to a multiple of 4, so that
 // every panel column starts 16-byte aligned (FP32) and 4-row groups can be read as one vector.
 constexpr int64_t panel_ld(int64_t nr) { return (nr + 3) & ~(int64_t)3; }
