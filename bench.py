@@ -170,8 +170,7 @@ def main():
                     help="first copy a 256 MiB buffer once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how it would "
-              "shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
