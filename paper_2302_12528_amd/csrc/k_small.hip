@@ -89,10 +89,11 @@ __device__ inline double rcp_nr(double q) {
 // Number of eigenvalues of T below x, from T scaled by a power of two to norm about one (diagonal
 // ds, squared off-diagonal e2s, shift xs).  The leading principal minors
 // p_i = (ds_i - xs) p_{i-1} - e2s_{i-1} p_{i-2} (p_{-1} = 1) are the products of the LDL^T pivots
-// q_i = p_i / p_{i-1}, so a sign change from p_{i-1} to p_i is a negative pivot; a pivot below pmin
-// in magnitude is replaced by -pmin (p_i = -pmin p_{i-1}).  The only dependent operation per step is
-// one FMA and the pivot test (e2s_{i-1} p_{i-2} is ready a step earlier, and no reciprocal is
-// needed); p_{i-1} and p_i are rescaled by a power of two every four steps.  The arrays are padded
+// q_i = p_i / p_{i-1}, so a sign change from p_{i-1} to p_i is a negative pivot.  Without a division a
+// tiny pivot needs no guard; a zero one (p_i = 0, which would stall the recurrence where e_i = 0) is
+// replaced by -pmin (p_i = -pmin p_{i-1}), as LAPACK replaces pivots below pivmin.  The only dependent
+// operations per step are one FMA and the zero test (e2s_{i-1} p_{i-2} is ready a step earlier);
+// p_{i-1} and p_i are rescaled by a power of two every four steps.  The arrays are padded
 // to c + 8 entries with ds = 8 and e2s = 0 (|xs| < 4): steps past the end change no sign, so the
 // four-step groups need no exit test and the next group's loads overlap the current one.
 __device__ inline int sturm_count_scaled(const double* ds, const double* e2s, int c, double xs, double pmin) {
@@ -115,7 +116,7 @@ __device__ inline int sturm_count_scaled(const double* ds, const double* e2s, in
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       double p = fma(dd[u] - xs, pm1, -ee[u] * pm2);
-      if (fabs(p) < pmin * fabs(pm1)) p = -pmin * pm1;
+      if (p == 0.0) p = -pmin * pm1;
       cnt += ((p < 0.0) != (pm1 < 0.0));
       pm2 = pm1;
       pm1 = p;

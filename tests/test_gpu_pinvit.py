@@ -96,3 +96,21 @@ def test_pinvit_matches_lobpcg_diffusion(torch_cuda):
     assert np.max(np.abs(lam_p - lam_l) / lam_l) <= 1e-10
     assert residuals(p.A, X_p, lam_p, na).max() <= p.tol
     print(f"pinvit {info_p['iters']} iterations, lobpcg {info_l['iters']}", flush=True)
+
+
+def test_pinvit_not_converged_returns_pairs(torch_cuda):
+    """maxit reached: NOT_CONVERGED, and the current Ritz pairs are still written (finite, orthonormal,
+    Ritz values at or above the exact eigenvalues)."""
+    import paper_2302_12528_amd as pk
+    print("pinvit maxit=3 laplace2d_32", flush=True)
+    p = synth.cfg1()
+    s = pk.Solver(p.A, p.k, p.m, 1e-14, factor_precision="fp32", grid=p.grid)
+    ev, X, info = s.pinvit(p.X0, maxit=3, allow_not_converged=True)
+    s.close()
+    ev, X = ev.cpu().numpy(), X.cpu().numpy()
+    import paper_2302_12528_amd.native as nv
+    assert info["status"] == nv.LOBPCG_NOT_CONVERGED and info["iters"] == 3
+    assert np.all(np.isfinite(ev)) and np.all(np.isfinite(X))
+    assert np.max(np.abs(X.T @ X - np.eye(p.k))) <= 1e-12
+    lam = np.sort(np.linalg.eigvalsh(p.A.toarray()))[: p.k]
+    assert np.all(ev >= lam * (1 - 1e-12))
