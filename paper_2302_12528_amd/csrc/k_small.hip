@@ -76,6 +76,13 @@ constexpr int kSyevThreads = 256;
 constexpr int kSyevWaves = kSyevThreads / 64;
 constexpr int kSyevLds = 96;
 constexpr int kSyevMax = 192;
+// from this many eigenvalues on, the register eigensolver bisects them in a launch of its own with
+// one workgroup per eigenvalue (fewer rounds than splitting one workgroup's points among them), as
+// long as that launch stays within kSyevSplitMaxBlocks workgroups; a larger batch already fills the
+// chip with one workgroup per problem (c = 96, nev = 32: 353 -> 286 us for one problem; c = 48,
+// nev = 16: 177 -> 248 us for 256 problems)
+constexpr int kSyevSplitMinNev = 8;
+constexpr int kSyevSplitMaxBlocks = 1024;
 
 // 1/q from the hardware reciprocal refined by two Newton steps (about one ulp), a shorter
 // dependency chain than the IEEE division sequence.
@@ -188,7 +195,7 @@ __device__ __attribute__((always_inline)) void cluster_mgs_cols(double (&z)[NB][
 // c + 8 doubles of LDS each, s2: c; cnt: one int per thread; lu: 5 c nev doubles of global scratch.
 // Returns the largest number of later members of a cluster (0 when every eigenvalue is isolated);
 // Z and lam are complete and visible to the whole workgroup on return.
-template <int NB>
+template <int NB, bool PRESET = false>
 __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, const double* e, int c, int nev, double* s1, double* s2,
                             double* s3, double* lam, int* cnt, short* cend, double* Z, int lz, double* lu) {
   const int tid = threadIdx.x, lane = tid % 64, wid = tid / 64;
@@ -215,6 +222,7 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   }
   const double eps = 2.220446049250313e-16;
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  if constexpr (!PRESET) {   // otherwise lam holds the eigenvalues already
   gl -= 2.0 * eps * tnorm * c + 2.0 * pivmin;
   gu += 2.0 * eps * tnorm * c + 2.0 * pivmin;
   // T scaled by sc = 2^-ilogb(||T||) for the Sturm counts (s3: scaled diagonal; both padded to
@@ -279,6 +287,7 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   }
   for (int j = tid; j < nev; j += kSyevThreads) lam[j] = 0.5 * (lo[j] + hi[j]);
   __syncthreads();
+  }
   // ---- 3. eigenvectors of T by inverse iteration ----
   const double ortol = 1e-3 * tnorm;
   if (tid == 0) {
@@ -726,7 +735,101 @@ __device__ __attribute__((always_inline)) void tridiag_rows(double (&A)[NB][NB],
 // its share of p^T v; after a second barrier every thread applies H -= v w^T + w v^T,
 // w = p - (t / 2) (p^T v) v, and Q -= t (Q v) v^T to its own entries.  Steps 2 and 3 are those of
 // the LDS form; step 4 is C = Q Z, one matrix-core product of Q and Z from LDS.
-template <int NB>
+// Global scratch of the three-launch form (doubles from the instance's start): the inverse-
+// iteration factors (5 c^2, when they do not fit in LDS), Q (c x c, row stride c + 1), the diagonal
+// and off-diagonal of T (e[c - 1] = 0) and the eigenvalues.
+struct SyevSplit {
+  int64_t q, d, e, lam;
+};
+__device__ __host__ inline SyevSplit syev_split_offsets(int c) {
+  const int64_t q = 5 * (int64_t)c * c, d = q + (int64_t)c * (c + 1);
+  return {q, d, d + c, d + 2 * c};
+}
+
+// Eigenvalue j = blockIdx.x of the tridiagonal T that syev_reg_kernel<NB, 1> left in the scratch,
+// by multisection on Sturm counts with kSyevThreads points per round (the Gershgorin interval,
+// tolerance and scaled counts are those of tridiag_eigs, so the bracket invariant
+// count(lo) <= j < count(hi) and the stopping rule are the same; only the number of points per
+// round differs).  The new bracket is the last point before the first point whose count exceeds j
+// and that point, found with wave ballots.
+__global__ void __launch_bounds__(kSyevThreads) syev_bisect_kernel(double* __restrict__ work, int64_t wstride, int c,
+                                                                   int nev, const int32_t* __restrict__ active) {
+  if (active && !active[blockIdx.y]) return;
+  work += (int64_t)blockIdx.y * wstride;
+  const int j = blockIdx.x;
+  if (j >= nev) return;
+  const SyevSplit sp = syev_split_offsets(c);
+  __shared__ double ds[kSyevMax + 8], e2[kSyevMax + 8];
+  __shared__ int wfirst[kSyevWaves], wva[kSyevWaves], wvb[kSyevWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const double* d = work + sp.d;
+  const double* e = work + sp.e;
+  double gl = 1e300, gu = -1e300, tnorm = 0.0, emax2 = 0.0;
+  for (int i = lane; i < c; i += 64) {
+    const double ei = (i < c - 1) ? fabs(e[i]) : 0.0;
+    const double em = (i > 0) ? fabs(e[i - 1]) : 0.0;
+    gl = fmin(gl, d[i] - ei - em);
+    gu = fmax(gu, d[i] + ei + em);
+    tnorm = fmax(tnorm, fabs(d[i]) + ei + em);
+    emax2 = fmax(emax2, ei * ei);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, off, 64));
+    gu = fmax(gu, __shfl_xor(gu, off, 64));
+    tnorm = fmax(tnorm, __shfl_xor(tnorm, off, 64));
+    emax2 = fmax(emax2, __shfl_xor(emax2, off, 64));
+  }
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  gl -= 2.0 * eps * tnorm * c + 2.0 * pivmin;
+  gu += 2.0 * eps * tnorm * c + 2.0 * pivmin;
+  const double sc = (tnorm > 0.0) ? ldexp(1.0, -ilogb(tnorm)) : 1.0;
+  const double pmin = fmax(sc * pivmin, 0x1p-100);
+  for (int i = tid; i < c + 8; i += kSyevThreads) {
+    const double es = (i < c - 1) ? sc * e[i] : 0.0;
+    e2[i] = es * es;
+    ds[i] = (i < c) ? sc * d[i] : 8.0;
+  }
+  __syncthreads();
+  double l = gl, h = gu;   // the same in every thread
+  constexpr double inv = 1.0 / (double)(kSyevThreads + 1);
+  for (int round = 0; round < 200; ++round) {
+    if (!(h - l > 2.0 * eps * fmax(fabs(l), fabs(h)) + pivmin)) break;
+    const double w = h - l;
+    const double x = l + w * ((double)(tid + 1) * inv);
+    // the points are nondecreasing in tid, so the valid ones (strictly inside) are a contiguous run
+    const bool valid = (x > l && x < h);
+    const bool above = valid && sturm_count_scaled(ds, e2, c, sc * x, pmin) >= j + 1;
+    const uint64_t ma = __ballot(above), mv = __ballot(valid);
+    if (lane == 0) {
+      wfirst[wid] = ma ? 64 * wid + __builtin_ctzll(ma) : kSyevThreads;
+      wva[wid] = mv ? 64 * wid + __builtin_ctzll(mv) : kSyevThreads;
+      wvb[wid] = mv ? 64 * wid + 64 - __builtin_clzll(mv) : -1;
+    }
+    __syncthreads();
+    int tc = kSyevThreads, va = kSyevThreads, vb = -1;
+#pragma unroll
+    for (int w2 = 0; w2 < kSyevWaves; ++w2) {
+      tc = min(tc, wfirst[w2]);
+      va = min(va, wva[w2]);
+      vb = max(vb, wvb[w2]);
+    }
+    __syncthreads();
+    auto point = [l, w](int t) { return l + w * ((double)(t + 1) * inv); };
+    const int end = (tc < kSyevThreads) ? tc : vb;   // one past the last point kept as the low end
+    const double nl = (end - 1 >= va) ? point(end - 1) : l;
+    double nh = (tc < kSyevThreads) ? point(tc) : h;
+    if (nl == l && nh == h) nh = nl;   // no interior point strictly inside: the bracket is at ulp level
+    l = nl;
+    h = nh;
+  }
+  if (tid == 0) work[sp.lam + j] = 0.5 * (l + h);
+}
+
+// MODE 0 does all four steps.  MODE 1 stops after step 1 and leaves T and Q in the global scratch
+// (layout of syev_split_offsets); the eigenvalues are then bisected by syev_bisect_kernel, one
+// workgroup per eigenvalue, and MODE 2 loads T, Q and the eigenvalues and does steps 3 and 4.
+template <int NB, int MODE>
 __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __restrict__ H, int64_t ldh,
                                                                 int64_t hstride, int c, int nev,
                                                                 double* __restrict__ evals, int64_t estride,
@@ -751,25 +854,51 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   __shared__ short cend[CM];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int ti = wid * 4 + (lane >> 4), tj = lane & 15;
-  double A[NB][NB], Q[NB][NB];
+  const SyevSplit sp = syev_split_offsets(c);
+  double Q[NB][NB];
+  if constexpr (MODE != 2) {
+    double A[NB][NB];
 #pragma unroll
-  for (int a = 0; a < NB; ++a)
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int i = ti + 16 * a, j = tj + 16 * b;
-      A[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
-      Q[a][b] = (i == j) ? 1.0 : 0.0;
+      for (int b = 0; b < NB; ++b) {
+        const int i = ti + 16 * a, j = tj + 16 * b;
+        A[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
+        Q[a][b] = (i == j) ? 1.0 : 0.0;
+      }
+    // ---- 1. tridiagonalization, accumulating Q ----
+    tridiag_rows<NB, 0>(A, Q, c, ti, tj, &vb[0][0], &pb[0][0], &pvp[0][0], tb, d, e);
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int i = ti + 16 * a, j = tj + 16 * b;
+        if (i == j && i + 2 >= c && i < c) d[i] = A[a][b];
+        if (c >= 2 && i == c - 1 && j == c - 2) e[c - 2] = A[a][b];
+      }
+    if constexpr (MODE == 1) {
+      double* gq = work + sp.q;
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int i = ti + 16 * a, j = tj + 16 * b;
+          if (i < c && j < c) gq[i * (c + 1) + j] = Q[a][b];
+        }
+      __syncthreads();
+      for (int i = tid; i < c; i += kSyevThreads) {
+        work[sp.d + i] = d[i];
+        work[sp.e + i] = (i < c - 1) ? e[i] : 0.0;
+      }
+      return;
     }
-  // ---- 1. tridiagonalization, accumulating Q ----
-  tridiag_rows<NB, 0>(A, Q, c, ti, tj, &vb[0][0], &pb[0][0], &pvp[0][0], tb, d, e);
-#pragma unroll
-  for (int a = 0; a < NB; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int i = ti + 16 * a, j = tj + 16 * b;
-      if (i == j && i + 2 >= c && i < c) d[i] = A[a][b];
-      if (c >= 2 && i == c - 1 && j == c - 2) e[c - 2] = A[a][b];
+  } else {
+    for (int i = tid; i < c; i += kSyevThreads) {
+      d[i] = work[sp.d + i];
+      e[i] = work[sp.e + i];
+      lam[i] = (i < nev) ? work[sp.lam + i] : 0.0;
     }
+  }
   const int lz = nev + 1;
   double* Z = pool;
   int64_t used = (int64_t)c * lz;
@@ -781,20 +910,24 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   } else {
     lu = work;
   }
-  if (used + (int64_t)c * (c + 1) <= POOL) sq = pool + used;
-  else sq = work + 5 * (int64_t)c * nev;
   const int lq = c + 1;
+  if constexpr (MODE == 2) {
+    sq = work + sp.q;   // as step 1 left it
+  } else {
+    if (used + (int64_t)c * (c + 1) <= POOL) sq = pool + used;
+    else sq = work + 5 * (int64_t)c * nev;
 #pragma unroll
-  for (int a = 0; a < NB; ++a)
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int i = ti + 16 * a, j = tj + 16 * b;
-      if (i < c && j < c) sq[i * lq + j] = Q[a][b];
-    }
-  if (tid == 0) e[c - 1] = 0.0;
+      for (int b = 0; b < NB; ++b) {
+        const int i = ti + 16 * a, j = tj + 16 * b;
+        if (i < c && j < c) sq[i * lq + j] = Q[a][b];
+      }
+    if (tid == 0) e[c - 1] = 0.0;
+  }
   __syncthreads();
   // ---- 2, 3. eigenvalues and eigenvectors of T ----
-  const int maxrank = tridiag_eigs<NB>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu);
+  const int maxrank = tridiag_eigs<NB, MODE == 2>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu);
   // ---- 4. C = Q Z (c x nev): 16 x 16 tiles, one wave per tile, 16x16x4 FP64 MFMAs ----
   typedef Mfma<double>::v4 v4;
   const int tn = (nev + 15) / 16, c4 = (c + 3) & ~3;
@@ -1176,17 +1309,35 @@ __global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __res
 
 int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c + 16; }
 
+namespace {
+template <int NB>
+void launch_syev_reg(const double* H, int64_t ldh, int64_t hstride, int c, int nev, double* evals, int64_t estride,
+                     double* C, int64_t cstride, double* work, int64_t ws, int* info, const int32_t* active, int B,
+                     hipStream_t st) {
+  if (nev < kSyevSplitMinNev || (int64_t)B * nev > kSyevSplitMaxBlocks) {
+    syev_reg_kernel<NB, 0><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws,
+                                                       info, active);
+    return;
+  }
+  syev_reg_kernel<NB, 1><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws,
+                                                     info, active);
+  syev_bisect_kernel<<<dim3(nev, B), kSyevThreads, 0, st>>>(work, ws, c, nev, active);
+  syev_reg_kernel<NB, 2><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws,
+                                                     info, active);
+}
+}  // namespace
+
 void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, int nev, double* evals, int64_t estride,
                  double* C, int64_t cstride, double* work, int* info, const int32_t* active, int B, hipStream_t st) {
   const int64_t ws = syev_scratch(c);
   if (c <= 16)
-    syev_reg_kernel<1><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+    launch_syev_reg<1>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
   else if (c <= 32)
-    syev_reg_kernel<2><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+    launch_syev_reg<2>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
   else if (c <= 48)
-    syev_reg_kernel<3><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+    launch_syev_reg<3>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
   else if (c <= 96)
-    syev_reg_kernel<6><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+    launch_syev_reg<6>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
   else
     syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
 }

@@ -70,6 +70,30 @@ def test_syev_small(torch_cuda, c):
     assert np.max(np.abs(H @ V - V * w)) <= 100 * c * U64 * hn
 
 
+@pytest.mark.parametrize("c", [24, 48, 96])
+def test_syev_clusters(torch_cuda, c):
+    # a six-fold eigenvalue, a pair 1e-12 apart and a zero eigenvalue: the bisection brackets reach
+    # ulp level and inverse iteration has to orthogonalise inside the clusters
+    import paper_2302_12528_amd as pk
+    print(f"syev clusters c={c}", flush=True)
+    rng = np.random.default_rng(100 + c)
+    Q, _ = np.linalg.qr(rng.standard_normal((c, c)))
+    lam = np.sort(rng.uniform(-2.0, 3.0, c))
+    lam[2:8] = 0.75
+    lam[10] = lam[11] + 1e-12
+    lam[12] = 0.0
+    lam = np.sort(lam)
+    H = (Q * lam) @ Q.T
+    H = 0.5 * (H + H.T)
+    w, V = pk.syev_small(H)
+    w, V = _np(w), _np(V)
+    hn = np.linalg.norm(H, 2)
+    assert np.max(np.abs(w - np.linalg.eigvalsh(H))) <= 50 * c * U64 * hn
+    assert np.all(np.diff(w) >= 0)
+    assert np.max(np.abs(V.T @ V - np.eye(c))) <= 100 * c * U64
+    assert np.max(np.abs(H @ V - V * w)) <= 100 * c * U64 * hn
+
+
 @pytest.mark.parametrize("kappa", [1.0, 1e3, 1e6])
 @pytest.mark.parametrize("lower", [True, False])
 @pytest.mark.parametrize("nc", [(20000, 32), (5000, 16), (1000, 64), (64, 64)])
