@@ -291,8 +291,12 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   // ---- 3. eigenvectors of T by inverse iteration ----
   const double ortol = 1e-3 * tnorm;
   if (tid == 0) {
-    cend[nev - 1] = (short)nev;
-    for (int j = nev - 2; j >= 0; --j) cend[j] = (lam[j + 1] - lam[j] < ortol) ? cend[j + 1] : (short)(j + 1);
+    short ce = (short)nev;
+    cend[nev - 1] = ce;
+    for (int j = nev - 2; j >= 0; --j) {
+      ce = (lam[j + 1] - lam[j] < ortol) ? ce : (short)(j + 1);
+      cend[j] = ce;
+    }
   }
   double* U0 = lu;
   double* U1 = lu + (int64_t)c * nev;
@@ -301,31 +305,35 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   double* Pv = lu + 4 * (int64_t)c * nev;
   const double tiny = eps * tnorm + pivmin;
   // the diagonal of U with entries below tiny replaced by +-tiny (the elimination itself keeps the
-  // unreplaced pivots)
+  // unreplaced pivots); U0 holds the reciprocals of that diagonal
   auto clamp_tiny = [tiny](double u) { return (fabs(u) < tiny) ? ((u < 0.0) ? -tiny : tiny) : u; };
   for (int j = tid; j < nev; j += kSyevThreads) {
     const double lj = lam[j];
     double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0;
     for (int k = 0; k + 1 < c; ++k) {
+      // partial pivoting between the current row (cd, cs, 0) and the next (sub, nd, ns), written
+      // with selects so that the lanes of a wave share one division
       const double sub = e[k];
       const double nd = d[k + 1] - lj;
       const double ns = (k + 2 < c) ? e[k + 1] : 0.0;
-      if (fabs(cd) >= fabs(sub)) {
-        const double m = (cd != 0.0) ? sub / cd : 0.0;
-        U0[k * nev + j] = clamp_tiny(cd); U1[k * nev + j] = cs; U2[k * nev + j] = 0.0; Pv[k * nev + j] = 0.0;
-        Lm[k * nev + j] = m;
-        cd = nd - m * cs;
-        cs = ns;
-      } else {
-        const double m = cd / sub;
-        U0[k * nev + j] = clamp_tiny(sub); U1[k * nev + j] = nd; U2[k * nev + j] = ns; Pv[k * nev + j] = 1.0;
-        Lm[k * nev + j] = m;
-        cd = cs - m * nd;
-        cs = -m * ns;
-      }
+      const bool sw = !(fabs(cd) >= fabs(sub));
+      const double piv = sw ? sub : cd;
+      const double m = (piv != 0.0) ? (sw ? cd : sub) / piv : 0.0;   // piv == 0 only when sub == 0
+      U0[k * nev + j] = 1.0 / clamp_tiny(piv);
+      U1[k * nev + j] = sw ? nd : cs;
+      U2[k * nev + j] = sw ? ns : 0.0;
+      Pv[k * nev + j] = sw ? 1.0 : 0.0;
+      Lm[k * nev + j] = m;
+      const double ncd = sw ? cs - m * nd : nd - m * cs;
+      cs = sw ? -m * ns : ns;
+      cd = ncd;
     }
-    U0[(c - 1) * nev + j] = clamp_tiny(cd);
-    for (int i = 0; i < c; ++i) Z[i * lz + j] = 1.0 + 0.25 * (double)((i * 7 + j * 13) % 11) / 11.0;
+    U0[(c - 1) * nev + j] = 1.0 / clamp_tiny(cd);
+  }
+  // start vectors, fixed and not orthogonal to any eigenvector of interest
+  for (int q = tid; q < c * nev; q += kSyevThreads) {
+    const int i = q / nev, j = q - i * nev;
+    Z[i * lz + j] = 1.0 + (double)((i * 7 + j * 13) % 11) * (0.25 / 11.0);
   }
   __syncthreads();
   int maxrank = 0;
@@ -366,7 +374,7 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
         for (int u = 0; u < 4; ++u) {
           const int k = k0 - u;
           const bool ok = k >= 0;
-          u0[u] = ok ? U0[k * nev + j] : 1.0;
+          u0[u] = ok ? U0[k * nev + j] : 1.0;   // reciprocal pivot
           u1[u] = ok ? U1[k * nev + j] : 0.0;
           u2[u] = ok ? U2[k * nev + j] : 0.0;
           zz[u] = ok ? Z[k * lz + j] : 0.0;
@@ -378,7 +386,7 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
           double y = zz[u];
           if (k + 1 < c) y -= u1[u] * z1;
           if (k + 2 < c) y -= u2[u] * z2;
-          y /= u0[u];
+          y *= u0[u];
           Z[k * lz + j] = y;
           nrm += y * y;
           z2 = z1;
@@ -883,7 +891,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const int i = ti + 16 * a, j = tj + 16 * b;
-          if (i < c && j < c) gq[i * (c + 1) + j] = Q[a][b];
+          if (i < c && j < c) gq[j * (c + 1) + i] = Q[a][b];   // transposed
         }
       __syncthreads();
       for (int i = tid; i < c; i += kSyevThreads) {
@@ -902,17 +910,13 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   const int lz = nev + 1;
   double* Z = pool;
   int64_t used = (int64_t)c * lz;
-  double* lu;
   double* sq;
-  if (used + 5 * (int64_t)c * nev <= POOL) {
-    lu = pool + used;
-    used += 5 * (int64_t)c * nev;
-  } else {
-    lu = work;
-  }
+  const bool lu_lds = (used + 5 * (int64_t)c * nev <= POOL);   // uniform
+  double* const lu = pool + used;
+  if (lu_lds) used += 5 * (int64_t)c * nev;
   const int lq = c + 1;
   if constexpr (MODE == 2) {
-    sq = work + sp.q;   // as step 1 left it
+    sq = work + sp.q;   // Q^T, as step 1 left it
   } else {
     if (used + (int64_t)c * (c + 1) <= POOL) sq = pool + used;
     else sq = work + 5 * (int64_t)c * nev;
@@ -927,7 +931,10 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   }
   __syncthreads();
   // ---- 2, 3. eigenvalues and eigenvectors of T ----
-  const int maxrank = tridiag_eigs<NB, MODE == 2>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu);
+  // two inlined copies, so that the factors are addressed as LDS or as global memory, not through
+  // generic pointers
+  const int maxrank = lu_lds ? tridiag_eigs<NB, MODE == 2>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu)
+                             : tridiag_eigs<NB, MODE == 2>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, work);
   // ---- 4. C = Q Z (c x nev): 16 x 16 tiles, one wave per tile, 16x16x4 FP64 MFMAs ----
   typedef Mfma<double>::v4 v4;
   const int tn = (nev + 15) / 16, c4 = (c + 3) & ~3;
@@ -935,11 +942,28 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
     const int i0 = 16 * (tile / tn), j0 = 16 * (tile % tn);
     v4 acc = {0.0, 0.0, 0.0, 0.0};
     const int ia = i0 + (lane & 15), jb = j0 + (lane & 15);
-    for (int l0 = 0; l0 < c4; l0 += 4) {
-      const int l = l0 + (lane >> 4);
-      const double qa = (l < c && ia < c) ? sq[ia * lq + l] : 0.0;
-      const double zb = (l < c && jb < nev) ? Z[l * lz + jb] : 0.0;
-      acc = Mfma<double>::op(qa, zb, acc);
+    if constexpr (MODE == 2) {
+      // Q^T from global memory: rows l of 16 consecutive entries, every load issued before the
+      // products
+      double qa[CM / 4];
+#pragma unroll
+      for (int u = 0; u < CM / 4; ++u) {
+        const int l = 4 * u + (lane >> 4);
+        qa[u] = (l < c && ia < c) ? sq[l * lq + ia] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < CM / 4; ++u) {
+        const int l = 4 * u + (lane >> 4);
+        const double zb = (l < c && jb < nev) ? Z[l * lz + jb] : 0.0;
+        acc = Mfma<double>::op(qa[u], zb, acc);
+      }
+    } else {
+      for (int l0 = 0; l0 < c4; l0 += 4) {
+        const int l = l0 + (lane >> 4);
+        const double qa = (l < c && ia < c) ? sq[ia * lq + l] : 0.0;
+        const double zb = (l < c && jb < nev) ? Z[l * lz + jb] : 0.0;
+        acc = Mfma<double>::op(qa, zb, acc);
+      }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
