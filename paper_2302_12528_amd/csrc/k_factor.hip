@@ -228,13 +228,18 @@ __device__ inline void load_cm_vec(T (*As)[TB + 1], const T* M, int64_t ld, int 
 //     the waves at or left of the published quarter take its 16 row steps (row j of X broadcast
 //     across the wave with readlane) while the waves to its right update.
 template <typename T>
-__global__ void __launch_bounds__(256) potrf_trsm_kernel(FactorDev D, int64_t task_off, T* panel, T* upd,
-                                                         T* dinv, int* flag) {
-  __shared__ T Ls[TB][TB + 1];   // the K-major tile C(I, p)
-  __shared__ T Xs[TB][TB + 1];   // Xs[k][c] = inv(L)[c][k]
+constexpr int potrf_lds_elems() { return 2 * TB * (TB + 1) + 2 * TB * ((sizeof(T) == 4) ? 20 : 18); }
+
+// One task of the panel step (tk: {s, I, J, p}); lds: potrf_lds_elems<T>() elements of LDS, 16-byte
+// aligned.
+template <typename T>
+__device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& D, const int* tk, T* panel,
+                                                               T* upd, T* dinv, int* flag, T* lds) {
+  T(*Ls)[TB + 1] = reinterpret_cast<T(*)[TB + 1]>(lds);                  // the K-major tile C(I, p)
+  T(*Xs)[TB + 1] = reinterpret_cast<T(*)[TB + 1]>(lds + TB * (TB + 1));  // Xs[k][c] = inv(L)[c][k]
   constexpr int LBS = (sizeof(T) == 4) ? 20 : 18;   // 16-byte aligned rows
-  __shared__ T Lb[2][TB][LBS];   // the published quarter of L, double-buffered
-  const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
+  // the published quarter of L, double-buffered
+  T(*Lb)[TB][LBS] = reinterpret_cast<T(*)[TB][LBS]>(lds + 2 * TB * (TB + 1));
   const int s = tk[0], I = tk[1], p = tk[3];
   const Sn S = sn_of(D, s);
   const int r0 = p * TB, h = min(TB, S.nc - r0);
@@ -365,13 +370,21 @@ __global__ void __launch_bounds__(256) potrf_trsm_kernel(FactorDev D, int64_t ta
     }
 }
 
-// Trailing update of a panel step, C(I,J) -= C(I,p) C(J,p)^T for p < J < np (task s, I, J, p); the
-// task (s, p, p, p) instead stores L_pp from its staging slot into tile (p, p).
 template <typename T>
-__global__ void __launch_bounds__(256) update_kernel(FactorDev D, int64_t task_off, T* panel, T* upd, T* dinv) {
-  __shared__ T As[TB][TB + 1];
-  __shared__ T Bs[TB][TB + 1];
-  const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
+__global__ void __launch_bounds__(256) potrf_trsm_kernel(FactorDev D, int64_t task_off, T* panel, T* upd,
+                                                         T* dinv, int* flag) {
+  __shared__ __align__(16) T lds[potrf_lds_elems<T>()];
+  potrf_trsm_body<T>(D, D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x)), panel, upd, dinv, flag, lds);
+}
+
+// Trailing update of a panel step, C(I,J) -= C(I,p) C(J,p)^T for p < J < np (task s, I, J, p); the
+// task (s, p, p, p) instead stores L_pp from its staging slot into tile (p, p).  lds: 2 TB (TB + 1)
+// elements.
+template <typename T>
+__device__ __attribute__((always_inline)) void update_body(const FactorDev& D, const int* tk, T* panel, T* upd,
+                                                           T* dinv, T* lds) {
+  T(*As)[TB + 1] = reinterpret_cast<T(*)[TB + 1]>(lds);
+  T(*Bs)[TB + 1] = reinterpret_cast<T(*)[TB + 1]>(lds + TB * (TB + 1));
   const int s = tk[0], I = tk[1], J = tk[2], p = tk[3];
   const Sn S = sn_of(D, s);
   const int tid = threadIdx.x;
@@ -428,6 +441,29 @@ __global__ void __launch_bounds__(256) update_kernel(FactorDev D, int64_t task_o
         if (c < hJ) C[r + (int64_t)c * ldc] = cv[b][a][q] - acc[b][a][q];
       }
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) update_kernel(FactorDev D, int64_t task_off, T* panel, T* upd, T* dinv) {
+  __shared__ __align__(16) T lds[2 * TB * (TB + 1)];
+  update_body<T>(D, D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x)), panel, upd, dinv, lds);
+}
+
+// The update of panel p's columns beyond p + 1 (blocks npotrf ..) together with the factorization of
+// panel p + 1 (blocks 0 .. npotrf - 1) in one launch: they read and write disjoint tiles (column p,
+// which both read, is final), so the second may start before the first has finished without a
+// second stream and its synchronization.
+template <typename T>
+__global__ void __launch_bounds__(256) potrf_update_kernel(FactorDev D, int64_t potrf_off, int npotrf,
+                                                           int64_t upd_off, int nupd, T* panel, T* upd, T* dinv,
+                                                           int* flag) {
+  constexpr int NL = potrf_lds_elems<T>() > 2 * TB * (TB + 1) ? potrf_lds_elems<T>() : 2 * TB * (TB + 1);
+  __shared__ __align__(16) T lds[NL];
+  const int64_t b = blockIdx.x;
+  if (b < npotrf)
+    potrf_trsm_body<T>(D, D.tasks + 4 * (potrf_off + xcd_block(b, npotrf)), panel, upd, dinv, flag, lds);
+  else
+    update_body<T>(D, D.tasks + 4 * (upd_off + xcd_block(b - npotrf, nupd)), panel, upd, dinv, lds);
 }
 
 // Schur complement tile (I, J) of U_s (I >= J >= np): C -= L(I, :) L(J, :)^T over all nc panel
@@ -635,6 +671,7 @@ void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t 
       break;
 
     case kUpdate:
+    case kUpdateRest:
       update_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv);
       break;
     case kSchur:
@@ -657,6 +694,16 @@ void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t 
       break;
   }
 }
+template <typename T>
+void launch_potrf_update(const FactorDev& D, int64_t potrf_off, int npotrf, int64_t upd_off, int nupd, T* panel,
+                         T* upd, T* dinv, int* flag, hipStream_t st) {
+  potrf_update_kernel<T><<<npotrf + nupd, 256, 0, st>>>(D, potrf_off, npotrf, upd_off, nupd, panel, upd, dinv, flag);
+}
+template void launch_potrf_update<float>(const FactorDev&, int64_t, int, int64_t, int, float*, float*, float*, int*,
+                                         hipStream_t);
+template void launch_potrf_update<double>(const FactorDev&, int64_t, int, int64_t, int, double*, double*, double*,
+                                          int*, hipStream_t);
+
 template void launch_factor_step<float>(const FactorDev&, int, int, int64_t, int, int64_t, int64_t, float*, float*,
                                         float*, float*, int*, hipStream_t);
 template void launch_factor_step<double>(const FactorDev&, int, int, int64_t, int, int64_t, int64_t, double*,

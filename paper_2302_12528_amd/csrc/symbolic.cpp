@@ -433,16 +433,25 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
       end_step();
       // trailing update of the panel columns; task (s, p, p, p) moves L_pp from its staging slot
       // into the panel (the panel step's other tasks read the unfactored tile (p, p) while it is
-      // formed)
+      // formed).  Column p + 1 is a step of its own so that the next panel step can start after it
+      // while the columns beyond are updated (one step of lookahead).
       begin_step(kUpdate);
       for (int32_t q = q0; q < q1; ++q) {
         int s = S.level_sn[q];
         int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
         if (np > p) {
           push(s, p, p, p);
-          for (int J = p + 1; J < np; ++J)
-            for (int I = J; I < rt; ++I) push(s, I, J, p);
+          if (p + 1 < np)
+            for (int I = p + 1; I < rt; ++I) push(s, I, p + 1, p);
         }
+      }
+      end_step();
+      begin_step(kUpdateRest);
+      for (int32_t q = q0; q < q1; ++q) {
+        int s = S.level_sn[q];
+        int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+        for (int J = p + 2; J < np; ++J)
+          for (int I = J; I < rt; ++I) push(s, I, J, p);
       }
       end_step();
     }
@@ -847,7 +856,8 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
       const bool plevel = (st.kind == kInvT1 || st.kind == kInvX21);   // p holds the recursion level
       if (p < 0 || (!plevel && p >= np) || I < 0 || I >= rt || J < 0 || J >= rt) return "task tile";
       if (st.kind == kSchur && !(J >= np && I >= J)) return "Schur tile order";
-      if (st.kind == kUpdate && !((J > p && J < np && I >= J) || (I == p && J == p))) return "update tile order";
+      if (st.kind == kUpdate && !((J == p + 1 && J < np && I >= J) || (I == p && J == p))) return "update tile order";
+      if (st.kind == kUpdateRest && !(J > p + 1 && J < np && I >= J)) return "update tile order";
       if ((st.kind == kPotrf || st.kind == kTrsm || st.kind == kInvScale) && !(J == p && I >= p))
         return "trsm tile order";
       if (st.kind == kInvUpdate && !(J < p && I >= p)) return "inverse update tile order";

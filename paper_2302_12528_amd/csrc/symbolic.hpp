@@ -84,11 +84,13 @@ struct FactorPlan {
   std::vector<int32_t> level_max_nr;   // per level: the largest front (rows) of the level
 };
 // kPotrf: Cholesky of diagonal tile p with the trsm of the tiles below it (kTrsm: the trsm alone);
-// kUpdate: trailing update of the panel columns; kSchur: U_s -= L21 L21^T after the last panel step.
+// kUpdate: trailing update of the next panel column (p + 1) and the move of L_pp into the panel;
+// kUpdateRest: the trailing update of the panel columns after it (they may run while panel p + 1 is
+// factored); kSchur: U_s -= L21 L21^T after the last panel step.
 // kInvPrep / kInvT1 / kInvX21 / kInvP21: the inverse phase P_s = [inv(L11); L21 inv(L11)] (kInvScale and
 // kInvUpdate: the column sweep it replaces, no longer planned).
 enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6,
-                kSchur = 7, kInvT1 = 8, kInvX21 = 9, kInvP21 = 10 };
+                kSchur = 7, kInvT1 = 8, kInvX21 = 9, kInvP21 = 10, kUpdateRest = 11 };
 void build_factor_plan(const Symbolic& S, FactorPlan& plan);
 
 // Trisolve work lists.  Each output tile (64 rows of P_s for the forward sweep, 64
