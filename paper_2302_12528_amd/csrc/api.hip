@@ -420,11 +420,13 @@ lobpcg_status factor_t(lobpcg_ctx c) {
     for (size_t q = i; q < j; ++q) {
       const int kind = steps[q].kind;
       if (is_inv(kind) || kind == kSchur) continue;
-      if (sizeof(T) == 4 && kind == kUpdateRest && q + 1 < j && steps[q + 1].kind == kPotrf) {
-        launch_potrf_update<T>(c->FD, steps[q + 1].off, steps[q + 1].count, steps[q].off, steps[q].count, panel, upd,
-                               dinv, c->d_flag, ms);
-        ++q;
-        continue;
+      if constexpr (sizeof(T) == 4) {
+        if (kind == kUpdateRest && q + 1 < j && steps[q + 1].kind == kPotrf) {
+          launch_potrf_update(c->FD, steps[q + 1].off, steps[q + 1].count, steps[q].off, steps[q].count, panel, upd,
+                              dinv, c->d_flag, ms);
+          ++q;
+          continue;
+        }
       }
       if (sizeof(T) == 8 && kind == kUpdate && q + 1 < j && steps[q + 1].kind == kUpdateRest &&
           steps[q + 1].off == steps[q].off + steps[q].count) {

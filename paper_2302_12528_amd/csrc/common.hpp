@@ -107,10 +107,9 @@ void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t 
                         int64_t asm_off, int64_t asm_count, T* panel, T* upd, T* dinv, T* lcopy, int* flag,
                         hipStream_t st);
 // the panel step p + 1 (npotrf tasks from potrf_off) and the update of panel p's columns beyond p + 1
-// (nupd tasks from upd_off) in one launch
-template <typename T>
-void launch_potrf_update(const FactorDev& D, int64_t potrf_off, int npotrf, int64_t upd_off, int nupd, T* panel,
-                         T* upd, T* dinv, int* flag, hipStream_t st);
+// (nupd tasks from upd_off) in one launch (FP32 factors)
+void launch_potrf_update(const FactorDev& D, int64_t potrf_off, int npotrf, int64_t upd_off, int nupd, float* panel,
+                         float* upd, float* dinv, int* flag, hipStream_t st);
 
 // ---- supernodal triangular solves (k_trisolve.hip) ----
 struct SolveDev {

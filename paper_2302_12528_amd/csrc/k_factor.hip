@@ -694,15 +694,11 @@ void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t 
       break;
   }
 }
-template <typename T>
-void launch_potrf_update(const FactorDev& D, int64_t potrf_off, int npotrf, int64_t upd_off, int nupd, T* panel,
-                         T* upd, T* dinv, int* flag, hipStream_t st) {
-  potrf_update_kernel<T><<<npotrf + nupd, 256, 0, st>>>(D, potrf_off, npotrf, upd_off, nupd, panel, upd, dinv, flag);
+void launch_potrf_update(const FactorDev& D, int64_t potrf_off, int npotrf, int64_t upd_off, int nupd, float* panel,
+                         float* upd, float* dinv, int* flag, hipStream_t st) {
+  potrf_update_kernel<float><<<npotrf + nupd, 256, 0, st>>>(D, potrf_off, npotrf, upd_off, nupd, panel, upd, dinv,
+                                                            flag);
 }
-template void launch_potrf_update<float>(const FactorDev&, int64_t, int, int64_t, int, float*, float*, float*, int*,
-                                         hipStream_t);
-template void launch_potrf_update<double>(const FactorDev&, int64_t, int, int64_t, int, double*, double*, double*,
-                                          int*, hipStream_t);
 
 template void launch_factor_step<float>(const FactorDev&, int, int, int64_t, int, int64_t, int64_t, float*, float*,
                                         float*, float*, int*, hipStream_t);
