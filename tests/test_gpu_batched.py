@@ -70,6 +70,31 @@ def test_batch_invariance(torch_cuda):
         assert abs(info1["iters"] - infos[b]["iters"]) <= 1
 
 
+def test_large_batch_one_launch_eigensolver(torch_cuda):
+    """72 problems x m = 16 Ritz pairs: the Rayleigh-Ritz eigensolver runs as one launch per batch
+    (more bisection workgroups than a separate launch is given); every problem meets eq. (stop) and
+    the first four agree with a four-problem batch, whose eigensolver runs as three launches."""
+    import paper_2302_12528_amd as pk
+    probs = _small_batch(72)
+    print(f"batched count={len(probs)}", flush=True)
+    bs = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, grids=[p.grid for p in probs])
+    evals, evecs, infos, _ = bs.solve([p.X0 for p in probs])
+    bs.close()
+    for b, p in enumerate(probs):
+        lam = evals[b].cpu().numpy()
+        res = residuals(p.A, evecs[b].cpu().numpy(), lam, infos[b]["norm_a"])
+        assert np.all(res <= 1e-10 * (1 + np.abs(lam) / infos[b]["norm_a"]) * 1.001), b
+    small = pk.BatchedSolver([p.A for p in probs[:4]], 8, 16, 1e-10, grids=[p.grid for p in probs[:4]])
+    ev4, _, infos4, _ = small.solve([p.X0 for p in probs[:4]])
+    small.close()
+    for b in range(4):
+        a, c = evals[b].cpu().numpy(), ev4[b].cpu().numpy()
+        d = np.max(np.abs(a - c) / np.abs(c))
+        print(f"problem {b}: eig rel diff {d:.2e}, iters {infos[b]['iters']} / {infos4[b]['iters']}", flush=True)
+        assert d <= 1e-11
+        assert abs(infos[b]["iters"] - infos4[b]["iters"]) <= 1
+
+
 def test_batched_uneven_and_graph_ordering(torch_cuda):
     """Different sizes, one problem without a grid hint (graph nested dissection), default start blocks."""
     import paper_2302_12528_amd as pk
