@@ -754,7 +754,7 @@ __device__ __host__ inline SyevSplit syev_split_offsets(int c) {
   return {q, d, d + c, d + 2 * c};
 }
 
-// Eigenvalue j = blockIdx.x of the tridiagonal T that syev_reg_kernel<NB, 1> left in the scratch,
+// Eigenvalue j = blockIdx.x of the tridiagonal T that syev_tridiag_kernel<NB> left in the scratch,
 // by multisection on Sturm counts with kSyevThreads points per round (the Gershgorin interval,
 // tolerance and scaled counts are those of tridiag_eigs, so the bracket invariant
 // count(lo) <= j < count(hi) and the stopping rule are the same; only the number of points per
@@ -834,9 +834,157 @@ __global__ void __launch_bounds__(kSyevThreads) syev_bisect_kernel(double* __res
   if (tid == 0) work[sp.lam + j] = 0.5 * (l + h);
 }
 
-// MODE 0 does all four steps.  MODE 1 stops after step 1 and leaves T and Q in the global scratch
-// (layout of syev_split_offsets); the eigenvalues are then bisected by syev_bisect_kernel, one
-// workgroup per eigenvalue, and MODE 2 loads T, Q and the eigenvalues and does steps 3 and 4.
+// Step 1 with the work of each reflector split between two groups of four waves on the same 16 x 16
+// thread grid: the matrix group holds H (thread (ti, tj): entries (ti + 16 a, tj + 16 b)), forms v
+// and t and applies H -= v w^T + w v^T as tridiag_rows does; the Q group holds the same entries of
+// Q and applies Q -= t (Q v) v^T as soon as v is published, while the matrix group forms p = t H v.
+// M is H or Q by group; QG: this thread is in the Q group (wave-uniform).
+template <int NB, int AK>
+__device__ __attribute__((always_inline)) void tridiag_rows_split(double (&M)[NB][NB], bool QG, int c, int ti,
+                                                                  int tj, double* vb, double* pb, double* pvp,
+                                                                  double* tb, double* d, double* e) {
+  constexpr int CM = 16 * NB;
+#pragma unroll 1
+  for (int r = 0; r < 16; ++r) {
+    const int k = 16 * AK + r;
+    if (k + 2 >= c) break;   // uniform
+    const int buf = k & 1;
+    if (!QG && ti == r) {
+      double ss = 0.0, al = 0.0;
+#pragma unroll
+      for (int b = AK; b < NB; ++b) {
+        const int j = tj + 16 * b;
+        const double x = M[AK][b];
+        ss += (j >= k + 2) ? x * x : 0.0;
+        al += (j == k + 1) ? x : 0.0;
+        if (j == k) d[k] = x;
+      }
+      ss = row16_sum(ss);
+      al = row16_sum(al);
+      double t = 0.0, beta = al, scale = 0.0;
+      if (ss > 0.0) {
+        const double xn = sqrt(al * al + ss);
+        beta = (al >= 0.0) ? -xn : xn;
+        t = (beta - al) / beta;
+        scale = 1.0 / (al - beta);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = tj + 16 * b;
+        vb[buf * CM + j] = (b >= AK && j > k + 1) ? M[AK][b] * scale : (j == k + 1 ? 1.0 : 0.0);
+      }
+      if (tj == 0) {
+        tb[buf] = t;
+        e[k] = beta;
+      }
+    }
+    __syncthreads();
+    const double t = tb[buf];
+    if (t == 0.0) continue;   // uniform; every buffer is double-buffered by step parity
+    double vc[NB];
+#pragma unroll
+    for (int b = AK; b < NB; ++b) vc[b] = vb[buf * CM + tj + 16 * b];
+    double pp[NB], vr[NB];
+    if (QG) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        double sq_ = 0.0;
+#pragma unroll
+        for (int b = AK; b < NB; ++b) sq_ = fma(M[a][b], vc[b], sq_);
+        const double qa = t * row16_sum(sq_);
+#pragma unroll
+        for (int b = AK; b < NB; ++b) M[a][b] -= qa * vc[b];
+      }
+    } else {
+#pragma unroll
+      for (int a = AK; a < NB; ++a) vr[a] = vb[buf * CM + ti + 16 * a];
+      double pv = 0.0;
+#pragma unroll
+      for (int a = AK; a < NB; ++a) {
+        double sp = 0.0;
+#pragma unroll
+        for (int b = AK; b < NB; ++b) sp = fma(M[a][b], vc[b], sp);
+        pp[a] = t * row16_sum(sp);
+        pv = fma(pp[a], vr[a], pv);
+      }
+      if (tj == 0) {
+#pragma unroll
+        for (int a = AK; a < NB; ++a) pb[buf * CM + ti + 16 * a] = pp[a];
+        pvp[buf * 16 + ti] = pv;
+      }
+    }
+    __syncthreads();
+    if (!QG) {
+      double K = 0.0;
+#pragma unroll
+      for (int g = 0; g < 16; ++g) K += pvp[buf * 16 + g];
+      K *= 0.5 * t;
+      double wc[NB];
+#pragma unroll
+      for (int b = AK; b < NB; ++b) wc[b] = pb[buf * CM + tj + 16 * b] - K * vc[b];
+#pragma unroll
+      for (int a = AK; a < NB; ++a) {
+        const double wr = pp[a] - K * vr[a];
+#pragma unroll
+        for (int b = AK; b < NB; ++b) M[a][b] -= vr[a] * wc[b] + wr * vc[b];
+      }
+    }
+  }
+  if constexpr (AK + 1 < NB) tridiag_rows_split<NB, AK + 1>(M, QG, c, ti, tj, vb, pb, pvp, tb, d, e);
+}
+
+// Step 1 of the three-launch form: T (d, e with e[c - 1] = 0) and Q^T to the global scratch, with
+// 2 kSyevThreads threads (the two groups of tridiag_rows_split).
+template <int NB>
+__global__ void __launch_bounds__(2 * kSyevThreads) syev_tridiag_kernel(const double* __restrict__ H, int64_t ldh,
+                                                                        int64_t hstride, int c,
+                                                                        double* __restrict__ work, int64_t wstride,
+                                                                        const int32_t* __restrict__ active) {
+  constexpr int CM = 16 * NB;
+  if (active && !active[blockIdx.x]) return;
+  H += (int64_t)blockIdx.x * hstride;
+  work += (int64_t)blockIdx.x * wstride;
+  __shared__ double vb[2][CM], pb[2][CM], pvp[2][16], tb[2];
+  __shared__ double d[CM], e[CM];
+  const SyevSplit sp = syev_split_offsets(c);
+  const int tid = threadIdx.x;
+  const bool QG = tid >= kSyevThreads;   // waves 4..7
+  const int g = tid & (kSyevThreads - 1), lane = g & 63, wid = g >> 6;
+  const int ti = wid * 4 + (lane >> 4), tj = lane & 15;
+  double M[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      if (QG) M[a][b] = (i == j) ? 1.0 : 0.0;
+      else M[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
+    }
+  tridiag_rows_split<NB, 0>(M, QG, c, ti, tj, &vb[0][0], &pb[0][0], &pvp[0][0], tb, d, e);
+  double* gq = work + sp.q;
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int i = ti + 16 * a, j = tj + 16 * b;
+      if (QG) {
+        if (i < c && j < c) gq[j * (c + 1) + i] = M[a][b];   // transposed
+      } else {
+        if (i == j && i + 2 >= c && i < c) d[i] = M[a][b];
+        if (c >= 2 && i == c - 1 && j == c - 2) e[c - 2] = M[a][b];
+      }
+    }
+  __syncthreads();
+  for (int i = tid; i < c; i += 2 * kSyevThreads) {
+    work[sp.d + i] = d[i];
+    work[sp.e + i] = (i < c - 1) ? e[i] : 0.0;
+  }
+}
+
+// MODE 0 does all four steps.  In the three-launch form syev_tridiag_kernel does step 1 and leaves
+// T and Q^T in the global scratch (layout of syev_split_offsets), syev_bisect_kernel finds the
+// eigenvalues with one workgroup each, and MODE 1 loads T, Q^T and the eigenvalues and does steps 3
+// and 4.
 template <int NB, int MODE>
 __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __restrict__ H, int64_t ldh,
                                                                 int64_t hstride, int c, int nev,
@@ -864,7 +1012,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   const int ti = wid * 4 + (lane >> 4), tj = lane & 15;
   const SyevSplit sp = syev_split_offsets(c);
   double Q[NB][NB];
-  if constexpr (MODE != 2) {
+  if constexpr (MODE == 0) {
     double A[NB][NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a)
@@ -884,22 +1032,6 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
         if (i == j && i + 2 >= c && i < c) d[i] = A[a][b];
         if (c >= 2 && i == c - 1 && j == c - 2) e[c - 2] = A[a][b];
       }
-    if constexpr (MODE == 1) {
-      double* gq = work + sp.q;
-#pragma unroll
-      for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const int i = ti + 16 * a, j = tj + 16 * b;
-          if (i < c && j < c) gq[j * (c + 1) + i] = Q[a][b];   // transposed
-        }
-      __syncthreads();
-      for (int i = tid; i < c; i += kSyevThreads) {
-        work[sp.d + i] = d[i];
-        work[sp.e + i] = (i < c - 1) ? e[i] : 0.0;
-      }
-      return;
-    }
   } else {
     for (int i = tid; i < c; i += kSyevThreads) {
       d[i] = work[sp.d + i];
@@ -915,7 +1047,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   double* const lu = pool + used;
   if (lu_lds) used += 5 * (int64_t)c * nev;
   const int lq = c + 1;
-  if constexpr (MODE == 2) {
+  if constexpr (MODE == 1) {
     sq = work + sp.q;   // Q^T, as step 1 left it
   } else {
     if (used + (int64_t)c * (c + 1) <= POOL) sq = pool + used;
@@ -933,8 +1065,8 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   // ---- 2, 3. eigenvalues and eigenvectors of T ----
   // two inlined copies, so that the factors are addressed as LDS or as global memory, not through
   // generic pointers
-  const int maxrank = lu_lds ? tridiag_eigs<NB, MODE == 2>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu)
-                             : tridiag_eigs<NB, MODE == 2>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, work);
+  const int maxrank = lu_lds ? tridiag_eigs<NB, MODE == 1>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu)
+                             : tridiag_eigs<NB, MODE == 1>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, work);
   // ---- 4. C = Q Z (c x nev): 16 x 16 tiles, one wave per tile, 16x16x4 FP64 MFMAs ----
   typedef Mfma<double>::v4 v4;
   const int tn = (nev + 15) / 16, c4 = (c + 3) & ~3;
@@ -942,7 +1074,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
     const int i0 = 16 * (tile / tn), j0 = 16 * (tile % tn);
     v4 acc = {0.0, 0.0, 0.0, 0.0};
     const int ia = i0 + (lane & 15), jb = j0 + (lane & 15);
-    if constexpr (MODE == 2) {
+    if constexpr (MODE == 1) {
       // Q^T from global memory: rows l of 16 consecutive entries, every load issued before the
       // products
       double qa[CM / 4];
@@ -1343,10 +1475,9 @@ void launch_syev_reg(const double* H, int64_t ldh, int64_t hstride, int c, int n
                                                        info, active);
     return;
   }
-  syev_reg_kernel<NB, 1><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws,
-                                                     info, active);
+  syev_tridiag_kernel<NB><<<B, 2 * kSyevThreads, 0, st>>>(H, ldh, hstride, c, work, ws, active);
   syev_bisect_kernel<<<dim3(nev, B), kSyevThreads, 0, st>>>(work, ws, c, nev, active);
-  syev_reg_kernel<NB, 2><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws,
+  syev_reg_kernel<NB, 1><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws,
                                                      info, active);
 }
 }  // namespace
