@@ -419,7 +419,7 @@ lobpcg_status factor_t(lobpcg_ctx c) {
     while (j < steps.size() && steps[j].level == l) ++j;
     for (size_t q = i; q < j; ++q) {
       const int kind = steps[q].kind;
-      if (is_inv(kind) || kind == kSchur) continue;
+      if (is_inv(kind) || kind == kSchur || kind == kSchur2) continue;
       if constexpr (sizeof(T) == 4) {
         if (kind == kUpdateRest && q + 1 < j && steps[q + 1].kind == kPotrf) {
           launch_potrf_update(c->FD, steps[q + 1].off, steps[q + 1].count, steps[q].off, steps[q].count, panel, upd,
@@ -442,7 +442,7 @@ lobpcg_status factor_t(lobpcg_ctx c) {
     hipEvent_t panels_done = c->fev[e++];
     HIP_TRY(hipEventRecord(panels_done, ms));
     for (size_t q = i; q < j; ++q)
-      if (steps[q].kind == kSchur) launch(steps[q], ms);
+      if (steps[q].kind == kSchur || steps[q].kind == kSchur2) launch(steps[q], ms);
     hipEvent_t schur_done = c->fev[e++];
     HIP_TRY(hipEventRecord(schur_done, ms));
     HIP_TRY(hipStreamWaitEvent(ss, panels_done, 0));

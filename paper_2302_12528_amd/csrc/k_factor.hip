@@ -526,6 +526,121 @@ __global__ void __launch_bounds__(256) schur_kernel(FactorDev D, int64_t task_of
     }
 }
 
+// Schur complement on 128 x 128 blocks (task (s, I, J): tiles I, I + 1 by J, J + 1 of U_s, I >= J,
+// both counted from np in pairs): wave w takes the 64 x 64 tile (I + w / 2, J + w % 2), skipping the
+// one above the diagonal of a diagonal block and tiles past the front.  The operands are staged 32
+// panel columns at a time for all 128 rows (64 need more registers: fewer waves, slower), so each staged element feeds two tiles: half the operand
+// traffic per product of schur_kernel, for the levels with large fronts.
+constexpr int kSchurK = 32;
+template <typename T>
+__global__ void __launch_bounds__(256) schur2_kernel(FactorDev D, int64_t task_off, T* panel, T* upd) {
+  constexpr int W2 = 2 * TB;   // 128 rows
+  // row padding: the four 16-lane groups of an MFMA operand read fall in different banks
+  constexpr int LP = (sizeof(T) == 4) ? W2 + 16 : W2 + 8;
+  __shared__ T As[kSchurK][LP];
+  __shared__ T Bs[kSchurK][LP];
+  const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
+  const int s = tk[0], I = tk[1], J = tk[2];
+  const Sn S = sn_of(D, s);
+  int rI, hI0, rJ, hJ0;
+  tile_rows(S, I, rI, hI0);
+  tile_rows(S, J, rJ, hJ0);
+  const int hI = min(W2, S.nr - rI), hJ = min(W2, S.nr - rJ);   // rows of the two tile rows / columns
+  int64_t ldc;
+  T* C = front_ptr(panel, upd, S, rI, rJ, ldc);
+  const int64_t ldp = panel_ld(S.nr);
+  const T* Ap = panel + S.panel + rI;   // L(rI + r, k) = Ap[r + k ldp]
+  const T* Bp = panel + S.panel + rJ;
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int qr = (w / 2) * TB, qc = (w % 2) * TB;   // this wave's tile in the block
+  const bool live = (qr < hI) && (qc < hJ) && !(I == J && qr < qc);   // wave-uniform
+  typename Mfma<T>::v4 acc[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[b][a][q] = 0;
+  const bool va = ((reinterpret_cast<uintptr_t>(Ap) | (uintptr_t)(ldp * sizeof(T))) & 15) == 0;
+  const bool vb = ((reinterpret_cast<uintptr_t>(Bp) | (uintptr_t)(ldp * sizeof(T))) & 15) == 0;
+  // loader: element e = tid + 256 q (q < NQ) is rows 4 (e % 32) .. + 3 of chunk column e / 32
+  constexpr int NQ = kSchurK / 8;
+  auto load = [&](T (&v)[NQ][4], const T* M, int h, int K, bool vec) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + 256 * q, k = e / 32, r = 4 * (e % 32);
+      if (k < K && r < h) {
+        const T* src = M + r + (int64_t)k * ldp;
+        if (vec && r + 3 < h) {
+          if constexpr (sizeof(T) == 4) {
+            const f32x4_t x = *reinterpret_cast<const f32x4_t*>(src);
+            v[q][0] = x.x; v[q][1] = x.y; v[q][2] = x.z; v[q][3] = x.w;
+          } else {
+            const f64x2_t x0 = *reinterpret_cast<const f64x2_t*>(src), x1 = *reinterpret_cast<const f64x2_t*>(src + 2);
+            v[q][0] = x0.x; v[q][1] = x0.y; v[q][2] = x1.x; v[q][3] = x1.y;
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[q][j] = (r + j < h) ? src[j] : (T)0;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[q][j] = (T)0;
+      }
+    }
+  };
+  auto store = [&](const T (&v)[NQ][4], T (*Ls)[LP]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + 256 * q, k = e / 32, r = 4 * (e % 32);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Ls[k][r + j] = v[q][j];
+    }
+  };
+  T na[NQ][4], nb[NQ][4];
+  load(na, Ap, hI, min(kSchurK, S.nc), va);
+  load(nb, Bp, hJ, min(kSchurK, S.nc), vb);
+  const int kl = lane / 16, il = lane % 16;
+  for (int k0 = 0; k0 < S.nc; k0 += kSchurK) {
+    const int K = min(kSchurK, S.nc - k0);
+    __syncthreads();   // the previous chunk's products are done with As, Bs
+    store(na, As);
+    store(nb, Bs);
+    __syncthreads();
+    if (k0 + kSchurK < S.nc) {
+      const int K2 = min(kSchurK, S.nc - k0 - kSchurK);
+      load(na, Ap + (int64_t)(k0 + kSchurK) * ldp, hI, K2, va);
+      load(nb, Bp + (int64_t)(k0 + kSchurK) * ldp, hJ, K2, vb);
+    }
+    if (live) {
+      for (int ks = 0; ks < K; ks += 4) {   // columns past K are zero in both operands
+        T af[4], bf[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = Bs[ks + kl][qc + 16 * b + il];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = As[ks + kl][qr + 16 * a + il];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int a = 0; a < 4; ++a) acc[b][a] = Mfma<T>::op(bf[b], af[a], acc[b][a]);
+      }
+    }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = qr + 16 * a + lane % 16;
+      if (r >= hI) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = qc + 16 * b + Mfma<T>::drow(lane, q);
+        if (c < hJ) C[r + (int64_t)c * ldc] -= acc[b][a][q];
+      }
+    }
+}
+
 // Inverse phase, column t of supernode s: L11 column t (rows t..nc-1) and L21 column t go to the
 // level scratch, and the panel's own part of column t becomes column t of the block-diagonal
 // start of X = inv(L11): the inverse of the diagonal tile holding t, zero elsewhere.
@@ -676,6 +791,9 @@ void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t 
       break;
     case kSchur:
       schur_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd);
+      break;
+    case kSchur2:
+      schur2_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd);
       break;
     case kInvPrep:
       invprep_kernel<T><<<(unsigned)((count + 3) / 4), 256, 0, st>>>(D, task_off, count, panel, dinv, lcopy);

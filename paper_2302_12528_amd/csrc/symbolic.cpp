@@ -460,8 +460,18 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
     for (int32_t q = q0; q < q1; ++q) {
       int s = S.level_sn[q];
       int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+      if (rt - np >= kSchurWideTiles) continue;
       for (int J = np; J < rt; ++J)
         for (int I = J; I < rt; ++I) push(s, I, J, 0);
+    }
+    end_step();
+    begin_step(kSchur2);
+    for (int32_t q = q0; q < q1; ++q) {
+      int s = S.level_sn[q];
+      int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+      if (rt - np < kSchurWideTiles) continue;
+      for (int J = np; J < rt; J += 2)
+        for (int I = J; I < rt; I += 2) push(s, I, J, 0);
     }
     end_step();
     // inverse phase: P_s = [inv(L11); L21 inv(L11)].  X = inv(L11) by recursive doubling over
@@ -856,6 +866,8 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
       const bool plevel = (st.kind == kInvT1 || st.kind == kInvX21);   // p holds the recursion level
       if (p < 0 || (!plevel && p >= np) || I < 0 || I >= rt || J < 0 || J >= rt) return "task tile";
       if (st.kind == kSchur && !(J >= np && I >= J)) return "Schur tile order";
+      if (st.kind == kSchur2 && !(J >= np && I >= J && (I - np) % 2 == 0 && (J - np) % 2 == 0 && rt - np >= kSchurWideTiles))
+        return "Schur block order";
       if (st.kind == kUpdate && !((J == p + 1 && J < np && I >= J) || (I == p && J == p))) return "update tile order";
       if (st.kind == kUpdateRest && !(J > p + 1 && J < np && I >= J)) return "update tile order";
       if ((st.kind == kPotrf || st.kind == kTrsm || st.kind == kInvScale) && !(J == p && I >= p))

@@ -90,7 +90,10 @@ struct FactorPlan {
 // kInvPrep / kInvT1 / kInvX21 / kInvP21: the inverse phase P_s = [inv(L11); L21 inv(L11)] (kInvScale and
 // kInvUpdate: the column sweep it replaces, no longer planned).
 enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6,
-                kSchur = 7, kInvT1 = 8, kInvX21 = 9, kInvP21 = 10, kUpdateRest = 11 };
+                kSchur = 7, kInvT1 = 8, kInvX21 = 9, kInvP21 = 10, kUpdateRest = 11, kSchur2 = 12 };
+// kSchur2: the Schur complement of fronts with at least kSchurWideTiles tile rows below the panel, on
+// 128 x 128 blocks (task (s, I, J) with I - np and J - np even: tiles I, I + 1 by J, J + 1)
+constexpr int kSchurWideTiles = 8;
 void build_factor_plan(const Symbolic& S, FactorPlan& plan);
 
 // Trisolve work lists.  Each output tile (64 rows of P_s for the forward sweep, 64
