@@ -258,3 +258,111 @@ def test_planted_mistake_qr_transpose_is_caught():
     W = rng.standard_normal((500, 12))
     Q, R = mixed_qr.mixed_qr(W)
     assert np.linalg.norm(W - Q @ R.T) / np.linalg.norm(W) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 (block PINVIT, mixed precision) and the sparse preconditioner of section 5.1.
+# ---------------------------------------------------------------------------
+
+def _cfg1_closed(count):
+    return closed_form_2d(32, count)
+
+
+def test_mixed_pinvit_reaches_closed_form_cfg1():
+    # Algorithm 1 with the FP32 sparse factor of section 5.1 on the 32 x 32 Laplacian: the four
+    # smallest eigenvalues in closed form (4 sin^2(i pi/66) + 4 sin^2(j pi/66)) to 1e-10.
+    p = synth.cfg1()
+    na = dense.norm2(p.A)
+    T = precond.Preconditioner(p.A, "fp32")
+    th, X, it = pinvit.mixed_pinvit(p.A, p.X0, p.k, p.tol, T, na, maxit=300)
+    ref = _cfg1_closed(4)
+    assert it < 300
+    assert np.max(np.abs(th - ref) / ref) <= 1e-10
+    res = ol.residual_norms(p.A, X, th, na)
+    assert np.all(res <= p.tol)
+    assert np.max(np.abs(X.T @ X - np.eye(p.k))) < 1e-12
+
+
+def test_mixed_pinvit_theorem1_rate_with_measured_gamma():
+    # Theorem 1 (k = 1): with gamma = ||I - A^{1/2} T A^{1/2}||_2 measured for the FP32 factor, every step
+    # with rho in [lambda_1, lambda_2) contracts (rho - lambda_1)/(lambda_2 - rho) by at most
+    # (gamma + (1 - gamma) lambda_1/lambda_2)^2.  The Rayleigh quotient of iteration j is the theta that
+    # mixed_pinvit returns when stopped after j iterations (the iteration is deterministic).
+    p = synth.cfg1()
+    na = dense.norm2(p.A)
+    T = precond.Preconditioner(p.A, "fp32")
+    gamma = precond.preconditioner_gamma(p.A.toarray(), "fp32")
+    assert 0 < gamma < 1e-4
+    l1, l2 = _cfg1_closed(2)
+    q2 = pinvit.rate_bound(gamma, l1, l2)
+    x0 = p.X0[:, :1]
+    rhos = [pinvit.mixed_pinvit(p.A, x0, 1, 1e-300, T, na, maxit=j)[0][0] for j in range(1, 12)]
+    checked = 0
+    for a, b in zip(rhos[:-1], rhos[1:]):
+        ra, rb = pinvit.ratio(a, l1, l2), pinvit.ratio(b, l1, l2)
+        if l1 <= a < l2 and ra > 1e-6:
+            assert rb <= q2 * ra * (1 + 1e-6)
+            checked += 1
+    assert checked >= 4
+    # the bound is sharp for an almost exact preconditioner: the last contractions approach it
+    assert rb / ra > 0.95 * q2
+
+
+def test_planted_mistake_pinvit_update_sign_is_caught():
+    # X~ = X + W instead of X - W: the closed-form pin above fails
+    p = synth.cfg1()
+    na = dense.norm2(p.A)
+    T = precond.Preconditioner(p.A, "fp32")
+    th, _, it = pinvit.mixed_pinvit(p.A, p.X0, p.k, p.tol, lambda r: -T(r), na, maxit=100)
+    ref = _cfg1_closed(4)
+    assert it == 100 or np.max(np.abs(th - ref) / ref) > 1e-3
+
+
+def _sparse_case(N):
+    A = synth.cfg2(N=N).A
+    lam = np.linalg.eigvalsh(A.toarray())
+    R = np.random.default_rng(3).standard_normal((A.shape[0], 8))
+    return A, lam[-1], lam[-1] / lam[0], R
+
+
+@pytest.mark.parametrize("N", [12, 16])
+def test_sparse_preconditioner_solve_accuracy(N):
+    # The sparse branch (SuperLU, no pivoting, minimum-degree order) against the mathematics of a
+    # backward-stable solve: ||A W - R||_F <= 10 u ||A||_2 ||W||_F, and against a second, independent
+    # library route (dense LAPACK Cholesky in FP64): every column within kappa u of A^{-1} R, for the
+    # FP64 factor with u = u64 and the FP32 factor (lower(R), FP32 solves, working(W)) with u = u32.
+    import scipy.linalg as sla
+    A, na, kappa, R = _sparse_case(N)
+    Wex = sla.cho_solve(sla.cho_factor(A.toarray()), R)
+    for prec, u in (("fp64", np.finfo(np.float64).eps / 2), ("fp32", np.finfo(np.float32).eps / 2)):
+        W = precond.Preconditioner(A, prec)(R)
+        assert W.dtype == np.float64
+        assert np.linalg.norm(A @ W - R) <= 10 * u * na * np.linalg.norm(W), prec
+        col = np.linalg.norm(W - Wex, axis=0) / np.linalg.norm(Wex, axis=0)
+        assert col.max() <= kappa * u, prec
+        if prec == "fp32":
+            # and not better than FP32 allows: the factor really is held in single precision
+            assert col.max() >= 1e-3 * kappa * u
+
+
+def test_planted_mistake_preconditioner_one_triangular_solve_is_caught():
+    # applying only the lower triangular solve (the SuperLU L factor) is far outside the pin
+    import scipy.sparse.linalg as spla
+    A, na, kappa, R = _sparse_case(12)
+    Pc = precond.Preconditioner(A, "fp64")
+    lu = Pc.lu
+    Wbad = np.zeros_like(R)
+    Wbad[lu.perm_c] = spla.spsolve_triangular(lu.L.tocsr(), R[lu.perm_r], lower=True)
+    u = np.finfo(np.float64).eps / 2
+    assert np.linalg.norm(A @ Wbad - R) > 1e6 * 10 * u * na * np.linalg.norm(Wbad)
+
+
+def test_planted_mistake_preconditioner_half_precision_is_caught():
+    # lower(R) rounded to half precision instead of single: the FP32 branch's kappa u32 pin fails
+    import scipy.linalg as sla
+    A, na, kappa, R = _sparse_case(12)
+    Wex = sla.cho_solve(sla.cho_factor(A.toarray()), R)
+    Pc = precond.Preconditioner(A, "fp32")
+    Wbad = Pc(R.astype(np.float16).astype(np.float64))
+    col = np.linalg.norm(Wbad - Wex, axis=0) / np.linalg.norm(Wex, axis=0)
+    assert col.max() > kappa * np.finfo(np.float32).eps / 2
