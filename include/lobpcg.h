@@ -96,6 +96,14 @@ typedef struct {
   int32_t flags;             /* bit field of LOBPCG_FLAG_* (default 0) */
   double norm_a;             /* > 0: use this ||A||_2 instead of the section 5.1 estimate */
   double eig_tol;            /* > 0: also require ||r_j||^2 <= eig_tol |theta_j| (theta_m - theta_j) */
+  /* Launch plan of the triangular solves (section 5.1's two solves): 0 = automatic (the whole
+   * supernodal tree in one workgroup when its panels are small, otherwise one launch sequence per
+   * level), -1 = one launch sequence per level always, L > 0 = the bottom L levels as subtrees of
+   * one workgroup each.  Results agree to rounding; the choice only moves work between kernels. */
+  int32_t subtree_levels;
+  /* Factorization: fronts with at least this many 64-row tiles below their diagonal block apply
+   * the Schur complement on 128 x 128 blocks (0 = default, 8).  Same arithmetic per entry. */
+  int32_t schur_wide_tiles;
 } lobpcg_options;
 
 typedef struct {

@@ -50,6 +50,9 @@ double now_s() {
 
 int pad_m(int m) { return m <= 8 ? 8 : m <= 16 ? 16 : m <= 32 ? 32 : 64; }
 
+// lobpcg_options.subtree_levels (0 automatic, -1 none, L > 0) as build_solve_plan's argument (-1 automatic)
+int plan_sub_levels(const lobpcg_options& o) { return o.subtree_levels == 0 ? -1 : o.subtree_levels < 0 ? 0 : o.subtree_levels; }
+
 constexpr int64_t kMaxBufferBytes = ((int64_t)1 << 31) - 64;   // buffer-resource extent limit of the solve kernels
 
 // Host side of an instance segmentation.
@@ -160,6 +163,8 @@ struct lobpcg_ctx_s {
   int32_t *d_prow = nullptr, *d_pcol = nullptr, *d_vmap = nullptr, *d_perm = nullptr, *d_iperm = nullptr;
   double *d_aval_orig = nullptr, *d_aval = nullptr, *d_dense = nullptr;
   int64_t ld_dense = 0;
+  double* d_mmpart = nullptr;   // dense A: partial products of the split reduction ranges of A X
+  int64_t mmpart_elems = 0;
   // factor (T = float or double)
   void *panel = nullptr, *upd = nullptr, *dinv = nullptr, *lcopy = nullptr;
   int* d_flag = nullptr;      // factor breakdown
@@ -370,7 +375,7 @@ lobpcg_status check_launch(const char* where) {
 // Y = A X in the permuted basis (the whole union)
 void apply_a(lobpcg_ctx c, const double* X, int64_t ldx, double* Y, int64_t ldy, int cols) {
   if (c->dense)
-    launch_dense_mm(c->d_dense, c->ld_dense, c->n, X, ldx, Y, ldy, cols, c->st);
+    launch_dense_mm(c->d_dense, c->ld_dense, c->n, X, ldx, Y, ldy, cols, c->d_mmpart, c->mmpart_elems, c->st);
   else
     launch_spmm_csr(c->d_prow, c->d_pcol, c->d_aval, c->n, X, ldx, Y, ldy, cols, c->st);
 }
@@ -566,7 +571,10 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
     if (opt.norm_a < 0 || !std::isfinite(opt.norm_a)) return fail(LOBPCG_ERR_INVALID_ARG, "norm_a");
     if (opt.eig_tol < 0 || !std::isfinite(opt.eig_tol)) return fail(LOBPCG_ERR_INVALID_ARG, "eig_tol");
     if (opt.flags & ~(LOBPCG_FLAG_GRAPH | LOBPCG_FLAG_AUTOTUNE)) return fail(LOBPCG_ERR_INVALID_ARG, "unknown flags");
+    if (opt.subtree_levels < -1) return fail(LOBPCG_ERR_INVALID_ARG, "subtree_levels must be >= -1");
+    if (opt.schur_wide_tiles < 0) return fail(LOBPCG_ERR_INVALID_ARG, "schur_wide_tiles must be >= 0");
   }
+  if (opt.schur_wide_tiles == 0) opt.schur_wide_tiles = kSchurWideTiles;
   auto c = new lobpcg_ctx_s();
   lobpcg_ctx_s& C = *c;
   C.st = static_cast<hipStream_t>(hip_stream);
@@ -634,9 +642,9 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
     delete c;
     return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
   }
-  build_factor_plan(C.S, C.FP);
+  build_factor_plan(C.S, C.FP, opt.schur_wide_tiles);
   C.split_target = default_split_target(factor_precision == LOBPCG_FP32 ? 4 : 8);
-  build_solve_plan(C.S, 64, C.split_target, C.SP);
+  build_solve_plan(C.S, 64, C.split_target, C.SP, plan_sub_levels(opt));
   std::vector<int32_t> prow, pcol, vmap, apos;
   if (!C.dense) {
     permute_pattern(C.S, rowptr, colind, prow, pcol, vmap);
@@ -707,6 +715,8 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
     D.dense = C.d_dense;
     D.ld_dense = n;
     D.is_dense = 1;
+    C.mmpart_elems = dense_mm_scratch(n);
+    SETUP_TRY(C.alloc(C.d_mmpart, C.mmpart_elems));
   } else {
     SETUP_TRY(upload(c, C.d_prow, prow));
     SETUP_TRY(upload(c, C.d_pcol, pcol));
@@ -904,7 +914,7 @@ lobpcg_status apply_chunk_rows(lobpcg_ctx c, int64_t rpc) {
 
 lobpcg_status apply_split_target(lobpcg_ctx c, int target) {
   c->split_target = target;
-  build_solve_plan(c->S, 64, target, c->SP);
+  build_solve_plan(c->S, 64, target, c->SP, plan_sub_levels(c->opt));
   const std::string err = verify_solve_plan(c->S, c->SP);
   if (!err.empty()) return fail(LOBPCG_ERR_INVALID_ARG, "solve plan failed verification: " + err);
   ST_TRY(install_solve_plan(c));

@@ -60,9 +60,11 @@ int tsqr_upper_rows_per_block(int c, int elem_bytes);
 // Y = A X for permuted CSR A; X, Y n x c row-major (ld), any c >= 1.
 void launch_spmm_csr(const int32_t* rowptr, const int32_t* colind, const double* val, int64_t n,
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int c, hipStream_t st);
-// Y = A X for dense row-major A (n x n, lda).
+// Y = A X for dense row-major A (n x n, lda) on the FP64 matrix cores; part (part_elems doubles) holds
+// the partial products of split reduction ranges (dense_mm_scratch(n) covers every c <= 64 fully).
+int64_t dense_mm_scratch(int64_t n);
 void launch_dense_mm(const double* A, int64_t lda, int64_t n, const double* X, int64_t ldx, double* Y,
-                     int64_t ldy, int c, hipStream_t st);
+                     int64_t ldy, int c, double* part, int64_t part_elems, hipStream_t st);
 // dst[i*ldd + j] = src[(idx[i] - base)*lds + j], i < nrows, j < c (idx NULL = identity)
 void launch_gather_rows(const double* src, int64_t lds, const int32_t* idx, int64_t base, double* dst, int64_t ldd,
                         int64_t nrows, int c, hipStream_t st);

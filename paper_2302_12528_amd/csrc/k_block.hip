@@ -3,12 +3,14 @@
 // the permutation, value gathers, start-block generation).  Blocks are
 // row-major so that one row of an n x c block is contiguous.
 #include "common.hpp"
+#include "mfma.hpp"
 
 namespace lobpcg {
 
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kMmMaxSplits = 8;   // reduction ranges of the dense product
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -75,67 +77,122 @@ __global__ void __launch_bounds__(kThreads) spmm_csr2_kernel(const int32_t* __re
 }
 
 // ----------------------------------------------------------------------------
-// 64 x 64 output tile of C = alpha * A B + beta * C with A (rows x K) and B (K x cols)
-// both row-major.  256 threads, 4 x 4 outputs each, K staged through LDS 16 at a time.
+// Dense Y = A X on the FP64 matrix cores (dense A, Algorithm 3 line 13).  A workgroup of 8 waves
+// computes a 128 x 64 output tile over one range of the reduction index (gridDim.z ranges of kspan):
+// wave w owns rows 16 w .. 16 w + 15 as four 16 x 16 blocks accumulated by v_mfma_f64_16x16x4f64.
+// Chunks of 32 reduction indices of the A rows ([row][k], row-major as A) and of the X rows
+// ([k][col]) pass through LDS; the next chunk is loaded into registers (16-byte loads) while the
+// current one is multiplied.  With one range the tile is written to Y, otherwise to part[z] and
+// dense_mm_reduce_kernel adds the ranges in a fixed order.
+// LDS strides: A rows of 34 doubles (lanes i, g of an operand read fall on banks 4 i + 2 g, all
+// distinct over a half wave), X rows of 80 doubles (the two k rows of a half wave 128 bytes apart).
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) gemm_nn_kernel(const double* A, int64_t lda,
-                                                           const double* __restrict__ B, int64_t ldb,
-                                                           double* C, int64_t ldc, int64_t rows, int K,
-                                                           int cols, double alpha, double beta) {
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][64];
-  const int t = threadIdx.x;
-  const int tx = t % 16, ty = t / 16;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
+constexpr int kMmRows = 128, kMmK = 32, kMmLdA = kMmK + 2, kMmLdX = 64 + 16, kMmThreads = 512;
+
+template <bool VEC>
+__global__ void __launch_bounds__(kMmThreads) dense_mm_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
+                                                              const double* __restrict__ X, int64_t ldx,
+                                                              double* __restrict__ Y, int64_t ldy, int c,
+                                                              int64_t kspan, double* __restrict__ part) {
+  typedef Mfma<double> MF;
+  typedef MF::v4 V4;
+  __shared__ __align__(16) double As[kMmRows][kMmLdA];
+  __shared__ __align__(16) double Xs[kMmK][kMmLdX];
+  const int t = threadIdx.x, lane = t % 64, w = t / 64, i = lane % 16, g = lane / 16;
+  const int64_t r0 = (int64_t)blockIdx.x * kMmRows;
   const int c0 = blockIdx.y * 64;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  const int lr = t / 4, lk = (t % 4) * 4;      // A loader: row lr, k lk..lk+3
-  const int bk = t / 16, bc = (t % 16) * 4;    // B loader: k bk, cols bc..bc+3
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  const int64_t kb = (int64_t)blockIdx.z * kspan;
+  const int64_t ke = min(n, kb + kspan);
+  // loaders: A pair e = t + 512 q (q < 4) is row e / 16, reduction pair e % 16; X pair e = t + 512 q
+  // (q < 2) is reduction row e / 32, column pair e % 32
+  double2 ra[4], rx[2];
+  auto load = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t r = r0 + lr;
-      const int k = k0 + lk + q;
-      As[lk + q][lr] = (r < rows && k < K) ? A[r * lda + k] : 0.0;
+      const int e = t + kMmThreads * q;
+      const int64_t r = r0 + e / 16, k = k0 + 2 * (e % 16);
+      double2 v = make_double2(0.0, 0.0);
+      if (r < n) {
+        const double* src = A + r * lda + k;
+        if (VEC && k + 1 < ke) {
+          v = *reinterpret_cast<const double2*>(src);
+        } else {
+          if (k < ke) v.x = src[0];
+          if (k + 1 < ke) v.y = src[1];
+        }
+      }
+      ra[q] = v;
     }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = t + kMmThreads * q;
+      const int64_t k = k0 + e / 32;
+      const int col = c0 + 2 * (e % 32);
+      double2 v = make_double2(0.0, 0.0);
+      if (k < ke) {
+        const double* src = X + k * ldx + col;
+        if (VEC && col + 1 < c) {
+          v = *reinterpret_cast<const double2*>(src);
+        } else {
+          if (col < c) v.x = src[0];
+          if (col + 1 < c) v.y = src[1];
+        }
+      }
+      rx[q] = v;
+    }
+  };
+  V4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = V4{0, 0, 0, 0};
+  if (kb < ke) load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += kMmK) {
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int k = k0 + bk;
-      const int cc = c0 + bc + q;
-      Bs[bk][bc + q] = (k < K && cc < cols) ? B[(int64_t)k * ldb + cc] : 0.0;
+      const int e = t + kMmThreads * q;
+      *reinterpret_cast<double2*>(&As[e / 16][2 * (e % 16)]) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = t + kMmThreads * q;
+      *reinterpret_cast<double2*>(&Xs[e / 32][2 * (e % 32)]) = rx[q];
     }
     __syncthreads();
+    if (k0 + kMmK < ke) load(k0 + kMmK);
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      double a[4], b[4];
+    for (int kk = 0; kk < kMmK; kk += 4) {
+      const double a = As[16 * w + i][kk + g];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[k][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t r = r0 + ty + 16 * i;
-    if (r >= rows) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cc = c0 + tx + 16 * j;
-      if (cc >= cols) continue;
-      double v = alpha * acc[i][j];
-      if (beta != 0.0) v = fma(beta, C[r * ldc + cc], v);
-      C[r * ldc + cc] = v;
+      for (int cb = 0; cb < 4; ++cb) acc[cb] = MF::op(a, Xs[kk + g][16 * cb + i], acc[cb]);
     }
   }
+  const int cpad = gridDim.y * 64;
+  double* P = part ? part + (int64_t)blockIdx.z * n * cpad : nullptr;
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = r0 + 16 * w + MF::drow(lane, q);
+      const int col = c0 + 16 * cb + i;
+      if (r >= n || col >= c) continue;
+      if (P)
+        P[r * cpad + col] = acc[cb][q];
+      else
+        Y[r * ldy + col] = acc[cb][q];
+    }
+}
+
+// Y(r, col) = sum over z = 0 .. nz - 1, in order, of part[z](r, col)
+__global__ void __launch_bounds__(kThreads) dense_mm_reduce_kernel(const double* __restrict__ part, int nz,
+                                                                   int64_t n, int c, int cpad,
+                                                                   double* __restrict__ Y, int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= n * c) return;
+  const int64_t r = e / c;
+  const int col = (int)(e % c);
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += part[((int64_t)z * n + r) * cpad + col];
+  Y[r * ldy + col] = s;
 }
 
 __global__ void gather_rows_kernel(const double* __restrict__ src, int64_t lds, const int32_t* __restrict__ idx,
@@ -246,11 +303,28 @@ void launch_spmm_csr(const int32_t* rowptr, const int32_t* colind, const double*
   }
 }
 
+int64_t dense_mm_scratch(int64_t n) { return (int64_t)kMmMaxSplits * n * 64; }
+
 void launch_dense_mm(const double* A, int64_t lda, int64_t n, const double* X, int64_t ldx, double* Y,
-                     int64_t ldy, int c, hipStream_t st) {
+                     int64_t ldy, int c, double* part, int64_t part_elems, hipStream_t st) {
   if (n <= 0 || c <= 0) return;
-  dim3 g(ceil_div(n, 64), ceil_div(c, 64));
-  gemm_nn_kernel<<<g, kThreads, 0, st>>>(A, lda, X, ldx, Y, ldy, n, (int)n, c, 1.0, 0.0);
+  const int rt = ceil_div(n, kMmRows), ct = ceil_div(c, 64);
+  // split the reduction range until about 512 workgroups are in flight (two per compute unit), as far
+  // as the partial products fit in part
+  int64_t nz = 1;
+  while (nz < kMmMaxSplits && (int64_t)rt * ct * nz < 512 && 2 * nz * n * ct * 64 <= part_elems &&
+         n >= 2 * nz * kMmK)
+    nz *= 2;
+  const int64_t kspan = (int64_t)ceil_div(ceil_div(n, nz), kMmK) * kMmK;
+  nz = ceil_div(n, kspan);
+  const bool vec = ((lda | ldx) % 2 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)X % 16 == 0);
+  double* P = (nz > 1) ? part : nullptr;
+  dim3 g(rt, ct, (unsigned)nz);
+  if (vec)
+    dense_mm_kernel<true><<<g, kMmThreads, 0, st>>>(A, lda, n, X, ldx, Y, ldy, c, kspan, P);
+  else
+    dense_mm_kernel<false><<<g, kMmThreads, 0, st>>>(A, lda, n, X, ldx, Y, ldy, c, kspan, P);
+  if (P) dense_mm_reduce_kernel<<<grid1(n * c), kThreads, 0, st>>>(P, (int)nz, n, c, ct * 64, Y, ldy);
 }
 
 void launch_gather_rows(const double* src, int64_t lds, const int32_t* idx, int64_t base, double* dst, int64_t ldd,

@@ -385,8 +385,10 @@ void assembly_positions(const Symbolic& S, const std::vector<int32_t>& prow,
   }
 }
 
-void build_factor_plan(const Symbolic& S, FactorPlan& P) {
+void build_factor_plan(const Symbolic& S, FactorPlan& P, int schur_wide_tiles) {
   P = FactorPlan();
+  P.schur_wide_tiles = std::max(1, schur_wide_tiles);
+  const int wide = P.schur_wide_tiles;
   auto push = [&](int s, int I, int J, int p) {
     P.tasks.push_back(s); P.tasks.push_back(I); P.tasks.push_back(J); P.tasks.push_back(p);
   };
@@ -460,7 +462,7 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
     for (int32_t q = q0; q < q1; ++q) {
       int s = S.level_sn[q];
       int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
-      if (rt - np >= kSchurWideTiles) continue;
+      if (rt - np >= wide) continue;
       for (int J = np; J < rt; ++J)
         for (int I = J; I < rt; ++I) push(s, I, J, 0);
     }
@@ -469,7 +471,7 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P) {
     for (int32_t q = q0; q < q1; ++q) {
       int s = S.level_sn[q];
       int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
-      if (rt - np < kSchurWideTiles) continue;
+      if (rt - np < wide) continue;
       for (int J = np; J < rt; J += 2)
         for (int I = J; I < rt; I += 2) push(s, I, J, 0);
     }
@@ -866,7 +868,7 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
       const bool plevel = (st.kind == kInvT1 || st.kind == kInvX21);   // p holds the recursion level
       if (p < 0 || (!plevel && p >= np) || I < 0 || I >= rt || J < 0 || J >= rt) return "task tile";
       if (st.kind == kSchur && !(J >= np && I >= J)) return "Schur tile order";
-      if (st.kind == kSchur2 && !(J >= np && I >= J && (I - np) % 2 == 0 && (J - np) % 2 == 0 && rt - np >= kSchurWideTiles))
+      if (st.kind == kSchur2 && !(J >= np && I >= J && (I - np) % 2 == 0 && (J - np) % 2 == 0 && rt - np >= F.schur_wide_tiles))
         return "Schur block order";
       if (st.kind == kUpdate && !((J == p + 1 && J < np && I >= J) || (I == p && J == p))) return "update tile order";
       if (st.kind == kUpdateRest && !(J > p + 1 && J < np && I >= J)) return "update tile order";

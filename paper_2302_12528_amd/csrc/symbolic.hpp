@@ -82,6 +82,7 @@ struct FactorPlan {
   std::vector<int32_t> asm_items;    // 2 ints (s, t) per assembly work item, grouped per level
   std::vector<int64_t> asm_level_off;  // nlevels+1
   std::vector<int32_t> level_max_nr;   // per level: the largest front (rows) of the level
+  int schur_wide_tiles = 8;            // fronts with at least this many tile rows below the panel use kSchur2
 };
 // kPotrf: Cholesky of diagonal tile p with the trsm of the tiles below it (kTrsm: the trsm alone);
 // kUpdate: trailing update of the next panel column (p + 1) and the move of L_pp into the panel;
@@ -91,10 +92,10 @@ struct FactorPlan {
 // kInvUpdate: the column sweep it replaces, no longer planned).
 enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6,
                 kSchur = 7, kInvT1 = 8, kInvX21 = 9, kInvP21 = 10, kUpdateRest = 11, kSchur2 = 12 };
-// kSchur2: the Schur complement of fronts with at least kSchurWideTiles tile rows below the panel, on
+// kSchur2: the Schur complement of fronts with at least schur_wide_tiles tile rows below the panel, on
 // 128 x 128 blocks (task (s, I, J) with I - np and J - np even: tiles I, I + 1 by J, J + 1)
 constexpr int kSchurWideTiles = 8;
-void build_factor_plan(const Symbolic& S, FactorPlan& plan);
+void build_factor_plan(const Symbolic& S, FactorPlan& plan, int schur_wide_tiles = kSchurWideTiles);
 
 // Trisolve work lists.  Each output tile (64 rows of P_s for the forward sweep, 64
 // own columns for the backward sweep) is one item, or, on levels with fewer tiles

@@ -38,7 +38,8 @@ class Matrix(ct.Structure):
 
 class Options(ct.Structure):
     _fields_ = [("leaf_size", ct.c_int32), ("stop_rule", ct.c_int32), ("qr_lower", ct.c_int32),
-                ("flags", ct.c_int32), ("norm_a", ct.c_double), ("eig_tol", ct.c_double)]
+                ("flags", ct.c_int32), ("norm_a", ct.c_double), ("eig_tol", ct.c_double),
+                ("subtree_levels", ct.c_int32), ("schur_wide_tiles", ct.c_int32)]
 
 
 class Info(ct.Structure):

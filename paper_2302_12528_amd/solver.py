@@ -86,12 +86,15 @@ class Solver:
 
     def __init__(self, A, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
                  grid=(0, 0, 0), leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
-                 norm_a: float = 0.0, eig_tol: float = 0.0, graph: bool = False, autotune: bool = False):
+                 norm_a: float = 0.0, eig_tol: float = 0.0, graph: bool = False, autotune: bool = False,
+                 subtree_levels: int = 0, schur_wide_tiles: int = 0):
         self.lib = nv.load()
         _torch()
         M, keep = make_matrix(A, grid)
         opt = nv.Options()
         opt.leaf_size = leaf_size
+        opt.subtree_levels = subtree_levels
+        opt.schur_wide_tiles = schur_wide_tiles
         opt.stop_rule = _STOP[stop]
         opt.qr_lower = 1 if qr_lower else 0
         opt.norm_a = norm_a

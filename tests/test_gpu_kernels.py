@@ -121,7 +121,7 @@ def _solver(A, k, m, prec, grid=(0, 0, 0), **kw):
     return pk.Solver(A, k, m, 1e-10, factor_precision=prec, grid=grid, **kw)
 
 
-@pytest.mark.parametrize("case", ["laplace2d_32", "diffusion3d_12", "dense_300"])
+@pytest.mark.parametrize("case", ["laplace2d_32", "diffusion3d_12", "dense_300", "dense_1031", "dense_4096"])
 def test_apply_a(torch_cuda, case):
     print(f"apply_a {case}", flush=True)
     if case == "laplace2d_32":
@@ -129,12 +129,12 @@ def test_apply_a(torch_cuda, case):
     elif case == "diffusion3d_12":
         A, grid = synth.cfg2(N=12).A, (12, 12, 12)
     else:
-        A, grid = synth.dense_spd(300)[0], (0, 0, 0)
+        A, grid = synth.dense_spd(int(case.split("_")[1]))[0], (0, 0, 0)
     s = _solver(A, 2, 4, "fp64", grid)
     perm = s.permutation()
     Ap = permuted(A, perm)
     rng = np.random.default_rng(1)
-    for c in (1, 5, 8, 16, 33, 64, 96):
+    for c in (1, 5, 8, 16, 32, 33, 48, 64, 96):
         X = rng.standard_normal((A.shape[0], c))
         Y = _np(s.apply_a(X))
         ref = Ap @ X
@@ -144,30 +144,67 @@ def test_apply_a(torch_cuda, case):
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["laplace2d_32", "diffusion3d_16", "diffusion3d_16_graph", "dense_500",
-                                  "laplace2d_33x31"])
-def test_apply_precond(torch_cuda, prec, case):
-    print(f"precond {case} {prec}", flush=True)
+_KAPPA = {}
+
+
+def _precond_case(case):
     if case == "laplace2d_32":
-        A, grid, m = synth.laplace2d(32), (32, 32, 1), 8
-    elif case == "diffusion3d_16":
-        A, grid, m = synth.cfg2(N=16).A, (16, 16, 16), 32
-    elif case == "diffusion3d_16_graph":
-        A, grid, m = synth.cfg2(N=16).A, (0, 0, 0), 16
-    elif case == "laplace2d_33x31":
-        L1 = synth.laplace2d(33)
-        A, grid, m = L1, (0, 0, 0), 13
-    else:
-        A, grid, m = synth.dense_spd(500, seed=4, hi=1e3)[0], (0, 0, 0), 24
-    s = _solver(A, 1, m, prec, grid)
+        return synth.laplace2d(32), (32, 32, 1), 8
+    if case == "diffusion3d_16":
+        return synth.cfg2(N=16).A, (16, 16, 16), 32
+    if case == "diffusion3d_16_graph":
+        return synth.cfg2(N=16).A, (0, 0, 0), 16
+    if case == "diffusion3d_32":
+        return synth.cfg2(N=32).A, (32, 32, 32), 32
+    if case == "laplace2d_33x31":
+        return synth.laplace2d(33), (0, 0, 0), 13
+    return synth.dense_spd(500, seed=4, hi=1e3)[0], (0, 0, 0), 24
+
+
+def _kappa(case, A):
+    """2-norm condition number of A (extreme eigenvalues by Lanczos, the smallest by shift-invert)."""
+    if case not in _KAPPA:
+        import scipy.sparse.linalg as spla
+        if sp.issparse(A):
+            lmax = spla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
+            lmin = spla.eigsh(A, k=1, sigma=0, which="LM", return_eigenvectors=False)[0]
+        else:
+            lam = np.linalg.eigvalsh(A)
+            lmin, lmax = lam[0], lam[-1]
+        _KAPPA[case] = lmax / lmin
+    return _KAPPA[case]
+
+
+# Launch plans of the preconditioner: "auto" (what setup picks: one workgroup for the whole tree when the
+# panels are small, else one launch sequence per level), "levels" (the per-level gather / tile / split /
+# finalize sweeps that large factors take, forced on small ones) and "wide" (per-level sweeps and a
+# factor whose every Schur complement runs on 128 x 128 blocks).
+_PLANS = {"auto": {}, "levels": {"subtree_levels": -1}, "wide": {"subtree_levels": -1, "schur_wide_tiles": 1}}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case,plan", [("laplace2d_32", "auto"), ("laplace2d_32", "levels"), ("laplace2d_32", "wide"),
+                                       ("diffusion3d_16", "auto"), ("diffusion3d_16", "levels"),
+                                       ("diffusion3d_16", "wide"), ("diffusion3d_16_graph", "auto"),
+                                       ("diffusion3d_16_graph", "levels"), ("dense_500", "auto"),
+                                       ("laplace2d_33x31", "auto"), ("laplace2d_33x31", "wide"),
+                                       ("diffusion3d_32", "auto")])
+def test_apply_precond(torch_cuda, prec, case, plan):
+    # Section 5.1's two triangular solves (Algorithm 3 lines 9-10) against the oracle's FP64 solve, column by
+    # column: an FP64 factor to 1e-9 relative; an FP32 factor within 4 kappa(A) u32 (a backward-stable
+    # Cholesky and solve in single precision; the oracle's own FP32 branch is pinned to the same bound).
+    print(f"precond {case} {plan} {prec}", flush=True)
+    A, grid, m = _precond_case(case)
+    s = _solver(A, 1, m, prec, grid, **_PLANS[plan])
     perm = s.permutation()
     Ap = permuted(A, perm)
     rng = np.random.default_rng(2)
     R = rng.standard_normal((A.shape[0], m))
     W = _np(s.apply_precond(R))
-    Wref = opc.Preconditioner(Ap, "fp64")(R)
-    err = np.linalg.norm(W - Wref) / np.linalg.norm(Wref)
-    tol = 1e-9 if prec == "fp64" else 5e-4
-    assert err < tol, err
     s.close()
+    Wref = opc.Preconditioner(Ap, "fp64")(R)
+    col = np.linalg.norm(W - Wref, axis=0) / np.linalg.norm(Wref, axis=0)
+    bound = 1e-9 if prec == "fp64" else 4 * _kappa(case, A) * U32
+    print(f"  max column error {col.max():.3e} (bound {bound:.3e})", flush=True)
+    assert np.all(np.isfinite(W))
+    assert col.max() <= bound, (col.max(), bound)
