@@ -248,6 +248,19 @@ lobpcg_status lobpcg_apply_precond(lobpcg_ctx ctx, const double* R, double* W);
 lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t c, int64_t ldw, int32_t lower_step1,
                               double* R, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): lobpcg_mixed_qr with the same arguments, kernels and
+ * results, whose scratch (plans, TSQR tree, R factors, Gram partial sums, breakdown flag) lives in
+ * one fixed device array of LOBPCG_NOALLOC_SCRATCH_BYTES per GPU that the library holds until the
+ * process ends; the call allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * The caller passes W and R as for lobpcg_mixed_qr.  Sizes whose scratch would exceed the array
+ * return INVALID_ARG before any work (n <= 262,144 fits for c <= 32, n <= 65,536 for c <= 64).
+ * Every call on one GPU uses that GPU's array and leaves it holding its own intermediates: calls
+ * that overlap on one GPU (two host threads, or two streams whose work overlaps) race. */
+#define LOBPCG_NOALLOC_SCRATCH_BYTES (32u << 20)
+lobpcg_status lobpcg_mixed_qr_noalloc(double* W, int64_t n, int32_t c, int64_t ldw, int32_t lower_step1,
+                                      double* R, void* hip_stream);
+
 /* G = X^T Y (device; X n x c1, Y n x c2, row-major; G c1 x c2 row-major),
  * deterministic two-stage reduction.  c1, c2 <= 256. */
 lobpcg_status lobpcg_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1408,6 +1409,46 @@ struct TempSeg {
 
 }  // namespace
 
+// ---- scratch of lobpcg_mixed_qr_noalloc ----
+// One fixed array per GPU (each device holds its own copy at its own address), held until the process
+// ends.  Host code never uses the name itself: its device address comes from hipGetSymbolAddress, once
+// per device, and is kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[LOBPCG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+lobpcg_status scratch_for_current_device(unsigned char*& out) {
+  out = nullptr;
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LOBPCG_ERR_INVALID_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(LOBPCG_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return LOBPCG_OK;
+}
+
+// Layout of a fixed buffer: 256-byte aligned pieces in order, as byte offsets.
+struct Carve {
+  int64_t used = 0;
+  int64_t take(int64_t bytes) {
+    const int64_t off = used;
+    used += (std::max<int64_t>(bytes, 1) + 255) & ~(int64_t)255;
+    return off;
+  }
+};
+
+}  // namespace
+
 extern "C" {
 
 const char* lobpcg_status_string(lobpcg_status s) {
@@ -1728,6 +1769,87 @@ lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t cc, int64_t ldw, int
   if (s == LOBPCG_OK && hipStreamSynchronize(st) != hipSuccess) s = fail(LOBPCG_ERR_HIP, "sync");
   if (s == LOBPCG_OK && h) s = fail(LOBPCG_ERR_ORTHO_BREAKDOWN, "Cholesky of V^T V failed");
   (void)hipStreamSynchronize(st);
+  return s;
+}
+
+lobpcg_status lobpcg_mixed_qr_noalloc(double* W, int64_t n, int32_t cc, int64_t ldw, int32_t lower_step1,
+                                      double* R, void* hip_stream) {
+  if (!W || n < 1 || cc < 1 || cc > 64 || ldw < cc || n < cc)
+    return fail(LOBPCG_ERR_INVALID_ARG, "bad arguments to lobpcg_mixed_qr_noalloc");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // host plans: the one-instance segmentation and the TSQR tree, as lobpcg_mixed_qr builds them
+  SegHost H;
+  build_segments(std::vector<int64_t>{0, n}, default_chunk_rows(n), H);
+  const int eb = lower_step1 ? 4 : 8;
+  TsqrHost th;
+  build_tsqr(std::vector<int64_t>{0, n}, cc, tsqr_rows_per_block(cc, eb), tsqr_upper_rows_per_block(cc, eb), th);
+  const int64_t nt = (int64_t)H.tile_inst.size(), nch = (int64_t)H.chunk_inst.size();
+  const int64_t c2 = (int64_t)cc * cc;
+  // layout of the scratch array (sizes first, so that too large a problem is rejected before any work)
+  Carve K;
+  const int64_t o_active = K.take(4), o_tile_inst = K.take(4 * nt), o_tile_r0 = K.take(8 * nt),
+                o_tile_rows = K.take(4 * nt), o_chunk_inst = K.take(4 * nch), o_chunk_r0 = K.take(8 * nch),
+                o_chunk_rows = K.take(4 * nch), o_chunk_off = K.take(8),
+                o_items = K.take(4 * (int64_t)th.items.size()), o_flag = K.take(16), o_Rl = K.take(8 * c2),
+                o_Gv = K.take(8 * c2), o_Lt = K.take(8 * c2), o_gp = K.take(8 * nch * c2),
+                o_ws = K.take(2 * th.half * eb);
+  if (K.used > (int64_t)LOBPCG_NOALLOC_SCRATCH_BYTES)
+    return fail(LOBPCG_ERR_INVALID_ARG, "lobpcg_mixed_qr_noalloc: n = " + std::to_string(n) + ", c = " +
+                                            std::to_string(cc) + " needs " + std::to_string(K.used) +
+                                            " bytes of scratch, more than the fixed " +
+                                            std::to_string((long long)LOBPCG_NOALLOC_SCRATCH_BYTES));
+  unsigned char* base = nullptr;
+  ST_TRY(scratch_for_current_device(base));
+  auto i32 = [&](int64_t off) { return reinterpret_cast<int32_t*>(base + off); };
+  auto i64 = [&](int64_t off) { return reinterpret_cast<int64_t*>(base + off); };
+  auto f64 = [&](int64_t off) { return reinterpret_cast<double*>(base + off); };
+  SegDev S{};
+  S.B = 1;
+  S.active = i32(o_active);
+  S.tile_inst = i32(o_tile_inst);
+  S.tile_r0 = i64(o_tile_r0);
+  S.tile_rows = i32(o_tile_rows);
+  S.ntiles = nt;
+  S.chunk_inst = i32(o_chunk_inst);
+  S.chunk_r0 = i64(o_chunk_r0);
+  S.chunk_rows = i32(o_chunk_rows);
+  S.nchunks = nch;
+  S.inst_chunk_off = i32(o_chunk_off);
+  TsqrPlanDev tp{};
+  tp.rb = th.rb;
+  tp.rbu = th.rbu;
+  tp.nlevels = (int)th.level_off.size() - 1;
+  tp.level_off = th.level_off.data();
+  tp.half = th.half;
+  tp.items = i32(o_items);
+  // the plans into the array (ordinary copies on the stream; the host vectors outlive them because the
+  // call synchronises the stream before it returns), the breakdown flag cleared by a kernel
+  const int32_t one = 1;
+  auto put = [&](const void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  HIP_TRY(put(S.active, &one, sizeof(one)));
+  HIP_TRY(put(S.tile_inst, H.tile_inst.data(), nt * sizeof(int32_t)));
+  HIP_TRY(put(S.tile_r0, H.tile_r0.data(), nt * sizeof(int64_t)));
+  HIP_TRY(put(S.tile_rows, H.tile_rows.data(), nt * sizeof(int32_t)));
+  HIP_TRY(put(S.chunk_inst, H.chunk_inst.data(), nch * sizeof(int32_t)));
+  HIP_TRY(put(S.chunk_r0, H.chunk_r0.data(), nch * sizeof(int64_t)));
+  HIP_TRY(put(S.chunk_rows, H.chunk_rows.data(), nch * sizeof(int32_t)));
+  HIP_TRY(put(S.inst_chunk_off, H.inst_chunk_off.data(), 2 * sizeof(int32_t)));
+  HIP_TRY(put(tp.items, th.items.data(), th.items.size() * sizeof(int32_t)));
+  int* dflag = i32(o_flag);
+  launch_fill_int(dflag, 0, 4, st);
+  if (lower_step1)
+    mixed_qr_seg<float>(st, S, tp, W, ldw, cc, base + o_ws, base + o_Rl, f64(o_Lt), f64(o_Gv), f64(o_gp), dflag, R);
+  else
+    mixed_qr_seg<double>(st, S, tp, W, ldw, cc, base + o_ws, base + o_Rl, f64(o_Lt), f64(o_Gv), f64(o_gp), dflag,
+                         R);
+  lobpcg_status s = check_launch("mixed_qr_noalloc");
+  int h = 0;
+  if (s == LOBPCG_OK && hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    s = fail(LOBPCG_ERR_HIP, "flag readback");
+  if (hipStreamSynchronize(st) != hipSuccess && s == LOBPCG_OK) s = fail(LOBPCG_ERR_HIP, "sync");
+  if (s == LOBPCG_OK && h) s = fail(LOBPCG_ERR_ORTHO_BREAKDOWN, "Cholesky of V^T V failed");
   return s;
 }
 

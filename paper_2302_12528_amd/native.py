@@ -75,6 +75,8 @@ SIGNATURES = {
     "lobpcg_apply_precond": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "lobpcg_mixed_qr": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int64, ct.c_int32, ct.c_void_p,
                                    ct.c_void_p]),
+    "lobpcg_mixed_qr_noalloc": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int64, ct.c_int32,
+                                           ct.c_void_p, ct.c_void_p]),
     "lobpcg_gram": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int32, ct.c_int32,
                                ct.c_void_p, ct.c_void_p]),
     "lobpcg_syev_small": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p]),

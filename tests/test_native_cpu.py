@@ -156,3 +156,12 @@ def test_symbolic_64cube_plan_size(lib):
     # exact geometric nested-dissection fill is 1.567e8; the relaxed supernodes stay within 15 % of it
     assert 1.5e8 < st["nnz_factor"] < 1.8e8
     assert st["levels"] <= 16
+
+
+def test_mixed_qr_noalloc_rejects_oversized_problems_before_gpu_work(lib):
+    # the size check runs on the host before the scratch array or W is touched
+    fake = ct.c_void_p(0x1000)
+    st = lib.lobpcg_mixed_qr_noalloc(fake, 4_000_000, 64, 64, 0, None, None)
+    assert st == nv.LOBPCG_ERR_INVALID_ARG and "scratch" in nv.last_error()
+    st = lib.lobpcg_mixed_qr_noalloc(fake, 100, 65, 65, 1, None, None)
+    assert st == nv.LOBPCG_ERR_INVALID_ARG
