@@ -24,6 +24,13 @@ m+1:c for both, which is the printed text at the first iteration (c = 2m).
 
 Everything is float64 except the preconditioner, which runs in the factor's
 precision.
+
+Line 1 (mixed_lobpcg): the start block of the working-precision loop is computed
+by the same LOBPCG run entirely in single precision (every array float32:
+single(A), single(X0), products, QR, Rayleigh-Ritz, residual, and the
+preconditioner's output) until the test holds with the first-stage tolerance
+(section 5.1 sets it to 5e-6); that X, widened to float64, then enters line 2
+with P = [].
 """
 from __future__ import annotations
 
@@ -41,6 +48,7 @@ class Result:
     converged: bool
     residuals: np.ndarray
     history: list
+    block: np.ndarray = None   # all m columns of X at exit
 
 
 def _sym(H):
@@ -71,9 +79,9 @@ def leading_converged(flags) -> int:
     return nc
 
 
-def rayleigh_ritz_start(A, X0):
+def rayleigh_ritz_start(A, X0, dtype=np.float64):
     """Line 2 with the diagonal-Theta reading: orthonormalise X0, then Rayleigh-Ritz on span(X0)."""
-    X, _ = np.linalg.qr(np.asarray(X0, dtype=np.float64))
+    X, _ = np.linalg.qr(np.asarray(X0, dtype=dtype))
     AX = A @ X
     theta, Y = np.linalg.eigh(_sym(X.T @ AX))
     return X @ Y, theta
@@ -89,14 +97,21 @@ def hl_update(S, C, D, m):
 
 def lobpcg(A, X0, k: int, tol: float, *, precond=None, precond_precision="fp64",
            norm_a: float, maxit: int = 1000, stop: str = "bj", eig_tol: float = 0.0,
-           callback=None) -> Result:
-    """k smallest eigenpairs of the SPD matrix A (dense ndarray or scipy sparse)."""
+           callback=None, dtype=np.float64) -> Result:
+    """k smallest eigenpairs of the SPD matrix A (dense ndarray or scipy sparse).
+
+    dtype=np.float32 runs every step in single precision (the lower-precision LOBPCG of line 1):
+    A and X0 are rounded to float32 and the preconditioner's output too."""
     n, m = X0.shape
     if not (1 <= k <= m) or 3 * m > n:
         raise ValueError("need 1 <= k <= m and 3m <= n")
     if precond is None:
         precond = Preconditioner(A, precond_precision)
-    X, theta = rayleigh_ritz_start(A, X0)
+    if dtype != np.float64:
+        A = A.astype(dtype)
+        f_t = precond
+        precond = lambda R: f_t(R).astype(dtype)            # noqa: E731
+    X, theta = rayleigh_ritz_start(A, X0, dtype)
     P = None
     history = []
     res = None
@@ -118,7 +133,7 @@ def lobpcg(A, X0, k: int, tol: float, *, precond=None, precond_precision="fp64",
         if callback is not None:
             callback(it, X, P, theta, res)
         if nc >= k:                                                  # lines 6-8
-            return Result(theta[:k].copy(), X[:, :k].copy(), it, True, res[:k].copy(), history)
+            return Result(theta[:k].copy(), X[:, :k].copy(), it, True, res[:k].copy(), history, X.copy())
         W = precond(R)                                               # lines 9-10
         B = X if P is None else np.hstack([X, P])
         for _ in range(2):                                           # line 11
@@ -129,4 +144,26 @@ def lobpcg(A, X0, k: int, tol: float, *, precond=None, precond_precision="fp64",
         D, C = np.linalg.eigh(_sym(S.T @ AS))                        # line 14
         X, P, theta = hl_update(S, C, D, m)                          # lines 15-16
     return Result(theta[:k].copy(), X[:, :k].copy(), maxit, False,
-                  res[:k].copy() if res is not None else None, history)
+                  res[:k].copy() if res is not None else None, history, X.copy())
+
+
+@dataclasses.dataclass
+class MixedResult:
+    evals: np.ndarray
+    evecs: np.ndarray
+    iters: int            # working-precision loop (lines 2-17)
+    stage1_iters: int     # single-precision LOBPCG of line 1
+    converged: bool
+    stage1_converged: bool
+    stage1_X: np.ndarray  # the float32 start block line 1 produced
+    residuals: np.ndarray
+
+
+def mixed_lobpcg(A, X0, k: int, tol: float, tol1: float, *, precond, norm_a: float, maxit: int = 1000,
+                 stop: str = "paper") -> MixedResult:
+    """Algorithm 3 with line 1: a single-precision LOBPCG from single(X0) to tol1, then the
+    working-precision loop from working(X) with P = [] (MPLOBPCG-schol of section 5.1)."""
+    s1 = lobpcg(A, X0, k, tol1, precond=precond, norm_a=norm_a, maxit=maxit, stop=stop, dtype=np.float32)
+    X1 = s1.block
+    s2 = lobpcg(A, X1.astype(np.float64), k, tol, precond=precond, norm_a=norm_a, maxit=maxit, stop=stop)
+    return MixedResult(s2.evals, s2.evecs, s2.iters, s1.iters, s2.converged, s1.converged, X1, s2.residuals)

@@ -366,3 +366,73 @@ def test_planted_mistake_preconditioner_half_precision_is_caught():
     Wbad = Pc(R.astype(np.float16).astype(np.float64))
     col = np.linalg.norm(Wbad - Wex, axis=0) / np.linalg.norm(Wex, axis=0)
     assert col.max() > kappa * np.finfo(np.float32).eps / 2
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3 line 1: the single-precision LOBPCG that computes the start block (MPLOBPCG-schol with
+# the first-stage tolerance 5e-6 of section 5.1).
+# ---------------------------------------------------------------------------
+
+def _stage1_case():
+    p = synth.cfg1()
+    na = dense.norm2(p.A)
+    T = precond.Preconditioner(p.A, "fp32")
+    return p, na, T
+
+
+def test_stage1_single_precision_meets_its_tolerance_and_closed_form():
+    # The first stage runs in float32 end to end and stops once eq. (stop) holds with 5e-6; its Ritz values
+    # then lie within the Kato-Temple bound ||r||^2 / gap plus the float32 rounding of A X (about
+    # u32 ||A|| absolute) of the closed form 4 sin^2(i pi/66) + 4 sin^2(j pi/66).
+    p, na, T = _stage1_case()
+    s1 = ol.lobpcg(p.A, p.X0, p.k, 5e-6, precond=T, norm_a=na, stop="paper", dtype=np.float32)
+    assert s1.converged and s1.block.dtype == np.float32 and s1.block.shape == (p.n, p.m)
+    X = s1.block.astype(np.float64)
+    theta = np.diag(X.T @ (p.A @ X)) / np.sum(X * X, axis=0)
+    res = ol.residual_norms(p.A, X[:, :p.k], theta[:p.k], na, mode="paper")
+    assert np.all(res <= 2 * 5e-6)                       # recomputed in FP64: float32 rounding stays well inside
+    ref = _cfg1_closed(p.k)
+    u32 = np.finfo(np.float32).eps / 2
+    gap = _cfg1_closed(p.m + 1)[p.m] - ref               # distance to the spectrum outside the block
+    bound = (5e-6 * (na + ref)) ** 2 / gap + 4 * u32 * na
+    assert np.all(np.abs(theta[:p.k] - ref) <= bound)
+    assert np.max(np.abs(theta[:p.k] - ref) / ref) > 1e-12   # single precision: not FP64-accurate
+
+
+def test_mixed_lobpcg_two_stages_reach_closed_form():
+    # Line 1 then lines 2-17: the FP64 loop from working(X) reaches the closed form to 1e-10 and the residual
+    # gate, and needs fewer working-precision iterations than the loop started from X0 itself.
+    p, na, T = _stage1_case()
+    r = ol.mixed_lobpcg(p.A, p.X0, p.k, p.tol, 5e-6, precond=T, norm_a=na, stop="paper")
+    assert r.converged and r.stage1_converged
+    ref = _cfg1_closed(p.k)
+    assert np.max(np.abs(r.evals - ref) / ref) <= 1e-10
+    assert np.all(ol.residual_norms(p.A, r.evecs, r.evals, na, mode="paper") <= p.tol)
+    single = ol.lobpcg(p.A, p.X0, p.k, p.tol, precond=T, norm_a=na, stop="paper")
+    assert r.iters < single.iters
+
+
+def test_planted_mistake_stage1_result_dropped_is_caught(monkeypatch):
+    # A first stage whose result is lost (the second stage restarts from X0) takes as many
+    # working-precision iterations as no first stage at all, which the two-stage pin rejects.
+    p, na, T = _stage1_case()
+    single = ol.lobpcg(p.A, p.X0, p.k, p.tol, precond=T, norm_a=na, stop="paper")
+    real = ol.lobpcg
+
+    def lossy(A, X0, k, tol, **kw):
+        r = real(A, X0, k, tol, **kw)
+        if kw.get("dtype") == np.float32:
+            r.block = np.asarray(X0, dtype=np.float32)
+        return r
+    monkeypatch.setattr(ol, "lobpcg", lossy)
+    r = ol.mixed_lobpcg(p.A, p.X0, p.k, p.tol, 5e-6, precond=T, norm_a=na, stop="paper")
+    assert not r.iters < single.iters
+
+
+def test_planted_mistake_stage1_in_double_is_caught():
+    # Running the first stage in float64 gives Ritz values accurate far beyond single precision: the
+    # last assertion of the first pin rejects it.
+    p, na, T = _stage1_case()
+    s1 = ol.lobpcg(p.A, p.X0, p.k, 1e-11, precond=T, norm_a=na, stop="paper", dtype=np.float64)
+    ref = _cfg1_closed(p.k)
+    assert not np.max(np.abs(s1.evals - ref) / ref) > 1e-12
