@@ -6,7 +6,10 @@ cell coefficients exp(N(0,1)), nested dissection), k = 16, m = 32, tol = 1e-10.
 One step = numeric factorization of the permuted matrix (FP32 factor) plus
 lobpcg_solve to tolerance, with the matrix and start block already on the GPU.
 The same step with an FP64 factor (and FP64 Algorithm 2 step 1) is timed on the
-same GPU for the mixed-vs-FP64 comparison.  Prints one JSON line.
+same GPU for the mixed-vs-FP64 comparison, and with the single-precision first
+stage of Algorithm 3 line 1 (MPLOBPCG-schol).  Side records: the dense SPD
+workload (n = 8192), the batched Schrodinger workload, the backward of the 3D
+Schrodinger workload, Algorithm 1 and the CPU oracle.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -72,7 +75,7 @@ def event_time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def batched_run(torch, pk, steps, count):
+def batched_run(torch, pk, steps, count, graph=False):
     """Batched Schrodinger workload: `count` 2D operators (side U{48..128}), k=8, m=16, FP32 factors, one
     context; a step = numeric factorization of the union + lobpcg_solve_batched to tol for all of them."""
     import numpy as np
@@ -81,7 +84,7 @@ def batched_run(torch, pk, steps, count):
     log(f"batched: setup {count} problems, n total {sum(p.n for p in probs)}")
     t0 = time.perf_counter()
     bs = pk.BatchedSolver([p.A for p in probs], 8, 16, 1e-10, factor_precision="fp32",
-                          grids=[p.grid for p in probs])
+                          grids=[p.grid for p in probs], graph=graph)
     t_setup = time.perf_counter() - t0
     X0s = [torch.from_numpy(np.ascontiguousarray(p.X0)).cuda() for p in probs]
     from paper_2302_12528_amd import native as nv
@@ -104,30 +107,140 @@ def batched_run(torch, pk, steps, count):
     bs.close()
     return {"workload": f"schrodinger2d_batch{count}: {count} 2D -Laplacian+V operators, side U{{48..128}}, "
                         f"k=8, m=16, tol=1e-10, FP32 factors; step = factorization + batched solve",
+            "graph": graph,
             "time_to_tol_s": round(dt, 5), "problems_per_s": round(count / dt, 2), "t_setup_s": round(t_setup, 3),
             "iters_min": int(min(iters)), "iters_max": int(max(iters)), "iters_mean": float(np.mean(iters)),
             "max_stop_residual": worst, "n_total": int(sum(p.n for p in probs))}
 
 
 def cpu_baseline():
-    """The oracle on a bounded sample: the same generator at 32^3, factor + solve to tol."""
+    """The oracle on a bounded sample: the same generator at 32^3, factor + solve to tol, with the host's
+    BLAS threads and again with one thread; next to it the oracle's full-size 64^3 time recorded when
+    tests/golden/diffusion3d_64.json was written (on the 8-core build container, not this host)."""
     import synth
     from oracle import dense, lobpcg, precond
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     p = synth.cfg2(N=32)
     na = dense.norm2(p.A)
+
+    def run():
+        t0 = time.perf_counter()
+        P = precond.Preconditioner(p.A, "fp64")
+        r = lobpcg.lobpcg(p.A, p.X0, p.k, p.tol, precond=P, norm_a=na, stop="paper")
+        return time.perf_counter() - t0, r.iters
+    dt, iters = run()
+    out = {"value": round(dt, 3), "unit": "s", "cores": threads, "kind": "oracle",
+           "sample": f"same recipe at 32^3 (n=32768, k=16, m=32, tol=1e-10): oracle FP64 LOBPCG with SuperLU "
+                     f"FP64 factor (single-threaded) + numpy BLAS, factor + solve, {iters} iterations; "
+                     f"not scaled to 64^3"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            dt1, _ = run()
+        out["single_thread_s"] = round(dt1, 3)
+    gold = os.path.join(ROOT, "tests", "golden", "diffusion3d_64.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+        out["full_size_64cubed"] = {"factor_s": round(g["t_factor"], 1), "solve_s": round(g["t_solve"], 1),
+                                    "iters": g["iters"], "cores": 8,
+                                    "where": "build container (8 cores), when the golden file was written"}
+    return out
+
+
+def dense_run(torch, pk, steps):
+    """Dense SPD workload at full size (n = 8192, geometric spectrum in [1, 1e6], k = 32, m = 64, tol 1e-10 with
+    the eigenvalue guard ||r_j||^2 <= 1e-12 |theta_j| (theta_m - theta_j)): time to tol with the FP32 dense factor
+    (matrix cores) and with the FP64 one, the dense A W (FP64 matrix cores) and the two dense triangular solves."""
+    import numpy as np
+    import synth
+    log("dense: generating dense_spd_8192")
+    p = synth.cfg3()
+    X0 = torch.from_numpy(np.ascontiguousarray(p.X0)).cuda()
+    n, m = p.n, p.m
+    out = {"workload": "dense_spd_8192: A = Q diag(geomspace(1, 1e6)) Q^T, n=8192, k=32, m=64, tol=1e-10, "
+                       "eig_tol=1e-12; step = numeric factorization + solve to tol"}
+    for prec, tol1 in (("fp32", 0.0), ("fp64", 0.0), ("fp32", 5e-6)):
+        label = "mixed" if prec == "fp32" and tol1 == 0 else ("fp64" if prec == "fp64" else "mp_schol")
+        log(f"dense: setup {label}")
+        s = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision=prec, qr_lower=(prec == "fp32"), eig_tol=1e-12,
+                      stage1_tol=tol1)
+        dt, infos, lam, X = time_steps(torch, s, X0, steps if label == "mixed" else 1, 1, f"dense {label}")
+        info = infos[-1]
+        rec = {"time_to_tol_s": round(dt, 5), "iters": info["iters"], "t_factor_s": round(info["t_factor"], 5),
+               "t_solve_s": round(info["t_solve"], 5)}
+        if tol1 > 0:
+            rec["stage1_iters"] = info["stage1_iters"]
+            rec["t_stage1_s"] = round(info["t_stage1"], 5)
+        lam = lam.cpu().numpy()
+        spec = p.extra["spectrum"][: p.k]
+        rec["max_eig_rel_err_vs_prescribed"] = float(np.max(np.abs(lam - spec) / spec))
+        if label == "mixed":
+            Xr = torch.randn(n, m, dtype=torch.float64, device="cuda")
+            ms_mm = event_time(torch, lambda: s.apply_a(Xr), 20)
+            ms_tr = event_time(torch, lambda: s.apply_precond(Xr), 20)
+            flops = 2.0 * n * n * m
+            out["dense_aw"] = {"ms": round(ms_mm, 4), "TFLOPs": round(flops / (ms_mm * 1e-3) / 1e12, 2),
+                               "peak_TFLOPs": 78.6, "frac": round(flops / (ms_mm * 1e-3) / 1e12 / 78.6, 4),
+                               "note": "A W, c = 64, FP64 matrix cores; 2 n^2 c flop"}
+            out["dense_trisolve"] = {"ms": round(ms_tr, 4), "TFLOPs": round(flops / (ms_tr * 1e-3) / 1e12, 2),
+                                     "peak_TFLOPs": 157.3, "frac": round(flops / (ms_tr * 1e-3) / 1e12 / 157.3, 4),
+                                     "note": "two FP32 triangular solves with 64 right-hand sides (with the cast "
+                                             "in and out); 2 n^2 c flop"}
+        s.close()
+        out[label] = rec
+    out["speedup_vs_fp64"] = round(out["fp64"]["time_to_tol_s"] / out["mixed"]["time_to_tol_s"], 3)
+    return out
+
+
+def backward_run(torch, pk, fd_amps=2):
+    """Differentiation workload at full size (3D -Laplacian + V on 48^3, V = 32 Gaussian bumps, loss = sum of the
+    8 smallest eigenvalues + <x_1, g>^2): forward solve to tol 1e-12 with the FP32 factor, the adjoint, and
+    central differences (h = 1e-6) of the loss on the first few amplitudes."""
+    import numpy as np
+    import synth
+    from paper_2302_12528_amd.autograd import eigh_potential
+    log("backward: generating schrodinger3d_48")
+    p = synth.cfg5()
+    L0, phi, a0, g = p.extra["L0"], p.extra["phi"], p.extra["amps"], p.extra["g"]
+    s = pk.Solver(L0, p.k, p.m, 1e-12, factor_precision="fp32", grid=p.grid)
+    phit = torch.from_numpy(phi).cuda()
+    gt = torch.from_numpy(g).cuda()
+    X0 = torch.from_numpy(np.ascontiguousarray(p.X0)).cuda()
+
+    def loss_of(amp):
+        lam, X = eigh_potential(phit @ amp, s, X0)
+        return lam.sum() + (X[:, 0] @ gt) ** 2
+
+    amp = torch.from_numpy(a0.copy()).cuda().requires_grad_(True)
+    loss_of(amp.detach())   # warm-up (factorization plan, buffers)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P = precond.Preconditioner(p.A, "fp64")
-    r = lobpcg.lobpcg(p.A, p.X0, p.k, p.tol, precond=P, norm_a=na, stop="paper")
-    dt = time.perf_counter() - t0
-    return {"value": round(dt, 3), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": f"same recipe at 32^3 (n=32768, k=16, m=32, tol=1e-10): oracle FP64 LOBPCG with SuperLU "
-                      f"FP64 factor (single-threaded) + numpy BLAS, factor + solve, {r.iters} iterations; "
-                      f"not scaled to 64^3"}
+    L = loss_of(amp)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    (ga,) = torch.autograd.grad(L, amp)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    pcg = s.backward_iters()
+    ga = ga.cpu().numpy()
+    fd = []
+    h = 1e-6
+    for q in range(fd_amps):
+        e = torch.zeros_like(amp)
+        e[q] = h
+        with torch.no_grad():
+            d = (loss_of(amp.detach() + e) - loss_of(amp.detach() - e)).item() / (2 * h)
+        fd.append({"amp": q, "fd": d, "adjoint": float(ga[q]), "rel_diff": abs(d - ga[q]) / max(1.0, abs(ga[q]))})
+    s.close()
+    return {"workload": "schrodinger3d_48: -Laplacian + V on 48^3 (n=110592), 32 bumps, k=8, m=16, tol=1e-12, FP32 "
+                        "factor; loss = sum of 8 eigenvalues + <x_1, g>^2",
+            "t_forward_s": round(t1 - t0, 5), "t_backward_s": round(t2 - t1, 5), "adjoint_pcg_iters": pcg,
+            "loss": float(L.item()), "fd_check": fd}
 
 
 def traffic_from_profile():
@@ -165,6 +278,9 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched run (0 = skip)")
     ap.add_argument("--pinvit-maxit", type=int, default=400, help="iteration cap of the PINVIT run (0 = skip)")
+    ap.add_argument("--no-stage1", action="store_true", help="skip the MPLOBPCG-schol (line 1) record")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense n = 8192 record")
+    ap.add_argument("--no-backward", action="store_true", help="skip the 48^3 backward record")
     ap.add_argument("--autotune", action="store_true", help="time the solve-plan split and reduction chunk at setup")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first copy a 256 MiB buffer once (reference dispatch for hardware byte counters)")
@@ -212,10 +328,16 @@ def main():
     # live by the library with HIP events on its stream around every application inside the timed
     # solves.  Algorithmic bytes per application: the lower factor read once per sweep, lower(R)
     # read, the intermediate y written and read, and W (FP64) written.
+    # Algorithmic bytes per application: the exact factor L (no explicit zeros) read once per sweep in FP32,
+    # and 4 FP32 passes over the n x m right-hand side block: 2 * 4 * nnz(L) + 16 n m.  The supernodal
+    # factor also stores the explicit zeros of its dense fronts and the solve writes W in FP64; the byte
+    # count with those is reported beside it (stored_bytes).
     nnzL = info["nnz_factor"]
+    nnzL_exact = pk.exact_fill(p.A, grid=p.grid)
     n_pc = sum(i["n_precond"] for i in infos)
     ms_pc = 1e3 * sum(i["t_precond_gpu"] for i in infos) / max(1, n_pc)
-    bytes_pc = 2 * nnzL * 4 + 3 * p.n * p.m * 4 + p.n * p.m * 8
+    bytes_pc = 2 * nnzL_exact * 4 + 16 * p.n * p.m
+    bytes_pc_stored = 2 * nnzL * 4 + 3 * p.n * p.m * 4 + p.n * p.m * 8
     gbs_pc = bytes_pc / (ms_pc * 1e-3) / 1e9
     # SpMM A W (line 13), c = m, timed the same way: A's CSR arrays read once, W read, A W written.
     nnz = p.A.nnz
@@ -241,6 +363,19 @@ def main():
                   "max_eig_rel_diff_vs_lobpcg": float(np.max(np.abs(lam_pv.cpu().numpy() - lam_np) / lam_np))}
     mixed.close()
 
+    # MPLOBPCG-schol: Algorithm 3 with line 1 (single-precision LOBPCG to 5e-6 first), same factor
+    mp = None
+    if not args.no_stage1:
+        log("setup mp_schol (fp32 factor + single-precision first stage)")
+        smp = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp32", grid=p.grid, stage1_tol=5e-6)
+        dtm, infos_m, lam_m, _ = time_steps(torch, smp, X0, max(1, min(args.steps, 3)), 1, "mp_schol")
+        smp.close()
+        im = infos_m[-1]
+        mp = {"time_to_tol_s": round(dtm, 5), "stage1_iters": im["stage1_iters"], "iters": im["iters"],
+              "t_stage1_s": round(im["t_stage1"], 5), "t_factor_s": round(im["t_factor"], 5),
+              "t_solve_s": round(im["t_solve"], 5), "stage1_tol": 5e-6,
+              "max_eig_rel_diff_vs_mixed": float(np.max(np.abs(lam_m.cpu().numpy() - lam_np) / lam_np))}
+
     fp64 = None
     if not args.no_fp64:
         log("setup fp64 factor")
@@ -249,7 +384,7 @@ def main():
         dt64, infos64, lam64, _ = time_steps(torch, s64, X0, max(1, min(args.steps, 2)), 1, "fp64")
         n64 = sum(i["n_precond"] for i in infos64)
         ms_pc64 = 1e3 * sum(i["t_precond_gpu"] for i in infos64) / max(1, n64)
-        bytes_pc64 = 2 * nnzL * 8 + 3 * p.n * p.m * 8 + p.n * p.m * 8
+        bytes_pc64 = 2 * nnzL_exact * 8 + 4 * 8 * p.n * p.m
         s64.close()
         fp64 = {"time_to_tol_s": round(dt64, 5), "iters": infos64[-1]["iters"],
                 "t_factor_s": round(infos64[-1]["t_factor"], 5), "t_solve_s": round(infos64[-1]["t_solve"], 5),
@@ -274,14 +409,22 @@ def main():
                      "kernel": "preconditioner application (forward + backward supernodal sweeps, FP32 factor), "
                                "HIP events around each application in the timed solves",
                      "ms": round(ms_pc, 4), "applications": n_pc, "algorithmic_bytes": bytes_pc,
-                     "ms_isolated": round(ms_pc_iso, 4)},
+                     "nnz_factor_exact": nnzL_exact, "stored_bytes": bytes_pc_stored,
+                     "frac_on_stored_bytes": round(bytes_pc_stored / (ms_pc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "target_frac": 0.6, "ms_isolated": round(ms_pc_iso, 4)},
         "spmm": {"ms": round(ms_spmm, 4), "GBs": round(gbs_spmm, 1), "frac": round(gbs_spmm / HBM_PEAK_GBS, 4),
                  "launches": n_sp, "algorithmic_bytes": bytes_spmm},
         "parity": parity,
+        "mp_schol": mp,
         "pinvit": pinvit,
     }
     if args.batched > 0:
         out["batched"] = batched_run(torch, pk, 1, args.batched)
+        out["batched_graph"] = batched_run(torch, pk, 1, args.batched, graph=True)
+    if not args.no_dense:
+        out["dense"] = dense_run(torch, pk, 2)
+    if not args.no_backward:
+        out["backward"] = backward_run(torch, pk)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a 32^3 sample)")
         out["cpu_baseline"] = cpu_baseline()

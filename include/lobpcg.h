@@ -87,6 +87,27 @@ typedef struct {
  * The choice changes the order of floating-point reductions, so results may differ in the
  * last bits from an untuned context. */
 #define LOBPCG_FLAG_AUTOTUNE 2
+/* LOBPCG_FLAG_FORCE_FP64_REDO: treat every FP32-step-1 Algorithm 2 of the iteration loop as if its
+ * step-3 Cholesky had broken down, so that each iteration takes the recovery path (at the next
+ * synchronisation the iteration is redone from its saved inputs with step 1 in FP64).  For testing
+ * that path: the results equal those of qr_lower = 0 (step 1 in FP64 throughout), and
+ * lobpcg_info.fallbacks counts the redone iterations; the start block's Algorithm 2 (and that of
+ * lobpcg_pinvit) then runs with step 1 in FP64 directly.  No effect when qr_lower = 0. */
+#define LOBPCG_FLAG_FORCE_FP64_REDO 4
+
+/* Device memory of a context from the caller (section 8 of the boundary: the caller's framework owns
+ * every device byte).  alloc(bytes, user) returns device memory on the current device, aligned to at
+ * least 256 bytes, or NULL on failure (setup then returns ALLOC); free(ptr, user) takes it back.
+ * Both are called only from the host thread inside lobpcg_setup, lobpcg_solve, lobpcg_backward and
+ * lobpcg_destroy; the library synchronises its streams before the frees in lobpcg_destroy, so the
+ * memory is idle when it is returned.  The library may use a block on streams other than the one bound
+ * at setup (its factorization side stream, its graph stream); an allocator that hands a freed block to
+ * other work must not do so before free() is called. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} lobpcg_allocator;
 
 /* Optional tuning of setup (pass NULL for defaults). */
 typedef struct {
@@ -104,12 +125,23 @@ typedef struct {
   /* Factorization: fronts with at least this many 64-row tiles below their diagonal block apply
    * the Schur complement on 128 x 128 blocks (0 = default, 8).  Same arithmetic per entry. */
   int32_t schur_wide_tiles;
+  /* > 0: Algorithm 3 line 1 - before the working-precision loop, a LOBPCG run in single precision
+   * (FP32 blocks, single(A), FP32 products, Gram matrices, updates, residual, preconditioner output
+   * and QR; the small Rayleigh-Ritz and Cholesky matrices in FP64) from single(X0) until the test of
+   * eq. (stop) holds with this tolerance (section 5.1 uses 5e-6), whose X then starts the loop with
+   * P = [].  0 = off (default).  Also for batched contexts, per problem. */
+  double stage1_tol;
+  /* NULL: device memory from hipMalloc/hipFree.  Otherwise every device allocation of the context goes
+   * through it (the struct is copied at setup; user must stay valid until lobpcg_destroy). */
+  const lobpcg_allocator* allocator;
 } lobpcg_options;
 
 typedef struct {
   int32_t iters;             /* outer iterations of Algorithm 3 */
   int32_t n_conv;            /* n_c at exit */
-  int32_t fallbacks;         /* Algorithm 2 retries in FP64 */
+  int32_t fallbacks;         /* Algorithm 2 retries in FP64: an FP32 step 1 whose step-3 Cholesky broke
+                                down is redone with step 1 in FP64 (in the loop: the whole iteration's
+                                lines 11-16, at the next synchronisation) */
   int32_t nlevels;           /* levels of the supernodal elimination tree */
   double norm_a;             /* ||A||_2 used by the convergence test */
   double t_symbolic;         /* s, host ordering + symbolic analysis (setup) */
@@ -124,6 +156,12 @@ typedef struct {
   double t_spmm_gpu;         /* s, sum over the products A W (line 13) */
   int32_t n_precond;         /* number of preconditioner applications timed */
   int32_t n_spmm;            /* number of products A W timed */
+  /* First stage (lobpcg_options.stage1_tol > 0; zero otherwise).  iters above counts the
+   * working-precision loop only. */
+  int32_t stage1_iters;      /* outer iterations of the single-precision LOBPCG */
+  int32_t stage1_exit;       /* 1 its test held, 2 iteration cap, 3 ended early (its FP32 QR broke
+                                down or a residual was not finite: the previous X was kept) */
+  double t_stage1;           /* s, wall time of the first stage (included in t_solve) */
 } lobpcg_info;
 
 /* Set up a solver for the k smallest eigenpairs with block size m (Algorithm 3
@@ -210,6 +248,10 @@ int32_t lobpcg_batch_count(lobpcg_ctx ctx);
 lobpcg_status lobpcg_backward(lobpcg_ctx ctx, const double* d_evals, const double* d_evecs,
                               double* d_diag);
 
+/* Iterations of the projected preconditioned CG in the latest lobpcg_backward on ctx (0 before
+ * the first one, or for a NULL ctx). */
+int32_t lobpcg_backward_iters(lobpcg_ctx ctx);
+
 lobpcg_status lobpcg_destroy(lobpcg_ctx ctx);
 const char* lobpcg_status_string(lobpcg_status s);
 const char* lobpcg_last_error(void);
@@ -224,6 +266,12 @@ const char* lobpcg_last_error(void);
  *  largest front rows, largest supernode columns, update-matrix entries,
  *  panel entries}. */
 lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t* perm_host, double* stats);
+
+/* Host-only: entries of the exact Cholesky factor L of Pi^T A Pi (diagonal included) for the ordering
+ * lobpcg_symbolic builds, counted on the elimination tree without forming L (section 5.1's factor
+ * without the supernodes' explicit zeros; the dense format gives n(n+1)/2).  *nnz_exact (host) receives
+ * it.  Work O(nnz(L)) on the host; no GPU use.  Errors: INVALID_ARG. */
+lobpcg_status lobpcg_exact_fill(const lobpcg_matrix* A, int32_t leaf_size, double* nnz_exact);
 
 /* Launch shapes in use: out3 = {split target of the triangular-solve plan, rows per reduction
  * chunk, 0 = defaults / 1 = tuned at setup / 2 = read from the tuning cache}. */

@@ -95,6 +95,7 @@ struct TsqrHost {
   std::vector<int64_t> level_off;
   std::vector<int32_t> items;
   int64_t half = 1;
+  int combine = 0;
 };
 
 // rb rows per item at level 0, rbu (a multiple of c) at the levels above
@@ -139,6 +140,59 @@ void build_tsqr(const std::vector<int64_t>& inst_off, int c, int rb, int rbu, Ts
   T.half = maxout * c * c;
 }
 
+// FP32 plans for c <= 32: leaves of kTsqrCombineRows rows, Gram chunks of kTsqrCombineSlots leaf factors,
+// one combining item per instance (see TsqrPlanDev); other plans: the Householder tree above.
+void build_tsqr_plan(const std::vector<int64_t>& inst_off, int c, int elem_bytes, TsqrHost& T) {
+  if (elem_bytes != 4 || c > 32) {
+    build_tsqr(inst_off, c, tsqr_rows_per_block(c, elem_bytes), tsqr_upper_rows_per_block(c, elem_bytes), T);
+    return;
+  }
+  T = TsqrHost();
+  T.rb = kTsqrCombineRows;
+  T.rbu = 0;
+  T.combine = 1;
+  const int B = (int)inst_off.size() - 1;
+  std::vector<int64_t> cnt(B), sbase(B), nchk(B), pbase(B);
+  int64_t nslots = 0, nparts = 0;
+  T.level_off.push_back(0);
+  for (int b = 0; b < B; ++b) {
+    const int64_t rows = inst_off[b + 1] - inst_off[b];
+    cnt[b] = (rows + kTsqrCombineRows - 1) / kTsqrCombineRows;
+    sbase[b] = nslots;
+    for (int64_t q = 0; q < cnt[b]; ++q) {
+      T.items.push_back(b);
+      T.items.push_back((int32_t)(inst_off[b] + q * kTsqrCombineRows));
+      T.items.push_back((int32_t)std::min<int64_t>(kTsqrCombineRows, rows - q * kTsqrCombineRows));
+      T.items.push_back((int32_t)(nslots + q));
+    }
+    nslots += cnt[b];
+  }
+  T.level_off.push_back((int64_t)T.items.size() / 4);
+  for (int b = 0; b < B; ++b) {
+    nchk[b] = (cnt[b] + kTsqrCombineSlots - 1) / kTsqrCombineSlots;
+    pbase[b] = nparts;
+    for (int64_t q = 0; q < nchk[b]; ++q) {
+      T.items.push_back(b);
+      T.items.push_back((int32_t)(sbase[b] + q * kTsqrCombineSlots));
+      T.items.push_back((int32_t)std::min<int64_t>(kTsqrCombineSlots, cnt[b] - q * kTsqrCombineSlots));
+      T.items.push_back((int32_t)(nparts + q));
+    }
+    nparts += nchk[b];
+  }
+  T.level_off.push_back((int64_t)T.items.size() / 4);
+  for (int b = 0; b < B; ++b) {
+    T.items.push_back(b);
+    T.items.push_back((int32_t)pbase[b]);
+    T.items.push_back((int32_t)nchk[b]);
+    T.items.push_back(b);
+  }
+  T.level_off.push_back((int64_t)T.items.size() / 4);
+  // first half: the leaf factors (FP32); second half: the FP64 partials and then the B per-instance
+  // sums (two FP32 elements each)
+  T.half = std::max<int64_t>(nslots * c * c, 2 * (nparts + B) * c * c);
+  T.half += T.half & 1;   // the FP64 partials start 8-byte aligned
+}
+
 }  // namespace
 
 struct lobpcg_ctx_s {
@@ -177,6 +231,12 @@ struct lobpcg_ctx_s {
   // iteration
   double* Sb[2] = {nullptr, nullptr};
   double* ASb[2] = {nullptr, nullptr};
+  // lower-precision first stage (Algorithm 3 line 1), allocated on its first use: FP32 copies of
+  // S and AS (same layout), of A's values (CSR) or of dense A
+  float* Sf[2] = {nullptr, nullptr};
+  float* ASf[2] = {nullptr, nullptr};
+  float* d_aval32 = nullptr;
+  float* d_dense32 = nullptr;
   void *rhs = nullptr, *ybuf = nullptr, *xbuf = nullptr, *uvec = nullptr, *fpart = nullptr, *bpart = nullptr;
   double *gpart = nullptr, *H = nullptr, *Cev = nullptr, *evals = nullptr, *Gupd = nullptr, *Gc = nullptr;
   double *norms = nullptr, *syev_work = nullptr;
@@ -210,13 +270,25 @@ struct lobpcg_ctx_s {
   void* h_rb = nullptr;       // pinned host copy of the norms | evals | flags block
   int64_t rb_bytes = 0;
 
+  // device memory: the caller's allocator (lobpcg_options.allocator) when given, else hipMalloc
+  lobpcg_allocator ua{};
   template <typename X>
   lobpcg_status alloc(X*& p, int64_t count) {
     p = nullptr;
     if (count <= 0) count = 1;
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, (size_t)count * sizeof(X));
-    if (e != hipSuccess) return fail(LOBPCG_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+    const size_t bytes = (size_t)count * sizeof(X);
+    if (ua.alloc) {
+      q = ua.alloc(bytes, ua.user);
+      if (!q) return fail(LOBPCG_ERR_ALLOC, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+      if (reinterpret_cast<uintptr_t>(q) % 256 != 0) {
+        ua.free(q, ua.user);
+        return fail(LOBPCG_ERR_ALLOC, "the caller's allocator returned memory that is not 256-byte aligned");
+      }
+    } else {
+      hipError_t e = hipMalloc(&q, bytes);
+      if (e != hipSuccess) return fail(LOBPCG_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
     allocs.push_back(q);
     p = static_cast<X*>(q);
     return LOBPCG_OK;
@@ -228,6 +300,10 @@ struct lobpcg_ctx_s {
     return s;
   }
   ~lobpcg_ctx_s() {
+    // the memory may go straight back to the caller's allocator: every queued kernel finishes first
+    if (st) (void)hipStreamSynchronize(st);
+    if (fst) (void)hipStreamSynchronize(fst);
+    if (gst) (void)hipStreamSynchronize(gst);
     if (h_rb) (void)hipHostFree(h_rb);
     for (hipGraphExec_t g : gexec)
       if (g) (void)hipGraphExecDestroy(g);
@@ -238,7 +314,12 @@ struct lobpcg_ctx_s {
     if (fst) (void)hipStreamDestroy(fst);
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
-    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : allocs) {
+      if (ua.free)
+        ua.free(p, ua.user);
+      else
+        (void)hipFree(p);
+    }
   }
 };
 
@@ -282,6 +363,7 @@ lobpcg_status upload_tsqr(lobpcg_ctx c, TsqrHost& H, TsqrPlanDev& D) {
   D.nlevels = (int)H.level_off.size() - 1;
   D.level_off = H.level_off.data();
   D.half = H.half;
+  D.combine = H.combine;
   ST_TRY(upload_const(c, D.items, H.items));
   return LOBPCG_OK;
 }
@@ -524,7 +606,8 @@ lobpcg_status ortho(lobpcg_ctx c, double* W, int64_t ld, int cc) {
   lobpcg_ctx_s& C = *c;
   launch_fill_int(C.d_qflag, 0, 2 * C.B, C.st);
   int* qflag2 = C.d_qflag + C.B;
-  if (C.opt.qr_lower) {
+  // (LOBPCG_FLAG_FORCE_FP64_REDO: the FP32 attempt counts as broken down, so step 1 runs in FP64 on W itself)
+  if (C.opt.qr_lower && !(C.opt.flags & LOBPCG_FLAG_FORCE_FP64_REDO)) {
     mixed_qr_seg<float>(C.st, C.SG, C.TP32, W, ld, cc, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, C.d_qflag, nullptr);
     SegDev R = C.SG;
     R.active = C.d_qflag;
@@ -571,13 +654,20 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
       return fail(LOBPCG_ERR_INVALID_ARG, "stop_rule");
     if (opt.norm_a < 0 || !std::isfinite(opt.norm_a)) return fail(LOBPCG_ERR_INVALID_ARG, "norm_a");
     if (opt.eig_tol < 0 || !std::isfinite(opt.eig_tol)) return fail(LOBPCG_ERR_INVALID_ARG, "eig_tol");
-    if (opt.flags & ~(LOBPCG_FLAG_GRAPH | LOBPCG_FLAG_AUTOTUNE)) return fail(LOBPCG_ERR_INVALID_ARG, "unknown flags");
+    if (opt.flags & ~(LOBPCG_FLAG_GRAPH | LOBPCG_FLAG_AUTOTUNE | LOBPCG_FLAG_FORCE_FP64_REDO))
+      return fail(LOBPCG_ERR_INVALID_ARG, "unknown flags");
     if (opt.subtree_levels < -1) return fail(LOBPCG_ERR_INVALID_ARG, "subtree_levels must be >= -1");
     if (opt.schur_wide_tiles < 0) return fail(LOBPCG_ERR_INVALID_ARG, "schur_wide_tiles must be >= 0");
+    if (opt.stage1_tol < 0 || !std::isfinite(opt.stage1_tol))
+      return fail(LOBPCG_ERR_INVALID_ARG, "stage1_tol must be >= 0 and finite");
   }
   if (opt.schur_wide_tiles == 0) opt.schur_wide_tiles = kSchurWideTiles;
+  if (opt.allocator && (!opt.allocator->alloc || !opt.allocator->free))
+    return fail(LOBPCG_ERR_INVALID_ARG, "allocator needs both alloc and free");
   auto c = new lobpcg_ctx_s();
   lobpcg_ctx_s& C = *c;
+  if (opt.allocator) C.ua = *opt.allocator;
+  opt.allocator = nullptr;   // the context keeps its own copy
   C.st = static_cast<hipStream_t>(hip_stream);
   C.B = count;
   C.k = k;
@@ -664,8 +754,8 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
       }
   C.chunk_rows = default_chunk_rows(n);
   build_segments(inst_off, C.chunk_rows, C.SH);
-  build_tsqr(inst_off, m, tsqr_rows_per_block(m, 4), tsqr_upper_rows_per_block(m, 4), C.TQ32);
-  build_tsqr(inst_off, m, tsqr_rows_per_block(m, 8), tsqr_upper_rows_per_block(m, 8), C.TQ64);
+  build_tsqr_plan(inst_off, m, 4, C.TQ32);
+  build_tsqr_plan(inst_off, m, 8, C.TQ64);
   C.t_symbolic = now_s() - t0;
   auto cleanup = [&](lobpcg_status s) {
     delete c;
@@ -979,41 +1069,81 @@ lobpcg_status autotune(lobpcg_ctx c) {
 // Algorithm 3 lines 9-16 of one steady-state or first iteration on the context's current stream:
 // S = [X | P | W] in Sb[cur] (W at column wslot), AS likewise; the new X, P, AX, AP go to Sb[1 - cur].
 // With `timed`, events ev[0..3] bracket the preconditioner and the product A W.
+lobpcg_status iteration_tail(lobpcg_ctx c, int cur, bool haveP, const SegDev& S, bool retry, bool timed);
+
 lobpcg_status iteration_body(lobpcg_ctx c, int cur, bool haveP, bool timed) {
+  lobpcg_ctx_s& C = *c;
+  const int m = C.m, m3 = 3 * m;
+  // lines 9-10: W = working(f_T(lower(R)))   (on the union; frozen instances are ignored below)
+  double* W = C.Sb[cur] + (haveP ? 2 * m : m);
+  if (timed) HIP_TRY(hipEventRecord(C.ev[0], C.st));
+  precond(c, W, m3);
+  if (timed) HIP_TRY(hipEventRecord(C.ev[1], C.st));
+  ST_TRY(check_launch("preconditioner"));
+  return iteration_tail(c, cur, haveP, C.SG, false, timed);
+}
+
+// Lines 11-16 for the instances S.active selects.  retry = false: Algorithm 2 with the context's step 1
+// (FP32 step 1: a breakdown of step 3 sets qflag[b]; FP64 step 1: qflag[B + b]).  retry = true: the
+// redo of an iteration whose FP32 attempt broke down, with step 1 in FP64 (qflag[B + b] on breakdown).
+lobpcg_status iteration_tail(lobpcg_ctx c, int cur, bool haveP, const SegDev& S, bool retry, bool timed) {
   lobpcg_ctx_s& C = *c;
   hipStream_t st = C.st;
   const int B = C.B, m = C.m, m3 = 3 * m;
   double* Sx = C.Sb[cur];
   double* ASx = C.ASb[cur];
-  // lines 9-10: W = working(f_T(lower(R)))   (on the union; frozen instances are ignored below)
   const int wslot = haveP ? 2 * m : m;
   double* W = Sx + wslot;
-  if (timed) HIP_TRY(hipEventRecord(C.ev[0], st));
-  precond(c, W, m3);
-  if (timed) HIP_TRY(hipEventRecord(C.ev[1], st));
-  ST_TRY(check_launch("preconditioner"));
   // line 11: orthogonalize W against [X, P] twice
   for (int pass = 0; pass < 2; ++pass) {
-    launch_sgram(C.SG, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, st);
-    launch_supdate(C.SG, Sx, m3, C.Gc, m, (int64_t)2 * m * m, W, m3, wslot, m, -1.0, 1.0, st);
+    launch_sgram(S, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, st);
+    launch_supdate(S, Sx, m3, C.Gc, m, (int64_t)2 * m * m, W, m3, wslot, m, -1.0, 1.0, st);
   }
   ST_TRY(check_launch("block Gram-Schmidt"));
   // line 12: W = Q of Algorithm 2
-  ST_TRY(ortho(c, W, m3, m));
+  int* qflag2 = C.d_qflag + B;
+  if (retry) {
+    launch_fill_int(qflag2, 0, B, st);
+    mixed_qr_seg<double>(st, S, C.TP64, W, m3, m, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, qflag2, nullptr);
+  } else {
+    launch_fill_int(C.d_qflag, 0, 2 * B, st);
+    if (C.opt.qr_lower)
+      mixed_qr_seg<float>(st, S, C.TP32, W, m3, m, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, C.d_qflag, nullptr);
+    else
+      mixed_qr_seg<double>(st, S, C.TP64, W, m3, m, C.tsqr_ws, C.Rl, C.Lt, C.Gv, C.gpart, qflag2, nullptr);
+  }
+  ST_TRY(check_launch("mixed QR"));
   // line 13: A_p = S^T A S, with A W the only new product
   if (timed) HIP_TRY(hipEventRecord(C.ev[2], st));
   apply_a(c, W, m3, ASx + wslot, m3, m);
   if (timed) HIP_TRY(hipEventRecord(C.ev[3], st));
   const int cc = wslot + m;
-  launch_sgram(C.SG, Sx, m3, ASx, m3, cc, cc, C.H, (int64_t)m3 * m3, C.gpart, st);
+  launch_sgram(S, Sx, m3, ASx, m3, cc, cc, C.H, (int64_t)m3 * m3, C.gpart, st);
   // line 14: A_p C = C D
   launch_syev(C.H, cc, (int64_t)m3 * m3, cc, m, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info,
-              C.d_active, B, st);
+              S.active, B, st);
   // lines 15-16: HL basis and the new X, P (and A X, A P by the same combination)
-  launch_hl_build(C.Cev, (int64_t)m3 * m3, cc, m, C.Gupd, (int64_t)m3 * 2 * m, C.d_active, B, st);
-  launch_supdate(C.SG, Sx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
-  launch_supdate(C.SG, ASx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.ASb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
+  launch_hl_build(C.Cev, (int64_t)m3 * m3, cc, m, C.Gupd, (int64_t)m3 * 2 * m, S.active, B, st);
+  launch_supdate(S, Sx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
+  launch_supdate(S, ASx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.ASb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
   return check_launch("Rayleigh-Ritz");
+}
+
+// Redo of the iteration that read S = Sb[prev] for the instances whose FP32 Algorithm 2 broke down
+// (qflag[b] set): W is restored from the solve's result x, which still holds that iteration's
+// f_T(lower(R)) exactly as it was widened into W, and lines 11-16 run again with step 1 in FP64 for those
+// instances only; their new X, P, A X, A P replace the failed ones in Sb[1 - prev].
+lobpcg_status retry_iteration(lobpcg_ctx c, int prev, bool haveP, bool all_active) {
+  lobpcg_ctx_s& C = *c;
+  const int m = C.m, m3 = 3 * m;
+  double* W = C.Sb[prev] + (haveP ? 2 * m : m);
+  if (C.prec == LOBPCG_FP32)
+    launch_convert_block<float, double>(static_cast<const float*>(C.xbuf), C.mp, W, m3, C.n, m, C.st);
+  else
+    launch_convert_block<double, double>(static_cast<const double*>(C.xbuf), C.mp, W, m3, C.n, m, C.st);
+  SegDev R = C.SG;
+  R.active = all_active ? C.d_active : C.d_qflag;
+  return iteration_tail(c, prev, haveP, R, true, false);
 }
 
 // Capture iteration_body(cur, haveP = true) as an executable graph on the context's stream.
@@ -1042,6 +1172,172 @@ struct StreamSwap {
   hipStream_t saved;
   ~StreamSwap() { c->st = saved; }
 };
+
+// ---- Algorithm 3 line 1: the lower-precision LOBPCG that computes the start block ----
+// Every n-sized step (products with A, Gram matrices, block updates, residual, the preconditioner,
+// the QR of W) runs on FP32 blocks in FP32 arithmetic; the small matrices they produce (Gram
+// matrices, the Rayleigh-Ritz matrix, the Cholesky factor of Algorithm 2 step 3) are widened to FP64
+// and handled by the working-precision small kernels, whose cost does not depend on n.
+
+// Y = A X in FP32 (A's values rounded to FP32 by prepare_stage1)
+void apply_a32(lobpcg_ctx c, const float* X, int64_t ldx, float* Y, int64_t ldy, int cols) {
+  if (c->dense)
+    launch_dense_mm<float>(c->d_dense32, c->ld_dense, c->n, X, ldx, Y, ldy, cols, reinterpret_cast<float*>(c->d_mmpart),
+                           2 * c->mmpart_elems, c->st);
+  else
+    launch_spmm_csr<float>(c->d_prow, c->d_pcol, c->d_aval32, c->n, X, ldx, Y, ldy, cols, c->st);
+}
+
+// FP32 buffers of the first stage and single(A), refreshed from the current values on every solve
+lobpcg_status prepare_stage1(lobpcg_ctx c) {
+  lobpcg_ctx_s& C = *c;
+  const int64_t n = C.n, m3 = 3 * C.m;
+  for (int b = 0; b < 2; ++b) {
+    if (!C.Sf[b]) ST_TRY(C.alloc(C.Sf[b], n * m3));
+    if (!C.ASf[b]) ST_TRY(C.alloc(C.ASf[b], n * m3));
+  }
+  if (C.dense) {
+    if (!C.d_dense32) ST_TRY(C.alloc(C.d_dense32, n * C.ld_dense));
+    launch_convert_block<double, float>(C.d_dense, C.ld_dense, C.d_dense32, C.ld_dense, n, (int)n, C.st);
+  } else {
+    if (!C.d_aval32) ST_TRY(C.alloc(C.d_aval32, C.nnz));
+    launch_convert_block<double, float>(C.d_aval, 1, C.d_aval32, 1, C.nnz, 1, C.st);
+  }
+  return check_launch("first-stage buffers");
+}
+
+// Algorithm 2 with every n-sized step in FP32 on an FP32 block W (the first stage's QR): FP32
+// Householder R_l, V = W R_l^{-1}, the Gram matrix V^T V by FP32 products (chunk sums in FP64),
+// its Cholesky factor in FP64, Q = V L^{-T}.  A breakdown of the Cholesky sets qflag[b]; there is
+// no retry (the host ends the first stage for that instance).
+lobpcg_status ortho32(lobpcg_ctx c, float* W, int64_t ld, int cc) {
+  lobpcg_ctx_s& C = *c;
+  float* Rl = static_cast<float*>(C.Rl);
+  launch_fill_int(C.d_qflag, 0, 2 * C.B, C.st);
+  launch_stsqr<float>(C.SG, C.TP32, W, ld, cc, static_cast<float*>(C.tsqr_ws), Rl, C.st);
+  launch_strsm_rows<float>(C.SG, W, ld, cc, Rl, (int64_t)cc * cc, C.st);
+  launch_sgram<float>(C.SG, W, ld, W, ld, cc, cc, C.Gv, (int64_t)cc * cc, C.gpart, C.st);
+  launch_chol_upper<float>(C.Gv, Rl, cc, C.Lt, nullptr, C.d_qflag, C.SG.active, C.B, C.st);
+  launch_strsm_rows<double>(C.SG, W, ld, cc, C.Lt, (int64_t)cc * cc, C.st);
+  return check_launch("first-stage QR");
+}
+
+// Rayleigh-Ritz of S = Sx (cc columns) with AS = ASx into the next buffers: X, P (cc > m) and A X,
+// A P by the Hetmaniuk-Lehoucq basis, as the working-precision loop does.
+void rayleigh_ritz32(lobpcg_ctx c, float* Sx, float* ASx, float* Sn, float* ASn, int cc) {
+  lobpcg_ctx_s& C = *c;
+  const int m = C.m, m3 = 3 * m;
+  const int nout = (cc > m) ? 2 * m : m;
+  launch_sgram<float>(C.SG, Sx, m3, ASx, m3, cc, cc, C.H, (int64_t)m3 * m3, C.gpart, C.st);
+  launch_syev(C.H, cc, (int64_t)m3 * m3, cc, m, C.evals, m3, C.Cev, (int64_t)m3 * m3, C.syev_work, C.d_info,
+              C.d_active, C.B, C.st);
+  launch_hl_build(C.Cev, (int64_t)m3 * m3, cc, m, C.Gupd, (int64_t)m3 * 2 * m, C.d_active, C.B, C.st);
+  launch_supdate<float>(C.SG, Sx, m3, C.Gupd, nout, (int64_t)m3 * 2 * m, Sn, m3, cc, nout, 1.0, 0.0, C.st);
+  launch_supdate<float>(C.SG, ASx, m3, C.Gupd, nout, (int64_t)m3 * 2 * m, ASn, m3, cc, nout, 1.0, 0.0, C.st);
+}
+
+// One first-stage iteration (lines 9-16 in FP32) from S = Sf[cur] into Sf[1 - cur].
+template <typename T>
+lobpcg_status iteration_body32(lobpcg_ctx c, int cur, bool haveP) {
+  lobpcg_ctx_s& C = *c;
+  const int m = C.m, m3 = 3 * m;
+  float* Sx = C.Sf[cur];
+  float* ASx = C.ASf[cur];
+  const int wslot = haveP ? 2 * m : m;
+  float* W = Sx + wslot;
+  // lines 9-10: the solve result x (the factor's precision) becomes W
+  precond_t<T>(c, nullptr, 0, 0);
+  launch_convert_block<T, float>(static_cast<const T*>(C.xbuf), C.mp, W, m3, C.n, m, C.st);
+  for (int pass = 0; pass < 2; ++pass) {   // line 11
+    launch_sgram<float>(C.SG, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, C.st);
+    launch_supdate<float>(C.SG, Sx, m3, C.Gc, m, (int64_t)2 * m * m, W, m3, wslot, m, -1.0, 1.0, C.st);
+  }
+  ST_TRY(ortho32(c, W, m3, m));   // line 12
+  apply_a32(c, W, m3, ASx + wslot, m3, m);   // line 13
+  rayleigh_ritz32(c, Sx, ASx, C.Sf[1 - cur], C.ASf[1 - cur], wslot + m);   // lines 14-16
+  return check_launch("first-stage iteration");
+}
+
+// Runs the first stage for every instance from the FP64 start block in columns 0 .. m - 1 of Sb[0]
+// (permuted rows) to the test of eq. (stop) with tolerance tol1, and leaves its X there, widened to
+// FP64.  An instance whose FP32 QR breaks down or whose residuals stop being finite ends the stage
+// with the X of the iteration before (the start block if that was the first one).  Per instance:
+// iters1 = outer iterations, exit1 = 1 converged, 2 iteration cap, 3 ended early.
+template <typename T>
+lobpcg_status stage1_t(lobpcg_ctx c, double tol1, int32_t maxit, std::vector<int>& iters1, std::vector<int>& exit1) {
+  lobpcg_ctx_s& C = *c;
+  const int B = C.B, m = C.m, k = C.k, m3 = 3 * m;
+  const std::vector<int64_t>& off = C.SH.inst_off;
+  hipStream_t st = C.st;
+  ST_TRY(prepare_stage1(c));
+  iters1.assign(B, 0);
+  exit1.assign(B, 0);
+  std::vector<int> src(B, -1);   // where each instance's result X lives: -1 = the start block in Sb[0]
+  C.active.assign(B, 1);
+  ST_TRY(set_active(c));
+  launch_convert_block<double, float>(C.Sb[0], m3, C.Sf[0], m3, C.n, m, st);   // single(X0)
+  ST_TRY(ortho32(c, C.Sf[0], m3, m));
+  apply_a32(c, C.Sf[0], m3, C.ASf[0], m3, m);
+  rayleigh_ritz32(c, C.Sf[0], C.ASf[0], C.Sf[1], C.ASf[1], m);
+  ST_TRY(check_launch("first-stage start"));
+  int cur = 1;
+  bool haveP = false;
+  for (int it = 1; it <= maxit; ++it) {
+    launch_sresidual<T, float>(C.SG, C.ASf[cur], m3, C.Sf[cur], m3, C.evals, m3, m, static_cast<T*>(C.rhs), C.mp,
+                               C.norms, C.gpart, st);
+    ST_TRY(check_launch("first-stage residual"));
+    int active_before = 0;
+    for (int b = 0; b < B; ++b) active_before += C.active[b];
+    HIP_TRY(hipMemcpyAsync(C.h_rb, C.norms, C.rb_bytes, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double* hn = static_cast<const double*>(C.h_rb);
+    const double* th = hn + (int64_t)B * 2 * m;
+    const int32_t* qf = reinterpret_cast<const int32_t*>(th + (int64_t)B * m3);
+    int nactive = 0;
+    for (int b = 0; b < B; ++b) {
+      if (!C.active[b]) continue;
+      iters1[b] = it;
+      const double* hb = hn + (int64_t)b * 2 * m;
+      const double* tb = th + (int64_t)b * m3;
+      bool finite = true;
+      for (int j = 0; j < m; ++j)
+        if (!std::isfinite(hb[j]) || !std::isfinite(hb[m + j]) || !std::isfinite(tb[j])) finite = false;
+      if (qf[b] || !finite) {   // the QR that produced this X broke down: keep the previous X
+        src[b] = (it == 1) ? -1 : 1 - cur;
+        exit1[b] = 3;
+        C.active[b] = 0;
+        continue;
+      }
+      int nc = 0;
+      for (int j = 0; j < m; ++j) {
+        const double rn = std::sqrt(hb[j]), xn = std::sqrt(hb[m + j]);
+        const double denom = (C.opt.stop_rule == LOBPCG_STOP_PAPER) ? (C.norm_a[b] + std::fabs(tb[j])) * xn
+                                                                     : C.norm_a[b] * xn;
+        if (!(rn <= tol1 * denom)) break;
+        nc++;
+      }
+      if (nc >= k || it == maxit) {
+        src[b] = cur;
+        exit1[b] = (nc >= k) ? 1 : 2;
+        C.active[b] = 0;
+      } else {
+        ++nactive;
+      }
+    }
+    if (nactive == 0) break;
+    if (nactive != active_before) ST_TRY(set_active(c));
+    ST_TRY(iteration_body32<T>(c, cur, haveP));
+    cur = 1 - cur;
+    haveP = true;
+  }
+  // working(X) into the start block of the working-precision loop
+  for (int b = 0; b < B; ++b) {
+    if (src[b] < 0) continue;
+    const int64_t r0 = off[b], nb = off[b + 1] - off[b];
+    launch_convert_block<float, double>(C.Sf[src[b]] + r0 * m3, m3, C.Sb[0] + r0 * m3, m3, nb, m, st);
+  }
+  return check_launch("first-stage result");
+}
 
 // Algorithm 3 lines 2-17 for every instance of the context.
 lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, double* const* evals_out,
@@ -1078,6 +1374,18 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
       launch_gaussian_fill(X + off[b] * m3, nb, m, m3, 0x1234abcdull + (uint64_t)b, st);
   }
   ST_TRY(check_launch("start block"));
+  // line 1 (optional): a lower-precision LOBPCG refines the start block
+  std::vector<int> iters1(B, 0), exit1(B, 0);
+  double t_stage1 = 0;
+  if (C.opt.stage1_tol > 0) {
+    const double t1 = now_s();
+    ST_TRY(C.prec == LOBPCG_FP32 ? stage1_t<float>(c, C.opt.stage1_tol, maxit, iters1, exit1)
+                                 : stage1_t<double>(c, C.opt.stage1_tol, maxit, iters1, exit1));
+    HIP_TRY(hipStreamSynchronize(st));
+    t_stage1 = now_s() - t1;
+    C.active.assign(B, 1);
+    ST_TRY(set_active(c));
+  }
   ST_TRY(ortho(c, X, m3, m));
   apply_a(c, X, m3, C.ASb[cur], m3, m);
   launch_sgram(C.SG, X, m3, C.ASb[cur], m3, m, m, C.H, (int64_t)m3 * m3, C.gpart, st);
@@ -1088,7 +1396,7 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
   launch_supdate(C.SG, C.ASb[cur], m3, C.Gupd, m, (int64_t)m3 * 2 * m, C.ASb[1 - cur], m3, m, m, 1.0, 0.0, st);
   cur = 1 - cur;
   ST_TRY(check_launch("initial Rayleigh-Ritz"));
-  bool haveP = false;
+  bool haveP = false, prev_haveP = false;
   const bool timed = (B == 1) && !graph;
   bool pending = false;
   double t_pc = 0, t_sp = 0;
@@ -1132,10 +1440,31 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
     const double* th = hn + (int64_t)B * 2 * m;
     const int32_t* qf = reinterpret_cast<const int32_t*>(th + (int64_t)B * m3);
     harvest();
-    // the previous Algorithm 2 call: FP64 retries taken, and retries that broke down as well
+    // the previous iteration's Algorithm 2: an FP32 attempt that broke down is redone with step 1 in
+    // FP64 (that iteration's lines 11-16 for those instances), then the residual is formed again
+    if (it == 1) {   // the start block's Algorithm 2 retried on the device already
+      for (int b = 0; b < B; ++b) C.fallbacks += (C.active[b] && qf[b]) ? 1 : 0;
+    } else {
+      const bool force = (C.opt.flags & LOBPCG_FLAG_FORCE_FP64_REDO) && C.opt.qr_lower;
+      bool redo = false;
+      for (int b = 0; b < B; ++b) redo = redo || (C.active[b] && (qf[b] || force));
+      if (redo) {
+        for (int b = 0; b < B; ++b) C.fallbacks += (C.active[b] && (qf[b] || force)) ? 1 : 0;
+        ST_TRY(retry_iteration(c, 1 - cur, prev_haveP, force));
+        if (C.prec == LOBPCG_FP32)
+          launch_sresidual<float>(C.SG, ASx, m3, Sx, m3, C.evals, m3, m, static_cast<float*>(C.rhs), C.mp, C.norms,
+                                  C.gpart, st);
+        else
+          launch_sresidual<double>(C.SG, ASx, m3, Sx, m3, C.evals, m3, m, static_cast<double*>(C.rhs), C.mp,
+                                   C.norms, C.gpart, st);
+        ST_TRY(check_launch("residual after the FP64 retry"));
+        HIP_TRY(hipMemcpyAsync(C.h_rb, C.norms, C.rb_bytes, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+      }
+    }
+    // Algorithm 2 that broke down with step 1 in FP64 (the retry, or the FP64-only configuration)
     for (int b = 0; b < B; ++b) {
       if (!C.active[b]) continue;
-      C.fallbacks += qf[b];
       if (qf[B + b]) {
         status[b] = LOBPCG_ERR_ORTHO_BREAKDOWN;
         C.active[b] = 0;
@@ -1198,6 +1527,7 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
       pending = timed;
     }
     cur = 1 - cur;
+    prev_haveP = haveP;
     haveP = true;
     // frozen instances keep their (already emitted) results; their rows of the new buffers are not used
   }
@@ -1227,6 +1557,9 @@ lobpcg_status solve_core(lobpcg_ctx c, const double* const* X0, int32_t maxit, d
       I.t_spmm_gpu = t_sp;
       I.n_precond = n_pc;
       I.n_spmm = n_sp;
+      I.stage1_iters = iters1[b];
+      I.stage1_exit = exit1[b];
+      I.t_stage1 = t_stage1;
     }
   }
   // the context keeps the final Ritz pairs of a single instance for lobpcg_backward
@@ -1659,6 +1992,8 @@ lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double*
   return LOBPCG_OK;
 }
 
+int32_t lobpcg_backward_iters(lobpcg_ctx c) { return c ? c->bw_iters : 0; }
+
 lobpcg_status lobpcg_destroy(lobpcg_ctx c) {
   if (!c) return LOBPCG_OK;
   if (c->st) (void)hipStreamSynchronize(c->st);
@@ -1697,6 +2032,23 @@ lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t
     stats[6] = (double)S.upd_total;
     stats[7] = (double)S.panel_total;
   }
+
+  return LOBPCG_OK;
+}
+
+lobpcg_status lobpcg_exact_fill(const lobpcg_matrix* A, int32_t leaf_size, double* nnz_exact) {
+  if (!nnz_exact) return fail(LOBPCG_ERR_INVALID_ARG, "NULL argument");
+  ST_TRY(validate_matrix(A));
+  if (A->format == 1) {
+    *nnz_exact = (double)A->n * (A->n + 1) / 2;
+    return LOBPCG_OK;
+  }
+  Symbolic S;
+  std::string err = analyze(A->n, A->rowptr, A->colind, A->grid, false, leaf_size > 0 ? leaf_size : 64, S);
+  if (!err.empty()) return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
+  std::vector<int32_t> prow, pcol, vmap;
+  permute_pattern(S, A->rowptr, A->colind, prow, pcol, vmap);
+  *nnz_exact = (double)exact_fill(A->n, prow, pcol);
   return LOBPCG_OK;
 }
 
@@ -1740,14 +2092,14 @@ lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t cc, int64_t ldw, int
   TempSeg T;
   if (!T.init(n)) return fail(LOBPCG_ERR_ALLOC, "hipMalloc failed");
   TsqrHost th;
-  build_tsqr(std::vector<int64_t>{0, n}, cc, tsqr_rows_per_block(cc, lower_step1 ? 4 : 8),
-             tsqr_upper_rows_per_block(cc, lower_step1 ? 4 : 8), th);
+  build_tsqr_plan(std::vector<int64_t>{0, n}, cc, lower_step1 ? 4 : 8, th);
   TsqrPlanDev tp{};
   tp.rb = th.rb;
   tp.rbu = th.rbu;
   tp.nlevels = (int)th.level_off.size() - 1;
   tp.level_off = th.level_off.data();
   tp.half = th.half;
+  tp.combine = th.combine;
   void* ws = T.get(2 * th.half * 8);
   void* Rl = T.get((int64_t)cc * cc * 8);
   double* Gv = (double*)T.get((int64_t)cc * cc * 8);
@@ -1782,7 +2134,7 @@ lobpcg_status lobpcg_mixed_qr_noalloc(double* W, int64_t n, int32_t cc, int64_t 
   build_segments(std::vector<int64_t>{0, n}, default_chunk_rows(n), H);
   const int eb = lower_step1 ? 4 : 8;
   TsqrHost th;
-  build_tsqr(std::vector<int64_t>{0, n}, cc, tsqr_rows_per_block(cc, eb), tsqr_upper_rows_per_block(cc, eb), th);
+  build_tsqr_plan(std::vector<int64_t>{0, n}, cc, eb, th);
   const int64_t nt = (int64_t)H.tile_inst.size(), nch = (int64_t)H.chunk_inst.size();
   const int64_t c2 = (int64_t)cc * cc;
   // layout of the scratch array (sizes first, so that too large a problem is rejected before any work)
@@ -1821,6 +2173,7 @@ lobpcg_status lobpcg_mixed_qr_noalloc(double* W, int64_t n, int32_t cc, int64_t 
   tp.nlevels = (int)th.level_off.size() - 1;
   tp.level_off = th.level_off.data();
   tp.half = th.half;
+  tp.combine = th.combine;
   tp.items = i32(o_items);
   // the plans into the array (ordinary copies on the stream; the host vectors outlive them because the
   // call synchronises the stream before it returns), the breakdown flag cleared by a kernel

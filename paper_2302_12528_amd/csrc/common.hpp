@@ -36,35 +36,54 @@ struct TsqrPlanDev {
   const int64_t* level_off;   // host, nlevels + 1
   const int32_t* items;       // device
   int64_t half;               // elements per scratch half
+  // combine = 1 (FP32 plans with c <= 32): three levels - the FP32 Householder leaves of kTsqrCombineRows
+  // rows (slots in the first scratch half), chunk items {instance, first slot, slots, partial} whose FP64
+  // Gram partials go to the second scratch half, and per-instance items {instance, first partial,
+  // partials, slot} that sum them (the sums follow the partials) and write their Cholesky factor as R
+  int combine;
 };
+constexpr int kTsqrCombineRows = 256;    // leaf rows of combining plans
+constexpr int kTsqrCombineSlots = 4;     // leaf factors per Gram chunk
 
-void launch_sgram(const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1, int c2,
+// Block element types TI / TX / TW: double (working precision) or float (the lower-precision first
+// stage of Algorithm 3 line 1); small matrices (G, M, theta, norms) are FP64 either way.
+template <typename TI>
+void launch_sgram(const SegDev& S, const TI* X, int64_t ldx, const TI* Y, int64_t ldy, int c1, int c2,
                   double* G, int64_t gstride, double* part, hipStream_t st);
-void launch_supdate(const SegDev& S, const double* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
-                    double* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st);
-template <typename T>
-void launch_sresidual(const SegDev& S, const double* AX, int64_t ldax, const double* X, int64_t ldx,
+template <typename TX>
+void launch_supdate(const SegDev& S, const TX* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
+                    TX* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st);
+template <typename T, typename TI>
+void launch_sresidual(const SegDev& S, const TI* AX, int64_t ldax, const TI* X, int64_t ldx,
                       const double* theta, int64_t tstride, int m, T* R, int64_t ldr, double* norms, double* part,
                       hipStream_t st);
-void launch_scolnorms(const SegDev& S, const double* X, int64_t ldx, int c, double* norms, int64_t nstride,
+template <typename TI>
+void launch_scolnorms(const SegDev& S, const TI* X, int64_t ldx, int c, double* norms, int64_t nstride,
                       double* part, hipStream_t st);
-template <typename TU>
-void launch_strsm_rows(const SegDev& S, double* W, int64_t ld, int c, const TU* U, int64_t ustride, hipStream_t st);
-template <typename T>
-void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const double* W, int64_t ldw, int c, T* scratch, T* R,
+template <typename TU, typename TW>
+void launch_strsm_rows(const SegDev& S, TW* W, int64_t ld, int c, const TU* U, int64_t ustride, hipStream_t st);
+template <typename T, typename Tin>
+void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const Tin* W, int64_t ldw, int c, T* scratch, T* R,
                   hipStream_t st);
 int tsqr_rows_per_block(int c, int elem_bytes);
 int tsqr_upper_rows_per_block(int c, int elem_bytes);
 
 // ---- products with A and data movement (k_block.hip) ----
-// Y = A X for permuted CSR A; X, Y n x c row-major (ld), any c >= 1.
-void launch_spmm_csr(const int32_t* rowptr, const int32_t* colind, const double* val, int64_t n,
-                     const double* X, int64_t ldx, double* Y, int64_t ldy, int c, hipStream_t st);
+// Y = A X for permuted CSR A; X, Y n x c row-major (ld), any c >= 1; T = double, or float for the
+// lower-precision first stage.
+template <typename T>
+void launch_spmm_csr(const int32_t* rowptr, const int32_t* colind, const T* val, int64_t n,
+                     const T* X, int64_t ldx, T* Y, int64_t ldy, int c, hipStream_t st);
 // Y = A X for dense row-major A (n x n, lda) on the FP64 matrix cores; part (part_elems doubles) holds
 // the partial products of split reduction ranges (dense_mm_scratch(n) covers every c <= 64 fully).
+// (T = float: the same on the FP32 matrix cores.)
 int64_t dense_mm_scratch(int64_t n);
-void launch_dense_mm(const double* A, int64_t lda, int64_t n, const double* X, int64_t ldx, double* Y,
-                     int64_t ldy, int c, double* part, int64_t part_elems, hipStream_t st);
+template <typename T>
+void launch_dense_mm(const T* A, int64_t lda, int64_t n, const T* X, int64_t ldx, T* Y,
+                     int64_t ldy, int c, T* part, int64_t part_elems, hipStream_t st);
+// dst[i*ldd + j] = (Tout) src[i*lds + j], i < n, j < c (IEEE round to nearest when narrowing)
+template <typename Tin, typename Tout>
+void launch_convert_block(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t n, int c, hipStream_t st);
 // dst[i*ldd + j] = src[(idx[i] - base)*lds + j], i < nrows, j < c (idx NULL = identity)
 void launch_gather_rows(const double* src, int64_t lds, const int32_t* idx, int64_t base, double* dst, int64_t ldd,
                         int64_t nrows, int c, hipStream_t st);

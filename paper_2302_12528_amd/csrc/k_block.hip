@@ -17,18 +17,18 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // ----------------------------------------------------------------------------
 // SpMM: a group of G lanes handles one row; lane j handles column blockIdx.y*G + j.
 // ----------------------------------------------------------------------------
-template <int G>
+template <int G, typename T>
 __global__ void __launch_bounds__(kThreads) spmm_csr_kernel(const int32_t* __restrict__ rowptr,
                                                             const int32_t* __restrict__ colind,
-                                                            const double* __restrict__ val, int64_t n,
-                                                            const double* __restrict__ X, int64_t ldx,
-                                                            double* __restrict__ Y, int64_t ldy, int c) {
+                                                            const T* __restrict__ val, int64_t n,
+                                                            const T* __restrict__ X, int64_t ldx,
+                                                            T* __restrict__ Y, int64_t ldy, int c) {
   const int lane = threadIdx.x % G;
   const int64_t row = (int64_t)blockIdx.x * (kThreads / G) + threadIdx.x / G;
   const int col = blockIdx.y * G + lane;
   if (row >= n || col >= c) return;
   const int32_t e0 = rowptr[row], e1 = rowptr[row + 1];
-  double acc = 0.0;
+  T acc = 0;
   for (int32_t e = e0; e < e1; ++e) acc = fma(val[e], X[(int64_t)colind[e] * ldx + col], acc);
   Y[row * ldy + col] = acc;
 }
@@ -36,31 +36,33 @@ __global__ void __launch_bounds__(kThreads) spmm_csr_kernel(const int32_t* __res
 // Two columns per lane with 16-byte loads and stores (c, ldx, ldy even, X and Y 16-byte aligned):
 // a group of G lanes covers 2G columns of one row; the entries of a row are fetched four at a
 // time so that four row gathers of X are in flight per lane.  Each output is the same fma chain
-// in entry order as the one-column kernel.
-template <int G>
+// in entry order as the one-column kernel.  (FP32, for the lower-precision first stage: 8-byte
+// accesses, the same structure.)
+template <int G, typename T>
 __global__ void __launch_bounds__(kThreads) spmm_csr2_kernel(const int32_t* __restrict__ rowptr,
                                                              const int32_t* __restrict__ colind,
-                                                             const double* __restrict__ val, int64_t n,
-                                                             const double* __restrict__ X, int64_t ldx,
-                                                             double* __restrict__ Y, int64_t ldy, int c) {
+                                                             const T* __restrict__ val, int64_t n,
+                                                             const T* __restrict__ X, int64_t ldx,
+                                                             T* __restrict__ Y, int64_t ldy, int c) {
+  typedef T V2 __attribute__((ext_vector_type(2)));
   const int lane = threadIdx.x % G;
   const int64_t row = (int64_t)blockIdx.x * (kThreads / G) + threadIdx.x / G;
   const int col = (blockIdx.y * G + lane) * 2;
   if (row >= n || col >= c) return;
   const int32_t e0 = rowptr[row], e1 = rowptr[row + 1];
-  double ax = 0.0, ay = 0.0;
+  T ax = 0, ay = 0;
   int32_t e = e0;
   for (; e + 4 <= e1; e += 4) {
     int32_t j[4];
-    double v[4];
-    double2 x[4];
+    T v[4];
+    V2 x[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       j[q] = colind[e + q];
       v[q] = val[e + q];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[q] = *reinterpret_cast<const double2*>(X + (int64_t)j[q] * ldx + col);
+    for (int q = 0; q < 4; ++q) x[q] = *reinterpret_cast<const V2*>(X + (int64_t)j[q] * ldx + col);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       ax = fma(v[q], x[q].x, ax);
@@ -68,12 +70,12 @@ __global__ void __launch_bounds__(kThreads) spmm_csr2_kernel(const int32_t* __re
     }
   }
   for (; e < e1; ++e) {
-    const double v = val[e];
-    const double2 x = *reinterpret_cast<const double2*>(X + (int64_t)colind[e] * ldx + col);
+    const T v = val[e];
+    const V2 x = *reinterpret_cast<const V2*>(X + (int64_t)colind[e] * ldx + col);
     ax = fma(v, x.x, ax);
     ay = fma(v, x.y, ay);
   }
-  *reinterpret_cast<double2*>(Y + row * ldy + col) = make_double2(ax, ay);
+  *reinterpret_cast<V2*>(Y + row * ldy + col) = V2{ax, ay};
 }
 
 // ----------------------------------------------------------------------------
@@ -89,15 +91,16 @@ __global__ void __launch_bounds__(kThreads) spmm_csr2_kernel(const int32_t* __re
 // ----------------------------------------------------------------------------
 constexpr int kMmRows = 128, kMmK = 32, kMmLdA = kMmK + 2, kMmLdX = 64 + 16, kMmThreads = 512;
 
-template <bool VEC>
-__global__ void __launch_bounds__(kMmThreads) dense_mm_kernel(const double* __restrict__ A, int64_t lda, int64_t n,
-                                                              const double* __restrict__ X, int64_t ldx,
-                                                              double* __restrict__ Y, int64_t ldy, int c,
-                                                              int64_t kspan, double* __restrict__ part) {
-  typedef Mfma<double> MF;
-  typedef MF::v4 V4;
-  __shared__ __align__(16) double As[kMmRows][kMmLdA];
-  __shared__ __align__(16) double Xs[kMmK][kMmLdX];
+template <bool VEC, typename T>
+__global__ void __launch_bounds__(kMmThreads) dense_mm_kernel(const T* __restrict__ A, int64_t lda, int64_t n,
+                                                              const T* __restrict__ X, int64_t ldx,
+                                                              T* __restrict__ Y, int64_t ldy, int c,
+                                                              int64_t kspan, T* __restrict__ part) {
+  typedef Mfma<T> MF;
+  typedef typename MF::v4 V4;
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  __shared__ __align__(16) T As[kMmRows][kMmLdA];
+  __shared__ __align__(16) T Xs[kMmK][kMmLdX];
   const int t = threadIdx.x, lane = t % 64, w = t / 64, i = lane % 16, g = lane / 16;
   const int64_t r0 = (int64_t)blockIdx.x * kMmRows;
   const int c0 = blockIdx.y * 64;
@@ -105,17 +108,17 @@ __global__ void __launch_bounds__(kMmThreads) dense_mm_kernel(const double* __re
   const int64_t ke = min(n, kb + kspan);
   // loaders: A pair e = t + 512 q (q < 4) is row e / 16, reduction pair e % 16; X pair e = t + 512 q
   // (q < 2) is reduction row e / 32, column pair e % 32
-  double2 ra[4], rx[2];
+  V2 ra[4], rx[2];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = t + kMmThreads * q;
       const int64_t r = r0 + e / 16, k = k0 + 2 * (e % 16);
-      double2 v = make_double2(0.0, 0.0);
+      V2 v = V2{0, 0};
       if (r < n) {
-        const double* src = A + r * lda + k;
+        const T* src = A + r * lda + k;
         if (VEC && k + 1 < ke) {
-          v = *reinterpret_cast<const double2*>(src);
+          v = *reinterpret_cast<const V2*>(src);
         } else {
           if (k < ke) v.x = src[0];
           if (k + 1 < ke) v.y = src[1];
@@ -128,11 +131,11 @@ __global__ void __launch_bounds__(kMmThreads) dense_mm_kernel(const double* __re
       const int e = t + kMmThreads * q;
       const int64_t k = k0 + e / 32;
       const int col = c0 + 2 * (e % 32);
-      double2 v = make_double2(0.0, 0.0);
+      V2 v = V2{0, 0};
       if (k < ke) {
-        const double* src = X + k * ldx + col;
+        const T* src = X + k * ldx + col;
         if (VEC && col + 1 < c) {
-          v = *reinterpret_cast<const double2*>(src);
+          v = *reinterpret_cast<const V2*>(src);
         } else {
           if (col < c) v.x = src[0];
           if (col + 1 < c) v.y = src[1];
@@ -150,24 +153,24 @@ __global__ void __launch_bounds__(kMmThreads) dense_mm_kernel(const double* __re
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = t + kMmThreads * q;
-      *reinterpret_cast<double2*>(&As[e / 16][2 * (e % 16)]) = ra[q];
+      *reinterpret_cast<V2*>(&As[e / 16][2 * (e % 16)]) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int e = t + kMmThreads * q;
-      *reinterpret_cast<double2*>(&Xs[e / 32][2 * (e % 32)]) = rx[q];
+      *reinterpret_cast<V2*>(&Xs[e / 32][2 * (e % 32)]) = rx[q];
     }
     __syncthreads();
     if (k0 + kMmK < ke) load(k0 + kMmK);
 #pragma unroll
     for (int kk = 0; kk < kMmK; kk += 4) {
-      const double a = As[16 * w + i][kk + g];
+      const T a = As[16 * w + i][kk + g];
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[cb] = MF::op(a, Xs[kk + g][16 * cb + i], acc[cb]);
     }
   }
   const int cpad = gridDim.y * 64;
-  double* P = part ? part + (int64_t)blockIdx.z * n * cpad : nullptr;
+  T* P = part ? part + (int64_t)blockIdx.z * n * cpad : nullptr;
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
@@ -183,14 +186,15 @@ __global__ void __launch_bounds__(kMmThreads) dense_mm_kernel(const double* __re
 }
 
 // Y(r, col) = sum over z = 0 .. nz - 1, in order, of part[z](r, col)
-__global__ void __launch_bounds__(kThreads) dense_mm_reduce_kernel(const double* __restrict__ part, int nz,
+template <typename T>
+__global__ void __launch_bounds__(kThreads) dense_mm_reduce_kernel(const T* __restrict__ part, int nz,
                                                                    int64_t n, int c, int cpad,
-                                                                   double* __restrict__ Y, int64_t ldy) {
+                                                                   T* __restrict__ Y, int64_t ldy) {
   const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (e >= n * c) return;
   const int64_t r = e / c;
   const int col = (int)(e % c);
-  double s = 0.0;
+  T s = 0;
   for (int z = 0; z < nz; ++z) s += part[((int64_t)z * n + r) * cpad + col];
   Y[r * ldy + col] = s;
 }
@@ -253,6 +257,16 @@ __global__ void copy_block_kernel(const double* __restrict__ src, int64_t lds, d
   dst[i * ldd + j] = src[i * lds + j];
 }
 
+template <typename Tin, typename Tout>
+__global__ void convert_block_kernel(const Tin* __restrict__ src, int64_t lds, Tout* __restrict__ dst, int64_t ldd,
+                                     int64_t n, int c) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * c) return;
+  const int64_t i = e / c;
+  const int j = (int)(e % c);
+  dst[i * ldd + j] = (Tout)src[i * lds + j];
+}
+
 __global__ void sub_block_kernel(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
                                  int64_t ldd, int64_t n, int c) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -266,47 +280,54 @@ inline dim3 grid1(int64_t total) { return dim3((unsigned)((total + kThreads - 1)
 
 }  // namespace
 
-void launch_spmm_csr(const int32_t* rowptr, const int32_t* colind, const double* val, int64_t n, const double* X,
-                     int64_t ldx, double* Y, int64_t ldy, int c, hipStream_t st) {
+template <typename T>
+void launch_spmm_csr(const int32_t* rowptr, const int32_t* colind, const T* val, int64_t n, const T* X,
+                     int64_t ldx, T* Y, int64_t ldy, int c, hipStream_t st) {
   if (n <= 0 || c <= 0) return;
   const bool pairs = (c % 2 == 0) && (ldx % 2 == 0) && (ldy % 2 == 0) && ((uintptr_t)X % 16 == 0) &&
                      ((uintptr_t)Y % 16 == 0);
   if (pairs) {
     const int half = c / 2;
     if (half <= 4) {
-      spmm_csr2_kernel<4><<<dim3(ceil_div(n, kThreads / 4), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx,
+      spmm_csr2_kernel<4, T><<<dim3(ceil_div(n, kThreads / 4), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx,
                                                                                  Y, ldy, c);
     } else if (half <= 8) {
-      spmm_csr2_kernel<8><<<dim3(ceil_div(n, kThreads / 8), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx,
+      spmm_csr2_kernel<8, T><<<dim3(ceil_div(n, kThreads / 8), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx,
                                                                                  Y, ldy, c);
     } else if (half <= 16) {
-      spmm_csr2_kernel<16><<<dim3(ceil_div(n, kThreads / 16), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X,
+      spmm_csr2_kernel<16, T><<<dim3(ceil_div(n, kThreads / 16), 1), kThreads, 0, st>>>(rowptr, colind, val, n, X,
                                                                                    ldx, Y, ldy, c);
     } else {
-      spmm_csr2_kernel<32><<<dim3(ceil_div(n, kThreads / 32), ceil_div(half, 32)), kThreads, 0, st>>>(
+      spmm_csr2_kernel<32, T><<<dim3(ceil_div(n, kThreads / 32), ceil_div(half, 32)), kThreads, 0, st>>>(
           rowptr, colind, val, n, X, ldx, Y, ldy, c);
     }
     return;
   }
   if (c <= 8) {
     dim3 g(ceil_div(n, kThreads / 8), 1);
-    spmm_csr_kernel<8><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);
+    spmm_csr_kernel<8, T><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);
   } else if (c <= 16) {
     dim3 g(ceil_div(n, kThreads / 16), 1);
-    spmm_csr_kernel<16><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);
+    spmm_csr_kernel<16, T><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);
   } else if (c <= 32) {
     dim3 g(ceil_div(n, kThreads / 32), 1);
-    spmm_csr_kernel<32><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);
+    spmm_csr_kernel<32, T><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);
   } else {
     dim3 g(ceil_div(n, kThreads / 64), ceil_div(c, 64));
-    spmm_csr_kernel<64><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);
+    spmm_csr_kernel<64, T><<<g, kThreads, 0, st>>>(rowptr, colind, val, n, X, ldx, Y, ldy, c);
   }
 }
 
+template void launch_spmm_csr<double>(const int32_t*, const int32_t*, const double*, int64_t, const double*, int64_t,
+                                       double*, int64_t, int, hipStream_t);
+template void launch_spmm_csr<float>(const int32_t*, const int32_t*, const float*, int64_t, const float*, int64_t,
+                                      float*, int64_t, int, hipStream_t);
+
 int64_t dense_mm_scratch(int64_t n) { return (int64_t)kMmMaxSplits * n * 64; }
 
-void launch_dense_mm(const double* A, int64_t lda, int64_t n, const double* X, int64_t ldx, double* Y,
-                     int64_t ldy, int c, double* part, int64_t part_elems, hipStream_t st) {
+template <typename T>
+void launch_dense_mm(const T* A, int64_t lda, int64_t n, const T* X, int64_t ldx, T* Y,
+                     int64_t ldy, int c, T* part, int64_t part_elems, hipStream_t st) {
   if (n <= 0 || c <= 0) return;
   const int rt = ceil_div(n, kMmRows), ct = ceil_div(c, 64);
   // split the reduction range until about 512 workgroups are in flight (two per compute unit), as far
@@ -318,14 +339,29 @@ void launch_dense_mm(const double* A, int64_t lda, int64_t n, const double* X, i
   const int64_t kspan = (int64_t)ceil_div(ceil_div(n, nz), kMmK) * kMmK;
   nz = ceil_div(n, kspan);
   const bool vec = ((lda | ldx) % 2 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)X % 16 == 0);
-  double* P = (nz > 1) ? part : nullptr;
+  T* P = (nz > 1) ? part : nullptr;
   dim3 g(rt, ct, (unsigned)nz);
   if (vec)
-    dense_mm_kernel<true><<<g, kMmThreads, 0, st>>>(A, lda, n, X, ldx, Y, ldy, c, kspan, P);
+    dense_mm_kernel<true, T><<<g, kMmThreads, 0, st>>>(A, lda, n, X, ldx, Y, ldy, c, kspan, P);
   else
-    dense_mm_kernel<false><<<g, kMmThreads, 0, st>>>(A, lda, n, X, ldx, Y, ldy, c, kspan, P);
-  if (P) dense_mm_reduce_kernel<<<grid1(n * c), kThreads, 0, st>>>(P, (int)nz, n, c, ct * 64, Y, ldy);
+    dense_mm_kernel<false, T><<<g, kMmThreads, 0, st>>>(A, lda, n, X, ldx, Y, ldy, c, kspan, P);
+  if (P) dense_mm_reduce_kernel<T><<<grid1(n * c), kThreads, 0, st>>>(P, (int)nz, n, c, ct * 64, Y, ldy);
 }
+template void launch_dense_mm<double>(const double*, int64_t, int64_t, const double*, int64_t, double*, int64_t, int,
+                                      double*, int64_t, hipStream_t);
+template void launch_dense_mm<float>(const float*, int64_t, int64_t, const float*, int64_t, float*, int64_t, int,
+                                     float*, int64_t, hipStream_t);
+
+template <typename Tin, typename Tout>
+void launch_convert_block(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t n, int c, hipStream_t st) {
+  if (n <= 0 || c <= 0) return;
+  convert_block_kernel<Tin, Tout><<<grid1(n * c), kThreads, 0, st>>>(src, lds, dst, ldd, n, c);
+}
+template void launch_convert_block<double, float>(const double*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+template void launch_convert_block<float, double>(const float*, int64_t, double*, int64_t, int64_t, int, hipStream_t);
+template void launch_convert_block<float, float>(const float*, int64_t, float*, int64_t, int64_t, int, hipStream_t);
+template void launch_convert_block<double, double>(const double*, int64_t, double*, int64_t, int64_t, int,
+                                                   hipStream_t);
 
 void launch_gather_rows(const double* src, int64_t lds, const int32_t* idx, int64_t base, double* dst, int64_t ldd,
                         int64_t nrows, int c, hipStream_t st) {

@@ -27,12 +27,12 @@ inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // v_mfma_f64_16x16x4f64 over 4 rows at a time.  Lane (i, g) = (l % 16, l / 16) reads row r + g,
 // columns 16 b + i, of X and Y directly (16 consecutive doubles per row and lane group).
 // ---------------------------------------------------------------------------
-template <int RB, int CB>
-__global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const double* __restrict__ X, int64_t ldx,
-                                                                 const double* __restrict__ Y, int64_t ldy, int c1,
+template <int RB, int CB, typename TI>
+__global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const TI* __restrict__ X, int64_t ldx,
+                                                                 const TI* __restrict__ Y, int64_t ldy, int c1,
                                                                  int c2, int tiles_j, double* __restrict__ part) {
-  typedef Mfma<double> MF;
-  typedef MF::v4 V4;
+  typedef Mfma<TI> MF;
+  typedef typename MF::v4 V4;
   constexpr int T1 = 32 * RB, T2 = 32 * CB;
   const int q = blockIdx.x;
   const int b = S.chunk_inst[q];
@@ -54,19 +54,19 @@ __global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const
   for (int u = 0; u < RB; ++u) xc[u] = (ci0 + 16 * u + i < c1);
 #pragma unroll
   for (int v = 0; v < CB; ++v) yc[v] = (cj0 + 16 * v + i < c2);
-  const double* xp = X + ci0 + i;
-  const double* yp = Y + cj0 + i;
+  const TI* xp = X + ci0 + i;
+  const TI* yp = Y + cj0 + i;
   constexpr int U = 4;   // 4-row steps whose loads are issued together
   for (int64_t r0 = rbeg; r0 < rend; r0 += 4 * U) {
-    double xa[U][RB], yb[U][CB];
+    TI xa[U][RB], yb[U][CB];
 #pragma unroll
     for (int s = 0; s < U; ++s) {
       const int64_t r = r0 + 4 * s + g;
       const bool rok = r < rend;
 #pragma unroll
-      for (int u = 0; u < RB; ++u) xa[s][u] = (rok && xc[u]) ? xp[r * ldx + 16 * u] : 0.0;
+      for (int u = 0; u < RB; ++u) xa[s][u] = (rok && xc[u]) ? xp[r * ldx + 16 * u] : (TI)0;
 #pragma unroll
-      for (int v = 0; v < CB; ++v) yb[s][v] = (rok && yc[v]) ? yp[r * ldy + 16 * v] : 0.0;
+      for (int v = 0; v < CB; ++v) yb[s][v] = (rok && yc[v]) ? yp[r * ldy + 16 * v] : (TI)0;
     }
 #pragma unroll
     for (int s = 0; s < U; ++s)
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const
       for (int e = 0; e < 4; ++e) {
         const int gi = ci0 + 16 * u + MF::drow(lane, e);
         const int gj = cj0 + 16 * v + i;
-        if (gi < c1 && gj < c2) P[gi * c2 + gj] = acc[u][v][e];
+        if (gi < c1 && gj < c2) P[gi * c2 + gj] = (double)acc[u][v][e];
       }
 }
 
@@ -122,19 +122,20 @@ __global__ void __launch_bounds__(256) sreduce_kernel(SegDev S, const double* __
 }
 
 // ---------------------------------------------------------------------------
-// Block update on one 64-row tile: Y = alpha X M_b + beta Y (64 x 64 output tile).  X (64 rows x
-// 16 reduction columns) and M (16 x 64) are staged through LDS with coalesced loads; wave w
-// accumulates output rows 16 w .. 16 w + 15 over all four 16-column blocks with
-// v_mfma_f64_16x16x4f64.
+// Block update on one 64-row tile: Y = alpha X M_b + beta Y (64 x 64 output tile) in the blocks'
+// precision TX (M is FP64 and rounded to TX).  X (64 rows x 16 reduction columns) and M (16 x 64) are
+// staged through LDS with coalesced loads; wave w accumulates output rows 16 w .. 16 w + 15 over all
+// four 16-column blocks with 16x16x4 MFMAs in TX.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const double* X, int64_t ldx,
+template <typename TX>
+__global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const TX* X, int64_t ldx,
                                                            const double* __restrict__ M, int64_t ldm, int64_t mstride,
-                                                           double* Y, int64_t ldy, int K, int cols, double alpha,
+                                                           TX* Y, int64_t ldy, int K, int cols, double alpha,
                                                            double beta) {
-  typedef Mfma<double> MF;
-  typedef MF::v4 V4;
-  __shared__ double As[16][65];   // As[k][row]
-  __shared__ double Bs[16][65];   // Bs[k][col]
+  typedef Mfma<TX> MF;
+  typedef typename MF::v4 V4;
+  __shared__ TX As[16][65];   // As[k][row]
+  __shared__ TX Bs[16][65];   // Bs[k][col]
   const int q = blockIdx.x;
   const int b = S.tile_inst[q];
   if (!S.active[b]) return;
@@ -151,13 +152,13 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const doubl
   const int lr = t / 4, lk = (t % 4) * 4;   // X loader: row lr, reduction columns lk .. lk + 3
   const int bk = t / 16, bc = (t % 16) * 4; // M loader: reduction row bk, columns bc .. bc + 3
   for (int k0 = 0; k0 < K; k0 += 16) {
-    double xa[4], mb[4];
+    TX xa[4], mb[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + lk + u;
-      xa[u] = (lr < rows && k < K) ? X[(r0 + lr) * ldx + k] : 0.0;
+      xa[u] = (lr < rows && k < K) ? X[(r0 + lr) * ldx + k] : (TX)0;
       const int kb = k0 + bk, cc = c0 + bc + u;
-      mb[u] = (kb < K && cc < cols) ? Mb[(int64_t)kb * ldm + cc] : 0.0;
+      mb[u] = (kb < K && cc < cols) ? (TX)Mb[(int64_t)kb * ldm + cc] : (TX)0;
     }
     __syncthreads();
 #pragma unroll
@@ -168,7 +169,7 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const doubl
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
-      const double av = As[kk + g][16 * w + i];
+      const TX av = As[kk + g][16 * w + i];
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[cb] = MF::op(av, Bs[kk + g][16 * cb + i], acc[cb]);
     }
@@ -180,8 +181,8 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const doubl
       const int r = 16 * w + MF::drow(lane, e);
       const int cc = c0 + 16 * cb + i;
       if (r >= rows || cc >= cols) continue;
-      double v = alpha * acc[cb][e];
-      if (beta != 0.0) v = fma(beta, Y[(r0 + r) * ldy + cc], v);
+      TX v = (TX)alpha * acc[cb][e];
+      if (beta != 0.0) v = fma((TX)beta, Y[(r0 + r) * ldy + cc], v);
       Y[(r0 + r) * ldy + cc] = v;
     }
 }
@@ -189,9 +190,9 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const doubl
 // ---------------------------------------------------------------------------
 // Residual over one chunk: R = AX - X diag(theta_b) (cast to T), partial column sums of squares.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kThreads) sresidual_kernel(SegDev S, const double* __restrict__ AX, int64_t ldax,
-                                                             const double* __restrict__ X, int64_t ldx,
+template <typename T, typename TI>
+__global__ void __launch_bounds__(kThreads) sresidual_kernel(SegDev S, const TI* __restrict__ AX, int64_t ldax,
+                                                             const TI* __restrict__ X, int64_t ldx,
                                                              const double* __restrict__ theta, int64_t tstride,
                                                              int m, T* __restrict__ R, int64_t ldr,
                                                              double* __restrict__ part) {
@@ -205,13 +206,13 @@ __global__ void __launch_bounds__(kThreads) sresidual_kernel(SegDev S, const dou
   const int64_t rend = rbeg + S.chunk_rows[q];
   double rs = 0.0, xs = 0.0;
   if (j < m) {
-    const double th = theta[(int64_t)b * tstride + j];
+    const TI th = (TI)theta[(int64_t)b * tstride + j];
     for (int64_t r = rbeg + g; r < rend; r += 4) {
-      const double x = X[r * ldx + j];
-      const double v = AX[r * ldax + j] - x * th;
+      const TI x = X[r * ldx + j];
+      const TI v = AX[r * ldax + j] - x * th;
       R[r * ldr + j] = (T)v;
-      rs = fma(v, v, rs);
-      xs = fma(x, x, xs);
+      rs = fma((double)v, (double)v, rs);
+      xs = fma((double)x, (double)x, xs);
     }
   }
   red[0][g][j] = rs;
@@ -226,9 +227,9 @@ __global__ void __launch_bounds__(kThreads) sresidual_kernel(SegDev S, const dou
 // The same residual with two columns per lane (16-byte loads of X and AX, 8-byte stores of R): a
 // row is read by CPL = m / 2 consecutive lanes, a wave covers 64 / CPL rows per step and four steps
 // are loaded together.  Per-lane partial sums go through LDS and are added in a fixed order.
-template <typename T, int CPL>
-__global__ void __launch_bounds__(kThreads) sresidual2_kernel(SegDev S, const double* __restrict__ AX, int64_t ldax,
-                                                              const double* __restrict__ X, int64_t ldx,
+template <typename T, int CPL, typename TI>
+__global__ void __launch_bounds__(kThreads) sresidual2_kernel(SegDev S, const TI* __restrict__ AX, int64_t ldax,
+                                                              const TI* __restrict__ X, int64_t ldx,
                                                               const double* __restrict__ theta, int64_t tstride,
                                                               T* __restrict__ R, int64_t ldr,
                                                               double* __restrict__ part) {
@@ -241,33 +242,34 @@ __global__ void __launch_bounds__(kThreads) sresidual2_kernel(SegDev S, const do
   const int jp = lane % CPL, rl = lane / CPL;
   const int64_t rbeg = S.chunk_r0[q];
   const int64_t rend = rbeg + S.chunk_rows[q];
-  const double th0 = theta[(int64_t)b * tstride + 2 * jp], th1 = theta[(int64_t)b * tstride + 2 * jp + 1];
+  typedef TI V2 __attribute__((ext_vector_type(2)));
+  const TI th0 = (TI)theta[(int64_t)b * tstride + 2 * jp], th1 = (TI)theta[(int64_t)b * tstride + 2 * jp + 1];
   double rs0 = 0.0, rs1 = 0.0, xs0 = 0.0, xs1 = 0.0;
   for (int64_t r0 = rbeg + w * RPW + rl; r0 < rend; r0 += (int64_t)U * RPB) {
-    f64x2_t xv[U], av[U];
+    V2 xv[U], av[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t r = r0 + (int64_t)u * RPB;
       if (r < rend) {
-        xv[u] = *reinterpret_cast<const f64x2_t*>(X + r * ldx + 2 * jp);
-        av[u] = *reinterpret_cast<const f64x2_t*>(AX + r * ldax + 2 * jp);
+        xv[u] = *reinterpret_cast<const V2*>(X + r * ldx + 2 * jp);
+        av[u] = *reinterpret_cast<const V2*>(AX + r * ldax + 2 * jp);
       } else {
-        xv[u] = f64x2_t{0.0, 0.0};
-        av[u] = f64x2_t{0.0, 0.0};
+        xv[u] = V2{0, 0};
+        av[u] = V2{0, 0};
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t r = r0 + (int64_t)u * RPB;
-      const double v0 = av[u].x - xv[u].x * th0, v1 = av[u].y - xv[u].y * th1;
+      const TI v0 = av[u].x - xv[u].x * th0, v1 = av[u].y - xv[u].y * th1;
       if (r < rend) {
         R[r * ldr + 2 * jp] = (T)v0;
         R[r * ldr + 2 * jp + 1] = (T)v1;
       }
-      rs0 = fma(v0, v0, rs0);
-      rs1 = fma(v1, v1, rs1);
-      xs0 = fma(xv[u].x, xv[u].x, xs0);
-      xs1 = fma(xv[u].y, xv[u].y, xs1);
+      rs0 = fma((double)v0, (double)v0, rs0);
+      rs1 = fma((double)v1, (double)v1, rs1);
+      xs0 = fma((double)xv[u].x, (double)xv[u].x, xs0);
+      xs1 = fma((double)xv[u].y, (double)xv[u].y, xs1);
     }
   }
   red[w][rl][2 * jp][0] = rs0;
@@ -284,7 +286,8 @@ __global__ void __launch_bounds__(kThreads) sresidual2_kernel(SegDev S, const do
   }
 }
 
-__global__ void __launch_bounds__(kThreads) scolnorm_kernel(SegDev S, const double* __restrict__ X, int64_t ldx,
+template <typename TI>
+__global__ void __launch_bounds__(kThreads) scolnorm_kernel(SegDev S, const TI* __restrict__ X, int64_t ldx,
                                                             int c, double* __restrict__ part) {
   __shared__ double red[4][64];
   const int q = blockIdx.x;
@@ -297,7 +300,7 @@ __global__ void __launch_bounds__(kThreads) scolnorm_kernel(SegDev S, const doub
   double xs = 0.0;
   if (j < c)
     for (int64_t r = rbeg + g; r < rend; r += 4) {
-      const double x = X[r * ldx + j];
+      const double x = (double)X[r * ldx + j];
       xs = fma(x, x, xs);
     }
   red[g][j] = xs;
@@ -308,8 +311,8 @@ __global__ void __launch_bounds__(kThreads) scolnorm_kernel(SegDev S, const doub
 // ---------------------------------------------------------------------------
 // Row-wise triangular solve on one 64-row tile: W_b <- W_b U_b^{-1}.
 // ---------------------------------------------------------------------------
-template <typename TU>
-__global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, double* W, int64_t ld, int c,
+template <typename TU, typename TW>
+__global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, TW* W, int64_t ld, int c,
                                                         const TU* __restrict__ U, int64_t ustride) {
   extern __shared__ double smem[];
   double* Us = smem;            // c x c
@@ -324,7 +327,7 @@ __global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, double* W, int
   for (int e = t; e < c * c; e += 64) Us[e] = (double)Ub[e];
   for (int e = t; e < 64 * c; e += 64) {
     const int i = e / c, j = e % c;
-    Ws[j * 64 + i] = (i < rows) ? W[(r0 + i) * ld + j] : 0.0;
+    Ws[j * 64 + i] = (i < rows) ? (double)W[(r0 + i) * ld + j] : 0.0;
   }
   __syncthreads();
   for (int j = 0; j < c; ++j) {
@@ -336,15 +339,16 @@ __global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, double* W, int
   __syncthreads();
   for (int e = t; e < 64 * c; e += 64) {
     const int i = e / c, j = e % c;
-    if (i < rows) W[(r0 + i) * ld + j] = Ws[j * 64 + i];
+    if (i < rows) W[(r0 + i) * ld + j] = (TW)Ws[j * 64 + i];
   }
 }
 
 // The same solve for c == CP columns with the row in registers (fully unrolled), one row per
 // thread: U_b is read through the scalar cache (all lanes use the same element), so nothing is
-// staged in LDS and many tiles share a compute unit.
-template <typename TU, int CP>
-__global__ void __launch_bounds__(64) strsm_rows_reg_kernel(SegDev S, double* W, int64_t ld,
+// staged in LDS and many tiles share a compute unit.  Arithmetic in FP64 for FP64 blocks, in the
+// blocks' precision otherwise.
+template <typename TU, int CP, typename TW>
+__global__ void __launch_bounds__(64) strsm_rows_reg_kernel(SegDev S, TW* W, int64_t ld,
                                                             const TU* __restrict__ U, int64_t ustride) {
   const int q = blockIdx.x;
   const int b = S.tile_inst[q];
@@ -354,15 +358,15 @@ __global__ void __launch_bounds__(64) strsm_rows_reg_kernel(SegDev S, double* W,
   const TU* Ub = U + (int64_t)b * ustride;
   const int t = threadIdx.x;
   if (t >= rows) return;
-  double* row = W + (r0 + t) * ld;
-  double x[CP];
+  TW* row = W + (r0 + t) * ld;
+  TW x[CP];
 #pragma unroll
   for (int k = 0; k < CP; ++k) x[k] = row[k];
 #pragma unroll
   for (int j = 0; j < CP; ++j) {
-    x[j] /= (double)Ub[j * CP + j];
+    x[j] /= (TW)Ub[j * CP + j];
 #pragma unroll
-    for (int k = j + 1; k < CP; ++k) x[k] -= x[j] * (double)Ub[j * CP + k];
+    for (int k = j + 1; k < CP; ++k) x[k] -= x[j] * (TW)Ub[j * CP + k];
   }
 #pragma unroll
   for (int k = 0; k < CP; ++k) row[k] = x[k];
@@ -378,6 +382,7 @@ __global__ void __launch_bounds__(64) strsm_rows_reg_kernel(SegDev S, double* W,
 // ---------------------------------------------------------------------------
 constexpr int kTsqrRows = 256;
 constexpr int kTsqrRowsWide = 1024;   // FP32 blocks of the upper levels (stacked R factors), c <= 32
+constexpr int kTsqrCombineRpl = kTsqrCombineRows / 64;   // rows per lane of the leaves of combining plans
 
 template <typename T, typename Tin, int CP, int NR = kTsqrRows>
 __global__ void __launch_bounds__(NR) stsqr_kernel(SegDev S, const Tin* in, int64_t ldin,
@@ -492,13 +497,20 @@ __device__ inline float lane_value(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
 
+__device__ inline double lane_f64(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // TSQR block in FP32 by one wave, four blocks per workgroup, no barriers: lane l holds rows l, l + 64,
-// l + 128, l + 192 of the block in registers.  Column j is always register column 0: after each
+// ..., l + 64 (RPL - 1) of the block (at most 64 RPL rows) in registers.  Column j is always register column 0: after each
 // Householder step the remaining columns move one register to the left.  For column j the wave
 // all-reduce gives sigma = sum_{r > j} a_rj^2 and S_k = sum_{r > j} a_rj a_rk together; with
 // v = e_j + scale a(j+1:, j), w_k = a_jk + scale S_k and every row is updated in place.  Row j of R
 // is staged in LDS as it is produced.
-template <typename Tin, int CP>
+template <typename Tin, int CP, int RPL = 4>
 __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in, int64_t ldin,
                                                          const int32_t* __restrict__ items, int64_t nitems, int c,
                                                          float* out) {
@@ -512,9 +524,9 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
   const int64_t r0 = it[1];
   const int rows = it[2];
   const int slot = it[3];
-  float a[4][CP];
+  float a[RPL][CP];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < RPL; ++s) {
     const int r = 64 * s + lane;
 #pragma unroll
     for (int k = 0; k < CP; ++k) a[s][k] = (r < rows && k < c) ? (float)in[(r0 + r) * ldin + k] : 0.f;
@@ -527,7 +539,7 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
 #pragma unroll
     for (int k = 0; k < CP; ++k) q[k] = 0.f;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < RPL; ++s) {
       const float x = (64 * s + lane > j) ? a[s][0] : 0.f;
 #pragma unroll
       for (int k = 0; k < CP; ++k) q[k] += x * a[s][k];
@@ -546,7 +558,7 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
 #pragma unroll
       for (int k = 1; k < CP; ++k) w[k] = lane_value(a[0][k], j) + scale * qs[k];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
+      for (int s = 0; s < RPL; ++s) {
         const int r = 64 * s + lane;
         const float coef = (r > j) ? tau * scale * a[s][0] : ((r == j) ? tau : 0.f);
 #pragma unroll
@@ -560,7 +572,7 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
         if (j + k < CP) R[j][j + k] = a[0][k];
     }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < RPL; ++s) {
 #pragma unroll
       for (int k = 0; k + 1 < CP; ++k) a[s][k] = a[s][k + 1];
       a[s][CP - 1] = 0.f;
@@ -573,6 +585,124 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
   }
 }
 
+// Combining step of the TSQR tree for c <= 32 (FP32 plans): the R factor of the stacked leaf factors
+// [R_1; ...; R_q] is the Cholesky factor of sum_s R_s^T R_s.  The leaves are FP32, so every product
+// R_s(i, j) R_s(i, k) is exact in FP64 and the sums carry FP64 rounding only: the combined factor is
+// perturbed by O(kappa^2 u64), below the leaves' own O(kappa u32) for kappa < u32 / u64.
+// Partial sums: one workgroup per chunk item {instance, first slot, slots (<= kTsqrCombineSlots),
+// partial index}; wave w owns the 16 x 16 block (w / 2, w % 2) of the Gram matrix, accumulated by
+// v_mfma_f64_16x16x4f64 over the rows of the chunk's leaf factors (slot s occupies c x c FP32 at
+// in + s c^2).  All loads of the chunk are issued before the first product.
+__global__ void __launch_bounds__(256) tsqr_gram_partial_kernel(const SegDev S, const float* __restrict__ in,
+                                                                const int32_t* __restrict__ items, int c,
+                                                                double* __restrict__ part) {
+  typedef Mfma<double> MF;
+  typedef MF::v4 V4;
+  constexpr int STEPS = kTsqrCombineSlots * 32 / 16;   // 16 rows per step, at most 32 rows per slot
+  const int* it = items + 4 * blockIdx.x;
+  const int b = it[0];
+  if (!S.active[b]) return;
+  const int64_t s0 = it[1];
+  const int ns = it[2];
+  const int q = it[3];
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int i = lane % 16, g = lane / 16;
+  const int ci = 16 * (w / 2) + i, cj = 16 * (w % 2) + i;
+  const bool okc = (ci < c), okj = (cj < c);
+  const int rows = ns * c;
+  const float* base = in + s0 * c * c;
+  float xa[STEPS][4], yb[STEPS][4];
+#pragma unroll
+  for (int st = 0; st < STEPS; ++st)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 16 * st + 4 * u + g;
+      const bool ok = r < rows;
+      xa[st][u] = (ok && okc) ? base[(int64_t)r * c + ci] : 0.f;
+      yb[st][u] = (ok && okj) ? base[(int64_t)r * c + cj] : 0.f;
+    }
+  V4 acc = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int st = 0; st < STEPS; ++st)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = MF::op((double)xa[st][u], (double)yb[st][u], acc);
+  double* P = part + (int64_t)q * c * c;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int gi = 16 * (w / 2) + MF::drow(lane, e);
+    if (gi < c && okj) P[gi * c + cj] = acc[e];
+  }
+}
+
+// G_b = sum of instance b's partials {instance, first partial, partials, -} in a fixed order, written to
+// part[gbase + b]: a block takes 16 elements, its 16 thread groups every 16th partial each (four
+// independent sums), and the 16 group sums are added in order.
+__global__ void __launch_bounds__(256) tsqr_gram_reduce_kernel(const SegDev S, double* __restrict__ part,
+                                                               const int32_t* __restrict__ items, int len,
+                                                               int64_t gbase) {
+  __shared__ double red[kRedGroups][kRedElems];
+  const int* it = items + 4 * blockIdx.y;
+  const int b = it[0];
+  if (!S.active[b]) return;
+  const int q0 = it[1], q1 = it[1] + it[2];
+  const int g = threadIdx.x / kRedElems, l = threadIdx.x % kRedElems;
+  const int e = blockIdx.x * kRedElems + l;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (e < len) {
+    int q = q0 + g;
+    for (; q + 3 * kRedGroups < q1; q += 4 * kRedGroups) {
+      s0 += part[(int64_t)q * len + e];
+      s1 += part[(int64_t)(q + kRedGroups) * len + e];
+      s2 += part[(int64_t)(q + 2 * kRedGroups) * len + e];
+      s3 += part[(int64_t)(q + 3 * kRedGroups) * len + e];
+    }
+    for (; q < q1; q += kRedGroups) s0 += part[(int64_t)q * len + e];
+  }
+  red[g][l] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (g == 0 && e < len) {
+    double t = 0.0;
+#pragma unroll
+    for (int h = 0; h < kRedGroups; ++h) t += red[h][l];
+    part[(gbase + b) * len + e] = t;
+  }
+}
+
+// Cholesky factor of G_b (at part[gbase + b]) by one wave (lane i holds row i), written as the upper
+// triangular R (FP32, c x c at out + slot c^2) for item {instance, -, -, slot}.  A non-positive pivot
+// (lower(W) numerically rank deficient) is replaced by 1, which keeps R nonsingular: W R^{-1} then spans
+// span(W) and the Cholesky of Algorithm 2 step 3 reports the breakdown.
+template <int CP>
+__global__ void __launch_bounds__(64) tsqr_combine_chol_kernel(const SegDev S, const double* __restrict__ part,
+                                                               const int32_t* __restrict__ items, int c,
+                                                               int64_t gbase, float* __restrict__ out) {
+  const int* it = items + 4 * blockIdx.x;
+  const int b = it[0];
+  if (!S.active[b]) return;
+  const int slot = it[3];
+  const int i = threadIdx.x;
+  const int64_t cc = (int64_t)c * c;
+  const double* G = part + (gbase + b) * cc;
+  double a[CP];
+#pragma unroll
+  for (int k = 0; k < CP; ++k) a[k] = (i < c && k < c) ? 0.5 * (G[i * c + k] + G[k * c + i]) : 0.0;
+#pragma unroll
+  for (int j = 0; j < CP; ++j) {
+    if (j < c) {   // uniform
+      double d = lane_f64(a[j], j);
+      if (!(d > 0.0) || !isfinite(d)) d = 1.0;
+      const double ljj = sqrt(d);
+      a[j] = (i == j) ? ljj : a[j] / ljj;
+#pragma unroll
+      for (int k = j + 1; k < CP; ++k) a[k] -= a[j] * lane_f64(a[j], k);
+    }
+  }
+  // row i of L is column i of R
+  float* R = out + (int64_t)slot * cc;
+  if (i < c)
+    for (int k = 0; k < c; ++k) R[k * c + i] = (k <= i) ? (float)a[k] : 0.f;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -581,13 +711,13 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
 namespace {
 inline int gram_rt(int c) { return c <= 32 ? 1 : c <= 64 ? 2 : 3; }
 
-template <int RB, int CB>
-void sgram_launch(dim3 g, const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1, int c2,
+template <int RB, int CB, typename TI>
+void sgram_launch(dim3 g, const SegDev& S, const TI* X, int64_t ldx, const TI* Y, int64_t ldy, int c1, int c2,
                   int tj, double* part, hipStream_t st) {
-  sgram_partial_kernel<RB, CB><<<g, kThreads, 0, st>>>(S, X, ldx, Y, ldy, c1, c2, tj, part);
+  sgram_partial_kernel<RB, CB, TI><<<g, kThreads, 0, st>>>(S, X, ldx, Y, ldy, c1, c2, tj, part);
 }
-template <int RB>
-void sgram_ct(int ct, dim3 g, const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1,
+template <int RB, typename TI>
+void sgram_ct(int ct, dim3 g, const SegDev& S, const TI* X, int64_t ldx, const TI* Y, int64_t ldy, int c1,
               int c2, int tj, double* part, hipStream_t st) {
   switch (ct) {
     case 1: sgram_launch<RB, 1>(g, S, X, ldx, Y, ldy, c1, c2, tj, part, st); break;
@@ -597,7 +727,8 @@ void sgram_ct(int ct, dim3 g, const SegDev& S, const double* X, int64_t ldx, con
 }
 }  // namespace
 
-void launch_sgram(const SegDev& S, const double* X, int64_t ldx, const double* Y, int64_t ldy, int c1, int c2,
+template <typename TI>
+void launch_sgram(const SegDev& S, const TI* X, int64_t ldx, const TI* Y, int64_t ldy, int c1, int c2,
                   double* G, int64_t gstride, double* part, hipStream_t st) {
   if (c1 <= 0 || c2 <= 0 || S.nchunks <= 0) return;
   const int rt = gram_rt(c1), ct = gram_rt(c2);
@@ -611,52 +742,74 @@ void launch_sgram(const SegDev& S, const double* X, int64_t ldx, const double* Y
   const int len = c1 * c2;
   sreduce_kernel<<<dim3(cdiv(len, kRedElems), S.B), 256, 0, st>>>(S, part, len, G, gstride);
 }
+template void launch_sgram<double>(const SegDev&, const double*, int64_t, const double*, int64_t, int, int, double*,
+                                   int64_t, double*, hipStream_t);
+template void launch_sgram<float>(const SegDev&, const float*, int64_t, const float*, int64_t, int, int, double*,
+                                  int64_t, double*, hipStream_t);
 
-void launch_supdate(const SegDev& S, const double* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
-                    double* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st) {
+template <typename TX>
+void launch_supdate(const SegDev& S, const TX* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
+                    TX* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st) {
   if (cout <= 0 || S.ntiles <= 0) return;
   dim3 g((unsigned)S.ntiles, cdiv(cout, 64));
-  supdate_kernel<<<g, kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin, cout, alpha, beta);
+  supdate_kernel<TX><<<g, kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin, cout, alpha, beta);
 }
+template void launch_supdate<double>(const SegDev&, const double*, int64_t, const double*, int64_t, int64_t, double*,
+                                     int64_t, int, int, double, double, hipStream_t);
+template void launch_supdate<float>(const SegDev&, const float*, int64_t, const double*, int64_t, int64_t, float*,
+                                    int64_t, int, int, double, double, hipStream_t);
 
-template <typename T>
-void launch_sresidual(const SegDev& S, const double* AX, int64_t ldax, const double* X, int64_t ldx,
+template <typename T, typename TI>
+void launch_sresidual(const SegDev& S, const TI* AX, int64_t ldax, const TI* X, int64_t ldx,
                       const double* theta, int64_t tstride, int m, T* R, int64_t ldr, double* norms, double* part,
                       hipStream_t st) {
   if (S.nchunks <= 0) return;
   const bool vec = (ldx % 2 == 0) && (ldax % 2 == 0) && (ldr % 2 == 0) &&
                    ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(AX)) % 16 == 0);
   const unsigned g = (unsigned)S.nchunks;
-  if (vec && m == 32) sresidual2_kernel<T, 16><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
-  else if (vec && m == 16) sresidual2_kernel<T, 8><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
-  else if (vec && m == 8) sresidual2_kernel<T, 4><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
-  else sresidual_kernel<T><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, m, R, ldr, part);
+  if (vec && m == 32) sresidual2_kernel<T, 16, TI><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
+  else if (vec && m == 16) sresidual2_kernel<T, 8, TI><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
+  else if (vec && m == 8) sresidual2_kernel<T, 4, TI><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, R, ldr, part);
+  else sresidual_kernel<T, TI><<<g, kThreads, 0, st>>>(S, AX, ldax, X, ldx, theta, tstride, m, R, ldr, part);
   sreduce_kernel<<<dim3(cdiv(2 * m, kRedElems), S.B), 256, 0, st>>>(S, part, 2 * m, norms, 2 * m);
 }
-template void launch_sresidual<float>(const SegDev&, const double*, int64_t, const double*, int64_t, const double*,
-                                      int64_t, int, float*, int64_t, double*, double*, hipStream_t);
-template void launch_sresidual<double>(const SegDev&, const double*, int64_t, const double*, int64_t, const double*,
-                                       int64_t, int, double*, int64_t, double*, double*, hipStream_t);
+#define INST_RES(T, TI)                                                                                            \
+  template void launch_sresidual<T, TI>(const SegDev&, const TI*, int64_t, const TI*, int64_t, const double*, int64_t, \
+                                        int, T*, int64_t, double*, double*, hipStream_t);
+INST_RES(float, double)
+INST_RES(double, double)
+INST_RES(float, float)
+INST_RES(double, float)
+#undef INST_RES
 
-void launch_scolnorms(const SegDev& S, const double* X, int64_t ldx, int c, double* norms, int64_t nstride,
+template <typename TI>
+void launch_scolnorms(const SegDev& S, const TI* X, int64_t ldx, int c, double* norms, int64_t nstride,
                       double* part, hipStream_t st) {
   if (S.nchunks <= 0) return;
-  scolnorm_kernel<<<(unsigned)S.nchunks, kThreads, 0, st>>>(S, X, ldx, c, part);
+  scolnorm_kernel<TI><<<(unsigned)S.nchunks, kThreads, 0, st>>>(S, X, ldx, c, part);
   sreduce_kernel<<<dim3(cdiv(c, kRedElems), S.B), 256, 0, st>>>(S, part, c, norms, nstride);
 }
+template void launch_scolnorms<double>(const SegDev&, const double*, int64_t, int, double*, int64_t, double*,
+                                       hipStream_t);
+template void launch_scolnorms<float>(const SegDev&, const float*, int64_t, int, double*, int64_t, double*,
+                                      hipStream_t);
 
-template <typename TU>
-void launch_strsm_rows(const SegDev& S, double* W, int64_t ld, int c, const TU* U, int64_t ustride, hipStream_t st) {
+template <typename TU, typename TW>
+void launch_strsm_rows(const SegDev& S, TW* W, int64_t ld, int c, const TU* U, int64_t ustride, hipStream_t st) {
   if (S.ntiles <= 0) return;
   const size_t lds = (size_t)(c * c + 64 * c) * sizeof(double);
   const unsigned g = (unsigned)S.ntiles;
-  if (c == 8) strsm_rows_reg_kernel<TU, 8><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
-  else if (c == 16) strsm_rows_reg_kernel<TU, 16><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
-  else if (c == 32) strsm_rows_reg_kernel<TU, 32><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
-  else strsm_rows_kernel<TU><<<g, 64, lds, st>>>(S, W, ld, c, U, ustride);
+  if (c == 8) strsm_rows_reg_kernel<TU, 8, TW><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
+  else if (c == 16) strsm_rows_reg_kernel<TU, 16, TW><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
+  else if (c == 32) strsm_rows_reg_kernel<TU, 32, TW><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
+  else strsm_rows_kernel<TU, TW><<<g, 64, lds, st>>>(S, W, ld, c, U, ustride);
 }
-template void launch_strsm_rows<float>(const SegDev&, double*, int64_t, int, const float*, int64_t, hipStream_t);
-template void launch_strsm_rows<double>(const SegDev&, double*, int64_t, int, const double*, int64_t, hipStream_t);
+template void launch_strsm_rows<float, double>(const SegDev&, double*, int64_t, int, const float*, int64_t, hipStream_t);
+template void launch_strsm_rows<double, double>(const SegDev&, double*, int64_t, int, const double*, int64_t,
+                                                hipStream_t);
+template void launch_strsm_rows<float, float>(const SegDev&, float*, int64_t, int, const float*, int64_t, hipStream_t);
+template void launch_strsm_rows<double, float>(const SegDev&, float*, int64_t, int, const double*, int64_t,
+                                               hipStream_t);
 
 template <typename T, typename Tin, int CP>
 void stsqr_go(unsigned grid, const SegDev& S, const Tin* in, int64_t ld, const int32_t* items, int c, T* out,
@@ -683,16 +836,36 @@ void stsqr_launch(unsigned grid, const SegDev& S, const Tin* in, int64_t ld, con
   else stsqr_go<T, Tin, 64>(grid, S, in, ld, items, c, out, st);
 }
 
-template <typename T>
-void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const double* W, int64_t ldw, int c, T* scratch, T* R,
+template <typename T, typename Tin>
+void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const Tin* W, int64_t ldw, int c, T* scratch, T* R,
                   hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    if (P.combine) {   // FP32 leaves of kTsqrRowsCombine rows, then the FP64 Gram and its Cholesky factor
+      const int64_t i0 = P.level_off[0], i1 = P.level_off[1], i2 = P.level_off[2], i3 = P.level_off[3];
+      const unsigned g4 = (unsigned)((i1 - i0 + 3) / 4);
+      const int32_t* it0 = P.items + 4 * i0;
+      if (c <= 8) stsqr_wave_kernel<Tin, 8, kTsqrCombineRpl><<<g4, 256, 0, st>>>(S, W, ldw, it0, i1 - i0, c, scratch);
+      else if (c <= 16) stsqr_wave_kernel<Tin, 16, kTsqrCombineRpl><<<g4, 256, 0, st>>>(S, W, ldw, it0, i1 - i0, c, scratch);
+      else stsqr_wave_kernel<Tin, 32, kTsqrCombineRpl><<<g4, 256, 0, st>>>(S, W, ldw, it0, i1 - i0, c, scratch);
+      double* part = reinterpret_cast<double*>(scratch + P.half);
+      const int64_t gbase = i2 - i1;   // the per-instance Gram matrices follow the partials
+      const int32_t* it2 = P.items + 4 * i2;
+      tsqr_gram_partial_kernel<<<(unsigned)(i2 - i1), 256, 0, st>>>(S, scratch, P.items + 4 * i1, c, part);
+      tsqr_gram_reduce_kernel<<<dim3(cdiv(c * c, kRedElems), (unsigned)(i3 - i2)), 256, 0, st>>>(S, part, it2, c * c,
+                                                                                              gbase);
+      if (c <= 8) tsqr_combine_chol_kernel<8><<<(unsigned)(i3 - i2), 64, 0, st>>>(S, part, it2, c, gbase, R);
+      else if (c <= 16) tsqr_combine_chol_kernel<16><<<(unsigned)(i3 - i2), 64, 0, st>>>(S, part, it2, c, gbase, R);
+      else tsqr_combine_chol_kernel<32><<<(unsigned)(i3 - i2), 64, 0, st>>>(S, part, it2, c, gbase, R);
+      return;
+    }
+  }
   for (int l = 0; l < P.nlevels; ++l) {
     const int64_t i0 = P.level_off[l], i1 = P.level_off[l + 1];
     if (i1 <= i0) continue;
     T* out = (l == P.nlevels - 1) ? R : scratch + (l % 2) * P.half;
     const unsigned grid = (unsigned)(i1 - i0);
     if (l == 0) {
-      stsqr_launch<T, double>(grid, S, W, ldw, P.items + 4 * i0, c, out, st);
+      stsqr_launch<T, Tin>(grid, S, W, ldw, P.items + 4 * i0, c, out, st);
       continue;
     }
     const T* in = scratch + ((l - 1) % 2) * P.half;
@@ -707,10 +880,12 @@ void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const double* W, int64_
     stsqr_launch<T, T>(grid, S, in, c, P.items + 4 * i0, c, out, st);
   }
 }
-template void launch_stsqr<float>(const SegDev&, const TsqrPlanDev&, const double*, int64_t, int, float*, float*,
-                                  hipStream_t);
-template void launch_stsqr<double>(const SegDev&, const TsqrPlanDev&, const double*, int64_t, int, double*, double*,
-                                   hipStream_t);
+template void launch_stsqr<float, double>(const SegDev&, const TsqrPlanDev&, const double*, int64_t, int, float*,
+                                          float*, hipStream_t);
+template void launch_stsqr<double, double>(const SegDev&, const TsqrPlanDev&, const double*, int64_t, int, double*,
+                                           double*, hipStream_t);
+template void launch_stsqr<float, float>(const SegDev&, const TsqrPlanDev&, const float*, int64_t, int, float*, float*,
+                                         hipStream_t);
 
 int tsqr_rows_per_block(int c, int elem_bytes) {
   (void)c;

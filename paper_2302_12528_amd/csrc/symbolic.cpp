@@ -385,6 +385,36 @@ void assembly_positions(const Symbolic& S, const std::vector<int32_t>& prow,
   }
 }
 
+int64_t exact_fill(int64_t n, const std::vector<int32_t>& prow, const std::vector<int32_t>& pcol) {
+  // elimination tree of the lower triangle (ancestors with path compression)
+  std::vector<int32_t> parent(n, -1), anc(n, -1);
+  for (int64_t i = 0; i < n; ++i)
+    for (int32_t e = prow[i]; e < prow[i + 1]; ++e) {
+      int32_t k = pcol[e];
+      while (k >= 0 && k < i) {
+        const int32_t next = anc[k];
+        anc[k] = (int32_t)i;
+        if (next < 0) {
+          parent[k] = (int32_t)i;
+          break;
+        }
+        k = next;
+      }
+    }
+  // row i of L: the union of the tree paths from each k < i with A(i, k) != 0 up to i
+  std::vector<int32_t> mark(n, -1);
+  int64_t count = n;
+  for (int64_t i = 0; i < n; ++i) {
+    mark[i] = (int32_t)i;
+    for (int32_t e = prow[i]; e < prow[i + 1]; ++e)
+      for (int32_t k = pcol[e]; k >= 0 && k < i && mark[k] != i; k = parent[k]) {
+        mark[k] = (int32_t)i;
+        ++count;
+      }
+  }
+  return count;
+}
+
 void build_factor_plan(const Symbolic& S, FactorPlan& P, int schur_wide_tiles) {
   P = FactorPlan();
   P.schur_wide_tiles = std::max(1, schur_wide_tiles);

@@ -74,6 +74,10 @@ void permute_pattern(const Symbolic& S, const int32_t* rowptr, const int32_t* co
 void assembly_positions(const Symbolic& S, const std::vector<int32_t>& prow,
                         const std::vector<int32_t>& pcol, std::vector<int32_t>& apos);
 
+// Entries of the exact Cholesky factor (diagonal included) of the permuted pattern: what an
+// elimination without the supernodes' explicit zeros would store.  O(nnz(L)) host work.
+int64_t exact_fill(int64_t n, const std::vector<int32_t>& prow, const std::vector<int32_t>& pcol);
+
 // Factorization task lists: tasks are int4 {s, I, J, p}; steps[] holds (offset, count, kind, level).
 struct FactorPlan {
   std::vector<int32_t> tasks;        // 4 ints per task

@@ -26,6 +26,7 @@ LOBPCG_FP64 = 0
 LOBPCG_FP32 = 1
 LOBPCG_FLAG_GRAPH = 1
 LOBPCG_FLAG_AUTOTUNE = 2
+LOBPCG_FLAG_FORCE_FP64_REDO = 4
 LOBPCG_STOP_PAPER = 0
 LOBPCG_STOP_NORMA = 1
 
@@ -36,10 +37,19 @@ class Matrix(ct.Structure):
                 ("dense", ct.c_void_p), ("ld", ct.c_int64)]
 
 
+ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_size_t, ct.c_void_p)
+FREE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p)
+
+
+class Allocator(ct.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ct.c_void_p)]
+
+
 class Options(ct.Structure):
     _fields_ = [("leaf_size", ct.c_int32), ("stop_rule", ct.c_int32), ("qr_lower", ct.c_int32),
                 ("flags", ct.c_int32), ("norm_a", ct.c_double), ("eig_tol", ct.c_double),
-                ("subtree_levels", ct.c_int32), ("schur_wide_tiles", ct.c_int32)]
+                ("subtree_levels", ct.c_int32), ("schur_wide_tiles", ct.c_int32), ("stage1_tol", ct.c_double),
+                ("allocator", ct.POINTER(Allocator))]
 
 
 class Info(ct.Structure):
@@ -47,7 +57,8 @@ class Info(ct.Structure):
                 ("norm_a", ct.c_double), ("t_symbolic", ct.c_double), ("t_factor", ct.c_double),
                 ("t_solve", ct.c_double), ("nnz_factor", ct.c_double), ("factor_flops", ct.c_double),
                 ("resid", ct.c_void_p), ("t_precond_gpu", ct.c_double), ("t_spmm_gpu", ct.c_double),
-                ("n_precond", ct.c_int32), ("n_spmm", ct.c_int32)]
+                ("n_precond", ct.c_int32), ("n_spmm", ct.c_int32), ("stage1_iters", ct.c_int32),
+                ("stage1_exit", ct.c_int32), ("t_stage1", ct.c_double)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/lobpcg.h
@@ -65,10 +76,12 @@ SIGNATURES = {
     "lobpcg_pinvit": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.POINTER(Info),
                                  ct.c_void_p]),
     "lobpcg_backward": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "lobpcg_backward_iters": (ct.c_int32, [ct.c_void_p]),
     "lobpcg_destroy": (ct.c_int, [ct.c_void_p]),
     "lobpcg_status_string": (ct.c_char_p, [ct.c_int]),
     "lobpcg_last_error": (ct.c_char_p, []),
     "lobpcg_symbolic": (ct.c_int, [ct.POINTER(Matrix), ct.c_int32, ct.c_void_p, ct.c_void_p]),
+    "lobpcg_exact_fill": (ct.c_int, [ct.POINTER(Matrix), ct.c_int32, ct.c_void_p]),
     "lobpcg_get_permutation": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "lobpcg_get_tuning": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
     "lobpcg_apply_a": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32]),

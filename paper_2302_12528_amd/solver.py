@@ -40,6 +40,34 @@ def _dev_f64(x, shape=None):
     return x
 
 
+@nv.ALLOC_FN
+def _torch_alloc(nbytes, user):
+    try:
+        torch = _torch()
+        return torch.cuda.caching_allocator_alloc(max(int(nbytes), 1), torch.cuda.current_device(),
+                                                  torch.cuda.current_stream())
+    except Exception:   # the library reports LOBPCG_ERR_ALLOC
+        return None
+
+
+@nv.FREE_FN
+def _torch_free(ptr, user):
+    import torch
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+# lobpcg_allocator over torch's caching allocator: every device byte of a context is a torch block
+TORCH_ALLOCATOR = nv.Allocator(_torch_alloc, _torch_free, None)
+
+
+def _allocator(kind: str):
+    if kind == "torch":
+        return ct.pointer(TORCH_ALLOCATOR)
+    if kind == "hip":
+        return None
+    raise ValueError(f"allocator must be 'torch' or 'hip', not {kind!r}")
+
+
 def make_matrix(A, grid=(0, 0, 0)):
     """Build the lobpcg_matrix struct for a scipy CSR matrix or a dense numpy array.
 
@@ -81,25 +109,39 @@ def symbolic(A, grid=(0, 0, 0), leaf_size=64):
     return perm, dict(zip(keys, stats.tolist()))
 
 
+def exact_fill(A, grid=(0, 0, 0), leaf_size=64):
+    """Entries of the exact Cholesky factor for the ordering setup builds (host only, no GPU)."""
+    lib = nv.load()
+    M, keep = make_matrix(A, grid)
+    out = np.zeros(1, dtype=np.float64)
+    nv.check(lib.lobpcg_exact_fill(ct.byref(M), leaf_size, out.ctypes.data))
+    del keep
+    return float(out[0])
+
+
 class Solver:
     """k smallest eigenpairs of an SPD matrix with the mixed-precision LOBPCG of Algorithm 3."""
 
     def __init__(self, A, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
                  grid=(0, 0, 0), leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
                  norm_a: float = 0.0, eig_tol: float = 0.0, graph: bool = False, autotune: bool = False,
-                 subtree_levels: int = 0, schur_wide_tiles: int = 0):
+                 subtree_levels: int = 0, schur_wide_tiles: int = 0, stage1_tol: float = 0.0,
+                 force_fp64_redo: bool = False, allocator: str = "torch"):
         self.lib = nv.load()
         _torch()
         M, keep = make_matrix(A, grid)
         opt = nv.Options()
+        opt.allocator = _allocator(allocator)
         opt.leaf_size = leaf_size
         opt.subtree_levels = subtree_levels
         opt.schur_wide_tiles = schur_wide_tiles
+        opt.stage1_tol = stage1_tol
         opt.stop_rule = _STOP[stop]
         opt.qr_lower = 1 if qr_lower else 0
         opt.norm_a = norm_a
         opt.eig_tol = eig_tol
-        opt.flags = (nv.LOBPCG_FLAG_GRAPH if graph else 0) | (nv.LOBPCG_FLAG_AUTOTUNE if autotune else 0)
+        opt.flags = ((nv.LOBPCG_FLAG_GRAPH if graph else 0) | (nv.LOBPCG_FLAG_AUTOTUNE if autotune else 0) |
+                     (nv.LOBPCG_FLAG_FORCE_FP64_REDO if force_fp64_redo else 0))
         ctx = ct.c_void_p()
         self.ctx = None
         st = self.lib.lobpcg_setup(ct.byref(M), k, m, tol, _PREC[factor_precision], _stream(), ct.byref(opt),
@@ -181,6 +223,10 @@ class Solver:
         nv.check(self.lib.lobpcg_backward(self.ctx, _ptr(de), _ptr(dx), _ptr(out)))
         return out
 
+    def backward_iters(self) -> int:
+        """Projected PCG iterations of the latest backward()."""
+        return int(self.lib.lobpcg_backward_iters(self.ctx))
+
     def permutation(self) -> np.ndarray:
         perm = np.zeros(self.n, dtype=np.int32)
         nv.check(self.lib.lobpcg_get_permutation(self.ctx, perm.ctypes.data))
@@ -210,7 +256,8 @@ class BatchedSolver:
 
     def __init__(self, mats, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
                  grids=None, leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
-                 eig_tol: float = 0.0, graph: bool = False, autotune: bool = False):
+                 eig_tol: float = 0.0, graph: bool = False, autotune: bool = False, stage1_tol: float = 0.0,
+                 allocator: str = "torch"):
         self.lib = nv.load()
         _torch()
         count = len(mats)
@@ -228,6 +275,8 @@ class BatchedSolver:
         opt.stop_rule = _STOP[stop]
         opt.qr_lower = 1 if qr_lower else 0
         opt.eig_tol = eig_tol
+        opt.stage1_tol = stage1_tol
+        opt.allocator = _allocator(allocator)
         opt.flags = (nv.LOBPCG_FLAG_GRAPH if graph else 0) | (nv.LOBPCG_FLAG_AUTOTUNE if autotune else 0)
         ctx = ct.c_void_p()
         self.ctx = None

@@ -182,3 +182,17 @@ def test_dense_spd_8192_full_size(torch_cuda):
     assert err.max() <= 1e-10, err
     assert res.max() <= p.tol, res
     assert np.max(np.abs(X.T @ X - np.eye(p.k))) <= 1e-12
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_fp64_redo_path_equals_fp64_step1(torch_cuda, graph):
+    # Recovery from a breakdown of Algorithm 2's FP32 attempt (section 3.2): the iteration is redone from its
+    # saved inputs with step 1 in FP64.  Forcing that path at every iteration must reproduce, bit for bit,
+    # the solve that uses step 1 in FP64 from the start, and count one fallback per redone iteration.
+    print(f"fp64 redo path diffusion3d_12 graph={graph}", flush=True)
+    p = synth.cfg2(N=12, k=8, m=16)
+    lam_a, X_a, info_a = _run(p, "fp32", grid=(12, 12, 12), qr_lower=False, graph=graph)
+    lam_b, X_b, info_b = _run(p, "fp32", grid=(12, 12, 12), force_fp64_redo=True, graph=graph)
+    assert info_a["iters"] == info_b["iters"]
+    assert info_b["fallbacks"] == info_b["iters"] - 1
+    assert np.array_equal(lam_a, lam_b) and np.array_equal(X_a, X_b)

@@ -139,6 +139,7 @@ def test_symbolic_ordering_and_fill(lib, case):
     Ap = sp.csr_matrix(A)[perm][:, perm]
     exact = _exact_fill(Ap)
     assert st["nnz_factor"] >= exact
+    assert sv.exact_fill(A, grid=grid, leaf_size=16) == exact
     assert st["nnz_factor"] <= 2.5 * exact      # relaxed supernodes add a bounded amount of explicit zeros
     assert st["levels"] >= 2
 
@@ -155,6 +156,8 @@ def test_symbolic_64cube_plan_size(lib):
     perm, st = sv.symbolic(A, grid=(64, 64, 64))
     # exact geometric nested-dissection fill is 1.567e8; the relaxed supernodes stay within 15 % of it
     assert 1.5e8 < st["nnz_factor"] < 1.8e8
+    exact = sv.exact_fill(A, grid=(64, 64, 64))
+    assert 1.5e8 < exact < st["nnz_factor"]
     assert st["levels"] <= 16
 
 
