@@ -10,18 +10,21 @@ import numpy as np
 import scipy.sparse as sp
 
 
+def _dense_hermitian(A):
+    """A as a dense array, made exactly Hermitian ((A + A^H) / 2; the transpose for real A)."""
+    Ad = A.toarray() if sp.issparse(A) else np.asarray(A)
+    Ad = Ad.astype(np.complex128 if np.iscomplexobj(Ad) else np.float64)
+    return 0.5 * (Ad + Ad.conj().T)
+
+
 def smallest_eigenpairs(A, k: int):
-    """Return (lam[:k] ascending, U[:, :k]) of the symmetric matrix A (dense or sparse)."""
-    Ad = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
-    Ad = 0.5 * (Ad + Ad.T)
-    lam, U = np.linalg.eigh(Ad)
+    """Return (lam[:k] ascending, U[:, :k]) of the symmetric or Hermitian matrix A (dense or sparse)."""
+    lam, U = np.linalg.eigh(_dense_hermitian(A))
     return lam[:k].copy(), U[:, :k].copy()
 
 
 def all_eigenpairs(A):
-    Ad = A.toarray() if sp.issparse(A) else np.asarray(A, dtype=np.float64)
-    Ad = 0.5 * (Ad + Ad.T)
-    return np.linalg.eigh(Ad)
+    return np.linalg.eigh(_dense_hermitian(A))
 
 
 def norm2(A) -> float:

@@ -262,5 +262,36 @@ def paper2d(x0_seed: int = 106) -> Problem:
                    extra={"eigs": laplace2d_rect_eigs(5, 5000)})
 
 
+def gauge_laplace2d(p: int, q: int, seed: int = 7) -> sp.csr_matrix:
+    """A complex Hermitian positive definite matrix with a known spectrum: D L D^H for the p x q Dirichlet
+    5-point Laplacian L and D = diag(exp(i phi)) with phases phi ~ U(0, 2 pi) per node (seeded).  Every
+    coupling L_jk = -1 becomes -exp(i (phi_j - phi_k)); D is unitary, so the eigenvalues are those of L
+    (laplace2d_rect_eigs) and the eigenvectors D u."""
+    L = laplace2d_rect(p, q).tocoo()
+    phi = np.random.default_rng(seed).uniform(0.0, 2.0 * np.pi, p * q)
+    vals = L.data * np.exp(1j * (phi[L.row] - phi[L.col]))
+    A = sp.csr_matrix(sp.coo_matrix((vals, (L.row, L.col)), shape=L.shape), dtype=np.complex128)
+    A.sum_duplicates()
+    A.sort_indices()
+    A.indptr = A.indptr.astype(np.int32)
+    A.indices = A.indices.astype(np.int32)
+    return A
+
+
+def dense_hpd(n: int, seed: int = 13, lo: float = 1.0, hi: float = 1e3):
+    """A = Q diag(lambda) Q^H with Q from QR of a seeded complex Gaussian, lambda = geomspace(lo, hi, n)."""
+    r = np.random.default_rng(seed)
+    G = r.standard_normal((n, n)) + 1j * r.standard_normal((n, n))
+    Q, _ = np.linalg.qr(G)
+    lam = np.geomspace(lo, hi, n)
+    A = (Q * lam) @ Q.conj().T
+    return 0.5 * (A + A.conj().T), lam
+
+
+def complex_block(n: int, m: int, seed: int) -> np.ndarray:
+    r = np.random.default_rng(seed)
+    return r.standard_normal((n, m)) + 1j * r.standard_normal((n, m))
+
+
 def random_block(n: int, m: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal((n, m))

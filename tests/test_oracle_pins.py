@@ -436,3 +436,49 @@ def test_planted_mistake_stage1_in_double_is_caught():
     s1 = ol.lobpcg(p.A, p.X0, p.k, 1e-11, precond=T, norm_a=na, stop="paper", dtype=np.float64)
     ref = _cfg1_closed(p.k)
     assert not np.max(np.abs(s1.evals - ref) / ref) > 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Complex Hermitian matrices (section 1): the brute-force path of the oracle on Hermitian inputs, and the
+# real symmetric embedding the GPU path solves.
+# ---------------------------------------------------------------------------
+
+def test_gauge_laplacian_closed_form():
+    # D L D^H with a unitary diagonal D has the spectrum of L: 4 sin^2(i pi/(2(p+1))) + 4 sin^2(j pi/(2(q+1)))
+    A = synth.gauge_laplace2d(9, 11)
+    assert np.iscomplexobj(A.data) and np.abs(A.imag).max() > 0.1
+    Ad = A.toarray()
+    assert np.allclose(Ad, Ad.conj().T, atol=0, rtol=0)
+    lam, U = dense.smallest_eigenpairs(A, 12)
+    np.testing.assert_allclose(lam, synth.laplace2d_rect_eigs(9, 11)[:12], rtol=1e-13)
+    R = Ad @ U - U * lam
+    assert np.linalg.norm(R) < 1e-12 and np.allclose(U.conj().T @ U, np.eye(12), atol=1e-13)
+
+
+def test_dense_hpd_prescribed_spectrum():
+    A, lam = synth.dense_hpd(120)
+    got, _ = dense.smallest_eigenpairs(A, 10)
+    np.testing.assert_allclose(got, lam[:10], rtol=1e-12)
+
+
+def test_real_embedding_doubles_each_eigenvalue():
+    # M = [[B, -C], [C, B]] for A = B + iC: every eigenvalue of A twice, and [u; v] for x = u + iv
+    A = synth.gauge_laplace2d(6, 7).toarray()
+    B, C = A.real, A.imag
+    M = np.block([[B, -C], [C, B]])
+    assert np.allclose(M, M.T)
+    lamA, UA = np.linalg.eigh(A)
+    lamM = np.linalg.eigvalsh(M)
+    np.testing.assert_allclose(lamM[0::2], lamA, rtol=1e-12)
+    np.testing.assert_allclose(lamM[1::2], lamA, rtol=1e-12)
+    x = UA[:, 0]
+    z = np.concatenate([x.real, x.imag])
+    assert np.linalg.norm(M @ z - lamA[0] * z) < 1e-12
+
+
+def test_planted_mistake_embedding_sign_is_caught():
+    # the wrong sign on the off-diagonal blocks ([[B, C], [C, B]]) is not even symmetric
+    A = synth.gauge_laplace2d(6, 7).toarray()
+    B, C = A.real, A.imag
+    M_bad = np.block([[B, C], [C, B]])
+    assert not np.allclose(M_bad, M_bad.T)
