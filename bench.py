@@ -4,10 +4,12 @@
 Workload: 3D 7-point variable-coefficient diffusion on a 64^3 grid (n = 262,144,
 cell coefficients exp(N(0,1)), nested dissection), k = 16, m = 32, tol = 1e-10.
 One step = numeric factorization of the permuted matrix (FP32 factor) plus
-lobpcg_solve to tolerance, with the matrix and start block already on the GPU.
-The same step with an FP64 factor (and FP64 Algorithm 2 step 1) is timed on the
-same GPU for the mixed-vs-FP64 comparison, and with the single-precision first
-stage of Algorithm 3 line 1 (MPLOBPCG-schol).  Side records: the dense SPD
+lobpcg_solve to tolerance with Algorithm 3 as a whole (MPLOBPCG-schol: the
+single-precision first stage of line 1 to 5e-6, then the working-precision loop
+with the FP32-factor preconditioner and Algorithm 2), with the matrix and start
+block already on the GPU.  The same step with an FP64 factor (DLOBPCG-dchol:
+FP64 Algorithm 2 step 1, no first stage) is timed on the same GPU for the
+mixed-vs-FP64 comparison, and without the first stage (DLOBPCG-schol).  Side records: the dense SPD
 workload (n = 8192), the batched Schrodinger workload, the backward of the 3D
 Schrodinger workload, Algorithm 1 and the CPU oracle.  Prints one JSON line.
 """
@@ -243,6 +245,40 @@ def backward_run(torch, pk, fd_amps=2):
             "loss": float(L.item()), "fd_check": fd}
 
 
+def hermitian_run(torch, pk):
+    """Complex Hermitian workload: the reconstructed 5 x 5000 Laplacian with random node phases
+    (D L D^H, D = diag(exp(i phi)); the paper's complex 2D-Laplace of section 5.5 stands behind it), k = 30,
+    m = 32, tol = 1e-12 under eq. (stop) with the exact ||A||_2, through the real symmetric embedding:
+    time to tol with the FP32 factor (and the first stage) and with the FP64 factor, same GPU."""
+    import numpy as np
+    import synth
+    A = synth.gauge_laplace2d(5, 5000)
+    eigs = synth.laplace2d_rect_eigs(5, 5000)
+    na = float(eigs[-1])
+    X0 = torch.from_numpy(synth.complex_block(25000, 32, 23)).cuda()
+    out = {"workload": "gauge_laplace2d_5x5000: complex Hermitian D L D^H, n=25000, k=30, m=32, tol=1e-12; step "
+                       "= numeric factorization + solve to tol"}
+    for label, prec, tol1 in (("mixed", "fp32", 5e-6), ("fp64", "fp64", 0.0)):
+        log(f"hermitian: {label}")
+        s = pk.Solver(A, 30, 32, 1e-12, factor_precision=prec, grid=(5, 5000, 1), stop="paper", norm_a=na,
+                      stage1_tol=tol1, qr_lower=(prec == "fp32"))
+        for _ in range(1):
+            s.factor()
+            s.solve(X0, maxit=5000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.factor()
+        lam, X, info = s.solve(X0, maxit=5000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s.close()
+        lam = lam.cpu().numpy()
+        out[label] = {"time_to_tol_s": round(dt, 5), "iters": info["iters"], "stage1_iters": info["stage1_iters"],
+                      "max_eig_rel_err_vs_closed_form": float(np.max(np.abs(lam - eigs[:30]) / eigs[:30]))}
+    out["speedup_vs_fp64"] = round(out["fp64"]["time_to_tol_s"] / out["mixed"]["time_to_tol_s"], 3)
+    return out
+
+
 def traffic_from_profile():
     """HBM bytes per preconditioner application from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE passes, each scaled by a copy of known size), or None once the solve sources differ
@@ -278,9 +314,12 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--batched", type=int, default=256, help="problems in the batched run (0 = skip)")
     ap.add_argument("--pinvit-maxit", type=int, default=400, help="iteration cap of the PINVIT run (0 = skip)")
-    ap.add_argument("--no-stage1", action="store_true", help="skip the MPLOBPCG-schol (line 1) record")
+    ap.add_argument("--stage1-tol", type=float, default=5e-6,
+                    help="first-stage tolerance of the timed solve (Algorithm 3 line 1; 0 = no first stage)")
+    ap.add_argument("--no-schol", action="store_true", help="skip the record without the first stage")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense n = 8192 record")
     ap.add_argument("--no-backward", action="store_true", help="skip the 48^3 backward record")
+    ap.add_argument("--no-hermitian", action="store_true", help="skip the complex Hermitian record")
     ap.add_argument("--autotune", action="store_true", help="time the solve-plan split and reduction chunk at setup")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first copy a 256 MiB buffer once (reference dispatch for hardware byte counters)")
@@ -303,9 +342,10 @@ def main():
     log(f"generating {args.workload}")
     p = workload(args.workload)
     X0 = torch.from_numpy(np.ascontiguousarray(p.X0)).cuda()
-    log(f"setup mixed (fp32 factor), n={p.n}")
+    log(f"setup mixed (fp32 factor, first stage to {args.stage1_tol}), n={p.n}")
     t0 = time.perf_counter()
-    mixed = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp32", grid=p.grid, autotune=args.autotune)
+    mixed = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp32", grid=p.grid, autotune=args.autotune,
+                      stage1_tol=args.stage1_tol)
     t_setup = time.perf_counter() - t0
     dt, infos, lam, X = time_steps(torch, mixed, X0, args.steps, args.warmup, "mixed")
     info = infos[-1]
@@ -363,18 +403,17 @@ def main():
                   "max_eig_rel_diff_vs_lobpcg": float(np.max(np.abs(lam_pv.cpu().numpy() - lam_np) / lam_np))}
     mixed.close()
 
-    # MPLOBPCG-schol: Algorithm 3 with line 1 (single-precision LOBPCG to 5e-6 first), same factor
-    mp = None
-    if not args.no_stage1:
-        log("setup mp_schol (fp32 factor + single-precision first stage)")
-        smp = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp32", grid=p.grid, stage1_tol=5e-6)
-        dtm, infos_m, lam_m, _ = time_steps(torch, smp, X0, max(1, min(args.steps, 3)), 1, "mp_schol")
-        smp.close()
-        im = infos_m[-1]
-        mp = {"time_to_tol_s": round(dtm, 5), "stage1_iters": im["stage1_iters"], "iters": im["iters"],
-              "t_stage1_s": round(im["t_stage1"], 5), "t_factor_s": round(im["t_factor"], 5),
-              "t_solve_s": round(im["t_solve"], 5), "stage1_tol": 5e-6,
-              "max_eig_rel_diff_vs_mixed": float(np.max(np.abs(lam_m.cpu().numpy() - lam_np) / lam_np))}
+    # DLOBPCG-schol: the same FP32 factor and Algorithm 2, without the first stage of line 1
+    schol = None
+    if not args.no_schol:
+        log("setup schol (fp32 factor, no first stage)")
+        sch = pk.Solver(p.A, p.k, p.m, p.tol, factor_precision="fp32", grid=p.grid)
+        dts, infos_s, lam_s, _ = time_steps(torch, sch, X0, max(1, min(args.steps, 3)), 1, "schol")
+        sch.close()
+        i_s = infos_s[-1]
+        schol = {"time_to_tol_s": round(dts, 5), "iters": i_s["iters"], "t_factor_s": round(i_s["t_factor"], 5),
+                 "t_solve_s": round(i_s["t_solve"], 5),
+                 "max_eig_rel_diff_vs_mixed": float(np.max(np.abs(lam_s.cpu().numpy() - lam_np) / lam_np))}
 
     fp64 = None
     if not args.no_fp64:
@@ -396,10 +435,12 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": False, "scaling": "strong",
         "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: 3D 7-point variable-coefficient diffusion, n={p.n}, nnz={nnz}, "
-                               f"k={p.k}, m={p.m}, tol={p.tol}, nested dissection, FP32 factor; step = numeric "
-                               f"factorization + solve to tol",
-                   "n": p.n, "k": p.k, "m": p.m, "tol": p.tol},
-        "iters": info["iters"], "t_factor_s": round(info["t_factor"], 5), "t_solve_s": round(info["t_solve"], 5),
+                               f"k={p.k}, m={p.m}, tol={p.tol}, nested dissection, FP32 factor; Algorithm 3 with "
+                               f"the single-precision first stage to {args.stage1_tol} (MPLOBPCG-schol); step = "
+                               f"numeric factorization + solve to tol",
+                   "n": p.n, "k": p.k, "m": p.m, "tol": p.tol, "stage1_tol": args.stage1_tol},
+        "iters": info["iters"], "stage1_iters": info["stage1_iters"], "t_stage1_s": round(info["t_stage1"], 5),
+        "t_factor_s": round(info["t_factor"], 5), "t_solve_s": round(info["t_solve"], 5),
         "t_setup_s": round(t_setup, 3), "t_symbolic_s": round(info["t_symbolic"], 4),
         "nnz_factor": nnzL, "factor_flops": info["factor_flops"], "norm_a_estimate": info["norm_a"],
         "fp64": fp64,
@@ -407,7 +448,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs_pc, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs_pc / HBM_PEAK_GBS, 4), "traffic": traffic_from_profile(),
                      "kernel": "preconditioner application (forward + backward supernodal sweeps, FP32 factor), "
-                               "HIP events around each application in the timed solves",
+                               "HIP events around each application in the working-precision iterations of the "
+                               "timed solves",
                      "ms": round(ms_pc, 4), "applications": n_pc, "algorithmic_bytes": bytes_pc,
                      "nnz_factor_exact": nnzL_exact, "stored_bytes": bytes_pc_stored,
                      "frac_on_stored_bytes": round(bytes_pc_stored / (ms_pc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -415,7 +457,7 @@ def main():
         "spmm": {"ms": round(ms_spmm, 4), "GBs": round(gbs_spmm, 1), "frac": round(gbs_spmm / HBM_PEAK_GBS, 4),
                  "launches": n_sp, "algorithmic_bytes": bytes_spmm},
         "parity": parity,
-        "mp_schol": mp,
+        "schol_no_stage1": schol,
         "pinvit": pinvit,
     }
     if args.batched > 0:
@@ -425,6 +467,8 @@ def main():
         out["dense"] = dense_run(torch, pk, 2)
     if not args.no_backward:
         out["backward"] = backward_run(torch, pk)
+    if not args.no_hermitian:
+        out["hermitian"] = hermitian_run(torch, pk)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a 32^3 sample)")
         out["cpu_baseline"] = cpu_baseline()

@@ -234,6 +234,31 @@ lobpcg_status lobpcg_setup_batched(const lobpcg_matrix* A, int32_t count, int32_
 lobpcg_status lobpcg_solve_batched(lobpcg_ctx ctx, const double* const* X0, int32_t maxit,
                                    double* const* evals, double* const* evecs, lobpcg_info* infos);
 
+/* Complex Hermitian positive definite A (section 1; the paper's complex dense and 2D-Laplace tests of
+ * sections 5.4-5.5).  A->format 2: CSR as for format 0 but val holds 2 nnz doubles (real and imaginary
+ * part of each entry, interleaved), full Hermitian pattern; format 3: dense n x n complex, row-major,
+ * interleaved (2 ld doubles per row).  Host pointers; a grid hint (g0, g1, 1) is used for ordering.
+ * The context holds the real symmetric positive definite embedding M = [[B, -C], [C, B]] of
+ * A = B + iC (order 2n): each eigenvalue of A is a double eigenvalue of M, so the loop runs with 2k
+ * wanted pairs and block 2m, and the factor of M is the real form of A's complex Cholesky factor, held
+ * in factor_precision.  Requires 1 <= k <= m <= 32 and 6m <= 2n; dense n <= 8192.  Errors as
+ * lobpcg_setup (INVALID_ARG also for a matrix that is not Hermitian). */
+lobpcg_status lobpcg_setup_hermitian(const lobpcg_matrix* A, int32_t k, int32_t m, double tol,
+                                     lobpcg_precision factor_precision, void* hip_stream,
+                                     const lobpcg_options* opts, lobpcg_ctx* out);
+
+/* Algorithm 3 for a Hermitian context: X0 (device, n x m complex, row-major, interleaved re/im; NULL =
+ * seeded complex Gaussian block), evals (device, k, ascending), evecs (device, n x k complex, row-major,
+ * interleaved; unit 2-norm, each determined up to a complex phase).  Eigenvector j is read from the first
+ * real Ritz vector of pair j of the embedding, and the k vectors are then made orthonormal in complex
+ * arithmetic (a Cholesky QR: X <- X L^{-H} with X^H X = L L^H; the vectors read from the pairs are
+ * orthonormal up to about residual / gap already, so this changes them by that much).  For an eigenvalue
+ * of A that is itself multiple the pairs must separate for the vectors to span its eigenspace.  info as
+ * lobpcg_solve (iters, residuals of the k pairs before the QR, n_conv counted in pairs).  lobpcg_solve,
+ * lobpcg_pinvit, lobpcg_backward and lobpcg_update_values reject Hermitian contexts. */
+lobpcg_status lobpcg_solve_hermitian(lobpcg_ctx ctx, const double* X0, int32_t maxit, double* evals,
+                                     double* evecs, lobpcg_info* info);
+
 /* Number of problems held by ctx (1 for lobpcg_setup). */
 int32_t lobpcg_batch_count(lobpcg_ctx ctx);
 

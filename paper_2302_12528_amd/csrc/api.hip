@@ -140,10 +140,10 @@ void build_tsqr(const std::vector<int64_t>& inst_off, int c, int rb, int rbu, Ts
   T.half = maxout * c * c;
 }
 
-// FP32 plans for c <= 32: leaves of kTsqrCombineRows rows, Gram chunks of kTsqrCombineSlots leaf factors,
+// FP32 plans for c <= 64: leaves of kTsqrCombineRows rows, Gram chunks of kTsqrCombineSlots leaf factors,
 // one combining item per instance (see TsqrPlanDev); other plans: the Householder tree above.
 void build_tsqr_plan(const std::vector<int64_t>& inst_off, int c, int elem_bytes, TsqrHost& T) {
-  if (elem_bytes != 4 || c > 32) {
+  if (elem_bytes != 4 || c > 64) {
     build_tsqr(inst_off, c, tsqr_rows_per_block(c, elem_bytes), tsqr_upper_rows_per_block(c, elem_bytes), T);
     return;
   }
@@ -245,6 +245,11 @@ struct lobpcg_ctx_s {
   std::vector<double> norm_a;
   int cur = 0;
   bool solved = false;
+  // complex Hermitian problem held as its real symmetric embedding (lobpcg_setup_hermitian): the
+  // complex size, number of pairs and block size; 0 for real problems
+  int64_t herm_n = 0;
+  int herm_k = 0, herm_m = 0;
+  double* herm_scratch = nullptr;
   double t_symbolic = 0, t_factor = 0;
   int fallbacks = 0;
   // backward (adjoint) buffers, allocated on first use
@@ -1817,6 +1822,200 @@ lobpcg_status lobpcg_setup_batched(const lobpcg_matrix* A, int32_t count, int32_
   return setup_core(A, count, k, m, tol, factor_precision, hip_stream, opts, out);
 }
 
+// ---- complex Hermitian matrices (section 1: A Hermitian positive definite) ----
+// A = B + iC (B symmetric, C antisymmetric) is held as the real symmetric positive definite
+// M = [[B, -C], [C, B]] of order 2n.  A x = lambda x with x = u + iv gives M [u; v] = lambda [u; v] and
+// M [-v; u] = lambda [-v; u], so every eigenvalue of A is a double eigenvalue of M, the k smallest
+// eigenpairs of A are the 2k smallest of M, and x = u + iv is read from any unit vector [u; v] of the
+// pair.  The working-precision loop, the lower-precision factor of M (the real form of the complex
+// Cholesky factor of A) and Algorithm 2 run unchanged on M.
+namespace {
+
+lobpcg_status validate_hermitian(const lobpcg_matrix* A) {
+  if (!A) return fail(LOBPCG_ERR_INVALID_ARG, "A is NULL");
+  if (A->n < 1 || A->n > (int64_t)INT32_MAX / 2 - 1) return fail(LOBPCG_ERR_INVALID_ARG, "n out of range");
+  const int64_t n = A->n;
+  auto herm_pair = [](double ar, double ai, double br, double bi) {   // (a, b) = (A_ij, A_ji): b = conj(a)
+    const double s = std::max(std::max(std::fabs(ar), std::fabs(ai)), std::max(std::fabs(br), std::fabs(bi)));
+    return std::fabs(ar - br) <= 1e-12 * s && std::fabs(ai + bi) <= 1e-12 * s;
+  };
+  if (A->format == 3) {
+    if (!A->dense) return fail(LOBPCG_ERR_INVALID_ARG, "dense pointer is NULL");
+    if (A->ld < n) return fail(LOBPCG_ERR_INVALID_ARG, "ld < n");
+    if (n > 8192) return fail(LOBPCG_ERR_INVALID_ARG, "dense Hermitian matrices are limited to n <= 8192");
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j <= i; ++j) {
+        const double* a = A->dense + 2 * (i * A->ld + j);
+        const double* b = A->dense + 2 * (j * A->ld + i);
+        if (!std::isfinite(a[0]) || !std::isfinite(a[1])) return fail(LOBPCG_ERR_INVALID_ARG, "non-finite matrix entry");
+        if (!herm_pair(a[0], a[1], b[0], b[1])) return fail(LOBPCG_ERR_INVALID_ARG, "matrix is not Hermitian");
+      }
+    for (int64_t i = 0; i < n; ++i)
+      if (!(A->dense[2 * (i * A->ld + i)] > 0)) return fail(LOBPCG_ERR_INVALID_ARG, "non-positive diagonal");
+    return LOBPCG_OK;
+  }
+  if (A->format != 2) return fail(LOBPCG_ERR_INVALID_ARG, "Hermitian format must be 2 (CSR) or 3 (dense)");
+  if (!A->rowptr || !A->colind || !A->val) return fail(LOBPCG_ERR_INVALID_ARG, "CSR pointer is NULL");
+  if (A->rowptr[0] != 0 || A->rowptr[n] != A->nnz || A->nnz < n)
+    return fail(LOBPCG_ERR_INVALID_ARG, "rowptr inconsistent with nnz");
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t e0 = A->rowptr[i], e1 = A->rowptr[i + 1];
+    if (e1 < e0) return fail(LOBPCG_ERR_INVALID_ARG, "rowptr not monotone");
+    bool diag = false;
+    for (int32_t e = e0; e < e1; ++e) {
+      const int32_t j = A->colind[e];
+      if (j < 0 || j >= n) return fail(LOBPCG_ERR_INVALID_ARG, "column index out of range");
+      if (e > e0 && A->colind[e - 1] >= j) return fail(LOBPCG_ERR_INVALID_ARG, "columns not sorted/unique");
+      const double ar = A->val[2 * e], ai = A->val[2 * e + 1];
+      if (!std::isfinite(ar) || !std::isfinite(ai)) return fail(LOBPCG_ERR_INVALID_ARG, "non-finite matrix entry");
+      if (j == i) {
+        diag = true;
+        if (!(ar > 0)) return fail(LOBPCG_ERR_INVALID_ARG, "non-positive diagonal");
+      }
+      const int32_t* b = A->colind + A->rowptr[j];
+      const int32_t* en = A->colind + A->rowptr[j + 1];
+      const int32_t* it = std::lower_bound(b, en, (int32_t)i);
+      if (it == en || *it != i) return fail(LOBPCG_ERR_INVALID_ARG, "pattern is not symmetric");
+      const int64_t t = it - A->colind;
+      if (!herm_pair(ar, ai, A->val[2 * t], A->val[2 * t + 1]))
+        return fail(LOBPCG_ERR_INVALID_ARG, "matrix is not Hermitian");
+    }
+    if (!diag) return fail(LOBPCG_ERR_INVALID_ARG, "missing diagonal entry");
+  }
+  return LOBPCG_OK;
+}
+
+}  // namespace
+
+lobpcg_status lobpcg_setup_hermitian(const lobpcg_matrix* A, int32_t k, int32_t m, double tol,
+                                     lobpcg_precision factor_precision, void* hip_stream, const lobpcg_options* opts,
+                                     lobpcg_ctx* out) {
+  if (out) *out = nullptr;
+  if (!out) return fail(LOBPCG_ERR_INVALID_ARG, "out is NULL");
+  ST_TRY(validate_hermitian(A));
+  if (k < 1 || m < k) return fail(LOBPCG_ERR_INVALID_ARG, "need 1 <= k <= m");
+  if (m > 32) return fail(LOBPCG_ERR_INVALID_ARG, "Hermitian block size m must be <= 32");
+  const int64_t n = A->n, n2 = 2 * n;
+  lobpcg_matrix M{};
+  M.n = n2;
+  std::vector<int32_t> rp, ci;
+  std::vector<double> va;
+  if (A->format == 3) {
+    M.format = 1;
+    M.ld = n2;
+    va.assign((size_t)n2 * n2, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = 0; j < n; ++j) {
+        const double br = A->dense[2 * (i * A->ld + j)], bi = A->dense[2 * (i * A->ld + j) + 1];
+        va[i * n2 + j] = br;
+        va[i * n2 + n + j] = -bi;
+        va[(n + i) * n2 + j] = bi;
+        va[(n + i) * n2 + n + j] = br;
+      }
+    M.dense = va.data();
+  } else {
+    // rows i < n: B_i then -C_i (columns n + j); rows n + i: C_i then B_i.  Entries of C that are zero
+    // (the diagonal, real couplings) are left out; C's pattern is symmetric, so M's is too.
+    rp.reserve(n2 + 1);
+    rp.push_back(0);
+    for (int half = 0; half < 2; ++half)
+      for (int64_t i = 0; i < n; ++i) {
+        for (int pass = 0; pass < 2; ++pass) {
+          const bool b_block = (pass == half);   // which n x n block supplies columns pass * n + j
+          for (int32_t e = A->rowptr[i]; e < A->rowptr[i + 1]; ++e) {
+            const double re = A->val[2 * e], im = A->val[2 * e + 1];
+            if (b_block) {
+              ci.push_back((int32_t)(pass * n + A->colind[e]));
+              va.push_back(re);
+            } else if (im != 0.0) {
+              ci.push_back((int32_t)(pass * n + A->colind[e]));
+              va.push_back(half == 0 ? -im : im);
+            }
+          }
+        }
+        rp.push_back((int32_t)ci.size());
+      }
+    M.format = 0;
+    M.nnz = (int64_t)ci.size();
+    M.rowptr = rp.data();
+    M.colind = ci.data();
+    M.val = va.data();
+    // a 2D grid hint (g0, g1, 1) becomes (2, g0, g1): the two copies are the outer dimension
+    if (A->grid[0] > 0 && A->grid[1] > 0 && A->grid[2] <= 1 &&
+        (int64_t)A->grid[0] * A->grid[1] == n) {
+      M.grid[0] = 2;
+      M.grid[1] = A->grid[0];
+      M.grid[2] = A->grid[1];
+    }
+  }
+  lobpcg_ctx c = nullptr;
+  ST_TRY(setup_core(&M, 1, 2 * k, 2 * m, tol, factor_precision, hip_stream, opts, &c));
+  c->herm_n = n;
+  c->herm_k = k;
+  c->herm_m = m;
+  *out = c;
+  return LOBPCG_OK;
+}
+
+lobpcg_status lobpcg_solve_hermitian(lobpcg_ctx c, const double* X0, int32_t maxit, double* evals, double* evecs,
+                                     lobpcg_info* info) {
+  if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
+  if (!c->herm_n) return fail(LOBPCG_ERR_INVALID_ARG, "not a Hermitian context (lobpcg_setup_hermitian)");
+  if (maxit < 1) return fail(LOBPCG_ERR_INVALID_ARG, "maxit must be >= 1");
+  if (!evals || !evecs) return fail(LOBPCG_ERR_INVALID_ARG, "output pointer is NULL");
+  g_last_error.clear();
+  lobpcg_ctx_s& C = *c;
+  const int64_t n = C.herm_n;
+  const int k = C.herm_k, m = C.herm_m;
+  // scratch: the real start block (2n x 2m), the 2k real Ritz values and vectors (2n x 2k)
+  // scratch: the real start block (2n x 2m), the 2k real Ritz values and vectors (2n x 2k), and a seeded
+  // complex start block (n x m) when the caller gives none
+  if (!C.herm_scratch) ST_TRY(C.alloc(C.herm_scratch, 2 * n * 2 * m + 2 * k + 2 * n * 2 * k + n * 2 * m));
+  double* X0r = C.herm_scratch;
+  double* evr = X0r + 2 * n * 2 * m;
+  double* Zr = evr + 2 * k;
+  double* Xg = Zr + 2 * n * 2 * k;
+  if (X0) {
+    launch_herm_expand(X0, n, m, X0r, C.st);
+  } else {
+    launch_gaussian_fill(Xg, n, 2 * m, 2 * m, 0x6e7a11ull, C.st);   // re, im of a seeded complex block
+    launch_herm_expand(Xg, n, m, X0r, C.st);
+  }
+  ST_TRY(check_launch("Hermitian start block"));
+  lobpcg_info ri{};
+  std::vector<double> res(2 * k);
+  ri.resid = info && info->resid ? res.data() : nullptr;
+  const double* x0[1] = {X0r};
+  double* ev[1] = {evr};
+  double* ec[1] = {Zr};
+  const lobpcg_status s = solve_core(c, x0, maxit, ev, ec, &ri);
+  if (s == LOBPCG_OK || s == LOBPCG_NOT_CONVERGED) {
+    launch_herm_extract(Zr, evr, n, k, evecs, evals, C.st);
+    // The real pair vectors are orthonormal; the complex vectors read from them are so only up to how far
+    // each pair's span is from closed under multiplication by i (about residual / gap).  A Cholesky QR in
+    // complex arithmetic (Gram matrix G = X^H X from the real Gram matrix of X over the first n rows of
+    // Zr, the rest zero) makes them orthonormal: X <- X L^{-H}, G = L L^H.
+    launch_convert_block<double, double>(evecs, 2 * k, Zr, 2 * k, n, 2 * k, C.st);
+    HIP_TRY(hipMemsetAsync(Zr + n * 2 * k, 0, (size_t)n * 2 * k * sizeof(double), C.st));
+    C.active.assign(1, 1);
+    ST_TRY(set_active(c));
+    launch_sgram(C.SG, Zr, 2 * k, Zr, 2 * k, 2 * k, 2 * k, C.H, 0, C.gpart, C.st);
+    launch_herm_orthonormalize(evecs, n, k, C.H, C.Cev, C.st);
+    ST_TRY(check_launch("Hermitian extraction"));
+    HIP_TRY(hipStreamSynchronize(C.st));
+  }
+  C.solved = false;   // the context's pairs are those of M
+  if (info) {
+    double* r = info->resid;
+    *info = ri;
+    info->resid = r;
+    info->n_conv = ri.n_conv / 2;
+    if (r)
+      for (int j = 0; j < k; ++j) r[j] = res[2 * j];
+  }
+  return s;
+}
+
 lobpcg_status lobpcg_factor(lobpcg_ctx c) {
   if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
   c->solved = false;
@@ -1825,7 +2024,7 @@ lobpcg_status lobpcg_factor(lobpcg_ctx c) {
 
 lobpcg_status lobpcg_update_values(lobpcg_ctx c, const double* vals, int32_t vals_on_device, const double* shift) {
   if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
-  if (c->dense) return fail(LOBPCG_ERR_INVALID_ARG, "update_values supports CSR matrices only");
+  if (c->dense || c->herm_n) return fail(LOBPCG_ERR_INVALID_ARG, "update_values supports real CSR matrices only");
   if (vals) {
     HIP_TRY(hipMemcpyAsync(c->d_aval_orig, vals, c->nnz * sizeof(double),
                            vals_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->st));
@@ -1840,6 +2039,7 @@ lobpcg_status lobpcg_update_values(lobpcg_ctx c, const double* vals, int32_t val
 lobpcg_status lobpcg_solve(lobpcg_ctx c, const double* X0, int32_t maxit, double* evals, double* evecs,
                            lobpcg_info* info) {
   if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
+  if (c->herm_n) return fail(LOBPCG_ERR_INVALID_ARG, "Hermitian context: use lobpcg_solve_hermitian");
   if (c->B != 1) return fail(LOBPCG_ERR_INVALID_ARG, "batched context: use lobpcg_solve_batched");
   if (maxit < 1) return fail(LOBPCG_ERR_INVALID_ARG, "maxit must be >= 1");
   if (!evals || !evecs) return fail(LOBPCG_ERR_INVALID_ARG, "output pointer is NULL");
@@ -1853,7 +2053,7 @@ lobpcg_status lobpcg_solve(lobpcg_ctx c, const double* X0, int32_t maxit, double
 lobpcg_status lobpcg_pinvit(lobpcg_ctx c, const double* X0, int32_t maxit, double* evals, double* evecs,
                             lobpcg_info* info, double* theta_hist) {
   if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
-  if (c->B != 1) return fail(LOBPCG_ERR_INVALID_ARG, "PINVIT supports single-problem contexts");
+  if (c->B != 1 || c->herm_n) return fail(LOBPCG_ERR_INVALID_ARG, "PINVIT supports real single-problem contexts");
   if (maxit < 1) return fail(LOBPCG_ERR_INVALID_ARG, "maxit must be >= 1");
   if (!evals || !evecs) return fail(LOBPCG_ERR_INVALID_ARG, "output pointer is NULL");
   g_last_error.clear();
@@ -1883,7 +2083,7 @@ int32_t lobpcg_batch_count(lobpcg_ctx c) { return c ? c->B : 0; }
 lobpcg_status lobpcg_backward(lobpcg_ctx c, const double* d_evals, const double* d_evecs, double* d_diag) {
   if (!c) return fail(LOBPCG_ERR_INVALID_ARG, "ctx is NULL");
   if (!d_diag) return fail(LOBPCG_ERR_INVALID_ARG, "d_diag is NULL");
-  if (c->B != 1) return fail(LOBPCG_ERR_INVALID_ARG, "backward supports single-instance contexts");
+  if (c->B != 1 || c->herm_n) return fail(LOBPCG_ERR_INVALID_ARG, "backward supports real single-instance contexts");
   if (!c->solved) return fail(LOBPCG_ERR_STATE, "backward needs a successful lobpcg_solve first");
   lobpcg_ctx_s& C = *c;
   hipStream_t st = C.st;

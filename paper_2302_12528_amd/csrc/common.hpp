@@ -36,7 +36,7 @@ struct TsqrPlanDev {
   const int64_t* level_off;   // host, nlevels + 1
   const int32_t* items;       // device
   int64_t half;               // elements per scratch half
-  // combine = 1 (FP32 plans with c <= 32): three levels - the FP32 Householder leaves of kTsqrCombineRows
+  // combine = 1 (FP32 plans with c <= 64): three levels - the FP32 Householder leaves of kTsqrCombineRows
   // rows (slots in the first scratch half), chunk items {instance, first slot, slots, partial} whose FP64
   // Gram partials go to the second scratch half, and per-instance items {instance, first partial,
   // partials, slot} that sum them (the sums follow the partials) and write their Cholesky factor as R
@@ -81,6 +81,15 @@ int64_t dense_mm_scratch(int64_t n);
 template <typename T>
 void launch_dense_mm(const T* A, int64_t lda, int64_t n, const T* X, int64_t ldx, T* Y,
                      int64_t ldy, int c, T* part, int64_t part_elems, hipStream_t st);
+// Complex blocks (interleaved re, im; row-major) and the real symmetric embedding of a Hermitian
+// problem: Y (2n x 2m) = [[Re X, -Im X], [Im X, Re X]] for X (n x m); X (n x k) and lam (k) from the 2k
+// Ritz pairs of the embedding (Z 2n x 2k, theta 2k): x_j = Z[0:n, 2j] + i Z[n:2n, 2j], lam_j = theta_2j.
+void launch_herm_expand(const double* X, int64_t n, int m, double* Y, hipStream_t st);
+void launch_herm_extract(const double* Z, const double* theta, int64_t n, int k, double* X, double* lam,
+                         hipStream_t st);
+// X (n x k complex, k <= 32) <- X L^{-H} with G = X^H X = L L^H formed from R, the real Gram matrix of X
+// read as real n x 2k; L: k x k complex scratch.
+void launch_herm_orthonormalize(double* X, int64_t n, int k, const double* R, double* L, hipStream_t st);
 // dst[i*ldd + j] = (Tout) src[i*lds + j], i < n, j < c (IEEE round to nearest when narrowing)
 template <typename Tin, typename Tout>
 void launch_convert_block(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t n, int c, hipStream_t st);

@@ -2,6 +2,8 @@
 // for dense A) and the data-movement kernels around them (row gathers for
 // the permutation, value gathers, start-block generation).  Blocks are
 // row-major so that one row of an n x c block is contiguous.
+#include <algorithm>
+
 #include "common.hpp"
 #include "mfma.hpp"
 
@@ -276,6 +278,101 @@ __global__ void sub_block_kernel(const double* __restrict__ src, int64_t lds, do
   dst[i * ldd + j] -= src[i * lds + j];
 }
 
+// Complex n x m block X (element (i, j) = X[2 (i m + j)] + i X[2 (i m + j) + 1]) -> the real 2n x 2m block
+// [[Re X, -Im X], [Im X, Re X]] of the real symmetric embedding (its columns span the embedded complex
+// span, closed under multiplication by i).
+__global__ void herm_expand_kernel(const double* __restrict__ X, int64_t n, int m, double* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * m) return;
+  const int64_t i = e / m;
+  const int j = (int)(e % m);
+  const double re = X[2 * e], im = X[2 * e + 1];
+  const int64_t ld = 2 * m;
+  Y[i * ld + j] = re;
+  Y[i * ld + m + j] = -im;
+  Y[(n + i) * ld + j] = im;
+  Y[(n + i) * ld + m + j] = re;
+}
+
+// The k complex eigenpairs from the 2k real Ritz pairs of the embedding (Z 2n x 2k, row-major): pair j
+// is columns 2j, 2j + 1 (one double eigenvalue); x_j = Z[0:n, 2j] + i Z[n:2n, 2j], lambda_j = theta_2j.
+__global__ void herm_extract_kernel(const double* __restrict__ Z, const double* __restrict__ theta, int64_t n, int k,
+                                    double* __restrict__ X, double* __restrict__ lam) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < k) lam[e] = theta[2 * e];
+  if (e >= n * k) return;
+  const int64_t i = e / k;
+  const int j = (int)(e % k);
+  X[2 * e] = Z[i * 2 * k + 2 * j];
+  X[2 * e + 1] = Z[(n + i) * 2 * k + 2 * j];
+}
+
+// Complex Gram matrix of the extracted eigenvectors from the real Gram R (2k x 2k) of the same block read
+// as real n x 2k (columns Re x_1, Im x_1, Re x_2, ...): G_ij = x_i^H x_j = (R_{2i,2j} + R_{2i+1,2j+1}) +
+// i (R_{2i,2j+1} - R_{2i+1,2j}); then its Cholesky factor G = L L^H (complex, L lower), by one thread
+// (k <= 32, once per solve).  A non-positive pivot leaves L = I (the vectors are then returned as read).
+__global__ void herm_chol_kernel(const double* __restrict__ R, int k, double* __restrict__ L) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int k2 = 2 * k;
+  auto re = [&](int i, int j) { return R[(2 * i) * k2 + 2 * j] + R[(2 * i + 1) * k2 + 2 * j + 1]; };
+  auto im = [&](int i, int j) { return R[(2 * i) * k2 + 2 * j + 1] - R[(2 * i + 1) * k2 + 2 * j]; };
+  bool ok = true;
+  for (int j = 0; j < k && ok; ++j) {
+    double dj = re(j, j);
+    for (int q = 0; q < j; ++q) dj -= L[2 * (j * k + q)] * L[2 * (j * k + q)] + L[2 * (j * k + q) + 1] * L[2 * (j * k + q) + 1];
+    if (!(dj > 0.0)) {
+      ok = false;
+      break;
+    }
+    const double ljj = sqrt(dj);
+    L[2 * (j * k + j)] = ljj;
+    L[2 * (j * k + j) + 1] = 0.0;
+    for (int i = j + 1; i < k; ++i) {   // L_ij = (G_ij - sum_q L_iq conj(L_jq)) / L_jj, G_ij = conj(G_ji)
+      double sr = re(j, i), si = -im(j, i);
+      for (int q = 0; q < j; ++q) {
+        const double ar = L[2 * (i * k + q)], ai = L[2 * (i * k + q) + 1];
+        const double br = L[2 * (j * k + q)], bi = -L[2 * (j * k + q) + 1];
+        sr -= ar * br - ai * bi;
+        si -= ar * bi + ai * br;
+      }
+      L[2 * (i * k + j)] = sr / ljj;
+      L[2 * (i * k + j) + 1] = si / ljj;
+    }
+    for (int i = 0; i < j; ++i) {
+      L[2 * (i * k + j)] = 0.0;
+      L[2 * (i * k + j) + 1] = 0.0;
+    }
+  }
+  if (!ok)
+    for (int e = 0; e < k * k; ++e) {
+      L[2 * e] = (e / k == e % k) ? 1.0 : 0.0;
+      L[2 * e + 1] = 0.0;
+    }
+}
+
+// X <- X L^{-H} row by row (X n x k complex, one thread per row): y L^H = x, with (L^H)_{qj} = conj(L_{jq}).
+__global__ void herm_rowsolve_kernel(double* __restrict__ X, int64_t n, int k, const double* __restrict__ L) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double yr[32], yi[32];
+  double* x = X + 2 * i * k;
+  for (int j = 0; j < k; ++j) {
+    double sr = x[2 * j], si = x[2 * j + 1];
+    for (int q = 0; q < j; ++q) {   // subtract y_q conj(L_jq)
+      const double lr = L[2 * (j * k + q)], li = -L[2 * (j * k + q) + 1];
+      sr -= yr[q] * lr - yi[q] * li;
+      si -= yr[q] * li + yi[q] * lr;
+    }
+    const double d = L[2 * (j * k + j)];
+    yr[j] = sr / d;
+    yi[j] = si / d;
+  }
+  for (int j = 0; j < k; ++j) {
+    x[2 * j] = yr[j];
+    x[2 * j + 1] = yi[j];
+  }
+}
+
 inline dim3 grid1(int64_t total) { return dim3((unsigned)((total + kThreads - 1) / kThreads)); }
 
 }  // namespace
@@ -351,6 +448,23 @@ template void launch_dense_mm<double>(const double*, int64_t, int64_t, const dou
                                       double*, int64_t, hipStream_t);
 template void launch_dense_mm<float>(const float*, int64_t, int64_t, const float*, int64_t, float*, int64_t, int,
                                      float*, int64_t, hipStream_t);
+
+void launch_herm_expand(const double* X, int64_t n, int m, double* Y, hipStream_t st) {
+  if (n <= 0 || m <= 0) return;
+  herm_expand_kernel<<<grid1(n * m), kThreads, 0, st>>>(X, n, m, Y);
+}
+
+void launch_herm_extract(const double* Z, const double* theta, int64_t n, int k, double* X, double* lam,
+                         hipStream_t st) {
+  if (n <= 0 || k <= 0) return;
+  herm_extract_kernel<<<grid1(std::max<int64_t>(n * k, k)), kThreads, 0, st>>>(Z, theta, n, k, X, lam);
+}
+
+void launch_herm_orthonormalize(double* X, int64_t n, int k, const double* R, double* L, hipStream_t st) {
+  if (n <= 0 || k <= 0 || k > 32) return;
+  herm_chol_kernel<<<1, 64, 0, st>>>(R, k, L);
+  herm_rowsolve_kernel<<<grid1(n), kThreads, 0, st>>>(X, n, k, L);
+}
 
 template <typename Tin, typename Tout>
 void launch_convert_block(const Tin* src, int64_t lds, Tout* dst, int64_t ldd, int64_t n, int c, hipStream_t st) {

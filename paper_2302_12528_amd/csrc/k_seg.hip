@@ -585,20 +585,20 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
   }
 }
 
-// Combining step of the TSQR tree for c <= 32 (FP32 plans): the R factor of the stacked leaf factors
+// Combining step of the TSQR tree for c <= 64 (FP32 plans): the R factor of the stacked leaf factors
 // [R_1; ...; R_q] is the Cholesky factor of sum_s R_s^T R_s.  The leaves are FP32, so every product
 // R_s(i, j) R_s(i, k) is exact in FP64 and the sums carry FP64 rounding only: the combined factor is
 // perturbed by O(kappa^2 u64), below the leaves' own O(kappa u32) for kappa < u32 / u64.
 // Partial sums: one workgroup per chunk item {instance, first slot, slots (<= kTsqrCombineSlots),
-// partial index}; wave w owns the 16 x 16 block (w / 2, w % 2) of the Gram matrix, accumulated by
-// v_mfma_f64_16x16x4f64 over the rows of the chunk's leaf factors (slot s occupies c x c FP32 at
-// in + s c^2).  All loads of the chunk are issued before the first product.
+// partial index}; wave w owns the (16 CB) x (16 CB) block (w / 2, w % 2) of the Gram matrix (CB = 1 for
+// c <= 32, 2 for c <= 64), accumulated by v_mfma_f64_16x16x4f64 over the rows of the chunk's leaf factors
+// (slot s occupies c x c FP32 at in + s c^2), 64 rows at a time with their loads issued together.
+template <int CB>
 __global__ void __launch_bounds__(256) tsqr_gram_partial_kernel(const SegDev S, const float* __restrict__ in,
                                                                 const int32_t* __restrict__ items, int c,
                                                                 double* __restrict__ part) {
   typedef Mfma<double> MF;
   typedef MF::v4 V4;
-  constexpr int STEPS = kTsqrCombineSlots * 32 / 16;   // 16 rows per step, at most 32 rows per slot
   const int* it = items + 4 * blockIdx.x;
   const int b = it[0];
   if (!S.active[b]) return;
@@ -607,31 +607,44 @@ __global__ void __launch_bounds__(256) tsqr_gram_partial_kernel(const SegDev S, 
   const int q = it[3];
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   const int i = lane % 16, g = lane / 16;
-  const int ci = 16 * (w / 2) + i, cj = 16 * (w % 2) + i;
-  const bool okc = (ci < c), okj = (cj < c);
+  const int ci0 = 16 * CB * (w / 2), cj0 = 16 * CB * (w % 2);
   const int rows = ns * c;
   const float* base = in + s0 * c * c;
-  float xa[STEPS][4], yb[STEPS][4];
+  V4 acc[CB][CB];
 #pragma unroll
-  for (int st = 0; st < STEPS; ++st)
+  for (int u = 0; u < CB; ++u)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = 16 * st + 4 * u + g;
+    for (int v = 0; v < CB; ++v) acc[u][v] = V4{0, 0, 0, 0};
+  for (int r0 = 0; r0 < rows; r0 += 64) {
+    float xa[16][CB], yb[16][CB];
+#pragma unroll
+    for (int st = 0; st < 16; ++st) {
+      const int r = r0 + 4 * st + g;
       const bool ok = r < rows;
-      xa[st][u] = (ok && okc) ? base[(int64_t)r * c + ci] : 0.f;
-      yb[st][u] = (ok && okj) ? base[(int64_t)r * c + cj] : 0.f;
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int cx = ci0 + 16 * u + i, cy = cj0 + 16 * u + i;
+        xa[st][u] = (ok && cx < c) ? base[(int64_t)r * c + cx] : 0.f;
+        yb[st][u] = (ok && cy < c) ? base[(int64_t)r * c + cy] : 0.f;
+      }
     }
-  V4 acc = V4{0, 0, 0, 0};
 #pragma unroll
-  for (int st = 0; st < STEPS; ++st)
+    for (int st = 0; st < 16; ++st)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = MF::op((double)xa[st][u], (double)yb[st][u], acc);
+      for (int u = 0; u < CB; ++u)
+#pragma unroll
+        for (int v = 0; v < CB; ++v) acc[u][v] = MF::op((double)xa[st][u], (double)yb[st][v], acc[u][v]);
+  }
   double* P = part + (int64_t)q * c * c;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int gi = 16 * (w / 2) + MF::drow(lane, e);
-    if (gi < c && okj) P[gi * c + cj] = acc[e];
-  }
+  for (int u = 0; u < CB; ++u)
+#pragma unroll
+    for (int v = 0; v < CB; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = ci0 + 16 * u + MF::drow(lane, e), gj = cj0 + 16 * v + i;
+        if (gi < c && gj < c) P[gi * c + gj] = acc[u][v][e];
+      }
 }
 
 // G_b = sum of instance b's partials {instance, first partial, partials, -} in a fixed order, written to
@@ -846,16 +859,21 @@ void launch_stsqr(const SegDev& S, const TsqrPlanDev& P, const Tin* W, int64_t l
       const int32_t* it0 = P.items + 4 * i0;
       if (c <= 8) stsqr_wave_kernel<Tin, 8, kTsqrCombineRpl><<<g4, 256, 0, st>>>(S, W, ldw, it0, i1 - i0, c, scratch);
       else if (c <= 16) stsqr_wave_kernel<Tin, 16, kTsqrCombineRpl><<<g4, 256, 0, st>>>(S, W, ldw, it0, i1 - i0, c, scratch);
-      else stsqr_wave_kernel<Tin, 32, kTsqrCombineRpl><<<g4, 256, 0, st>>>(S, W, ldw, it0, i1 - i0, c, scratch);
+      else if (c <= 32) stsqr_wave_kernel<Tin, 32, kTsqrCombineRpl><<<g4, 256, 0, st>>>(S, W, ldw, it0, i1 - i0, c, scratch);
+      else stsqr_go<T, Tin, 64>((unsigned)(i1 - i0), S, W, ldw, it0, c, scratch, st);   // one workgroup per leaf
       double* part = reinterpret_cast<double*>(scratch + P.half);
       const int64_t gbase = i2 - i1;   // the per-instance Gram matrices follow the partials
       const int32_t* it2 = P.items + 4 * i2;
-      tsqr_gram_partial_kernel<<<(unsigned)(i2 - i1), 256, 0, st>>>(S, scratch, P.items + 4 * i1, c, part);
+      if (c <= 32)
+        tsqr_gram_partial_kernel<1><<<(unsigned)(i2 - i1), 256, 0, st>>>(S, scratch, P.items + 4 * i1, c, part);
+      else
+        tsqr_gram_partial_kernel<2><<<(unsigned)(i2 - i1), 256, 0, st>>>(S, scratch, P.items + 4 * i1, c, part);
       tsqr_gram_reduce_kernel<<<dim3(cdiv(c * c, kRedElems), (unsigned)(i3 - i2)), 256, 0, st>>>(S, part, it2, c * c,
                                                                                               gbase);
       if (c <= 8) tsqr_combine_chol_kernel<8><<<(unsigned)(i3 - i2), 64, 0, st>>>(S, part, it2, c, gbase, R);
       else if (c <= 16) tsqr_combine_chol_kernel<16><<<(unsigned)(i3 - i2), 64, 0, st>>>(S, part, it2, c, gbase, R);
-      else tsqr_combine_chol_kernel<32><<<(unsigned)(i3 - i2), 64, 0, st>>>(S, part, it2, c, gbase, R);
+      else if (c <= 32) tsqr_combine_chol_kernel<32><<<(unsigned)(i3 - i2), 64, 0, st>>>(S, part, it2, c, gbase, R);
+      else tsqr_combine_chol_kernel<64><<<(unsigned)(i3 - i2), 64, 0, st>>>(S, part, it2, c, gbase, R);
       return;
     }
   }

@@ -465,6 +465,28 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   return maxrank;
 }
 
+// Global scratch of the three-launch forms (doubles from the instance's start).  For c <= 96: the
+// inverse-iteration factors (5 c^2, when they do not fit in LDS), Q (c x c, row stride c + 1), the
+// diagonal and off-diagonal of T (e[c - 1] = 0) and the eigenvalues.
+// For c > 96 (the 32 x 32 grid tridiagonalization) the scratch instead holds, as the LDS/global form of
+// syev_kernel expects it, the reflectors below the subdiagonal of a (c x c, row stride c + 1) at 0, then
+// Z (c x c) and the inverse-iteration factors (5 c^2), and after them d, e, the eigenvalues and the
+// reflector scalars tau (q unused).
+struct SyevSplit {
+  int64_t q, d, e, lam, tau;
+};
+__device__ __host__ inline SyevSplit syev_split_offsets(int c) {
+  if (c > 96) {
+    const int64_t d = 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c;
+    return {0, d, d + c, d + 2 * c, d + 3 * c};
+  }
+  const int64_t q = 5 * (int64_t)c * c, d = q + (int64_t)c * (c + 1);
+  return {q, d, d + c, d + 2 * c, d + 3 * c};
+}
+
+// MODE 0: all four steps.  MODE 1 (c > 96): syev_tridiag32_kernel has left the reflectors in the scratch's
+// a and d, e, tau after it, and syev_bisect_kernel the eigenvalues; steps 3 and 4 only.
+template <int MODE>
 __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __restrict__ H, int64_t ldh,
                                                             int64_t hstride, int c, int nev,
                                                             double* __restrict__ evals, int64_t estride,
@@ -491,6 +513,16 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   double* a = in_lds ? sa : work;
   double* Z = in_lds ? sz : work + (int64_t)c * la;   // c x nev, row stride la
   double* lu = work + 2 * (int64_t)c * la;            // U0 | U1 | U2 | L | piv, each c x nev, index [k * nev + j]
+  if constexpr (MODE == 1) {
+    const SyevSplit sp = syev_split_offsets(c);
+    for (int i = tid; i < c; i += kSyevThreads) {
+      d[i] = work[sp.d + i];
+      e[i] = work[sp.e + i];
+      tau[i] = work[sp.tau + i];
+      lam[i] = (i < nev) ? work[sp.lam + i] : 0.0;
+    }
+    __syncthreads();
+  } else {
   for (int q = tid; q < c * c; q += kSyevThreads) {
     const int i = q / c, j = q % c;
     a[i * la + j] = 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]);
@@ -587,7 +619,8 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     e[c - 1] = 0.0;
   }
   __syncthreads();
-  const int maxrank = tridiag_eigs<0>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, in_lds ? la : nev, lu);
+  }
+  const int maxrank = tridiag_eigs<0, MODE == 1>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, in_lds ? la : nev, lu);
   const int lz = in_lds ? la : nev;   // row stride of Z
   // ---- 4. back-transformation C = Q Z: G threads per column (a power of two), each a row segment ----
   int G = 1;
@@ -743,17 +776,6 @@ __device__ __attribute__((always_inline)) void tridiag_rows(double (&A)[NB][NB],
 // its share of p^T v; after a second barrier every thread applies H -= v w^T + w v^T,
 // w = p - (t / 2) (p^T v) v, and Q -= t (Q v) v^T to its own entries.  Steps 2 and 3 are those of
 // the LDS form; step 4 is C = Q Z, one matrix-core product of Q and Z from LDS.
-// Global scratch of the three-launch form (doubles from the instance's start): the inverse-
-// iteration factors (5 c^2, when they do not fit in LDS), Q (c x c, row stride c + 1), the diagonal
-// and off-diagonal of T (e[c - 1] = 0) and the eigenvalues.
-struct SyevSplit {
-  int64_t q, d, e, lam;
-};
-__device__ __host__ inline SyevSplit syev_split_offsets(int c) {
-  const int64_t q = 5 * (int64_t)c * c, d = q + (int64_t)c * (c + 1);
-  return {q, d, d + c, d + 2 * c};
-}
-
 // Eigenvalue j = blockIdx.x of the tridiagonal T that syev_tridiag_kernel<NB> left in the scratch,
 // by multisection on Sturm counts with kSyevThreads points per round (the Gershgorin interval,
 // tolerance and scaled counts are those of tridiag_eigs, so the bracket invariant
@@ -978,6 +1000,140 @@ __global__ void __launch_bounds__(2 * kSyevThreads) syev_tridiag_kernel(const do
   for (int i = tid; i < c; i += 2 * kSyevThreads) {
     work[sp.d + i] = d[i];
     work[sp.e + i] = (i < c - 1) ? e[i] : 0.0;
+  }
+}
+
+// Sum over the 32 lanes of a half wave (lanes 32 h .. 32 h + 15 and 32 h + 16 .. 32 h + 31): both halves
+// of the pair add the same two values, so every lane of the half ends with the same bits.
+__device__ inline double row32_sum(double x) {
+  x = row16_sum(x);
+  return x + __shfl_xor(x, 16, 64);
+}
+
+// Step 1 for 96 < c <= 192 (three-launch form): the matrix in the registers of a 16 x 32 thread grid of
+// 512 threads, thread (ti, tj) = (2 wave + lane / 32, lane % 32) holding H(ti + 16 a, tj + 32 b), a < 12,
+// b < 6 (72 doubles).  Reflector k: the 32 lanes of grid row k % 16 form v and t from their entries of row
+// k and publish them; after a barrier every grid row forms its entries of p = t H v by a 32-lane sum and
+// publishes them with its share of p^T v; after a second barrier every thread applies H -= v w^T + w v^T
+// with w = p - (t / 2)(p^T v) v.  Q is not formed: the reflectors go to the scratch's a below the
+// subdiagonal (LAPACK's layout), with tau, d and e after it, for syev_kernel<1> to apply to Z.  Rows of
+// the 16-row blocks before AK and columns of the 32-column blocks before AK / 2 are finished and skipped.
+constexpr int kT32Rows = 12, kT32Cols = 6, kSyevThreads32 = 512;
+
+template <int AK>
+__device__ __attribute__((always_inline)) void tridiag32_rows(double (&A)[kT32Rows][kT32Cols], int c, int ti, int tj,
+                                                              double* vb, double* pb, double* pvp, double* tb,
+                                                              double* d, double* e, double* tau, double* ga, int la) {
+  constexpr int CM = 192, NA = kT32Rows, NBC = kT32Cols, BK = AK / 2;
+#pragma unroll 1
+  for (int r = 0; r < 16; ++r) {
+    const int k = 16 * AK + r;
+    if (k + 2 >= c) break;   // uniform
+    const int buf = k & 1;
+    if (ti == r) {
+      double ss = 0.0, al = 0.0;
+#pragma unroll
+      for (int b = BK; b < NBC; ++b) {
+        const int j = tj + 32 * b;
+        const double x = A[AK][b];
+        ss += (j >= k + 2) ? x * x : 0.0;
+        al += (j == k + 1) ? x : 0.0;
+        if (j == k) d[k] = x;
+      }
+      ss = row32_sum(ss);
+      al = row32_sum(al);
+      double t = 0.0, beta = al, scale = 0.0;
+      if (ss > 0.0) {
+        const double xn = sqrt(al * al + ss);
+        beta = (al >= 0.0) ? -xn : xn;
+        t = (beta - al) / beta;
+        scale = 1.0 / (al - beta);
+      }
+#pragma unroll
+      for (int b = 0; b < NBC; ++b) {
+        const int j = tj + 32 * b;
+        const double v = (b >= BK && j > k + 1) ? A[AK][b] * scale : (j == k + 1 ? 1.0 : 0.0);
+        vb[buf * CM + j] = v;
+        if (j > k + 1 && j < c) ga[(int64_t)j * la + k] = v;
+      }
+      if (tj == 0) {
+        tb[buf] = t;
+        tau[k] = t;
+        e[k] = beta;
+      }
+    }
+    __syncthreads();
+    const double t = tb[buf];
+    if (t == 0.0) continue;   // uniform; every buffer is double-buffered by step parity
+    double vc[NBC];
+#pragma unroll
+    for (int b = BK; b < NBC; ++b) vc[b] = vb[buf * CM + tj + 32 * b];
+    double pv = 0.0;
+#pragma unroll
+    for (int a = AK; a < NA; ++a) {
+      double sp = 0.0;
+#pragma unroll
+      for (int b = BK; b < NBC; ++b) sp = fma(A[a][b], vc[b], sp);
+      const double pa = t * row32_sum(sp);
+      pv = fma(pa, vb[buf * CM + ti + 16 * a], pv);
+      if (tj == 0) pb[buf * CM + ti + 16 * a] = pa;
+    }
+    if (tj == 0) pvp[buf * 16 + ti] = pv;
+    __syncthreads();
+    double K = 0.0;
+#pragma unroll
+    for (int g = 0; g < 16; ++g) K += pvp[buf * 16 + g];
+    K *= 0.5 * t;
+    double wc[NBC];
+#pragma unroll
+    for (int b = BK; b < NBC; ++b) wc[b] = pb[buf * CM + tj + 32 * b] - K * vc[b];
+#pragma unroll
+    for (int a = AK; a < NA; ++a) {
+      const double vr = vb[buf * CM + ti + 16 * a];
+      const double wr = pb[buf * CM + ti + 16 * a] - K * vr;
+#pragma unroll
+      for (int b = BK; b < NBC; ++b) A[a][b] -= vr * wc[b] + wr * vc[b];
+    }
+  }
+  if constexpr (AK + 1 < NA) tridiag32_rows<AK + 1>(A, c, ti, tj, vb, pb, pvp, tb, d, e, tau, ga, la);
+}
+
+__global__ void __launch_bounds__(kSyevThreads32) syev_tridiag32_kernel(const double* __restrict__ H, int64_t ldh,
+                                                                        int64_t hstride, int c,
+                                                                        double* __restrict__ work, int64_t wstride,
+                                                                        const int32_t* __restrict__ active) {
+  constexpr int CM = 192;
+  if (active && !active[blockIdx.x]) return;
+  H += (int64_t)blockIdx.x * hstride;
+  work += (int64_t)blockIdx.x * wstride;
+  __shared__ double vb[2][CM], pb[2][CM], pvp[2][16], tb[2];
+  __shared__ double d[CM], e[CM], tau[CM];
+  const SyevSplit sp = syev_split_offsets(c);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int ti = 2 * wid + (lane >> 5), tj = lane & 31;
+  const int la = c + 1;
+  double A[kT32Rows][kT32Cols];
+#pragma unroll
+  for (int a = 0; a < kT32Rows; ++a)
+#pragma unroll
+    for (int b = 0; b < kT32Cols; ++b) {
+      const int i = ti + 16 * a, j = tj + 32 * b;
+      A[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
+    }
+  tridiag32_rows<0>(A, c, ti, tj, &vb[0][0], &pb[0][0], &pvp[0][0], tb, d, e, tau, work, la);
+#pragma unroll
+  for (int a = 0; a < kT32Rows; ++a)
+#pragma unroll
+    for (int b = 0; b < kT32Cols; ++b) {
+      const int i = ti + 16 * a, j = tj + 32 * b;
+      if (i == j && i + 2 >= c && i < c) d[i] = A[a][b];
+      if (c >= 2 && i == c - 1 && j == c - 2) e[c - 2] = A[a][b];
+    }
+  __syncthreads();
+  for (int i = tid; i < c; i += kSyevThreads32) {
+    work[sp.d + i] = d[i];
+    work[sp.e + i] = (i < c - 1) ? e[i] : 0.0;
+    work[sp.tau + i] = (i + 2 < c) ? tau[i] : 0.0;
   }
 }
 
@@ -1238,7 +1394,9 @@ __device__ inline Mfma<double>::v4 tile_mm(const double* A, int ars, int aks, in
 // q + 16 u (u < RC) of columns s + 16 h (h < NCOL), so every column sum is a 16-lane DPP sum, and a
 // column step needs one barrier (the owners of column j normalise it and publish it; every later
 // column then subtracts its projection on it, with the next column's owners already done).
-template <int NCOL, int RC>
+// C1G: C1 is read from the eigenvector matrix in global memory (L2-resident) instead of an LDS copy, so
+// that W and T fit in LDS for c = 192, m = 64.
+template <int NCOL, int RC, bool C1G = false>
 __global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __restrict__ C, int64_t cstride, int c,
                                                             int m, double* __restrict__ G, int64_t gstride,
                                                             const int32_t* __restrict__ active) {
@@ -1247,14 +1405,16 @@ __global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __rest
   if (active && !active[blockIdx.x]) return;
   C += (int64_t)blockIdx.x * cstride;
   G += (int64_t)blockIdx.x * gstride;
-  __shared__ double c1[CM * LD], w[CM * LD], tm[MM * LD], wb[2][CM];
+  __shared__ double c1s[C1G ? 1 : CM * LD], w[CM * LD], tm[MM * LD], wb[2][CM];
+  const double* c1 = C1G ? C : c1s;
+  const int l1 = C1G ? c : LD;   // row stride of c1
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int ldg = (c > m) ? 2 * m : m;
   for (int q = tid; q < c * m; q += kHlThreads) {
     const int i = q / m, j = q % m;
     const double x = C[(int64_t)i * c + j];
     G[(int64_t)i * ldg + j] = x;
-    c1[i * LD + j] = x;
+    if constexpr (!C1G) c1s[i * LD + j] = x;
   }
   if (c <= m) return;
   __syncthreads();
@@ -1262,7 +1422,7 @@ __global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __rest
   // W = E1 - C1 C1(0:m, :)^T
   for (int tile = wid; tile < tr * tcm; tile += 4) {
     const int i0 = 16 * (tile / tcm), j0 = 16 * (tile % tcm);
-    const Mfma<double>::v4 acc = tile_mm(c1 + i0 * LD, LD, 1, c - i0, c1 + j0 * LD, 1, LD, m - j0, m);
+    const Mfma<double>::v4 acc = tile_mm(c1 + i0 * l1, l1, 1, c - i0, c1 + j0 * l1, 1, l1, m - j0, m);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = i0 + Mfma<double>::drow(lane, q), j = j0 + (lane & 15);
@@ -1276,7 +1436,7 @@ __global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __rest
     // T = C1^T W, then W -= C1 T
     for (int tile = wid; tile < tcm * tcm; tile += 4) {
       const int l0 = 16 * (tile / tcm), j0 = 16 * (tile % tcm);
-      const Mfma<double>::v4 acc = tile_mm(c1 + l0, 1, LD, m - l0, w + j0, LD, 1, m - j0, c);
+      const Mfma<double>::v4 acc = tile_mm(c1 + l0, 1, l1, m - l0, w + j0, LD, 1, m - j0, c);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int l = l0 + Mfma<double>::drow(lane, q), j = j0 + (lane & 15);
@@ -1286,7 +1446,7 @@ __global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __rest
     __syncthreads();
     for (int tile = wid; tile < tr * tcm; tile += 4) {
       const int i0 = 16 * (tile / tcm), j0 = 16 * (tile % tcm);
-      const Mfma<double>::v4 acc = tile_mm(c1 + i0 * LD, LD, 1, c - i0, tm + j0, LD, 1, m - j0, m);
+      const Mfma<double>::v4 acc = tile_mm(c1 + i0 * l1, l1, 1, c - i0, tm + j0, LD, 1, m - j0, m);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + Mfma<double>::drow(lane, q), j = j0 + (lane & 15);
@@ -1463,7 +1623,7 @@ __global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __res
 
 }  // namespace
 
-int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c + 16; }
+int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c + 4 * (int64_t)c + 16; }
 
 namespace {
 template <int NB>
@@ -1493,14 +1653,22 @@ void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, int nev, 
     launch_syev_reg<3>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
   else if (c <= 96)
     launch_syev_reg<6>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
-  else
-    syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
+  else if (c <= 192 && nev >= kSyevSplitMinNev && (int64_t)B * nev <= kSyevSplitMaxBlocks) {
+    syev_tridiag32_kernel<<<B, kSyevThreads32, 0, st>>>(H, ldh, hstride, c, work, ws, active);
+    syev_bisect_kernel<<<dim3(nev, B), kSyevThreads, 0, st>>>(work, ws, c, nev, active);
+    syev_kernel<1><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info,
+                                               active);
+  } else
+    syev_kernel<0><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info,
+                                               active);
 }
 
 void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, int64_t gstride,
                      const int32_t* active, int B, hipStream_t st) {
   if (m <= 16 && c <= 48) hl_reg_kernel<1, 3><<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
   else if (m <= 32 && c <= 96) hl_reg_kernel<2, 6><<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
+  else if (m <= 64 && c <= 192)
+    hl_reg_kernel<4, 12, true><<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
   else hl_build_kernel<<<B, kHlThreads, 0, st>>>(C, cstride, c, m, G, gstride, active);
 }
 

@@ -73,6 +73,10 @@ SIGNATURES = {
     "lobpcg_solve_batched": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p,
                                         ct.POINTER(Info)]),
     "lobpcg_batch_count": (ct.c_int32, [ct.c_void_p]),
+    "lobpcg_setup_hermitian": (ct.c_int, [ct.POINTER(Matrix), ct.c_int32, ct.c_int32, ct.c_double, ct.c_int,
+                                          ct.c_void_p, ct.POINTER(Options), ct.POINTER(ct.c_void_p)]),
+    "lobpcg_solve_hermitian": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                          ct.POINTER(Info)]),
     "lobpcg_pinvit": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.POINTER(Info),
                                  ct.c_void_p]),
     "lobpcg_backward": (ct.c_int, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),

@@ -76,18 +76,21 @@ def make_matrix(A, grid=(0, 0, 0)):
     M = nv.Matrix()
     M.grid[0], M.grid[1], M.grid[2] = [int(g) for g in grid]
     if isinstance(A, np.ndarray):
-        Ad = np.ascontiguousarray(A, dtype=np.float64)
-        M.format = 1
+        cplx = np.iscomplexobj(A)
+        Ad = np.ascontiguousarray(A, dtype=np.complex128 if cplx else np.float64)
+        M.format = 3 if cplx else 1
         M.n = Ad.shape[0]
         M.ld = Ad.shape[1]
         M.dense = Ad.ctypes.data
         return M, (Ad,)
     import scipy.sparse as sp
     Ac = sp.csr_matrix(A)
+    Ac.sort_indices()
+    cplx = np.iscomplexobj(Ac.data)
     rp = np.ascontiguousarray(Ac.indptr, dtype=np.int32)
     ci = np.ascontiguousarray(Ac.indices, dtype=np.int32)
-    va = np.ascontiguousarray(Ac.data, dtype=np.float64)
-    M.format = 0
+    va = np.ascontiguousarray(Ac.data, dtype=np.complex128 if cplx else np.float64)
+    M.format = 2 if cplx else 0
     M.n = Ac.shape[0]
     M.nnz = va.size
     M.rowptr = rp.ctypes.data
@@ -144,8 +147,9 @@ class Solver:
                      (nv.LOBPCG_FLAG_FORCE_FP64_REDO if force_fp64_redo else 0))
         ctx = ct.c_void_p()
         self.ctx = None
-        st = self.lib.lobpcg_setup(ct.byref(M), k, m, tol, _PREC[factor_precision], _stream(), ct.byref(opt),
-                                   ct.byref(ctx))
+        self.hermitian = M.format in (2, 3)
+        setup = self.lib.lobpcg_setup_hermitian if self.hermitian else self.lib.lobpcg_setup
+        st = setup(ct.byref(M), k, m, tol, _PREC[factor_precision], _stream(), ct.byref(opt), ct.byref(ctx))
         del keep
         nv.check(st)
         self.ctx = ctx
@@ -170,15 +174,27 @@ class Solver:
             pass
 
     def solve(self, X0=None, maxit: int = 1000, allow_not_converged: bool = False):
+        """(evals, evecs, info); evecs is complex128 (n x k) for a Hermitian matrix."""
         torch = _torch()
-        x0 = _dev_f64(X0, (self.n, self.m)) if X0 is not None else None
+        if self.hermitian:
+            x0 = None
+            if X0 is not None:
+                x0 = (torch.from_numpy(np.ascontiguousarray(X0, dtype=np.complex128)) if isinstance(X0, np.ndarray)
+                      else X0).to(device="cuda", dtype=torch.complex128).contiguous()
+                if tuple(x0.shape) != (self.n, self.m):
+                    raise ValueError(f"expected shape {(self.n, self.m)}, got {tuple(x0.shape)}")
+            evecs = torch.empty((self.n, self.k), dtype=torch.complex128, device="cuda")
+            solve = self.lib.lobpcg_solve_hermitian
+        else:
+            x0 = _dev_f64(X0, (self.n, self.m)) if X0 is not None else None
+            evecs = torch.empty((self.n, self.k), dtype=torch.float64, device="cuda")
+            solve = self.lib.lobpcg_solve
         evals = torch.empty(self.k, dtype=torch.float64, device="cuda")
-        evecs = torch.empty((self.n, self.k), dtype=torch.float64, device="cuda")
         info = nv.Info()
         res = np.zeros(self.k, dtype=np.float64)
         info.resid = res.ctypes.data
         allow = (nv.LOBPCG_OK, nv.LOBPCG_NOT_CONVERGED) if allow_not_converged else (nv.LOBPCG_OK,)
-        st = self.lib.lobpcg_solve(self.ctx, _ptr(x0), maxit, _ptr(evals), _ptr(evecs), ct.byref(info))
+        st = solve(self.ctx, _ptr(x0), maxit, _ptr(evals), _ptr(evecs), ct.byref(info))
         nv.check(st, allow)
         out = {f: getattr(info, f) for f, _ in nv.Info._fields_ if f != "resid"}
         out["resid"] = res.copy()

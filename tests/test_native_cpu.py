@@ -168,3 +168,19 @@ def test_mixed_qr_noalloc_rejects_oversized_problems_before_gpu_work(lib):
     assert st == nv.LOBPCG_ERR_INVALID_ARG and "scratch" in nv.last_error()
     st = lib.lobpcg_mixed_qr_noalloc(fake, 100, 65, 65, 1, None, None)
     assert st == nv.LOBPCG_ERR_INVALID_ARG
+
+
+def test_hermitian_setup_validates_on_the_host(lib):
+    # complex CSR (format 2): a matrix that is not Hermitian, and block sizes beyond the embedding's limit,
+    # are rejected before any GPU work
+    A = synth.gauge_laplace2d(6, 7).tolil()
+    A[0, 1] = A[0, 1] * 1j   # breaks A_10 = conj(A_01)
+    M, keep = sv.make_matrix(A.tocsr(), (6, 7, 1))
+    assert M.format == 2
+    ctx = ct.c_void_p()
+    st = lib.lobpcg_setup_hermitian(ct.byref(M), 2, 4, 1e-10, nv.LOBPCG_FP32, None, None, ct.byref(ctx))
+    assert st == nv.LOBPCG_ERR_INVALID_ARG and "Hermitian" in nv.last_error()
+    M, keep = sv.make_matrix(synth.gauge_laplace2d(6, 7), (6, 7, 1))
+    st = lib.lobpcg_setup_hermitian(ct.byref(M), 2, 40, 1e-10, nv.LOBPCG_FP32, None, None, ct.byref(ctx))
+    assert st == nv.LOBPCG_ERR_INVALID_ARG and "m must be" in nv.last_error()
+    assert lib.lobpcg_solve_hermitian(None, None, 10, None, None, None) == nv.LOBPCG_ERR_INVALID_ARG
