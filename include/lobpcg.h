@@ -240,8 +240,8 @@ lobpcg_status lobpcg_solve_batched(lobpcg_ctx ctx, const double* const* X0, int3
  * interleaved (2 ld doubles per row).  Host pointers; a grid hint (g0, g1, 1) is used for ordering.
  * The context holds the real symmetric positive definite embedding M = [[B, -C], [C, B]] of
  * A = B + iC (order 2n): each eigenvalue of A is a double eigenvalue of M, so the loop runs with 2k
- * wanted pairs and block 2m, and the factor of M is the real form of A's complex Cholesky factor, held
- * in factor_precision.  Requires 1 <= k <= m <= 32 and 6m <= 2n; dense n <= 8192.  Errors as
+ * wanted pairs and block 2m, and the preconditioner is the Cholesky factor of M (nested dissection on
+ * M's graph), held in factor_precision.  Requires 1 <= k <= m <= 32 and 6m <= 2n; dense n <= 8192.  Errors as
  * lobpcg_setup (INVALID_ARG also for a matrix that is not Hermitian). */
 lobpcg_status lobpcg_setup_hermitian(const lobpcg_matrix* A, int32_t k, int32_t m, double tol,
                                      lobpcg_precision factor_precision, void* hip_stream,
