@@ -340,10 +340,11 @@ lobpcg_status lobpcg_gram(const double* X, int64_t ldx, const double* Y, int64_t
                           int32_t c1, int32_t c2, double* G, void* hip_stream);
 
 /* Symmetric eigensolver for a small c x c FP64 matrix (device, row-major,
- * symmetrised as (H + H^T)/2): evals ascending (device, c), evecs (device,
- * c x c row-major, column j = eigenvector j).  c <= 192.  (Algorithm 3
- * line 14.) */
-lobpcg_status lobpcg_syev_small(const double* H, int32_t c, double* evals, double* evecs,
+ * symmetrised as (H + H^T)/2): the nev smallest eigenpairs, evals ascending
+ * (device, nev), evecs (device, c x c row-major; column j < nev =
+ * eigenvector j, the other columns are not written).  1 <= nev <= c <= 192.
+ * (Algorithm 3 line 14.) */
+lobpcg_status lobpcg_syev_small(const double* H, int32_t c, int32_t nev, double* evals, double* evecs,
                                 void* hip_stream);
 
 #ifdef __cplusplus

@@ -2421,13 +2421,15 @@ lobpcg_status lobpcg_gram(const double* X, int64_t ldx, const double* Y, int64_t
   return s;
 }
 
-lobpcg_status lobpcg_syev_small(const double* H, int32_t cc, double* evals, double* evecs, void* hip_stream) {
-  if (!H || !evals || !evecs || cc < 1 || cc > 192) return fail(LOBPCG_ERR_INVALID_ARG, "bad arguments to syev");
+lobpcg_status lobpcg_syev_small(const double* H, int32_t cc, int32_t nev, double* evals, double* evecs,
+                                void* hip_stream) {
+  if (!H || !evals || !evecs || cc < 1 || cc > 192 || nev < 1 || nev > cc)
+    return fail(LOBPCG_ERR_INVALID_ARG, "bad arguments to syev");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   void* work = nullptr;
   HIP_TRY(hipMalloc(&work, (size_t)syev_scratch(cc) * 8 + 64));
   int* info = reinterpret_cast<int*>(static_cast<char*>(work) + syev_scratch(cc) * 8);
-  launch_syev(H, cc, 0, cc, cc, evals, 0, evecs, 0, static_cast<double*>(work), info, nullptr, 1, st);
+  launch_syev(H, cc, 0, cc, nev, evals, 0, evecs, 0, static_cast<double*>(work), info, nullptr, 1, st);
   lobpcg_status s = check_launch("syev");
   (void)hipStreamSynchronize(st);
   (void)hipFree(work);

@@ -5,6 +5,7 @@
 //    C(1:m, m+1:c)^T and G = [C(:,1:m), C(:,m+1:c) V];
 //  * Algorithm 2's step 3: the Cholesky factorization of V^T V.
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "mfma.hpp"
@@ -141,13 +142,13 @@ __device__ inline int sturm_count_scaled(const double* ds, const double* e2s, in
 }
 
 // Modified Gram-Schmidt inside the clusters of eigenvectors (eigenvalue order) with Z (c x nev,
-// c, nev <= 16 NB) in registers: thread (slot s = tid / 16, lane q16 of its 16-lane row) holds rows
-// q16 + 16 u of columns s + 16 h, so column sums are 16-lane DPP sums.  Column q is published by its
-// owners (one barrier, buffers alternating per executed step); the later members of its cluster
+// c <= 16 NR, nev <= 16 NC) in registers: thread (slot s = tid / 16, lane q16 of its 16-lane row) holds
+// rows q16 + 16 u of columns s + 16 h, so column sums are 16-lane DPP sums.  Column q is published by
+// its owners (one barrier, buffers alternating per executed step); the later members of its cluster
 // subtract their projections on it and the owners of q + 1 normalise it right away.  HQ is static
 // (column block of q), so register indices are static.
-template <int NB, int HQ>
-__device__ __attribute__((always_inline)) void cluster_mgs_cols(double (&z)[NB][NB], int nev, const short* cend,
+template <int NR, int NC, int HQ>
+__device__ __attribute__((always_inline)) void cluster_mgs_cols(double (&z)[NC][NR], int nev, const short* cend,
                                                                 double* wb0, double* wb1, int& ns) {
   const int tid = threadIdx.x, q16 = tid & 15, slot = tid >> 4;
 #pragma unroll 1
@@ -160,42 +161,211 @@ __device__ __attribute__((always_inline)) void cluster_mgs_cols(double (&z)[NB][
     ++ns;
     if (slot == sq) {
 #pragma unroll
-      for (int u = 0; u < NB; ++u) wb[q16 + 16 * u] = z[HQ][u];
+      for (int u = 0; u < NR; ++u) wb[q16 + 16 * u] = z[HQ][u];
     }
     __syncthreads();
-    double wq[NB];
+    double wq[NR];
 #pragma unroll
-    for (int u = 0; u < NB; ++u) wq[u] = wb[q16 + 16 * u];
+    for (int u = 0; u < NR; ++u) wq[u] = wb[q16 + 16 * u];
 #pragma unroll
-    for (int h = HQ; h < NB; ++h) {
+    for (int h = HQ; h < NC; ++h) {
       const int col = slot + 16 * h;
       if (col > q && col < qe) {   // uniform over the 16 lanes of a slot
         double dt = 0.0;
 #pragma unroll
-        for (int u = 0; u < NB; ++u) dt = fma(z[h][u], wq[u], dt);
+        for (int u = 0; u < NR; ++u) dt = fma(z[h][u], wq[u], dt);
         dt = row16_sum(dt);
 #pragma unroll
-        for (int u = 0; u < NB; ++u) z[h][u] = fma(-dt, wq[u], z[h][u]);
+        for (int u = 0; u < NR; ++u) z[h][u] = fma(-dt, wq[u], z[h][u]);
         if (col == q + 1) {
           double nn = 0.0;
 #pragma unroll
-          for (int u = 0; u < NB; ++u) nn = fma(z[h][u], z[h][u], nn);
+          for (int u = 0; u < NR; ++u) nn = fma(z[h][u], z[h][u], nn);
           const double inv = 1.0 / sqrt(row16_sum(nn));
 #pragma unroll
-          for (int u = 0; u < NB; ++u) z[h][u] *= inv;
+          for (int u = 0; u < NR; ++u) z[h][u] *= inv;
         }
       }
     }
   }
-  if constexpr (HQ + 1 < NB) cluster_mgs_cols<NB, HQ + 1>(z, nev, cend, wb0, wb1, ns);
+  if constexpr (HQ + 1 < NC) cluster_mgs_cols<NR, NC, HQ + 1>(z, nev, cend, wb0, wb1, ns);
+}
+
+// Inverse iteration for eigenvector j of the tridiagonal T (diagonal d, off-diagonal e) at its
+// eigenvalue lj, one thread per vector.  The factors of P (T - lj I) = L U (partial pivoting, as LAPACK's
+// dlagtf) are stored per step k at [k nev + j]: U0 the reciprocal of U's diagonal (an entry below tiny
+// in magnitude taken as +-tiny), U1 its first superdiagonal, Lm the multiplier of L, Pv 1 where rows k
+// and k + 1 were swapped (U's second superdiagonal is then e[k + 1], else 0).  Every pass runs in chunks
+// of CH steps whose loads carry no condition, so that they are issued together before the chunk's
+// arithmetic, and a step-by-step tail.
+//
+// One elimination step on the active row (cd, cs) and the next row (sub, nd, ns) of T - lj I, with the
+// forward substitution of the right-hand side (zk, zn) carried along.  With FAST the multiplier uses the
+// reciprocal pivot from rcp_nr (no division in the dependent chain) and bad is set where the pivot lies
+// outside [2^-1000, 2^1000], where that reciprocal is not accurate; otherwise it is the quotient itself.
+template <bool FAST>
+__device__ __attribute__((always_inline)) void ii_step(double& cd, double& cs, double& zk, double sub, double nd,
+                                                       double ns, double zn, double tiny, double rtiny, bool& bad,
+                                                       double* u0, double* u1, double* lm, double* pv, double* zo) {
+  const bool sw = !(fabs(cd) >= fabs(sub));
+  const double piv = sw ? sub : cd, oth = sw ? cd : sub;
+  const double big = (piv < 0.0) ? -rtiny : rtiny;
+  double m, rp;
+  if constexpr (FAST) {
+    rp = rcp_nr(piv);
+    bad |= !(fabs(piv) >= 0x1p-1000 && fabs(piv) <= 0x1p+1000);
+    m = oth * rp;
+  } else {
+    rp = 1.0 / piv;
+    m = (piv != 0.0) ? oth / piv : 0.0;   // |m| <= 1; piv == 0 only when sub == cd == 0
+  }
+  *u0 = (fabs(piv) >= tiny) ? rp : big;
+  *u1 = sw ? nd : cs;
+  *lm = m;
+  *pv = sw ? 1.0 : 0.0;
+  const double ncd = sw ? cs - m * nd : nd - m * cs;
+  cs = sw ? -m * ns : ns;
+  cd = ncd;
+  const double lo = sw ? zn : zk, hi = sw ? zk : zn;
+  *zo = lo;
+  zk = hi - m * lo;
+}
+
+// Factorization fused with the first forward substitution P, L^-1 of the fixed start vector
+// s_i = 1 + ((7 i + 13 j) mod 11) / 44 (not orthogonal to any eigenvector of interest); the result goes to
+// Z.  A thread whose fast pass met a pivot outside rcp_nr's range redoes the pass with divisions.
+template <int CH>
+__device__ __attribute__((always_inline)) void ii_factor(const double* d, const double* e, int c, int nev, int j,
+                                                         double lj, double tiny, double rtiny, double* U0, double* U1,
+                                                         double* Lm, double* Pv, double* Z, int lz) {
+  auto start = [j](int i) { return 1.0 + (double)((7 * i + 13 * j) % 11) * (0.25 / 11.0); };
+  auto pass = [&](auto fast) -> bool {
+    constexpr bool F = decltype(fast)::value;
+    bool bad = false;
+    double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0, zk = start(0);
+    int k0 = 0;
+    if constexpr (F) {
+      for (; k0 + CH + 1 < c; k0 += CH) {   // every step of the chunk has k + 2 < c
+        double ek[CH], dn[CH], en[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          ek[u] = e[k0 + u];
+          dn[u] = d[k0 + u + 1];
+          en[u] = e[k0 + u + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int k = k0 + u;
+          ii_step<true>(cd, cs, zk, ek[u], dn[u] - lj, en[u], start(k + 1), tiny, rtiny, bad, &U0[k * nev + j],
+                        &U1[k * nev + j], &Lm[k * nev + j], &Pv[k * nev + j], &Z[k * lz + j]);
+        }
+      }
+    }
+    for (; k0 + 1 < c; ++k0)
+      ii_step<F>(cd, cs, zk, e[k0], d[k0 + 1] - lj, (k0 + 2 < c) ? e[k0 + 1] : 0.0, start(k0 + 1), tiny, rtiny, bad,
+                 &U0[k0 * nev + j], &U1[k0 * nev + j], &Lm[k0 * nev + j], &Pv[k0 * nev + j], &Z[k0 * lz + j]);
+    const double rl = F ? rcp_nr(cd) : 1.0 / cd;
+    if (F) bad |= !(fabs(cd) >= 0x1p-1000 && fabs(cd) <= 0x1p+1000);
+    U0[(c - 1) * nev + j] = (fabs(cd) >= tiny) ? rl : ((cd < 0.0) ? -rtiny : rtiny);
+    Z[(c - 1) * lz + j] = zk;
+    return bad;
+  };
+  if (pass(std::true_type{})) pass(std::false_type{});
+}
+
+// Forward substitution P, L^-1 applied to Z's column j in place.
+template <int CH>
+__device__ __attribute__((always_inline)) void ii_forward(int c, int nev, int j, const double* Lm, const double* Pv,
+                                                          double* Z, int lz) {
+  double zk = Z[j];
+  int k0 = 0;
+  for (; k0 + CH < c; k0 += CH) {   // every step of the chunk has k + 1 < c
+    double pv[CH], lm[CH], zn[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      pv[u] = Pv[(k0 + u) * nev + j];
+      lm[u] = Lm[(k0 + u) * nev + j];
+      zn[u] = Z[(k0 + u + 1) * lz + j];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const bool sw = pv[u] != 0.0;
+      const double lo = sw ? zn[u] : zk, hi = sw ? zk : zn[u];
+      Z[(k0 + u) * lz + j] = lo;
+      zk = hi - lm[u] * lo;
+    }
+  }
+  for (; k0 + 1 < c; ++k0) {
+    const bool sw = Pv[k0 * nev + j] != 0.0;
+    const double zn = Z[(k0 + 1) * lz + j];
+    const double lo = sw ? zn : zk, hi = sw ? zk : zn;
+    Z[k0 * lz + j] = lo;
+    zk = hi - Lm[k0 * nev + j] * lo;
+  }
+  Z[(c - 1) * lz + j] = zk;
+}
+
+// Back substitution U^-1 on Z's column j in place, then scaling of the column to unit 2-norm.
+template <int CH>
+__device__ __attribute__((always_inline)) void ii_backward(const double* e, int c, int nev, int j, const double* U0,
+                                                           const double* U1, const double* Pv, double* Z, int lz) {
+  // rows c - 1 and c - 2 first (no superdiagonal entries beyond the matrix)
+  double z1 = Z[(c - 1) * lz + j] * U0[(c - 1) * nev + j], z2 = 0.0;   // Z[k + 1], Z[k + 2]
+  Z[(c - 1) * lz + j] = z1;
+  double nrm = z1 * z1;
+  if (c >= 2) {
+    const int k = c - 2;
+    const double y = (Z[k * lz + j] - U1[k * nev + j] * z1) * U0[k * nev + j];
+    Z[k * lz + j] = y;
+    nrm = fma(y, y, nrm);
+    z2 = z1;
+    z1 = y;
+  }
+  int k0 = c - 3;
+  for (; k0 - CH + 1 >= 0; k0 -= CH) {   // rows k0 .. k0 - CH + 1
+    double u0[CH], u1[CH], u2[CH], zz[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int k = k0 - u;
+      u0[u] = U0[k * nev + j];
+      u1[u] = U1[k * nev + j];
+      u2[u] = Pv[k * nev + j] * e[k + 1];
+      zz[u] = Z[k * lz + j];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const double y = ((zz[u] - u1[u] * z1) - u2[u] * z2) * u0[u];
+      Z[(k0 - u) * lz + j] = y;
+      nrm = fma(y, y, nrm);
+      z2 = z1;
+      z1 = y;
+    }
+  }
+  for (; k0 >= 0; --k0) {
+    const double y = ((Z[k0 * lz + j] - U1[k0 * nev + j] * z1) - Pv[k0 * nev + j] * e[k0 + 1] * z2) * U0[k0 * nev + j];
+    Z[k0 * lz + j] = y;
+    nrm = fma(y, y, nrm);
+    z2 = z1;
+    z1 = y;
+  }
+  const double sc = 1.0 / sqrt(nrm);
+  int i0 = 0;
+  for (; i0 + CH <= c; i0 += CH) {
+    double zz[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) zz[u] = Z[(i0 + u) * lz + j];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) Z[(i0 + u) * lz + j] = zz[u] * sc;
+  }
+  for (; i0 < c; ++i0) Z[i0 * lz + j] *= sc;
 }
 
 // Steps 2 and 3 for the tridiagonal T (diagonal d, off-diagonal e in LDS, e[c - 1] = 0): the nev
 // smallest eigenvalues in lam and the eigenvectors of T in Z (c x nev, row stride lz).  s1, s3:
-// c + 8 doubles of LDS each, s2: c; cnt: one int per thread; lu: 5 c nev doubles of global scratch.
+// c + 8 doubles of LDS each, s2: c; cnt: one int per thread; lu: 4 c nev doubles (LDS or global scratch).
 // Returns the largest number of later members of a cluster (0 when every eigenvalue is isolated);
 // Z and lam are complete and visible to the whole workgroup on return.
-template <int NB, bool PRESET = false>
+template <int NR, int NC, bool PRESET = false, int CH = 8>
 __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, const double* e, int c, int nev, double* s1, double* s2,
                             double* s3, double* lam, int* cnt, short* cend, double* Z, int lz, double* lu) {
   const int tid = threadIdx.x, lane = tid % 64, wid = tid / 64;
@@ -300,127 +470,37 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   }
   double* U0 = lu;
   double* U1 = lu + (int64_t)c * nev;
-  double* U2 = lu + 2 * (int64_t)c * nev;
-  double* Lm = lu + 3 * (int64_t)c * nev;
-  double* Pv = lu + 4 * (int64_t)c * nev;
+  double* Lm = lu + 2 * (int64_t)c * nev;
+  double* Pv = lu + 3 * (int64_t)c * nev;
   const double tiny = eps * tnorm + pivmin;
-  // the diagonal of U with entries below tiny replaced by +-tiny (the elimination itself keeps the
-  // unreplaced pivots); U0 holds the reciprocals of that diagonal
-  auto clamp_tiny = [tiny](double u) { return (fabs(u) < tiny) ? ((u < 0.0) ? -tiny : tiny) : u; };
-  for (int j = tid; j < nev; j += kSyevThreads) {
-    const double lj = lam[j];
-    double cd = d[0] - lj, cs = (c > 1) ? e[0] : 0.0;
-    for (int k = 0; k + 1 < c; ++k) {
-      // partial pivoting between the current row (cd, cs, 0) and the next (sub, nd, ns), written
-      // with selects so that the lanes of a wave share one division
-      const double sub = e[k];
-      const double nd = d[k + 1] - lj;
-      const double ns = (k + 2 < c) ? e[k + 1] : 0.0;
-      const bool sw = !(fabs(cd) >= fabs(sub));
-      const double piv = sw ? sub : cd;
-      const double m = (piv != 0.0) ? (sw ? cd : sub) / piv : 0.0;   // piv == 0 only when sub == 0
-      U0[k * nev + j] = 1.0 / clamp_tiny(piv);
-      U1[k * nev + j] = sw ? nd : cs;
-      U2[k * nev + j] = sw ? ns : 0.0;
-      Pv[k * nev + j] = sw ? 1.0 : 0.0;
-      Lm[k * nev + j] = m;
-      const double ncd = sw ? cs - m * nd : nd - m * cs;
-      cs = sw ? -m * ns : ns;
-      cd = ncd;
-    }
-    U0[(c - 1) * nev + j] = 1.0 / clamp_tiny(cd);
-  }
-  // start vectors, fixed and not orthogonal to any eigenvector of interest
-  for (int q = tid; q < c * nev; q += kSyevThreads) {
-    const int i = q / nev, j = q - i * nev;
-    Z[i * lz + j] = 1.0 + (double)((i * 7 + j * 13) % 11) * (0.25 / 11.0);
-  }
-  __syncthreads();
+  const double rtiny = 1.0 / tiny;
   int maxrank = 0;
-  for (int j = 0; j < nev; ++j) maxrank = max(maxrank, (int)cend[j] - j - 1);
   for (int itn = 0; itn < 2; ++itn) {
     for (int j = tid; j < nev; j += kSyevThreads) {
-      // forward: P and L, carrying the running entry in a register; factors fetched 4 steps ahead
-      double zk = Z[j];
-      for (int k0 = 0; k0 + 1 < c; k0 += 4) {
-        double pv[4], lm[4], zn[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + u;
-          const bool ok = k + 1 < c;
-          pv[u] = ok ? Pv[k * nev + j] : 0.0;
-          lm[u] = ok ? Lm[k * nev + j] : 0.0;
-          zn[u] = ok ? Z[(k + 1) * lz + j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 + u;
-          if (k + 1 >= c) break;
-          double lo_ = zk, hi_ = zn[u];
-          if (pv[u] != 0.0) {
-            lo_ = zn[u];
-            hi_ = zk;
-          }
-          Z[k * lz + j] = lo_;
-          zk = hi_ - lm[u] * lo_;
-        }
-      }
-      Z[(c - 1) * lz + j] = zk;
-      // backward: U with two superdiagonals, factors fetched 4 steps ahead
-      double nrm = 0.0, z1 = 0.0, z2 = 0.0;   // Z[k + 1], Z[k + 2]
-      for (int k0 = c - 1; k0 >= 0; k0 -= 4) {
-        double u0[4], u1[4], u2[4], zz[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 - u;
-          const bool ok = k >= 0;
-          u0[u] = ok ? U0[k * nev + j] : 1.0;   // reciprocal pivot
-          u1[u] = ok ? U1[k * nev + j] : 0.0;
-          u2[u] = ok ? U2[k * nev + j] : 0.0;
-          zz[u] = ok ? Z[k * lz + j] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int k = k0 - u;
-          if (k < 0) break;
-          double y = zz[u];
-          if (k + 1 < c) y -= u1[u] * z1;
-          if (k + 2 < c) y -= u2[u] * z2;
-          y *= u0[u];
-          Z[k * lz + j] = y;
-          nrm += y * y;
-          z2 = z1;
-          z1 = y;
-        }
-      }
-      nrm = 1.0 / sqrt(nrm);
-      for (int i0 = 0; i0 < c; i0 += 8) {
-        double zz[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) zz[u] = (i0 + u < c) ? Z[(i0 + u) * lz + j] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (i0 + u < c) Z[(i0 + u) * lz + j] = zz[u] * nrm;
-      }
+      if (itn == 0) ii_factor<CH>(d, e, c, nev, j, lam[j], tiny, rtiny, U0, U1, Lm, Pv, Z, lz);
+      else ii_forward<CH>(c, nev, j, Lm, Pv, Z, lz);
+      ii_backward<CH>(e, c, nev, j, U0, U1, Pv, Z, lz);
     }
     __syncthreads();
-    if constexpr (NB > 0) {
+    if (itn == 0)
+      for (int j = 0; j < nev; ++j) maxrank = max(maxrank, (int)cend[j] - j - 1);
+    if constexpr (NC > 0) {
       if (maxrank > 0) {   // uniform
         const int q16 = tid & 15, slot = tid >> 4;
-        double z[NB][NB];
+        double z[NC][NR];
 #pragma unroll
-        for (int h = 0; h < NB; ++h)
+        for (int h = 0; h < NC; ++h)
 #pragma unroll
-          for (int u = 0; u < NB; ++u) {
+          for (int u = 0; u < NR; ++u) {
             const int i = q16 + 16 * u, j = slot + 16 * h;
             z[h][u] = (i < c && j < nev) ? Z[i * lz + j] : 0.0;
           }
         int ns = 0;
-        cluster_mgs_cols<NB, 0>(z, nev, cend, s1, s3, ns);
+        cluster_mgs_cols<NR, NC, 0>(z, nev, cend, s1, s3, ns);
 #pragma unroll
-        for (int h = 0; h < NB; ++h)
+        for (int h = 0; h < NC; ++h)
 #pragma unroll
-          for (int u = 0; u < NB; ++u) {
+          for (int u = 0; u < NR; ++u) {
             const int i = q16 + 16 * u, j = slot + 16 * h;
             if (i < c && j < nev) Z[i * lz + j] = z[h][u];
           }
@@ -466,27 +546,26 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
 }
 
 // Global scratch of the three-launch forms (doubles from the instance's start).  For c <= 96: the
-// inverse-iteration factors (5 c^2, when they do not fit in LDS), Q (c x c, row stride c + 1), the
+// inverse-iteration factors (4 c^2, when they do not fit in LDS), Q (c x c, row stride c + 1), the
 // diagonal and off-diagonal of T (e[c - 1] = 0) and the eigenvalues.
-// For c > 96 (the 32 x 32 grid tridiagonalization) the scratch instead holds, as the LDS/global form of
-// syev_kernel expects it, the reflectors below the subdiagonal of a (c x c, row stride c + 1) at 0, then
-// Z (c x c) and the inverse-iteration factors (5 c^2), and after them d, e, the eigenvalues and the
+// For c > 96 (the 16 x 32 grid tridiagonalization) the scratch instead holds the reflector rows V
+// (c x c, row stride c + 1) at 0, then a c x (c + 1) block only syev_kernel uses (its Z; its matrix takes
+// the place of V), the inverse-iteration factors (4 c^2), and after them d, e, the eigenvalues and the
 // reflector scalars tau (q unused).
 struct SyevSplit {
   int64_t q, d, e, lam, tau;
 };
 __device__ __host__ inline SyevSplit syev_split_offsets(int c) {
   if (c > 96) {
-    const int64_t d = 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c;
+    const int64_t d = 2 * (int64_t)c * (c + 1) + 4 * (int64_t)c * c;
     return {0, d, d + c, d + 2 * c, d + 3 * c};
   }
-  const int64_t q = 5 * (int64_t)c * c, d = q + (int64_t)c * (c + 1);
+  const int64_t q = 4 * (int64_t)c * c, d = q + (int64_t)c * (c + 1);
   return {q, d, d + c, d + 2 * c, d + 3 * c};
 }
 
-// MODE 0: all four steps.  MODE 1 (c > 96): syev_tridiag32_kernel has left the reflectors in the scratch's
-// a and d, e, tau after it, and syev_bisect_kernel the eigenvalues; steps 3 and 4 only.
-template <int MODE>
+// All four steps in one workgroup per problem, the matrix in LDS (c <= 96) or in the global scratch: the
+// form for c > 96 when the three-launch form does not apply (large batches, nev > 64).
 __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __restrict__ H, int64_t ldh,
                                                             int64_t hstride, int c, int nev,
                                                             double* __restrict__ evals, int64_t estride,
@@ -512,17 +591,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
   const bool in_lds = (c <= kSyevLds);
   double* a = in_lds ? sa : work;
   double* Z = in_lds ? sz : work + (int64_t)c * la;   // c x nev, row stride la
-  double* lu = work + 2 * (int64_t)c * la;            // U0 | U1 | U2 | L | piv, each c x nev, index [k * nev + j]
-  if constexpr (MODE == 1) {
-    const SyevSplit sp = syev_split_offsets(c);
-    for (int i = tid; i < c; i += kSyevThreads) {
-      d[i] = work[sp.d + i];
-      e[i] = work[sp.e + i];
-      tau[i] = work[sp.tau + i];
-      lam[i] = (i < nev) ? work[sp.lam + i] : 0.0;
-    }
-    __syncthreads();
-  } else {
+  double* lu = work + 2 * (int64_t)c * la;            // U0 | U1 | L | piv, each c x nev, index [k * nev + j]
   for (int q = tid; q < c * c; q += kSyevThreads) {
     const int i = q / c, j = q % c;
     a[i * la + j] = 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]);
@@ -619,8 +688,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(const double* __rest
     e[c - 1] = 0.0;
   }
   __syncthreads();
-  }
-  const int maxrank = tridiag_eigs<0, MODE == 1>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, in_lds ? la : nev, lu);
+  const int maxrank = tridiag_eigs<0, 0>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, in_lds ? la : nev, lu);
   const int lz = in_lds ? la : nev;   // row stride of Z
   // ---- 4. back-transformation C = Q Z: G threads per column (a power of two), each a row segment ----
   int G = 1;
@@ -1015,9 +1083,10 @@ __device__ inline double row32_sum(double x) {
 // b < 6 (72 doubles).  Reflector k: the 32 lanes of grid row k % 16 form v and t from their entries of row
 // k and publish them; after a barrier every grid row forms its entries of p = t H v by a 32-lane sum and
 // publishes them with its share of p^T v; after a second barrier every thread applies H -= v w^T + w v^T
-// with w = p - (t / 2)(p^T v) v.  Q is not formed: the reflectors go to the scratch's a below the
-// subdiagonal (LAPACK's layout), with tau, d and e after it, for syev_kernel<1> to apply to Z.  Rows of
-// the 16-row blocks before AK and columns of the 32-column blocks before AK / 2 are finished and skipped.
+// with w = p - (t / 2)(p^T v) v.  Q is not formed: reflector k goes to row k of the scratch's V (row
+// stride c + 1; zero before entry k + 1, which is 1), with tau, d and e after it, for syev_bt_kernel to
+// apply to Z.  Rows of the 16-row blocks before AK and columns of the 32-column blocks before AK / 2 are
+// finished and skipped.
 constexpr int kT32Rows = 12, kT32Cols = 6, kSyevThreads32 = 512;
 
 template <int AK>
@@ -1054,7 +1123,7 @@ __device__ __attribute__((always_inline)) void tridiag32_rows(double (&A)[kT32Ro
         const int j = tj + 32 * b;
         const double v = (b >= BK && j > k + 1) ? A[AK][b] * scale : (j == k + 1 ? 1.0 : 0.0);
         vb[buf * CM + j] = v;
-        if (j > k + 1 && j < c) ga[(int64_t)j * la + k] = v;
+        if (j < c) ga[(int64_t)k * la + j] = v;
       }
       if (tj == 0) {
         tb[buf] = t;
@@ -1137,6 +1206,110 @@ __global__ void __launch_bounds__(kSyevThreads32) syev_tridiag32_kernel(const do
   }
 }
 
+// Step 3 for 96 < c <= 192, nev <= 64 (three-launch form, after syev_tridiag32_kernel and
+// syev_bisect_kernel): inverse iteration with Z in LDS, the factors in the global scratch and the
+// cluster re-orthonormalisation in registers (12 rows x 4 columns per thread); Z goes to C(:, 0:nev)
+// for syev_bt_kernel.
+constexpr int kVecNev = 64;
+__global__ void __launch_bounds__(kSyevThreads) syev_vec_kernel(double* __restrict__ C, int64_t cstride, int c,
+                                                                int nev, double* __restrict__ evals, int64_t estride,
+                                                                double* __restrict__ work, int64_t wstride, int* info,
+                                                                const int32_t* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
+  evals += (int64_t)blockIdx.x * estride;
+  C += (int64_t)blockIdx.x * cstride;
+  work += (int64_t)blockIdx.x * wstride;
+  __shared__ double Z[kSyevMax * (kVecNev + 1)];
+  __shared__ double d[kSyevMax], e[kSyevMax], lam[kSyevMax];
+  __shared__ double s1[kSyevMax + 8], s2[kSyevMax], s3[kSyevMax + 8];
+  __shared__ int cnt[kSyevThreads];
+  __shared__ short cend[kSyevMax];
+  const SyevSplit sp = syev_split_offsets(c);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < c; i += kSyevThreads) {
+    d[i] = work[sp.d + i];
+    e[i] = work[sp.e + i];
+    lam[i] = (i < nev) ? work[sp.lam + i] : 0.0;
+  }
+  __syncthreads();
+  const int lz = nev + 1;
+  double* lu = work + 2 * (int64_t)c * (c + 1);
+  const int maxrank = tridiag_eigs<12, 4, true, 16>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu);
+  for (int q = tid; q < c * nev; q += kSyevThreads) {
+    const int i = q / nev, j = q - i * nev;
+    C[(int64_t)i * c + j] = Z[i * lz + j];
+  }
+  for (int j = tid; j < nev; j += kSyevThreads) evals[j] = lam[j];
+  if (tid == 0 && info) info[blockIdx.x] = maxrank;
+}
+
+// Step 4 for 96 < c <= 192: C(:, 0:nev) <- Q C(:, 0:nev) with Q = H_0 H_1 ... H_{c-3} from the reflector
+// rows V of syev_tridiag32_kernel, H_k = I - tau_k v_k v_k^T applied for k = c - 3 down to 0.  Columns
+// are independent: workgroup (x, problem) takes 8 of them, 32 lanes per column, each lane 6 rows
+// (i = lane32 + 32 u) in registers, so a reflector costs a 32-lane sum and no barrier.  Reflectors are
+// staged through LDS 16 at a time (double-buffered; one barrier per 16).
+constexpr int kBtCols = 8, kBtStage = 16;
+__global__ void __launch_bounds__(kSyevThreads) syev_bt_kernel(double* __restrict__ C, int64_t cstride, int c,
+                                                               int nev, const double* __restrict__ work,
+                                                               int64_t wstride, const int32_t* __restrict__ active) {
+  if (active && !active[blockIdx.y]) return;
+  C += (int64_t)blockIdx.y * cstride;
+  work += (int64_t)blockIdx.y * wstride;
+  __shared__ double vs[2][kBtStage][kSyevMax];
+  __shared__ double ts[2][kBtStage];
+  const SyevSplit sp = syev_split_offsets(c);
+  const int tid = threadIdx.x, l32 = tid & 31;
+  const int j = kBtCols * blockIdx.x + (tid >> 5);
+  const bool jok = j < nev;
+  const int la = c + 1;
+  double z[6];
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int i = l32 + 32 * u;
+    z[u] = (jok && i < c) ? C[(int64_t)i * c + j] : 0.0;
+  }
+  const int kt = c - 3;   // first reflector applied; stages cover k = kt, kt - 1, ... in groups of 16
+  const int nst = (kt + kBtStage) / kBtStage;
+  // stage s holds reflectors k = kt - 16 s - r, r < 16 (rows of V; zero rows past k < 0)
+  auto load_stage = [&](int st, int buf) {
+    for (int q = tid; q < kBtStage * kSyevMax; q += kSyevThreads) {
+      const int r = q / kSyevMax, i = q - r * kSyevMax;
+      const int k = kt - kBtStage * st - r;
+      vs[buf][r][i] = (k >= 0 && i < c) ? work[(int64_t)k * la + i] : 0.0;
+    }
+    if (tid < kBtStage) {
+      const int k = kt - kBtStage * st - tid;
+      ts[buf][tid] = (k >= 0) ? work[sp.tau + k] : 0.0;
+    }
+  };
+  if (kt >= 0) load_stage(0, 0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) load_stage(st + 1, buf ^ 1);   // the other buffer was released by the last barrier
+#pragma unroll 4
+    for (int r = 0; r < kBtStage; ++r) {
+      const double t = ts[buf][r];
+      if (t == 0.0) continue;   // uniform
+      double v[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) v[u] = vs[buf][r][l32 + 32 * u];
+      double sdot = 0.0;
+#pragma unroll
+      for (int u = 0; u < 6; ++u) sdot = fma(v[u], z[u], sdot);
+      sdot = t * row32_sum(sdot);
+#pragma unroll
+      for (int u = 0; u < 6; ++u) z[u] = fma(-sdot, v[u], z[u]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+    const int i = l32 + 32 * u;
+    if (jok && i < c) C[(int64_t)i * c + j] = z[u];
+  }
+}
+
 // MODE 0 does all four steps.  In the three-launch form syev_tridiag_kernel does step 1 and leaves
 // T and Q^T in the global scratch (layout of syev_split_offsets), syev_bisect_kernel finds the
 // eigenvalues with one workgroup each, and MODE 1 loads T, Q^T and the eigenvalues and does steps 3
@@ -1156,9 +1329,9 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   evals += (int64_t)blockIdx.x * estride;
   C += (int64_t)blockIdx.x * cstride;
   work += (int64_t)blockIdx.x * wstride;
-  // Z (c x nev, row stride nev + 1), then the inverse-iteration factors (5 c nev) and Q (c x c,
+  // Z (c x nev, row stride nev + 1), then the inverse-iteration factors (4 c nev) and Q (c x c,
   // row stride c + 1) where they fit; what does not fit goes to the global scratch
-  constexpr int POOL = (NB <= 3) ? 2 * CM * LQ + 5 * CM * CM : 2 * CM * LQ;
+  constexpr int POOL = (NB <= 3) ? 2 * CM * LQ + 4 * CM * CM : 2 * CM * LQ;
   __shared__ double pool[POOL];
   __shared__ double vb[2][CM], pb[2][CM], pvp[2][16], tb[2];
   __shared__ double d[CM], e[CM], s1[CM + 8], s2[CM], s3[CM + 8], lam[CM];
@@ -1199,15 +1372,15 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   double* Z = pool;
   int64_t used = (int64_t)c * lz;
   double* sq;
-  const bool lu_lds = (used + 5 * (int64_t)c * nev <= POOL);   // uniform
+  const bool lu_lds = (used + 4 * (int64_t)c * nev <= POOL);   // uniform
   double* const lu = pool + used;
-  if (lu_lds) used += 5 * (int64_t)c * nev;
+  if (lu_lds) used += 4 * (int64_t)c * nev;
   const int lq = c + 1;
   if constexpr (MODE == 1) {
     sq = work + sp.q;   // Q^T, as step 1 left it
   } else {
     if (used + (int64_t)c * (c + 1) <= POOL) sq = pool + used;
-    else sq = work + 5 * (int64_t)c * nev;
+    else sq = work + 4 * (int64_t)c * nev;
 #pragma unroll
     for (int a = 0; a < NB; ++a)
 #pragma unroll
@@ -1221,8 +1394,8 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
   // ---- 2, 3. eigenvalues and eigenvectors of T ----
   // two inlined copies, so that the factors are addressed as LDS or as global memory, not through
   // generic pointers
-  const int maxrank = lu_lds ? tridiag_eigs<NB, MODE == 1>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu)
-                             : tridiag_eigs<NB, MODE == 1>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, work);
+  const int maxrank = lu_lds ? tridiag_eigs<NB, NB, MODE == 1>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu)
+                             : tridiag_eigs<NB, NB, MODE == 1>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, work);
   // ---- 4. C = Q Z (c x nev): 16 x 16 tiles, one wave per tile, 16x16x4 FP64 MFMAs ----
   typedef Mfma<double>::v4 v4;
   const int tn = (nev + 15) / 16, c4 = (c + 3) & ~3;
@@ -1623,7 +1796,7 @@ __global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __res
 
 }  // namespace
 
-int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 5 * (int64_t)c * c + 4 * (int64_t)c + 16; }
+int64_t syev_scratch(int c) { return 2 * (int64_t)c * (c + 1) + 4 * (int64_t)c * c + 4 * (int64_t)c + 16; }
 
 namespace {
 template <int NB>
@@ -1653,14 +1826,14 @@ void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, int nev, 
     launch_syev_reg<3>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
   else if (c <= 96)
     launch_syev_reg<6>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
-  else if (c <= 192 && nev >= kSyevSplitMinNev && (int64_t)B * nev <= kSyevSplitMaxBlocks) {
+  else if (c <= 192 && nev >= kSyevSplitMinNev && nev <= kVecNev && (int64_t)B * nev <= kSyevSplitMaxBlocks) {
     syev_tridiag32_kernel<<<B, kSyevThreads32, 0, st>>>(H, ldh, hstride, c, work, ws, active);
     syev_bisect_kernel<<<dim3(nev, B), kSyevThreads, 0, st>>>(work, ws, c, nev, active);
-    syev_kernel<1><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info,
-                                               active);
+    syev_vec_kernel<<<B, kSyevThreads, 0, st>>>(C, cstride, c, nev, evals, estride, work, ws, info, active);
+    syev_bt_kernel<<<dim3((nev + kBtCols - 1) / kBtCols, B), kSyevThreads, 0, st>>>(C, cstride, c, nev, work, ws,
+                                                                                    active);
   } else
-    syev_kernel<0><<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info,
-                                               active);
+    syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
 }
 
 void launch_hl_build(const double* C, int64_t cstride, int c, int m, double* G, int64_t gstride,

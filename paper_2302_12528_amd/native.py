@@ -96,7 +96,7 @@ SIGNATURES = {
                                            ct.c_void_p, ct.c_void_p]),
     "lobpcg_gram": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int64, ct.c_int32, ct.c_int32,
                                ct.c_void_p, ct.c_void_p]),
-    "lobpcg_syev_small": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "lobpcg_syev_small": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
 }
 
 _lib = None

@@ -370,12 +370,13 @@ def gram(X, Y):
     return G
 
 
-def syev_small(H):
+def syev_small(H, nev=None):
     torch = _torch()
     lib = nv.load()
     H = _dev_f64(H)
     c = H.shape[0]
-    w = torch.empty(c, dtype=torch.float64, device="cuda")
+    nev = c if nev is None else int(nev)
+    w = torch.empty(nev, dtype=torch.float64, device="cuda")
     V = torch.empty((c, c), dtype=torch.float64, device="cuda")
-    nv.check(lib.lobpcg_syev_small(_ptr(H), c, _ptr(w), _ptr(V), _stream()))
-    return w, V
+    nv.check(lib.lobpcg_syev_small(_ptr(H), c, nev, _ptr(w), _ptr(V), _stream()))
+    return w, V[:, :nev]

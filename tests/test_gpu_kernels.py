@@ -94,6 +94,34 @@ def test_syev_clusters(torch_cuda, c):
     assert np.max(np.abs(H @ V - V * w)) <= 100 * c * U64 * hn
 
 
+@pytest.mark.parametrize("c,nev", [(72, 16), (96, 32), (100, 8), (128, 40), (160, 48), (192, 32), (192, 64),
+                                   (192, 65)])
+@pytest.mark.parametrize("clustered", [False, True])
+def test_syev_partial(torch_cuda, c, nev, clustered):
+    # the nev smallest pairs, as the Rayleigh-Ritz step asks for them (c = 3m, nev = m); for c > 96 and
+    # nev <= 64 this is the inverse-iteration kernel with the factors in global memory and the separate
+    # back-transformation, nev = 65 takes the one-workgroup form
+    import paper_2302_12528_amd as pk
+    print(f"syev partial c={c} nev={nev} clustered={clustered}", flush=True)
+    rng = np.random.default_rng(200 + c + nev)
+    Q, _ = np.linalg.qr(rng.standard_normal((c, c)))
+    lam = np.sort(rng.uniform(0.0, 10.0, c))
+    if clustered:
+        # the wanted eigenvalues inside one cluster (gaps below 1e-3 ||T||), with a triple eigenvalue
+        lam[:nev] = np.sort(rng.uniform(0.001, 0.005, nev))
+        lam[3:6] = lam[3]
+    H = (Q * lam) @ Q.T
+    H = 0.5 * (H + H.T)
+    w, V = pk.syev_small(H, nev)
+    w, V = _np(w), _np(V)
+    assert w.shape == (nev,) and V.shape == (c, nev)
+    hn = np.linalg.norm(H, 2)
+    assert np.max(np.abs(w - np.linalg.eigvalsh(H)[:nev])) <= 50 * c * U64 * hn
+    assert np.all(np.diff(w) >= 0)
+    assert np.max(np.abs(V.T @ V - np.eye(nev))) <= 100 * c * U64
+    assert np.max(np.abs(H @ V - V * w)) <= 100 * c * U64 * hn
+
+
 @pytest.mark.parametrize("kappa", [1.0, 1e3, 1e6])
 @pytest.mark.parametrize("lower", [True, False])
 @pytest.mark.parametrize("nc", [(20000, 32), (5000, 16), (1000, 64), (64, 64)])
