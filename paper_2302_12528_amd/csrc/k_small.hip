@@ -545,10 +545,10 @@ __device__ __attribute__((always_inline)) int tridiag_eigs(const double* d, cons
   return maxrank;
 }
 
-// Global scratch of the three-launch forms (doubles from the instance's start).  For c <= 96: the
+// Global scratch of the split forms (doubles from the instance's start).  For c <= 96: the
 // inverse-iteration factors (4 c^2, when they do not fit in LDS), Q (c x c, row stride c + 1), the
 // diagonal and off-diagonal of T (e[c - 1] = 0) and the eigenvalues.
-// For c > 96 (the 16 x 32 grid tridiagonalization) the scratch instead holds the reflector rows V
+// For c > 96 (the reflector form) the scratch instead holds the reflector rows V
 // (c x c, row stride c + 1) at 0, then a c x (c + 1) block only syev_kernel uses (its Z; its matrix takes
 // the place of V), the inverse-iteration factors (4 c^2), and after them d, e, the eigenvalues and the
 // reflector scalars tau (q unused).
@@ -927,64 +927,105 @@ __global__ void __launch_bounds__(kSyevThreads) syev_bisect_kernel(double* __res
 // Step 1 with the work of each reflector split between two groups of four waves on the same 16 x 16
 // thread grid: the matrix group holds H (thread (ti, tj): entries (ti + 16 a, tj + 16 b)), forms v
 // and t and applies H -= v w^T + w v^T as tridiag_rows does; the Q group holds the same entries of
-// Q and applies Q -= t (Q v) v^T as soon as v is published, while the matrix group forms p = t H v.
-// M is H or Q by group; QG: this thread is in the Q group (wave-uniform).
+// Q and applies Q -= t (Q v) v^T, rows a < NB / 2 while the matrix group forms p = t H v and the
+// others while it applies the update.  The reflector of step k + 1 is formed ahead: after the second
+// barrier of step k, the grid row owning row k + 1 updates that row first, forms and publishes v and t
+// from it, and only then updates its other rows, so that the next step's first barrier does not wait
+// for a whole update followed by the owner's norms and divisions.  M is H or Q by group; QG: this thread
+// is in the Q group (wave-uniform).
+//
+// f(std::integral_constant<int, A>), ..., f(std::integral_constant<int, B - 1>), so that f may index register
+// arrays with its argument.
+template <int A, int B, typename F>
+__device__ __attribute__((always_inline)) void static_for(F&& f) {
+  if constexpr (A < B) {
+    f(std::integral_constant<int, A>{});
+    static_for<A + 1, B>(f);
+  }
+}
+
+// Owner phase: v and t of the reflector of row kk (in the static 16-row block AO) from that row's
+// entries, published in buffer kk & 1, with d[kk] and e[kk].
+template <int NB, int AO>
+__device__ __attribute__((always_inline)) void tri_owner(const double (&M)[NB][NB], int kk, int tj, double* vb,
+                                                         double* tb, double* d, double* e, double* tau, double* ga,
+                                                         int la, int c) {
+  constexpr int CM = 16 * NB;
+  const int buf = kk & 1;
+  double ss = 0.0, al = 0.0;
+#pragma unroll
+  for (int b = AO; b < NB; ++b) {
+    const int j = tj + 16 * b;
+    const double x = M[AO][b];
+    ss += (j >= kk + 2) ? x * x : 0.0;
+    al += (j == kk + 1) ? x : 0.0;
+    if (j == kk) d[kk] = x;
+  }
+  ss = row16_sum(ss);
+  al = row16_sum(al);
+  double t = 0.0, beta = al, scale = 0.0;
+  if (ss > 0.0) {
+    const double xn = sqrt(al * al + ss);
+    beta = (al >= 0.0) ? -xn : xn;
+    t = (beta - al) / beta;
+    scale = 1.0 / (al - beta);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = tj + 16 * b;
+    const double v = (b >= AO && j > kk + 1) ? M[AO][b] * scale : (j == kk + 1 ? 1.0 : 0.0);
+    vb[buf * CM + j] = v;
+    if (ga && j < c) ga[(int64_t)kk * la + j] = v;
+  }
+  if (tj == 0) {
+    tb[buf] = t;
+    e[kk] = beta;
+    if (tau) tau[kk] = t;
+  }
+}
+
+// Q rows a in [A0, A1): Q(a, :) -= t (Q(a, :) v) v^T, over the column blocks from B0 (v is zero before).
+template <int NB, int A0, int A1, int B0>
+__device__ __attribute__((always_inline)) void tri_qrows(double (&M)[NB][NB], const double (&vc)[NB], double t) {
+#pragma unroll
+  for (int a = A0; a < A1; ++a) {
+    double sq_ = 0.0;
+#pragma unroll
+    for (int b = B0; b < NB; ++b) sq_ = fma(M[a][b], vc[b], sq_);
+    const double qa = t * row16_sum(sq_);
+#pragma unroll
+    for (int b = B0; b < NB; ++b) M[a][b] -= qa * vc[b];
+  }
+}
+
 template <int NB, int AK>
 __device__ __attribute__((always_inline)) void tridiag_rows_split(double (&M)[NB][NB], bool QG, int c, int ti,
                                                                   int tj, double* vb, double* pb, double* pvp,
-                                                                  double* tb, double* d, double* e) {
-  constexpr int CM = 16 * NB;
+                                                                  double* tb, double* d, double* e, double* tau,
+                                                                  double* ga, int la) {
+  constexpr int CM = 16 * NB, QH = NB / 2;
 #pragma unroll 1
   for (int r = 0; r < 16; ++r) {
     const int k = 16 * AK + r;
     if (k + 2 >= c) break;   // uniform
     const int buf = k & 1;
-    if (!QG && ti == r) {
-      double ss = 0.0, al = 0.0;
-#pragma unroll
-      for (int b = AK; b < NB; ++b) {
-        const int j = tj + 16 * b;
-        const double x = M[AK][b];
-        ss += (j >= k + 2) ? x * x : 0.0;
-        al += (j == k + 1) ? x : 0.0;
-        if (j == k) d[k] = x;
-      }
-      ss = row16_sum(ss);
-      al = row16_sum(al);
-      double t = 0.0, beta = al, scale = 0.0;
-      if (ss > 0.0) {
-        const double xn = sqrt(al * al + ss);
-        beta = (al >= 0.0) ? -xn : xn;
-        t = (beta - al) / beta;
-        scale = 1.0 / (al - beta);
-      }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int j = tj + 16 * b;
-        vb[buf * CM + j] = (b >= AK && j > k + 1) ? M[AK][b] * scale : (j == k + 1 ? 1.0 : 0.0);
-      }
-      if (tj == 0) {
-        tb[buf] = t;
-        e[k] = beta;
-      }
-    }
+    // the owner of row k + 1 (when there is a reflector k + 1): grid row (k + 1) % 16, block AK or AK + 1
+    const bool own = !QG && (k + 3 < c) && ti == ((r + 1) & 15);
     __syncthreads();
     const double t = tb[buf];
-    if (t == 0.0) continue;   // uniform; every buffer is double-buffered by step parity
     double vc[NB];
 #pragma unroll
     for (int b = AK; b < NB; ++b) vc[b] = vb[buf * CM + tj + 16 * b];
+    if (t == 0.0) {   // uniform: the reflector is the identity, H and Q stay as they are
+      if (own) {
+        if (r < 15) tri_owner<NB, AK>(M, k + 1, tj, vb, tb, d, e, tau, ga, la, c);
+        else if constexpr (AK + 1 < NB) tri_owner<NB, AK + 1>(M, k + 1, tj, vb, tb, d, e, tau, ga, la, c);
+      }
+      continue;   // every buffer is double-buffered by step parity
+    }
     double pp[NB], vr[NB];
     if (QG) {
-#pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        double sq_ = 0.0;
-#pragma unroll
-        for (int b = AK; b < NB; ++b) sq_ = fma(M[a][b], vc[b], sq_);
-        const double qa = t * row16_sum(sq_);
-#pragma unroll
-        for (int b = AK; b < NB; ++b) M[a][b] -= qa * vc[b];
-      }
+      tri_qrows<NB, 0, QH, AK>(M, vc, t);
     } else {
 #pragma unroll
       for (int a = AK; a < NB; ++a) vr[a] = vb[buf * CM + ti + 16 * a];
@@ -1004,23 +1045,44 @@ __device__ __attribute__((always_inline)) void tridiag_rows_split(double (&M)[NB
       }
     }
     __syncthreads();
-    if (!QG) {
-      double K = 0.0;
+    if (QG) {
+      tri_qrows<NB, QH, NB, AK>(M, vc, t);
+    } else {
+      double g[16];
 #pragma unroll
-      for (int g = 0; g < 16; ++g) K += pvp[buf * 16 + g];
-      K *= 0.5 * t;
+      for (int q = 0; q < 16; ++q) g[q] = pvp[buf * 16 + q];
+#pragma unroll
+      for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+        for (int q = 0; q < h; ++q) g[q] += g[q + h];
+      const double K = 0.5 * t * g[0];
       double wc[NB];
 #pragma unroll
       for (int b = AK; b < NB; ++b) wc[b] = pb[buf * CM + tj + 16 * b] - K * vc[b];
-#pragma unroll
-      for (int a = AK; a < NB; ++a) {
+      // row a of this thread's block: H(a, :) -= v_a w^T + w_a v^T
+      auto upd = [&](auto ac) {
+        constexpr int a = decltype(ac)::value;
         const double wr = pp[a] - K * vr[a];
 #pragma unroll
         for (int b = AK; b < NB; ++b) M[a][b] -= vr[a] * wc[b] + wr * vc[b];
+      };
+      // the owner's row k + 1 first, then its reflector, then the other rows
+      const int ao = (r < 15) ? AK : AK + 1;
+      if (own) {
+        if (r < 15) {
+          upd(std::integral_constant<int, AK>{});
+          tri_owner<NB, AK>(M, k + 1, tj, vb, tb, d, e, tau, ga, la, c);
+        } else if constexpr (AK + 1 < NB) {
+          upd(std::integral_constant<int, AK + 1>{});
+          tri_owner<NB, AK + 1>(M, k + 1, tj, vb, tb, d, e, tau, ga, la, c);
+        }
       }
+      static_for<AK, NB>([&](auto ac) {
+        if (!(own && decltype(ac)::value == ao)) upd(ac);
+      });
     }
   }
-  if constexpr (AK + 1 < NB) tridiag_rows_split<NB, AK + 1>(M, QG, c, ti, tj, vb, pb, pvp, tb, d, e);
+  if constexpr (AK + 1 < NB) tridiag_rows_split<NB, AK + 1>(M, QG, c, ti, tj, vb, pb, pvp, tb, d, e, tau, ga, la);
 }
 
 // Step 1 of the three-launch form: T (d, e with e[c - 1] = 0) and Q^T to the global scratch, with
@@ -1050,7 +1112,10 @@ __global__ void __launch_bounds__(2 * kSyevThreads) syev_tridiag_kernel(const do
       if (QG) M[a][b] = (i == j) ? 1.0 : 0.0;
       else M[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
     }
-  tridiag_rows_split<NB, 0>(M, QG, c, ti, tj, &vb[0][0], &pb[0][0], &pvp[0][0], tb, d, e);
+  // reflector 0 is formed before the loop; every later one by the owner of its row at the end of the step
+  // before it
+  if (!QG && ti == 0 && c > 2) tri_owner<NB, 0>(M, 0, tj, &vb[0][0], tb, d, e, nullptr, nullptr, 0, c);
+  tridiag_rows_split<NB, 0>(M, QG, c, ti, tj, &vb[0][0], &pb[0][0], &pvp[0][0], tb, d, e, nullptr, nullptr, 0);
   double* gq = work + sp.q;
 #pragma unroll
   for (int a = 0; a < NB; ++a)
@@ -1206,24 +1271,28 @@ __global__ void __launch_bounds__(kSyevThreads32) syev_tridiag32_kernel(const do
   }
 }
 
-// Step 3 for 96 < c <= 192, nev <= 64 (three-launch form, after syev_tridiag32_kernel and
-// syev_bisect_kernel): inverse iteration with Z in LDS, the factors in the global scratch and the
-// cluster re-orthonormalisation in registers (12 rows x 4 columns per thread); Z goes to C(:, 0:nev)
-// for syev_bt_kernel.
-constexpr int kVecNev = 64;
+// Step 3 of the reflector form (96 < c <= 192, nev <= 64; after syev_tridiag32_kernel and
+// syev_bisect_kernel): inverse iteration with Z in LDS, the factors in LDS when
+// they fit beside it and in the global scratch otherwise, and the cluster re-orthonormalisation in
+// registers (NR rows x NC columns per thread, c <= 16 NR, nev <= 16 NC); Z goes to C(:, 0:nev) for
+// syev_bt_kernel.
+constexpr int kVecNev = 64, kVecPool = 18528;   // doubles: Z, and the factors when c (5 nev + 1) fits
+template <int NR, int NC>
 __global__ void __launch_bounds__(kSyevThreads) syev_vec_kernel(double* __restrict__ C, int64_t cstride, int c,
                                                                 int nev, double* __restrict__ evals, int64_t estride,
                                                                 double* __restrict__ work, int64_t wstride, int* info,
                                                                 const int32_t* __restrict__ active) {
+  constexpr int CM = 16 * NR;
+  static_assert(CM * (kVecNev + 1) <= kVecPool, "Z fits in the pool");
   if (active && !active[blockIdx.x]) return;
   evals += (int64_t)blockIdx.x * estride;
   C += (int64_t)blockIdx.x * cstride;
   work += (int64_t)blockIdx.x * wstride;
-  __shared__ double Z[kSyevMax * (kVecNev + 1)];
-  __shared__ double d[kSyevMax], e[kSyevMax], lam[kSyevMax];
-  __shared__ double s1[kSyevMax + 8], s2[kSyevMax], s3[kSyevMax + 8];
+  __shared__ double pool[kVecPool];
+  __shared__ double d[CM], e[CM], lam[CM];
+  __shared__ double s1[CM + 8], s2[CM], s3[CM + 8];
   __shared__ int cnt[kSyevThreads];
-  __shared__ short cend[kSyevMax];
+  __shared__ short cend[CM];
   const SyevSplit sp = syev_split_offsets(c);
   const int tid = threadIdx.x;
   for (int i = tid; i < c; i += kSyevThreads) {
@@ -1233,8 +1302,13 @@ __global__ void __launch_bounds__(kSyevThreads) syev_vec_kernel(double* __restri
   }
   __syncthreads();
   const int lz = nev + 1;
-  double* lu = work + 2 * (int64_t)c * (c + 1);
-  const int maxrank = tridiag_eigs<12, 4, true, 16>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, lu);
+  double* Z = pool;
+  const bool lu_lds = (int64_t)c * lz + 4 * (int64_t)c * nev <= kVecPool;   // uniform
+  // two inlined copies, so that the factors are addressed as LDS or as global memory
+  const int maxrank =
+      lu_lds ? tridiag_eigs<NR, NC, true, 8>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz, pool + (int64_t)c * lz)
+             : tridiag_eigs<NR, NC, true, 16>(d, e, c, nev, s1, s2, s3, lam, cnt, cend, Z, lz,
+                                              work + 2 * (int64_t)c * (c + 1));
   for (int q = tid; q < c * nev; q += kSyevThreads) {
     const int i = q / nev, j = q - i * nev;
     C[(int64_t)i * c + j] = Z[i * lz + j];
@@ -1243,37 +1317,38 @@ __global__ void __launch_bounds__(kSyevThreads) syev_vec_kernel(double* __restri
   if (tid == 0 && info) info[blockIdx.x] = maxrank;
 }
 
-// Step 4 for 96 < c <= 192: C(:, 0:nev) <- Q C(:, 0:nev) with Q = H_0 H_1 ... H_{c-3} from the reflector
-// rows V of syev_tridiag32_kernel, H_k = I - tau_k v_k v_k^T applied for k = c - 3 down to 0.  Columns
-// are independent: workgroup (x, problem) takes 8 of them, 32 lanes per column, each lane 6 rows
-// (i = lane32 + 32 u) in registers, so a reflector costs a 32-lane sum and no barrier.  Reflectors are
-// staged through LDS 16 at a time (double-buffered; one barrier per 16).
+// Step 4 of the reflector form: C(:, 0:nev) <- Q C(:, 0:nev) with Q = H_0 H_1 ... H_{c-3} from the reflector
+// rows V, H_k = I - tau_k v_k v_k^T applied for k = c - 3 down to 0.  Columns are independent: workgroup
+// (x, problem) takes 8 of them, 32 lanes per column, each lane RPL rows (i = lane32 + 32 u, c <= 32 RPL)
+// in registers, so a reflector costs a 32-lane sum and no barrier.  Reflectors are staged through LDS 16
+// at a time (double-buffered; one barrier per 16).
 constexpr int kBtCols = 8, kBtStage = 16;
+template <int RPL>
 __global__ void __launch_bounds__(kSyevThreads) syev_bt_kernel(double* __restrict__ C, int64_t cstride, int c,
                                                                int nev, const double* __restrict__ work,
                                                                int64_t wstride, const int32_t* __restrict__ active) {
+  constexpr int CM = 32 * RPL;
   if (active && !active[blockIdx.y]) return;
   C += (int64_t)blockIdx.y * cstride;
   work += (int64_t)blockIdx.y * wstride;
-  __shared__ double vs[2][kBtStage][kSyevMax];
+  __shared__ double vs[2][kBtStage][CM];
   __shared__ double ts[2][kBtStage];
   const SyevSplit sp = syev_split_offsets(c);
   const int tid = threadIdx.x, l32 = tid & 31;
   const int j = kBtCols * blockIdx.x + (tid >> 5);
   const bool jok = j < nev;
   const int la = c + 1;
-  double z[6];
+  double z[RPL];
 #pragma unroll
-  for (int u = 0; u < 6; ++u) {
+  for (int u = 0; u < RPL; ++u) {
     const int i = l32 + 32 * u;
     z[u] = (jok && i < c) ? C[(int64_t)i * c + j] : 0.0;
   }
-  const int kt = c - 3;   // first reflector applied; stages cover k = kt, kt - 1, ... in groups of 16
+  const int kt = c - 3;   // first reflector applied; stage s holds k = kt - 16 s - r, r < 16
   const int nst = (kt + kBtStage) / kBtStage;
-  // stage s holds reflectors k = kt - 16 s - r, r < 16 (rows of V; zero rows past k < 0)
   auto load_stage = [&](int st, int buf) {
-    for (int q = tid; q < kBtStage * kSyevMax; q += kSyevThreads) {
-      const int r = q / kSyevMax, i = q - r * kSyevMax;
+    for (int q = tid; q < kBtStage * CM; q += kSyevThreads) {
+      const int r = q / CM, i = q - r * CM;
       const int k = kt - kBtStage * st - r;
       vs[buf][r][i] = (k >= 0 && i < c) ? work[(int64_t)k * la + i] : 0.0;
     }
@@ -1291,20 +1366,20 @@ __global__ void __launch_bounds__(kSyevThreads) syev_bt_kernel(double* __restric
     for (int r = 0; r < kBtStage; ++r) {
       const double t = ts[buf][r];
       if (t == 0.0) continue;   // uniform
-      double v[6];
+      double v[RPL];
 #pragma unroll
-      for (int u = 0; u < 6; ++u) v[u] = vs[buf][r][l32 + 32 * u];
+      for (int u = 0; u < RPL; ++u) v[u] = vs[buf][r][l32 + 32 * u];
       double sdot = 0.0;
 #pragma unroll
-      for (int u = 0; u < 6; ++u) sdot = fma(v[u], z[u], sdot);
+      for (int u = 0; u < RPL; ++u) sdot = fma(v[u], z[u], sdot);
       sdot = t * row32_sum(sdot);
 #pragma unroll
-      for (int u = 0; u < 6; ++u) z[u] = fma(-sdot, v[u], z[u]);
+      for (int u = 0; u < RPL; ++u) z[u] = fma(-sdot, v[u], z[u]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 6; ++u) {
+  for (int u = 0; u < RPL; ++u) {
     const int i = l32 + 32 * u;
     if (jok && i < c) C[(int64_t)i * c + j] = z[u];
   }
@@ -1827,11 +1902,12 @@ void launch_syev(const double* H, int64_t ldh, int64_t hstride, int c, int nev, 
   else if (c <= 96)
     launch_syev_reg<6>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active, B, st);
   else if (c <= 192 && nev >= kSyevSplitMinNev && nev <= kVecNev && (int64_t)B * nev <= kSyevSplitMaxBlocks) {
+    // reflector form: tridiagonalization, bisection, inverse iteration, back-transformation
     syev_tridiag32_kernel<<<B, kSyevThreads32, 0, st>>>(H, ldh, hstride, c, work, ws, active);
     syev_bisect_kernel<<<dim3(nev, B), kSyevThreads, 0, st>>>(work, ws, c, nev, active);
-    syev_vec_kernel<<<B, kSyevThreads, 0, st>>>(C, cstride, c, nev, evals, estride, work, ws, info, active);
-    syev_bt_kernel<<<dim3((nev + kBtCols - 1) / kBtCols, B), kSyevThreads, 0, st>>>(C, cstride, c, nev, work, ws,
-                                                                                    active);
+    syev_vec_kernel<12, 4><<<B, kSyevThreads, 0, st>>>(C, cstride, c, nev, evals, estride, work, ws, info, active);
+    syev_bt_kernel<6><<<dim3((nev + kBtCols - 1) / kBtCols, B), kSyevThreads, 0, st>>>(C, cstride, c, nev, work, ws,
+                                                                                       active);
   } else
     syev_kernel<<<B, kSyevThreads, 0, st>>>(H, ldh, hstride, c, nev, evals, estride, C, cstride, work, ws, info, active);
 }
