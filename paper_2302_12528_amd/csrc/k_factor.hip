@@ -224,9 +224,9 @@ __device__ inline void load_cm_vec(T (*As)[TB + 1], const T* M, int64_t ld, int 
 //     so wave w holds 16 whole columns.  Quarter by quarter, the owning wave factors its 16 columns
 //     alone (L[c][j] of another row c is a readlane) and publishes them through LDS; after one
 //     barrier the waves to its right subtract the rank-16 product from their columns;
-//   inverse: X = inv(L) by forward substitution on the identity, each quarter for its 16 columns:
-//     the waves at or left of the published quarter take its 16 row steps (row j of X broadcast
-//     across the wave with readlane) while the waves to its right update.
+//   inverse X = inv(L) by 16 x 16 blocks: wave w inverts the diagonal block L_ww by forward
+//     substitution (lane c < 16 holds column c), then forms its blocks below the diagonal in order,
+//     X_iw = -X_ii (sum_{k = w}^{i - 1} L_ik X_kw), on the matrix cores (one barrier per block row).
 template <typename T>
 constexpr int potrf_lds_elems() { return 2 * TB * (TB + 1) + 2 * TB * ((sizeof(T) == 4) ? 20 : 18); }
 
@@ -235,11 +235,13 @@ constexpr int potrf_lds_elems() { return 2 * TB * (TB + 1) + 2 * TB * ((sizeof(T
 template <typename T>
 __device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& D, const int* tk, T* panel,
                                                                T* upd, T* dinv, int* flag, T* lds) {
-  T(*Ls)[TB + 1] = reinterpret_cast<T(*)[TB + 1]>(lds);                  // the K-major tile C(I, p)
+  T(*Ls)[TB + 1] = reinterpret_cast<T(*)[TB + 1]>(lds);                  // L, then the K-major tile C(I, p)
   T(*Xs)[TB + 1] = reinterpret_cast<T(*)[TB + 1]>(lds + TB * (TB + 1));  // Xs[k][c] = inv(L)[c][k]
   constexpr int LBS = (sizeof(T) == 4) ? 20 : 18;   // 16-byte aligned rows
-  // the published quarter of L, double-buffered
+  // the published quarter of L, double-buffered; after the factorization the first TB entries hold
+  // the reciprocals of L's diagonal
   T(*Lb)[TB][LBS] = reinterpret_cast<T(*)[TB][LBS]>(lds + 2 * TB * (TB + 1));
+  T* rd = lds + 2 * TB * (TB + 1);
   const int s = tk[0], I = tk[1], p = tk[3];
   const Sn S = sn_of(D, s);
   const int r0 = p * TB, h = min(TB, S.nc - r0);
@@ -265,15 +267,16 @@ __device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& 
     const int c = 16 * w + kk;
     a[kk] = (i < h && c < h) ? tile[i + (int64_t)c * ld] : (i == c ? (T)1 : (T)0);
   }
+  // X starts as zero: its blocks above the diagonal stay so
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    Xs[e / TB][e % TB] = (T)0;
+  }
   int bad = 0;
+  T rrow = (T)1;   // 1 / L[i][i] on lane i of the wave owning column i
   // the outer loop stays rolled: this kernel runs once per panel step, so its code is fetched cold
   // each time and must stay short
-  // x: row i, columns 16 w .. 16 w + 15 of X = inv(L): step j scales row j of X by 1 / L[j][j] and
-  // subtracts L[i][j] times it from the rows below; only quarters w <= j / 16 hold nonzero columns
-  // of row j
-  T x[16];
-#pragma unroll
-  for (int kk = 0; kk < 16; ++kk) x[kk] = (i == 16 * w + kk) ? (T)1 : (T)0;
 #pragma unroll 1
   for (int jb = 0; jb < 4; ++jb) {
     T (*lb)[LBS] = Lb[jb & 1];
@@ -287,8 +290,15 @@ __device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& 
           d = (T)1;
           if (bad == 0) bad = j + 1;
         }
-        const T ljj = sqrt(d);
-        const T rinv = (T)1 / ljj;
+        T ljj, rinv;
+        if constexpr (sizeof(T) == 4) {
+          rinv = __builtin_amdgcn_rsqf(d);   // 1 ulp: L of the FP32 preconditioner
+          ljj = d * rinv;
+        } else {
+          ljj = sqrt(d);
+          rinv = (T)1 / ljj;
+        }
+        if (i == j) rrow = rinv;
         const T li = a[jj] * rinv;
         a[jj] = (i > j) ? li : (i == j ? ljj : (T)0);
 #pragma unroll
@@ -306,18 +316,6 @@ __device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& 
       for (int jj = 0; jj < 16; ++jj)
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) a[kk] -= lrow[jj] * lb[16 * w + kk][jj];
-    } else {
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) {
-        const int j = 16 * jb + jj;
-        const T rinv = (T)1 / lb[j][jj];
-        const T lbi = (i > j) ? lb[i][jj] : (T)0;
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-          if (i == j) x[kk] *= rinv;
-          x[kk] -= lbi * rdl(x[kk], j);
-        }
-      }
     }
   }
   if (I == p && bad != 0 && i == 0 && bad <= h) flag[0] = S.begin + r0 + bad;
@@ -327,15 +325,58 @@ __device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& 
   for (int kk = 0; kk < 16; ++kk) {
     const int c = 16 * w + kk;
     if (I == p) lstage[i + TB * c] = (c <= i) ? a[kk] : (T)0;
+    Ls[i][c] = a[kk];
   }
+  if (i >= 16 * w && i < 16 * w + 16) rd[i] = rrow;   // Lb is no longer read
+  __syncthreads();
+  // X_ww = inv(L_ww): lane c < 16 of wave w solves L_ww x = e_c
+  const int w16 = 16 * w;
+  if (i < 16) {
+    T x[16];
 #pragma unroll
-  for (int kk = 0; kk < 16; ++kk) Xs[16 * w + kk][i] = x[kk];
+    for (int r = 0; r < 16; ++r) {
+      T sum = (r == i) ? (T)1 : (T)0;
+#pragma unroll
+      for (int k = 0; k < r; ++k) sum -= Ls[w16 + r][w16 + k] * x[k];
+      x[r] = sum * rd[w16 + r];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Xs[w16 + i][w16 + r] = x[r];
+  }
+  __syncthreads();
+  // X_iw for i = w + 1 + t, one block row per round; k-index of step u for this lane: drow(lane, u),
+  // so that register u of a product's accumulator is the left operand of the next product at step u
+  {
+    const int lane = tid % 64, l16 = lane % 16;
+#pragma unroll 1
+    for (int t = 0; t < 3; ++t) {
+      const int ib = w + 1 + t;
+      if (ib < 4) {
+        typename Mfma<T>::v4 acc = {0, 0, 0, 0};
+        for (int kb = w; kb < ib; ++kb)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int kx = 16 * kb + Mfma<T>::drow(lane, u);
+            acc = Mfma<T>::op(Ls[16 * ib + l16][kx], Xs[w16 + l16][kx], acc);   // T = sum_k L_ik X_kw
+          }
+        typename Mfma<T>::v4 m = {0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {   // M^T = T^T X_ii^T
+          const int kx = 16 * ib + Mfma<T>::drow(lane, u);
+          m = Mfma<T>::op(acc[u], Xs[kx][16 * ib + l16], m);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xs[w16 + Mfma<T>::drow(lane, q)][16 * ib + l16] = -m[q];
+      }
+      __syncthreads();
+    }
+  }
   if (I == p) {
     T* di = dinv + D.dinv_off[s] + (int64_t)p * TB * TB;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int c = 16 * w + kk;
-      di[i + TB * c] = (i < h && c < h) ? x[kk] : (T)0;
+      di[i + TB * c] = (i < h && c < h) ? Xs[c][i] : (T)0;
     }
     return;
   }
