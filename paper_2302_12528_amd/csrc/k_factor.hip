@@ -107,7 +107,20 @@ __global__ void __launch_bounds__(NT) assemble_kernel(FactorDev D, int64_t item_
     const int nbc = D.nr[c] - D.nc[c];
     const T* uc = upd + D.upd_off[c] + (int64_t)jt * nbc;
     const int32_t* rel = D.relpos + D.row_off[c] + D.nc[c];
-    for (int ic = jt + lane; ic < nbc; ic += NT) colbuf[rel[ic]] += uc[ic];
+    // four entries per thread in flight before their scatter (the child's rows map to distinct rows)
+    for (int ic0 = jt; ic0 < nbc; ic0 += 4 * NT) {
+      int ri[4];
+      T uv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ic = ic0 + lane + NT * u;
+        ri[u] = (ic < nbc) ? rel[ic] : -1;
+        uv[u] = (ic < nbc) ? uc[ic] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (ri[u] >= 0) colbuf[ri[u]] += uv[u];
+    }
     __syncthreads();
   }
   for (int r = rlo + lane; r < S.nr; r += NT) col[r - rlo] = colbuf[r];
@@ -697,17 +710,43 @@ __global__ void __launch_bounds__(256) invprep_kernel(FactorDev D, int64_t task_
   T* col = panel + S.panel + (int64_t)t * panel_ld(S.nr);
   T* lc = lcopy + D.lcopy_off[s];
   T* l21 = lc + 2 * (int64_t)S.nc * S.nc;
-  for (int r = lane; r < S.nr; r += 64) {
-    if (r < S.nc) {
-      if (r >= t) lc[(int64_t)t * S.nc + r] = col[r];
-    } else {
-      l21[(int64_t)t * S.nb + (r - S.nc)] = col[r];
+  // eight rows per lane in flight: the loads of a group are issued before its stores (which could
+  // otherwise not pass them, as the compiler cannot tell the buffers apart)
+  constexpr int G = 8;
+  for (int r0 = 0; r0 < S.nr; r0 += 64 * G) {
+    T v[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int r = r0 + lane + 64 * u;
+      v[u] = (r < S.nr) ? col[r] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int r = r0 + lane + 64 * u;
+      if (r >= S.nr) break;
+      if (r < S.nc) {
+        if (r >= t) lc[(int64_t)t * S.nc + r] = v[u];
+      } else {
+        l21[(int64_t)t * S.nb + (r - S.nc)] = v[u];
+      }
     }
   }
   __threadfence_block();
   const int qt = t / TB;
   const T* di = dinv + D.dinv_off[s] + (int64_t)qt * TB * TB + (int64_t)(t - qt * TB) * TB;   // column of inv(L_qq)
-  for (int r = lane; r < S.nc; r += 64) col[r] = (r / TB == qt) ? di[r - qt * TB] : (T)0;
+  for (int r0 = 0; r0 < S.nc; r0 += 64 * G) {
+    T v[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int r = r0 + lane + 64 * u;
+      v[u] = (r < S.nc && r / TB == qt) ? di[r - qt * TB] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int r = r0 + lane + 64 * u;
+      if (r < S.nc) col[r] = v[u];
+    }
+  }
 }
 
 // One 64 x 64 output tile of the inverse phase, C = alpha sum_k A(:, k) B(k, :) over the task's
