@@ -111,7 +111,7 @@ typedef struct {
 
 /* Optional tuning of setup (pass NULL for defaults). */
 typedef struct {
-  int32_t leaf_size;         /* nested-dissection leaf volume (default 64) */
+  int32_t leaf_size;         /* nested-dissection leaf volume; 0 (default) = 256 for a 3D grid hint, 64 otherwise */
   int32_t stop_rule;         /* lobpcg_stop_rule (default LOBPCG_STOP_PAPER) */
   int32_t qr_lower;          /* 1 = Algorithm 2 step 1 in FP32 (default), 0 = in FP64 */
   int32_t flags;             /* bit field of LOBPCG_FLAG_* (default 0) */

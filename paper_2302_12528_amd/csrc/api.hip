@@ -649,12 +649,12 @@ lobpcg_status setup_core(const lobpcg_matrix* mats, int32_t count, int32_t k, in
   if (factor_precision != LOBPCG_FP32 && factor_precision != LOBPCG_FP64)
     return fail(LOBPCG_ERR_INVALID_ARG, "factor_precision must be LOBPCG_FP32 or LOBPCG_FP64");
   lobpcg_options opt{};
-  opt.leaf_size = 64;
+  opt.leaf_size = 0;
   opt.stop_rule = LOBPCG_STOP_PAPER;
   opt.qr_lower = 1;
   if (opts) {
     opt = *opts;
-    if (opt.leaf_size <= 0) opt.leaf_size = 64;
+    if (opt.leaf_size < 0) opt.leaf_size = 0;
     if (opt.stop_rule != LOBPCG_STOP_PAPER && opt.stop_rule != LOBPCG_STOP_NORMA)
       return fail(LOBPCG_ERR_INVALID_ARG, "stop_rule");
     if (opt.norm_a < 0 || !std::isfinite(opt.norm_a)) return fail(LOBPCG_ERR_INVALID_ARG, "norm_a");
@@ -2206,7 +2206,7 @@ lobpcg_status lobpcg_symbolic(const lobpcg_matrix* A, int32_t leaf_size, int32_t
   Symbolic S;
   const bool dense = (A->format == 1);
   std::string err = analyze(A->n, dense ? nullptr : A->rowptr, dense ? nullptr : A->colind, A->grid, dense,
-                            leaf_size > 0 ? leaf_size : 64, S);
+                            leaf_size, S);
   if (!err.empty()) return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
   {
     FactorPlan F;
@@ -2244,7 +2244,7 @@ lobpcg_status lobpcg_exact_fill(const lobpcg_matrix* A, int32_t leaf_size, doubl
     return LOBPCG_OK;
   }
   Symbolic S;
-  std::string err = analyze(A->n, A->rowptr, A->colind, A->grid, false, leaf_size > 0 ? leaf_size : 64, S);
+  std::string err = analyze(A->n, A->rowptr, A->colind, A->grid, false, leaf_size, S);
   if (!err.empty()) return fail(LOBPCG_ERR_INVALID_ARG, "symbolic analysis: " + err);
   std::vector<int32_t> prow, pcol, vmap;
   permute_pattern(S, A->rowptr, A->colind, prow, pcol, vmap);

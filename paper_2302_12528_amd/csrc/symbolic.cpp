@@ -152,12 +152,11 @@ std::string analyze(int64_t n, const int32_t* rowptr, const int32_t* colind, con
 std::string analyze_multi(int64_t n, const int32_t* rowptr, const int32_t* colind, const std::vector<Component>& comps,
                           bool dense, int leaf_size, Symbolic& S) {
   if (n <= 0) return "n must be positive";
-  if (leaf_size < 1) leaf_size = 64;
   Builder B;
   B.n = n;
   B.rowptr = rowptr;
   B.colind = colind;
-  B.leaf = leaf_size;
+  B.leaf = leaf_size >= 1 ? leaf_size : 64;
   B.perm.assign(n, -1);
   if (dense) {
     if (comps.size() != 1) return "dense matrices are not batched";
@@ -172,6 +171,7 @@ std::string analyze_multi(int64_t n, const int32_t* rowptr, const int32_t* colin
       const bool use_grid = c.grid[0] > 0 && c.grid[1] > 0 && c.grid[2] > 0 &&
                             (int64_t)c.grid[0] * c.grid[1] * c.grid[2] == c.n;
       B.offset = c.off;
+      if (leaf_size < 1) B.leaf = default_leaf(use_grid ? c.grid : nullptr);
       if (use_grid) {
         int g[3] = {c.grid[0], c.grid[1], c.grid[2]};
         B.box(g, {0, 0, 0}, {g[0], g[1], g[2]});

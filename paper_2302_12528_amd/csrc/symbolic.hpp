@@ -52,9 +52,16 @@ struct Symbolic {
   int nb(int s) const { return nr[s] - nc[s]; }
 };
 
+// Leaf volume of the nested dissection when the caller leaves it open (leaf_size < 1): 256 for a 3D
+// grid (every dimension above 1), where a deeper tree costs more supernodal levels, and so more
+// dependent launches per triangular solve, than the extra fill of larger leaves; 64 otherwise.
+inline int default_leaf(const int32_t* grid) {
+  return (grid && grid[0] > 1 && grid[1] > 1 && grid[2] > 1) ? 256 : 64;
+}
+
 // Build the ordering and supernode partition.  grid: structured-grid hint
-// (all > 0) or zeros; dense = true gives one supernode with natural order.
-// Returns an empty string on success, else a message.
+// (all > 0) or zeros; dense = true gives one supernode with natural order; leaf_size < 1: default_leaf
+// per component.  Returns an empty string on success, else a message.
 std::string analyze(int64_t n, const int32_t* rowptr, const int32_t* colind, const int32_t grid[3],
                     bool dense, int leaf_size, Symbolic& out);
 

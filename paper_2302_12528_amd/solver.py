@@ -99,7 +99,7 @@ def make_matrix(A, grid=(0, 0, 0)):
     return M, (rp, ci, va)
 
 
-def symbolic(A, grid=(0, 0, 0), leaf_size=64):
+def symbolic(A, grid=(0, 0, 0), leaf_size=0):
     """Host-only ordering and supernode statistics (no GPU)."""
     lib = nv.load()
     M, keep = make_matrix(A, grid)
@@ -112,7 +112,7 @@ def symbolic(A, grid=(0, 0, 0), leaf_size=64):
     return perm, dict(zip(keys, stats.tolist()))
 
 
-def exact_fill(A, grid=(0, 0, 0), leaf_size=64):
+def exact_fill(A, grid=(0, 0, 0), leaf_size=0):
     """Entries of the exact Cholesky factor for the ordering setup builds (host only, no GPU)."""
     lib = nv.load()
     M, keep = make_matrix(A, grid)
@@ -126,7 +126,7 @@ class Solver:
     """k smallest eigenpairs of an SPD matrix with the mixed-precision LOBPCG of Algorithm 3."""
 
     def __init__(self, A, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
-                 grid=(0, 0, 0), leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
+                 grid=(0, 0, 0), leaf_size: int = 0, stop: str = "paper", qr_lower: bool = True,
                  norm_a: float = 0.0, eig_tol: float = 0.0, graph: bool = False, autotune: bool = False,
                  subtree_levels: int = 0, schur_wide_tiles: int = 0, stage1_tol: float = 0.0,
                  force_fp64_redo: bool = False, allocator: str = "torch"):
@@ -271,7 +271,7 @@ class BatchedSolver:
     block-diagonal union, per-problem convergence)."""
 
     def __init__(self, mats, k: int, m: int, tol: float = 1e-10, factor_precision: str = "fp32",
-                 grids=None, leaf_size: int = 64, stop: str = "paper", qr_lower: bool = True,
+                 grids=None, leaf_size: int = 0, stop: str = "paper", qr_lower: bool = True,
                  eig_tol: float = 0.0, graph: bool = False, autotune: bool = False, stage1_tol: float = 0.0,
                  allocator: str = "torch"):
         self.lib = nv.load()

@@ -153,12 +153,21 @@ def test_symbolic_dense(lib):
 
 def test_symbolic_64cube_plan_size(lib):
     A = synth.cfg2(N=64).A
-    perm, st = sv.symbolic(A, grid=(64, 64, 64))
-    # exact geometric nested-dissection fill is 1.567e8; the relaxed supernodes stay within 15 % of it
+    perm, st = sv.symbolic(A, grid=(64, 64, 64), leaf_size=64)
+    # exact geometric nested-dissection fill with 64-node leaves is 1.567e8; the relaxed supernodes stay
+    # within 15 % of it
     assert 1.5e8 < st["nnz_factor"] < 1.8e8
-    exact = sv.exact_fill(A, grid=(64, 64, 64))
+    exact = sv.exact_fill(A, grid=(64, 64, 64), leaf_size=64)
     assert 1.5e8 < exact < st["nnz_factor"]
-    assert st["levels"] <= 16
+    assert st["levels"] == 13
+    # the default for a 3D grid: 256-node leaves, two levels fewer for about 11 % more stored entries
+    perm2, st2 = sv.symbolic(A, grid=(64, 64, 64))
+    assert st2["levels"] == 11 and st["nnz_factor"] < st2["nnz_factor"] < 1.15 * st["nnz_factor"]
+    assert abs(st2["flops"] / st["flops"] - 1.0) < 0.03
+    assert sorted(perm2.tolist()) == list(range(64 ** 3))
+    # a 2D grid keeps 64-node leaves
+    B = synth.laplace2d_rect(40, 50)
+    assert np.array_equal(sv.symbolic(B, grid=(40, 50, 1))[0], sv.symbolic(B, grid=(40, 50, 1), leaf_size=64)[0])
 
 
 def test_mixed_qr_noalloc_rejects_oversized_problems_before_gpu_work(lib):
