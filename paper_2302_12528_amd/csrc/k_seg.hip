@@ -123,19 +123,21 @@ __global__ void __launch_bounds__(256) sreduce_kernel(SegDev S, const double* __
 
 // ---------------------------------------------------------------------------
 // Block update on one 64-row tile: Y = alpha X M_b + beta Y (64 x 64 output tile) in the blocks'
-// precision TX (M is FP64 and rounded to TX).  X (64 rows x 16 reduction columns) and M (16 x 64) are
-// staged through LDS with coalesced loads; wave w accumulates output rows 16 w .. 16 w + 15 over all
-// four 16-column blocks with 16x16x4 MFMAs in TX.
+// precision TX (M is FP64 and rounded to TX).  X (64 rows x 32 reduction columns) and M (32 x 64) are
+// staged through LDS, the next 32 columns loaded into registers (8 consecutive elements per thread,
+// 16-byte loads when the rows allow) while the current ones are multiplied; wave w accumulates output
+// rows 16 w .. 16 w + 15 over all four 16-column blocks with 16x16x4 MFMAs in TX.
 // ---------------------------------------------------------------------------
+constexpr int kUpdK = 32;
 template <typename TX>
 __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const TX* X, int64_t ldx,
                                                            const double* __restrict__ M, int64_t ldm, int64_t mstride,
                                                            TX* Y, int64_t ldy, int K, int cols, double alpha,
-                                                           double beta) {
+                                                           double beta, bool vec) {
   typedef Mfma<TX> MF;
   typedef typename MF::v4 V4;
-  __shared__ TX As[16][65];   // As[k][row]
-  __shared__ TX Bs[16][65];   // Bs[k][col]
+  __shared__ TX As[kUpdK][65];   // As[k][row]
+  __shared__ TX Bs[kUpdK][65];   // Bs[k][col]
   const int q = blockIdx.x;
   const int b = S.tile_inst[q];
   if (!S.active[b]) return;
@@ -149,26 +151,51 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const TX* X
   V4 acc[4];
 #pragma unroll
   for (int cb = 0; cb < 4; ++cb) acc[cb] = V4{0, 0, 0, 0};
-  const int lr = t / 4, lk = (t % 4) * 4;   // X loader: row lr, reduction columns lk .. lk + 3
-  const int bk = t / 16, bc = (t % 16) * 4; // M loader: reduction row bk, columns bc .. bc + 3
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    TX xa[4], mb[4];
+  const int lr = t / 4, lk = (t % 4) * 8;   // X loader: row lr, reduction columns lk .. lk + 7
+  const int bk = t / 8, bc = (t % 8) * 8;   // M loader: reduction row bk, columns bc .. bc + 7
+  const TX* xrow = X + (r0 + lr) * ldx;
+  const bool rok = lr < rows;
+  TX xa[8], mb[8];
+  auto load = [&](int k0) {
+    const int kx = k0 + lk;
+    if (vec && rok && kx + 8 <= K) {
+      if constexpr (sizeof(TX) == 8) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = k0 + lk + u;
-      xa[u] = (lr < rows && k < K) ? X[(r0 + lr) * ldx + k] : (TX)0;
-      const int kb = k0 + bk, cc = c0 + bc + u;
+        for (int u = 0; u < 4; ++u) {
+          const f64x2_t v = *reinterpret_cast<const f64x2_t*>(xrow + kx + 2 * u);
+          xa[2 * u] = v.x;
+          xa[2 * u + 1] = v.y;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const f32x4_t v = *reinterpret_cast<const f32x4_t*>(xrow + kx + 4 * u);
+          xa[4 * u] = v.x; xa[4 * u + 1] = v.y; xa[4 * u + 2] = v.z; xa[4 * u + 3] = v.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xa[u] = (rok && kx + u < K) ? xrow[kx + u] : (TX)0;
+    }
+    const int kb = k0 + bk;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int cc = c0 + bc + u;
       mb[u] = (kb < K && cc < cols) ? (TX)Mb[(int64_t)kb * ldm + cc] : (TX)0;
     }
-    __syncthreads();
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += kUpdK) {
+    __syncthreads();   // the previous chunk's products are done with As, Bs
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 8; ++u) {
       As[lk + u][lr] = xa[u];
       Bs[bk][bc + u] = mb[u];
     }
     __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
+    if (k0 + kUpdK < K) load(k0 + kUpdK);
+    const int kc = min(kUpdK, K - k0);   // columns past it are zero in both operands
+    for (int kk = 0; kk < kc; kk += 4) {
       const TX av = As[kk + g][16 * w + i];
 #pragma unroll
       for (int cb = 0; cb < 4; ++cb) acc[cb] = MF::op(av, Bs[kk + g][16 * cb + i], acc[cb]);
@@ -765,7 +792,8 @@ void launch_supdate(const SegDev& S, const TX* X, int64_t ldx, const double* M, 
                     TX* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st) {
   if (cout <= 0 || S.ntiles <= 0) return;
   dim3 g((unsigned)S.ntiles, cdiv(cout, 64));
-  supdate_kernel<TX><<<g, kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin, cout, alpha, beta);
+  const bool vec = ((reinterpret_cast<uintptr_t>(X) | (uintptr_t)(ldx * sizeof(TX))) & 15) == 0;
+  supdate_kernel<TX><<<g, kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin, cout, alpha, beta, vec);
 }
 template void launch_supdate<double>(const SegDev&, const double*, int64_t, const double*, int64_t, int64_t, double*,
                                      int64_t, int, int, double, double, hipStream_t);
