@@ -499,9 +499,10 @@ lobpcg_status factor_t(lobpcg_ctx c) {
   // stream keeps the levels in order), and only L21 inv(L11) overwrites rows that the Schur
   // complement reads, so that step waits for it.
   // Panel steps with one step of lookahead (FP32 factors): the update of the columns beyond p + 1
-  // by panel p shares one launch with the factorization of panel p + 1, which reads and writes
-  // column p + 1 only.  (An FP64 workgroup of that launch would hold the LDS of the factorization
-  // kernel, one workgroup per CU, so FP64 factors keep one update launch per panel step.)
+  // by panel p shares one launch with the factorization of panel p + 1, which applies panel p to
+  // column p + 1 itself and reads and writes that column only.  (An FP64 workgroup of that launch
+  // would hold the LDS of the factorization kernel, one workgroup per CU, so FP64 factors keep one
+  // update launch per panel step.)
   int e = 0;
   HIP_TRY(hipEventRecord(c->fev[e], ms));
   HIP_TRY(hipStreamWaitEvent(ss, c->fev[e++], 0));
@@ -514,21 +515,12 @@ lobpcg_status factor_t(lobpcg_ctx c) {
       const int kind = steps[q].kind;
       if (is_inv(kind) || kind == kSchur || kind == kSchur2) continue;
       if constexpr (sizeof(T) == 4) {
-        if (kind == kUpdateRest && q + 1 < j && steps[q + 1].kind == kPotrf) {
+        if (kind == kUpdate && q + 1 < j && steps[q + 1].kind == kPotrf) {
           launch_potrf_update(c->FD, steps[q + 1].off, steps[q + 1].count, steps[q].off, steps[q].count, panel, upd,
                               dinv, c->d_flag, ms);
           ++q;
           continue;
         }
-      }
-      if (sizeof(T) == 8 && kind == kUpdate && q + 1 < j && steps[q + 1].kind == kUpdateRest &&
-          steps[q + 1].off == steps[q].off + steps[q].count) {
-        // without the lookahead, both parts of the update in one launch (their tasks are adjacent)
-        FactorPlan::Step both = steps[q];
-        both.count += steps[q + 1].count;
-        launch(both, ms);
-        ++q;
-        continue;
       }
       launch(steps[q], ms);
     }

@@ -3,8 +3,19 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace lobpcg {
+
+// f(std::integral_constant<int, A>), ..., f(std::integral_constant<int, B - 1>), so that f may index
+// register arrays with its argument.
+template <int A, int B, typename F>
+__device__ __attribute__((always_inline)) void static_for(F&& f) {
+  if constexpr (A < B) {
+    f(std::integral_constant<int, A>{});
+    static_for<A + 1, B>(f);
+  }
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2): block b runs on XCD
 // b % 8.  xcd_block(b, G) renumbers the G blocks so that each XCD receives a contiguous range of

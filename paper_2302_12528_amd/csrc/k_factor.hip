@@ -228,11 +228,12 @@ __device__ inline void load_cm_vec(T (*As)[TB + 1], const T* M, int64_t ld, int 
   chunk_store(c, As);
 }
 
-// Task (s, I, p) of a panel step: the Cholesky factor L_pp of diagonal tile (p, p) and its inverse
-// are formed in the workgroup (every task of the step repeats this small computation, so the step
-// needs one launch); the task with I == p writes L_pp and inv(L_pp), every other task replaces its
-// tile (I, p) by C inv(L_pp)^T.  Rows and columns of the tile at or beyond h are padded with the
-// identity.
+// Task (s, I, p) of a panel step: first the update of tile (I, p) and of the diagonal tile (p, p) by
+// panel p - 1 (the trailing update of the previous step leaves column p to this step), then the
+// Cholesky factor L_pp of the diagonal tile and its inverse are formed in the workgroup (every task of
+// the step repeats this small computation, so the step needs one launch); the task with I == p writes
+// L_pp and inv(L_pp), every other task replaces its tile (I, p) by C inv(L_pp)^T.  Rows and columns of
+// the tile at or beyond h are padded with the identity.
 //   factorization: thread (row i, quarter w) holds row i, columns 16 w .. 16 w + 15 in registers,
 //     so wave w holds 16 whole columns.  Quarter by quarter, the owning wave factors its 16 columns
 //     alone (L[c][j] of another row c is a readlane) and publishes them through LDS; after one
@@ -279,6 +280,61 @@ __device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& 
   for (int kk = 0; kk < 16; ++kk) {
     const int c = 16 * w + kk;
     a[kk] = (i < h && c < h) ? tile[i + (int64_t)c * ld] : (i == c ? (T)1 : (T)0);
+  }
+  if (p > 0) {
+    // Column p still lacks panel p - 1's contribution (the step's own part of the trailing update):
+    // C(I, p) -= L(I, p - 1) L(p, p - 1)^T and the diagonal tile's D -= L(p, p - 1) L(p, p - 1)^T (every
+    // task forms the latter, as it forms the factorization), on the matrix cores with K-major operands
+    // in Ls and Xs; the products go through LDS into the layouts of a[] and cv[].
+    int rQ, wQ;
+    tile_rows(S, p - 1, rQ, wQ);
+    int64_t lda, ldb;
+    const T* Ap = front_ptr(panel, upd, S, rI, rQ, lda);
+    const T* Bp = front_ptr(panel, upd, S, r0, rQ, ldb);
+    if (I != p) load_cm_vec(Ls, Ap, lda, hI, wQ);
+    load_cm_vec(Xs, Bp, ldb, h, wQ);
+    __syncthreads();
+    // one product at a time, so that only one set of accumulators is live: tile I's into Ls (after
+    // every wave has read its operand there), then the diagonal tile's into Xs
+    const int lane = tid % 64, qr = (w / 2) * 32, qc = (w % 2) * 32;
+    typename Mfma<T>::v4 acc[2][2];
+    auto to_lds = [&](T (*M)[TB + 1]) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) M[qr + 16 * a2 + lane % 16][qc + 16 * b + Mfma<T>::drow(lane, q)] = acc[b][a2][q];
+    };
+    auto zero = [&]() {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[b][a2][q] = 0;
+    };
+    if (I != p) {
+      zero();
+      tile_mfma<T>(Ls, Xs, (wQ + 3) & ~3, acc);
+      __syncthreads();
+      to_lds(Ls);
+    }
+    zero();
+    tile_mfma<T>(Xs, Xs, (wQ + 3) & ~3, acc);
+    __syncthreads();
+    to_lds(Xs);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) a[kk] -= Xs[i][16 * w + kk];
+    if (I != p) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = tid + 256 * q;
+        cv[q] -= Ls[e % TB][e / TB];
+      }
+    }
+    __syncthreads();
   }
   // X starts as zero: its blocks above the diagonal stay so
 #pragma unroll
@@ -503,10 +559,11 @@ __global__ void __launch_bounds__(256) update_kernel(FactorDev D, int64_t task_o
   update_body<T>(D, D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x)), panel, upd, dinv, lds);
 }
 
-// The update of panel p's columns beyond p + 1 (blocks npotrf ..) together with the factorization of
-// panel p + 1 (blocks 0 .. npotrf - 1) in one launch: they read and write disjoint tiles (column p,
-// which both read, is final), so the second may start before the first has finished without a
-// second stream and its synchronization.
+// The update of panel p's columns beyond p + 1 and the move of L_pp into the panel (blocks npotrf ..)
+// together with the factorization of panel p + 1, which applies panel p to column p + 1 itself (blocks
+// 0 .. npotrf - 1), in one launch: they read and write disjoint tiles (column p, which both read, is
+// final), so the second may start before the first has finished without a second stream and its
+// synchronization.
 template <typename T>
 __global__ void __launch_bounds__(256) potrf_update_kernel(FactorDev D, int64_t potrf_off, int npotrf,
                                                            int64_t upd_off, int nupd, T* panel, T* upd, T* dinv,
@@ -866,7 +923,6 @@ void launch_factor_step(const FactorDev& D, int kind, int level_max_nr, int64_t 
       break;
 
     case kUpdate:
-    case kUpdateRest:
       update_kernel<T><<<count, 256, 0, st>>>(D, task_off, panel, upd, dinv);
       break;
     case kSchur:

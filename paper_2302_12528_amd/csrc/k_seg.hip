@@ -489,19 +489,23 @@ __global__ void __launch_bounds__(NR) stsqr_kernel(SegDev S, const Tin* in, int6
     for (int k = 0; k < c; ++k) R[(int64_t)t * c + k] = (k >= t && t < rows) ? A[k * LP + t] : (T)0;
 }
 
-// Sum over the 64 lanes of a wave of each of the CP values q[0..CP) (CP = 8, 16 or 32), returned
-// in out[] as wave-uniform values.  Recursive halving: at each exchange a lane keeps half of its
-// vector and adds the partner lane's copy of that half (CP - 1 shuffles), the lane bits left over
-// are summed directly, and value k then sits in lane k << (6 - log2 CP).
-template <int CP>
-__device__ inline void wave_allreduce(float (&q)[CP], float (&out)[CP]) {
-  constexpr int LOG = (CP == 32) ? 5 : (CP == 16) ? 4 : 3;
-  static_assert((1 << LOG) == CP, "CP must be 8, 16 or 32");
+// Sum over the 64 lanes of a wave of each of the N values q[0..N) (N <= 32), returned in out[] as
+// wave-uniform values.  With P = 2^LOG >= N (the values padded with zeros), recursive halving: at each
+// exchange a lane keeps half of its vector and adds the partner lane's copy of that half (P - 1
+// shuffles), the lane bits left over are summed directly, and value k then sits in lane k << (6 - LOG).
+template <int N>
+__device__ inline void wave_allreduce(const float (&qin)[N], float (&out)[N]) {
+  constexpr int LOG = (N <= 1) ? 0 : (N <= 2) ? 1 : (N <= 4) ? 2 : (N <= 8) ? 3 : (N <= 16) ? 4 : 5;
+  constexpr int P = 1 << LOG;
+  static_assert(N <= 32, "at most 32 values");
   const int lane = threadIdx.x % 64;
+  float q[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) q[k] = (k < N) ? qin[k] : 0.f;
 #pragma unroll
   for (int st = 0; st < LOG; ++st) {
     const int m = 32 >> st;
-    const int half = CP >> (st + 1);
+    const int half = P >> (st + 1);
     // lane-dependent choice between q[i] and q[i + half] by bit masks (a select between two array
     // elements would be folded into a lane-dependent array index)
     const uint32_t hm = (lane & m) ? 0xffffffffu : 0u;
@@ -516,7 +520,7 @@ __device__ inline void wave_allreduce(float (&q)[CP], float (&out)[CP]) {
 #pragma unroll
   for (int m = 32 >> LOG; m >= 1; m >>= 1) q[0] += __shfl_xor(q[0], m, 64);
 #pragma unroll
-  for (int k = 0; k < CP; ++k)
+  for (int k = 0; k < N; ++k)
     out[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, q[0]), k << (6 - LOG)));
 }
 
@@ -532,16 +536,16 @@ __device__ inline double lane_f64(double v, int l) {
 }
 
 // TSQR block in FP32 by one wave, four blocks per workgroup, no barriers: lane l holds rows l, l + 64,
-// ..., l + 64 (RPL - 1) of the block (at most 64 RPL rows) in registers.  Column j is always register column 0: after each
-// Householder step the remaining columns move one register to the left.  For column j the wave
-// all-reduce gives sigma = sum_{r > j} a_rj^2 and S_k = sum_{r > j} a_rj a_rk together; with
-// v = e_j + scale a(j+1:, j), w_k = a_jk + scale S_k and every row is updated in place.  Row j of R
-// is staged in LDS as it is produced.
+// ..., l + 64 (RPL - 1) of the block (at most 64 RPL rows) in registers.  The column loop is unrolled,
+// so step j touches only columns j .. CP - 1.  For column j the wave all-reduce gives
+// sigma = sum_{r > j} a_rj^2 and S_k = sum_{r > j} a_rj a_rk together; with v = e_j + scale a(j+1:, j),
+// w_k = a_jk + scale S_k and every row is updated in place.  Row j is final after step j (later
+// reflectors leave rows above their own untouched), so lane j ends up holding row j of R (its
+// diagonal kept aside as beta_j).
 template <typename Tin, int CP, int RPL = 4>
 __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in, int64_t ldin,
                                                          const int32_t* __restrict__ items, int64_t nitems, int c,
                                                          float* out) {
-  __shared__ float Rs[4][CP][CP + 1];
   const int lane = threadIdx.x % 64, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
   const int64_t item = (int64_t)blockIdx.x * 4 + wv;
   if (item >= nitems) return;   // whole wave
@@ -558,57 +562,50 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
 #pragma unroll
     for (int k = 0; k < CP; ++k) a[s][k] = (r < rows && k < c) ? (float)in[(r0 + r) * ldin + k] : 0.f;
   }
-  float (*R)[CP + 1] = Rs[wv];
-  for (int e = lane; e < CP * (CP + 1); e += 64) (&R[0][0])[e] = 0.f;
   const int kmax = (c < rows) ? c : rows;
-  for (int j = 0; j < kmax; ++j) {
-    float q[CP];
+  float rjj = 0.f;
+  static_for<0, CP>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    constexpr int N = CP - j;   // columns j .. CP - 1
+    if (j >= kmax) return;      // uniform
+    float q[N];
 #pragma unroll
-    for (int k = 0; k < CP; ++k) q[k] = 0.f;
+    for (int k = 0; k < N; ++k) q[k] = 0.f;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
-      const float x = (64 * s + lane > j) ? a[s][0] : 0.f;
+      const float x = (64 * s + lane > j) ? a[s][j] : 0.f;
 #pragma unroll
-      for (int k = 0; k < CP; ++k) q[k] += x * a[s][k];
+      for (int k = 0; k < N; ++k) q[k] += x * a[s][j + k];
     }
-    float qs[CP];
-    wave_allreduce<CP>(q, qs);
+    float qs[N];
+    wave_allreduce<N>(q, qs);
     const float sigma = qs[0];
-    const float alpha = lane_value(a[0][0], j);
+    const float alpha = lane_value(a[0][j], j);
     float beta = alpha;
     if (sigma > 0.f) {   // otherwise nothing below the diagonal: H_j = I (uniform)
       const float xn = sqrtf(alpha * alpha + sigma);
       beta = (alpha >= 0.f) ? -xn : xn;
       const float tau = (beta - alpha) / beta;
       const float scale = 1.f / (alpha - beta);
-      float w[CP];
+      float w[N];
 #pragma unroll
-      for (int k = 1; k < CP; ++k) w[k] = lane_value(a[0][k], j) + scale * qs[k];
+      for (int k = 1; k < N; ++k) w[k] = lane_value(a[0][j + k], j) + scale * qs[k];
 #pragma unroll
       for (int s = 0; s < RPL; ++s) {
         const int r = 64 * s + lane;
-        const float coef = (r > j) ? tau * scale * a[s][0] : ((r == j) ? tau : 0.f);
+        const float coef = (r > j) ? tau * scale * a[s][j] : ((r == j) ? tau : 0.f);
 #pragma unroll
-        for (int k = 1; k < CP; ++k) a[s][k] -= coef * w[k];
+        for (int k = 1; k < N; ++k) a[s][j + k] -= coef * w[k];
       }
     }
-    if (lane == j) {
-      R[j][j] = beta;
+    if (lane == j) rjj = beta;
+  });
+  // lane l < c writes row l of R (zero below row kmax)
+  if (lane < c) {
+    float* Ro = out + (int64_t)slot * c * c + (int64_t)lane * c;
 #pragma unroll
-      for (int k = 1; k < CP; ++k)
-        if (j + k < CP) R[j][j + k] = a[0][k];
-    }
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-#pragma unroll
-      for (int k = 0; k + 1 < CP; ++k) a[s][k] = a[s][k + 1];
-      a[s][CP - 1] = 0.f;
-    }
-  }
-  float* Ro = out + (int64_t)slot * c * c;
-  for (int e = lane; e < c * c; e += 64) {
-    const int rr = e / c, cc = e % c;
-    Ro[e] = (cc >= rr) ? R[rr][cc] : 0.f;
+    for (int k = 0; k < CP; ++k)
+      if (k < c) Ro[k] = (lane >= kmax || k < lane) ? 0.f : (k == lane ? rjj : a[0][k]);
   }
 }
 

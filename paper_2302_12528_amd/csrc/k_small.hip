@@ -935,16 +935,6 @@ __global__ void __launch_bounds__(kSyevThreads) syev_bisect_kernel(double* __res
 // from it, and only then updates its other rows, so that the next step's first barrier does not wait
 // for a whole update followed by the owner's norms and divisions.  M is H or Q by group; QG: this thread
 // is in the Q group (wave-uniform).
-//
-// f(std::integral_constant<int, A>), ..., f(std::integral_constant<int, B - 1>), so that f may index register
-// arrays with its argument.
-template <int A, int B, typename F>
-__device__ __attribute__((always_inline)) void static_for(F&& f) {
-  if constexpr (A < B) {
-    f(std::integral_constant<int, A>{});
-    static_for<A + 1, B>(f);
-  }
-}
 
 // Owner phase: v and t of the reflector of row kk (in the static 16-row block AO) from that row's
 // entries, published in buffer kk & 1, with d[kk] and e[kk].

@@ -453,8 +453,9 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P, int schur_wide_tiles) {
     push(l, 0, 0, 0);   // one marker task: the assembly kernel reads asm_items of level l
     end_step();
     for (int p = 0; p < maxnp; ++p) {
-      // diagonal tile p and the tiles below it in one step: task (s, p, p, p) writes L_pp and its
-      // inverse, tasks (s, I > p, p, p) the trsm of tile (I, p)
+      // diagonal tile p and the tiles below it in one step: every task first applies panel p - 1 to
+      // its tile; task (s, p, p, p) writes L_pp and its inverse, tasks (s, I > p, p, p) the trsm of
+      // tile (I, p)
       begin_step(kPotrf);
       for (int32_t q = q0; q < q1; ++q) {
         int s = S.level_sn[q];
@@ -463,25 +464,15 @@ void build_factor_plan(const Symbolic& S, FactorPlan& P, int schur_wide_tiles) {
           for (int I = p; I < rt; ++I) push(s, I, p, p);
       }
       end_step();
-      // trailing update of the panel columns; task (s, p, p, p) moves L_pp from its staging slot
-      // into the panel (the panel step's other tasks read the unfactored tile (p, p) while it is
-      // formed).  Column p + 1 is a step of its own so that the next panel step can start after it
-      // while the columns beyond are updated (one step of lookahead).
+      // trailing update of the panel columns beyond p + 1 (column p + 1 is updated by the next panel
+      // step's own tasks, so that step needs no launch of its own before it: one step of lookahead);
+      // task (s, p, p, p) moves L_pp from its staging slot into the panel (the panel step's other
+      // tasks read the unfactored tile (p, p) while it is formed)
       begin_step(kUpdate);
       for (int32_t q = q0; q < q1; ++q) {
         int s = S.level_sn[q];
         int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
-        if (np > p) {
-          push(s, p, p, p);
-          if (p + 1 < np)
-            for (int I = p + 1; I < rt; ++I) push(s, I, p + 1, p);
-        }
-      }
-      end_step();
-      begin_step(kUpdateRest);
-      for (int32_t q = q0; q < q1; ++q) {
-        int s = S.level_sn[q];
-        int np = ntiles(S.nc[s]), rt = np + ntiles(S.nr[s] - S.nc[s]);
+        if (np > p) push(s, p, p, p);
         for (int J = p + 2; J < np; ++J)
           for (int I = J; I < rt; ++I) push(s, I, J, p);
       }
@@ -900,8 +891,8 @@ std::string verify(const Symbolic& S, const FactorPlan& F, const SolvePlan& P, c
       if (st.kind == kSchur && !(J >= np && I >= J)) return "Schur tile order";
       if (st.kind == kSchur2 && !(J >= np && I >= J && (I - np) % 2 == 0 && (J - np) % 2 == 0 && rt - np >= F.schur_wide_tiles))
         return "Schur block order";
-      if (st.kind == kUpdate && !((J == p + 1 && J < np && I >= J) || (I == p && J == p))) return "update tile order";
-      if (st.kind == kUpdateRest && !(J > p + 1 && J < np && I >= J)) return "update tile order";
+      if (st.kind == kUpdate && !((J > p + 1 && J < np && I >= J) || (I == p && J == p))) return "update tile order";
+      if (st.kind == kUpdateRest) return "update step kind";
       if ((st.kind == kPotrf || st.kind == kTrsm || st.kind == kInvScale) && !(J == p && I >= p))
         return "trsm tile order";
       if (st.kind == kInvUpdate && !(J < p && I >= p)) return "inverse update tile order";

@@ -95,10 +95,10 @@ struct FactorPlan {
   std::vector<int32_t> level_max_nr;   // per level: the largest front (rows) of the level
   int schur_wide_tiles = 8;            // fronts with at least this many tile rows below the panel use kSchur2
 };
-// kPotrf: Cholesky of diagonal tile p with the trsm of the tiles below it (kTrsm: the trsm alone);
-// kUpdate: trailing update of the next panel column (p + 1) and the move of L_pp into the panel;
-// kUpdateRest: the trailing update of the panel columns after it (they may run while panel p + 1 is
-// factored); kSchur: U_s -= L21 L21^T after the last panel step.
+// kPotrf: update of column p by panel p - 1, then the Cholesky factor of diagonal tile p with the trsm
+// of the tiles below it (kTrsm: the trsm alone); kUpdate: the move of L_pp into the panel and the
+// trailing update of the panel columns after p + 1 (they may run while panel p + 1 is factored);
+// kUpdateRest: no longer planned; kSchur: U_s -= L21 L21^T after the last panel step.
 // kInvPrep / kInvT1 / kInvX21 / kInvP21: the inverse phase P_s = [inv(L11); L21 inv(L11)] (kInvScale and
 // kInvUpdate: the column sweep it replaces, no longer planned).
 enum StepKind { kAssemble = 0, kPotrf = 1, kTrsm = 2, kUpdate = 3, kInvPrep = 4, kInvScale = 5, kInvUpdate = 6,
