@@ -353,6 +353,11 @@ __device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& 
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
         const int j = 16 * jb + jj;
+        // the column's entries in the rows of the quarter's diagonal block, read before the pivot is
+        // known: l_i l_r = a_ij a_rj / d, so the update needs a_rj, not l_rj
+        T sk[16];
+#pragma unroll
+        for (int kk = jj + 1; kk < 16; ++kk) sk[kk] = rdl(a[jj], 16 * jb + kk);
         T d = rdl(a[jj], j);
         const bool ok = (d > (T)0) && (d < (T)INFINITY);
         if (!ok) {
@@ -369,9 +374,10 @@ __device__ __attribute__((always_inline)) void potrf_trsm_body(const FactorDev& 
         }
         if (i == j) rrow = rinv;
         const T li = a[jj] * rinv;
+        const T t = li * rinv;   // a_ij / d
         a[jj] = (i > j) ? li : (i == j ? ljj : (T)0);
 #pragma unroll
-        for (int kk = jj + 1; kk < 16; ++kk) a[kk] -= li * rdl(a[jj], 16 * jb + kk);
+        for (int kk = jj + 1; kk < 16; ++kk) a[kk] -= t * sk[kk];
       }
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) lb[i][jj] = a[jj];
@@ -639,17 +645,20 @@ __global__ void __launch_bounds__(256) schur_kernel(FactorDev D, int64_t task_of
 
 // Schur complement on 128 x 128 blocks (task (s, I, J): tiles I, I + 1 by J, J + 1 of U_s, I >= J,
 // both counted from np in pairs): wave w takes the 64 x 64 tile (I + w / 2, J + w % 2), skipping the
-// one above the diagonal of a diagonal block and tiles past the front.  The operands are staged 32
-// panel columns at a time for all 128 rows (64 need more registers: fewer waves, slower), so each staged element feeds two tiles: half the operand
-// traffic per product of schur_kernel, for the levels with large fronts.
-constexpr int kSchurK = 32;
+// one above the diagonal of a diagonal block and tiles past the front.  The operands are staged 16
+// panel columns at a time for all 128 rows, in two LDS buffers (the next chunk is written into the
+// other buffer after the current one's products, one barrier per chunk; 32-column chunks in two
+// buffers hold twice the LDS, fewer workgroups per compute unit, and were slower), so each staged
+// element feeds two tiles: half the operand traffic per product of schur_kernel, for the levels with
+// large fronts.
+constexpr int kSchurK = 16;
 template <typename T>
 __global__ void __launch_bounds__(256) schur2_kernel(FactorDev D, int64_t task_off, T* panel, T* upd) {
   constexpr int W2 = 2 * TB;   // 128 rows
   // row padding: the four 16-lane groups of an MFMA operand read fall in different banks
   constexpr int LP = (sizeof(T) == 4) ? W2 + 16 : W2 + 8;
-  __shared__ T As[kSchurK][LP];
-  __shared__ T Bs[kSchurK][LP];
+  __shared__ T As[2][kSchurK][LP];
+  __shared__ T Bs[2][kSchurK][LP];
   const int* tk = D.tasks + 4 * (task_off + xcd_block(blockIdx.x, gridDim.x));
   const int s = tk[0], I = tk[1], J = tk[2];
   const Sn S = sn_of(D, s);
@@ -711,31 +720,40 @@ __global__ void __launch_bounds__(256) schur2_kernel(FactorDev D, int64_t task_o
   T na[NQ][4], nb[NQ][4];
   load(na, Ap, hI, min(kSchurK, S.nc), va);
   load(nb, Bp, hJ, min(kSchurK, S.nc), vb);
+  store(na, As[0]);
+  store(nb, Bs[0]);
+  __syncthreads();
   const int kl = lane / 16, il = lane % 16;
+  int buf = 0;
   for (int k0 = 0; k0 < S.nc; k0 += kSchurK) {
     const int K = min(kSchurK, S.nc - k0);
-    __syncthreads();   // the previous chunk's products are done with As, Bs
-    store(na, As);
-    store(nb, Bs);
-    __syncthreads();
-    if (k0 + kSchurK < S.nc) {
+    const bool more = k0 + kSchurK < S.nc;
+    if (more) {
       const int K2 = min(kSchurK, S.nc - k0 - kSchurK);
       load(na, Ap + (int64_t)(k0 + kSchurK) * ldp, hI, K2, va);
       load(nb, Bp + (int64_t)(k0 + kSchurK) * ldp, hJ, K2, vb);
     }
     if (live) {
-      for (int ks = 0; ks < K; ks += 4) {   // columns past K are zero in both operands
+      const T (*Ac)[LP] = As[buf];
+      const T (*Bc)[LP] = Bs[buf];
+      for (int ks = 0; ks < K; ks += 4) {
         T af[4], bf[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bf[b] = Bs[ks + kl][qc + 16 * b + il];
+        for (int b = 0; b < 4; ++b) bf[b] = Bc[ks + kl][qc + 16 * b + il];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) af[a] = As[ks + kl][qr + 16 * a + il];
+        for (int a = 0; a < 4; ++a) af[a] = Ac[ks + kl][qr + 16 * a + il];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
           for (int a = 0; a < 4; ++a) acc[b][a] = Mfma<T>::op(bf[b], af[a], acc[b][a]);
       }
     }
+    if (more) {
+      store(na, As[buf ^ 1]);
+      store(nb, Bs[buf ^ 1]);
+    }
+    __syncthreads();
+    buf ^= 1;
   }
   if (!live) return;
 #pragma unroll
