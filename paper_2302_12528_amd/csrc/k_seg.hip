@@ -9,6 +9,8 @@
 //   colnorms  ||X_b(:, j)||^2
 //   trsm      Y_b U_b = X_b row by row (Algorithm 2 steps 2 and 4)
 //   tsqr      R factor of each X_b (Algorithm 2 step 1), Householder in T
+#include <algorithm>
+
 #include "common.hpp"
 #include "mfma.hpp"
 #include "bufload.hpp"
@@ -178,10 +180,13 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const TX* X
       for (int u = 0; u < 8; ++u) xa[u] = (rok && kx + u < K) ? xrow[kx + u] : (TX)0;
     }
     const int kb = k0 + bk;
+    // clamped addresses, so that the loads are unconditional (issued together) and masked afterwards
+    const int kbc = min(kb, K - 1);
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int cc = c0 + bc + u;
-      mb[u] = (kb < K && cc < cols) ? (TX)Mb[(int64_t)kb * ldm + cc] : (TX)0;
+      const double v = Mb[(int64_t)kbc * ldm + min(cc, cols - 1)];
+      mb[u] = (kb < K && cc < cols) ? (TX)v : (TX)0;
     }
   };
   load(0);
@@ -212,6 +217,151 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const TX* X
       if (beta != 0.0) v = fma((TX)beta, Y[(r0 + r) * ldy + cc], v);
       Y[(r0 + r) * ldy + cc] = v;
     }
+}
+
+// The same update with M staged once per workgroup, for K <= kUpdMaxK: the 16 NCB-column slice of M_b
+// (rounded to TX) sits in LDS column-major, Ms[c][k], and each workgroup walks 64-row tiles with a grid
+// stride, staging M again only when the instance changes.  Wave w takes tile rows 16 w .. 16 w + 15 with
+// no barriers: for every 16 reduction columns lane (i, g) loads its row's columns 16 kb + 4 g .. + 3 (one
+// 16-byte load in FP32) and uses them as the B operand of four MFMAs whose k-index is that column (the
+// order of the reduction index is free as long as both operands follow it); the A operand is M^T, read
+// as 4 consecutive k from Ms.  D = M^T X^T, so lane (i, g) ends with row i and 4 consecutive columns of
+// each 16-column block (in FP64 the A operand takes the columns in the order ci = 4 (i % 4) + i / 4 to
+// make them consecutive), written as 16-byte vectors.
+constexpr int kUpdMaxK = 96;
+template <typename TX, int NCB>
+__global__ void __launch_bounds__(kThreads) supdate_ms_kernel(SegDev S, const TX* X, int64_t ldx,
+                                                              const double* __restrict__ M, int64_t ldm,
+                                                              int64_t mstride, TX* Y, int64_t ldy, int K, int cols,
+                                                              double alpha, double beta) {
+  typedef Mfma<TX> MF;
+  typedef typename MF::v4 V4;
+  constexpr int LK = kUpdMaxK + 4;   // 16-byte aligned rows; consecutive rows start 4 banks apart
+  constexpr int NKB = kUpdMaxK / 16;
+  constexpr int VW = 16 / sizeof(TX);
+  __shared__ __align__(16) TX Ms[16 * NCB][LK];
+  const int t = threadIdx.x, lane = t % 64, w = t / 64;
+  const int i = lane % 16, g = lane / 16;
+  const int ci = (sizeof(TX) == 8) ? 4 * (i % 4) + i / 4 : i;
+  const int c0 = blockIdx.y * 16 * NCB;
+  const int nkb = (K + 15) / 16;
+  const TX al = (TX)alpha, be = (TX)beta;
+  int cur = -1;
+  for (int64_t q = blockIdx.x; q < S.ntiles; q += gridDim.x) {
+    // tile fields are uniform: in scalar registers, buffer resources need no per-lane loop
+    const int b = __builtin_amdgcn_readfirstlane(S.tile_inst[q]);
+    if (!S.active[b]) continue;   // uniform
+    const int64_t r0t = S.tile_r0[q];
+    const int64_t r0 = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)r0t) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(r0t >> 32)) << 32);
+    const int rows = __builtin_amdgcn_readfirstlane(S.tile_rows[q]);
+    const int r = 16 * w + i;
+    const bool rok = r < rows;
+    if (b != cur) {   // uniform
+      __syncthreads();   // the previous instance's products are done with Ms
+      const double* Mb = M + (int64_t)b * mstride;
+      // unconditional buffer loads (out-of-range offsets read zeros), all issued before the LDS stores
+      const i32x4_t mrs = make_rsrc(Mb, ((int64_t)(K - 1) * ldm + cols) * (int64_t)sizeof(double));
+      constexpr int NE = 16 * NCB * kUpdMaxK / kThreads;
+      double mt[NE];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = t + kThreads * u, k = e / (16 * NCB), c = e % (16 * NCB);
+        const bool ok = k < K && c0 + c < cols;
+        mt[u] = Buf<double>::load1(mrs, ok ? (int32_t)(((int64_t)k * ldm + c0 + c) * (int64_t)sizeof(double)) : kOob, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = t + kThreads * u;
+        Ms[e % (16 * NCB)][e / (16 * NCB)] = (TX)mt[u];
+      }
+      __syncthreads();
+      cur = b;
+    }
+    // this tile's rows: unconditional buffer loads, zeros past the tile's rows and past K
+    TX xv[NKB][4];
+    const i32x4_t xrs = make_rsrc(X + r0 * ldx, (int64_t)rows * ldx * (int64_t)sizeof(TX));
+    // per-lane part of the offset in the VGPR (row, the lane group's 4 columns), uniform part in the SGPR
+    const int32_t xoff = (int32_t)(((int64_t)r * ldx + 4 * g) * (int64_t)sizeof(TX));
+    if ((K & 3) == 0) {   // uniform: every group of four columns is whole or past K
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        const int32_t v = (rok && kb < nkb && 16 * kb + 4 * g < K) ? xoff : kOob;
+#pragma unroll
+        for (int h = 0; h < 4 / VW; ++h) {
+          TX q[VW];
+          Buf<TX>::load16(xrs, v, 16 * kb * (int32_t)sizeof(TX) + 16 * h, q);
+#pragma unroll
+          for (int u = 0; u < VW; ++u) xv[kb][VW * h + u] = q[u];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          xv[kb][u] = Buf<TX>::load1(xrs, (rok && 16 * kb + 4 * g + u < K) ? xoff + u * (int32_t)sizeof(TX) : kOob,
+                                     16 * kb * (int32_t)sizeof(TX));
+    }
+    V4 acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = V4{0, 0, 0, 0};
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      if (kb >= nkb) break;   // uniform; Ms is zero past K
+      TX mv[NCB][4];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const TX* src = &Ms[16 * cb + ci][16 * kb + 4 * g];
+        if constexpr (sizeof(TX) == 4) {
+          const f32x4_t v = *reinterpret_cast<const f32x4_t*>(src);
+          mv[cb][0] = v.x; mv[cb][1] = v.y; mv[cb][2] = v.z; mv[cb][3] = v.w;
+        } else {
+          const f64x2_t v0 = *reinterpret_cast<const f64x2_t*>(src), v1 = *reinterpret_cast<const f64x2_t*>(src + 2);
+          mv[cb][0] = v0.x; mv[cb][1] = v0.y; mv[cb][2] = v1.x; mv[cb][3] = v1.y;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = MF::op(mv[cb][u], xv[kb][u], acc[cb]);
+    }
+    if (!rok) continue;
+    TX* yr = Y + (r0 + r) * ldy;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int c = c0 + 16 * cb + 4 * g;   // register v holds column c + v
+      if (c >= cols) continue;
+      TX v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = al * acc[cb][u];
+      if (c + 3 < cols) {
+        if constexpr (sizeof(TX) == 4) {
+          f32x4_t* d = reinterpret_cast<f32x4_t*>(yr + c);
+          f32x4_t o = {v[0], v[1], v[2], v[3]};
+          if (beta != 0.0) {
+            const f32x4_t y = *d;
+            o = f32x4_t{fmaf(be, y.x, v[0]), fmaf(be, y.y, v[1]), fmaf(be, y.z, v[2]), fmaf(be, y.w, v[3])};
+          }
+          *d = o;
+        } else {
+          f64x2_t* d = reinterpret_cast<f64x2_t*>(yr + c);
+          f64x2_t o0 = {v[0], v[1]}, o1 = {v[2], v[3]};
+          if (beta != 0.0) {
+            const f64x2_t y0 = d[0], y1 = d[1];
+            o0 = f64x2_t{fma(be, y0.x, v[0]), fma(be, y0.y, v[1])};
+            o1 = f64x2_t{fma(be, y1.x, v[2]), fma(be, y1.y, v[3])};
+          }
+          d[0] = o0;
+          d[1] = o1;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (c + u < cols) yr[c + u] = (beta != 0.0) ? fma(be, yr[c + u], v[u]) : v[u];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -784,12 +934,39 @@ template void launch_sgram<double>(const SegDev&, const double*, int64_t, const 
 template void launch_sgram<float>(const SegDev&, const float*, int64_t, const float*, int64_t, int, int, double*,
                                   int64_t, double*, hipStream_t);
 
+// Workgroups of `threads` threads of a kernel that the device holds at once (occupancy times compute
+// units); 1024 if the runtime cannot tell.
+static int64_t resident_blocks(const void* kernel, int threads) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || cus <= 0 || per_cu <= 0)
+    return 1024;
+  return (int64_t)cus * per_cu;
+}
+
 template <typename TX>
 void launch_supdate(const SegDev& S, const TX* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
                     TX* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st) {
   if (cout <= 0 || S.ntiles <= 0) return;
-  dim3 g((unsigned)S.ntiles, cdiv(cout, 64));
   const bool vec = ((reinterpret_cast<uintptr_t>(X) | (uintptr_t)(ldx * sizeof(TX))) & 15) == 0;
+  const bool yvec = ((reinterpret_cast<uintptr_t>(Y) | (uintptr_t)(ldy * sizeof(TX))) & 15) == 0;
+  if (vec && yvec && cin <= kUpdMaxK) {
+    // as many workgroups per column block as are resident at once (no partial last round), each
+    // walking several tiles, so that M is staged a few times per launch rather than once per tile
+    if (cout <= 32) {
+      static const int64_t cap = resident_blocks(reinterpret_cast<const void*>(&supdate_ms_kernel<TX, 2>), kThreads);
+      const unsigned gx = (unsigned)std::min<int64_t>(S.ntiles, cap);
+      supdate_ms_kernel<TX, 2><<<dim3(gx, cdiv(cout, 32)), kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin,
+                                                                             cout, alpha, beta);
+    } else {
+      static const int64_t cap = resident_blocks(reinterpret_cast<const void*>(&supdate_ms_kernel<TX, 4>), kThreads);
+      const unsigned gx = (unsigned)std::min<int64_t>(S.ntiles, cap);
+      supdate_ms_kernel<TX, 4><<<dim3(gx, cdiv(cout, 64)), kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin,
+                                                                             cout, alpha, beta);
+    }
+    return;
+  }
+  dim3 g((unsigned)S.ntiles, cdiv(cout, 64));
   supdate_kernel<TX><<<g, kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin, cout, alpha, beta, vec);
 }
 template void launch_supdate<double>(const SegDev&, const double*, int64_t, const double*, int64_t, int64_t, double*,
