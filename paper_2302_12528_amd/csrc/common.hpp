@@ -7,6 +7,16 @@
 
 namespace lobpcg {
 
+// v if c, else +0, by a bit mask rather than a select: a select between a loaded value and a constant
+// may be compiled into a branch around the load, and a load inside a per-lane branch is waited for
+// there, one round trip per load.
+__device__ inline float keep_if(bool c, float v) {
+  return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) & (c ? 0xffffffffu : 0u));
+}
+__device__ inline double keep_if(bool c, double v) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & (c ? ~(uint64_t)0 : (uint64_t)0));
+}
+
 // f(std::integral_constant<int, A>), ..., f(std::integral_constant<int, B - 1>), so that f may index
 // register arrays with its argument.
 template <int A, int B, typename F>

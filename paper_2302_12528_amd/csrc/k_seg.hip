@@ -706,11 +706,31 @@ __global__ void __launch_bounds__(256) stsqr_wave_kernel(SegDev S, const Tin* in
   const int rows = it[2];
   const int slot = it[3];
   float a[RPL][CP];
+  // loads from clamped addresses, masked afterwards: unconditional, so that they are all in flight
+  // together; FP64 rows two columns per load when the rows allow
+  bool pairs = false;
+  if constexpr (sizeof(Tin) == 8)
+    pairs = (c % 2 == 0) && ((reinterpret_cast<uintptr_t>(in) | (uintptr_t)(ldin * 8)) % 16 == 0);   // uniform
+  if (pairs) {
 #pragma unroll
-  for (int s = 0; s < RPL; ++s) {
-    const int r = 64 * s + lane;
+    for (int s = 0; s < RPL; ++s) {
+      const int r = 64 * s + lane;
+      const Tin* src = in + (r0 + min(r, rows - 1)) * ldin;
 #pragma unroll
-    for (int k = 0; k < CP; ++k) a[s][k] = (r < rows && k < c) ? (float)in[(r0 + r) * ldin + k] : 0.f;
+      for (int kp = 0; kp < CP / 2; ++kp) {
+        const f64x2_t v = *reinterpret_cast<const f64x2_t*>(src + 2 * min(kp, c / 2 - 1));
+        a[s][2 * kp] = keep_if(r < rows && 2 * kp < c, (float)v.x);
+        a[s][2 * kp + 1] = keep_if(r < rows && 2 * kp + 1 < c, (float)v.y);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int r = 64 * s + lane;
+      const Tin* src = in + (r0 + min(r, rows - 1)) * ldin;
+#pragma unroll
+      for (int k = 0; k < CP; ++k) a[s][k] = keep_if(r < rows && k < c, (float)src[min(k, c - 1)]);
+    }
   }
   const int kmax = (c < rows) ? c : rows;
   float rjj = 0.f;
@@ -795,11 +815,12 @@ __global__ void __launch_bounds__(256) tsqr_gram_partial_kernel(const SegDev S, 
     for (int st = 0; st < 16; ++st) {
       const int r = r0 + 4 * st + g;
       const bool ok = r < rows;
+      const float* src = base + (int64_t)min(r, rows - 1) * c;   // clamped: unconditional loads
 #pragma unroll
       for (int u = 0; u < CB; ++u) {
         const int cx = ci0 + 16 * u + i, cy = cj0 + 16 * u + i;
-        xa[st][u] = (ok && cx < c) ? base[(int64_t)r * c + cx] : 0.f;
-        yb[st][u] = (ok && cy < c) ? base[(int64_t)r * c + cy] : 0.f;
+        xa[st][u] = keep_if(ok && cx < c, src[min(cx, c - 1)]);
+        yb[st][u] = keep_if(ok && cy < c, src[min(cy, c - 1)]);
       }
     }
 #pragma unroll
@@ -871,8 +892,12 @@ __global__ void __launch_bounds__(64) tsqr_combine_chol_kernel(const SegDev S, c
   const int64_t cc = (int64_t)c * c;
   const double* G = part + (gbase + b) * cc;
   double a[CP];
+  const int ic = min(i, c - 1);   // clamped: unconditional loads
 #pragma unroll
-  for (int k = 0; k < CP; ++k) a[k] = (i < c && k < c) ? 0.5 * (G[i * c + k] + G[k * c + i]) : 0.0;
+  for (int k = 0; k < CP; ++k) {
+    const int kc = min(k, c - 1);
+    a[k] = keep_if(i < c && k < c, 0.5 * (G[ic * c + kc] + G[kc * c + ic]));
+  }
 #pragma unroll
   for (int j = 0; j < CP; ++j) {
     if (j < c) {   // uniform
@@ -884,10 +909,13 @@ __global__ void __launch_bounds__(64) tsqr_combine_chol_kernel(const SegDev S, c
       for (int k = j + 1; k < CP; ++k) a[k] -= a[j] * lane_f64(a[j], k);
     }
   }
-  // row i of L is column i of R
+  // row i of L is column i of R (a compile-time loop: a[] stays in registers)
   float* R = out + (int64_t)slot * cc;
-  if (i < c)
-    for (int k = 0; k < c; ++k) R[k * c + i] = (k <= i) ? (float)a[k] : 0.f;
+  if (i < c) {
+#pragma unroll
+    for (int k = 0; k < CP; ++k)
+      if (k < c) R[k * c + i] = (k <= i) ? (float)a[k] : 0.f;
+  }
 }
 
 }  // namespace

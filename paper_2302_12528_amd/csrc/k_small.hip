@@ -1101,8 +1101,12 @@ __global__ void __launch_bounds__(2 * kSyevThreads) syev_tridiag_kernel(const do
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int i = ti + 16 * a, j = tj + 16 * b;
-      if (QG) M[a][b] = (i == j) ? 1.0 : 0.0;
-      else M[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
+      if (QG) {
+        M[a][b] = (i == j) ? 1.0 : 0.0;
+      } else {   // clamped addresses: unconditional loads, all in flight together
+        const int ic = min(i, c - 1), jc = min(j, c - 1);
+        M[a][b] = keep_if(i < c && j < c, 0.5 * (H[(int64_t)ic * ldh + jc] + H[(int64_t)jc * ldh + ic]));
+      }
     }
   // reflector 0 is formed before the loop; every later one by the owner of its row at the end of the step
   // before it
@@ -1244,7 +1248,8 @@ __global__ void __launch_bounds__(kSyevThreads32) syev_tridiag32_kernel(const do
 #pragma unroll
     for (int b = 0; b < kT32Cols; ++b) {
       const int i = ti + 16 * a, j = tj + 32 * b;
-      A[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
+      const int ic = min(i, c - 1), jc = min(j, c - 1);   // clamped: unconditional loads
+      A[a][b] = keep_if(i < c && j < c, 0.5 * (H[(int64_t)ic * ldh + jc] + H[(int64_t)jc * ldh + ic]));
     }
   tridiag32_rows<0>(A, c, ti, tj, &vb[0][0], &pb[0][0], &pvp[0][0], tb, d, e, tau, work, la);
 #pragma unroll
@@ -1415,7 +1420,8 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int i = ti + 16 * a, j = tj + 16 * b;
-        A[a][b] = (i < c && j < c) ? 0.5 * (H[(int64_t)i * ldh + j] + H[(int64_t)j * ldh + i]) : 0.0;
+        const int ic = min(i, c - 1), jc = min(j, c - 1);   // clamped: unconditional loads
+        A[a][b] = keep_if(i < c && j < c, 0.5 * (H[(int64_t)ic * ldh + jc] + H[(int64_t)jc * ldh + ic]));
         Q[a][b] = (i == j) ? 1.0 : 0.0;
       }
     // ---- 1. tridiagonalization, accumulating Q ----
@@ -1823,8 +1829,12 @@ __global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __res
   flag += blockIdx.x;
   const int i = threadIdx.x;
   double a[CP];
+  const int ic = min(i, c - 1);   // clamped addresses: the loads are unconditional and in flight together
 #pragma unroll
-  for (int k = 0; k < CP; ++k) a[k] = (i < c && k < c) ? 0.5 * (G[i * c + k] + G[k * c + i]) : 0.0;
+  for (int k = 0; k < CP; ++k) {
+    const int kc = min(k, c - 1);
+    a[k] = keep_if(i < c && k < c, 0.5 * (G[ic * c + kc] + G[kc * c + ic]));
+  }
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < CP; ++j) {
@@ -1850,7 +1860,9 @@ __global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __res
   if (Rout) {
     double rl[CP];
 #pragma unroll
-    for (int k = 0; k < CP; ++k) rl[k] = (i < c && k < c) ? (double)Rl[k * c + i] : 0.0;
+    for (int k = 0; k < CP; ++k) {
+      rl[k] = keep_if(i < c && k < c, (double)Rl[min(k, c - 1) * c + ic]);
+    }
 #pragma unroll
     for (int r = 0; r < CP; ++r) {
       double sum = 0.0;

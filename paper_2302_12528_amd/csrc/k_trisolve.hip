@@ -122,26 +122,43 @@ __device__ inline void reduce_blocks(const V4 (&acc)[4][NCB], V4 (&out)[NCB], V4
   }
 }
 
-// Store of the 4 values a lane holds for one output row: columns c0 + drow(lane, v), v = 0..3.  In
-// FP32 these are 4 consecutive columns (one 16-byte store); sub: dst = (load ? dst : 0) - val.
+template <typename T> __device__ constexpr T kZero4[4] = {0, 0, 0, 0};
+
+// The 4 values a lane holds for one output row: columns c0 + drow(lane, v), v = 0..3 (in FP32 4
+// consecutive columns, one 16-byte access).  load_cols reads the current values there (row must be a
+// valid row; columns past M read column 0 instead).
 template <typename T, int M>
-__device__ inline void store_cols(T* row, int c0, const typename Mfma<T>::v4& val, bool sub, bool load) {
+__device__ inline void load_cols(const T* row, int c0, T (&o)[4]) {
+  const int lane = threadIdx.x % 64;
+  if constexpr (sizeof(T) == 4) {
+    const int col = c0 + 4 * (lane / 16);
+    const f32x4_t v = *reinterpret_cast<const f32x4_t*>(row + (col < M ? col : 0));
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = c0 + Mfma<T>::drow(lane, q);
+      o[q] = row[col < M ? col : 0];
+    }
+  }
+}
+
+// Store of those values; sub: dst = old - val (old from load_cols), else dst = val.
+template <typename T, int M>
+__device__ inline void store_cols(T* row, int c0, const typename Mfma<T>::v4& val, bool sub, const T (&old)[4]) {
   const int lane = threadIdx.x % 64;
   if constexpr (sizeof(T) == 4) {
     const int col = c0 + 4 * (lane / 16);
     if (col >= M) return;
-    f32x4_t* d = reinterpret_cast<f32x4_t*>(row + col);
     f32x4_t v = val;
-    if (sub) v = (load ? *d : f32x4_t{0, 0, 0, 0}) - v;
-    *d = v;
+    if (sub) v = f32x4_t{old[0], old[1], old[2], old[3]} - v;
+    *reinterpret_cast<f32x4_t*>(row + col) = v;
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int col = c0 + Mfma<T>::drow(lane, q);
       if (col >= M) continue;
-      T v = val[q];
-      if (sub) v = (load ? row[col] : (T)0) - v;
-      row[col] = v;
+      row[col] = sub ? old[q] - val[q] : val[q];
     }
   }
 }
@@ -252,33 +269,65 @@ __device__ inline void fwd_tile(const SolveItem& it, int wave, typename Mfma<T>:
     cur = nxt;
   }
   // The MFMA computed D = b^T P^T: register v of lane (i, g) in block (p, w, c) is output row
-  // 16 VW p + VW i + w, column 16 c + drow(lane, v) (4 consecutive columns in FP32).
-  auto emit = [&](int p, int w, const V4 (&blk)[NCB]) {
-    const int rr = 16 * VW * p + VW * i + w;
-    if (rr >= h) return;
+  // 16 VW p + VW i + w, column 16 c + drow(lane, v) (4 consecutive columns in FP32).  Rows below the
+  // own columns of a supernode with children subtract from the gathered update vector: when the tile
+  // has such rows (a uniform test), the current values of all of a lane's rows are requested first,
+  // unconditionally (an address clamped into the tile) and masked per row afterwards, so that they are
+  // in flight together; a load under a per-lane condition would be waited for inside its branch.
+  constexpr int NRL = (NW > 1) ? 1 : VW * NP;   // rows per lane
+  auto row_of = [&](int e) { return (NW > 1) ? 16 * VW * (wave / VW) + VW * i + wave % VW
+                                             : 16 * VW * (e / VW) + VW * i + e % VW; };
+  auto dest = [&](int rr, bool& sub) -> T* {
     const int row = r0 + rr;
-    T* base;
-    bool sub = false;   // below row: -d = -L21 y_s, added to the gathered children's contributions
-    if (slot >= 0) {
-      base = part + ((int64_t)slot * TR + rr) * M;
-    } else if (row < nc) {
-      base = y + (int64_t)(begin + row) * M;
+    sub = false;
+    if (slot >= 0) return part + ((int64_t)slot * TR + rr) * M;
+    if (row < nc) return y + (int64_t)(begin + row) * M;
+    sub = true;   // below row: -d = -L21 y_s, added to the gathered children's contributions
+    return uvec + ((int64_t)it.aux + row - nc) * M;
+  };
+  const bool rmw = parent && slot < 0 && r0 + h > nc;   // uniform
+  // rows in groups whose current values take at most 64 registers
+  constexpr int RG = (sizeof(T) * NRL * NCB * 4 <= 256) ? NRL : 1;
+  auto emit = [&](int e, const V4 (&blk)[NCB], const T (&old)[NCB][4]) {
+    const int rr = row_of(e);
+    if (rr >= h) return;
+    bool sub;
+    T* base = dest(rr, sub);
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) store_cols<T, M>(base, 16 * c, blk[c], sub, old[c]);
+  };
+  V4 blk[NCB];
+  if constexpr (NW > 1) reduce_blocks<V4, NCB>(acc, blk, red, wave);
+#pragma unroll
+  for (int e0 = 0; e0 < NRL; e0 += RG) {
+    T old[RG][NCB][4];
+    if (rmw) {
+      bool keep[RG];
+#pragma unroll
+      for (int e = 0; e < RG; ++e) {
+        const T* base = dest(min(row_of(e0 + e), h - 1), keep[e]);
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) load_cols<T, M>(base, 16 * c, old[e][c]);
+      }
+#pragma unroll
+      for (int e = 0; e < RG; ++e)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) old[e][c][q] = keep_if(keep[e], old[e][c][q]);
     } else {
-      base = uvec + ((int64_t)it.aux + row - nc) * M;
-      sub = true;
+#pragma unroll
+      for (int e = 0; e < RG; ++e)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) old[e][c][q] = (T)0;
     }
 #pragma unroll
-    for (int c = 0; c < NCB; ++c) store_cols<T, M>(base, 16 * c, blk[c], sub, sub && parent);
-  };
-  if constexpr (NW > 1) {
-    V4 blk[NCB];
-    reduce_blocks<V4, NCB>(acc, blk, red, wave);
-    emit(wave / VW, wave % VW, blk);
-  } else {
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int w = 0; w < VW; ++w) emit(p, w, acc[VW * p + w]);
+    for (int e = 0; e < RG; ++e) {
+      if constexpr (NW > 1) emit(e0 + e, blk, old[e]);
+      else emit(e0 + e, acc[e0 + e], old[e]);
+    }
   }
 }
 
@@ -425,9 +474,9 @@ __device__ inline void bwd_tile(const SolveItem& it, int wave, typename Mfma<T>:
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
       if (slot >= 0) {
-        store_cols<T, M>(part + ((int64_t)slot * TR + jj) * M, 16 * c, blk[c], false, false);
+        store_cols<T, M>(part + ((int64_t)slot * TR + jj) * M, 16 * c, blk[c], false, kZero4<T>);
       } else {
-        store_cols<T, M>(x + row * M, 16 * c, blk[c], false, false);
+        store_cols<T, M>(x + row * M, 16 * c, blk[c], false, kZero4<T>);
         if (W) store_cols_f64<T>(W + row * ldw, 16 * c, blk[c], mw);
       }
     }
