@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <type_traits>
 
@@ -15,6 +16,36 @@ __device__ inline float keep_if(bool c, float v) {
 }
 __device__ inline double keep_if(bool c, double v) {
   return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, v) & (c ? ~(uint64_t)0 : (uint64_t)0));
+}
+
+// Cholesky factor of a c x c symmetric positive definite matrix held by one wave, lane i holding row i
+// in a[0 .. CP) (c <= CP <= 64, entries past c zero).  Step j publishes column j of the current matrix in
+// the wave's LDS column buffer cb (64 doubles) and every lane reads the pivot and the column entries it
+// needs from there (uniform addresses; one wave's LDS accesses complete in order, so no barrier), with
+// l_i l_k = (l_i / l_jj) a_kj.  On return a[j] = L[i][j] for j <= i (entries above the diagonal are not
+// meaningful); a non-positive or non-finite pivot is replaced by 1 and reported through bad.
+template <int CP>
+__device__ inline void wave_cholesky(double (&a)[CP], int c, double* cb, bool& bad) {
+  const int i = threadIdx.x % 64;
+#pragma unroll
+  for (int j = 0; j < CP; ++j) {
+    if (j < c) {   // uniform
+      cb[i] = a[j];
+      __builtin_amdgcn_wave_barrier();
+      double d = cb[j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = true;
+        d = 1.0;
+      }
+      const double ljj = sqrt(d), rinv = 1.0 / ljj;
+      const double l = (i == j) ? ljj : a[j] * rinv;
+      a[j] = l;
+      const double t = l * rinv;
+#pragma unroll
+      for (int k = j + 1; k < CP; ++k) a[k] -= t * cb[k];
+      __builtin_amdgcn_wave_barrier();   // this step's reads of cb before the next step's writes
+    }
+  }
 }
 
 // f(std::integral_constant<int, A>), ..., f(std::integral_constant<int, B - 1>), so that f may index

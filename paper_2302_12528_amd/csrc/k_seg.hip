@@ -891,6 +891,7 @@ __global__ void __launch_bounds__(64) tsqr_combine_chol_kernel(const SegDev S, c
   const int i = threadIdx.x;
   const int64_t cc = (int64_t)c * c;
   const double* G = part + (gbase + b) * cc;
+  __shared__ double cb[64];
   double a[CP];
   const int ic = min(i, c - 1);   // clamped: unconditional loads
 #pragma unroll
@@ -898,17 +899,8 @@ __global__ void __launch_bounds__(64) tsqr_combine_chol_kernel(const SegDev S, c
     const int kc = min(k, c - 1);
     a[k] = keep_if(i < c && k < c, 0.5 * (G[ic * c + kc] + G[kc * c + ic]));
   }
-#pragma unroll
-  for (int j = 0; j < CP; ++j) {
-    if (j < c) {   // uniform
-      double d = lane_f64(a[j], j);
-      if (!(d > 0.0) || !isfinite(d)) d = 1.0;
-      const double ljj = sqrt(d);
-      a[j] = (i == j) ? ljj : a[j] / ljj;
-#pragma unroll
-      for (int k = j + 1; k < CP; ++k) a[k] -= a[j] * lane_f64(a[j], k);
-    }
-  }
+  bool bad = false;   // a non-positive pivot is replaced by 1
+  wave_cholesky<CP>(a, c, cb, bad);
   // row i of L is column i of R (a compile-time loop: a[] stays in registers)
   float* R = out + (int64_t)slot * cc;
   if (i < c) {

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <type_traits>
 
+#include "bufload.hpp"
 #include "common.hpp"
 #include "mfma.hpp"
 
@@ -1813,11 +1814,11 @@ __global__ void __launch_bounds__(256) chol_upper_kernel(const double* __restric
   }
 }
 
-// The same factorization by one wave for c <= CP: lane i holds row i of the symmetrised G, so the
-// diagonal and L[k][j] of another row k are readlanes and no barrier is needed.  Rout = L^T Rl with
-// lane j forming column j.
+// The same for 32 < c <= CP (registers for the row of G and the column of Rl leave no room for the
+// staged form below): lane i holds row i of the symmetrised G, the diagonal and L[k][j] of another row
+// k are readlanes, no barrier is needed.  Rout = L^T Rl with lane j forming column j.
 template <typename T, int CP>
-__global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __restrict__ G, const T* __restrict__ Rl,
+__global__ void __launch_bounds__(64) chol_upper_wave_rl_kernel(const double* __restrict__ G, const T* __restrict__ Rl,
                                                              int c, double* __restrict__ Lt, double* __restrict__ Rout,
                                                              int* flag, const int32_t* __restrict__ active) {
   if (active && !active[blockIdx.x]) return;
@@ -1869,6 +1870,76 @@ __global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __res
 #pragma unroll
       for (int k = r; k < CP; ++k) sum += rdl64(a[r], k) * rl[k];
       if (i < c && r < c) Rout[r * c + i] = sum;
+    }
+  }
+}
+
+// The same factorization by one wave for c <= CP <= 32: lane i holds row i of the symmetrised G and
+// the pivot column goes through LDS each step (wave_cholesky), so no barrier is needed.  Rout = L^T Rl
+// with lane j forming column j from the rows of L staged in LDS.
+template <typename T, int CP>
+__global__ void __launch_bounds__(64) chol_upper_wave_kernel(const double* __restrict__ G, const T* __restrict__ Rl,
+                                                             int c, double* __restrict__ Lt, double* __restrict__ Rout,
+                                                             int* flag, const int32_t* __restrict__ active) {
+  if (active && !active[blockIdx.x]) return;
+  const int64_t off = (int64_t)blockIdx.x * c * c;
+  G += off;
+  Rl += off;
+  Lt += off;
+  if (Rout) Rout += off;
+  flag += blockIdx.x;
+  __shared__ __align__(16) double cb[64];
+  __shared__ __align__(16) double Ls[CP][CP + 2];
+  const int i = threadIdx.x;
+  double a[CP];
+  const int ic = min(i, c - 1);   // clamped addresses: the loads are unconditional and in flight together
+#pragma unroll
+  for (int k = 0; k < CP; ++k) {
+    const int kc = min(k, c - 1);
+    a[k] = keep_if(i < c && k < c, 0.5 * (G[ic * c + kc] + G[kc * c + ic]));
+  }
+  // Rl's column i, requested before the factorization
+  double rl[CP];
+  if (Rout) {
+#pragma unroll
+    for (int k = 0; k < CP; ++k) rl[k] = keep_if(i < c && k < c, (double)Rl[min(k, c - 1) * c + ic]);
+  }
+  bool bad = false;
+  wave_cholesky<CP>(a, c, cb, bad);
+  if (bad && i == 0) flag[0] = 1;
+  // column i of Lt = row i of L (zeros below the diagonal of Lt)
+  if (i < c) {
+#pragma unroll
+    for (int k = 0; k < CP; ++k)
+      if (k < c) Lt[k * c + i] = (k <= i) ? a[k] : 0.0;
+  }
+  if (Rout) {
+    {
+      // Rout[r][i] = sum_{k >= r} L[k][r] Rl[k][i]: row k of L from LDS (uniform reads, two columns each)
+      if (i < CP) {
+#pragma unroll
+        for (int k = 0; k < CP; ++k) Ls[i][k] = (k <= i) ? a[k] : 0.0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      double sum[CP];
+#pragma unroll
+      for (int r = 0; r < CP; ++r) sum[r] = 0.0;
+#pragma unroll
+      for (int k = 0; k < CP; ++k) {
+        if (k < c) {   // uniform
+#pragma unroll
+          for (int r = 0; r <= k; r += 2) {   // Ls[k][k + 1] is zero
+            const f64x2_t l2 = *reinterpret_cast<const f64x2_t*>(&Ls[k][r]);
+            sum[r] += l2.x * rl[k];
+            if (r + 1 < CP) sum[r + 1] += l2.y * rl[k];
+          }
+        }
+      }
+      if (i < c) {
+#pragma unroll
+        for (int r = 0; r < CP; ++r)
+          if (r < c) Rout[r * c + i] = sum[r];
+      }
     }
   }
 }
@@ -1929,7 +2000,7 @@ template <typename T>
 void launch_chol_upper(const double* G, const T* Rl, int c, double* Lt, double* Rout, int* flag,
                        const int32_t* active, int B, hipStream_t st) {
   if (c <= 32) chol_upper_wave_kernel<T, 32><<<B, 64, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
-  else if (c <= 64) chol_upper_wave_kernel<T, 64><<<B, 64, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
+  else if (c <= 64) chol_upper_wave_rl_kernel<T, 64><<<B, 64, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
   else chol_upper_kernel<T><<<B, 256, 0, st>>>(G, Rl, c, Lt, Rout, flag, active);
 }
 template void launch_chol_upper<float>(const double*, const float*, int, double*, double*, int*, const int32_t*, int,
