@@ -639,10 +639,25 @@ __global__ void __launch_bounds__(NR) stsqr_kernel(SegDev S, const Tin* in, int6
     for (int k = 0; k < c; ++k) R[(int64_t)t * c + k] = (k >= t && t < rows) ? A[k * LP + t] : (T)0;
 }
 
+// Exchange with lane ^ M (M = 1, 2, 4, 8, 16) inside 32-lane halves: DPP moves for 1, 2 (quad
+// permutes) and 8 (rotation by 8 inside a 16-lane row), swizzles in bit-mask mode for 4 and 16.
+template <int M>
+__device__ inline float lane_xor(float v) {
+  const int x = __builtin_bit_cast(int, v);
+  int y;
+  if constexpr (M == 1) y = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);        // quad_perm [1,0,3,2]
+  else if constexpr (M == 2) y = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  else if constexpr (M == 4) y = __builtin_amdgcn_ds_swizzle(x, 0x101F);                // and 31, xor 4
+  else if constexpr (M == 8) y = __builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false);  // row_ror 8
+  else y = __builtin_amdgcn_ds_swizzle(x, 0x401F);                                       // and 31, xor 16
+  return __builtin_bit_cast(float, y);
+}
+
 // Sum over the 64 lanes of a wave of each of the N values q[0..N) (N <= 32), returned in out[] as
-// wave-uniform values.  With P = 2^LOG >= N (the values padded with zeros), recursive halving: at each
-// exchange a lane keeps half of its vector and adds the partner lane's copy of that half (P - 1
-// shuffles), the lane bits left over are summed directly, and value k then sits in lane k << (6 - LOG).
+// wave-uniform values.  With P = 2^LOG >= N (the values padded with zeros), recursive halving over lane
+// bits 0 .. LOG - 1: at the exchange on bit b a lane keeps half of its vector and adds the partner lane's
+// copy of that half (P - 1 exchanges in all), the lane bits LOG .. 4 are summed directly, and value k then
+// sits in the lanes whose low LOG bits are k's bit-reversal, as two halves (bit 5) added on extraction.
 template <int N>
 __device__ inline void wave_allreduce(const float (&qin)[N], float (&out)[N]) {
   constexpr int LOG = (N <= 1) ? 0 : (N <= 2) ? 1 : (N <= 4) ? 2 : (N <= 8) ? 3 : (N <= 16) ? 4 : 5;
@@ -652,10 +667,8 @@ __device__ inline void wave_allreduce(const float (&qin)[N], float (&out)[N]) {
   float q[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) q[k] = (k < N) ? qin[k] : 0.f;
-#pragma unroll
-  for (int st = 0; st < LOG; ++st) {
-    const int m = 32 >> st;
-    const int half = P >> (st + 1);
+  static_for<0, LOG>([&](auto S) {
+    constexpr int st = decltype(S)::value, m = 1 << st, half = P >> (st + 1);
     // lane-dependent choice between q[i] and q[i + half] by bit masks (a select between two array
     // elements would be folded into a lane-dependent array index)
     const uint32_t hm = (lane & m) ? 0xffffffffu : 0u;
@@ -664,14 +677,18 @@ __device__ inline void wave_allreduce(const float (&qin)[N], float (&out)[N]) {
       const uint32_t lo_b = __builtin_bit_cast(uint32_t, q[i]), hi_b = __builtin_bit_cast(uint32_t, q[i + half]);
       const float keep = __builtin_bit_cast(float, (hi_b & hm) | (lo_b & ~hm));
       const float send = __builtin_bit_cast(float, (lo_b & hm) | (hi_b & ~hm));
-      q[i] = keep + __shfl_xor(send, m, 64);
+      q[i] = keep + lane_xor<m>(send);
     }
+  });
+  static_for<LOG, 5>([&](auto S) { q[0] += lane_xor<(1 << decltype(S)::value)>(q[0]); });
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int r = 0;   // bit-reversal of k over LOG bits
+#pragma unroll
+    for (int b = 0; b < LOG; ++b) r |= ((k >> b) & 1) << (LOG - 1 - b);
+    out[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, q[0]), r)) +
+             __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, q[0]), r + 32));
   }
-#pragma unroll
-  for (int m = 32 >> LOG; m >= 1; m >>= 1) q[0] += __shfl_xor(q[0], m, 64);
-#pragma unroll
-  for (int k = 0; k < N; ++k)
-    out[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, q[0]), k << (6 - LOG)));
 }
 
 __device__ inline float lane_value(float v, int l) {
