@@ -27,7 +27,8 @@ inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // Gram partials over one chunk of rows with FP64 matrix cores: the (32 RB) x (32 CB) output tile
 // is split 2 x 2 over the four waves, each wave RB x CB blocks of 16 x 16 accumulated by
 // v_mfma_f64_16x16x4f64 over 4 rows at a time.  Lane (i, g) = (l % 16, l / 16) reads row r + g,
-// columns 16 b + i, of X and Y directly (16 consecutive doubles per row and lane group).
+// columns 16 b + i, of X and Y directly (16 consecutive doubles per row and lane group); the loads
+// of the next rows are in flight while the current ones are multiplied.
 // ---------------------------------------------------------------------------
 template <int RB, int CB, typename TI>
 __global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const TI* __restrict__ X, int64_t ldx,
@@ -45,37 +46,63 @@ __global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const
   const int ci0 = ti * T1 + (w / 2) * 16 * RB;   // first X column of this wave
   const int cj0 = tj * T2 + (w % 2) * 16 * CB;   // first Y column of this wave
   const int64_t rbeg = S.chunk_r0[q];
-  const int64_t rend = rbeg + S.chunk_rows[q];
   V4 acc[RB][CB];
 #pragma unroll
   for (int u = 0; u < RB; ++u)
 #pragma unroll
     for (int v = 0; v < CB; ++v) acc[u][v] = V4{0, 0, 0, 0};
-  bool xc[RB], yc[CB];
+  // Buffer loads over the chunk: a row past the chunk reads zero by the resource's range, a column past
+  // c1 (c2) by an out-of-range offset, so every load is issued unconditionally.  The row step is the
+  // wave-uniform offset; the loads of the next rows are issued before the current ones are multiplied.
+  constexpr int U = (RB + CB <= 2) ? 8 : 4;
+  constexpr int64_t SZ = sizeof(TI);
+  const int nrows = S.chunk_rows[q];
+  const i32x4_t xr = make_rsrc(X + rbeg * ldx, (int64_t)nrows * ldx * SZ);
+  const i32x4_t yr = make_rsrc(Y + rbeg * ldy, (int64_t)nrows * ldy * SZ);
+  int32_t xo[U][RB], yo[U][CB];
 #pragma unroll
-  for (int u = 0; u < RB; ++u) xc[u] = (ci0 + 16 * u + i < c1);
+  for (int s = 0; s < U; ++s) {
 #pragma unroll
-  for (int v = 0; v < CB; ++v) yc[v] = (cj0 + 16 * v + i < c2);
-  const TI* xp = X + ci0 + i;
-  const TI* yp = Y + cj0 + i;
-  constexpr int U = 4;   // 4-row steps whose loads are issued together
-  for (int64_t r0 = rbeg; r0 < rend; r0 += 4 * U) {
-    TI xa[U][RB], yb[U][CB];
+    for (int u = 0; u < RB; ++u) {
+      const int col = ci0 + 16 * u + i;
+      xo[s][u] = col < c1 ? (int32_t)(((4 * s + g) * ldx + col) * SZ) : kOob;
+    }
+#pragma unroll
+    for (int v = 0; v < CB; ++v) {
+      const int col = cj0 + 16 * v + i;
+      yo[s][v] = col < c2 ? (int32_t)(((4 * s + g) * ldy + col) * SZ) : kOob;
+    }
+  }
+  const int32_t xstep = (int32_t)(4 * U * ldx * SZ), ystep = (int32_t)(4 * U * ldy * SZ);
+  auto load_group = [&](int32_t xs, int32_t ys, TI (&xd)[U][RB], TI (&yd)[U][CB]) {
 #pragma unroll
     for (int s = 0; s < U; ++s) {
-      const int64_t r = r0 + 4 * s + g;
-      const bool rok = r < rend;
 #pragma unroll
-      for (int u = 0; u < RB; ++u) xa[s][u] = (rok && xc[u]) ? xp[r * ldx + 16 * u] : (TI)0;
+      for (int u = 0; u < RB; ++u) xd[s][u] = Buf<TI>::load1(xr, xo[s][u], xs);
 #pragma unroll
-      for (int v = 0; v < CB; ++v) yb[s][v] = (rok && yc[v]) ? yp[r * ldy + 16 * v] : (TI)0;
+      for (int v = 0; v < CB; ++v) yd[s][v] = Buf<TI>::load1(yr, yo[s][v], ys);
     }
+  };
+  auto mult_group = [&](const TI (&xd)[U][RB], const TI (&yd)[U][CB]) {
 #pragma unroll
     for (int s = 0; s < U; ++s)
 #pragma unroll
       for (int u = 0; u < RB; ++u)
 #pragma unroll
-        for (int v = 0; v < CB; ++v) acc[u][v] = MF::op(xa[s][u], yb[s][v], acc[u][v]);
+        for (int v = 0; v < CB; ++v) acc[u][v] = MF::op(xd[s][u], yd[s][v], acc[u][v]);
+  };
+  // Two register groups in turn (no copies between them, so no load is waited for early); groups past
+  // the chunk read zeros.
+  TI xa[U][RB], yb[U][CB], xn[U][RB], yn[U][CB];
+  load_group(0, 0, xa, yb);
+  int32_t xs = 0, ys = 0;
+  for (int r = 0; r < nrows; r += 8 * U) {
+    load_group(xs + xstep, ys + ystep, xn, yn);
+    mult_group(xa, yb);
+    xs += 2 * xstep;
+    ys += 2 * ystep;
+    load_group(xs, ys, xa, yb);
+    mult_group(xn, yn);
   }
   double* P = part + (int64_t)q * c1 * c2;
 #pragma unroll
