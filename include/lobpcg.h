@@ -314,7 +314,7 @@ lobpcg_status lobpcg_apply_a(lobpcg_ctx ctx, const double* X, int64_t ldx, doubl
  * precision (Algorithm 3 lines 9-10): R, W device n x m, ld = m. */
 lobpcg_status lobpcg_apply_precond(lobpcg_ctx ctx, const double* R, double* W);
 
-/* Algorithm 2 in place on W (device, n x c row-major, ld >= c, c <= 64):
+/* Algorithm 2 in place on W (device, n x c row-major, c <= ldw < 2^22, c <= 64):
  * W <- Q; R (device, c x c row-major, nullable) <- upper triangular factor.
  * lower_step1 = 1: step 1 in FP32, else FP64.  Returns ORTHO_BREAKDOWN if the
  * step-3 Cholesky fails. */
@@ -335,7 +335,7 @@ lobpcg_status lobpcg_mixed_qr_noalloc(double* W, int64_t n, int32_t c, int64_t l
                                       double* R, void* hip_stream);
 
 /* G = X^T Y (device; X n x c1, Y n x c2, row-major; G c1 x c2 row-major),
- * deterministic two-stage reduction.  c1, c2 <= 256. */
+ * deterministic two-stage reduction.  c1, c2 <= 256; ldx, ldy <= 32768 (INVALID_ARG otherwise). */
 lobpcg_status lobpcg_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n,
                           int32_t c1, int32_t c2, double* G, void* hip_stream);
 

@@ -2278,7 +2278,7 @@ lobpcg_status lobpcg_apply_precond(lobpcg_ctx c, const double* R, double* W) {
 
 lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t cc, int64_t ldw, int32_t lower_step1, double* R,
                               void* hip_stream) {
-  if (!W || n < 1 || cc < 1 || cc > 64 || ldw < cc || n < cc)
+  if (!W || n < 1 || cc < 1 || cc > 64 || ldw < cc || ldw >= (1 << 22) || n < cc)
     return fail(LOBPCG_ERR_INVALID_ARG, "bad arguments to lobpcg_mixed_qr");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   TempSeg T;
@@ -2318,7 +2318,7 @@ lobpcg_status lobpcg_mixed_qr(double* W, int64_t n, int32_t cc, int64_t ldw, int
 
 lobpcg_status lobpcg_mixed_qr_noalloc(double* W, int64_t n, int32_t cc, int64_t ldw, int32_t lower_step1,
                                       double* R, void* hip_stream) {
-  if (!W || n < 1 || cc < 1 || cc > 64 || ldw < cc || n < cc)
+  if (!W || n < 1 || cc < 1 || cc > 64 || ldw < cc || ldw >= (1 << 22) || n < cc)
     return fail(LOBPCG_ERR_INVALID_ARG, "bad arguments to lobpcg_mixed_qr_noalloc");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   // host plans: the one-instance segmentation and the TSQR tree, as lobpcg_mixed_qr builds them
@@ -2400,7 +2400,10 @@ lobpcg_status lobpcg_mixed_qr_noalloc(double* W, int64_t n, int32_t cc, int64_t 
 
 lobpcg_status lobpcg_gram(const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t n, int32_t c1,
                           int32_t c2, double* G, void* hip_stream) {
-  if (!X || !Y || !G || n < 1 || c1 < 1 || c2 < 1 || c1 > 256 || c2 > 256 || ldx < c1 || ldy < c2)
+  // ldx, ldy <= 32768: a reduction chunk (at most 4096 rows) then spans less than 2 GiB, the range of
+  // the Gram kernel's 32-bit buffer offsets
+  if (!X || !Y || !G || n < 1 || c1 < 1 || c2 < 1 || c1 > 256 || c2 > 256 || ldx < c1 || ldy < c2 ||
+      ldx > 32768 || ldy > 32768)
     return fail(LOBPCG_ERR_INVALID_ARG, "bad arguments to lobpcg_gram");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   TempSeg T;

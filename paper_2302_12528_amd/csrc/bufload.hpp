@@ -1,10 +1,10 @@
-// Raw buffer loads (MUBUF) for the streaming kernels.
+// Raw buffer loads and stores (MUBUF) for the streaming kernels.
 //
 // A buffer resource describes [base, base + bytes); a load takes a per-lane byte offset (VGPR) and a
 // wave-uniform byte offset (SGPR), so a kernel that walks a matrix keeps one 32-bit offset per lane
 // and advances a scalar, instead of carrying a 64-bit address per load.  A load whose offset lies at
-// or beyond `bytes` returns zeros without touching memory; kOob is such an offset for every resource
-// made here (bytes < 2^31) and is how masked lanes are expressed.
+// or beyond `bytes` returns zeros without touching memory (a store there is dropped); kOob is such an
+// offset for every resource made here (bytes < 2^31) and is how masked lanes are expressed.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -29,6 +29,14 @@ __device__ i32x4_t llvm_buffer_load_i32x4(i32x4_t rsrc, int32_t voffset, int32_t
     __asm("llvm.amdgcn.raw.buffer.load.v4i32");
 __device__ i32x2_t llvm_buffer_load_i32x2(i32x4_t rsrc, int32_t voffset, int32_t soffset, int32_t aux)
     __asm("llvm.amdgcn.raw.buffer.load.v2i32");
+__device__ void llvm_buffer_store_f32x4(f32x4_t v, i32x4_t rsrc, int32_t voffset, int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.raw.buffer.store.v4f32");
+__device__ void llvm_buffer_store_f64x2(f64x2_t v, i32x4_t rsrc, int32_t voffset, int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.raw.buffer.store.v2f64");
+__device__ void llvm_buffer_store_f32(float v, i32x4_t rsrc, int32_t voffset, int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.raw.buffer.store.f32");
+__device__ void llvm_buffer_store_f64(double v, i32x4_t rsrc, int32_t voffset, int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.raw.buffer.store.f64");
 
 constexpr int32_t kOob = 0x7ffffff0;   // past the end of every resource (bytes < 2^31 - 2^4)
 
@@ -51,6 +59,10 @@ template <> struct Buf<float> {
     o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
   }
   static __device__ inline float load1(i32x4_t r, int32_t v, int32_t s) { return llvm_buffer_load_f32(r, v, s, 0); }
+  static __device__ inline void store16(i32x4_t r, int32_t v, int32_t s, const float (&o)[4]) {
+    llvm_buffer_store_f32x4(f32x4_t{o[0], o[1], o[2], o[3]}, r, v, s, 0);
+  }
+  static __device__ inline void store1(i32x4_t r, int32_t v, int32_t s, float o) { llvm_buffer_store_f32(o, r, v, s, 0); }
   static __device__ inline void load_idx(i32x4_t r, int32_t v, int32_t s, int32_t (&o)[4]) {
     const i32x4_t q = llvm_buffer_load_i32x4(r, v, s, 0);
     o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
@@ -62,6 +74,10 @@ template <> struct Buf<double> {
     o[0] = q.x; o[1] = q.y;
   }
   static __device__ inline double load1(i32x4_t r, int32_t v, int32_t s) { return llvm_buffer_load_f64(r, v, s, 0); }
+  static __device__ inline void store16(i32x4_t r, int32_t v, int32_t s, const double (&o)[2]) {
+    llvm_buffer_store_f64x2(f64x2_t{o[0], o[1]}, r, v, s, 0);
+  }
+  static __device__ inline void store1(i32x4_t r, int32_t v, int32_t s, double o) { llvm_buffer_store_f64(o, r, v, s, 0); }
   static __device__ inline void load_idx(i32x4_t r, int32_t v, int32_t s, int32_t (&o)[2]) {
     const i32x2_t q = llvm_buffer_load_i32x2(r, v, s, 0);
     o[0] = q.x; o[1] = q.y;

@@ -548,12 +548,23 @@ __global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, TW* W, int64_t
 }
 
 // The same solve for c == CP columns with the row in registers (fully unrolled), one row per
-// thread: U_b is read through the scalar cache (all lanes use the same element), so nothing is
-// staged in LDS and many tiles share a compute unit.  Arithmetic in FP64 for FP64 blocks, in the
-// blocks' precision otherwise.
+// thread.  The tile moves between memory and LDS in consecutive 16-byte pieces (whole rows per
+// instruction, so each cache line is requested once, where one row per lane would touch 64 lines
+// per instruction) and each thread takes its row from LDS; LDS rows are padded by 16 bytes so that
+// the row reads and the piece writes both spread over the banks.  While the rows are in registers
+// the same LDS holds U_b in the blocks' precision with reciprocal diagonal entries, read by all lanes
+// at once (broadcast) as the solve proceeds.  Arithmetic in FP64 for FP64 blocks, in the blocks'
+// precision otherwise.
 template <typename TU, int CP, typename TW>
-__global__ void __launch_bounds__(64) strsm_rows_reg_kernel(SegDev S, TW* W, int64_t ld,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) strsm_rows_reg_kernel(SegDev S, TW* W, int64_t ld,
                                                             const TU* __restrict__ U, int64_t ustride) {
+  constexpr int VW = 16 / sizeof(TW);     // elements per 16-byte piece
+  constexpr int PPR = CP / VW;            // pieces per row
+  constexpr int PITCH = CP + VW;          // LDS row pitch (elements)
+  constexpr int NP = PPR;                 // pieces per lane (64 rows x PPR pieces / 64 lanes)
+  constexpr int NU = CP * CP / 64;        // elements of U_b per lane
+  static_assert(CP * CP <= 64 * PITCH, "U_b must fit in the tile's LDS");
+  __shared__ __align__(16) TW Ws[64 * PITCH];
   const int q = blockIdx.x;
   const int b = S.tile_inst[q];
   if (!S.active[b]) return;
@@ -561,19 +572,90 @@ __global__ void __launch_bounds__(64) strsm_rows_reg_kernel(SegDev S, TW* W, int
   const int rows = S.tile_rows[q];
   const TU* Ub = U + (int64_t)b * ustride;
   const int t = threadIdx.x;
-  if (t >= rows) return;
-  TW* row = W + (r0 + t) * ld;
+  TW* tile = W + r0 * ld;
+  // Buffer accesses over the tile's rows: rows past it read zeros and their stores are dropped, so
+  // every access is issued unconditionally (64 ld elements stay below 2^31 bytes: ld < 2^22).
+  const i32x4_t rs = make_rsrc(tile, (int64_t)rows * ld * (int64_t)sizeof(TW));
+  // 16-byte pieces when the tile's rows allow (uniform), else element by element
+  const bool vec = ((reinterpret_cast<uintptr_t>(tile) | (uintptr_t)(ld * sizeof(TW))) % 16) == 0;
+  auto voff = [&](int r, int k) { return (int32_t)(((int64_t)r * ld + k) * (int64_t)sizeof(TW)); };
+  TU u[NU];
+#pragma unroll
+  for (int s = 0; s < NU; ++s) u[s] = Ub[s * 64 + t];
+  if (vec) {
+    TW v[NP][VW];
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int e = s * 64 + t;
+      Buf<TW>::load16(rs, voff(e / PPR, (e % PPR) * VW), 0, v[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int e = s * 64 + t;
+#pragma unroll
+      for (int h = 0; h < VW; ++h) Ws[(e / PPR) * PITCH + (e % PPR) * VW + h] = v[s][h];
+    }
+  } else {
+    TW v[CP];
+#pragma unroll
+    for (int s = 0; s < CP; ++s) {
+      const int e = s * 64 + t;
+      v[s] = Buf<TW>::load1(rs, voff(e / CP, e % CP), 0);
+    }
+#pragma unroll
+    for (int s = 0; s < CP; ++s) {
+      const int e = s * 64 + t;
+      Ws[(e / CP) * PITCH + e % CP] = v[s];
+    }
+  }
+  __syncthreads();
   TW x[CP];
 #pragma unroll
-  for (int k = 0; k < CP; ++k) x[k] = row[k];
+  for (int k = 0; k < CP; ++k) x[k] = Ws[t * PITCH + k];
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NU; ++s) {
+    const int e = s * 64 + t;
+    const TW w = (TW)u[s];
+    Ws[e] = (e / CP == e % CP) ? (TW)1 / w : w;
+  }
+  __syncthreads();
 #pragma unroll
   for (int j = 0; j < CP; ++j) {
-    x[j] /= (TW)Ub[j * CP + j];
+    x[j] *= Ws[j * CP + j];
 #pragma unroll
-    for (int k = j + 1; k < CP; ++k) x[k] -= x[j] * (TW)Ub[j * CP + k];
+    for (int k = j + 1; k < CP; ++k) x[k] -= x[j] * Ws[j * CP + k];
   }
+  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < CP; ++k) row[k] = x[k];
+  for (int k = 0; k < CP; ++k) Ws[t * PITCH + k] = x[k];
+  __syncthreads();
+  if (vec) {
+    TW v[NP][VW];
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int e = s * 64 + t;
+#pragma unroll
+      for (int h = 0; h < VW; ++h) v[s][h] = Ws[(e / PPR) * PITCH + (e % PPR) * VW + h];
+    }
+#pragma unroll
+    for (int s = 0; s < NP; ++s) {
+      const int e = s * 64 + t;
+      Buf<TW>::store16(rs, voff(e / PPR, (e % PPR) * VW), 0, v[s]);
+    }
+  } else {
+    TW v[CP];
+#pragma unroll
+    for (int s = 0; s < CP; ++s) {
+      const int e = s * 64 + t;
+      v[s] = Ws[(e / CP) * PITCH + e % CP];
+    }
+#pragma unroll
+    for (int s = 0; s < CP; ++s) {
+      const int e = s * 64 + t;
+      Buf<TW>::store1(rs, voff(e / CP, e % CP), 0, v[s]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -348,15 +348,21 @@ class BatchedSolver:
         return evals, evecs, outs, st
 
 
-def mixed_qr(W, lower: bool = True):
-    """Algorithm 2 on a device block W (n x c); returns (Q, R)."""
+def mixed_qr(W, lower: bool = True, ld: int = 0):
+    """Algorithm 2 on a device block W (n x c); returns (Q, R).  ld > c runs it on W held in the first
+    c columns of an n x ld buffer (the other columns are left untouched)."""
     torch = _torch()
     lib = nv.load()
-    Q = _dev_f64(W).clone()
-    n, c = Q.shape
+    W = _dev_f64(W)
+    n, c = W.shape
+    ld = max(ld, c)
+    buf = torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda")
+    buf[:, :c] = W
     R = torch.empty((c, c), dtype=torch.float64, device="cuda")
-    nv.check(lib.lobpcg_mixed_qr(_ptr(Q), n, c, c, 1 if lower else 0, _ptr(R), _stream()))
-    return Q, R
+    nv.check(lib.lobpcg_mixed_qr(_ptr(buf), n, c, ld, 1 if lower else 0, _ptr(R), _stream()))
+    if ld > c and not bool(torch.all(buf[:, c:] == 7.0)):
+        raise RuntimeError("lobpcg_mixed_qr wrote outside the block's columns")
+    return buf[:, :c].contiguous(), R
 
 
 def gram(X, Y):

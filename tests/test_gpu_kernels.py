@@ -144,6 +144,25 @@ def test_mixed_qr(torch_cuda, kappa, lower, nc):
     assert np.linalg.norm(R - sgn[:, None] * Rh) / np.linalg.norm(Rh) < 100 * kappa * U64
 
 
+@pytest.mark.parametrize("lower", [True, False])
+@pytest.mark.parametrize("ncl", [(3001, 32, 33), (2000, 16, 21), (777, 8, 96), (4100, 32, 96)])
+def test_mixed_qr_strided(torch_cuda, lower, ncl):
+    """Algorithm 2 on a block inside a wider buffer (odd leading dimensions take the element-wise
+    paths of the row solves, a ragged last tile their range limits)."""
+    import paper_2302_12528_amd as pk
+    n, c, ld = ncl
+    print(f"mixed_qr_strided n={n} c={c} ld={ld} lower={lower}", flush=True)
+    rng = np.random.default_rng(n + ld)
+    W = rng.standard_normal((n, c)) * np.geomspace(1.0, 1e-3, c)
+    Q, R = pk.mixed_qr(W, lower=lower, ld=ld)
+    Q, R = _np(Q), _np(R)
+    assert np.linalg.norm(Q.T @ Q - np.eye(c)) <= 10 * c * U64
+    assert np.linalg.norm(W - Q @ R) / np.linalg.norm(W) <= 100 * U64
+    _, Rh = oqr.householder_qr(W)
+    sgn = np.sign(np.diag(R)) * np.sign(np.diag(Rh))
+    assert np.linalg.norm(R - sgn[:, None] * Rh) / np.linalg.norm(Rh) < 100 * 1e3 * U64
+
+
 def _solver(A, k, m, prec, grid=(0, 0, 0), **kw):
     import paper_2302_12528_amd as pk
     return pk.Solver(A, k, m, 1e-10, factor_precision=prec, grid=grid, **kw)
