@@ -1091,11 +1091,14 @@ lobpcg_status iteration_tail(lobpcg_ctx c, int cur, bool haveP, const SegDev& S,
   double* ASx = C.ASb[cur];
   const int wslot = haveP ? 2 * m : m;
   double* W = Sx + wslot;
-  // line 11: orthogonalize W against [X, P] twice
-  for (int pass = 0; pass < 2; ++pass) {
-    launch_sgram(S, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, st);
+  // line 11: orthogonalize W against [X, P] twice (for one instance the first pass's update also forms
+  // the second pass's Gram matrix from the updated rows)
+  launch_sgram(S, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, st);
+  if (!(B == 1 && launch_supdate_gram(S, Sx, m3, C.Gc, m, W, m3, wslot, m, C.gpart, C.gpart_bytes / 8, C.Gc, st))) {
     launch_supdate(S, Sx, m3, C.Gc, m, (int64_t)2 * m * m, W, m3, wslot, m, -1.0, 1.0, st);
+    launch_sgram(S, Sx, m3, W, m3, wslot, m, C.Gc, (int64_t)2 * m * m, C.gpart, st);
   }
+  launch_supdate(S, Sx, m3, C.Gc, m, (int64_t)2 * m * m, W, m3, wslot, m, -1.0, 1.0, st);
   ST_TRY(check_launch("block Gram-Schmidt"));
   // line 12: W = Q of Algorithm 2
   int* qflag2 = C.d_qflag + B;

@@ -105,6 +105,11 @@ void launch_sgram(const SegDev& S, const TI* X, int64_t ldx, const TI* Y, int64_
 template <typename TX>
 void launch_supdate(const SegDev& S, const TX* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
                     TX* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st);
+// Y <- Y - X M (FP64, one instance, cin = K <= 64 and K % 4 == 0, cout = 32, 16-byte aligned rows) fused
+// with G = X(:, 0:K)^T Y of the updated Y (part: scratch of part_elems doubles for the workgroups'
+// partials).  Returns false, launching nothing, when the shapes do not qualify.
+bool launch_supdate_gram(const SegDev& S, const double* X, int64_t ldx, const double* M, int64_t ldm, double* Y,
+                         int64_t ldy, int K, int cols, double* part, int64_t part_elems, double* G, hipStream_t st);
 template <typename T, typename TI>
 void launch_sresidual(const SegDev& S, const TI* AX, int64_t ldax, const TI* X, int64_t ldx,
                       const double* theta, int64_t tstride, int m, T* R, int64_t ldr, double* norms, double* part,

@@ -255,18 +255,39 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const TX* X
 // as 4 consecutive k from Ms.  D = M^T X^T, so lane (i, g) ends with row i and 4 consecutive columns of
 // each 16-column block (in FP64 the A operand takes the columns in the order ci = 4 (i % 4) + i / 4 to
 // make them consecutive), written as 16-byte vectors.
+//
+// GRAM = true (FP64, one instance, K <= kGramMaxK, K % 4 == 0, cols = 16 NCB, beta = 1): the workgroup
+// also accumulates X(:, 0:K)^T Y_new over its tiles, for the next Gram-Schmidt pass, without reading X
+// and Y again from memory: each wave puts its 16 new rows of Y in LDS (zeros past the tile) and runs
+// 16 x 16 x 4 products with X's rows (re-read, cache-resident) as the A operand and the LDS rows as B;
+// after the last tile the four waves' sums are added in LDS in wave order and the workgroup writes
+// its K x cols partial to gpart[blockIdx.x] (deterministic for a fixed grid).
 constexpr int kUpdMaxK = 96;
-template <typename TX, int NCB>
+constexpr int kGramMaxK = 64;
+template <typename TX, int NCB, bool GRAM = false>
 __global__ void __launch_bounds__(kThreads) supdate_ms_kernel(SegDev S, const TX* X, int64_t ldx,
                                                               const double* __restrict__ M, int64_t ldm,
                                                               int64_t mstride, TX* Y, int64_t ldy, int K, int cols,
-                                                              double alpha, double beta) {
+                                                              double alpha, double beta,
+                                                              double* __restrict__ gpart = nullptr) {
   typedef Mfma<TX> MF;
   typedef typename MF::v4 V4;
   constexpr int LK = kUpdMaxK + 4;   // 16-byte aligned rows; consecutive rows start 4 banks apart
   constexpr int NKB = kUpdMaxK / 16;
   constexpr int VW = 16 / sizeof(TX);
+  constexpr int NAB = kGramMaxK / 16;
+  constexpr int WP = 16 * NCB + 2;   // LDS pitch of the new rows (16-byte aligned rows)
+  static_assert(!GRAM || sizeof(TX) == 8, "the fused Gram is FP64");
+  static_assert(!GRAM || kGramMaxK * 16 * NCB <= 16 * NCB * LK, "the Gram partial must fit in Ms");
   __shared__ __align__(16) TX Ms[16 * NCB][LK];
+  __shared__ __align__(16) TX Wl[GRAM ? 4 : 1][GRAM ? 16 : 1][GRAM ? WP : 1];
+  V4 acc2[GRAM ? NAB : 1][GRAM ? NCB : 1];
+  if constexpr (GRAM) {
+#pragma unroll
+    for (int ab = 0; ab < NAB; ++ab)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc2[ab][cb] = V4{0, 0, 0, 0};
+  }
   const int t = threadIdx.x, lane = t % 64, w = t / 64;
   const int i = lane % 16, g = lane / 16;
   const int ci = (sizeof(TX) == 8) ? 4 * (i % 4) + i / 4 : i;
@@ -353,6 +374,41 @@ __global__ void __launch_bounds__(kThreads) supdate_ms_kernel(SegDev S, const TX
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[cb] = MF::op(mv[cb][u], xv[kb][u], acc[cb]);
     }
+    if constexpr (GRAM) {
+      TX* yr = Y + (r0 + r) * ldy;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int c = 16 * cb + 4 * g;
+        f64x2_t o0 = {0.0, 0.0}, o1 = {0.0, 0.0};
+        if (rok) {
+          f64x2_t* d = reinterpret_cast<f64x2_t*>(yr + c);
+          const f64x2_t y0 = d[0], y1 = d[1];
+          o0 = f64x2_t{fma(be, y0.x, al * acc[cb][0]), fma(be, y0.y, al * acc[cb][1])};
+          o1 = f64x2_t{fma(be, y1.x, al * acc[cb][2]), fma(be, y1.y, al * acc[cb][3])};
+          d[0] = o0;
+          d[1] = o1;
+        }
+        *reinterpret_cast<f64x2_t*>(&Wl[w][i][c]) = o0;
+        *reinterpret_cast<f64x2_t*>(&Wl[w][i][c + 2]) = o1;
+      }
+      __builtin_amdgcn_wave_barrier();   // the wave's LDS rows are read back by other lanes of the wave
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int rr = 16 * w + 4 * s4 + g;   // rows past the tile read zeros (resource range)
+        double xa[NAB], wb[NCB];
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab)
+          xa[ab] = Buf<double>::load1(xrs, (16 * ab + i < K) ? (int32_t)(((int64_t)rr * ldx + 16 * ab + i) * 8) : kOob, 0);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) wb[cb] = Wl[w][4 * s4 + g][16 * cb + i];
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc2[ab][cb] = MF::op(xa[ab], wb[cb], acc2[ab][cb]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      continue;
+    }
     if (!rok) continue;
     TX* yr = Y + (r0 + r) * ldy;
 #pragma unroll
@@ -388,6 +444,57 @@ __global__ void __launch_bounds__(kThreads) supdate_ms_kernel(SegDev S, const TX
           if (c + u < cols) yr[c + u] = (beta != 0.0) ? fma(be, yr[c + u], v[u]) : v[u];
       }
     }
+  }
+  if constexpr (GRAM) {
+    // sum of the four waves' partials in wave order (Ms is free: every product is done after the barrier)
+    constexpr int NC = 16 * NCB;
+    TX* red = &Ms[0][0];
+    __syncthreads();
+#pragma unroll 1
+    for (int ww = 0; ww < 4; ++ww) {
+      if (w == ww) {
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int idx = (16 * ab + MF::drow(lane, e)) * NC + 16 * cb + i;
+              red[idx] = (ww == 0) ? acc2[ab][cb][e] : red[idx] + acc2[ab][cb][e];
+            }
+      }
+      __syncthreads();
+    }
+    double* P = gpart + (int64_t)blockIdx.x * K * NC;
+    for (int e = t; e < K * NC; e += kThreads) P[e] = red[e];
+  }
+}
+
+// out[e] = sum over p < nparts of part[p][e] (len elements each), in a fixed order: as sreduce_kernel, a
+// block takes 16 elements and its 16 thread groups every 16th partial with four independent sums.
+__global__ void __launch_bounds__(256) preduce_kernel(const double* __restrict__ part, int nparts, int len,
+                                                      double* __restrict__ out) {
+  __shared__ double red[kRedGroups][kRedElems];
+  const int g = threadIdx.x / kRedElems, l = threadIdx.x % kRedElems;
+  const int e = blockIdx.x * kRedElems + l;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (e < len) {
+    int q = g;
+    for (; q + 3 * kRedGroups < nparts; q += 4 * kRedGroups) {
+      s0 += part[(int64_t)q * len + e];
+      s1 += part[(int64_t)(q + kRedGroups) * len + e];
+      s2 += part[(int64_t)(q + 2 * kRedGroups) * len + e];
+      s3 += part[(int64_t)(q + 3 * kRedGroups) * len + e];
+    }
+    for (; q < nparts; q += kRedGroups) s0 += part[(int64_t)q * len + e];
+  }
+  red[g][l] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (g == 0 && e < len) {
+    double t = 0.0;
+#pragma unroll
+    for (int h = 0; h < kRedGroups; ++h) t += red[h][l];
+    out[e] = t;
   }
 }
 
@@ -1117,6 +1224,23 @@ void launch_supdate(const SegDev& S, const TX* X, int64_t ldx, const double* M, 
 }
 template void launch_supdate<double>(const SegDev&, const double*, int64_t, const double*, int64_t, int64_t, double*,
                                      int64_t, int, int, double, double, hipStream_t);
+
+bool launch_supdate_gram(const SegDev& S, const double* X, int64_t ldx, const double* M, int64_t ldm, double* Y,
+                         int64_t ldy, int K, int cols, double* part, int64_t part_elems, double* G, hipStream_t st) {
+  if (S.B != 1 || S.ntiles <= 0 || K < 4 || K > kGramMaxK || (K & 3) != 0 || cols != 32) return false;
+  const bool vec = ((reinterpret_cast<uintptr_t>(X) | (uintptr_t)(ldx * 8)) & 15) == 0;
+  const bool yvec = ((reinterpret_cast<uintptr_t>(Y) | (uintptr_t)(ldy * 8)) & 15) == 0;
+  if (!vec || !yvec) return false;
+  static const int64_t cap =
+      resident_blocks(reinterpret_cast<const void*>(&supdate_ms_kernel<double, 2, true>), kThreads);
+  const int64_t len = (int64_t)K * cols;
+  const int64_t gx = std::min<int64_t>(std::min<int64_t>(S.ntiles, cap), part_elems / len);
+  if (gx < 1) return false;
+  supdate_ms_kernel<double, 2, true><<<dim3((unsigned)gx, 1), kThreads, 0, st>>>(S, X, ldx, M, ldm, 0, Y, ldy, K, cols,
+                                                                               -1.0, 1.0, part);
+  preduce_kernel<<<cdiv(len, kRedElems), 256, 0, st>>>(part, (int)gx, (int)len, G);
+  return true;
+}
 template void launch_supdate<float>(const SegDev&, const float*, int64_t, const double*, int64_t, int64_t, float*,
                                     int64_t, int, int, double, double, hipStream_t);
 
