@@ -1124,8 +1124,8 @@ lobpcg_status iteration_tail(lobpcg_ctx c, int cur, bool haveP, const SegDev& S,
               S.active, B, st);
   // lines 15-16: HL basis and the new X, P (and A X, A P by the same combination)
   launch_hl_build(C.Cev, (int64_t)m3 * m3, cc, m, C.Gupd, (int64_t)m3 * 2 * m, S.active, B, st);
-  launch_supdate(S, Sx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
-  launch_supdate(S, ASx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.ASb[1 - cur], m3, cc, 2 * m, 1.0, 0.0, st);
+  launch_supdate_pair(S, Sx, ASx, m3, C.Gupd, 2 * m, (int64_t)m3 * 2 * m, C.Sb[1 - cur], C.ASb[1 - cur], m3, cc,
+                     2 * m, st);
   return check_launch("Rayleigh-Ritz");
 }
 

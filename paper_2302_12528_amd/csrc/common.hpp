@@ -105,6 +105,9 @@ void launch_sgram(const SegDev& S, const TI* X, int64_t ldx, const TI* Y, int64_
 template <typename TX>
 void launch_supdate(const SegDev& S, const TX* X, int64_t ldx, const double* M, int64_t ldm, int64_t mstride,
                     TX* Y, int64_t ldy, int cin, int cout, double alpha, double beta, hipStream_t st);
+// Y <- X M and Y2 <- X2 M (FP64, alpha 1, beta 0) in one launch when the shapes allow, else two.
+void launch_supdate_pair(const SegDev& S, const double* X, const double* X2, int64_t ldx, const double* M, int64_t ldm,
+                         int64_t mstride, double* Y, double* Y2, int64_t ldy, int cin, int cout, hipStream_t st);
 // Y <- Y - X M (FP64, one instance, cin = K <= 64 and K % 4 == 0, cout = 32, 16-byte aligned rows) fused
 // with G = X(:, 0:K)^T Y of the updated Y (part: scratch of part_elems doubles for the workgroups'
 // partials).  Returns false, launching nothing, when the shapes do not qualify.

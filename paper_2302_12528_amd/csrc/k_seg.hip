@@ -256,6 +256,8 @@ __global__ void __launch_bounds__(kThreads) supdate_kernel(SegDev S, const TX* X
 // each 16-column block (in FP64 the A operand takes the columns in the order ci = 4 (i % 4) + i / 4 to
 // make them consecutive), written as 16-byte vectors.
 //
+// A pair launch (gridDim.z = 2) applies the same M to a second pair of blocks (X2, Y2) in its z = 1 half.
+//
 // GRAM = true (FP64, one instance, K <= kGramMaxK, K % 4 == 0, cols = 16 NCB, beta = 1): the workgroup
 // also accumulates X(:, 0:K)^T Y_new over its tiles, for the next Gram-Schmidt pass, without reading X
 // and Y again from memory: each wave puts its 16 new rows of Y in LDS (zeros past the tile) and runs
@@ -269,13 +271,18 @@ __global__ void __launch_bounds__(kThreads) supdate_ms_kernel(SegDev S, const TX
                                                               const double* __restrict__ M, int64_t ldm,
                                                               int64_t mstride, TX* Y, int64_t ldy, int K, int cols,
                                                               double alpha, double beta,
-                                                              double* __restrict__ gpart = nullptr) {
+                                                              double* __restrict__ gpart = nullptr,
+                                                              const TX* X2 = nullptr, TX* Y2 = nullptr) {
   typedef Mfma<TX> MF;
   typedef typename MF::v4 V4;
   constexpr int LK = kUpdMaxK + 4;   // 16-byte aligned rows; consecutive rows start 4 banks apart
   constexpr int NKB = kUpdMaxK / 16;
   constexpr int VW = 16 / sizeof(TX);
   constexpr int NAB = kGramMaxK / 16;
+  if (blockIdx.z == 1) {   // the second product of a pair launch: same M, other blocks
+    X = X2;
+    Y = Y2;
+  }
   constexpr int WP = 16 * NCB + 2;   // LDS pitch of the new rows (16-byte aligned rows)
   static_assert(!GRAM || sizeof(TX) == 8, "the fused Gram is FP64");
   static_assert(!GRAM || kGramMaxK * 16 * NCB <= 16 * NCB * LK, "the Gram partial must fit in Ms");
@@ -1224,6 +1231,22 @@ void launch_supdate(const SegDev& S, const TX* X, int64_t ldx, const double* M, 
 }
 template void launch_supdate<double>(const SegDev&, const double*, int64_t, const double*, int64_t, int64_t, double*,
                                      int64_t, int, int, double, double, hipStream_t);
+
+void launch_supdate_pair(const SegDev& S, const double* X, const double* X2, int64_t ldx, const double* M, int64_t ldm,
+                         int64_t mstride, double* Y, double* Y2, int64_t ldy, int cin, int cout, hipStream_t st) {
+  const bool vec = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(X2) | (uintptr_t)(ldx * 8)) & 15) == 0;
+  const bool yvec = ((reinterpret_cast<uintptr_t>(Y) | reinterpret_cast<uintptr_t>(Y2) | (uintptr_t)(ldy * 8)) & 15) == 0;
+  if (cout <= 32 || cout > 64 || cin > kUpdMaxK || !vec || !yvec || S.ntiles <= 0) {
+    launch_supdate(S, X, ldx, M, ldm, mstride, Y, ldy, cin, cout, 1.0, 0.0, st);
+    launch_supdate(S, X2, ldx, M, ldm, mstride, Y2, ldy, cin, cout, 1.0, 0.0, st);
+    return;
+  }
+  // half of the resident workgroups for each product, so that both halves run at once
+  static const int64_t cap = resident_blocks(reinterpret_cast<const void*>(&supdate_ms_kernel<double, 4>), kThreads);
+  const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(S.ntiles, cap / 2));
+  supdate_ms_kernel<double, 4><<<dim3(gx, 1, 2), kThreads, 0, st>>>(S, X, ldx, M, ldm, mstride, Y, ldy, cin, cout, 1.0,
+                                                                    0.0, nullptr, X2, Y2);
+}
 
 bool launch_supdate_gram(const SegDev& S, const double* X, int64_t ldx, const double* M, int64_t ldm, double* Y,
                          int64_t ldy, int K, int cols, double* part, int64_t part_elems, double* G, hipStream_t st) {
