@@ -54,7 +54,8 @@ __global__ void __launch_bounds__(kThreads) sgram_partial_kernel(SegDev S, const
   // Buffer loads over the chunk: a row past the chunk reads zero by the resource's range, a column past
   // c1 (c2) by an out-of-range offset, so every load is issued unconditionally.  The row step is the
   // wave-uniform offset; the loads of the next rows are issued before the current ones are multiplied.
-  constexpr int U = (RB + CB <= 2) ? 8 : 4;
+  // Groups of 32 rows where the registers allow (FP32, or few columns), else 16.
+  constexpr int U = (RB + CB <= 2 || sizeof(TI) == 4) ? 8 : 4;
   constexpr int64_t SZ = sizeof(TI);
   const int nrows = S.chunk_rows[q];
   const i32x4_t xr = make_rsrc(X + rbeg * ldx, (int64_t)nrows * ldx * SZ);
