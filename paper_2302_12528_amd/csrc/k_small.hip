@@ -1621,15 +1621,32 @@ __global__ void __launch_bounds__(kHlThreads) hl_build_kernel(const double* __re
 // to a multiple of 4 with zeros); lda/ldb: element (r, k) of A at A[r * ars + k * aks], (k, n) of
 // B at B[k * bks + n * bns], rows of A at or beyond ra and columns of B at or beyond nb read as
 // zero.  Returns the lane's four entries (rows Mfma<double>::drow(lane, q), column lane % 16).
+// Reads come from clamped indices and are masked afterwards (`keep_if`), four steps' reads issued together,
+// so that no read waits inside a branch.
 __device__ inline Mfma<double>::v4 tile_mm(const double* A, int ars, int aks, int ra, const double* B, int bks,
                                             int bns, int nb, int K) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, kk = lane >> 4;
+  const bool aok = r < ra, bok = r < nb;
+  const double* Ar = A + min(r, ra - 1) * ars;
+  const double* Br = B + min(r, nb - 1) * bns;
   Mfma<double>::v4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int k = k0 + kk;
-    const double a = (k < K && r < ra) ? A[r * ars + k * aks] : 0.0;
-    const double b = (k < K && r < nb) ? B[k * bks + r * bns] : 0.0;
+  int k0 = 0;
+  for (; k0 + 16 <= K; k0 += 16) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + kk;
+      a[u] = keep_if(aok, Ar[k * aks]);
+      b[u] = keep_if(bok, Br[k * bks]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = Mfma<double>::op(a[u], b[u], acc);
+  }
+  for (; k0 < K; k0 += 4) {
+    const int k = k0 + kk, kc = min(k, K - 1);
+    const double a = keep_if(aok && k < K, Ar[kc * aks]);
+    const double b = keep_if(bok && k < K, Br[kc * bks]);
     acc = Mfma<double>::op(a, b, acc);
   }
   return acc;
@@ -1657,11 +1674,24 @@ __global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __rest
   const int l1 = C1G ? c : LD;   // row stride of c1
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int ldg = (c > m) ? 2 * m : m;
-  for (int q = tid; q < c * m; q += kHlThreads) {
-    const int i = q / m, j = q % m;
-    const double x = C[(int64_t)i * c + j];
-    G[(int64_t)i * ldg + j] = x;
-    if constexpr (!C1G) c1s[i * LD + j] = x;
+  // C1 in: every thread's reads issued before its first store (clamped indices, stores guarded)
+  constexpr int NE = (CM * MM + kHlThreads - 1) / kHlThreads;
+  {
+    double xv[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int q = min(tid + u * kHlThreads, c * m - 1);
+      xv[u] = C[(int64_t)(q / m) * c + q % m];
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int q = tid + u * kHlThreads;
+      if (q < c * m) {
+        const int i = q / m, j = q % m;
+        G[(int64_t)i * ldg + j] = xv[u];
+        if constexpr (!C1G) c1s[i * LD + j] = xv[u];
+      }
+    }
   }
   if (c <= m) return;
   __syncthreads();
@@ -1706,9 +1736,9 @@ __global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __rest
 #pragma unroll
     for (int h = 0; h < NCOL; ++h)
 #pragma unroll
-      for (int u = 0; u < RC; ++u) {
+      for (int u = 0; u < RC; ++u) {   // clamped reads, masked: all in flight together
         const int i = q16 + 16 * u, j = slot + 16 * h;
-        W[h][u] = (i < c && j < m) ? w[i * LD + j] : 0.0;
+        W[h][u] = keep_if(i < c && j < m, w[min(i, c - 1) * LD + min(j, m - 1)]);
       }
 #pragma unroll
     for (int hj = 0; hj < NCOL; ++hj) {
@@ -1756,9 +1786,18 @@ __global__ void __launch_bounds__(kHlThreads) hl_reg_kernel(const double* __rest
       }
     __syncthreads();
   }
-  for (int q = tid; q < c * m; q += kHlThreads) {
-    const int i = q / m, j = q % m;
-    G[(int64_t)i * ldg + m + j] = w[i * LD + j];
+  {
+    double xv[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int q = min(tid + u * kHlThreads, c * m - 1);
+      xv[u] = w[(q / m) * LD + q % m];
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int q = tid + u * kHlThreads;
+      if (q < c * m) G[(int64_t)(q / m) * ldg + m + q % m] = xv[u];
+    }
   }
 }
 
