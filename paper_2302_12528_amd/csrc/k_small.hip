@@ -1480,23 +1480,23 @@ __global__ void __launch_bounds__(kSyevThreads) syev_reg_kernel(const double* __
     if constexpr (MODE == 1) {
       // Q^T from global memory: rows l of 16 consecutive entries, every load issued before the
       // products
-      double qa[CM / 4];
+      // products (clamped indices, masked afterwards: no read waits inside a branch)
+      const int iac = min(ia, c - 1), jbc = min(jb, nev - 1);
+      double qa[CM / 4], zv[CM / 4];
 #pragma unroll
       for (int u = 0; u < CM / 4; ++u) {
-        const int l = 4 * u + (lane >> 4);
-        qa[u] = (l < c && ia < c) ? sq[l * lq + ia] : 0.0;
+        const int l = 4 * u + (lane >> 4), lc = min(l, c - 1);
+        qa[u] = keep_if(l < c && ia < c, sq[lc * lq + iac]);
+        zv[u] = keep_if(l < c && jb < nev, Z[lc * lz + jbc]);
       }
 #pragma unroll
-      for (int u = 0; u < CM / 4; ++u) {
-        const int l = 4 * u + (lane >> 4);
-        const double zb = (l < c && jb < nev) ? Z[l * lz + jb] : 0.0;
-        acc = Mfma<double>::op(qa[u], zb, acc);
-      }
+      for (int u = 0; u < CM / 4; ++u) acc = Mfma<double>::op(qa[u], zv[u], acc);
     } else {
+      const int iac = min(ia, c - 1), jbc = min(jb, nev - 1);
       for (int l0 = 0; l0 < c4; l0 += 4) {
-        const int l = l0 + (lane >> 4);
-        const double qa = (l < c && ia < c) ? sq[ia * lq + l] : 0.0;
-        const double zb = (l < c && jb < nev) ? Z[l * lz + jb] : 0.0;
+        const int l = l0 + (lane >> 4), lc = min(l, c - 1);
+        const double qa = keep_if(l < c && ia < c, sq[iac * lq + lc]);
+        const double zb = keep_if(l < c && jb < nev, Z[lc * lz + jbc]);
         acc = Mfma<double>::op(qa, zb, acc);
       }
     }
