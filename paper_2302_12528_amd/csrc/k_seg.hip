@@ -694,9 +694,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) st
   // 16-byte pieces when the tile's rows allow (uniform), else element by element
   const bool vec = ((reinterpret_cast<uintptr_t>(tile) | (uintptr_t)(ld * sizeof(TW))) % 16) == 0;
   auto voff = [&](int r, int k) { return (int32_t)(((int64_t)r * ld + k) * (int64_t)sizeof(TW)); };
+  // U_b's reads are issued with the tile's (for CP = 64 after the rows are in registers, which would
+  // otherwise hold both at once)
   TU u[NU];
+  if constexpr (CP < 64) {
 #pragma unroll
-  for (int s = 0; s < NU; ++s) u[s] = Ub[s * 64 + t];
+    for (int s = 0; s < NU; ++s) u[s] = Ub[s * 64 + t];
+  }
   if (vec) {
     TW v[NP][VW];
 #pragma unroll
@@ -727,6 +731,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) st
   TW x[CP];
 #pragma unroll
   for (int k = 0; k < CP; ++k) x[k] = Ws[t * PITCH + k];
+  if constexpr (CP >= 64) {
+#pragma unroll
+    for (int s = 0; s < NU; ++s) u[s] = Ub[s * 64 + t];
+  }
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < NU; ++s) {
@@ -1311,6 +1319,7 @@ void launch_strsm_rows(const SegDev& S, TW* W, int64_t ld, int c, const TU* U, i
   if (c == 8) strsm_rows_reg_kernel<TU, 8, TW><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
   else if (c == 16) strsm_rows_reg_kernel<TU, 16, TW><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
   else if (c == 32) strsm_rows_reg_kernel<TU, 32, TW><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
+  else if (c == 64) strsm_rows_reg_kernel<TU, 64, TW><<<g, 64, 0, st>>>(S, W, ld, U, ustride);
   else strsm_rows_kernel<TU, TW><<<g, 64, lds, st>>>(S, W, ld, c, U, ustride);
 }
 template void launch_strsm_rows<float, double>(const SegDev&, double*, int64_t, int, const float*, int64_t, hipStream_t);
