@@ -644,9 +644,19 @@ __global__ void __launch_bounds__(64) strsm_rows_kernel(SegDev S, TW* W, int64_t
   const TU* Ub = U + (int64_t)b * ustride;
   const int t = threadIdx.x;
   for (int e = t; e < c * c; e += 64) Us[e] = (double)Ub[e];
-  for (int e = t; e < 64 * c; e += 64) {
-    const int i = e / c, j = e % c;
-    Ws[j * 64 + i] = (i < rows) ? (double)W[(r0 + i) * ld + j] : 0.0;
+  // eight reads in flight per batch (clamped rows, masked afterwards), then their LDS stores
+  for (int e0 = 0; e0 < 64 * c; e0 += 8 * 64) {
+    double v[8];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int e = min(e0 + h * 64 + t, 64 * c - 1), i = e / c, j = e % c;
+      v[h] = keep_if(i < rows, (double)W[(r0 + min(i, rows - 1)) * ld + j]);
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int e = e0 + h * 64 + t;
+      if (e < 64 * c) Ws[(e % c) * 64 + e / c] = v[h];
+    }
   }
   __syncthreads();
   for (int j = 0; j < c; ++j) {
